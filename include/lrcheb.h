@@ -1,0 +1,182 @@
+/*
+ * lrcheb.h - C ABI of the low-rank ChebyshevT solver for parameter-dependent
+ * matrix equations on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the matrix equation of one Newton step on a parameter
+ * subset (Benner, Richter, Weinhandl, arXiv 2008.10275, Sec. 3.4,
+ * eq. newton_matrix1, written generically):
+ *
+ *     sum_{i<q} K_i X D_i = F,      D_i = diag(d[i, :]),  X, F in R^{n x m},
+ *
+ * with X kept in low-rank form U diag(s) V^T.  The iteration is the
+ * preconditioned Chebyshev method with truncation ("ChebyshevT", Sec. 4.1 and
+ * Sec. 5.1), the preconditioner is the operator at the subset's centre
+ * parameters (Sec. 4.2), factorised once (Sec. 5 uses a permuted LU), and
+ * Algorithm 1 (Sec. 4.1) drives one Newton step per subset from the upper
+ * median parameter's solution (Sec. 3.3).
+ *
+ * Conventions for every call:
+ *  - Host arrays passed in are copied; the library never keeps or frees caller
+ *    memory.  Pointers named *_dev are device pointers owned by the caller.
+ *  - Dense host matrices are column-major (Fortran order) unless stated.
+ *  - Device factors are row-major: element (row i, column j) at p[i * ld + j].
+ *  - Status: 0 success; LRC_ENOTCONV (> 0) is a warning (the result is valid,
+ *    the best iterate is kept); negative values are errors, with a message
+ *    available from lrc_last_error().  No call aborts the process.
+ *  - Work is enqueued on the context's stream; calls that return host data
+ *    synchronise that stream.  One context per host thread.
+ */
+#ifndef LRCHEB_H
+#define LRCHEB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrc_ctx_s* lrc_ctx;
+typedef struct lrc_ops_s* lrc_ops;
+typedef struct lrc_prob_s* lrc_prob;
+typedef int lrc_status;
+
+enum {
+  LRC_OK = 0,
+  LRC_ENOTCONV = 1,    /* tolerance not reached within the iteration limits */
+  LRC_EINVAL = -1,     /* invalid argument (message says which)              */
+  LRC_ENOMEM = -2,     /* device or host allocation failed                   */
+  LRC_EDEVICE = -3,    /* HIP runtime error (message holds the HIP string)   */
+  LRC_ESINGULAR = -4,  /* zero or non-finite pivot in the preconditioner LU  */
+  LRC_EBREAKDOWN = -5, /* Cholesky breakdown not recoverable by a shift      */
+  LRC_ECALLBACK = -6   /* a user callback returned non-zero                  */
+};
+
+/* precision of the inner iteration */
+enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1 };
+/* initial guess of lrc_solve */
+enum { LRC_INIT_ZERO = 0, LRC_INIT_MEDIAN = 1, LRC_INIT_GIVEN = 2 };
+
+typedef struct {
+  int rank_cap;        /* R: maximum rank of every truncated quantity           */
+  double trunc_tol;    /* relative Frobenius tail of every truncation (eps)     */
+  double res_tol;      /* stop at ||F - L(X)||_F <= res_tol * ||F||_F           */
+  int max_iter;        /* total Chebyshev updates (all restarts, all refinements) */
+  int restart;         /* restart the recurrence every `restart` updates (0: never) */
+  double cheb_c;       /* half-width of the spectrum interval (<= 0: from lrc_prob_spectrum) */
+  double cheb_d;       /* centre of the spectrum interval                       */
+  int precision;       /* LRC_FP64 or LRC_MIXED_FP32                            */
+  int refine_max;      /* mixed: maximum fp64 refinement steps                  */
+  double inner_tol;    /* mixed: residual reduction asked of each fp32 inner solve */
+  int init;            /* LRC_INIT_*                                            */
+  double median_tol;   /* relative residual of the median-parameter solve       */
+  int verify_fp64;     /* 1: finish with the entry-wise fp64 residual           */
+} lrc_opts;
+
+typedef struct {
+  int rank;              /* rank of the correction S (X = X0 + S)                */
+  int rank_x0;           /* rank of the fixed initial term X0                    */
+  int iters;             /* Chebyshev updates of the iterate (all stages)        */
+  int prec_applies;      /* preconditioner applications (matrix solves)          */
+  int refinements;       /* fp64 refinement steps (mixed precision)              */
+  int median_iters;      /* iterations of the median-parameter solve             */
+  double relres;         /* ||F - L(X)||_F / ||F||_F, fp64 entry-wise if verified */
+  double relres_est;     /* same quantity from the last truncated residual       */
+  double max_col_relres; /* max_j ||(F - L(X))_j|| / ||F_j|| (fp64 entry-wise)   */
+  double seconds_setup;  /* factorisation of the preconditioner (host + upload)  */
+  double seconds_solve;  /* lrc_solve wall time                                  */
+  int info_flags;        /* bit 0: shifted Cholesky used; bit 1: breakdown; bit 2: eigen not converged */
+} lrc_info;
+
+/* Default options (rank cap 20, tol 1e-8, res_tol 1e-8, restart 6, fp64). */
+void lrc_opts_default(lrc_opts* opts);
+
+/* --------------------------------------------------------------- context
+ * device: HIP device index.  stream: a hipStream_t borrowed from the caller
+ * (NULL = the null stream); it must outlive the context. */
+lrc_status lrc_create(lrc_ctx* ctx, int device, void* stream);
+void lrc_destroy(lrc_ctx ctx);
+const char* lrc_last_error(lrc_ctx ctx);
+/* Replace the stream used by later calls (borrowed). */
+lrc_status lrc_set_stream(lrc_ctx ctx, void* stream);
+
+/* --------------------------------------------------------------- operators
+ * q square operators K_i (n x n) in CSR: rowptr[i] (n+1, int64, starting at 0
+ * and ending at nnz_i), col[i] (nnz_i, int32, ascending inside a row, in
+ * [0, n)), val[i] (nnz_i doubles).  Copied to the device in fp64 and fp32.
+ * Errors: LRC_EINVAL for malformed CSR or q outside [1, 8]. */
+lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* rowptr,
+                          const int32_t* const* col, const double* const* val, lrc_ops* ops);
+/* New values for operator i on the same pattern (a new linearisation point). */
+lrc_status lrc_ops_update_values(lrc_ops ops, int i, const double* val);
+void lrc_ops_destroy(lrc_ops ops);
+/* W_i = K_i U for all i (device, row-major).  dtype 0: fp64, 1: fp32.
+ * U: n x r with ld ldu; W: q blocks of n x r with ld ldw, block i at
+ * W + i * n * ldw.  ldu, ldw multiples of 8, r <= min(ldu, ldw) <= 256. */
+lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U_dev, int ldu,
+                            void* W_dev, int ldw);
+
+/* --------------------------------------------------------------- problem
+ * One subset: m parameter columns, the table d (q x m, column-major, i.e.
+ * d[i + q*j] = diag(D_i)[j]) and F = FU diag(Fs) FV^T of rank rF
+ * (FU: n x rF, FV: m x rF, column-major; Fs NULL means ones).
+ * The operators must outlive the problem. */
+lrc_status lrc_prob_create(lrc_ops ops, int64_t m, const double* d, int rF, const double* FU,
+                           const double* Fs, const double* FV, lrc_prob* prob);
+void lrc_prob_destroy(lrc_prob prob);
+/* Factorise P = sum_i dbar_i K_i (dbar: q values, NULL = arithmetic means of the
+ * rows of d).  Nested-dissection ordering + multifrontal LU without pivoting
+ * on the host, inverted supernode blocks uploaded for the level-scheduled GPU
+ * solves.  leaf_size <= 0 selects the default.  LRC_ESINGULAR on a bad pivot. */
+lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size);
+/* Interval [d - c, d + c] enclosing the preconditioned spectra: the smallest
+ * interval holding 1 and every ratio d[i, j] / dbar_i (valid when K_0 + K_0^T
+ * and K_1..K_{q-1} are positive semi-definite). */
+lrc_status lrc_prob_spectrum(lrc_prob prob, double* c, double* d);
+/* Statistics of the factorisation: out[0] supernodes, [1] forward levels,
+ * [2] backward levels, [3] max front, [4] stored block entries,
+ * [5] host ordering s, [6] host factor s, [7] upload s. */
+lrc_status lrc_prob_precond_stats(lrc_prob prob, double out[8]);
+/* Z = P^{-1} R on device columns (row-major n x k, k <= 64). dtype 0/1. */
+lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* R_dev, int ldr,
+                                   void* Z_dev, int ldz);
+
+/* Solve.  init = LRC_INIT_GIVEN uses X0 = U0 diag(s0) V0^T (host, column-major,
+ * rank r0; s0 NULL = ones) as the fixed initial term; LRC_INIT_MEDIAN solves the
+ * upper-median parameter problem (Sec. 3.3) and uses X0 = x~ 1^T; the correction
+ * S with L(S) = F - L(X0) is computed by ChebyshevT.  info may be NULL. */
+lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0,
+                     const double* s0, const double* V0, lrc_info* info);
+/* Solution X = [U0 | U] diag([s0, s]) [V0 | V]^T as host arrays (column-major):
+ * pass NULL pointers to query *rank (total columns).  U: n x rank, V: m x rank. */
+lrc_status lrc_get_solution(lrc_prob prob, int* rank, double* U, double* s, double* V);
+/* Entry-wise fp64 residual of the current solution: ||F - L(X)||_F / ||F||_F and
+ * per-column norms ||(F - L(X))_j|| (colres: m values, may be NULL). */
+lrc_status lrc_residual(lrc_prob prob, double* relres, double* colres);
+
+/* Truncation T_{R,eps}(A diag(c) B^T) of device factors (row-major fp64 or fp32:
+ * dtype 0/1): A n x k (ld lda), B m x k (ld ldb), c (k host doubles).  Outputs:
+ * U (n x rank, ld ldu), V (m x rank, ld ldv) device; s (host, rank values);
+ * k <= 128, rank_cap <= 64.  CholeskyQR2 on both factors + fp64 SVD of the core. */
+lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
+                            const void* A_dev, int lda, const double* c, const void* B_dev,
+                            int ldb, int rank_cap, double tol, void* U_dev, int ldu,
+                            double* s, void* V_dev, int ldv, int* rank);
+
+/* --------------------------------------------------------------- Algorithm 1
+ * Split m columns into K subsets (sizes NULL: eq. clustering1 of Sec. 3.3),
+ * and for each subset k: factorise the centre preconditioner, solve the upper
+ * median problem, one low-rank Newton step.  The callback supplies, per subset,
+ * the operator values of the linearisation point (val_out[i] has nnz_i
+ * entries; leave untouched to keep the current values) and returns 0.
+ * Results: out[k] receives the subset's problem (owned by the caller, free with
+ * lrc_prob_destroy); info[k] its statistics (may be NULL). */
+typedef int (*lrc_linearize_fn)(void* user, int k, const double* xtilde, double* const* val_out);
+lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
+                              const int64_t* sizes, const double* f, lrc_linearize_fn cb,
+                              void* user, const lrc_opts* opts, lrc_prob* out, lrc_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRCHEB_H */

@@ -1,0 +1,647 @@
+// C ABI (include/lrcheb.h): argument checking, ownership, error capture.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver.hpp"
+
+using namespace lrc;
+
+struct lrc_ctx_s {
+  Ctx c;
+};
+struct lrc_ops_s {
+  Ops o;
+};
+struct lrc_prob_s {
+  Prob p;
+  std::unique_ptr<lrc_ops_s> owned_ops;
+};
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+template <class F>
+lrc_status guarded(Ctx* ctx, F&& f) {
+  try {
+    if (ctx) ctx->err.clear();
+    return f();
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return LRC_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return LRC_EINVAL;
+  }
+}
+
+void validate_csr(int64_t n, const int64_t* rp, const int32_t* col, const double* val, int i) {
+  const std::string op = "operator " + std::to_string(i) + ": ";
+  LRC_CHECK(rp && (rp[n] == 0 || (col && val)), ST_EINVAL, op + "null CSR array");
+  LRC_CHECK(rp[0] == 0, ST_EINVAL, op + "rowptr[0] must be 0");
+  LRC_CHECK(rp[n] >= 0 && rp[n] < (int64_t(1) << 31), ST_EINVAL, op + "nnz out of range");
+  for (int64_t r = 0; r < n; ++r) {
+    LRC_CHECK(rp[r + 1] >= rp[r], ST_EINVAL, op + "rowptr not non-decreasing");
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      LRC_CHECK(col[e] >= 0 && col[e] < n, ST_EINVAL, op + "column index out of range");
+      LRC_CHECK(e == rp[r] || col[e] > col[e - 1], ST_EINVAL,
+                op + "column indices must be strictly ascending within a row");
+      LRC_CHECK(std::isfinite(val[e]), ST_EINVAL, op + "non-finite value");
+    }
+  }
+}
+
+// P = sum_i w_i K_i on the union pattern (host CSR)
+CsrHost combine(const Ops& o, const std::vector<double>& w) {
+  CsrHost P;
+  P.n = o.n;
+  P.rowptr.assign(o.n + 1, 0);
+  std::vector<int32_t> cols;
+  std::vector<double> vals;
+  std::vector<double> acc(o.n, 0.0);
+  std::vector<char> seen(o.n, 0);
+  for (int64_t r = 0; r < o.n; ++r) {
+    cols.clear();
+    for (int i = 0; i < o.q; ++i) {
+      const auto& K = o.host[i];
+      for (int64_t e = K.rowptr[r]; e < K.rowptr[r + 1]; ++e) {
+        const int32_t c = K.col[e];
+        if (!seen[c]) { seen[c] = 1; cols.push_back(c); acc[c] = 0.0; }
+        acc[c] += w[i] * K.val[e];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t c : cols) {
+      P.col.push_back(c);
+      P.val.push_back(acc[c]);
+      seen[c] = 0;
+    }
+    P.rowptr[r + 1] = int64_t(P.col.size());
+  }
+  return P;
+}
+
+void build_levels(Prec& pr, hipStream_t s) {
+  const SupernodalFactor& F = pr.F;
+  const int TR = 64;
+  std::vector<int2> all;
+  std::vector<int> fcount(F.nlev_fwd, 0), bcount(F.nlev_bwd, 0);
+  std::vector<std::vector<int2>> fl(F.nlev_fwd), bl(F.nlev_bwd);
+  for (int sn = 0; sn < F.nsn; ++sn) {
+    const int f = F.ns[sn] + F.nb[sn];
+    for (int r0 = 0; r0 < f; r0 += TR) fl[F.height[sn]].push_back(make_int2(sn, r0));
+    for (int r0 = 0; r0 < F.ns[sn]; r0 += TR) bl[F.depth[sn]].push_back(make_int2(sn, r0));
+  }
+  std::vector<size_t> foff, boff;
+  for (auto& L : fl) { foff.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  for (auto& L : bl) { boff.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  pr.fwd_tasks = upload(all, s);
+  const int2* base = pr.fwd_tasks.as<int2>();
+  pr.fwd.clear();
+  pr.bwd.clear();
+  for (size_t l = 0; l < fl.size(); ++l) pr.fwd.push_back({base + foff[l], int(fl[l].size())});
+  for (size_t l = 0; l < bl.size(); ++l) pr.bwd.push_back({base + boff[l], int(bl[l].size())});
+}
+
+void upload_prec(Prec& pr, hipStream_t s) {
+  auto t0 = clk::now();
+  SupernodalFactor& F = pr.F;
+  pr.perm = upload(F.perm, s);
+  pr.j0 = upload(F.j0, s);
+  pr.ns = upload(F.ns, s);
+  pr.nb = upload(F.nb, s);
+  pr.fw_off = upload(F.fw_off, s);
+  pr.bw_off = upload(F.bw_off, s);
+  pr.front_off = upload(F.front_off, s);
+  pr.cb_off = upload(F.cb_off, s);
+  pr.asm_ptr = upload(F.asm_ptr, s);
+  pr.asm_src = upload(F.asm_src, s);
+  pr.bnd_off = upload(F.bnd_off, s);
+  pr.bnd = upload(F.bnd, s);
+  pr.fw64 = upload(F.fw, s);
+  pr.bw64 = upload(F.bw, s);
+  {
+    std::vector<float> f32(F.fw.begin(), F.fw.end());
+    pr.fw32 = upload(f32, s);
+    LRC_HIP(hipStreamSynchronize(s));
+    std::vector<float> b32(F.bw.begin(), F.bw.end());
+    pr.bw32 = upload(b32, s);
+    LRC_HIP(hipStreamSynchronize(s));
+  }
+  pr.cb_rows = F.cb_off[F.nsn];
+  auto fill = [&](auto& P, const void* fw, const void* bw) {
+    P.n = F.n;
+    P.perm = pr.perm.as<int>();
+    P.j0 = pr.j0.as<int>();
+    P.ns = pr.ns.as<int>();
+    P.nb = pr.nb.as<int>();
+    P.fw_off = pr.fw_off.as<int64_t>();
+    P.bw_off = pr.bw_off.as<int64_t>();
+    P.front_off = pr.front_off.as<int64_t>();
+    P.cb_off = pr.cb_off.as<int64_t>();
+    P.asm_ptr = pr.asm_ptr.as<int64_t>();
+    P.asm_src = pr.asm_src.as<int64_t>();
+    P.bnd_off = pr.bnd_off.as<int64_t>();
+    P.bnd = pr.bnd.as<int>();
+    using TT = std::remove_const_t<std::remove_pointer_t<decltype(P.fw)>>;
+    P.fw = static_cast<const TT*>(fw);
+    P.bw = static_cast<const TT*>(bw);
+  };
+  fill(pr.p64, pr.fw64.p, pr.bw64.p);
+  fill(pr.p32, pr.fw32.p, pr.bw32.p);
+  build_levels(pr, s);
+  LRC_HIP(hipStreamSynchronize(s));
+  // the dense blocks live on the device now
+  std::vector<double>().swap(F.fw);
+  std::vector<double>().swap(F.bw);
+  pr.seconds_upload = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void lrc_opts_default(lrc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rank_cap = 20;
+  o->trunc_tol = 1e-8;
+  o->res_tol = 1e-8;
+  o->max_iter = 200;
+  o->restart = 6;
+  o->cheb_c = 0.0;
+  o->cheb_d = 0.0;
+  o->precision = LRC_FP64;
+  o->refine_max = 8;
+  o->inner_tol = 1e-5;
+  o->init = LRC_INIT_MEDIAN;
+  o->median_tol = 1e-10;
+  o->verify_fp64 = 1;
+}
+
+lrc_status lrc_create(lrc_ctx* out, int device, void* stream) {
+  if (!out) return LRC_EINVAL;
+  *out = nullptr;
+  auto* c = new (std::nothrow) lrc_ctx_s();
+  if (!c) return LRC_ENOMEM;
+  lrc_status st = guarded(&c->c, [&]() -> lrc_status {
+    int count = 0;
+    LRC_HIP(hipGetDeviceCount(&count));
+    LRC_CHECK(device >= 0 && device < count, ST_EINVAL, "lrc_create: no such device");
+    LRC_HIP(hipSetDevice(device));
+    c->c.device = device;
+    c->c.handle = c;
+    c->c.stream = static_cast<hipStream_t>(stream);
+    LRC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->c.pinned), 64 * sizeof(double)));
+    LRC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->c.pinned_i), 64 * sizeof(int)));
+    return LRC_OK;
+  });
+  if (st != LRC_OK) {
+    static thread_local std::string last;
+    last = c->c.err;
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LRC_OK;
+}
+
+void lrc_destroy(lrc_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+  if (ctx->c.pinned_i) (void)hipHostFree(ctx->c.pinned_i);
+  delete ctx;
+}
+
+const char* lrc_last_error(lrc_ctx ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+lrc_status lrc_set_stream(lrc_ctx ctx, void* stream) {
+  if (!ctx) return LRC_EINVAL;
+  ctx->c.stream = static_cast<hipStream_t>(stream);
+  return LRC_OK;
+}
+
+lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* rowptr,
+                          const int32_t* const* col, const double* const* val, lrc_ops* out) {
+  if (!ctx || !out) return LRC_EINVAL;
+  *out = nullptr;
+  return guarded(&ctx->c, [&]() -> lrc_status {
+    LRC_CHECK(n >= 1 && n < (int64_t(1) << 31), ST_EINVAL, "lrc_ops_create: n out of range");
+    LRC_CHECK(q >= 1 && q <= kMaxOps, ST_EINVAL, "lrc_ops_create: q must be in [1, 8]");
+    LRC_CHECK(rowptr && col && val, ST_EINVAL, "lrc_ops_create: null array list");
+    for (int i = 0; i < q; ++i) validate_csr(n, rowptr[i], col[i], val[i], i);
+    auto o = std::make_unique<lrc_ops_s>();
+    Ops& O = o->o;
+    O.ctx = &ctx->c;
+    O.n = n;
+    O.q = q;
+    hipStream_t s = ctx->c.stream;
+    LRC_HIP(hipSetDevice(ctx->c.device));
+    for (int i = 0; i < q; ++i) {
+      CsrHost h;
+      h.n = n;
+      const int64_t nnz = rowptr[i][n];
+      h.rowptr.assign(rowptr[i], rowptr[i] + n + 1);
+      h.col.assign(col[i], col[i] + nnz);
+      h.val.assign(val[i], val[i] + nnz);
+      std::vector<int> rp32(h.rowptr.begin(), h.rowptr.end());
+      O.rowptr.push_back(upload(rp32, s));
+      O.col.push_back(upload(h.col, s));
+      O.val64.push_back(DevBuf(std::max<size_t>(nnz, 1) * 8));
+      O.val32.push_back(DevBuf(std::max<size_t>(nnz, 1) * 4));
+      LRC_HIP(hipStreamSynchronize(s));
+      O.host.push_back(std::move(h));
+      O.upload_values(i);
+    }
+    for (int i = 0; i < q; ++i) {
+      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n});
+      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n});
+    }
+    *out = o.release();
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_ops_update_values(lrc_ops ops, int i, const double* val) {
+  if (!ops) return LRC_EINVAL;
+  return guarded(ops->o.ctx, [&]() -> lrc_status {
+    LRC_CHECK(i >= 0 && i < ops->o.q && val, ST_EINVAL, "lrc_ops_update_values: bad arguments");
+    auto& h = ops->o.host[i];
+    for (size_t e = 0; e < h.val.size(); ++e)
+      LRC_CHECK(std::isfinite(val[e]), ST_EINVAL, "lrc_ops_update_values: non-finite value");
+    std::copy(val, val + h.val.size(), h.val.begin());
+    ops->o.upload_values(i);
+    return LRC_OK;
+  });
+}
+
+void lrc_ops_destroy(lrc_ops ops) { delete ops; }
+
+lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U, int ldu, void* W,
+                            int ldw) {
+  if (!ops) return LRC_EINVAL;
+  return guarded(ops->o.ctx, [&]() -> lrc_status {
+    const Ops& o = ops->o;
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "spmm: dtype must be 0 (fp64) or 1 (fp32)");
+    LRC_CHECK(r >= 1 && r <= (dtype == 0 ? 128 : 256), ST_EINVAL, "spmm: r out of range");
+    LRC_CHECK(U && W, ST_EINVAL, "spmm: null pointer");
+    if (dtype == 0) {
+      double* Wp[kMaxOps];
+      for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
+      launch_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu, nullptr, r, r,
+                          Wp, ldw, 2, o.ctx->stream);
+    } else {
+      float* Wp[kMaxOps];
+      for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
+      launch_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr, r, r, Wp,
+                         ldw, 4, o.ctx->stream);
+    }
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_prob_create(lrc_ops ops, int64_t m, const double* d, int rF, const double* FU,
+                           const double* Fs, const double* FV, lrc_prob* out) {
+  if (!ops || !out) return LRC_EINVAL;
+  *out = nullptr;
+  return guarded(ops->o.ctx, [&]() -> lrc_status {
+    Ops& o = ops->o;
+    LRC_CHECK(m >= 1, ST_EINVAL, "lrc_prob_create: m must be positive");
+    LRC_CHECK(d && FU && FV, ST_EINVAL, "lrc_prob_create: null input");
+    LRC_CHECK(rF >= 1 && rF <= 64, ST_EINVAL, "lrc_prob_create: rank of F must be in [1, 64]");
+    for (int64_t e = 0; e < int64_t(o.q) * m; ++e)
+      LRC_CHECK(std::isfinite(d[e]), ST_EINVAL, "lrc_prob_create: non-finite parameter");
+    for (int64_t e = 0; e < o.n * rF; ++e)
+      LRC_CHECK(std::isfinite(FU[e]), ST_EINVAL, "lrc_prob_create: non-finite entry in FU");
+    for (int64_t e = 0; e < m * rF; ++e)
+      LRC_CHECK(std::isfinite(FV[e]), ST_EINVAL, "lrc_prob_create: non-finite entry in FV");
+    auto pr = std::make_unique<lrc_prob_s>();
+    Prob& P = pr->p;
+    P.ops = &o;
+    P.ctx = o.ctx;
+    P.m = m;
+    P.d.assign(d, d + size_t(o.q) * m);
+    P.rF = rF;
+    P.FU.assign(FU, FU + size_t(o.n) * rF);
+    P.FV.assign(FV, FV + size_t(m) * rF);
+    P.Fs.assign(rF, 1.0);
+    if (Fs) P.Fs.assign(Fs, Fs + rF);
+    std::vector<double> rows(size_t(o.q) * m);
+    for (int i = 0; i < o.q; ++i)
+      for (int64_t j = 0; j < m; ++j) rows[size_t(i) * m + j] = d[size_t(j) * o.q + i];
+    hipStream_t s = o.ctx->stream;
+    P.d_rows = upload(rows, s);
+    P.F64.alloc(o.n, m, rF, s);
+    // host column-major -> device row-major
+    {
+      std::vector<double> u(size_t(o.n) * P.F64.ld, 0.0), v(size_t(m) * P.F64.ld, 0.0);
+      for (int a = 0; a < rF; ++a) {
+        for (int64_t i = 0; i < o.n; ++i) u[size_t(i) * P.F64.ld + a] = FU[size_t(a) * o.n + i];
+        for (int64_t j = 0; j < m; ++j) v[size_t(j) * P.F64.ld + a] = FV[size_t(a) * m + j];
+      }
+      LRC_HIP(hipMemcpyAsync(P.F64.U.p, u.data(), u.size() * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(P.F64.V.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(P.F64.s.p, P.Fs.data(), rF * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(P.F64.rank.p, &rF, 4, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipStreamSynchronize(s));
+    }
+    // ||F||_F^2 = sum_ab Fs_a Fs_b (FU^T FU)_ab (FV^T FV)_ab
+    double f2 = 0.0;
+    for (int a = 0; a < rF; ++a)
+      for (int b = 0; b < rF; ++b) {
+        double gu = 0.0, gv = 0.0;
+        for (int64_t i = 0; i < o.n; ++i) gu += FU[size_t(a) * o.n + i] * FU[size_t(b) * o.n + i];
+        for (int64_t j = 0; j < m; ++j) gv += FV[size_t(a) * m + j] * FV[size_t(b) * m + j];
+        f2 += P.Fs[a] * P.Fs[b] * gu * gv;
+      }
+    P.fnorm = std::sqrt(std::max(f2, 0.0));
+    LRC_CHECK(P.fnorm > 0.0, ST_EINVAL, "lrc_prob_create: F is zero");
+    P.dbar.assign(o.q, 0.0);
+    for (int i = 0; i < o.q; ++i) {
+      double acc = 0.0;
+      for (int64_t j = 0; j < m; ++j) acc += d[size_t(j) * o.q + i];
+      P.dbar[i] = acc / double(m);
+    }
+    *out = pr.release();
+    return LRC_OK;
+  });
+}
+
+void lrc_prob_destroy(lrc_prob prob) { delete prob; }
+
+lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size) {
+  if (!prob) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    auto t0 = clk::now();
+    const Ops& o = *P.ops;
+    if (dbar) {
+      for (int i = 0; i < o.q; ++i)
+        LRC_CHECK(std::isfinite(dbar[i]), ST_EINVAL, "lrc_prob_precondition: non-finite dbar");
+      P.dbar.assign(dbar, dbar + o.q);
+    }
+    CsrHost Pm = combine(o, P.dbar);
+    auto pr = std::make_unique<Prec>();
+    std::string err;
+    const int rc = nd_factor(Pm, leaf_size > 0 ? leaf_size : 16, 0, &pr->F, &err);
+    if (rc == -4) throw Error(ST_ESINGULAR, err);
+    if (rc != 0) throw Error(ST_EINVAL, err);
+    upload_prec(*pr, P.ctx->stream);
+    P.prec = std::move(pr);
+    P.seconds_setup = std::chrono::duration<double>(clk::now() - t0).count();
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_prob_spectrum(lrc_prob prob, double* c, double* d) {
+  if (!prob || !c || !d) return LRC_EINVAL;
+  const Prob& P = prob->p;
+  double lo = 1.0, hi = 1.0;
+  for (int64_t j = 0; j < P.m; ++j)
+    for (int i = 0; i < P.ops->q; ++i) {
+      const double r = P.d[size_t(j) * P.ops->q + i] / P.dbar[i];
+      lo = std::min(lo, r);
+      hi = std::max(hi, r);
+    }
+  *c = 0.5 * (hi - lo);
+  *d = 0.5 * (hi + lo);
+  return LRC_OK;
+}
+
+lrc_status lrc_prob_precond_stats(lrc_prob prob, double out[8]) {
+  if (!prob || !out) return LRC_EINVAL;
+  const Prob& P = prob->p;
+  if (!P.prec) {
+    P.ctx->err = "lrc_prob_precond_stats: no preconditioner";
+    return LRC_EINVAL;
+  }
+  const auto& F = P.prec->F;
+  out[0] = F.nsn;
+  out[1] = F.nlev_fwd;
+  out[2] = F.nlev_bwd;
+  out[3] = double(F.max_front);
+  out[4] = F.dense_entries;
+  out[5] = F.seconds_order;
+  out[6] = F.seconds_factor;
+  out[7] = P.prec->seconds_upload;
+  return LRC_OK;
+}
+
+lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* R, int ldr,
+                                   void* Z, int ldz) {
+  if (!prob) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    LRC_CHECK(P.prec != nullptr, ST_EINVAL, "prec_apply: no preconditioner");
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "prec_apply: dtype must be 0 or 1");
+    LRC_CHECK(k >= 1 && k <= kPrecCols && ldr >= k && ldz >= k && R && Z, ST_EINVAL,
+              "prec_apply: bad arguments");
+    const int64_t n = P.ops->n;
+    const int ld = ld_for(k);
+    const size_t es = dtype == 0 ? 8 : 4;
+    DevBuf y(size_t(n) * ld * es), x(size_t(n) * ld * es),
+        cb(size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * ld * es);
+    hipStream_t s = P.ctx->stream;
+    if (dtype == 0)
+      launch_prec_apply<double>(P.prec->p64, P.prec->fwd, P.prec->bwd,
+                                static_cast<const double*>(R), ldr, static_cast<double*>(Z), ldz,
+                                nullptr, k, k, y.as<double>(), x.as<double>(), cb.as<double>(), ld,
+                                s);
+    else
+      launch_prec_apply<float>(P.prec->p32, P.prec->fwd, P.prec->bwd,
+                               static_cast<const float*>(R), ldr, static_cast<float*>(Z), ldz,
+                               nullptr, k, k, y.as<float>(), x.as<float>(), cb.as<float>(), ld, s);
+    LRC_HIP(hipStreamSynchronize(s));   // scratch buffers are released on return
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0,
+                     const double* s0, const double* V0, lrc_info* info) {
+  if (!prob || !opts) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    LRC_HIP(hipSetDevice(P.ctx->device));
+    return solve_problem(P, *opts, r0, U0, s0, V0, info);
+  });
+}
+
+lrc_status lrc_get_solution(lrc_prob prob, int* rank, double* U, double* s, double* V) {
+  if (!prob || !rank) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    LRC_CHECK(P.S.U.p != nullptr, ST_EINVAL, "lrc_get_solution: nothing solved yet");
+    const int r0 = P.rank_x0, rs = P.rank_s;
+    *rank = r0 + rs;
+    if (!U && !s && !V) return LRC_OK;
+    LRC_CHECK(U && s && V, ST_EINVAL, "lrc_get_solution: U, s and V are all required");
+    const int64_t n = P.ops->n, m = P.m;
+    hipStream_t st = P.ctx->stream;
+    auto fetch = [&](const LR<double>& X, int r, int col0) {
+      if (r == 0) return;
+      std::vector<double> u(size_t(n) * X.ld), v(size_t(m) * X.ld), sv(r);
+      LRC_HIP(hipMemcpyAsync(u.data(), X.U.p, u.size() * 8, hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipMemcpyAsync(v.data(), X.V.p, v.size() * 8, hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipMemcpyAsync(sv.data(), X.s.p, size_t(r) * 8, hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipStreamSynchronize(st));
+      for (int a = 0; a < r; ++a) {
+        for (int64_t i = 0; i < n; ++i) U[size_t(col0 + a) * n + i] = u[size_t(i) * X.ld + a];
+        for (int64_t j = 0; j < m; ++j) V[size_t(col0 + a) * m + j] = v[size_t(j) * X.ld + a];
+        s[col0 + a] = sv[a];
+      }
+    };
+    fetch(P.X0, r0, 0);
+    fetch(P.S, rs, r0);
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_residual(lrc_prob prob, double* relres, double* colres) {
+  if (!prob || !relres) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    LRC_CHECK(P.S.U.p != nullptr, ST_EINVAL, "lrc_residual: nothing solved yet");
+    *relres = residual_fp64(P, P.X0, P.rank_x0, P.S, colres) / P.fnorm;
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
+                            const void* A, int lda, const double* c, const void* B, int ldb,
+                            int rank_cap, double tol, void* U, int ldu, double* s, void* V,
+                            int ldv, int* rank) {
+  if (!ctx) return LRC_EINVAL;
+  return guarded(&ctx->c, [&]() -> lrc_status {
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "truncate: dtype must be 0 or 1");
+    LRC_CHECK(n >= 1 && m >= 1 && k >= 1 && k <= kTruncCap, ST_EINVAL,
+              "truncate: need n, m >= 1 and 1 <= k <= 128");
+    LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
+              "truncate: rank_cap in [1, 64] and <= ldu, ldv");
+    LRC_CHECK(A && B && c && U && V && s && rank && lda >= k && ldb >= k, ST_EINVAL,
+              "truncate: bad pointers or leading dimensions");
+    hipStream_t st = ctx->c.stream;
+    std::vector<double> ch(c, c + k);
+    DevBuf cd = upload(ch, st), sd(64 * 8), outs(16 * 8);
+    CoreView cv{};
+    cv.nb = 1;
+    cv.s[0] = cd.as<double>();
+    cv.coef[0] = 1.0;
+    cv.wdev[0] = nullptr;
+    cv.wconst[0] = k;
+    auto run = [&](auto* tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      Truncator<T> tr;
+      tr.alloc(n, m, st);
+      BlockView<T> av = view1<T>(static_cast<const T*>(A), lda, nullptr, k);
+      BlockView<T> bv = view1<T>(static_cast<const T*>(B), ldb, nullptr, k);
+      int* rk = reinterpret_cast<int*>(outs.as<double>() + 2);
+      tr.run(av, n, bv, m, cv, rank_cap, tol, static_cast<T*>(U), ldu, static_cast<T*>(V), ldv,
+             sd.as<double>(), rk, outs.as<double>(), st);
+      LRC_HIP(hipMemcpyAsync(rank, rk, sizeof(int), hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipStreamSynchronize(st));
+      if (*rank > 0)
+        LRC_HIP(hipMemcpyAsync(s, sd.p, size_t(*rank) * 8, hipMemcpyDeviceToHost, st));
+      int flags = 0;
+      LRC_HIP(hipMemcpyAsync(&flags, tr.st.info, sizeof(int), hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipStreamSynchronize(st));
+      if (flags & 2) throw Error(ST_EBREAKDOWN, "truncate: Cholesky breakdown");
+    };
+    if (dtype == 0) run(static_cast<double*>(nullptr));
+    else run(static_cast<float*>(nullptr));
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
+                              const int64_t* sizes, const double* f, lrc_linearize_fn cb,
+                              void* user, const lrc_opts* opts, lrc_prob* out, lrc_info* info) {
+  if (!ops || !opts || !out || !d || !f) return LRC_EINVAL;
+  Ops& base = ops->o;
+  return guarded(base.ctx, [&]() -> lrc_status {
+    LRC_CHECK(K >= 1 && K <= m, ST_EINVAL, "newton_subsets: need 1 <= K <= m");
+    std::vector<int64_t> sz(K);
+    if (sizes) {
+      int64_t tot = 0;
+      for (int k = 0; k < K; ++k) {
+        LRC_CHECK(sizes[k] >= 1, ST_EINVAL, "newton_subsets: empty subset");
+        sz[k] = sizes[k];
+        tot += sz[k];
+      }
+      LRC_CHECK(tot == m, ST_EINVAL, "newton_subsets: sizes must sum to m");
+    } else {
+      // eq. clustering1: floor(m / K) for the first K - 1 subsets, the rest last
+      for (int k = 0; k < K - 1; ++k) sz[k] = m / K;
+      sz[K - 1] = m - (K - 1) * (m / K);
+    }
+    for (int k = 0; k < K; ++k) out[k] = nullptr;
+    const int q = base.q;
+    const int64_t n = base.n;
+    std::vector<double> prev_x;
+    lrc_status worst = LRC_OK;
+    int64_t off = 0;
+    for (int k = 0; k < K; ++k) {
+      // private operators for this subset's linearisation point
+      auto so = std::make_unique<lrc_ops_s>();
+      {
+        std::vector<const int64_t*> rp(q);
+        std::vector<const int32_t*> cl(q);
+        std::vector<const double*> vl(q);
+        for (int i = 0; i < q; ++i) {
+          rp[i] = base.host[i].rowptr.data();
+          cl[i] = base.host[i].col.data();
+          vl[i] = base.host[i].val.data();
+        }
+        lrc_ops tmp = nullptr;
+        lrc_ctx_s* cx = static_cast<lrc_ctx_s*>(base.ctx->handle);
+        const lrc_status st = lrc_ops_create(cx, n, q, rp.data(), cl.data(), vl.data(), &tmp);
+        if (st != LRC_OK) return st;
+        so.reset(tmp);
+      }
+      if (cb) {
+        std::vector<std::vector<double>> vals(q);
+        std::vector<double*> vp(q);
+        for (int i = 0; i < q; ++i) {
+          vals[i] = so->o.host[i].val;
+          vp[i] = vals[i].data();
+        }
+        const int rc = cb(user, k, prev_x.empty() ? nullptr : prev_x.data(), vp.data());
+        if (rc != 0) throw Error(ST_ECALLBACK, "newton_subsets: callback returned non-zero");
+        for (int i = 0; i < q; ++i)
+          if (vals[i] != so->o.host[i].val) {
+            std::copy(vals[i].begin(), vals[i].end(), so->o.host[i].val.begin());
+            so->o.upload_values(i);
+          }
+      }
+      std::vector<double> ones(sz[k], 1.0);
+      lrc_prob pb = nullptr;
+      lrc_status st = lrc_prob_create(so.get(), sz[k], d + size_t(off) * q, 1, f, nullptr,
+                                      ones.data(), &pb);
+      if (st != LRC_OK) return st;
+      pb->owned_ops = std::move(so);
+      out[k] = pb;
+      st = lrc_prob_precondition(pb, nullptr, 0);
+      if (st != LRC_OK) return st;
+      lrc_opts o = *opts;
+      o.init = LRC_INIT_MEDIAN;
+      lrc_info inf{};
+      st = lrc_solve(pb, &o, 0, nullptr, nullptr, nullptr, &inf);
+      if (st < 0) return st;
+      if (st > worst) worst = st;
+      if (info) info[k] = inf;
+      // keep x~ of this subset for the next callback
+      prev_x.resize(n);
+      std::vector<double> u(size_t(n) * pb->p.X0.ld);
+      LRC_HIP(hipMemcpy(u.data(), pb->p.X0.U.p, u.size() * 8, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i) prev_x[i] = u[size_t(i) * pb->p.X0.ld];
+      off += sz[k];
+    }
+    return worst;
+  });
+}
+
+}  // extern "C"

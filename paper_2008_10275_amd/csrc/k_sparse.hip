@@ -1,0 +1,399 @@
+// Sparse kernels: fused CSR SpMM of the q operators against a tall factor, the
+// level-scheduled supernodal triangular solves of the preconditioner, and the
+// small vector kernels of the single-column (median parameter) solve.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace lrc {
+
+// ============================================================== SpMM
+template <class T>
+struct SpmmArgs {
+  DevCsr<T> op[kMaxOps];
+  T* W[kMaxOps];
+};
+
+// Every row of K_i is handled by `lpr` consecutive lanes; each lane owns CPL
+// consecutive columns of the factor.  Rows of U are contiguous (row-major), so
+// each nonzero K_i(row, j) costs one coalesced read of row j of U.  The grid's
+// y dimension runs over the q operators that share U.
+template <class T, int CPL>
+__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> args, const T* __restrict__ U,
+                                                   int ldu, const int* __restrict__ r_dev,
+                                                   int r_const, int lpr, int ldw) {
+  const DevCsr<T> K = args.op[blockIdx.y];
+  T* __restrict__ W = args.W[blockIdx.y];
+  const int r = r_dev ? *r_dev : r_const;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rpw = 64 / lpr;                       // rows per wave
+  const int sub = lane / lpr;
+  const int chunk = lane - sub * lpr;
+  const int c0 = chunk * CPL;
+  if (sub >= rpw || c0 >= r) return;
+  const int64_t rows_per_block = int64_t(rpw) * (blockDim.x >> 6);
+  for (int64_t row = int64_t(blockIdx.x) * rows_per_block + int64_t(wave) * rpw + sub; row < K.n;
+       row += int64_t(gridDim.x) * rows_per_block) {
+    T acc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = T(0);
+    const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
+    for (int e = e0; e < e1; ++e) {
+      const T v = K.val[e];
+      const T* __restrict__ u = U + int64_t(K.col[e]) * ldu + c0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c] += v * u[c];
+    }
+    T* w = W + row * ldw + c0;
+    if (c0 + CPL <= r) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) w[c] = acc[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (c0 + c < r) w[c] = acc[c];
+    }
+  }
+}
+
+template <class T>
+void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev, int r_const,
+                 int rcap, T* const* W, int ldw, int cpl, hipStream_t s) {
+  LRC_CHECK(q >= 1 && q <= kMaxOps, ST_EINVAL, "spmm: bad operator count");
+  LRC_CHECK(rcap >= 1, ST_EINVAL, "spmm: rank capacity must be positive");
+  LRC_CHECK(ldu % 8 == 0 && ldw % 8 == 0 && ldu >= rcap && ldw >= rcap, ST_EINVAL,
+            "spmm: leading dimensions must be multiples of 8 and cover the rank capacity");
+  const int lpr = int(ceil_div(rcap, cpl));
+  LRC_CHECK(lpr <= 64, ST_EINVAL, "spmm: rank capacity too large for the lane mapping");
+  SpmmArgs<T> a;
+  int64_t n = 0;
+  for (int i = 0; i < q; ++i) {
+    a.op[i] = ops[i];
+    a.W[i] = W[i];
+    n = std::max(n, ops[i].n);
+  }
+  const int rpw = 64 / lpr;
+  const int64_t rows_per_block = int64_t(rpw) * 4;
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32);
+  dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(q));
+  switch (cpl) {
+    case 2:
+      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
+                         lpr, ldw);
+      break;
+    case 4:
+      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
+                         lpr, ldw);
+      break;
+    case 8:
+      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
+                         lpr, ldw);
+      break;
+    default:
+      throw Error(ST_EINVAL, "spmm: columns per lane must be 2, 4 or 8");
+  }
+  LRC_HIP(hipGetLastError());
+}
+
+template void launch_spmm<float>(const DevCsr<float>*, int, const float*, int, const int*, int,
+                                 int, float* const*, int, int, hipStream_t);
+template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int, const int*,
+                                  int, int, double* const*, int, int, hipStream_t);
+
+// ============================================================== preconditioner
+// One workgroup computes TR output rows of one supernode for all k columns.
+// Thread t owns row (t % TR) and the column quads q = t / TR + NG * j.
+constexpr int kTR = 64;        // rows per workgroup
+constexpr int kIC = 32;        // input rows staged per LDS chunk
+constexpr int kKMAX = 64;      // max columns per apply
+
+template <class T>
+__device__ inline void assemble_front_row(const PrecDev<T>& P, int64_t frow, const T* cb, int ldw,
+                                          int c, T& v) {
+  const int64_t e0 = P.asm_ptr[frow], e1 = P.asm_ptr[frow + 1];
+  for (int64_t e = e0; e < e1; ++e) v += cb[P.asm_src[e] * ldw + c];
+}
+
+// forward level:  [y_own ; cb_s] = Fw_s * f_own + [0 ; f_bnd]
+template <class T>
+__global__ __launch_bounds__(256) void prec_fwd_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
+                                                       const T* __restrict__ R, int ldr,
+                                                       const int* __restrict__ k_dev, int k_const,
+                                                       T* __restrict__ y, T* __restrict__ cb,
+                                                       int ldw) {
+  __shared__ T stage[kIC][kKMAX + 1];
+  const int2 task = tasks[blockIdx.x];
+  const int sn = task.x;
+  const int k = k_dev ? *k_dev : k_const;
+  const int ns = P.ns[sn], nbv = P.nb[sn], f = ns + nbv, j0 = P.j0[sn];
+  const int64_t front0 = P.front_off[sn];
+  const T* __restrict__ fw = P.fw + P.fw_off[sn];
+  const int tr = threadIdx.x % kTR;
+  const int cg = threadIdx.x / kTR;              // 0..3
+  const int row = task.y + tr;
+  const bool rv = row < f;
+  T acc[kKMAX / 4];
+#pragma unroll
+  for (int j = 0; j < kKMAX / 4; ++j) acc[j] = T(0);
+  for (int i0 = 0; i0 < ns; i0 += kIC) {
+    const int ic = min(kIC, ns - i0);
+    for (int e = threadIdx.x; e < ic * k; e += blockDim.x) {
+      const int i = e / k, c = e - i * k;
+      T v = R[int64_t(P.perm[j0 + i0 + i]) * ldr + c];
+      assemble_front_row(P, front0 + i0 + i, cb, ldw, c, v);
+      stage[i][c] = v;
+    }
+    __syncthreads();
+    if (rv) {
+      for (int i = 0; i < ic; ++i) {
+        const T a = fw[int64_t(i0 + i) * f + row];
+#pragma unroll
+        for (int j = 0; j < kKMAX / 4; ++j) {
+          const int c = cg + 4 * j;
+          if (c < k) acc[j] += a * stage[i][c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!rv) return;
+#pragma unroll
+  for (int j = 0; j < kKMAX / 4; ++j) {
+    const int c = cg + 4 * j;
+    if (c >= k) continue;
+    T v = acc[j];
+    if (row < ns) {
+      y[int64_t(j0 + row) * ldw + c] = v;
+    } else {
+      assemble_front_row(P, front0 + row, cb, ldw, c, v);
+      cb[(P.cb_off[sn] + row - ns) * ldw + c] = v;
+    }
+  }
+}
+
+// backward level:  x_own = Bw_s * [y_own ; x(bnd)];  also Z(perm) = x
+template <class T>
+__global__ __launch_bounds__(256) void prec_bwd_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
+                                                       const int* __restrict__ k_dev, int k_const,
+                                                       const T* __restrict__ y, T* __restrict__ x,
+                                                       int ldw, T* __restrict__ Z, int ldz) {
+  __shared__ T stage[kIC][kKMAX + 1];
+  const int2 task = tasks[blockIdx.x];
+  const int sn = task.x;
+  const int k = k_dev ? *k_dev : k_const;
+  const int ns = P.ns[sn], nbv = P.nb[sn], f = ns + nbv, j0 = P.j0[sn];
+  const T* __restrict__ bw = P.bw + P.bw_off[sn];
+  const int* __restrict__ bnd = P.bnd + P.bnd_off[sn];
+  const int tr = threadIdx.x % kTR;
+  const int cg = threadIdx.x / kTR;
+  const int row = task.y + tr;
+  const bool rv = row < ns;
+  T acc[kKMAX / 4];
+#pragma unroll
+  for (int j = 0; j < kKMAX / 4; ++j) acc[j] = T(0);
+  for (int i0 = 0; i0 < f; i0 += kIC) {
+    const int ic = min(kIC, f - i0);
+    for (int e = threadIdx.x; e < ic * k; e += blockDim.x) {
+      const int i = e / k, c = e - i * k;
+      const int ii = i0 + i;
+      stage[i][c] = (ii < ns) ? y[int64_t(j0 + ii) * ldw + c] : x[int64_t(bnd[ii - ns]) * ldw + c];
+    }
+    __syncthreads();
+    if (rv) {
+      for (int i = 0; i < ic; ++i) {
+        const T a = bw[int64_t(i0 + i) * ns + row];
+#pragma unroll
+        for (int j = 0; j < kKMAX / 4; ++j) {
+          const int c = cg + 4 * j;
+          if (c < k) acc[j] += a * stage[i][c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!rv) return;
+  const int64_t orow = P.perm[j0 + row];
+#pragma unroll
+  for (int j = 0; j < kKMAX / 4; ++j) {
+    const int c = cg + 4 * j;
+    if (c >= k) continue;
+    x[int64_t(j0 + row) * ldw + c] = acc[j];
+    Z[orow * ldz + c] = acc[j];
+  }
+}
+
+template <class T>
+void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                       const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
+                       const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
+                       int ldw, hipStream_t s) {
+  LRC_CHECK(kcap >= 1 && kcap <= kKMAX, ST_EINVAL,
+            "preconditioner apply: at most 64 right-hand sides per call");
+  LRC_CHECK(ldw >= kcap && ldr >= kcap && ldz >= kcap, ST_EINVAL,
+            "preconditioner apply: leading dimension smaller than the column capacity");
+  for (const auto& L : fwd) {
+    if (L.count == 0) continue;
+    hipLaunchKernelGGL((prec_fwd_kernel<T>), dim3(L.count), dim3(256), 0, s, P, L.tasks, R, ldr,
+                       k_dev, k_const, ws_y, ws_cb, ldw);
+  }
+  for (const auto& L : bwd) {
+    if (L.count == 0) continue;
+    hipLaunchKernelGGL((prec_bwd_kernel<T>), dim3(L.count), dim3(256), 0, s, P, L.tasks, k_dev,
+                       k_const, ws_y, ws_x, ldw, Z, ldz);
+  }
+  LRC_HIP(hipGetLastError());
+}
+
+template void launch_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
+                                       const std::vector<LevelTasks>&, const float*, int, float*,
+                                       int, const int*, int, int, float*, float*, float*, int,
+                                       hipStream_t);
+template void launch_prec_apply<double>(const PrecDev<double>&, const std::vector<LevelTasks>&,
+                                        const std::vector<LevelTasks>&, const double*, int,
+                                        double*, int, const int*, int, int, double*, double*,
+                                        double*, int, hipStream_t);
+
+// ============================================================== vectors
+template <class Tin, class Tout>
+__global__ void cast_kernel(const Tin* __restrict__ x, int ldx, Tout* __restrict__ y, int ldy,
+                            int64_t rows, const int* cols_dev, int cols_const, int colcap) {
+  const int cols = cols_dev ? *cols_dev : cols_const;
+  const int64_t total = rows * colcap;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e / colcap;
+    const int c = int(e - r * colcap);
+    if (c < cols) y[r * ldy + c] = Tout(x[r * ldx + c]);
+  }
+}
+
+template <class Tin, class Tout>
+void launch_cast(const Tin* x, int ldx, Tout* y, int ldy, int64_t rows, const int* cols_dev,
+                 int cols_const, int colcap, hipStream_t s) {
+  const int64_t total = rows * colcap;
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(ceil_div(total, 256), 1), 8192);
+  hipLaunchKernelGGL((cast_kernel<Tin, Tout>), dim3(unsigned(blocks)), dim3(256), 0, s, x, ldx, y,
+                     ldy, rows, cols_dev, cols_const, colcap);
+  LRC_HIP(hipGetLastError());
+}
+template void launch_cast<double, float>(const double*, int, float*, int, int64_t, const int*, int,
+                                         int, hipStream_t);
+template void launch_cast<float, double>(const float*, int, double*, int, int64_t, const int*, int,
+                                         int, hipStream_t);
+template void launch_cast<double, double>(const double*, int, double*, int, int64_t, const int*,
+                                          int, int, hipStream_t);
+template void launch_cast<float, float>(const float*, int, float*, int, int64_t, const int*, int,
+                                        int, hipStream_t);
+
+// sum of squares of a vector in fixed order: blocks write partials, the last
+// stage (one block) adds them.
+__global__ void sumsq_partial(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    a += x[i] * x[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void sumsq_final(const double* __restrict__ part, int np, double* out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) a += part[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s) {
+  // `out` must hold 1 + 256 doubles: out[0] result, out[1..256] partials
+  hipLaunchKernelGGL(sumsq_partial, dim3(256), dim3(256), 0, s, x, n, out + 1);
+  hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, s, out + 1, 256, out);
+  LRC_HIP(hipGetLastError());
+}
+
+// r = f - sum_i coef_i W_i   (single column)
+struct VecPtrs {
+  double* W[kMaxOps];
+};
+__global__ void vec_resid_kernel(const double* __restrict__ f, VecPtrs Wp,
+                                 const double* __restrict__ coef, int q, int64_t n,
+                                 double* __restrict__ r) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    double v = f[i];
+    for (int t = 0; t < q; ++t) v -= coef[t] * Wp.W[t][i * 8];
+    r[i * 8] = v;
+  }
+}
+void launch_vec_resid(const double* f, double* const* W, const double* coef, int q, int64_t n,
+                      double* r, hipStream_t s) {
+  VecPtrs p;
+  for (int i = 0; i < q; ++i) p.W[i] = W[i];
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 4096);
+  hipLaunchKernelGGL(vec_resid_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, f, p, coef, q, n,
+                     r);
+  LRC_HIP(hipGetLastError());
+}
+
+// Chebyshev step on single columns stored with stride 8:
+//   dl = alpha * dl + beta * z ;  x += dl
+__global__ void vec_cheb_kernel(double* __restrict__ x, double* __restrict__ dl,
+                                const double* __restrict__ z, int64_t n, double alpha,
+                                double beta) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double d = alpha * dl[i * 8] + beta * z[i * 8];
+    dl[i * 8] = d;
+    x[i * 8] += d;
+  }
+}
+void launch_vec_cheb_update(double* x, double* dl, const double* z, int64_t n, double alpha,
+                            double beta, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 4096);
+  hipLaunchKernelGGL(vec_cheb_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, dl, z, n, alpha,
+                     beta);
+  LRC_HIP(hipGetLastError());
+}
+
+__global__ void fill_kernel(double* p, int64_t count, double v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+void launch_fill(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t blocks = std::min<int64_t>(ceil_div(count, 256), 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, count, v);
+  LRC_HIP(hipGetLastError());
+}
+
+__global__ void copy_cols_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst,
+                                 int ldd, int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e / cols;
+    const int c = int(e - r * cols);
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+void launch_copy_cols(const double* src, int lds, double* dst, int ldd, int64_t rows, int cols,
+                      hipStream_t s) {
+  if (rows * cols == 0) return;
+  const int64_t blocks = std::min<int64_t>(ceil_div(rows * cols, 256), 8192);
+  hipLaunchKernelGGL(copy_cols_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, cols);
+  LRC_HIP(hipGetLastError());
+}
+
+}  // namespace lrc

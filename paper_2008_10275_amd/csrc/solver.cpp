@@ -1,0 +1,684 @@
+// Host orchestration of the low-rank ChebyshevT solve (see solver.hpp).
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace lrc {
+
+using clk = std::chrono::steady_clock;
+static double secs_since(clk::time_point a) {
+  return std::chrono::duration<double>(clk::now() - a).count();
+}
+
+// One JSON line per residual check on stderr when LRC_LOG is set.
+static bool log_enabled() {
+  static const bool on = std::getenv("LRC_LOG") != nullptr;
+  return on;
+}
+static void log_line(const char* phase, int it, double norm, double ref) {
+  if (!log_enabled()) return;
+  std::fprintf(stderr, "{\"phase\": \"%s\", \"iter\": %d, \"norm\": %.6e, \"rel\": %.6e}\n",
+               phase, it, norm, ref > 0 ? norm / ref : 0.0);
+}
+
+// ------------------------------------------------------------------ Ops
+void Ops::upload_values(int i) {
+  const auto& h = host[i];
+  std::vector<float> v32(h.val.begin(), h.val.end());
+  hipStream_t s = ctx->stream;
+  LRC_HIP(hipMemcpyAsync(val64[i].p, h.val.data(), h.val.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(val32[i].p, v32.data(), v32.size() * 4, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipStreamSynchronize(s));   // v32 is a temporary
+}
+
+// ------------------------------------------------------------------ LR
+template <class T>
+void LR<T>::alloc(int64_t n_, int64_t m_, int cap_, hipStream_t st) {
+  n = n_;
+  m = m_;
+  cap = std::max(cap_, 1);
+  ld = ld_for(cap);
+  U.alloc(size_t(std::max<int64_t>(n, 1)) * ld * sizeof(T));
+  V.alloc(size_t(std::max<int64_t>(m, 1)) * ld * sizeof(T));
+  s.alloc(size_t(std::max(cap, 8)) * sizeof(double));
+  rank.alloc(16);
+  LRC_HIP(hipMemsetAsync(rank.p, 0, 16, st));
+  LRC_HIP(hipMemsetAsync(s.p, 0, s.bytes, st));
+}
+template struct LR<double>;
+template struct LR<float>;
+
+template <class T>
+BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double* rowscale) {
+  BlockView<T> v{};
+  v.nb = 1;
+  v.ptr[0] = p;
+  v.ld[0] = ld;
+  v.wdev[0] = wdev;
+  v.wconst[0] = wconst;
+  v.rowscale[0] = rowscale;
+  return v;
+}
+template BlockView<double> view1(const double*, int, const int*, int, const double*);
+template BlockView<float> view1(const float*, int, const int*, int, const double*);
+
+template <class T>
+static void add_block(BlockView<T>& v, const T* p, int ld, const int* wdev, int wconst,
+                      const double* rowscale = nullptr) {
+  LRC_CHECK(v.nb < kMaxBlocks, ST_EINVAL, "too many factor blocks (increase kMaxBlocks)");
+  const int b = v.nb++;
+  v.ptr[b] = p;
+  v.ld[b] = ld;
+  v.wdev[b] = wdev;
+  v.wconst[b] = wconst;
+  v.rowscale[b] = rowscale;
+}
+
+static void add_core(CoreView& c, const double* s, double coef, const int* wdev, int wconst) {
+  LRC_CHECK(c.nb < kMaxBlocks, ST_EINVAL, "too many core blocks");
+  const int b = c.nb++;
+  c.s[b] = s;
+  c.coef[b] = coef;
+  c.wdev[b] = wdev;
+  c.wconst[b] = wconst;
+}
+
+// ------------------------------------------------------------------ Truncator
+template <class T>
+void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
+  if (nmax_ <= nmax && mmax_ <= mmax && small.p) return;
+  nmax = std::max(nmax, nmax_);
+  mmax = std::max(mmax, mmax_);
+  kcap = kTruncCap;
+  ldq = kTruncCap;
+  max_rounds = 30 * (kcap - 1);
+  const size_t kk = size_t(kcap) * kcap;
+  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, XA, XB + invsig
+  const size_t arena = 16 * kk + kcap;
+  small.alloc(arena * sizeof(double));
+  double* b = small.as<double>();
+  for (int x = 0; x < 2; ++x) {
+    st.G[x] = b; b += kk;
+    st.R1[x] = b; b += kk;
+    st.T1[x] = b; b += kk;
+    st.R2[x] = b; b += kk;
+    st.R2i[x] = b; b += kk;
+  }
+  st.M = b; b += kk;
+  st.H = b; b += kk;
+  st.VM = b; b += kk;
+  st.W = b; b += kk;
+  st.XA = b; b += kk;
+  st.XB = b; b += kk;
+  st.invsig = b; b += kcap;
+  LRC_CHECK(size_t(b - small.as<double>()) == arena, ST_EINVAL, "truncation arena layout");
+  rot.alloc(size_t(max_rounds) * 64 * 2 * sizeof(double));
+  st.rot = rot.as<double>();
+  ints.alloc((kcap + 16) * sizeof(int));
+  int* ib = ints.as<int>();
+  st.order = ib;
+  st.rounds = ib + kcap;
+  st.k = ib + kcap + 1;
+  st.info = ib + kcap + 2;
+  LRC_HIP(hipMemsetAsync(small.p, 0, small.bytes, s));
+  LRC_HIP(hipMemsetAsync(ints.p, 0, ints.bytes, s));
+  gram_bytes = gram_workspace_bytes(nmax, mmax, kcap, sizeof(T) == 8);
+  gram_ws.alloc(gram_bytes);
+  Q1A.alloc(size_t(nmax) * ldq * sizeof(T));
+  Q1B.alloc(size_t(mmax) * ldq * sizeof(T));
+}
+
+template <class T>
+void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
+                       const CoreView& core, int rank_cap, double tol, T* Uout, int ldu,
+                       T* Vout, int ldv, double* s_out, int* rank_out, double* norm_out,
+                       hipStream_t s) {
+  LRC_CHECK(n <= nmax && m <= mmax, ST_EINVAL, "truncation workspace too small");
+  LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
+            "truncation: rank cap must be in [1, 64] and fit the output leading dimensions");
+  const double eps = sizeof(T) == 8 ? 1e-14 : 1e-6;
+  T* qa = Q1A.as<T>();
+  T* qb = Q1B.as<T>();
+  GramJob<T> g1[2] = {{A, n, st.G[0], st.k}, {B, m, st.G[1], nullptr}};
+  launch_gram<T>(g1, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info, s);
+  launch_chol(st, 1, kcap, eps, s);
+  TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
+  launch_tsmm<T>(t1, 2, kcap, kcap, s);
+  const BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
+  GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
+  launch_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info, s);
+  launch_chol(st, 2, kcap, eps, s);
+  launch_core_jacobi(st, core, kcap, max_rounds, s);
+  launch_jacobi_replay(st, kcap, s);
+  launch_trunc_finish(st, kcap, rank_cap, tol, s_out, rank_out, norm_out, s);
+  TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
+                      {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
+  launch_tsmm<T>(t2, 2, kcap, rank_cap, s);
+}
+template struct Truncator<double>;
+template struct Truncator<float>;
+
+// ------------------------------------------------------------------ ChebyshevT
+template <class T> static const std::vector<DevCsr<T>>& ops_dev(const Ops& o);
+template <> const std::vector<DevCsr<double>>& ops_dev<double>(const Ops& o) { return o.d64; }
+template <> const std::vector<DevCsr<float>>& ops_dev<float>(const Ops& o) { return o.d32; }
+
+template <class T>
+void Cheb<T>::alloc(Prob* p, int cap_) {
+  P = p;
+  cap = cap_;
+  hipStream_t s = P->ctx->stream;
+  const int64_t n = P->ops->n, m = P->m;
+  S.alloc(n, m, cap, s);
+  D.alloc(n, m, cap, s);
+  R.alloc(n, m, cap, s);
+  const int ld = ld_for(cap);
+  W.alloc(size_t(P->ops->q) * n * ld * sizeof(T));
+  Z.alloc(size_t(n) * ld * sizeof(T));
+  py.alloc(size_t(n) * ld * sizeof(T));
+  px.alloc(size_t(n) * ld * sizeof(T));
+  const int64_t cbr = P->prec ? P->prec->cb_rows : 0;
+  pcb.alloc(size_t(std::max<int64_t>(cbr, 1)) * ld * sizeof(T));
+  norm.alloc(64);
+  tr.alloc(n, m, s);
+}
+
+template <class T>
+void Cheb<T>::spmm(const T* U, int ldu, const int* r_dev) {
+  const Ops& o = *P->ops;
+  const int ld = ld_for(cap);
+  T* Wp[kMaxOps];
+  for (int i = 0; i < o.q; ++i) Wp[i] = W.as<T>() + size_t(i) * o.n * ld;
+  launch_spmm<T>(ops_dev<T>(o).data(), o.q, U, ldu, r_dev, 0, cap, Wp, ld,
+                 sizeof(T) == 8 ? 2 : 4, P->ctx->stream);
+}
+
+template <class T>
+void Cheb<T>::residual(const LR<T>& B, double* norm_dev) {
+  const Ops& o = *P->ops;
+  const int ld = ld_for(cap);
+  spmm(S.u(), S.ld, S.r());
+  BlockView<T> A{}, Bv{};
+  CoreView c{};
+  add_block(A, B.u(), B.ld, B.r(), 0);
+  add_block(Bv, B.v(), B.ld, B.r(), 0);
+  add_core(c, B.sv(), 1.0, B.r(), 0);
+  for (int i = 0; i < o.q; ++i) {
+    add_block(A, W.as<T>() + size_t(i) * o.n * ld, ld, S.r(), 0);
+    add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
+    add_core(c, S.sv(), -1.0, S.r(), 0);
+  }
+  tr.run(A, o.n, Bv, P->m, c, cap, 0.0, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev,
+         P->ctx->stream);
+}
+
+template <class T>
+void Cheb<T>::precond(const T* Rm, int ldr, const int* k_dev, T* Zm, int ldz) {
+  const int ld = ld_for(cap);
+  launch_prec_apply<T>(P->prec->dev<T>(), P->prec->fwd, P->prec->bwd, Rm, ldr, Zm, ldz, k_dev, 0,
+                       cap, py.as<T>(), px.as<T>(), pcb.as<T>(), ld, P->ctx->stream);
+}
+
+template <class T>
+int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c, double dc,
+                   int max_iter, bool* converged, double* last_norm, int* prec_applies,
+                   int* flags, double abs_target, int stall_limit) {
+  Ctx& ctx = *P->ctx;
+  hipStream_t s = ctx.stream;
+  const int64_t n = P->ops->n, m = P->m;
+  const int ld = ld_for(cap);
+  const double tol = o.trunc_tol;
+  c = std::max(c, 1e-12 * dc);
+  const double sigma = dc / c;
+  LRC_HIP(hipMemsetAsync(S.rank.p, 0, 16, s));
+  LRC_HIP(hipMemsetAsync(D.rank.p, 0, 16, s));
+  double* nd = norm.as<double>();
+  auto read_norm = [&]() {
+    LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, sizeof(double), hipMemcpyDeviceToHost, s));
+    ctx.sync();
+    return ctx.pinned[0];
+  };
+  // residual truncation uses the solver's tolerance relative to the residual
+  auto resid = [&]() {
+    const Ops& op = *P->ops;
+    spmm(S.u(), S.ld, S.r());
+    BlockView<T> A{}, Bv{};
+    CoreView cv{};
+    add_block(A, B.u(), B.ld, B.r(), 0);
+    add_block(Bv, B.v(), B.ld, B.r(), 0);
+    add_core(cv, B.sv(), 1.0, B.r(), 0);
+    for (int i = 0; i < op.q; ++i) {
+      add_block(A, W.as<T>() + size_t(i) * op.n * ld, ld, S.r(), 0);
+      add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
+      add_core(cv, S.sv(), -1.0, S.r(), 0);
+    }
+    tr.run(A, n, Bv, m, cv, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), nd, s);
+    return read_norm();
+  };
+  int iters = 0;
+  *converged = false;
+  const char* phase = sizeof(T) == 8 ? "cheb64" : "cheb32";
+  double nr = resid();
+  *last_norm = nr;
+  log_line(phase, iters, nr, ref_norm);
+  const double target = std::max(o.res_tol * ref_norm, abs_target);
+  const int cycle = o.restart > 0 ? o.restart : (1 << 30);
+  double best = nr;
+  int stall = 0;
+  while (true) {
+    if (!(nr > target)) { *converged = true; break; }
+    if (iters >= max_iter || !std::isfinite(nr) || stall >= stall_limit) break;
+    // (re)start
+    precond(R.u(), R.ld, R.r(), Z.as<T>(), ld);
+    ++*prec_applies;
+    {
+      BlockView<T> A = view1<T>(Z.as<T>(), ld, R.r(), 0);
+      BlockView<T> Bv = view1<T>(R.v(), R.ld, R.r(), 0);
+      CoreView cv{};
+      add_core(cv, R.sv(), 1.0 / dc, R.r(), 0);
+      tr.run(A, n, Bv, m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(), nd + 1, s);
+    }
+    double rho = c / dc;
+    for (int k = 0; k < cycle; ++k) {
+      {   // S <- T(S + D)
+        BlockView<T> A{}, Bv{};
+        CoreView cv{};
+        add_block(A, S.u(), S.ld, S.r(), 0);
+        add_block(A, D.u(), D.ld, D.r(), 0);
+        add_block(Bv, S.v(), S.ld, S.r(), 0);
+        add_block(Bv, D.v(), D.ld, D.r(), 0);
+        add_core(cv, S.sv(), 1.0, S.r(), 0);
+        add_core(cv, D.sv(), 1.0, D.r(), 0);
+        tr.run(A, n, Bv, m, cv, cap, tol, S.u(), S.ld, S.v(), S.ld, S.sv(), S.r(), nd + 2, s);
+      }
+      ++iters;
+      nr = resid();
+      *last_norm = nr;
+      log_line(phase, iters, nr, ref_norm);
+      // stagnation: no 30% gain over the best residual for `stall_limit` checks
+      if (nr < 0.7 * best) { best = nr; stall = 0; }
+      else { best = std::min(best, nr); ++stall; }
+      if (!(nr > target) || iters >= max_iter || k == cycle - 1 || !std::isfinite(nr) ||
+          stall >= stall_limit)
+        break;
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      precond(R.u(), R.ld, R.r(), Z.as<T>(), ld);
+      ++*prec_applies;
+      {   // D <- T(rho' rho D + (2 rho' / c) P^-1 R)
+        BlockView<T> A{}, Bv{};
+        CoreView cv{};
+        add_block(A, D.u(), D.ld, D.r(), 0);
+        add_block(A, Z.as<T>(), ld, R.r(), 0);
+        add_block(Bv, D.v(), D.ld, D.r(), 0);
+        add_block(Bv, R.v(), R.ld, R.r(), 0);
+        add_core(cv, D.sv(), rho_new * rho, D.r(), 0);
+        add_core(cv, R.sv(), 2.0 * rho_new / c, R.r(), 0);
+        tr.run(A, n, Bv, m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(), nd + 1, s);
+      }
+      rho = rho_new;
+    }
+  }
+  LRC_HIP(hipMemcpyAsync(ctx.pinned_i, tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  ctx.sync();
+  *flags |= ctx.pinned_i[0];
+  return iters;
+}
+template struct Cheb<double>;
+template struct Cheb<float>;
+
+// ------------------------------------------------------------------ helpers
+static void upload_lr(LR<double>& X, int r, const double* Uh, const double* sh, const double* Vh,
+                      hipStream_t s) {
+  // host column-major -> device row-major
+  std::vector<double> u(size_t(X.n) * X.ld, 0.0), v(size_t(X.m) * X.ld, 0.0),
+      sv(size_t(std::max(X.cap, 8)), 0.0);
+  for (int j = 0; j < r; ++j) {
+    for (int64_t i = 0; i < X.n; ++i) u[size_t(i) * X.ld + j] = Uh[size_t(j) * X.n + i];
+    for (int64_t i = 0; i < X.m; ++i) v[size_t(i) * X.ld + j] = Vh[size_t(j) * X.m + i];
+    sv[j] = sh ? sh[j] : 1.0;
+  }
+  LRC_HIP(hipMemcpyAsync(X.U.p, u.data(), u.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X.V.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X.s.p, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X.rank.p, &r, sizeof(int), hipMemcpyHostToDevice, s));
+  LRC_HIP(hipStreamSynchronize(s));
+}
+
+template <class Tin, class Tout>
+static void cast_lr(const LR<Tin>& a, LR<Tout>& b, hipStream_t s) {
+  const int cap = std::min(a.cap, b.cap);
+  launch_cast<Tin, Tout>(a.u(), a.ld, b.u(), b.ld, a.n, a.r(), 0, cap, s);
+  launch_cast<Tin, Tout>(a.v(), a.ld, b.v(), b.ld, a.m, a.r(), 0, cap, s);
+  LRC_HIP(hipMemcpyAsync(b.s.p, a.s.p, size_t(cap) * 8, hipMemcpyDeviceToDevice, s));
+  LRC_HIP(hipMemcpyAsync(b.rank.p, a.rank.p, sizeof(int), hipMemcpyDeviceToDevice, s));
+}
+
+static int read_rank(Ctx& ctx, const int* r) {
+  LRC_HIP(hipMemcpyAsync(ctx.pinned_i, r, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return ctx.pinned_i[0];
+}
+
+// Entry-wise fp64 residual of X = X0 + S.
+double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S, double* colres) {
+  Ctx& ctx = *P.ctx;
+  hipStream_t s = ctx.stream;
+  const Ops& o = *P.ops;
+  const int64_t n = o.n, m = P.m;
+  const int ld0 = X0.ld, lds = S.ld;
+  DevBuf W0(size_t(o.q) * n * ld0 * 8), WS(size_t(o.q) * n * lds * 8);
+  double* W0p[kMaxOps];
+  double* WSp[kMaxOps];
+  for (int i = 0; i < o.q; ++i) {
+    W0p[i] = W0.as<double>() + size_t(i) * n * ld0;
+    WSp[i] = WS.as<double>() + size_t(i) * n * lds;
+  }
+  if (r0 > 0) launch_spmm<double>(o.d64.data(), o.q, X0.u(), ld0, X0.r(), 0, X0.cap, W0p, ld0, 2, s);
+  launch_spmm<double>(o.d64.data(), o.q, S.u(), lds, S.r(), 0, S.cap, WSp, lds, 2, s);
+  BlockView<double> A{}, B{};
+  CoreView c{};
+  add_block(A, P.F64.u(), P.F64.ld, P.F64.r(), 0);
+  add_block(B, P.F64.v(), P.F64.ld, P.F64.r(), 0);
+  add_core(c, P.F64.sv(), 1.0, P.F64.r(), 0);
+  for (int i = 0; i < o.q; ++i) {
+    if (r0 > 0) {
+      add_block(A, W0p[i], ld0, X0.r(), 0);
+      add_block(B, X0.v(), ld0, X0.r(), 0, P.drow(i));
+      add_core(c, X0.sv(), -1.0, X0.r(), 0);
+    }
+    add_block(A, WSp[i], lds, S.r(), 0);
+    add_block(B, S.v(), lds, S.r(), 0, P.drow(i));
+    add_core(c, S.sv(), -1.0, S.r(), 0);
+  }
+  LRC_CHECK(P.rF + o.q * (X0.cap + S.cap) <= 192, ST_EINVAL,
+            "fp64 residual: more than 192 concatenated columns");
+  DevBuf colsq(size_t(m) * 8);
+  const size_t wsb = residual_workspace_bytes(n, m);
+  DevBuf ws(wsb);
+  launch_residual_fp64(A, n, B, c, m, 192, colsq.as<double>(), ws.as<double>(), wsb, s);
+  std::vector<double> h(m);
+  LRC_HIP(hipMemcpyAsync(h.data(), colsq.p, size_t(m) * 8, hipMemcpyDeviceToHost, s));
+  ctx.sync();
+  double tot = 0.0;
+  for (int64_t j = 0; j < m; ++j) {
+    tot += h[j];
+    if (colres) colres[j] = std::sqrt(std::max(h[j], 0.0));
+  }
+  return std::sqrt(tot);
+}
+
+// Right-hand side B = F - L(X0) in factored fp64 form (not truncated by rank
+// beyond the truncation capacity), into Bout.
+static void build_rhs(Prob& P, const LR<double>& X0, int r0, LR<double>& Bout, const lrc_opts& o,
+                      Truncator<double>& tr) {
+  Ctx& ctx = *P.ctx;
+  hipStream_t s = ctx.stream;
+  const Ops& op = *P.ops;
+  const int64_t n = op.n, m = P.m;
+  if (r0 == 0) {
+    LRC_CHECK(P.rF <= Bout.cap, ST_EINVAL,
+              "right-hand side rank exceeds the room left by q * rank_cap in 128 columns");
+    cast_lr<double, double>(P.F64, Bout, s);
+    return;
+  }
+  const int ld0 = X0.ld;
+  DevBuf W0(size_t(op.q) * n * ld0 * 8);
+  double* W0p[kMaxOps];
+  for (int i = 0; i < op.q; ++i) W0p[i] = W0.as<double>() + size_t(i) * n * ld0;
+  launch_spmm<double>(op.d64.data(), op.q, X0.u(), ld0, X0.r(), 0, X0.cap, W0p, ld0, 2, s);
+  BlockView<double> A{}, B{};
+  CoreView c{};
+  add_block(A, P.F64.u(), P.F64.ld, P.F64.r(), 0);
+  add_block(B, P.F64.v(), P.F64.ld, P.F64.r(), 0);
+  add_core(c, P.F64.sv(), 1.0, P.F64.r(), 0);
+  for (int i = 0; i < op.q; ++i) {
+    add_block(A, W0p[i], ld0, X0.r(), 0);
+    add_block(B, X0.v(), ld0, X0.r(), 0, P.drow(i));
+    add_core(c, X0.sv(), -1.0, X0.r(), 0);
+  }
+  DevBuf nrm(16);
+  const int cap = std::min(Bout.cap, 64);
+  tr.run(A, n, B, m, c, cap, std::min(1e-14, o.trunc_tol * 1e-3), Bout.u(), Bout.ld, Bout.v(),
+         Bout.ld, Bout.sv(), Bout.r(), nrm.as<double>(), s);
+}
+
+// Median-parameter solve  A(d_med) x = F[:, jmed]  by preconditioned Chebyshev
+// on one column (fp64, no truncation needed).
+static int median_solve(Prob& P, int jmed, double c, double dc, double tol, int max_iter,
+                        LR<double>& X0) {
+  Ctx& ctx = *P.ctx;
+  hipStream_t s = ctx.stream;
+  const Ops& op = *P.ops;
+  const int64_t n = op.n, m = P.m;
+  // f = FU diag(Fs) FV[jmed, :]^T
+  std::vector<double> f(n, 0.0);
+  for (int a = 0; a < P.rF; ++a) {
+    const double w = P.Fs[a] * P.FV[size_t(a) * m + jmed];
+    for (int64_t i = 0; i < n; ++i) f[i] += w * P.FU[size_t(a) * n + i];
+  }
+  double fn = 0.0;
+  for (double v : f) fn += v * v;
+  fn = std::sqrt(fn);
+  std::vector<double> coef(op.q);
+  for (int i = 0; i < op.q; ++i) coef[i] = P.d[size_t(jmed) * op.q + i];
+  DevBuf fd = upload(f, s), cd = upload(coef, s);
+  const int ld = 8;
+  DevBuf x(size_t(n) * ld * 8), dl(size_t(n) * ld * 8), r(size_t(n) * ld * 8),
+      z(size_t(n) * ld * 8), Wb(size_t(op.q) * n * ld * 8), nrm(300 * 8);
+  LRC_HIP(hipMemsetAsync(x.p, 0, x.bytes, s));
+  LRC_HIP(hipMemsetAsync(dl.p, 0, dl.bytes, s));
+  LRC_HIP(hipMemsetAsync(r.p, 0, r.bytes, s));
+  LRC_HIP(hipMemsetAsync(z.p, 0, z.bytes, s));
+  const int64_t cbr = P.prec->cb_rows;
+  DevBuf py(size_t(n) * ld * 8), px(size_t(n) * ld * 8), pcb(size_t(std::max<int64_t>(cbr, 1)) * ld * 8);
+  double* Wp[kMaxOps];
+  for (int i = 0; i < op.q; ++i) Wp[i] = Wb.as<double>() + size_t(i) * n * ld;
+  auto residual = [&]() {
+    launch_spmm<double>(op.d64.data(), op.q, x.as<double>(), ld, nullptr, 1, 1, Wp, ld, 2, s);
+    launch_vec_resid(fd.as<double>(), Wp, cd.as<double>(), op.q, n, r.as<double>(), s);
+    // norm of column 0 (stride 8): copy to a packed vector via cast (1 column)
+    launch_cast<double, double>(r.as<double>(), ld, z.as<double>(), 1, n, nullptr, 1, 1, s);
+    launch_sumsq(z.as<double>(), n, nrm.as<double>(), s);
+    LRC_HIP(hipMemcpyAsync(ctx.pinned, nrm.p, 8, hipMemcpyDeviceToHost, s));
+    ctx.sync();
+    return std::sqrt(ctx.pinned[0]);
+  };
+  auto prec = [&]() {
+    launch_prec_apply<double>(P.prec->p64, P.prec->fwd, P.prec->bwd, r.as<double>(), ld,
+                              z.as<double>(), ld, nullptr, 1, 1, py.as<double>(), px.as<double>(),
+                              pcb.as<double>(), ld, s);
+  };
+  c = std::max(c, 1e-12 * dc);
+  const double sigma = dc / c;
+  double nr = residual();
+  int it = 0;
+  if (nr > tol * fn) {
+    prec();
+    // dl = z / dc ; x += dl
+    launch_vec_cheb_update(x.as<double>(), dl.as<double>(), z.as<double>(), n, 0.0, 1.0 / dc, s);
+    double rho = c / dc;
+    ++it;
+    nr = residual();
+    while (nr > tol * fn && it < max_iter && std::isfinite(nr)) {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      prec();
+      launch_vec_cheb_update(x.as<double>(), dl.as<double>(), z.as<double>(), n, rho_new * rho,
+                             2.0 * rho_new / c, s);
+      rho = rho_new;
+      ++it;
+      nr = residual();
+    }
+  }
+  // X0 = x 1^T
+  X0.alloc(n, m, 1, s);
+  launch_copy_cols(x.as<double>(), ld, X0.u(), X0.ld, n, 1, s);
+  std::vector<double> ones(size_t(m) * X0.ld, 0.0);
+  for (int64_t j = 0; j < m; ++j) ones[size_t(j) * X0.ld] = 1.0;
+  const double one = 1.0;
+  const int r1 = 1;
+  LRC_HIP(hipMemcpyAsync(X0.V.p, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X0.s.p, &one, 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X0.rank.p, &r1, 4, hipMemcpyHostToDevice, s));
+  ctx.sync();
+  return it;
+}
+
+// ------------------------------------------------------------------ solve
+lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
+                         const double* V0, lrc_info* info) {
+  auto t0 = clk::now();
+  Ctx& ctx = *P.ctx;
+  hipStream_t s = ctx.stream;
+  const Ops& op = *P.ops;
+  const int64_t n = op.n, m = P.m;
+  LRC_CHECK(P.prec != nullptr, ST_EINVAL, "lrc_solve: call lrc_prob_precondition first");
+  LRC_CHECK(o.rank_cap >= 1 && o.rank_cap <= kPrecCols, ST_EINVAL,
+            "lrc_solve: rank_cap must be in [1, 64]");
+  LRC_CHECK(o.trunc_tol >= 0.0 && o.res_tol >= 0.0, ST_EINVAL, "lrc_solve: negative tolerance");
+  double c = o.cheb_c, dc = o.cheb_d;
+  if (!(c > 0.0) || !(dc > 0.0)) {
+    double lo = 1.0, hi = 1.0;
+    for (int64_t j = 0; j < m; ++j)
+      for (int i = 0; i < op.q; ++i) {
+        const double rt = P.d[size_t(j) * op.q + i] / P.dbar[i];
+        lo = std::min(lo, rt);
+        hi = std::max(hi, rt);
+      }
+    c = 0.5 * (hi - lo);
+    dc = 0.5 * (hi + lo);
+  }
+  lrc_info inf{};
+  // fixed initial term X0
+  P.X0 = LR<double>();
+  P.rank_x0 = 0;
+  if (o.init == LRC_INIT_MEDIAN) {
+    const int jmed = int(m / 2);
+    inf.median_iters = median_solve(P, jmed, c, dc, o.median_tol > 0 ? o.median_tol : 1e-10,
+                                    1000, P.X0);
+    P.rank_x0 = 1;
+  } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
+    LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
+    LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
+    P.X0.alloc(n, m, r0, s);
+    upload_lr(P.X0, r0, U0, s0, V0, s);
+    P.rank_x0 = r0;
+  } else {
+    P.X0.alloc(n, m, 1, s);
+  }
+  const int cap = o.rank_cap;
+  // room left for the right-hand side in the residual concatenation
+  // [B | K_0 S | ... | K_{q-1} S] of at most 128 columns
+  const int room = std::max(8, kTruncCap - op.q * cap);
+  const int bcap = std::min(std::min(64, room), std::max(P.rF + op.q, o.init == LRC_INIT_GIVEN ? 64 : 1));
+  Cheb<double> c64;
+  c64.alloc(&P, cap);
+  LR<double> B64;
+  B64.alloc(n, m, bcap, s);
+  build_rhs(P, P.X0, P.rank_x0, B64, o, c64.tr);
+  int flags = 0, iters = 0, papp = 0, refinements = 0;
+  bool conv = false;
+  double last = 0.0;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  if (o.precision == LRC_FP64) {
+    iters = c64.solve(B64, P.fnorm, o, c, dc, max_iter, &conv, &last, &papp, &flags);
+    P.S = std::move(c64.S);
+  } else {
+    // fp32 inner ChebyshevT wrapped in fp64 iterative refinement.  The inner
+    // right-hand side is the fp64 residual truncated to rank <= cap, so the
+    // inner correction gets its own cap to keep [rhs | K_i E] within 128 columns.
+    const int inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
+    Cheb<float> c32;
+    c32.alloc(&P, inner_cap);
+    LR<float> Bin;
+    Bin.alloc(n, m, cap, s);
+    LR<double> E64;
+    E64.alloc(n, m, inner_cap, s);
+    LR<double>& S64 = c64.S;
+    LRC_HIP(hipMemsetAsync(S64.rank.p, 0, 16, s));
+    double* nd = c64.norm.as<double>();
+    const double target = o.res_tol * P.fnorm;
+    const int refine_max = o.refine_max > 0 ? o.refine_max : 8;
+    while (true) {
+      // fp64 residual, truncated to the rank cap: the right-hand side of the correction
+      c64.residual(B64, nd);
+      LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, 8, hipMemcpyDeviceToHost, s));
+      ctx.sync();
+      last = ctx.pinned[0];
+      log_line("refine64", refinements, last, P.fnorm);
+      if (!(last > target)) { conv = true; break; }
+      if (refinements >= refine_max || iters >= max_iter || !std::isfinite(last)) break;
+      cast_lr<double, float>(c64.R, Bin, s);
+      lrc_opts oi = o;
+      oi.res_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+      bool cin = false;
+      double lin = 0.0;
+      // stop the inner solve at its relative tolerance, at a fraction of the
+      // outer target, or when the fp32 residual stagnates at its rounding floor
+      iters += c32.solve(Bin, last, oi, c, dc, max_iter - iters, &cin, &lin, &papp, &flags,
+                         0.5 * target, 2);
+      ++refinements;
+      cast_lr<float, double>(c32.S, E64, s);
+      BlockView<double> A{}, Bv{};
+      CoreView cv{};
+      add_block(A, S64.u(), S64.ld, S64.r(), 0);
+      add_block(A, E64.u(), E64.ld, E64.r(), 0);
+      add_block(Bv, S64.v(), S64.ld, S64.r(), 0);
+      add_block(Bv, E64.v(), E64.ld, E64.r(), 0);
+      add_core(cv, S64.sv(), 1.0, S64.r(), 0);
+      add_core(cv, E64.sv(), 1.0, E64.r(), 0);
+      c64.tr.run(A, n, Bv, m, cv, cap, o.trunc_tol, S64.u(), S64.ld, S64.v(), S64.ld, S64.sv(),
+                 S64.r(), nd + 3, s);
+    }
+    LRC_HIP(hipMemcpyAsync(ctx.pinned_i, c64.tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    ctx.sync();
+    flags |= ctx.pinned_i[0];
+    P.S = std::move(c64.S);
+  }
+  P.rank_s = read_rank(ctx, P.S.r());
+  inf.rank = P.rank_s;
+  inf.rank_x0 = P.rank_x0;
+  inf.iters = iters;
+  inf.prec_applies = papp;
+  inf.refinements = refinements;
+  inf.relres_est = last / P.fnorm;
+  inf.relres = inf.relres_est;
+  inf.info_flags = flags;
+  if (o.verify_fp64) {
+    std::vector<double> col(m);
+    const double nr = residual_fp64(P, P.X0, P.rank_x0, P.S, col.data());
+    inf.relres = nr / P.fnorm;
+    // per-column relative residuals against ||F_j||, with G = FU^T FU
+    std::vector<double> g(size_t(P.rF) * P.rF, 0.0);
+    for (int a = 0; a < P.rF; ++a)
+      for (int b = 0; b < P.rF; ++b) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) acc += P.FU[size_t(a) * n + i] * P.FU[size_t(b) * n + i];
+        g[size_t(a) * P.rF + b] = acc;
+      }
+    double mx = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+      double fj = 0.0;
+      for (int a = 0; a < P.rF; ++a)
+        for (int b = 0; b < P.rF; ++b)
+          fj += P.FV[size_t(a) * m + j] * P.Fs[a] * g[size_t(a) * P.rF + b] * P.Fs[b] *
+                P.FV[size_t(b) * m + j];
+      if (fj > 0) mx = std::max(mx, col[j] / std::sqrt(fj));
+    }
+    inf.max_col_relres = mx;
+  }
+  inf.seconds_setup = P.seconds_setup;
+  inf.seconds_solve = secs_since(t0);
+  if (info) *info = inf;
+  if (flags & 8)
+    throw Error(ST_EINVAL, "truncation capacity exceeded: more than 128 concatenated columns "
+                           "(reduce rank_cap or the rank of the right-hand side)");
+  const bool ok = conv && (!o.verify_fp64 || inf.relres <= o.res_tol);
+  return ok ? ST_OK : ST_NOTCONV;
+}
+
+}  // namespace lrc

@@ -1,0 +1,130 @@
+// Solver core: operators, preconditioner, truncation engine and the
+// ChebyshevT iteration (host orchestration of the HIP kernels).
+#pragma once
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/lrcheb.h"
+#include "host/ndfact.h"
+#include "kernels.hpp"
+
+namespace lrc {
+
+constexpr int kTruncCap = 128;   // max concatenated columns of a truncation
+constexpr int kPrecCols = 64;    // max right-hand sides per preconditioner apply
+
+struct Ctx {
+  void* handle = nullptr;        // the lrc_ctx that owns this context
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double* pinned = nullptr;      // small host-visible readback buffer
+  int* pinned_i = nullptr;
+  void sync() { LRC_HIP(hipStreamSynchronize(stream)); }
+};
+
+struct Ops {
+  Ctx* ctx = nullptr;
+  int64_t n = 0;
+  int q = 0;
+  std::vector<CsrHost> host;
+  std::vector<DevBuf> rowptr, col, val64, val32;
+  std::vector<DevCsr<double>> d64;
+  std::vector<DevCsr<float>> d32;
+  void upload_values(int i);
+};
+
+// supernodal factor of the preconditioner on the device
+struct Prec {
+  SupernodalFactor F;   // host copy (blocks freed after upload)
+  DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd;
+  DevBuf fw64, bw64, fw32, bw32;
+  DevBuf fwd_tasks, bwd_tasks;
+  std::vector<LevelTasks> fwd, bwd;
+  PrecDev<double> p64;
+  PrecDev<float> p32;
+  int64_t cb_rows = 0;
+  double seconds_upload = 0.0;
+  template <class T> const PrecDev<T>& dev() const;
+};
+template <> inline const PrecDev<double>& Prec::dev<double>() const { return p64; }
+template <> inline const PrecDev<float>& Prec::dev<float>() const { return p32; }
+
+// Low-rank factor U diag(s) V^T on the device, rank held on the device.
+template <class T>
+struct LR {
+  int64_t n = 0, m = 0;
+  int cap = 0, ld = 0;
+  DevBuf U, V, s, rank;
+  void alloc(int64_t n_, int64_t m_, int cap_, hipStream_t st);
+  T* u() const { return U.as<T>(); }
+  T* v() const { return V.as<T>(); }
+  double* sv() const { return s.as<double>(); }
+  int* r() const { return rank.as<int>(); }
+};
+
+// Workspace + state of the truncation T_{R,eps}(A diag(c) B^T).
+template <class T>
+struct Truncator {
+  int kcap = 0, ldq = 0, max_rounds = 0;
+  int64_t nmax = 0, mmax = 0;
+  DevBuf small, rot, ints, gram_ws, Q1A, Q1B;
+  size_t gram_bytes = 0;
+  TruncState st{};
+  void alloc(int64_t nmax_, int64_t mmax_, hipStream_t s);
+  // outputs may alias input blocks; s_out/rank_out/norm_out are device pointers
+  void run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
+           const CoreView& core, int rank_cap, double tol, T* Uout, int ldu, T* Vout, int ldv,
+           double* s_out, int* rank_out, double* norm_out, hipStream_t s);
+};
+
+struct Prob;
+
+// One ChebyshevT solve in precision T of  L(S) = B  (B given as an LR<T>).
+template <class T>
+struct Cheb {
+  Prob* P = nullptr;
+  int cap = 0;
+  LR<T> S, D, R;
+  DevBuf W, Z, py, px, pcb, norm;
+  Truncator<T> tr;
+  void alloc(Prob* p, int cap_);
+  // returns iterations; sets converged
+  int solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c, double dc,
+            int max_iter, bool* converged, double* last_norm, int* prec_applies, int* flags,
+            double abs_target = 0.0, int stall_limit = 1 << 30);
+  void residual(const LR<T>& B, double* norm_dev);
+  void precond(const T* R, int ldr, const int* k_dev, T* Z, int ldz);
+  void spmm(const T* U, int ldu, const int* r_dev);
+};
+
+struct Prob {
+  Ops* ops = nullptr;
+  Ctx* ctx = nullptr;
+  int64_t m = 0;
+  std::vector<double> d;          // q x m column-major
+  DevBuf d_rows;                  // q rows of m doubles (row i = diag(D_i))
+  int rF = 0;
+  std::vector<double> FU, Fs, FV; // host copies (column-major)
+  double fnorm = 0.0;             // ||F||_F
+  std::vector<double> dbar;
+  std::unique_ptr<Prec> prec;
+  double seconds_setup = 0.0;
+  // solution: X = X0 + S (fp64 factors)
+  LR<double> X0, S;
+  int rank_x0 = 0, rank_s = 0;
+  LR<double> F64;                  // F as a device LR (fp64)
+  const double* drow(int i) const { return d_rows.as<double>() + size_t(i) * m; }
+};
+
+// helpers
+template <class T>
+BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double* rowscale = nullptr);
+
+double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S, double* colres);
+
+lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
+                         const double* V0, lrc_info* info);
+
+}  // namespace lrc

@@ -1,0 +1,371 @@
+"""Python binding of the C ABI in include/lrcheb.h (argument marshalling only).
+
+Every computation happens inside liblrcheb.so (HIP kernels for gfx950 plus the
+host factorisation of the preconditioner).  If the library is missing this
+module raises on load: there is no fallback.
+
+Host arrays are NumPy float64 (column-major where the C ABI says so); device
+buffers are torch CUDA tensors (row-major, contiguous rows with the given
+leading dimension).  The CUDA stream of a context is torch's current stream at
+creation time unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrcheb.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lrcheb.h")
+
+LRC_OK, LRC_ENOTCONV, LRC_EINVAL, LRC_ENOMEM, LRC_EDEVICE = 0, 1, -1, -2, -3
+LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
+LRC_FP64, LRC_MIXED_FP32 = 0, 1
+LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN = 0, 1, 2
+
+
+class LrcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lrcheb error {code}: {msg}")
+        self.code = code
+
+
+class lrc_opts(C.Structure):
+    _fields_ = [("rank_cap", C.c_int), ("trunc_tol", C.c_double), ("res_tol", C.c_double),
+                ("max_iter", C.c_int), ("restart", C.c_int), ("cheb_c", C.c_double),
+                ("cheb_d", C.c_double), ("precision", C.c_int), ("refine_max", C.c_int),
+                ("inner_tol", C.c_double), ("init", C.c_int), ("median_tol", C.c_double),
+                ("verify_fp64", C.c_int)]
+
+
+class lrc_info(C.Structure):
+    _fields_ = [("rank", C.c_int), ("rank_x0", C.c_int), ("iters", C.c_int),
+                ("prec_applies", C.c_int), ("refinements", C.c_int), ("median_iters", C.c_int),
+                ("relres", C.c_double), ("relres_est", C.c_double),
+                ("max_col_relres", C.c_double), ("seconds_setup", C.c_double),
+                ("seconds_solve", C.c_double), ("info_flags", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+LINEARIZE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                           C.POINTER(C.POINTER(C.c_double)))
+
+_P = C.c_void_p
+_SIGS = {
+    "lrc_opts_default": (None, [C.POINTER(lrc_opts)]),
+    "lrc_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "lrc_destroy": (None, [_P]),
+    "lrc_last_error": (C.c_char_p, [_P]),
+    "lrc_set_stream": (C.c_int, [_P, _P]),
+    "lrc_ops_create": (C.c_int, [_P, C.c_int64, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                 C.POINTER(_P), C.POINTER(_P)]),
+    "lrc_ops_update_values": (C.c_int, [_P, C.c_int, _P]),
+    "lrc_ops_destroy": (None, [_P]),
+    "lrc_ops_spmm_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int]),
+    "lrc_prob_create": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, _P, C.POINTER(_P)]),
+    "lrc_prob_destroy": (None, [_P]),
+    "lrc_prob_precondition": (C.c_int, [_P, _P, C.c_int]),
+    "lrc_prob_spectrum": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lrc_prob_precond_stats": (C.c_int, [_P, _P]),
+    "lrc_prob_prec_apply_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int]),
+    "lrc_solve": (C.c_int, [_P, C.POINTER(lrc_opts), C.c_int, _P, _P, _P,
+                            C.POINTER(lrc_info)]),
+    "lrc_get_solution": (C.c_int, [_P, C.POINTER(C.c_int), _P, _P, _P]),
+    "lrc_residual": (C.c_int, [_P, C.POINTER(C.c_double), _P]),
+    "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
+                                   _P, C.c_int, C.c_int, C.c_double, _P, C.c_int, _P, _P,
+                                   C.c_int, C.POINTER(C.c_int)]),
+    "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, LINEARIZE_FN, _P,
+                                     C.POINTER(lrc_opts), C.POINTER(_P), C.POINTER(lrc_info)]),
+}
+
+_lib = None
+
+
+def header_symbols():
+    """Names of every function the public header declares."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lrc_[a-z_0-9]+)\s*\(", txt)) - {"lrc_linearize_fn"})
+
+
+def load():
+    """Load liblrcheb.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7, requested as libamdhip64.so).  Loading torch first makes
+    # the library's libamdhip64.so.7 dependency resolve to that same runtime, so
+    # device pointers and streams from torch are valid inside the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a, order="F"):
+    return np.require(np.asarray(a, dtype=np.float64), requirements=[order, "A", "O"])
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(ctx_handle, code):
+    if code < 0:
+        msg = load().lrc_last_error(ctx_handle)
+        raise LrcError(code, msg.decode() if msg else "")
+    return code
+
+
+def default_opts(**kw):
+    o = lrc_opts()
+    load().lrc_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+# --------------------------------------------------------------------------- context
+class Context:
+    """lrc_create / lrc_destroy.  stream: an int hipStream_t (None: torch's current)."""
+
+    def __init__(self, device=0, stream=None):
+        lib = load()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.handle = C.c_void_p()
+        code = lib.lrc_create(C.byref(self.handle), device, C.c_void_p(stream))
+        if code != 0:
+            raise LrcError(code, "lrc_create failed (no HIP device?)")
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().lrc_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(self.handle, load().lrc_set_stream(self.handle, C.c_void_p(stream)))
+
+
+class Operators:
+    """lrc_ops_create from a list of SciPy CSR matrices."""
+
+    def __init__(self, ctx, K):
+        lib = load()
+        self.ctx = ctx
+        n = K[0].shape[0]
+        self.n, self.q = n, len(K)
+        self._keep = []
+        rp, cl, vl = [], [], []
+        for Ki in K:
+            r = np.ascontiguousarray(Ki.indptr, dtype=np.int64)
+            c = np.ascontiguousarray(Ki.indices, dtype=np.int32)
+            v = np.ascontiguousarray(Ki.data, dtype=np.float64)
+            self._keep += [r, c, v]
+            rp.append(_ptr(r))
+            cl.append(_ptr(c))
+            vl.append(_ptr(v))
+        arr = C.c_void_p * self.q
+        self.nnz = [Ki.nnz for Ki in K]
+        self.handle = C.c_void_p()
+        _check(ctx.handle, lib.lrc_ops_create(ctx.handle, n, self.q, arr(*rp), arr(*cl),
+                                              arr(*vl), C.byref(self.handle)))
+
+    def update_values(self, i, val):
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        _check(self.ctx.handle, load().lrc_ops_update_values(self.handle, i, _ptr(v)))
+
+    def spmm_dev(self, U, W, r=None):
+        """W (q*n x ldw tensor) = [K_0 U; ...; K_{q-1} U] for a row-major U tensor."""
+        import torch
+        dtype = 0 if U.dtype == torch.float64 else 1
+        r = U.shape[1] if r is None else r
+        _check(self.ctx.handle, load().lrc_ops_spmm_dev(self.handle, dtype, r, _dev_ptr(U),
+                                                        U.stride(0), _dev_ptr(W), W.stride(0)))
+
+    def close(self):
+        if self.handle:
+            load().lrc_ops_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """lrc_prob_create: one subset with table d (q x m) and F = FU diag(Fs) FV^T."""
+
+    def __init__(self, ops, d, FU, FV, Fs=None, handle=None):
+        self.ops = ops
+        self.ctx = ops.ctx
+        self.d = np.asarray(d, dtype=np.float64)
+        self.m = self.d.shape[1]
+        if handle is not None:
+            self.handle = handle
+            return
+        FU = _f64(np.atleast_2d(FU.T).T if FU.ndim == 1 else FU)
+        FV = _f64(np.atleast_2d(FV.T).T if FV.ndim == 1 else FV)
+        dd = _f64(self.d)
+        fs = None if Fs is None else _f64(Fs)
+        self._keep = [FU, FV, dd, fs]
+        self.handle = C.c_void_p()
+        _check(self.ctx.handle, load().lrc_prob_create(ops.handle, self.m, _ptr(dd), FU.shape[1],
+                                                       _ptr(FU), _ptr(fs), _ptr(FV),
+                                                       C.byref(self.handle)))
+
+    def precondition(self, dbar=None, leaf_size=0):
+        db = None if dbar is None else _f64(dbar)
+        _check(self.ctx.handle, load().lrc_prob_precondition(self.handle, _ptr(db), leaf_size))
+
+    def spectrum(self):
+        c, d = C.c_double(), C.c_double()
+        _check(self.ctx.handle, load().lrc_prob_spectrum(self.handle, C.byref(c), C.byref(d)))
+        return c.value, d.value
+
+    def precond_stats(self):
+        out = np.zeros(8)
+        _check(self.ctx.handle, load().lrc_prob_precond_stats(self.handle, _ptr(out)))
+        keys = ["supernodes", "levels_fwd", "levels_bwd", "max_front", "block_entries",
+                "seconds_order", "seconds_factor", "seconds_upload"]
+        return dict(zip(keys, out.tolist()))
+
+    def prec_apply_dev(self, R, Z, k=None):
+        import torch
+        dtype = 0 if R.dtype == torch.float64 else 1
+        k = R.shape[1] if k is None else k
+        _check(self.ctx.handle, load().lrc_prob_prec_apply_dev(
+            self.handle, dtype, k, _dev_ptr(R), R.stride(0), _dev_ptr(Z), Z.stride(0)))
+
+    def solve(self, opts=None, X0=None, **kw):
+        """lrc_solve; X0 = (U0, s0, V0) host arrays for LRC_INIT_GIVEN.  Returns
+        (status, info dict)."""
+        o = opts if opts is not None else default_opts(**kw)
+        info = lrc_info()
+        r0, U0, s0, V0 = 0, None, None, None
+        if X0 is not None:
+            U0, s0, V0 = _f64(X0[0]), None if X0[1] is None else _f64(X0[1]), _f64(X0[2])
+            r0 = U0.shape[1]
+        code = load().lrc_solve(self.handle, C.byref(o), r0, _ptr(U0), _ptr(s0), _ptr(V0),
+                                C.byref(info))
+        _check(self.ctx.handle, code)
+        return code, info.as_dict()
+
+    def solution(self):
+        """Factors (U, s, V) of X = U diag(s) V^T (host, the x0 term first)."""
+        lib = load()
+        r = C.c_int()
+        _check(self.ctx.handle, lib.lrc_get_solution(self.handle, C.byref(r), None, None, None))
+        U = np.zeros((self.ops.n, r.value), order="F")
+        V = np.zeros((self.m, r.value), order="F")
+        s = np.zeros(r.value)
+        if r.value:
+            _check(self.ctx.handle, lib.lrc_get_solution(self.handle, C.byref(r), _ptr(U),
+                                                         _ptr(s), _ptr(V)))
+        return U, s, V
+
+    def residual(self):
+        rr = C.c_double()
+        col = np.zeros(self.m)
+        _check(self.ctx.handle, load().lrc_residual(self.handle, C.byref(rr), _ptr(col)))
+        return rr.value, col
+
+    def close(self):
+        if self.handle:
+            load().lrc_prob_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V):
+    """lrc_truncate_dev on row-major device tensors; returns (s, rank)."""
+    import torch
+    dtype = 0 if A.dtype == torch.float64 else 1
+    n, k = A.shape
+    m = B.shape[0]
+    cc = _f64(c)
+    s = np.zeros(64)
+    r = C.c_int()
+    _check(ctx.handle, load().lrc_truncate_dev(ctx.handle, dtype, n, m, k, _dev_ptr(A),
+                                               A.stride(0), _ptr(cc), _dev_ptr(B), B.stride(0),
+                                               rank_cap, tol, _dev_ptr(U), U.stride(0), _ptr(s),
+                                               _dev_ptr(V), V.stride(0), C.byref(r)))
+    return s[:r.value].copy(), r.value
+
+
+def newton_subsets(ops, d, K, f, opts=None, sizes=None, linearize=None, **kw):
+    """lrc_newton_subsets (Algorithm 1).  linearize(k, xtilde_or_None) may return a
+    list of q value arrays (or None to keep the values).  Returns (status,
+    [Problem], [info dict])."""
+    lib = load()
+    o = opts if opts is not None else default_opts(**kw)
+    dd = _f64(d)
+    ff = _f64(f)
+    sz = None if sizes is None else np.ascontiguousarray(sizes, dtype=np.int64)
+    n = ops.n
+
+    def _cb(user, k, xt, vals):
+        try:
+            x = None if not xt else np.ctypeslib.as_array(xt, shape=(n,)).copy()
+            new = linearize(k, x) if linearize else None
+            if new is not None:
+                for i, v in enumerate(new):
+                    if v is None:
+                        continue
+                    dst = np.ctypeslib.as_array(vals[i], shape=(ops.nnz[i],))
+                    dst[:] = v
+            return 0
+        except Exception:
+            return 1
+
+    cb = LINEARIZE_FN(_cb)
+    out = (C.c_void_p * K)()
+    infos = (lrc_info * K)()
+    code = lib.lrc_newton_subsets(ops.handle, dd.shape[1], _ptr(dd), K, _ptr(sz), _ptr(ff), cb,
+                                  None, C.byref(o), out, infos)
+    _check(ops.ctx.handle, code)
+    probs = []
+    off = 0
+    sizes_l = list(sz) if sz is not None else [dd.shape[1] // K] * (K - 1) + \
+        [dd.shape[1] - (K - 1) * (dd.shape[1] // K)]
+    for k in range(K):
+        p = Problem(ops, dd[:, off:off + sizes_l[k]], None, None, handle=C.c_void_p(out[k]))
+        probs.append(p)
+        off += sizes_l[k]
+    return code, probs, [infos[k].as_dict() for k in range(K)]

@@ -1,0 +1,172 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: fp64 kernels are compared to ~1e-10 relative (rounding order only);
+fp32 kernels to ~1e-5 (24-bit mantissa, short reductions); solver results are
+compared through residuals and solution products, never through factors
+(factors are unique only up to rotations)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import chebyshev as och
+from oracle import driver as odrv
+from oracle import lowrank as olr
+from workloads import config, three_term_2d, param_table
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "no GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2008_10275_amd import lrcheb
+    return lrcheb
+
+
+@pytest.fixture(scope="module")
+def ctx(torch, L):
+    return L.Context(0)
+
+
+def _dev(torch, a, dtype, ld=None):
+    a = np.asarray(a)
+    ld = ld or ((a.shape[1] + 7) // 8 * 8)
+    t = torch.zeros((a.shape[0], ld), dtype=dtype, device="cuda")
+    t[:, :a.shape[1]] = torch.from_numpy(np.ascontiguousarray(a)).to(dtype)
+    return t
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("r", [1, 7, 20, 40])
+def test_spmm_matches_sparse_product(torch, L, ctx, dt, r):
+    say("spmm", dt, r)
+    cfg = config("c1")
+    K = cfg["ops"].K
+    ops = L.Operators(ctx, K)
+    n = K[0].shape[0]
+    U = np.random.default_rng(r).standard_normal((n, r))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Ud = _dev(torch, U, tdt)
+    W = torch.zeros((len(K) * n, Ud.shape[1]), dtype=tdt, device="cuda")
+    ops.spmm_dev(Ud, W, r)
+    torch.cuda.synchronize()
+    Wh = W.double().cpu().numpy()
+    for i, Ki in enumerate(K):
+        ref = Ki @ U
+        got = Wh[i * n:(i + 1) * n, :r]
+        scale = (abs(Ki) @ np.abs(U)) + 1e-300
+        tol = 1e-14 if dt == "f64" else 2e-6
+        assert np.all(np.abs(got - ref) <= tol * scale + 1e-300), f"operator {i}"
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name,k", [("c1", 1), ("c1", 13), ("c2s", 40)])
+def test_preconditioner_solve_matches_sparse_lu(torch, L, ctx, dt, name, k):
+    say("prec", dt, name, k)
+    cfg = config("c1") if name == "c1" else config("c2", small=True)
+    K, d = cfg["ops"].K, cfg["d"]
+    ops = L.Operators(ctx, K)
+    n = K[0].shape[0]
+    prob = L.Problem(ops, d, np.ones((n, 1)), np.ones((d.shape[1], 1)))
+    prob.precondition()
+    st = prob.precond_stats()
+    assert st["levels_fwd"] >= 2
+    R = np.random.default_rng(k).standard_normal((n, k))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Rd = _dev(torch, R, tdt)
+    Zd = torch.zeros_like(Rd)
+    prob.prec_apply_dev(Rd, Zd, k)
+    torch.cuda.synchronize()
+    Z = Zd.double().cpu().numpy()[:, :k]
+    P = och.mean_preconditioner(K, och.mean_parameters(d))
+    Zs = och.DirectPreconditioner(P).solve(R)
+    err = np.linalg.norm(Z - Zs) / np.linalg.norm(Zs)
+    assert err < (1e-11 if dt == "f64" else 2e-4), err
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,m,k,cap,tol", [(3000, 400, 50, 20, 1e-8), (1000, 37, 9, 9, 0.0),
+                                           (2500, 300, 123, 40, 1e-8), (513, 60, 1, 5, 1e-8)])
+def test_truncation_matches_oracle(torch, L, ctx, dt, n, m, k, cap, tol):
+    say("truncate", dt, n, m, k, cap, tol)
+    rng = np.random.default_rng(k + n)
+    A = rng.standard_normal((n, k)) * rng.uniform(0.1, 10, k)
+    B = rng.standard_normal((m, k))
+    c = np.logspace(0, -9, k) * np.where(rng.uniform(size=k) < 0.5, -1, 1)
+    Uo, so, Vo = olr.truncate(A, np.diag(c), B, cap, tol)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Ad, Bd = _dev(torch, A, tdt), _dev(torch, B, tdt)
+    ld = max(8, (cap + 7) // 8 * 8)
+    Ud = torch.zeros((n, ld), dtype=tdt, device="cuda")
+    Vd = torch.zeros((m, ld), dtype=tdt, device="cuda")
+    s, r = L.truncate_dev(ctx, Ad, c, Bd, cap, tol, Ud, Vd)
+    U = Ud.double().cpu().numpy()[:, :r]
+    V = Vd.double().cpu().numpy()[:, :r]
+    if dt == "f64":
+        assert abs(r - so.size) <= 1
+        rr = min(r, so.size)
+        assert np.allclose(s[:rr], so[:rr], rtol=1e-8, atol=1e-12 * so[0])
+        X = U @ np.diag(s) @ V.T
+        Xo = Uo @ np.diag(so) @ Vo.T
+        assert np.linalg.norm(X - Xo) <= 1e-7 * np.linalg.norm(Xo) + 2 * (so[rr - 1] if r != so.size else 0)
+        assert np.allclose(U.T @ U, np.eye(r), atol=1e-10)
+    else:
+        assert np.allclose(s[:3], so[:3], rtol=1e-4)
+        X = U @ np.diag(s) @ V.T
+        Xo = Uo @ np.diag(so) @ Vo.T
+        assert np.linalg.norm(X - Xo) <= 1e-4 * np.linalg.norm(Xo)
+
+
+def test_c1_fp64_solve_matches_oracle(torch, L, ctx):
+    say("solve c1 fp64")
+    cfg = config("c1")
+    K, d, f = cfg["ops"].K, cfg["d"], cfg["f"]
+    m = d.shape[1]
+    ops = L.Operators(ctx, K)
+    prob = L.Problem(ops, d, f[:, None], np.ones((m, 1)))
+    prob.precondition()
+    code, info = prob.solve(rank_cap=20, trunc_tol=1e-8, res_tol=1e-8, init=L.LRC_INIT_MEDIAN)
+    say("info", info)
+    ref = odrv.newton_subset(K, d, f, 20, 1e-8, 1e-8)
+    assert code == 0
+    assert info["relres"] <= 1e-8
+    assert abs(info["iters"] - ref["info"].iters) <= 1
+    U, s, V = prob.solution()
+    X = U @ np.diag(s) @ V.T
+    Xo = sum(olr.lr_dense(*t) for t in odrv.solution_terms(ref))
+    # both satisfy relres <= 1e-8 with cond(A_j) ~ 1e8: compare within that bound
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) < 1e-1
+    rr, col = prob.residual()
+    Fd = np.outer(f, np.ones(m))
+    Xd_res = olr.relres_dense(K, d, X, Fd)
+    assert abs(rr - Xd_res) <= 1e-3 * Xd_res
+
+
+def test_c2_small_mixed_precision_reaches_1e6(torch, L, ctx):
+    say("solve c2-small mixed")
+    cfg = config("c2", small=True)
+    K, d, f = cfg["ops"].K, cfg["d"], cfg["f"]
+    m = d.shape[1]
+    ops = L.Operators(ctx, K)
+    prob = L.Problem(ops, d, f[:, None], np.ones((m, 1)))
+    prob.precondition()
+    code, info = prob.solve(rank_cap=40, trunc_tol=1e-8, res_tol=1e-6,
+                            precision=L.LRC_MIXED_FP32, init=L.LRC_INIT_MEDIAN)
+    say("info", info)
+    assert code == 0 and info["relres"] <= 1e-6
+    U, s, V = prob.solution()
+    X = U @ np.diag(s) @ V.T
+    Fd = np.outer(f, np.ones(m))
+    assert olr.relres_dense(K, d, X, Fd) <= 1.01e-6
