@@ -162,6 +162,18 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
                             int ldb, int rank_cap, double tol, void* U_dev, int ldu,
                             double* s, void* V_dev, int ldv, int* rank);
 
+/* --------------------------------------------------------------- timing
+ * Per-kernel-class timing with HIP events recorded on the stream each kernel
+ * is launched on (process-wide, not thread-safe; adds two event records per
+ * launch while on).  lrc_profile_enable(1) starts and clears the record,
+ * lrc_profile_enable(0) stops (the record is kept).  lrc_profile_read
+ * synchronises the recorded events and fills, for class c < ncls (the classes
+ * are named by lrc_profile_class_name; at most 32), ms[c] = summed kernel time
+ * and count[c] = launches (either may be NULL).  Returns the number of classes. */
+lrc_status lrc_profile_enable(int on);
+int lrc_profile_read(int ncls, double* ms, int* count);
+const char* lrc_profile_class_name(int c);
+
 /* --------------------------------------------------------------- Algorithm 1
  * Split m columns into K subsets (sizes NULL: eq. clustering1 of Sec. 3.3),
  * and for each subset k: factorise the centre preconditioner, solve the upper

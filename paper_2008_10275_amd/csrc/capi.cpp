@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "prof.hpp"
 #include "solver.hpp"
 
 using namespace lrc;
@@ -88,24 +89,42 @@ CsrHost combine(const Ops& o, const std::vector<double>& w) {
 
 void build_levels(Prec& pr, hipStream_t s) {
   const SupernodalFactor& F = pr.F;
-  const int TR = 64;
-  std::vector<int2> all;
-  std::vector<int> fcount(F.nlev_fwd, 0), bcount(F.nlev_bwd, 0);
-  std::vector<std::vector<int2>> fl(F.nlev_fwd), bl(F.nlev_bwd);
+  const int TR = 16;   // output rows per product workgroup
+  std::vector<std::vector<int2>> ft(F.nlev_fwd), bt(F.nlev_bwd), fr(F.nlev_fwd), br(F.nlev_bwd);
+  std::vector<int64_t> soff_f(F.nsn, 0), soff_b(F.nsn, 0), lf(F.nlev_fwd, 0), lb(F.nlev_bwd, 0);
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
-    for (int r0 = 0; r0 < f; r0 += TR) fl[F.height[sn]].push_back(make_int2(sn, r0));
-    for (int r0 = 0; r0 < F.ns[sn]; r0 += TR) bl[F.depth[sn]].push_back(make_int2(sn, r0));
+    const int hf = F.height[sn], db = F.depth[sn];
+    for (int r0 = 0; r0 < f; r0 += TR) ft[hf].push_back(make_int2(sn, r0));
+    for (int r0 = 0; r0 < F.ns[sn]; r0 += TR) bt[db].push_back(make_int2(sn, r0));
+    soff_f[sn] = lf[hf];
+    soff_b[sn] = lb[db];
+    for (int p = 0; p < f; ++p) {
+      fr[hf].push_back(make_int2(sn, p));
+      br[db].push_back(make_int2(sn, p));
+    }
+    lf[hf] += f;
+    lb[db] += f;
   }
-  std::vector<size_t> foff, boff;
-  for (auto& L : fl) { foff.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
-  for (auto& L : bl) { boff.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  pr.stage_rows = std::max(*std::max_element(lf.begin(), lf.end()),
+                           *std::max_element(lb.begin(), lb.end()));
+  std::vector<int2> all;
+  std::vector<size_t> fto, bto, fro, bro;
+  for (auto& L : ft) { fto.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  for (auto& L : bt) { bto.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  for (auto& L : fr) { fro.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
+  for (auto& L : br) { bro.push_back(all.size()); all.insert(all.end(), L.begin(), L.end()); }
   pr.fwd_tasks = upload(all, s);
+  pr.soff_fwd = upload(soff_f, s);
+  pr.soff_bwd = upload(soff_b, s);
   const int2* base = pr.fwd_tasks.as<int2>();
   pr.fwd.clear();
   pr.bwd.clear();
-  for (size_t l = 0; l < fl.size(); ++l) pr.fwd.push_back({base + foff[l], int(fl[l].size())});
-  for (size_t l = 0; l < bl.size(); ++l) pr.bwd.push_back({base + boff[l], int(bl[l].size())});
+  for (size_t l = 0; l < ft.size(); ++l)
+    pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size())});
+  for (size_t l = 0; l < bt.size(); ++l)
+    pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size())});
+  LRC_HIP(hipStreamSynchronize(s));
 }
 
 void upload_prec(Prec& pr, hipStream_t s) {
@@ -151,10 +170,12 @@ void upload_prec(Prec& pr, hipStream_t s) {
     using TT = std::remove_const_t<std::remove_pointer_t<decltype(P.fw)>>;
     P.fw = static_cast<const TT*>(fw);
     P.bw = static_cast<const TT*>(bw);
+    P.soff_fwd = pr.soff_fwd.as<int64_t>();
+    P.soff_bwd = pr.soff_bwd.as<int64_t>();
   };
+  build_levels(pr, s);
   fill(pr.p64, pr.fw64.p, pr.bw64.p);
   fill(pr.p32, pr.fw32.p, pr.bw32.p);
-  build_levels(pr, s);
   LRC_HIP(hipStreamSynchronize(s));
   // the dense blocks live on the device now
   std::vector<double>().swap(F.fw);
@@ -165,6 +186,26 @@ void upload_prec(Prec& pr, hipStream_t s) {
 }  // namespace
 
 extern "C" {
+
+lrc_status lrc_profile_enable(int on) {
+  Profiler& p = profiler();
+  if (on) p.clear();
+  p.on = on != 0;
+  return LRC_OK;
+}
+
+int lrc_profile_read(int ncls, double* ms, int* count) {
+  double t[K_COUNT];
+  int c[K_COUNT];
+  profiler().read(t, c);
+  for (int k = 0; k < K_COUNT && k < ncls; ++k) {
+    if (ms) ms[k] = t[k];
+    if (count) count[k] = c[k];
+  }
+  return K_COUNT;
+}
+
+const char* lrc_profile_class_name(int c) { return kclass_name(c); }
 
 void lrc_opts_default(lrc_opts* o) {
   if (!o) return;
@@ -445,17 +486,19 @@ lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* 
     const int ld = ld_for(k);
     const size_t es = dtype == 0 ? 8 : 4;
     DevBuf y(size_t(n) * ld * es), x(size_t(n) * ld * es),
-        cb(size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * ld * es);
+        cb(size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * ld * es),
+        st(size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * ld * es);
     hipStream_t s = P.ctx->stream;
     if (dtype == 0)
       launch_prec_apply<double>(P.prec->p64, P.prec->fwd, P.prec->bwd,
                                 static_cast<const double*>(R), ldr, static_cast<double*>(Z), ldz,
-                                nullptr, k, k, y.as<double>(), x.as<double>(), cb.as<double>(), ld,
-                                s);
+                                nullptr, k, k, y.as<double>(), x.as<double>(), cb.as<double>(),
+                                st.as<double>(), ld, s);
     else
       launch_prec_apply<float>(P.prec->p32, P.prec->fwd, P.prec->bwd,
                                static_cast<const float*>(R), ldr, static_cast<float*>(Z), ldz,
-                               nullptr, k, k, y.as<float>(), x.as<float>(), cb.as<float>(), ld, s);
+                               nullptr, k, k, y.as<float>(), x.as<float>(), cb.as<float>(),
+                               st.as<float>(), ld, s);
     LRC_HIP(hipStreamSynchronize(s));   // scratch buffers are released on return
     return LRC_OK;
   });

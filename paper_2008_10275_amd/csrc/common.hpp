@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -52,6 +53,13 @@ struct DevBuf {
     if (b == 0) return;
     LRC_HIP(hipMalloc(&p, b));
     bytes = b;
+    // debugging aid: LRC_POISON=1 fills fresh buffers with 0xFF bytes (NaN for
+    // floating point) so that a read of never-written memory shows up as NaN
+    static const bool poison = std::getenv("LRC_POISON") != nullptr;
+    if (poison) {
+      LRC_HIP(hipMemset(p, 0xFF, b));
+      LRC_HIP(hipDeviceSynchronize());
+    }
   }
   // grow-only reallocation (contents are not preserved)
   void reserve(size_t b) { if (b > bytes) alloc(b); }

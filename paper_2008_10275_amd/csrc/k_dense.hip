@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace lrc {
 
@@ -199,8 +200,12 @@ void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial
   // fp32 products accumulate in fp32 inside a workgroup; fp64 in fp64
   const size_t need = size_t(a.nwg0 + a.nwg1) * kTiles * 256 * sizeof(T);
   LRC_CHECK(need <= ws_bytes, ST_EINVAL, "gram: workspace too small");
-  hipLaunchKernelGGL((gram_kernel<T, T>), dim3(a.nwg0 + a.nwg1), dim3(256), 0, s, a,
-                     reinterpret_cast<T*>(ws_partial));
+  {
+    ProfScope ps(K_GRAM, s);
+    hipLaunchKernelGGL((gram_kernel<T, T>), dim3(a.nwg0 + a.nwg1), dim3(256), 0, s, a,
+                       reinterpret_cast<T*>(ws_partial));
+  }
+  ProfScope ps(K_GRAM_REDUCE, s);
   const int elems = kTiles * 256;
   hipLaunchKernelGGL((gram_reduce_kernel<T, T>), dim3(ceil_div(elems, 256), njobs), dim3(256), 0,
                      s, a, reinterpret_cast<const T*>(ws_partial), jobs[0].G,
@@ -303,6 +308,7 @@ void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStrea
     a.nwg1 = 0;
   }
   const int slices = int(ceil_div(rcap, kTsSlice));
+  ProfScope ps(K_TSMM, s);
   hipLaunchKernelGGL((tsmm_kernel<T>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
   LRC_HIP(hipGetLastError());
 }
@@ -420,6 +426,7 @@ void launch_residual_fp64(const BlockView<double>& A, int64_t n, const BlockView
   LRC_CHECK(ws_bytes >= residual_workspace_bytes(n, m), ST_EINVAL, "residual: workspace too small");
   const int groups = int(std::min<int64_t>(kResRowGroups, std::max<int64_t>(1, ceil_div(n, kResRows))));
   dim3 grid(unsigned(ceil_div(m, kResCols)), unsigned(groups));
+  ProfScope ps(K_RESIDUAL, s);
   hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, A, n, B, core, m, ws);
   hipLaunchKernelGGL(residual_reduce_kernel, dim3(unsigned(ceil_div(m, 256))), dim3(256), 0, s, ws,
                      groups, m, colsq);

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace lrc {
 
@@ -72,11 +73,14 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
       const double rjj = Rp[pk(j, j, k)];
       for (int c = j + 1 + tid; c < k; c += nt) Rp[pk(j, c, k)] /= rjj;
       __syncthreads();
-      const int m = k - j - 1;   // trailing size
-      for (int e = tid; e < m * m; e += nt) {
-        const int a = j + 1 + e / m, b = j + 1 + e % m;
-        if (b < a) continue;
-        Rp[pk(a, b, k)] -= Rp[pk(j, a, k)] * Rp[pk(j, b, k)];
+      // trailing update, 16 x 16 thread grid over (row a, column b >= a)
+      {
+        const int ty = tid >> 4, tx = tid & 15;
+        for (int a = j + 1 + ty; a < k; a += 16) {
+          const double rja = Rp[pk(j, a, k)];
+          const int base = pk(a, 0, k);            // row a starts at base + a
+          for (int b = a + tx; b < k; b += 16) Rp[base + b] -= rja * Rp[pk(j, b, k)];
+        }
       }
       __syncthreads();
     }
@@ -151,6 +155,7 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
 
 void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s) {
   LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
+  ProfScope ps(K_CHOL, s);
   hipLaunchKernelGGL(chol_kernel, dim3(2), dim3(256), 0, s, st, pass, kcap, eps_gram);
   LRC_HIP(hipGetLastError());
 }
@@ -230,6 +235,7 @@ static void small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const in
   a.k = k;
   a.kcap = kcap;
   const int t = (kcap + 15) / 16;
+  ProfScope ps(K_SMALL_GEMM, s);
   hipLaunchKernelGGL(small_gemm_kernel, dim3(t, t, njobs), dim3(256), 0, s, a);
 }
 
@@ -242,12 +248,15 @@ __device__ inline int rr_player(int pos, int t, int kp) {
 }
 
 // Two-sided Jacobi on the symmetric H (k x k, padded to even kp with a zero
-// row/column).  Every round applies kp/2 disjoint rotations H <- J^T H J; the
-// (c, s) of each round are logged so that V = prod J can be rebuilt per row.
+// row/column), stored in full in LDS (both triangles kept equal).  Every round
+// applies kp/2 disjoint rotations H <- J^T H J; the (c, s) of each round are
+// logged so that V = prod J can be rebuilt per row.
+constexpr int kJL = SK + 1;   // LDS row pitch of H (odd: fewer bank conflicts)
 __global__ __launch_bounds__(1024) void jacobi_kernel(TruncState st, int kcap, int max_rounds) {
-  __shared__ double Hp[SKP];
+  __shared__ double Hs[SK * kJL];
   __shared__ double cs_c[SK / 2], cs_s[SK / 2];
-  __shared__ int nrot;
+  __shared__ unsigned char pp[SK / 2], qq[SK / 2];                 // pair a = (pp[a], qq[a])
+  __shared__ int nrot, rrot;
   const int k = *st.k;
   const int kp = k + (k & 1);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -257,37 +266,45 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(TruncState st, int kcap, i
   }
   for (int e = tid; e < kp * kp; e += nt) {
     const int i = e / kp, j = e - i * kp;
-    if (j < i) continue;
-    Hp[pk(i, j, kp)] = (i < k && j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
+    Hs[i * kJL + j] = (i < k && j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
   }
-  // scale of H: entries below 1e-17 * trace(H) are rounding noise of the
-  // squared core (singular values below ~3e-9 of the largest) and are not rotated
+  const int npair = kp / 2;
+  __syncthreads();
+  // Off-diagonal entries below 1e-16 * trace(H) are rounding noise of the
+  // squared core and are not rotated; the eigenvalues are then accurate to
+  // that absolute level (singular values to ~1e-8 of the largest).
   __shared__ double hscale;
   if (tid == 0) {
     double tr = 0.0;
-    for (int i = 0; i < k; ++i) tr += fabs(Hp[pk(i, i, kp)]);
-    hscale = 1e-17 * tr;
+    for (int i = 0; i < k; ++i) tr += fabs(Hs[i * kJL + i]);
+    hscale = 1e-16 * tr;
   }
   __syncthreads();
   const double floor_abs = hscale;
-  const int npair = kp / 2;
-  const int nblocks = npair * (npair + 1) / 2;
+  // thread layout of the update phase: 16 threads per pair a (one per column
+  // group), each sweeping the columns j of rows pp[a], qq[a]
   int round = 0;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
     if (tid == 0) nrot = 0;
     __syncthreads();
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
+      if (tid == 0) rrot = 0;
+      __syncthreads();
       if (tid < npair) {
-        int p = rr_player(tid, t, kp), q = rr_player(kp - 1 - tid, t, kp);
-        if (p > q) { int x = p; p = q; q = x; }
-        const double hpp = Hp[pk(p, p, kp)], hqq = Hp[pk(q, q, kp)], hpq = Hp[pk(p, q, kp)];
+        // pair slot tid of round t: positions tid and kp-1-tid of the rotated list
+        const int x0 = tid == 0 ? 0 : 1 + (tid - 1 + t) % (kp - 1);
+        const int x1 = 1 + (kp - 2 - tid + t) % (kp - 1);
+        const int p = min(x0, x1), q = max(x0, x1);
+        pp[tid] = (unsigned char)p;
+        qq[tid] = (unsigned char)q;
+        const double hpp = Hs[p * kJL + p], hqq = Hs[q * kJL + q], hpq = Hs[p * kJL + q];
         double c = 1.0, s = 0.0;
-        if (fabs(hpq) > floor_abs && fabs(hpq) > 1e-15 * sqrt(fabs(hpp * hqq))) {
+        if (fabs(hpq) > floor_abs) {
           const double zeta = (hqq - hpp) / (2.0 * hpq);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = c * tt;
-          atomicAdd(&nrot, 1);
+          atomicAdd(&rrot, 1);
         }
         cs_c[tid] = c;
         cs_s[tid] = s;
@@ -295,44 +312,30 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(TruncState st, int kcap, i
         st.rot[(size_t(round) * (SK / 2) + tid) * 2 + 1] = s;
       }
       __syncthreads();
-      // blocks (a <= b) of pairs: H' = J_a^T H J_b on the 2 x 2 block
-      for (int e = tid; e < nblocks; e += nt) {
-        int a = 0, rem = e;
-        while (rem >= npair - a) { rem -= npair - a; ++a; }
-        const int b = a + rem;
-        int pa = rr_player(a, t, kp), qa = rr_player(kp - 1 - a, t, kp);
-        if (pa > qa) { int x = pa; pa = qa; qa = x; }
-        int pb = rr_player(b, t, kp), qb = rr_player(kp - 1 - b, t, kp);
-        if (pb > qb) { int x = pb; pb = qb; qb = x; }
+      if (rrot == 0) continue;          // nothing rotated in this round
+      if (tid == 0) nrot += rrot;
+      // H <- J^T H (rows), then H <- H J (columns), done as one pass over the
+      // 2 x 2 blocks (pair a, pair b): each block is owned by one thread.
+      for (int e = tid; e < npair * npair; e += nt) {
+        const int a = e / npair, b = e - a * npair;
         const double ca = cs_c[a], sa = cs_s[a], cb = cs_c[b], sb = cs_s[b];
-        if (a == b) {
-          if (sa == 0.0) continue;
-          const double hpp = Hp[pk(pa, pa, kp)], hqq = Hp[pk(qa, qa, kp)], hpq = Hp[pk(pa, qa, kp)];
-          const double tt = sa / ca;
-          Hp[pk(pa, pa, kp)] = hpp - tt * hpq;
-          Hp[pk(qa, qa, kp)] = hqq + tt * hpq;
-          Hp[pk(pa, qa, kp)] = 0.0;
-        } else {
-          if (sa == 0.0 && sb == 0.0) continue;
-          // rows {pa, qa} x columns {pb, qb}; entries stored at (min, max)
-          const int i0 = pa, i1 = qa, j0 = pb, j1 = qb;
-          const int x00 = i0 < j0 ? pk(i0, j0, kp) : pk(j0, i0, kp);
-          const int x01 = i0 < j1 ? pk(i0, j1, kp) : pk(j1, i0, kp);
-          const int x10 = i1 < j0 ? pk(i1, j0, kp) : pk(j0, i1, kp);
-          const int x11 = i1 < j1 ? pk(i1, j1, kp) : pk(j1, i1, kp);
-          const double h00 = Hp[x00], h01 = Hp[x01], h10 = Hp[x10], h11 = Hp[x11];
-          // left: rows p' = c p - s q, q' = s p + c q
-          const double l00 = ca * h00 - sa * h10, l01 = ca * h01 - sa * h11;
-          const double l10 = sa * h00 + ca * h10, l11 = sa * h01 + ca * h11;
-          // right: columns p' = c p - s q, q' = s p + c q
-          Hp[x00] = cb * l00 - sb * l01;
-          Hp[x01] = sb * l00 + cb * l01;
-          Hp[x10] = cb * l10 - sb * l11;
-          Hp[x11] = sb * l10 + cb * l11;
-        }
+        if (sa == 0.0 && sb == 0.0) continue;
+        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+        const double h00 = Hs[pa * kJL + pb], h01 = Hs[pa * kJL + qb];
+        const double h10 = Hs[qa * kJL + pb], h11 = Hs[qa * kJL + qb];
+        const double l00 = ca * h00 - sa * h10, l01 = ca * h01 - sa * h11;
+        const double l10 = sa * h00 + ca * h10, l11 = sa * h01 + ca * h11;
+        double r00 = cb * l00 - sb * l01, r01 = sb * l00 + cb * l01;
+        double r10 = cb * l10 - sb * l11, r11 = sb * l10 + cb * l11;
+        if (a == b) r01 = r10 = 0.0;      // the rotated pair is diagonalised
+        Hs[pa * kJL + pb] = r00;
+        Hs[pa * kJL + qb] = r01;
+        Hs[qa * kJL + pb] = r10;
+        Hs[qa * kJL + qb] = r11;
       }
       __syncthreads();
     }
+    __syncthreads();
     if (nrot == 0) break;
     __syncthreads();
   }
@@ -342,38 +345,58 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(TruncState st, int kcap, i
   }
 }
 
-// V = J_0 J_1 ... J_{T-1}: row i of V evolves independently, one wave per row.
+// V = J_0 J_1 ... J_{T-1}: every row of V evolves independently.  A workgroup
+// (one wave) owns kRepRows rows; lane a applies pair a's rotation to them.  The
+// rotation log is staged through LDS in batches of kRepBatch rounds.
+constexpr int kRepRows = 4;
+constexpr int kRepBatch = 16;
 __global__ __launch_bounds__(64) void jacobi_replay_kernel(TruncState st, int kcap) {
-  __shared__ double row[SK];
+  __shared__ double row[kRepRows][SK];
+  __shared__ double2 rb[kRepBatch][SK / 2];
   const int k = *st.k;
   const int kp = k + (k & 1);
-  const int i = blockIdx.x;
-  if (i >= k) return;
+  const int i0 = blockIdx.x * kRepRows;
+  if (i0 >= k) return;
   const int T = *st.rounds;
   const int lane = threadIdx.x;
-  for (int j = lane; j < kp; j += 64) row[j] = (j == i) ? 1.0 : 0.0;
-  __syncthreads();
+  for (int r = 0; r < kRepRows; ++r)
+    for (int j = lane; j < kp; j += 64) row[r][j] = (j == i0 + r) ? 1.0 : 0.0;
   const int npair = kp / 2;
-  for (int t = 0; t < T; ++t) {
-    if (lane < npair) {
-      const int tr = t % (kp - 1);
-      int p = rr_player(lane, tr, kp), q = rr_player(kp - 1 - lane, tr, kp);
-      if (p > q) { int x = p; p = q; q = x; }
-      const double c = st.rot[(size_t(t) * (SK / 2) + lane) * 2 + 0];
-      const double s = st.rot[(size_t(t) * (SK / 2) + lane) * 2 + 1];
-      if (s != 0.0) {
-        const double vp = row[p], vq = row[q];
-        row[p] = c * vp - s * vq;
-        row[q] = s * vp + c * vq;
-      }
-    }
+  const double2* rot = reinterpret_cast<const double2*>(st.rot);
+  for (int t0 = 0; t0 < T; t0 += kRepBatch) {
+    const int nb = min(kRepBatch, T - t0);
     __syncthreads();
+    for (int e = lane; e < nb * (SK / 2); e += 64) rb[e / (SK / 2)][e % (SK / 2)] = rot[size_t(t0) * (SK / 2) + e];
+    __syncthreads();
+    for (int tb = 0; tb < nb; ++tb) {
+      if (lane < npair) {
+        const int tr = (t0 + tb) % (kp - 1);
+        int p = rr_player(lane, tr, kp), q = rr_player(kp - 1 - lane, tr, kp);
+        if (p > q) { int x = p; p = q; q = x; }
+        const double2 cs = rb[tb][lane];
+        if (cs.y != 0.0) {
+#pragma unroll
+          for (int r = 0; r < kRepRows; ++r) {
+            const double vp = row[r][p], vq = row[r][q];
+            row[r][p] = cs.x * vp - cs.y * vq;
+            row[r][q] = cs.y * vp + cs.x * vq;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
-  for (int j = lane; j < k; j += 64) st.VM[size_t(i) * kcap + j] = row[j];
+  for (int r = 0; r < kRepRows; ++r) {
+    const int i = i0 + r;
+    if (i >= k) break;
+    for (int j = lane; j < k; j += 64) st.VM[size_t(i) * kcap + j] = row[r][j];
+  }
 }
 
 void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_replay_kernel, dim3(kcap), dim3(64), 0, s, st, kcap);
+  ProfScope ps(K_REPLAY, s);
+  hipLaunchKernelGGL(jacobi_replay_kernel, dim3((kcap + kRepRows - 1) / kRepRows), dim3(64), 0, s,
+                     st, kcap);
   LRC_HIP(hipGetLastError());
 }
 
@@ -394,6 +417,7 @@ void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, 
   // H = M^T M
   SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
   small_gemm(&jh, 1, core, st.k, kcap, s);
+  ProfScope ps(K_JACOBI, s);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, st, kcap, max_rounds);
   LRC_HIP(hipGetLastError());
 }
@@ -466,8 +490,11 @@ void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, doub
   none.nb = 0;
   SmallGemm jw{st.M, st.VM, st.W, nullptr, nullptr, nullptr, 0, 0, 0};
   small_gemm(&jw, 1, none, st.k, kcap, s);
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, st, kcap, rank_cap, tol, s_out,
-                     rank_out, norm_out);
+  {
+    ProfScope ps(K_SELECT, s);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, st, kcap, rank_cap, tol, s_out,
+                       rank_out, norm_out);
+  }
   // XA = R2i_A W[:, order] diag(1 / sigma),  XB = R2i_B V[:, order]
   SmallGemm jx[2];
   jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, st.invsig, rank_out, 0, 0, 0};

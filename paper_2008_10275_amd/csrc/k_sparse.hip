@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace lrc {
 
@@ -77,6 +78,7 @@ void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_
   const int64_t rows_per_block = int64_t(rpw) * 4;
   const int64_t blocks = std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32);
   dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(q));
+  ProfScope ps(K_SPMM, s);
   switch (cpl) {
     case 2:
       hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
@@ -102,124 +104,124 @@ template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int
                                   int, int, double* const*, int, int, hipStream_t);
 
 // ============================================================== preconditioner
-// One workgroup computes TR output rows of one supernode for all k columns.
-// Thread t owns row (t % TR) and the column quads q = t / TR + NG * j.
-constexpr int kTR = 64;        // rows per workgroup
-constexpr int kIC = 32;        // input rows staged per LDS chunk
+// Each level of the supernode tree is processed in two launches:
+//  1. gather: every front row of the level's supernodes is assembled into a
+//     dense staging block (forward: b(perm) + children's contribution rows;
+//     backward: [y_own ; x(boundary)]), one thread per entry;
+//  2. product: one workgroup per (supernode, 16 output rows); the 4 waves
+//     split the input dimension, each accumulates a 16 x 64 tile on MFMA
+//     (16x16x4), and the partial tiles are summed through LDS.
+typedef float floatx4_s __attribute__((ext_vector_type(4)));
+typedef double doublex4_s __attribute__((ext_vector_type(4)));
+template <class T> struct PMfma;
+template <> struct PMfma<float> {
+  typedef floatx4_s acc_t;
+  static __device__ inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int drow(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <> struct PMfma<double> {
+  typedef doublex4_s acc_t;
+  static __device__ inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int drow(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
 constexpr int kKMAX = 64;      // max columns per apply
+constexpr int kPT = 16;        // output rows per product workgroup
 
-template <class T>
-__device__ inline void assemble_front_row(const PrecDev<T>& P, int64_t frow, const T* cb, int ldw,
-                                          int c, T& v) {
-  const int64_t e0 = P.asm_ptr[frow], e1 = P.asm_ptr[frow + 1];
-  for (int64_t e = e0; e < e1; ++e) v += cb[P.asm_src[e] * ldw + c];
-}
-
-// forward level:  [y_own ; cb_s] = Fw_s * f_own + [0 ; f_bnd]
-template <class T>
-__global__ __launch_bounds__(256) void prec_fwd_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
-                                                       const T* __restrict__ R, int ldr,
-                                                       const int* __restrict__ k_dev, int k_const,
-                                                       T* __restrict__ y, T* __restrict__ cb,
-                                                       int ldw) {
-  __shared__ T stage[kIC][kKMAX + 1];
-  const int2 task = tasks[blockIdx.x];
-  const int sn = task.x;
+template <class T, bool FWD>
+__global__ __launch_bounds__(256) void prec_gather_kernel(PrecDev<T> P, const int2* __restrict__ rows,
+                                                          int nrows, const int64_t* __restrict__ soff,
+                                                          const T* __restrict__ R, int ldr,
+                                                          const T* __restrict__ y,
+                                                          const T* __restrict__ x,
+                                                          const T* __restrict__ cb, int ldw,
+                                                          const int* __restrict__ k_dev, int k_const,
+                                                          int kcap, T* __restrict__ stage) {
   const int k = k_dev ? *k_dev : k_const;
-  const int ns = P.ns[sn], nbv = P.nb[sn], f = ns + nbv, j0 = P.j0[sn];
-  const int64_t front0 = P.front_off[sn];
-  const T* __restrict__ fw = P.fw + P.fw_off[sn];
-  const int tr = threadIdx.x % kTR;
-  const int cg = threadIdx.x / kTR;              // 0..3
-  const int row = task.y + tr;
-  const bool rv = row < f;
-  T acc[kKMAX / 4];
-#pragma unroll
-  for (int j = 0; j < kKMAX / 4; ++j) acc[j] = T(0);
-  for (int i0 = 0; i0 < ns; i0 += kIC) {
-    const int ic = min(kIC, ns - i0);
-    for (int e = threadIdx.x; e < ic * k; e += blockDim.x) {
-      const int i = e / k, c = e - i * k;
-      T v = R[int64_t(P.perm[j0 + i0 + i]) * ldr + c];
-      assemble_front_row(P, front0 + i0 + i, cb, ldw, c, v);
-      stage[i][c] = v;
-    }
-    __syncthreads();
-    if (rv) {
-      for (int i = 0; i < ic; ++i) {
-        const T a = fw[int64_t(i0 + i) * f + row];
-#pragma unroll
-        for (int j = 0; j < kKMAX / 4; ++j) {
-          const int c = cg + 4 * j;
-          if (c < k) acc[j] += a * stage[i][c];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (!rv) return;
-#pragma unroll
-  for (int j = 0; j < kKMAX / 4; ++j) {
-    const int c = cg + 4 * j;
+  const int64_t total = int64_t(nrows) * kcap;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int item = int(e / kcap);
+    const int c = int(e - int64_t(item) * kcap);
     if (c >= k) continue;
-    T v = acc[j];
-    if (row < ns) {
-      y[int64_t(j0 + row) * ldw + c] = v;
+    const int2 sp = rows[item];
+    const int sn = sp.x, p = sp.y;
+    const int ns = P.ns[sn], j0 = P.j0[sn];
+    T v;
+    if (FWD) {
+      v = (p < ns) ? R[int64_t(P.perm[j0 + p]) * ldr + c] : T(0);
+      const int64_t fr = P.front_off[sn] + p;
+      for (int64_t q = P.asm_ptr[fr]; q < P.asm_ptr[fr + 1]; ++q) v += cb[P.asm_src[q] * ldw + c];
     } else {
-      assemble_front_row(P, front0 + row, cb, ldw, c, v);
-      cb[(P.cb_off[sn] + row - ns) * ldw + c] = v;
+      v = (p < ns) ? y[int64_t(j0 + p) * ldw + c]
+                   : x[int64_t(P.bnd[P.bnd_off[sn] + p - ns]) * ldw + c];
     }
+    stage[(soff[sn] + p) * ldw + c] = v;
   }
 }
 
-// backward level:  x_own = Bw_s * [y_own ; x(bnd)];  also Z(perm) = x
-template <class T>
-__global__ __launch_bounds__(256) void prec_bwd_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
-                                                       const int* __restrict__ k_dev, int k_const,
-                                                       const T* __restrict__ y, T* __restrict__ x,
-                                                       int ldw, T* __restrict__ Z, int ldz) {
-  __shared__ T stage[kIC][kKMAX + 1];
+template <class T, bool FWD>
+__global__ __launch_bounds__(256) void prec_product_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
+                                                           const int64_t* __restrict__ soff,
+                                                           const T* __restrict__ stage, int ldw,
+                                                           const int* __restrict__ k_dev, int k_const,
+                                                           T* __restrict__ y, T* __restrict__ x,
+                                                           T* __restrict__ cb, T* __restrict__ Z,
+                                                           int ldz) {
+  typedef typename PMfma<T>::acc_t acc_t;
+  __shared__ T red[4][kPT][kKMAX + 1];
   const int2 task = tasks[blockIdx.x];
-  const int sn = task.x;
+  const int sn = task.x, row0 = task.y;
   const int k = k_dev ? *k_dev : k_const;
-  const int ns = P.ns[sn], nbv = P.nb[sn], f = ns + nbv, j0 = P.j0[sn];
-  const T* __restrict__ bw = P.bw + P.bw_off[sn];
-  const int* __restrict__ bnd = P.bnd + P.bnd_off[sn];
-  const int tr = threadIdx.x % kTR;
-  const int cg = threadIdx.x / kTR;
-  const int row = task.y + tr;
-  const bool rv = row < ns;
-  T acc[kKMAX / 4];
+  const int KT = (k + 15) / 16;
+  const int ns = P.ns[sn], f = ns + P.nb[sn], j0 = P.j0[sn];
+  const int nin = FWD ? ns : f;
+  const int nout = FWD ? f : ns;
+  const T* __restrict__ M = FWD ? P.fw + P.fw_off[sn] : P.bw + P.bw_off[sn];
+  const int ldM = FWD ? f : ns;                  // column-major: element (row, i) at i * ldM + row
+  const T* __restrict__ In = stage + soff[sn] * ldw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = ((nin + 3) / 4 + 3) / 4 * 4;
+  const int i0 = wave * chunk, i1 = min(nin, i0 + chunk);
+  const int orow = row0 + (lane & 15);
+  const bool rowok = orow < nout;
+  acc_t acc[kKMAX / 16];
 #pragma unroll
-  for (int j = 0; j < kKMAX / 4; ++j) acc[j] = T(0);
-  for (int i0 = 0; i0 < f; i0 += kIC) {
-    const int ic = min(kIC, f - i0);
-    for (int e = threadIdx.x; e < ic * k; e += blockDim.x) {
-      const int i = e / k, c = e - i * k;
-      const int ii = i0 + i;
-      stage[i][c] = (ii < ns) ? y[int64_t(j0 + ii) * ldw + c] : x[int64_t(bnd[ii - ns]) * ldw + c];
-    }
-    __syncthreads();
-    if (rv) {
-      for (int i = 0; i < ic; ++i) {
-        const T a = bw[int64_t(i0 + i) * ns + row];
+  for (int t = 0; t < kKMAX / 16; ++t) acc[t] = acc_t{};
+  for (int kk = i0; kk < i1; kk += 4) {
+    const int i = kk + (lane >> 4);
+    const bool iok = i < i1;
+    const T a = (iok && rowok) ? M[int64_t(i) * ldM + orow] : T(0);
 #pragma unroll
-        for (int j = 0; j < kKMAX / 4; ++j) {
-          const int c = cg + 4 * j;
-          if (c < k) acc[j] += a * stage[i][c];
-        }
+    for (int t = 0; t < kKMAX / 16; ++t) {
+      if (t < KT) {
+        const int c = t * 16 + (lane & 15);
+        const T b = (iok && c < k) ? In[int64_t(i) * ldw + c] : T(0);
+        acc[t] = PMfma<T>::op(a, b, acc[t]);
       }
     }
-    __syncthreads();
   }
-  if (!rv) return;
-  const int64_t orow = P.perm[j0 + row];
 #pragma unroll
-  for (int j = 0; j < kKMAX / 4; ++j) {
-    const int c = cg + 4 * j;
-    if (c >= k) continue;
-    x[int64_t(j0 + row) * ldw + c] = acc[j];
-    Z[orow * ldz + c] = acc[j];
+  for (int t = 0; t < kKMAX / 16; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][PMfma<T>::drow(lane, v)][t * 16 + (lane & 15)] = acc[t][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPT * kKMAX; e += blockDim.x) {
+    const int r = e / kKMAX, c = e - r * kKMAX;
+    const int row = row0 + r;
+    if (c >= k || row >= nout) continue;
+    const T v = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
+    if (FWD) {
+      if (row < ns) y[int64_t(j0 + row) * ldw + c] = v;
+      else cb[(P.cb_off[sn] + row - ns) * ldw + c] = v + In[int64_t(row) * ldw + c];
+    } else {
+      x[int64_t(j0 + row) * ldw + c] = v;
+      Z[int64_t(P.perm[j0 + row]) * ldz + c] = v;
+    }
   }
 }
 
@@ -227,32 +229,54 @@ template <class T>
 void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                        const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
                        const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
-                       int ldw, hipStream_t s) {
+                       T* ws_stage, int ldw, hipStream_t s) {
   LRC_CHECK(kcap >= 1 && kcap <= kKMAX, ST_EINVAL,
             "preconditioner apply: at most 64 right-hand sides per call");
   LRC_CHECK(ldw >= kcap && ldr >= kcap && ldz >= kcap, ST_EINVAL,
             "preconditioner apply: leading dimension smaller than the column capacity");
+  auto gblocks = [&](int nrows) {
+    return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(int64_t(nrows) * kcap, 256), 1), 65535));
+  };
   for (const auto& L : fwd) {
     if (L.count == 0) continue;
-    hipLaunchKernelGGL((prec_fwd_kernel<T>), dim3(L.count), dim3(256), 0, s, P, L.tasks, R, ldr,
-                       k_dev, k_const, ws_y, ws_cb, ldw);
+    {
+      ProfScope ps(K_PREC_GATHER, s);
+      hipLaunchKernelGGL((prec_gather_kernel<T, true>), dim3(gblocks(L.nrows)), dim3(256), 0, s, P,
+                         L.rows, L.nrows, P.soff_fwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev, k_const,
+                         kcap, ws_stage);
+    }
+    {
+      ProfScope ps(K_PREC_PRODUCT, s);
+      hipLaunchKernelGGL((prec_product_kernel<T, true>), dim3(L.count), dim3(256), 0, s, P, L.tasks,
+                         P.soff_fwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z, ldz);
+    }
   }
   for (const auto& L : bwd) {
     if (L.count == 0) continue;
-    hipLaunchKernelGGL((prec_bwd_kernel<T>), dim3(L.count), dim3(256), 0, s, P, L.tasks, k_dev,
-                       k_const, ws_y, ws_x, ldw, Z, ldz);
+    {
+      ProfScope ps(K_PREC_GATHER, s);
+      hipLaunchKernelGGL((prec_gather_kernel<T, false>), dim3(gblocks(L.nrows)), dim3(256), 0, s,
+                         P, L.rows, L.nrows, P.soff_bwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev,
+                         k_const, kcap, ws_stage);
+    }
+    {
+      ProfScope ps(K_PREC_PRODUCT, s);
+      hipLaunchKernelGGL((prec_product_kernel<T, false>), dim3(L.count), dim3(256), 0, s, P,
+                         L.tasks, P.soff_bwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z,
+                         ldz);
+    }
   }
   LRC_HIP(hipGetLastError());
 }
 
 template void launch_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
                                        const std::vector<LevelTasks>&, const float*, int, float*,
-                                       int, const int*, int, int, float*, float*, float*, int,
-                                       hipStream_t);
+                                       int, const int*, int, int, float*, float*, float*, float*,
+                                       int, hipStream_t);
 template void launch_prec_apply<double>(const PrecDev<double>&, const std::vector<LevelTasks>&,
                                         const std::vector<LevelTasks>&, const double*, int,
                                         double*, int, const int*, int, int, double*, double*,
-                                        double*, int, hipStream_t);
+                                        double*, double*, int, hipStream_t);
 
 // ============================================================== vectors
 template <class Tin, class Tout>

@@ -27,8 +27,10 @@ void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_
 
 // Level-scheduled supernodal triangular solves (data from nd_factor).
 struct LevelTasks {
-  const int2* tasks;   // (supernode, first row) per workgroup
+  const int2* tasks;   // product: (supernode, first output row) per workgroup (16 rows)
   int count;
+  const int2* rows;    // gather: (supernode, front row) per staged row
+  int nrows;
 };
 
 template <class T>
@@ -48,15 +50,18 @@ struct PrecDev {
   const int* bnd;
   const T* fw;
   const T* bw;
+  const int64_t* soff_fwd;   // staging row offset of each supernode in its forward level
+  const int64_t* soff_bwd;   // ... in its backward level
 };
 
 // Z = P^{-1} R  (R, Z: n x k row-major; k read from k_dev or k_const, <= kcap <= 64).
-// ws_y, ws_x: n x ldw scratch; ws_cb: (contribution rows) x ldw scratch.
+// ws_y, ws_x: n x ldw scratch; ws_cb: (contribution rows) x ldw scratch;
+// ws_stage: (largest level's front rows) x ldw scratch.
 template <class T>
 void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                        const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
                        const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
-                       int ldw, hipStream_t s);
+                       T* ws_stage, int ldw, hipStream_t s);
 
 // ----------------------------------------------------------------- dense tall-skinny
 // Partial Gram products G = X^T X for up to two operands in one launch; the

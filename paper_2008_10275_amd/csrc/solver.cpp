@@ -159,6 +159,18 @@ void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, 
   TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
                       {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
   launch_tsmm<T>(t2, 2, kcap, rank_cap, s);
+  if (log_enabled()) {
+    int hk[4] = {0, 0, 0, 0};
+    double hn = 0.0;
+    LRC_HIP(hipMemcpyAsync(&hk[0], st.k, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&hk[1], rank_out, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&hk[2], st.info, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&hk[3], st.rounds, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&hn, norm_out, 8, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "{\"trunc\": %d, \"k\": %d, \"rank\": %d, \"norm\": %.9e, \"info\": %d, \"rounds\": %d}\n",
+                 int(sizeof(T)), hk[0], hk[1], hn, hk[2], hk[3]);
+  }
 }
 template struct Truncator<double>;
 template struct Truncator<float>;
@@ -183,7 +195,9 @@ void Cheb<T>::alloc(Prob* p, int cap_) {
   py.alloc(size_t(n) * ld * sizeof(T));
   px.alloc(size_t(n) * ld * sizeof(T));
   const int64_t cbr = P->prec ? P->prec->cb_rows : 0;
+  const int64_t str = P->prec ? P->prec->stage_rows : 0;
   pcb.alloc(size_t(std::max<int64_t>(cbr, 1)) * ld * sizeof(T));
+  pst.alloc(size_t(std::max<int64_t>(str, 1)) * ld * sizeof(T));
   norm.alloc(64);
   tr.alloc(n, m, s);
 }
@@ -199,7 +213,7 @@ void Cheb<T>::spmm(const T* U, int ldu, const int* r_dev) {
 }
 
 template <class T>
-void Cheb<T>::residual(const LR<T>& B, double* norm_dev) {
+void Cheb<T>::residual(const LR<T>& B, double* norm_dev, double tol) {
   const Ops& o = *P->ops;
   const int ld = ld_for(cap);
   spmm(S.u(), S.ld, S.r());
@@ -213,7 +227,7 @@ void Cheb<T>::residual(const LR<T>& B, double* norm_dev) {
     add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
     add_core(c, S.sv(), -1.0, S.r(), 0);
   }
-  tr.run(A, o.n, Bv, P->m, c, cap, 0.0, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev,
+  tr.run(A, o.n, Bv, P->m, c, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev,
          P->ctx->stream);
 }
 
@@ -221,7 +235,7 @@ template <class T>
 void Cheb<T>::precond(const T* Rm, int ldr, const int* k_dev, T* Zm, int ldz) {
   const int ld = ld_for(cap);
   launch_prec_apply<T>(P->prec->dev<T>(), P->prec->fwd, P->prec->bwd, Rm, ldr, Zm, ldz, k_dev, 0,
-                       cap, py.as<T>(), px.as<T>(), pcb.as<T>(), ld, P->ctx->stream);
+                       cap, py.as<T>(), px.as<T>(), pcb.as<T>(), pst.as<T>(), ld, P->ctx->stream);
 }
 
 template <class T>
@@ -475,7 +489,8 @@ static int median_solve(Prob& P, int jmed, double c, double dc, double tol, int 
   LRC_HIP(hipMemsetAsync(r.p, 0, r.bytes, s));
   LRC_HIP(hipMemsetAsync(z.p, 0, z.bytes, s));
   const int64_t cbr = P.prec->cb_rows;
-  DevBuf py(size_t(n) * ld * 8), px(size_t(n) * ld * 8), pcb(size_t(std::max<int64_t>(cbr, 1)) * ld * 8);
+  DevBuf py(size_t(n) * ld * 8), px(size_t(n) * ld * 8), pcb(size_t(std::max<int64_t>(cbr, 1)) * ld * 8),
+      pst(size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * ld * 8);
   double* Wp[kMaxOps];
   for (int i = 0; i < op.q; ++i) Wp[i] = Wb.as<double>() + size_t(i) * n * ld;
   auto residual = [&]() {
@@ -491,7 +506,7 @@ static int median_solve(Prob& P, int jmed, double c, double dc, double tol, int 
   auto prec = [&]() {
     launch_prec_apply<double>(P.prec->p64, P.prec->fwd, P.prec->bwd, r.as<double>(), ld,
                               z.as<double>(), ld, nullptr, 1, 1, py.as<double>(), px.as<double>(),
-                              pcb.as<double>(), ld, s);
+                              pcb.as<double>(), pst.as<double>(), ld, s);
   };
   c = std::max(c, 1e-12 * dc);
   const double sigma = dc / c;
@@ -558,7 +573,15 @@ lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, c
   P.rank_x0 = 0;
   if (o.init == LRC_INIT_MEDIAN) {
     const int jmed = int(m / 2);
-    inf.median_iters = median_solve(P, jmed, c, dc, o.median_tol > 0 ? o.median_tol : 1e-10,
+    // the single median column has its own, much narrower, spectrum interval
+    double lo = 1.0, hi = 1.0;
+    for (int i = 0; i < op.q; ++i) {
+      const double rt = P.d[size_t(jmed) * op.q + i] / P.dbar[i];
+      lo = std::min(lo, rt);
+      hi = std::max(hi, rt);
+    }
+    const double cm = std::max(0.5 * (hi - lo), 1e-3 * 0.5 * (hi + lo)), dm = 0.5 * (hi + lo);
+    inf.median_iters = median_solve(P, jmed, cm, dm, o.median_tol > 0 ? o.median_tol : 1e-10,
                                     1000, P.X0);
     P.rank_x0 = 1;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
@@ -603,9 +626,10 @@ lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, c
     double* nd = c64.norm.as<double>();
     const double target = o.res_tol * P.fnorm;
     const int refine_max = o.refine_max > 0 ? o.refine_max : 8;
+    const double rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
     while (true) {
-      // fp64 residual, truncated to the rank cap: the right-hand side of the correction
-      c64.residual(B64, nd);
+      // fp64 residual, truncated to the inner solve's accuracy: the correction's rhs
+      c64.residual(B64, nd, rhs_tol);
       LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, 8, hipMemcpyDeviceToHost, s));
       ctx.sync();
       last = ctx.pinned[0];

@@ -40,8 +40,9 @@ struct Prec {
   SupernodalFactor F;   // host copy (blocks freed after upload)
   DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd;
   DevBuf fw64, bw64, fw32, bw32;
-  DevBuf fwd_tasks, bwd_tasks;
+  DevBuf fwd_tasks, bwd_tasks, soff_fwd, soff_bwd;
   std::vector<LevelTasks> fwd, bwd;
+  int64_t stage_rows = 0;
   PrecDev<double> p64;
   PrecDev<float> p32;
   int64_t cb_rows = 0;
@@ -87,14 +88,14 @@ struct Cheb {
   Prob* P = nullptr;
   int cap = 0;
   LR<T> S, D, R;
-  DevBuf W, Z, py, px, pcb, norm;
+  DevBuf W, Z, py, px, pcb, pst, norm;
   Truncator<T> tr;
   void alloc(Prob* p, int cap_);
   // returns iterations; sets converged
   int solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c, double dc,
             int max_iter, bool* converged, double* last_norm, int* prec_applies, int* flags,
             double abs_target = 0.0, int stall_limit = 1 << 30);
-  void residual(const LR<T>& B, double* norm_dev);
+  void residual(const LR<T>& B, double* norm_dev, double tol = 0.0);
   void precond(const T* R, int ldr, const int* k_dev, T* Z, int ldz);
   void spmm(const T* U, int ldu, const int* r_dev);
 };

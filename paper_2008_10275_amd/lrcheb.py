@@ -80,6 +80,9 @@ _SIGS = {
     "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
                                    _P, C.c_int, C.c_int, C.c_double, _P, C.c_int, _P, _P,
                                    C.c_int, C.POINTER(C.c_int)]),
+    "lrc_profile_enable": (C.c_int, [C.c_int]),
+    "lrc_profile_read": (C.c_int, [C.c_int, _P, _P]),
+    "lrc_profile_class_name": (C.c_char_p, [C.c_int]),
     "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, LINEARIZE_FN, _P,
                                      C.POINTER(lrc_opts), C.POINTER(_P), C.POINTER(lrc_info)]),
 }
@@ -313,13 +316,31 @@ class Problem:
             pass
 
 
+def profile_enable(on=True):
+    """Start (clearing the record) or stop per-kernel-class HIP event timing."""
+    load().lrc_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """{class name: (summed kernel ms, launches)} of the events recorded so far."""
+    lib = load()
+    n = lib.lrc_profile_read(0, None, None)
+    ms = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int32)
+    lib.lrc_profile_read(n, _ptr(ms), _ptr(cnt))
+    return {lib.lrc_profile_class_name(i).decode(): (float(ms[i]), int(cnt[i]))
+            for i in range(n)}
+
+
 def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V):
     """lrc_truncate_dev on row-major device tensors; returns (s, rank)."""
     import torch
     dtype = 0 if A.dtype == torch.float64 else 1
-    n, k = A.shape
+    cc = _f64(np.ravel(c))
+    n, k = A.shape[0], cc.size
     m = B.shape[0]
-    cc = _f64(c)
+    if A.shape[1] < k or B.shape[1] < k:
+        raise ValueError("A and B need at least len(c) columns")
     s = np.zeros(64)
     r = C.c_int()
     _check(ctx.handle, load().lrc_truncate_dev(ctx.handle, dtype, n, m, k, _dev_ptr(A),
