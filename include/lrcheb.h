@@ -164,14 +164,20 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
 
 /* --------------------------------------------------------------- timing
  * Per-kernel-class timing with HIP events recorded on the stream each kernel
- * is launched on (process-wide, not thread-safe; adds two event records per
- * launch while on).  lrc_profile_enable(1) starts and clears the record,
- * lrc_profile_enable(0) stops (the record is kept).  lrc_profile_read
- * synchronises the recorded events and fills, for class c < ncls (the classes
- * are named by lrc_profile_class_name; at most 32), ms[c] = summed kernel time
- * and count[c] = launches (either may be NULL).  Returns the number of classes. */
-lrc_status lrc_profile_enable(int on);
-int lrc_profile_read(int ncls, double* ms, int* count);
+ * is launched on (process-wide, not thread-safe).  A class is a kernel family
+ * and its arithmetic type ("spmm.f32", "gram.f64", ...; lrc_profile_class_name).
+ * lrc_profile_enable(mode): 0 stops recording (the record is kept); 1 clears
+ * the record and brackets every launch with two event records; 2 clears and,
+ * in addition, copies the device-resident widths each launch reads (4-byte
+ * device-to-device copies before the first event, so outside the bracket)
+ * so that its algorithmic work can be totalled.  LRC_EINVAL for another mode.
+ * lrc_profile_read synchronises the recorded events and fills, for classes
+ * c < ncls (any array may be NULL): ms[c] summed kernel time, count[c]
+ * launches, work[c] summed algorithmic work of the launches recorded in mode
+ * 2 and unit[c] its unit (0 no model, 1 HBM bytes, 2 flops).  Returns the
+ * number of classes. */
+lrc_status lrc_profile_enable(int mode);
+int lrc_profile_read(int ncls, double* ms, int* count, double* work, int* unit);
 const char* lrc_profile_class_name(int c);
 
 /* --------------------------------------------------------------- Algorithm 1

@@ -92,9 +92,15 @@ void build_levels(Prec& pr, hipStream_t s) {
   const int TR = 16;   // output rows per product workgroup
   std::vector<std::vector<int2>> ft(F.nlev_fwd), bt(F.nlev_bwd), fr(F.nlev_fwd), br(F.nlev_bwd);
   std::vector<int64_t> soff_f(F.nsn, 0), soff_b(F.nsn, 0), lf(F.nlev_fwd, 0), lb(F.nlev_bwd, 0);
+  std::vector<double> blk_f(F.nlev_fwd, 0.0), blk_b(F.nlev_bwd, 0.0);
+  std::vector<int64_t> ns_f(F.nlev_fwd, 0), ns_b(F.nlev_bwd, 0);
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
     const int hf = F.height[sn], db = F.depth[sn];
+    blk_f[hf] += double(f) * F.ns[sn];
+    blk_b[db] += double(f) * F.ns[sn];
+    ns_f[hf] += F.ns[sn];
+    ns_b[db] += F.ns[sn];
     for (int r0 = 0; r0 < f; r0 += TR) ft[hf].push_back(make_int2(sn, r0));
     for (int r0 = 0; r0 < F.ns[sn]; r0 += TR) bt[db].push_back(make_int2(sn, r0));
     soff_f[sn] = lf[hf];
@@ -120,10 +126,14 @@ void build_levels(Prec& pr, hipStream_t s) {
   const int2* base = pr.fwd_tasks.as<int2>();
   pr.fwd.clear();
   pr.bwd.clear();
+  // forward products read the ns own rows of each front and write all f rows;
+  // backward products read all f rows and write the ns own rows twice (x, Z)
   for (size_t l = 0; l < ft.size(); ++l)
-    pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size())});
+    pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size()),
+                      blk_f[l], ns_f[l], lf[l]});
   for (size_t l = 0; l < bt.size(); ++l)
-    pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size())});
+    pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size()),
+                      blk_b[l], lb[l], 2 * ns_b[l]});
   LRC_HIP(hipStreamSynchronize(s));
 }
 
@@ -187,20 +197,23 @@ void upload_prec(Prec& pr, hipStream_t s) {
 
 extern "C" {
 
-lrc_status lrc_profile_enable(int on) {
+lrc_status lrc_profile_enable(int mode) {
+  if (mode < 0 || mode > 2) return LRC_EINVAL;
   Profiler& p = profiler();
-  if (on) p.clear();
-  p.on = on != 0;
+  if (mode) p.clear();
+  p.mode = mode;
   return LRC_OK;
 }
 
-int lrc_profile_read(int ncls, double* ms, int* count) {
-  double t[K_COUNT];
-  int c[K_COUNT];
-  profiler().read(t, c);
+int lrc_profile_read(int ncls, double* ms, int* count, double* work, int* unit) {
+  double t[K_COUNT], w[K_COUNT];
+  int c[K_COUNT], u[K_COUNT];
+  profiler().read(t, c, w, u);
   for (int k = 0; k < K_COUNT && k < ncls; ++k) {
     if (ms) ms[k] = t[k];
     if (count) count[k] = c[k];
+    if (work) work[k] = w[k];
+    if (unit) unit[k] = u[k];
   }
   return K_COUNT;
 }
@@ -300,8 +313,9 @@ lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* r
       O.upload_values(i);
     }
     for (int i = 0; i < q; ++i) {
-      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n});
-      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n});
+      const int64_t nnz = O.host[i].rowptr[n];
+      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz});
+      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz});
     }
     *out = o.release();
     return LRC_OK;

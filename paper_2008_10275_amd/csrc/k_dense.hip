@@ -13,6 +13,14 @@
 
 namespace lrc {
 
+template <class T>
+static std::vector<WTerm> view_terms(const BlockView<T>& v) {
+  std::vector<WTerm> t;
+  for (int b = 0; b < v.nb; ++b) t.push_back({v.wdev[b], v.wconst[b]});
+  return t;
+}
+
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -201,11 +209,20 @@ void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial
   const size_t need = size_t(a.nwg0 + a.nwg1) * kTiles * 256 * sizeof(T);
   LRC_CHECK(need <= ws_bytes, ST_EINVAL, "gram: workspace too small");
   {
-    ProfScope ps(K_GRAM, s);
+    // algorithmic flops: the k(k+1)/2 distinct entries of each Gram matrix,
+    // 2 flops per row each
+    Work w;
+    w.bytes = false;
+    const double r0 = double(a.rows[0]), r1 = double(a.rows[1]);
+    w.groups = {view_terms(jobs[0].X), view_terms(njobs > 1 ? jobs[1].X : jobs[0].X)};
+    w.f = [=](const std::vector<double>& v) {
+      return r0 * v[0] * (v[0] + 1.0) + r1 * v[1] * (v[1] + 1.0);
+    };
+    ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, w);
     hipLaunchKernelGGL((gram_kernel<T, T>), dim3(a.nwg0 + a.nwg1), dim3(256), 0, s, a,
                        reinterpret_cast<T*>(ws_partial));
   }
-  ProfScope ps(K_GRAM_REDUCE, s);
+  ProfScope ps(kcls(K_GRAM_REDUCE, is_f32<T>()), s);
   const int elems = kTiles * 256;
   hipLaunchKernelGGL((gram_reduce_kernel<T, T>), dim3(ceil_div(elems, 256), njobs), dim3(256), 0,
                      s, a, reinterpret_cast<const T*>(ws_partial), jobs[0].G,
@@ -308,7 +325,15 @@ void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStrea
     a.nwg1 = 0;
   }
   const int slices = int(ceil_div(rcap, kTsSlice));
-  ProfScope ps(K_TSMM, s);
+  // algorithmic flops: 2 rows k r per job
+  Work w;
+  w.bytes = false;
+  const double r0 = double(a.nwg0 > 0 ? jobs[0].rows : 0), r1 = double(a.nwg1 > 0 ? jobs[1].rows : 0);
+  w.groups = {view_terms(jobs[0].X), {{jobs[0].r_dev, 0}},
+              view_terms(njobs > 1 ? jobs[1].X : jobs[0].X),
+              {{njobs > 1 ? jobs[1].r_dev : jobs[0].r_dev, 0}}};
+  w.f = [=](const std::vector<double>& v) { return 2.0 * (r0 * v[0] * v[1] + r1 * v[2] * v[3]); };
+  ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, w);
   hipLaunchKernelGGL((tsmm_kernel<T>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
   LRC_HIP(hipGetLastError());
 }
@@ -426,7 +451,13 @@ void launch_residual_fp64(const BlockView<double>& A, int64_t n, const BlockView
   LRC_CHECK(ws_bytes >= residual_workspace_bytes(n, m), ST_EINVAL, "residual: workspace too small");
   const int groups = int(std::min<int64_t>(kResRowGroups, std::max<int64_t>(1, ceil_div(n, kResRows))));
   dim3 grid(unsigned(ceil_div(m, kResCols)), unsigned(groups));
-  ProfScope ps(K_RESIDUAL, s);
+  // algorithmic flops: every entry of the n x m residual is a k-term dot product
+  Work w;
+  w.bytes = false;
+  const double nm = double(n) * double(m);
+  w.groups = {view_terms(A)};
+  w.f = [=](const std::vector<double>& v) { return 2.0 * nm * v[0]; };
+  ProfScope ps(kcls(K_RESIDUAL, false), s, w);
   hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, A, n, B, core, m, ws);
   hipLaunchKernelGGL(residual_reduce_kernel, dim3(unsigned(ceil_div(m, 256))), dim3(256), 0, s, ws,
                      groups, m, colsq);

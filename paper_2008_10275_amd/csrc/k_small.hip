@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
 
 void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s) {
   LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
-  ProfScope ps(K_CHOL, s);
+  ProfScope ps(kcls(K_CHOL, false), s);
   hipLaunchKernelGGL(chol_kernel, dim3(2), dim3(256), 0, s, st, pass, kcap, eps_gram);
   LRC_HIP(hipGetLastError());
 }
@@ -235,7 +235,7 @@ static void small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const in
   a.k = k;
   a.kcap = kcap;
   const int t = (kcap + 15) / 16;
-  ProfScope ps(K_SMALL_GEMM, s);
+  ProfScope ps(kcls(K_SMALL_GEMM, false), s);
   hipLaunchKernelGGL(small_gemm_kernel, dim3(t, t, njobs), dim3(256), 0, s, a);
 }
 
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(64) void jacobi_replay_kernel(TruncState st, int kc
 }
 
 void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s) {
-  ProfScope ps(K_REPLAY, s);
+  ProfScope ps(kcls(K_REPLAY, false), s);
   hipLaunchKernelGGL(jacobi_replay_kernel, dim3((kcap + kRepRows - 1) / kRepRows), dim3(64), 0, s,
                      st, kcap);
   LRC_HIP(hipGetLastError());
@@ -417,7 +417,7 @@ void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, 
   // H = M^T M
   SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
   small_gemm(&jh, 1, core, st.k, kcap, s);
-  ProfScope ps(K_JACOBI, s);
+  ProfScope ps(kcls(K_JACOBI, false), s);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, st, kcap, max_rounds);
   LRC_HIP(hipGetLastError());
 }
@@ -491,7 +491,7 @@ void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, doub
   SmallGemm jw{st.M, st.VM, st.W, nullptr, nullptr, nullptr, 0, 0, 0};
   small_gemm(&jw, 1, none, st.k, kcap, s);
   {
-    ProfScope ps(K_SELECT, s);
+    ProfScope ps(kcls(K_SELECT, false), s);
     hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, st, kcap, rank_cap, tol, s_out,
                        rank_out, norm_out);
   }

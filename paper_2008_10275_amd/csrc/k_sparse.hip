@@ -78,7 +78,20 @@ void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_
   const int64_t rows_per_block = int64_t(rpw) * 4;
   const int64_t blocks = std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32);
   dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(q));
-  ProfScope ps(K_SPMM, s);
+  // algorithmic bytes: values + int32 columns + row pointers of every operator,
+  // U read once, every W_i written (all n rows)
+  Work w;
+  {
+    double fixed = 0.0, wrows = 0.0;
+    for (int i = 0; i < q; ++i) {
+      fixed += double(ops[i].nnz) * (sizeof(T) + 4) + double(ops[i].n + 1) * 4;
+      wrows += double(ops[i].n);
+    }
+    const double nr = double(n);
+    w.groups = {{{r_dev, r_const}}};
+    w.f = [=](const std::vector<double>& v) { return fixed + (nr + wrows) * v[0] * sizeof(T); };
+  }
+  ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, w);
   switch (cpl) {
     case 2:
       hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
@@ -225,6 +238,26 @@ __global__ __launch_bounds__(256) void prec_product_kernel(PrecDev<T> P, const i
   }
 }
 
+// algorithmic bytes of one level: a staged row is read from its source and
+// written once; a product reads the level's dense blocks once plus the staged
+// input rows, and writes its output rows (k columns each)
+template <class T>
+static Work gather_work(const LevelTasks& L, const int* k_dev, int k_const) {
+  Work w;
+  const double rows = double(L.nrows);
+  w.groups = {{{k_dev, k_const}}};
+  w.f = [=](const std::vector<double>& v) { return 2.0 * rows * v[0] * sizeof(T); };
+  return w;
+}
+template <class T>
+static Work product_work(const LevelTasks& L, const int* k_dev, int k_const) {
+  Work w;
+  const double blk = L.blk, io = double(L.in_rows + L.out_rows);
+  w.groups = {{{k_dev, k_const}}};
+  w.f = [=](const std::vector<double>& v) { return (blk + io * v[0]) * sizeof(T); };
+  return w;
+}
+
 template <class T>
 void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                        const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
@@ -240,13 +273,13 @@ void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
   for (const auto& L : fwd) {
     if (L.count == 0) continue;
     {
-      ProfScope ps(K_PREC_GATHER, s);
+      ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, k_dev, k_const));
       hipLaunchKernelGGL((prec_gather_kernel<T, true>), dim3(gblocks(L.nrows)), dim3(256), 0, s, P,
                          L.rows, L.nrows, P.soff_fwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev, k_const,
                          kcap, ws_stage);
     }
     {
-      ProfScope ps(K_PREC_PRODUCT, s);
+      ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, k_dev, k_const));
       hipLaunchKernelGGL((prec_product_kernel<T, true>), dim3(L.count), dim3(256), 0, s, P, L.tasks,
                          P.soff_fwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z, ldz);
     }
@@ -254,13 +287,13 @@ void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
   for (const auto& L : bwd) {
     if (L.count == 0) continue;
     {
-      ProfScope ps(K_PREC_GATHER, s);
+      ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, k_dev, k_const));
       hipLaunchKernelGGL((prec_gather_kernel<T, false>), dim3(gblocks(L.nrows)), dim3(256), 0, s,
                          P, L.rows, L.nrows, P.soff_bwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev,
                          k_const, kcap, ws_stage);
     }
     {
-      ProfScope ps(K_PREC_PRODUCT, s);
+      ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, k_dev, k_const));
       hipLaunchKernelGGL((prec_product_kernel<T, false>), dim3(L.count), dim3(256), 0, s, P,
                          L.tasks, P.soff_bwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z,
                          ldz);

@@ -15,6 +15,7 @@ struct DevCsr {
   const int* col;
   const T* val;
   int64_t n;
+  int64_t nnz;
 };
 
 constexpr int kMaxOps = 8;
@@ -31,6 +32,9 @@ struct LevelTasks {
   int count;
   const int2* rows;    // gather: (supernode, front row) per staged row
   int nrows;
+  double blk;          // dense block entries the level's products read
+  int64_t in_rows;     // staged rows the products read (per column)
+  int64_t out_rows;    // rows the products write (per column)
 };
 
 template <class T>

@@ -1,40 +1,64 @@
-// Opt-in timing of kernel classes with HIP events (recorded on the stream each
-// kernel is launched on).  Off by default; when on, every launch of a class is
-// bracketed by an event pair and the durations are summed on request.
+// Opt-in timing of kernel classes with HIP events recorded on the stream each
+// kernel is launched on.  Off by default.  Mode 1 brackets every launch of a
+// class with an event pair; mode 2 additionally snapshots, before the events,
+// the device-resident widths the launch reads (one 4-byte device copy each),
+// so that the algorithmic work of every launch (bytes or flops, from a model
+// written next to the launch) can be totalled afterwards.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <vector>
 
 namespace lrc {
 
 enum KClass {
   K_SPMM = 0, K_GRAM, K_GRAM_REDUCE, K_CHOL, K_TSMM, K_JACOBI, K_REPLAY, K_SMALL_GEMM,
-  K_SELECT, K_PREC_GATHER, K_PREC_PRODUCT, K_RESIDUAL, K_VECTOR, K_COUNT
+  K_SELECT, K_PREC_GATHER, K_PREC_PRODUCT, K_RESIDUAL, K_VECTOR, K_NBASE
+};
+// class index = base * 2 + (fp32 ? 1 : 0)
+constexpr int K_COUNT = 2 * K_NBASE;
+inline int kcls(KClass k, bool f32) { return 2 * int(k) + (f32 ? 1 : 0); }
+const char* kclass_name(int c);
+
+// One width the launch reads: the device int at `dev` when non-null, else `c`.
+struct WTerm {
+  const int* dev;
+  int c;
+};
+// Work model of a launch: widths w_g = sum of the terms of group g; the model
+// maps them to algorithmic work (unit: bytes if `bytes`, else flops).
+struct Work {
+  bool bytes = true;
+  std::vector<std::vector<WTerm>> groups;
+  std::function<double(const std::vector<double>&)> f;
+  bool valid() const { return bool(f); }
 };
 
-inline const char* kclass_name(int k) {
-  static const char* names[K_COUNT] = {"spmm", "gram", "gram_reduce", "chol", "tsmm", "jacobi",
-                                       "jacobi_replay", "small_gemm", "select", "prec_gather",
-                                       "prec_product", "residual_fp64", "vector"};
-  return (k >= 0 && k < K_COUNT) ? names[k] : "?";
-}
-
 struct Profiler {
-  bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[K_COUNT];
+  int mode = 0;   // 0 off, 1 events, 2 events + work
+  struct Launch {
+    hipEvent_t e0, e1;
+    Work w;
+    std::vector<std::vector<int>> slots;   // log slot of each device term (-1 const)
+  };
+  std::vector<Launch> ev[K_COUNT];
+  int* log_dev = nullptr;     // snapshot slots on the device
+  int log_cap = 0, log_used = 0;
   void clear();
-  // durations in ms and launch counts per class (synchronises the events)
-  void read(double* ms, int* count);
+  // per class: summed ms, launches, summed algorithmic work and its unit
+  // (0 none, 1 bytes, 2 flops); synchronises the recorded events
+  void read(double* ms, int* count, double* work, int* unit);
 };
 Profiler& profiler();
 
 struct ProfScope {
-  KClass k;
-  hipStream_t s;
   hipEvent_t e1 = nullptr;
-  ProfScope(KClass k_, hipStream_t s_);
+  hipStream_t s;
+  ProfScope(int cls, hipStream_t s_, Work w = Work());
   ~ProfScope();
 };
+
+template <class T> inline bool is_f32() { return sizeof(T) == 4; }
 
 }  // namespace lrc

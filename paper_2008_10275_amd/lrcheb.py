@@ -81,7 +81,7 @@ _SIGS = {
                                    _P, C.c_int, C.c_int, C.c_double, _P, C.c_int, _P, _P,
                                    C.c_int, C.POINTER(C.c_int)]),
     "lrc_profile_enable": (C.c_int, [C.c_int]),
-    "lrc_profile_read": (C.c_int, [C.c_int, _P, _P]),
+    "lrc_profile_read": (C.c_int, [C.c_int, _P, _P, _P, _P]),
     "lrc_profile_class_name": (C.c_char_p, [C.c_int]),
     "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, LINEARIZE_FN, _P,
                                      C.POINTER(lrc_opts), C.POINTER(_P), C.POINTER(lrc_info)]),
@@ -316,19 +316,28 @@ class Problem:
             pass
 
 
-def profile_enable(on=True):
-    """Start (clearing the record) or stop per-kernel-class HIP event timing."""
-    load().lrc_profile_enable(1 if on else 0)
+def profile_enable(mode=1):
+    """Per-kernel-class HIP event timing: 0 stop, 1 events, 2 events + work
+    accounting (both 1 and 2 clear the record)."""
+    code = load().lrc_profile_enable(int(mode))
+    if code != 0:
+        raise LrcError(code, "lrc_profile_enable: mode must be 0, 1 or 2")
 
 
 def profile_read():
-    """{class name: (summed kernel ms, launches)} of the events recorded so far."""
+    """{class: dict(ms, count, work, unit)} of the launches recorded so far
+    (unit: None, "B" or "flop")."""
     lib = load()
-    n = lib.lrc_profile_read(0, None, None)
+    n = lib.lrc_profile_read(0, None, None, None, None)
     ms = np.zeros(n)
     cnt = np.zeros(n, dtype=np.int32)
-    lib.lrc_profile_read(n, _ptr(ms), _ptr(cnt))
-    return {lib.lrc_profile_class_name(i).decode(): (float(ms[i]), int(cnt[i]))
+    work = np.zeros(n)
+    unit = np.zeros(n, dtype=np.int32)
+    lib.lrc_profile_read(n, _ptr(ms), _ptr(cnt), _ptr(work), _ptr(unit))
+    names = {0: None, 1: "B", 2: "flop"}
+    return {lib.lrc_profile_class_name(i).decode(): dict(ms=float(ms[i]), count=int(cnt[i]),
+                                                          work=float(work[i]),
+                                                          unit=names[int(unit[i])])
             for i in range(n)}
 
 
