@@ -162,6 +162,16 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
                             int ldb, int rank_cap, double tol, void* U_dev, int ldu,
                             double* s, void* V_dev, int ldv, int* rank);
 
+/* Same truncation with B's last k - k1 columns row-scaled: the product is
+ * A diag(c) [B1 | diag(w) B2]^T with B1 = B[:, :k1], B2 = B[:, k1:k], and A is
+ * handled as the two blocks A[:, :k1], A[:, k1:].  This is the structure of
+ * the factored residual's V side, [V_F | D_i V_S] (Sec. 3.4).  w_dev: m device
+ * doubles.  0 <= k1 < k. */
+lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k, int k1,
+                                   const void* A_dev, int lda, const double* c, const void* B_dev,
+                                   int ldb, const double* w_dev, int rank_cap, double tol,
+                                   void* U_dev, int ldu, double* s, void* V_dev, int ldv, int* rank);
+
 /* --------------------------------------------------------------- timing
  * Per-kernel-class timing with HIP events recorded on the stream each kernel
  * is launched on (process-wide, not thread-safe).  A class is a kernel family

@@ -614,6 +614,65 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
   });
 }
 
+lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k, int k1,
+                                   const void* A, int lda, const double* c, const void* B,
+                                   int ldb, const double* w_dev, int rank_cap, double tol, void* U,
+                                   int ldu, double* s, void* V, int ldv, int* rank) {
+  if (!ctx) return LRC_EINVAL;
+  return guarded(&ctx->c, [&]() -> lrc_status {
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "truncate: dtype must be 0 or 1");
+    LRC_CHECK(n >= 1 && m >= 1 && k >= 1 && k <= kTruncCap, ST_EINVAL,
+              "truncate: need n, m >= 1 and 1 <= k <= 128");
+    LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
+              "truncate: rank_cap in [1, 64] and <= ldu, ldv");
+    LRC_CHECK(A && B && c && U && V && s && rank && lda >= k && ldb >= k, ST_EINVAL,
+              "truncate: bad pointers or leading dimensions");
+    LRC_CHECK(w_dev && k1 >= 0 && k1 < k, ST_EINVAL, "truncate: need a row scale and 0 <= k1 < k");
+    hipStream_t st = ctx->c.stream;
+    std::vector<double> ch(c, c + k);
+    DevBuf cd = upload(ch, st), sd(64 * 8), outs(16 * 8);
+    CoreView cv{};
+    cv.nb = 1;
+    cv.s[0] = cd.as<double>();
+    cv.coef[0] = 1.0;
+    cv.wdev[0] = nullptr;
+    cv.wconst[0] = k;
+    auto run = [&](auto* tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      Truncator<T> tr;
+      tr.alloc(n, m, st);
+      // two blocks per side; the second block of B is row-scaled by w
+      const T* a = static_cast<const T*>(A);
+      const T* b = static_cast<const T*>(B);
+      BlockView<T> av{}, bv{};
+      av.nb = bv.nb = 2;
+      av.ptr[0] = a;
+      av.ptr[1] = a + k1;
+      bv.ptr[0] = b;
+      bv.ptr[1] = b + k1;
+      av.ld[0] = av.ld[1] = lda;
+      bv.ld[0] = bv.ld[1] = ldb;
+      av.wconst[0] = bv.wconst[0] = av.cap[0] = bv.cap[0] = k1;
+      av.wconst[1] = bv.wconst[1] = av.cap[1] = bv.cap[1] = k - k1;
+      bv.rowscale[1] = w_dev;
+      int* rk = reinterpret_cast<int*>(outs.as<double>() + 2);
+      tr.run(av, n, bv, m, cv, rank_cap, tol, static_cast<T*>(U), ldu, static_cast<T*>(V), ldv,
+             sd.as<double>(), rk, outs.as<double>(), st);
+      LRC_HIP(hipMemcpyAsync(rank, rk, sizeof(int), hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipStreamSynchronize(st));
+      if (*rank > 0)
+        LRC_HIP(hipMemcpyAsync(s, sd.p, size_t(*rank) * 8, hipMemcpyDeviceToHost, st));
+      int flags = 0;
+      LRC_HIP(hipMemcpyAsync(&flags, tr.st.info, sizeof(int), hipMemcpyDeviceToHost, st));
+      LRC_HIP(hipStreamSynchronize(st));
+      if (flags & 2) throw Error(ST_EBREAKDOWN, "truncate: Cholesky breakdown");
+    };
+    if (dtype == 0) run(static_cast<double*>(nullptr));
+    else run(static_cast<float*>(nullptr));
+    return LRC_OK;
+  });
+}
+
 lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
                               const int64_t* sizes, const double* f, lrc_linearize_fn cb,
                               void* user, const lrc_opts* opts, lrc_prob* out, lrc_info* info) {

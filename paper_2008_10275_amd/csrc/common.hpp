@@ -105,8 +105,17 @@ struct BlockView {
   const int* wdev[kMaxBlocks];
   int wconst[kMaxBlocks];
   int ld[kMaxBlocks];
+  int cap[kMaxBlocks];   // host-known upper bound of each block's width
   int nb;
 };
+
+// upper bound of the total width of a view (host side)
+template <class T>
+inline int view_cap(const BlockView<T>& v) {
+  int c = 0;
+  for (int b = 0; b < v.nb; ++b) c += v.cap[b];
+  return c;
+}
 
 // Diagonal core of a concatenation: block b contributes coef_b * s_b[j]
 // (s_b == nullptr means all ones) for its width (same widths as the views).

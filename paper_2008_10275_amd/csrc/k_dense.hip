@@ -41,9 +41,6 @@ template <> struct Mfma<double> {
 };
 
 constexpr int kKCAP = 192;          // max total columns of a concatenation
-constexpr int kKT = kKCAP / 16;     // 12 tiles per dimension
-constexpr int kTiles = kKT * (kKT + 1) / 2;   // 78 upper tiles
-constexpr int kGramRows = 32;       // rows staged per chunk
 
 // column -> (block, local column) tables of a view, built in LDS
 // (columns beyond kKCAP are dropped; the Gram reduction reports the overflow)
@@ -69,6 +66,21 @@ __device__ inline T view_at(const BlockView<T>& v, int b, int lc, int64_t row) {
 }
 
 // ============================================================== Gram
+// G = X^T X for up to two operands (the A and B sides of a truncation) in one
+// launch, k <= 128 columns.  Each wave streams rows straight from HBM in the
+// MFMA operand layout: for a 4-row slab, lane l holds row (l / 16) at columns
+// 16 t + (l % 16), so the A operand of tile (bi, bj) is the lane's value for
+// t = bi and the B operand its value for t = bj; all 36 upper tiles of the
+// 8 x 8 tile grid accumulate in registers (tiles beyond the device width are
+// skipped).  fp64 splits the tiles over two wave groups to halve the
+// accumulator registers.  The waves of a workgroup are summed through LDS in a
+// fixed order, one partial per workgroup is written, and a second kernel sums
+// the partials in a fixed order (results are bitwise reproducible).
+constexpr int kGK = 128;                       // columns of the Gram / TSMM kernels
+constexpr int kGT = kGK / 16;                  // 8 tiles per dimension
+constexpr int kGN = kGT * (kGT + 1) / 2;       // 36 upper tiles
+constexpr int kGramWgMax = 512;
+
 template <class T>
 struct GramArgs {
   BlockView<T> X[2];
@@ -77,121 +89,272 @@ struct GramArgs {
   int nwg1;
 };
 
-__device__ inline void tile_of(int t, int KT, int& bi, int& bj) {
-  // enumerate (bi <= bj) row by row
+template <class T>
+__device__ inline int view_width(const BlockView<T>& v) {
+  int k = 0;
+  for (int b = 0; b < v.nb; ++b) k += block_width(v, b);
+  return k;
+}
+
+// A concatenated column c of a view, ready for branch-free loads: columns
+// past the width point at a valid address (their values are never used);
+// for row-scaled views `sc` is a valid row-scale array of the view and `ss`
+// is 1 when the column's own block is scaled by it, 0 otherwise.
+template <class T>
+struct ColRef {
+  const T* p;
+  const double* sc;
+  int ld;
+  int ss;
+};
+
+template <class T>
+__device__ inline ColRef<T> resolve_col(const BlockView<T>& v, int c) {
+  ColRef<T> r{v.ptr[0], nullptr, 0, 0};
+  for (int b = 0; b < v.nb; ++b)
+    if (!r.sc && v.rowscale[b]) r.sc = v.rowscale[b];
+  int off = 0;
+  for (int b = 0; b < v.nb; ++b) {
+    const int w = block_width(v, b);
+    if (c >= off && c < off + w) {
+      r.p = v.ptr[b] + (c - off);
+      r.ld = v.ld[b];
+      if (v.rowscale[b]) { r.sc = v.rowscale[b]; r.ss = 1; }
+    }
+    off += w;
+  }
+  return r;
+}
+
+// Load row min(row, rmax) of a column (always a valid address; rows are
+// below 2^31 / ld, so offsets are 32-bit).  Callers mask rows they must not
+// count at the point of use, so that loads stay in flight.  SCALED requires a
+// row-scaled view (so that c.sc is a valid array).
+template <class T, bool SCALED>
+__device__ inline T col_load(const ColRef<T>& c, int64_t row, int64_t rmax) {
+  const int r = int(row < rmax ? row : rmax);
+  T x = c.p[r * c.ld];
+  if constexpr (SCALED) {
+    const double f = c.sc[r];
+    x *= c.ss ? T(f) : T(1);
+  }
+  return x;
+}
+
+template <class T>
+__host__ inline bool view_scaled(const BlockView<T>& v) {
+  for (int b = 0; b < v.nb; ++b)
+    if (v.rowscale[b]) return true;
+  return false;
+}
+
+// upper-tile enumeration of a KTM x KTM tile grid, row by row
+template <int KTM>
+struct TileTab {
+  static constexpr int N = KTM * (KTM + 1) / 2;
+  int bi[N], bj[N];
+  constexpr TileTab() : bi(), bj() {
+    int u = 0;
+    for (int i = 0; i < KTM; ++i)
+      for (int j = i; j < KTM; ++j) { bi[u] = i; bj[u] = j; ++u; }
+  }
+};
+__host__ __device__ constexpr int gtile_id(int bi, int bj) {
+  return bi * kGT - bi * (bi - 1) / 2 + (bj - bi);
+}
+__device__ inline void gtile_of(int id, int& bi, int& bj) {
   bi = 0;
-  int rem = t;
-  while (rem >= KT - bi) { rem -= KT - bi; ++bi; }
+  int rem = id;
+  while (rem >= kGT - bi) { rem -= kGT - bi; ++bi; }
   bj = bi + rem;
 }
 
-template <class T, class Tacc>
-__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a, Tacc* __restrict__ partial) {
+// Gram accumulation over the rows [r0, r1) of one operand for one wave of
+// tile group G: rows r0 + 8 (stream + NS i) + {0..7} per step, PD steps in
+// flight.  The loop is branch-free: all KTM column loads and all tiles of the
+// group are issued whatever the device width (tiles past it are computed on
+// valid data and never written), so that the scheduler keeps every load PD
+// steps ahead of its MFMAs.
+template <class T, int KTM, int NG, int G, int PD, bool SCALED>
+__device__ inline void gram_rows(const ColRef<T>* cr, int KT, int64_t r0, int64_t r1, int stream,
+                                 int sub, typename Mfma<T>::acc_t* acc) {
+  constexpr TileTab<KTM> tt{};
+  constexpr int NS = 4 / NG;
+  const int64_t step = 8 * NS;
+  // Columns past the width (inside the last 16-column tile) read valid but
+  // unrelated data: they only reach Gram entries of columns >= k, which are
+  // never used.  Rows past r1 belong to the next workgroup and are zeroed
+  // when consumed (masking at the load would make every load wait at once).
+  T xa[PD][KTM] = {}, xb[PD][KTM] = {};
+  const int64_t rl = r1 - 1;
+  int64_t q = r0 + 8 * stream;
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int64_t ra = q + d * step + sub, rb = ra + 4;
+#pragma unroll
+    for (int t = 0; t < KTM; ++t) {
+      if (t < KT) {
+        xa[d][t] = col_load<T, SCALED>(cr[t], ra, rl);
+        xb[d][t] = col_load<T, SCALED>(cr[t], rb, rl);
+      }
+    }
+  }
+  for (; q < r1; q += PD * step) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int64_t ra = q + d * step + sub, rb = ra + 4;
+      const bool oa = ra < r1, ob = rb < r1;
+      T ya[KTM], yb[KTM];
+#pragma unroll
+      for (int t = 0; t < KTM; ++t) {
+        ya[t] = oa ? xa[d][t] : T(0);
+        yb[t] = ob ? xb[d][t] : T(0);
+      }
+#pragma unroll
+      for (int u = G; u < tt.N; u += NG) {
+        if (tt.bj[u] < KT) {
+          acc[u / NG] = Mfma<T>::op(ya[tt.bi[u]], ya[tt.bj[u]], acc[u / NG]);
+          acc[u / NG] = Mfma<T>::op(yb[tt.bi[u]], yb[tt.bj[u]], acc[u / NG]);
+        }
+      }
+      const int64_t na = ra + PD * step, nb = na + 4;
+#pragma unroll
+      for (int t = 0; t < KTM; ++t) {
+        if (t < KT) {
+          xa[d][t] = col_load<T, SCALED>(cr[t], na, rl);
+          xb[d][t] = col_load<T, SCALED>(cr[t], nb, rl);
+        }
+      }
+    }
+  }
+}
+
+template <class T, int KTM, int NG, int PD, bool SCALED>
+__device__ inline void gram_rows_g(int g, const ColRef<T>* cr, int KT, int64_t r0, int64_t r1,
+                                   int stream, int sub, typename Mfma<T>::acc_t* acc) {
+  if (g == 0) gram_rows<T, KTM, NG, 0, PD, SCALED>(cr, KT, r0, r1, stream, sub, acc);
+  if constexpr (NG > 1)
+    if (g == 1) gram_rows<T, KTM, NG, 1, PD, SCALED>(cr, KT, r0, r1, stream, sub, acc);
+  if constexpr (NG > 2) {
+    if (g == 2) gram_rows<T, KTM, NG, 2, PD, SCALED>(cr, KT, r0, r1, stream, sub, acc);
+    if (g == 3) gram_rows<T, KTM, NG, 3, PD, SCALED>(cr, KT, r0, r1, stream, sub, acc);
+  }
+}
+
+template <class T, int KTM, int NG, int PD, bool SCALED1>
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a, T* __restrict__ partial) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T stage[kGramRows][kKCAP + 4];
-  __shared__ unsigned char blk[kKCAP];
-  __shared__ short loc[kKCAP];
+  constexpr TileTab<KTM> tt{};
+  constexpr int NTM = TileTab<KTM>::N;
+  constexpr int MAXT = (NTM + NG - 1) / NG;
+  constexpr int NS = 4 / NG;                 // row streams per workgroup
+  __shared__ T red[NTM * 256];
   const int job = blockIdx.x < a.nwg0 ? 0 : 1;
   const int wg = job == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
   const int nwg = job == 0 ? a.nwg0 : a.nwg1;
   const BlockView<T>& X = a.X[job];
   const int64_t rows = a.rows[job];
-  const int k = build_coltab(X, blk, loc);
+  const int k = min(view_width(X), 16 * KTM);
   const int KT = (k + 15) / 16;
-  const int T_ = KT * (KT + 1) / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int MAXT = (kTiles + 3) / 4;
+  const int g = wave % NG, stream = wave / NG;
+  ColRef<T> cr[KTM];
+#pragma unroll
+  for (int t = 0; t < KTM; ++t) cr[t] = resolve_col(X, 16 * t + (lane & 15));
   acc_t acc[MAXT];
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) acc[t] = acc_t{};
-  int tbi[MAXT], tbj[MAXT];
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    const int tt = wave + 4 * t;
-    if (tt < T_) tile_of(tt, KT, tbi[t], tbj[t]);
-    else { tbi[t] = -1; tbj[t] = -1; }
-  }
-  __syncthreads();
-  // contiguous row range of this workgroup, in chunks
-  const int64_t per = ceil_div(ceil_div(rows, kGramRows), nwg) * kGramRows;
+  const int64_t per = ceil_div(ceil_div(rows, int64_t(8)), int64_t(nwg)) * 8;
   const int64_t r0 = int64_t(wg) * per, r1 = std::min<int64_t>(rows, r0 + per);
-  const int kp = KT * 16;
-  for (int64_t c0 = r0; c0 < r1; c0 += kGramRows) {
-    const int nr = int(std::min<int64_t>(kGramRows, r1 - c0));
-    for (int e = threadIdx.x; e < kGramRows * kp; e += blockDim.x) {
-      const int rr = e / kp, c = e - rr * kp;
-      T v = T(0);
-      if (rr < nr && c < k) v = view_at(X, blk[c], loc[c], c0 + rr);
-      stage[rr][c] = v;
-    }
-    __syncthreads();
-    for (int kk = 0; kk < kGramRows; kk += 4) {
-      const int rr = kk + (lane >> 4), cc = lane & 15;
+  if (r0 < r1) {
+    // the row-scaled operand is the short V side: no deep prefetch there, so
+    // that it does not raise the register budget of the long side
+    if (SCALED1 && job == 1)
+      gram_rows_g<T, KTM, NG, 1, true>(g, cr, KT, r0, r1, stream, lane >> 4, acc);
+    else
+      gram_rows_g<T, KTM, NG, PD, false>(g, cr, KT, r0, r1, stream, lane >> 4, acc);
+  }
+  // sum the row streams in LDS (fixed order)
+  for (int s = 0; s < NS; ++s) {
+    if (stream == s) {
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        if (tbi[t] < 0) continue;
-        acc[t] = Mfma<T>::op(stage[rr][tbi[t] * 16 + cc], stage[rr][tbj[t] * 16 + cc], acc[t]);
+      for (int u = 0; u < NTM; ++u) {
+        if (u % NG == g && tt.bj[u] < KT) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            T* d = &red[u * 256 + Mfma<T>::drow(lane, i) * 16 + (lane & 15)];
+            *d = s == 0 ? acc[u / NG][i] : *d + acc[u / NG][i];
+          }
+        }
       }
     }
     __syncthreads();
   }
-  // write the compact upper tiles of this workgroup
-  Tacc* out = partial + (size_t(blockIdx.x) * kTiles) * 256;
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    const int tt = wave + 4 * t;
-    if (tt >= T_) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      out[size_t(tt) * 256 + Mfma<T>::drow(lane, i) * 16 + (lane & 15)] = Tacc(acc[t][i]);
+  // partial layout: tiles of the full 8 x 8 grid (ids of gtile_id)
+  T* out = partial + size_t(blockIdx.x) * kGN * 256;
+  for (int e = threadIdx.x; e < NTM * 256; e += blockDim.x) {
+    const int u = e >> 8;
+    if (tt.bj[u] < KT) out[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
   }
 }
 
-template <class T, class Tacc>
-__global__ void gram_reduce_kernel(GramArgs<T> a, const Tacc* __restrict__ partial, double* G0,
-                                   double* G1, int kcap, int* k0, int* k1, int* info) {
+// G[r][c] = sum over the job's workgroup partials (fixed order), both triangles
+// written; also publishes the width k = min(width, kcap) and flags widths
+// beyond the capacity (info bit 8).
+template <class T>
+__global__ __launch_bounds__(1024) void gram_reduce_kernel(GramArgs<T> a, const T* __restrict__ partial,
+                                                           double* G0, double* G1, int kcap,
+                                                           int* k0, int* k1, int* info) {
+  __shared__ double sh[16][64];
   const int job = blockIdx.y;
-  const BlockView<T>& X = a.X[job];
-  int ktot = 0;
-  for (int b = 0; b < X.nb; ++b) ktot += block_width(X, b);
-  const int kg = ktot < kKCAP ? ktot : kKCAP;     // columns the Gram kernel saw
-  const int k = kg < kcap ? kg : kcap;
+  const int ktot = view_width(a.X[job]);
+  const int kg = min(ktot, kGK);
+  const int k = min(kg, kcap);
   const int KT = (kg + 15) / 16;
-  const int T_ = KT * (KT + 1) / 2;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = e / 256, w = e & 255;
-  if (e == 0 && ktot > kcap && info) atomicOr(info, 8);
-  if (job == 0 && e == 0 && k0) *k0 = k;
-  if (job == 1 && e == 0 && k1) *k1 = k;
-  if (t >= T_) return;
-  int bi, bj;
-  tile_of(t, KT, bi, bj);
-  const int r = bi * 16 + w / 16, c = bj * 16 + (w & 15);
-  if (r >= k || c >= k || r > c) return;
+  const int tid = threadIdx.x, grp = tid >> 6, l = tid & 63;
+  const int e = blockIdx.x * 64 + l;
+  const int id = e >> 8, w = e & 255;
+  if (blockIdx.x == 0 && tid == 0) {
+    if (ktot > min(kcap, kGK) && info) atomicOr(info, 8);
+    if (job == 0 && k0) *k0 = k;
+    if (job == 1 && k1) *k1 = k;
+  }
+  int tbi = 0, tbj = 0;
+  if (id < kGN) gtile_of(id, tbi, tbj);
+  const bool valid = id < kGN && tbj < KT;
   const int w0 = job == 0 ? 0 : a.nwg0;
   const int nw = job == 0 ? a.nwg0 : a.nwg1;
   double s = 0.0;
-  for (int i = 0; i < nw; ++i) s += double(partial[(size_t(w0 + i) * kTiles + t) * 256 + w]);
+  if (valid)
+    for (int p = grp; p < nw; p += 16) s += double(partial[(size_t(w0 + p) * kGN + id) * 256 + w]);
+  sh[grp][l] = s;
+  __syncthreads();
+  if (grp != 0 || !valid) return;
+  double t = 0.0;
+#pragma unroll
+  for (int x = 0; x < 16; ++x) t += sh[x][l];
+  const int r = tbi * 16 + (w >> 4), c = tbj * 16 + (w & 15);
+  if (r >= k || c >= k || r > c) return;
   double* G = job == 0 ? G0 : G1;
-  G[size_t(r) * kcap + c] = s;
-  G[size_t(c) * kcap + r] = s;
+  G[size_t(r) * kcap + c] = t;
+  G[size_t(c) * kcap + r] = t;
 }
 
 static int gram_wgs(int64_t rows) {
   if (rows <= 0) return 1;
-  return int(std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(rows, 256))));
+  return int(std::min<int64_t>(kGramWgMax, std::max<int64_t>(1, ceil_div(rows, int64_t(512)))));
 }
 
 size_t gram_workspace_bytes(int64_t rows_a, int64_t rows_b, int kcap, bool fp64) {
   (void)kcap;
-  return size_t(gram_wgs(rows_a) + gram_wgs(rows_b)) * kTiles * 256 * (fp64 ? 8 : 4);
+  return size_t(gram_wgs(rows_a) + gram_wgs(rows_b)) * kGN * 256 * (fp64 ? 8 : 4);
 }
 
 template <class T>
 void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial, size_t ws_bytes,
                  int* info, hipStream_t s) {
   LRC_CHECK(njobs >= 1 && njobs <= 2, ST_EINVAL, "gram: one or two jobs");
-  LRC_CHECK(kcap <= kKCAP, ST_EINVAL, "gram: at most 192 columns");
+  LRC_CHECK(kcap <= kGK, ST_EINVAL, "gram: at most 128 columns");
   GramArgs<T> a;
   a.X[0] = jobs[0].X;
   a.rows[0] = jobs[0].rows;
@@ -205,8 +368,7 @@ void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial
     a.rows[1] = 0;
     a.nwg1 = 0;
   }
-  // fp32 products accumulate in fp32 inside a workgroup; fp64 in fp64
-  const size_t need = size_t(a.nwg0 + a.nwg1) * kTiles * 256 * sizeof(T);
+  const size_t need = size_t(a.nwg0 + a.nwg1) * kGN * 256 * sizeof(T);
   LRC_CHECK(need <= ws_bytes, ST_EINVAL, "gram: workspace too small");
   {
     // algorithmic flops: the k(k+1)/2 distinct entries of each Gram matrix,
@@ -219,13 +381,30 @@ void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial
       return r0 * v[0] * (v[0] + 1.0) + r1 * v[1] * (v[1] + 1.0);
     };
     ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, w);
-    hipLaunchKernelGGL((gram_kernel<T, T>), dim3(a.nwg0 + a.nwg1), dim3(256), 0, s, a,
-                       reinterpret_cast<T*>(ws_partial));
+    // tile grid sized by the host-known width bound of the operands
+    const int kb = std::min(kGK, std::max(view_cap(jobs[0].X),
+                                          njobs > 1 ? view_cap(jobs[1].X) : 0));
+    const dim3 grid(a.nwg0 + a.nwg1), blk(256);
+    T* part = reinterpret_cast<T*>(ws_partial);
+    // (tile grid, wave groups sharing the tiles, prefetch depth) per width
+    // class, chosen so that accumulators + operand ring fit the registers
+    constexpr bool F64 = sizeof(T) == 8;
+    const bool sc1 = njobs > 1 && view_scaled(jobs[1].X);
+    LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "gram: the first operand cannot be row-scaled");
+#define LRC_GRAM(KTM, NG, PD)                                                                \
+  do {                                                                                      \
+    if (sc1) hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, true>), grid, blk, 0, s, a, part); \
+    else hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, false>), grid, blk, 0, s, a, part);    \
+  } while (0)
+    if (kb <= 32) LRC_GRAM(2, 1, 4);
+    else if (kb <= 64) LRC_GRAM(4, 1, F64 ? 2 : 4);
+    else if (kb <= 96) LRC_GRAM(6, 2, F64 ? 2 : 4);
+    else LRC_GRAM(8, F64 ? 4 : 2, 2);
+#undef LRC_GRAM
   }
   ProfScope ps(kcls(K_GRAM_REDUCE, is_f32<T>()), s);
-  const int elems = kTiles * 256;
-  hipLaunchKernelGGL((gram_reduce_kernel<T, T>), dim3(ceil_div(elems, 256), njobs), dim3(256), 0,
-                     s, a, reinterpret_cast<const T*>(ws_partial), jobs[0].G,
+  hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3(kGN * 256 / 64, njobs), dim3(1024), 0, s, a,
+                     reinterpret_cast<const T*>(ws_partial), jobs[0].G,
                      njobs == 2 ? jobs[1].G : jobs[0].G, kcap, jobs[0].kout,
                      njobs == 2 ? jobs[1].kout : nullptr, info);
   LRC_HIP(hipGetLastError());
@@ -236,12 +415,14 @@ template void launch_gram<double>(const GramJob<double>*, int, int, double*, siz
                                   hipStream_t);
 
 // ============================================================== TSMM  Y = X * M
-// Output columns are processed in slices of 64 (grid.y); one workgroup stages
-// the k x 64 slice of M and 64-row blocks of X (in k-chunks of 32) in LDS.
+// Output columns in slices of 64 (grid.y).  A workgroup keeps its k x 64 slice
+// of M in LDS and walks 64-row blocks of X: each block is loaded coalesced
+// (64 consecutive columns of one row per wave instruction, the next block
+// prefetched into registers while the current one is multiplied) and staged
+// in LDS, from where the waves read the MFMA operands (wave w: rows 16 w ..).
 constexpr int kTsRows = 64;
-constexpr int kTsK = 32;
 constexpr int kTsSlice = 64;
-constexpr int kTsKCAP = 128;
+constexpr int kTsKCAP = kGK;
 
 template <class T>
 struct TsmmArgs {
@@ -249,53 +430,77 @@ struct TsmmArgs {
   int nwg0, nwg1;
 };
 
-template <class T>
+// Rows past the end are clamped (their products are never stored); columns
+// past the width meet zero rows of M.
+template <class T, bool SCALED>
+__device__ inline void tsmm_load(T (&v0)[kTsRows / 4], T (&v1)[kTsRows / 4], const ColRef<T>& c0,
+                                 const ColRef<T>& c1, bool two, int64_t b0, int lr,
+                                 int64_t rows) {
+#pragma unroll
+  for (int j = 0; j < kTsRows / 4; ++j) {
+    const int64_t row = b0 + lr + 4 * j;
+    v0[j] = col_load<T, SCALED>(c0, row, rows - 1);
+    if (two) v1[j] = col_load<T, SCALED>(c1, row, rows - 1);
+  }
+}
+
+template <class T, bool SCALED1>
 __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T Ms[kTsKCAP][kTsSlice + 4];
-  __shared__ T Xs[kTsRows][kTsK + 1];
-  __shared__ unsigned char blk[kKCAP];
-  __shared__ short loc[kKCAP];
+  __shared__ T Xs[kTsRows][kTsKCAP + 1];
   const int jb = blockIdx.x < a.nwg0 ? 0 : 1;
   const int wg = jb == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
   const int nwg = jb == 0 ? a.nwg0 : a.nwg1;
   const TsmmJob<T>& J = a.job[jb];
-  const int k = build_coltab(J.X, blk, loc);
+  const int k = min(view_width(J.X), kTsKCAP);
   const int r = *J.r_dev;
-  const int cs = blockIdx.y * kTsSlice;          // first output column of the slice
-  if (cs >= r || k > kTsKCAP) return;
-  const int rs = min(kTsSlice, r - cs);
+  const int cs0 = blockIdx.y * kTsSlice;
+  if (cs0 >= r) return;
+  const int rs = min(kTsSlice, r - cs0);
   const int kp = (k + 3) / 4 * 4;
   const int RT = (rs + 15) / 16;
-  for (int e = threadIdx.x; e < kp * kTsSlice; e += blockDim.x) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kp * kTsSlice; e += blockDim.x) {
     const int i = e / kTsSlice, c = e - i * kTsSlice;
-    Ms[i][c] = (i < k && c < rs) ? T(J.M[size_t(i) * J.ldm + cs + c]) : T(0);
+    Ms[i][c] = (i < k && c < rs) ? T(J.M[size_t(i) * J.ldm + cs0 + c]) : T(0);
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t row0 = int64_t(wg) * kTsRows; row0 < J.rows; row0 += int64_t(nwg) * kTsRows) {
+  // loader: thread -> columns lc, lc + 64 of rows (tid / 64) + 4 j
+  const int lc = tid & 63, lr = tid >> 6;
+  const ColRef<T> c0 = resolve_col(J.X, lc), c1 = resolve_col(J.X, lc + 64);
+  const bool two = kp > 64;
+  const bool scaled = SCALED1 && jb == 1;
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int LJ = kTsRows / 4;
+  T v0[LJ], v1[LJ];
+#pragma unroll
+  for (int j = 0; j < LJ; ++j) v1[j] = T(0);
+  int64_t row0 = int64_t(wg) * kTsRows;
+  auto load_block = [&](int64_t b0) {
+    if (scaled) tsmm_load<T, true>(v0, v1, c0, c1, two, b0, lr, J.rows);
+    else tsmm_load<T, false>(v0, v1, c0, c1, two, b0, lr, J.rows);
+  };
+  if (row0 < J.rows) load_block(row0);
+  for (; row0 < J.rows; row0 += int64_t(nwg) * kTsRows) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < LJ; ++j) {
+      Xs[lr + 4 * j][lc] = v0[j];
+      if (two) Xs[lr + 4 * j][lc + 64] = v1[j];
+    }
+    __syncthreads();
+    const int64_t next = row0 + int64_t(nwg) * kTsRows;
+    if (next < J.rows) load_block(next);
     acc_t acc[kTsSlice / 16];
 #pragma unroll
     for (int t = 0; t < kTsSlice / 16; ++t) acc[t] = acc_t{};
-    const int nr = int(std::min<int64_t>(kTsRows, J.rows - row0));
-    for (int k0 = 0; k0 < kp; k0 += kTsK) {
-      const int kc = std::min(kTsK, kp - k0);
-      for (int e = threadIdx.x; e < kTsRows * kTsK; e += blockDim.x) {
-        const int rr = e / kTsK, c = e - rr * kTsK;
-        T v = T(0);
-        if (rr < nr && c < kc && k0 + c < k) v = view_at(J.X, blk[k0 + c], loc[k0 + c], row0 + rr);
-        Xs[rr][c] = v;
-      }
-      __syncthreads();
-      for (int kk = 0; kk < kc; kk += 4) {
-        const T xa = Xs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
+    for (int kk = 0; kk < kp; kk += 4) {
+      const T xa = Xs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-        for (int t = 0; t < kTsSlice / 16; ++t) {
-          if (t < RT) acc[t] = Mfma<T>::op(xa, Ms[k0 + kk + (lane >> 4)][t * 16 + (lane & 15)], acc[t]);
-        }
-      }
-      __syncthreads();
+      for (int t = 0; t < kTsSlice / 16; ++t)
+        if (t < RT) acc[t] = Mfma<T>::op(xa, Ms[kk + (lane >> 4)][t * 16 + (lane & 15)], acc[t]);
     }
+    const int nr = int(std::min<int64_t>(kTsRows, J.rows - row0));
 #pragma unroll
     for (int t = 0; t < kTsSlice / 16; ++t) {
       if (t >= RT) continue;
@@ -304,7 +509,7 @@ __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = wave * 16 + Mfma<T>::drow(lane, i);
-        if (rr < nr) J.Y[(row0 + rr) * J.ldy + cs + c] = acc[t][i];
+        if (rr < nr) J.Y[(row0 + rr) * J.ldy + cs0 + c] = acc[t][i];
       }
     }
   }
@@ -315,26 +520,33 @@ void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStrea
   LRC_CHECK(njobs >= 1 && njobs <= 2, ST_EINVAL, "tsmm: one or two jobs");
   LRC_CHECK(kcap <= kTsKCAP && rcap <= kTsKCAP, ST_EINVAL, "tsmm: capacity exceeded");
   TsmmArgs<T> a;
+  const int cap_wg = sizeof(T) == 8 ? 256 : 512;
   a.job[0] = jobs[0];
-  a.nwg0 = int(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(jobs[0].rows, kTsRows))));
+  a.nwg0 = int(std::min<int64_t>(cap_wg, std::max<int64_t>(1, ceil_div(jobs[0].rows, kTsRows))));
   if (njobs == 2) {
     a.job[1] = jobs[1];
-    a.nwg1 = int(std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(jobs[1].rows, kTsRows))));
+    a.nwg1 = int(std::min<int64_t>(cap_wg, std::max<int64_t>(1, ceil_div(jobs[1].rows, kTsRows))));
   } else {
     a.job[1] = jobs[0];
     a.nwg1 = 0;
   }
   const int slices = int(ceil_div(rcap, kTsSlice));
-  // algorithmic flops: 2 rows k r per job
+  // algorithmic bytes: X read once per output slice is not counted; X once
+  // plus Y once per job
   Work w;
-  w.bytes = false;
-  const double r0 = double(a.nwg0 > 0 ? jobs[0].rows : 0), r1 = double(a.nwg1 > 0 ? jobs[1].rows : 0);
+  const double r0 = double(jobs[0].rows), r1 = double(njobs > 1 ? jobs[1].rows : 0);
   w.groups = {view_terms(jobs[0].X), {{jobs[0].r_dev, 0}},
               view_terms(njobs > 1 ? jobs[1].X : jobs[0].X),
               {{njobs > 1 ? jobs[1].r_dev : jobs[0].r_dev, 0}}};
-  w.f = [=](const std::vector<double>& v) { return 2.0 * (r0 * v[0] * v[1] + r1 * v[2] * v[3]); };
+  w.f = [=](const std::vector<double>& v) {
+    return double(sizeof(T)) * (r0 * (v[0] + v[1]) + r1 * (v[2] + v[3]));
+  };
   ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, w);
-  hipLaunchKernelGGL((tsmm_kernel<T>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
+  LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "tsmm: the first operand cannot be row-scaled");
+  if (njobs > 1 && view_scaled(jobs[1].X))
+    hipLaunchKernelGGL((tsmm_kernel<T, true>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((tsmm_kernel<T, false>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
   LRC_HIP(hipGetLastError());
 }
 template void launch_tsmm<float>(const TsmmJob<float>*, int, int, int, hipStream_t);

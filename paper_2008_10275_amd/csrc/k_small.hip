@@ -13,22 +13,30 @@ namespace lrc {
 constexpr int SK = 128;                         // capacity of the small kernels
 constexpr int SKP = SK * (SK + 1) / 2;          // packed upper triangle
 
-__device__ inline int pk(int i, int j, int k) {  // packed upper by rows, i <= j
+
+// ============================================================== Cholesky + inverse
+// One workgroup per side (A, B).  G is equilibrated (unit diagonal) and
+// factorised G_s = R^T R right-looking; the rows are scaled only at the end
+// (the trailing update divides by the pivot instead), so that each step needs
+// a single barrier: step j reads row j and writes rows > j.  A pivot at or
+// below tau = eps k restarts the factorisation of G_s + shift I (shift 10 tau,
+// then 100 times larger): the shift bounds ||R^-1|| by shift^-1/2, which keeps
+// X R^-1 well conditioned for the second pass.  Columns whose Gram diagonal
+// vanishes are treated as absent.  R^-1 by 16 x 16 blocks.  Outputs (ld = kcap):
+//   Rout = R D^{-1}   (so that X = Q Rout),  Tout = D R^{-1}  (so that Q = X Tout).
+__device__ inline int pu(int i, int j, int k) {   // packed upper by rows, i <= j
   return i * k - (i * (i - 1)) / 2 + (j - i);
 }
 
-// ============================================================== Cholesky + inverse
-// One workgroup per side (A, B).  G is equilibrated (unit diagonal), factorised
-// G_s = R^T R; a failed pivot restarts with a diagonal shift; columns whose
-// Gram diagonal vanishes are treated as absent.  Outputs (ld = kcap):
-//   Rout = R D^{-1}   (so that X = Q Rout),  Tout = D R^{-1}  (so that Q = X Tout).
-__global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int kcap,
-                                                   double eps) {
+constexpr int kCholThreads = 512;
+__global__ __launch_bounds__(kCholThreads) void chol_kernel(TruncState st, int pass, int kcap,
+                                                            double eps) {
   __shared__ double Rp[SKP];
   __shared__ double Xp[SKP];
   __shared__ double Wt[(SK / 16) * 256];
   __shared__ double dsc[SK];
-  __shared__ int fail;
+  __shared__ double pivv[SK];
+  __shared__ double s_gm;
   const int side = blockIdx.x;
   const int k = *st.k;
   const double* G = st.G[side];
@@ -36,111 +44,126 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
   double* Tout = pass == 1 ? st.T1[side] : st.R2i[side];
   const int tid = threadIdx.x, nt = blockDim.x;
   if (k == 0) return;
-  // equilibration
-  __shared__ double gmax;
-  if (tid == 0) {
-    double m = 0.0;
-    for (int j = 0; j < k; ++j) m = fmax(m, G[size_t(j) * kcap + j]);
-    gmax = m;
+  if (tid < 64) {
+    double gm = 0.0;
+    for (int j = tid; j < k; j += 64) gm = fmax(gm, G[size_t(j) * kcap + j]);
+    for (int o = 32; o > 0; o >>= 1) gm = fmax(gm, __shfl_xor(gm, o));
+    if (tid == 0) s_gm = gm;
   }
   __syncthreads();
   for (int j = tid; j < k; j += nt) {
     const double g = G[size_t(j) * kcap + j];
-    dsc[j] = (g > 1e-300 && g > 1e-28 * gmax) ? 1.0 / sqrt(g) : 0.0;
+    dsc[j] = (g > 1e-300 && g > 1e-28 * s_gm) ? 1.0 / sqrt(g) : 0.0;
   }
   __syncthreads();
-  double shift = 0.0;
   const double tau = eps * k;
-  for (int attempt = 0; attempt < 6; ++attempt) {
+  double shift = 0.0;
+  bool fail = true;
+  // trailing-update mapping: column slot tid % 128, row phase tid / 128
+  const int tc = tid & 127, tr = tid >> 7, nr = nt >> 7;
+  for (int attempt = 0; attempt < 6 && fail; ++attempt) {
     for (int e = tid; e < k * k; e += nt) {
       const int i = e / k, j = e - i * k;
       if (j < i) continue;
-      double v;
-      if (dsc[i] == 0.0 || dsc[j] == 0.0) v = (i == j) ? 1.0 : 0.0;
-      else v = dsc[i] * G[size_t(i) * kcap + j] * dsc[j] + (i == j ? shift : 0.0);
-      Rp[pk(i, j, k)] = v;
+      const double di = dsc[i], dj = dsc[j];
+      Rp[pu(i, j, k)] = (di == 0.0 || dj == 0.0)
+                            ? (i == j ? 1.0 : 0.0)
+                            : di * G[size_t(i) * kcap + j] * dj + (i == j ? shift : 0.0);
     }
-    if (tid == 0) fail = 0;
     __syncthreads();
+    fail = false;
     for (int j = 0; j < k; ++j) {
-      if (tid == 0) {
-        const double p = Rp[pk(j, j, k)];
-        if (!(p > tau)) fail = 1;
-        else Rp[pk(j, j, k)] = sqrt(p);
-      }
-      __syncthreads();
-      if (fail) break;
-      const double rjj = Rp[pk(j, j, k)];
-      for (int c = j + 1 + tid; c < k; c += nt) Rp[pk(j, c, k)] /= rjj;
-      __syncthreads();
-      // trailing update, 16 x 16 thread grid over (row a, column b >= a)
-      {
-        const int ty = tid >> 4, tx = tid & 15;
-        for (int a = j + 1 + ty; a < k; a += 16) {
-          const double rja = Rp[pk(j, a, k)];
-          const int base = pk(a, 0, k);            // row a starts at base + a
-          for (int b = a + tx; b < k; b += 16) Rp[base + b] -= rja * Rp[pk(j, b, k)];
+      const double p = Rp[pu(j, j, k)];
+      if (!(p > tau)) { fail = true; break; }       // same value in every thread
+      const double ip = 1.0 / p;
+      const int c = j + 1 + tc;
+      if (c < k) {
+        const double ajc = Rp[pu(j, c, k)] * ip;
+        // rows a = j + 1 + tr + nr * u, four at a time (loads before stores)
+        for (int a = j + 1 + tr; a <= c; a += 4 * nr) {
+          double x[4], y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int au = a + u * nr;
+            x[u] = au <= c ? Rp[pu(j, au, k)] : 0.0;
+            y[u] = au <= c ? Rp[pu(au, c, k)] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int au = a + u * nr;
+            if (au <= c) Rp[pu(au, c, k)] = y[u] - x[u] * ajc;
+          }
         }
       }
+      if (tid == 0) pivv[j] = p;
       __syncthreads();
     }
-    if (!fail) break;
-    shift = (shift == 0.0) ? 10.0 * tau : shift * 100.0;
-    if (tid == 0) atomicOr(st.info, 1);
-    __syncthreads();
+    if (fail) {
+      shift = shift == 0.0 ? 10.0 * tau : 100.0 * shift;
+      if (tid == 0) atomicOr(st.info, 1);
+      __syncthreads();
+    }
   }
   if (fail) {
     // give up on factorising: identity factor (the truncation then works on the
     // equilibrated columns as they are) and report the breakdown
     for (int e = tid; e < k * k; e += nt) {
       const int i = e / k, j = e - i * k;
-      if (j >= i) Rp[pk(i, j, k)] = (i == j) ? 1.0 : 0.0;
+      if (j >= i) Rp[pu(i, j, k)] = (i == j) ? 1.0 : 0.0;
     }
     if (tid == 0) atomicOr(st.info, 2);
-    __syncthreads();
+  } else {
+    // R[i][j] = A[i][j] / sqrt(p_i), R[i][i] = sqrt(p_i)
+    for (int e = tid; e < k * k; e += nt) {
+      const int i = e / k, j = e - i * k;
+      if (j < i) continue;
+      const double sp = sqrt(pivv[i]);
+      Rp[pu(i, j, k)] = (i == j) ? sp : Rp[pu(i, j, k)] / sp;
+    }
   }
+  __syncthreads();
   // Rout = R D^{-1}
   for (int e = tid; e < kcap * kcap; e += nt) {
     const int i = e / kcap, j = e - i * kcap;
     double v = 0.0;
-    if (i < k && j < k && j >= i && dsc[j] != 0.0) v = Rp[pk(i, j, k)] / dsc[j];
+    if (i < k && j < k && j >= i && dsc[j] != 0.0) v = Rp[pu(i, j, k)] / dsc[j];
     Rout[e] = v;
   }
-  // blocked inverse of the upper-triangular R (16 x 16 blocks)
+  // blocked inverse of the upper-triangular R (16 x 16 blocks): diagonal
+  // blocks by back substitution (one column per thread), then the block
+  // diagonals d = 1, 2, ... from X_IJ = -X_II sum_{r in I+1..J} R_Ir X_rJ
   const int nbk = (k + 15) / 16;
   for (int t = tid; t < nbk * 16; t += nt) {
-    const int I = t / 16, J = t;                 // column J inside diagonal block I
+    const int I = t / 16, J = t;
     if (J >= k) continue;
     const int lo = I * 16;
     for (int i = J; i >= lo; --i) {
-      double s = (i == J) ? 1.0 : 0.0;
-      for (int p = i + 1; p <= J; ++p) s -= Rp[pk(i, p, k)] * Xp[pk(p, J, k)];
-      Xp[pk(i, J, k)] = s / Rp[pk(i, i, k)];
+      double sacc = (i == J) ? 1.0 : 0.0;
+      for (int q = i + 1; q <= J; ++q) sacc -= Rp[pu(i, q, k)] * Xp[pu(q, J, k)];
+      Xp[pu(i, J, k)] = sacc / Rp[pu(i, i, k)];
     }
   }
   __syncthreads();
   for (int d = 1; d < nbk; ++d) {
     const int npairs = nbk - d;
-    // W_IJ = sum_{r in blocks I+1..J} R[I][r] X[r][J]
     for (int e = tid; e < npairs * 256; e += nt) {
       const int I = e / 256, w = e & 255, J = I + d;
       const int i = I * 16 + w / 16, j = J * 16 + (w & 15);
-      double s = 0.0;
+      double sacc = 0.0;
       if (i < k && j < k)
-        for (int r = (I + 1) * 16; r <= j; ++r) s += Rp[pk(i, r, k)] * Xp[pk(r, j, k)];
-      Wt[e] = s;
+        for (int r = (I + 1) * 16; r <= j; ++r) sacc += Rp[pu(i, r, k)] * Xp[pu(r, j, k)];
+      Wt[e] = sacc;
     }
     __syncthreads();
-    // X_IJ = -X_II W_IJ
     for (int e = tid; e < npairs * 256; e += nt) {
       const int I = e / 256, w = e & 255, J = I + d;
       const int ii = w / 16, jj = w & 15;
       const int i = I * 16 + ii, j = J * 16 + jj;
       if (i >= k || j >= k) continue;
-      double s = 0.0;
+      double sacc = 0.0;
       for (int q = ii; q < 16 && I * 16 + q < k; ++q)
-        s -= Xp[pk(i, I * 16 + q, k)] * Wt[I * 256 + q * 16 + jj];
-      Xp[pk(i, j, k)] = s;
+        sacc -= Xp[pu(i, I * 16 + q, k)] * Wt[I * 256 + q * 16 + jj];
+      Xp[pu(i, j, k)] = sacc;
     }
     __syncthreads();
   }
@@ -148,7 +171,7 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
   for (int e = tid; e < kcap * kcap; e += nt) {
     const int i = e / kcap, j = e - i * kcap;
     double v = 0.0;
-    if (i < k && j < k && j >= i) v = dsc[i] * Xp[pk(i, j, k)];
+    if (i < k && j < k && j >= i) v = dsc[i] * Xp[pu(i, j, k)];
     Tout[e] = v;
   }
 }
@@ -156,7 +179,7 @@ __global__ __launch_bounds__(256) void chol_kernel(TruncState st, int pass, int 
 void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s) {
   LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
   ProfScope ps(kcls(K_CHOL, false), s);
-  hipLaunchKernelGGL(chol_kernel, dim3(2), dim3(256), 0, s, st, pass, kcap, eps_gram);
+  hipLaunchKernelGGL(chol_kernel, dim3(2), dim3(kCholThreads), 0, s, st, pass, kcap, eps_gram);
   LRC_HIP(hipGetLastError());
 }
 
@@ -172,6 +195,8 @@ struct SmallGemm {
   const int* ncols_dev;      // optional: output columns (default k)
   int transA, transB;
   int use_core;              // mid = core coefficients
+  const int* rowperm;        // optional: output row i goes to row rowperm[i]
+  const int* inner_dev;      // optional: contraction length (default k)
 };
 
 struct SmallGemmArgs {
@@ -188,6 +213,7 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a) {
   const SmallGemm& g = a.g[blockIdx.z];
   const int k = *a.k;
   const int ncols = g.ncols_dev ? *g.ncols_dev : k;
+  const int kin = g.inner_dev ? *g.inner_dev : k;
   const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
   if (ti >= k || tj >= ncols) return;
   if (g.use_core) {
@@ -203,17 +229,17 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a) {
   const int i = ti + li, j = tj + lj;
   const int jc = (j < ncols) ? (g.colperm ? g.colperm[j] : j) : 0;
   double acc = 0.0;
-  for (int p0 = 0; p0 < k; p0 += 16) {
+  for (int p0 = 0; p0 < kin; p0 += 16) {
     __syncthreads();
     {
       const int p = p0 + lj;
       double v = 0.0;
-      if (i < k && p < k) v = g.transA ? g.A[size_t(p) * a.kcap + i] : g.A[size_t(i) * a.kcap + p];
+      if (i < k && p < kin) v = g.transA ? g.A[size_t(p) * a.kcap + i] : g.A[size_t(i) * a.kcap + p];
       As[li][lj] = v;
       const int pb = p0 + li;
       double w = 0.0;
-      if (pb < k && j < ncols) w = g.transB ? g.B[size_t(jc) * a.kcap + pb] : g.B[size_t(pb) * a.kcap + jc];
-      if (g.use_core && pb < k) w *= mid[pb];
+      if (pb < kin && j < ncols) w = g.transB ? g.B[size_t(jc) * a.kcap + pb] : g.B[size_t(pb) * a.kcap + jc];
+      if (g.use_core && pb < kin) w *= mid[pb];
       Bs[li][lj] = w;
     }
     __syncthreads();
@@ -222,7 +248,8 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a) {
   }
   if (i < k && j < ncols) {
     if (g.colscale) acc *= g.colscale[j];
-    g.C[size_t(i) * a.kcap + j] = acc;
+    const int io = g.rowperm ? g.rowperm[i] : i;
+    g.C[size_t(io) * a.kcap + j] = acc;
   }
 }
 
@@ -248,100 +275,134 @@ __device__ inline int rr_player(int pos, int t, int kp) {
 }
 
 // Two-sided Jacobi on the symmetric H (k x k, padded to even kp with a zero
-// row/column), stored in full in LDS (both triangles kept equal).  Every round
-// applies kp/2 disjoint rotations H <- J^T H J; the (c, s) of each round are
-// logged so that V = prod J can be rebuilt per row.
-constexpr int kJL = SK + 1;   // LDS row pitch of H (odd: fewer bank conflicts)
-__global__ __launch_bounds__(1024) void jacobi_kernel(TruncState st, int kcap, int max_rounds) {
-  __shared__ double Hs[SK * kJL];
-  __shared__ double cs_c[SK / 2], cs_s[SK / 2];
-  __shared__ unsigned char pp[SK / 2], qq[SK / 2];                 // pair a = (pp[a], qq[a])
-  __shared__ int nrot, rrot;
-  const int k = *st.k;
+// row/column), stored in full in LDS.  Every round applies kp/2 disjoint
+// rotations H <- J^T H J.  Each wave computes all of a round's rotations
+// itself (into its own LDS slots); a barrier separates those reads of H from
+// the update, and another ends the round.  Rounds without a rotation (the
+// same decision in every wave) skip both.  Up to
+// kJFuse the eigenvectors V = prod J accumulate in LDS next to H and are
+// written to st.VM (st.rounds = -1 marks this); beyond, the (c, s) of every
+// round are logged and V is rebuilt per row by the replay kernel.
+constexpr int kJL = SK + 1;
+constexpr int kJFuse = 88;
+constexpr int kJacThreads = 1024;
+__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(TruncState st, int kcap, int max_rounds) {
+  __shared__ double Ls[SK * kJL];
+  __shared__ double2 csw[kJacThreads / 64][SK / 2];
+  __shared__ short2 pqw[kJacThreads / 64][SK / 2];
+  __shared__ double s_floor;
+  const int k = *st.kj;
   const int kp = k + (k & 1);
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int P = kp + 1;
+  const bool fuse = k <= kJFuse;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   if (k <= 1) {
-    if (tid == 0) *st.rounds = 0;
+    if (tid == 0) {
+      if (k == 1) {
+        st.VM[0] = 1.0;
+        st.lam[0] = st.H[0];
+      }
+      *st.rounds = -1;
+    }
     return;
   }
+  double* H = Ls;
+  double* V = Ls + size_t(kp) * P;
   for (int e = tid; e < kp * kp; e += nt) {
     const int i = e / kp, j = e - i * kp;
-    Hs[i * kJL + j] = (i < k && j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
+    H[i * P + j] = (i < k && j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
+    if (fuse) V[i * P + j] = (i == j) ? 1.0 : 0.0;
   }
-  const int npair = kp / 2;
   __syncthreads();
   // Off-diagonal entries below 1e-16 * trace(H) are rounding noise of the
   // squared core and are not rotated; the eigenvalues are then accurate to
   // that absolute level (singular values to ~1e-8 of the largest).
-  __shared__ double hscale;
-  if (tid == 0) {
+  if (tid < 64) {
     double tr = 0.0;
-    for (int i = 0; i < k; ++i) tr += fabs(Hs[i * kJL + i]);
-    hscale = 1e-16 * tr;
+    for (int i = tid; i < k; i += 64) tr += fabs(H[i * P + i]);
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+    if (tid == 0) s_floor = 1e-16 * tr;
   }
   __syncthreads();
-  const double floor_abs = hscale;
-  // thread layout of the update phase: 16 threads per pair a (one per column
-  // group), each sweeping the columns j of rows pp[a], qq[a]
+  const double floor_abs = s_floor;
+  const int npair = kp / 2;
   int round = 0;
+  bool converged = false;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
-    if (tid == 0) nrot = 0;
-    __syncthreads();
+    int nrot = 0;
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
-      if (tid == 0) rrot = 0;
-      __syncthreads();
-      if (tid < npair) {
-        // pair slot tid of round t: positions tid and kp-1-tid of the rotated list
-        const int x0 = tid == 0 ? 0 : 1 + (tid - 1 + t) % (kp - 1);
-        const int x1 = 1 + (kp - 2 - tid + t) % (kp - 1);
+      bool rot = false;
+      if (lane < npair) {
+        // pair slot `lane` of round t: positions lane and kp-1-lane of the
+        // rotated list [0, 1 + (t + i) mod (kp - 1)]
+        const int x0 = lane == 0 ? 0 : 1 + (lane - 1 + t) % (kp - 1);
+        const int x1 = 1 + (kp - 2 - lane + t) % (kp - 1);
         const int p = min(x0, x1), q = max(x0, x1);
-        pp[tid] = (unsigned char)p;
-        qq[tid] = (unsigned char)q;
-        const double hpp = Hs[p * kJL + p], hqq = Hs[q * kJL + q], hpq = Hs[p * kJL + q];
-        double c = 1.0, s = 0.0;
+        const double hpp = H[p * P + p], hqq = H[q * P + q], hpq = H[p * P + q];
+        double c = 1.0, sn = 0.0;
         if (fabs(hpq) > floor_abs) {
           const double zeta = (hqq - hpp) / (2.0 * hpq);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
-          s = c * tt;
-          atomicAdd(&rrot, 1);
+          sn = c * tt;
+          rot = true;
         }
-        cs_c[tid] = c;
-        cs_s[tid] = s;
-        st.rot[(size_t(round) * (SK / 2) + tid) * 2 + 0] = c;
-        st.rot[(size_t(round) * (SK / 2) + tid) * 2 + 1] = s;
+        csw[wave][lane] = make_double2(c, sn);
+        pqw[wave][lane] = make_short2(short(p), short(q));
+        if (!fuse && wave == 0) {
+          st.rot[(size_t(round) * (SK / 2) + lane) * 2 + 0] = c;
+          st.rot[(size_t(round) * (SK / 2) + lane) * 2 + 1] = sn;
+        }
       }
-      __syncthreads();
-      if (rrot == 0) continue;          // nothing rotated in this round
-      if (tid == 0) nrot += rrot;
-      // H <- J^T H (rows), then H <- H J (columns), done as one pass over the
-      // 2 x 2 blocks (pair a, pair b): each block is owned by one thread.
+      const int rr = __popcll(__ballot(rot));
+      if (rr == 0) continue;          // H unchanged: no update, no barrier
+      nrot += rr;
+      __syncthreads();                // every wave has read the pivots of this round
+      // H <- J^T H J as one pass over the 2 x 2 blocks (pair a, pair b)
       for (int e = tid; e < npair * npair; e += nt) {
         const int a = e / npair, b = e - a * npair;
-        const double ca = cs_c[a], sa = cs_s[a], cb = cs_c[b], sb = cs_s[b];
-        if (sa == 0.0 && sb == 0.0) continue;
-        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-        const double h00 = Hs[pa * kJL + pb], h01 = Hs[pa * kJL + qb];
-        const double h10 = Hs[qa * kJL + pb], h11 = Hs[qa * kJL + qb];
-        const double l00 = ca * h00 - sa * h10, l01 = ca * h01 - sa * h11;
-        const double l10 = sa * h00 + ca * h10, l11 = sa * h01 + ca * h11;
-        double r00 = cb * l00 - sb * l01, r01 = sb * l00 + cb * l01;
-        double r10 = cb * l10 - sb * l11, r11 = sb * l10 + cb * l11;
+        const double2 ja = csw[wave][a], jb = csw[wave][b];
+        if (ja.y == 0.0 && jb.y == 0.0) continue;
+        const short2 qa2 = pqw[wave][a], qb2 = pqw[wave][b];
+        const int pa = qa2.x, qa = qa2.y, pb = qb2.x, qb = qb2.y;
+        const double h00 = H[pa * P + pb], h01 = H[pa * P + qb];
+        const double h10 = H[qa * P + pb], h11 = H[qa * P + qb];
+        const double l00 = ja.x * h00 - ja.y * h10, l01 = ja.x * h01 - ja.y * h11;
+        const double l10 = ja.y * h00 + ja.x * h10, l11 = ja.y * h01 + ja.x * h11;
+        double r00 = jb.x * l00 - jb.y * l01, r01 = jb.y * l00 + jb.x * l01;
+        double r10 = jb.x * l10 - jb.y * l11, r11 = jb.y * l10 + jb.x * l11;
         if (a == b) r01 = r10 = 0.0;      // the rotated pair is diagonalised
-        Hs[pa * kJL + pb] = r00;
-        Hs[pa * kJL + qb] = r01;
-        Hs[qa * kJL + pb] = r10;
-        Hs[qa * kJL + qb] = r11;
+        H[pa * P + pb] = r00;
+        H[pa * P + qb] = r01;
+        H[qa * P + pb] = r10;
+        H[qa * P + qb] = r11;
+      }
+      if (fuse) {
+        // V <- V J: columns (p_a, q_a) of every row
+        for (int e = tid; e < kp * npair; e += nt) {
+          const int i = e / npair, a = e - i * npair;
+          const double2 ja = csw[wave][a];
+          if (ja.y == 0.0) continue;
+          const short2 q2 = pqw[wave][a];
+          const double vp = V[i * P + q2.x], vq = V[i * P + q2.y];
+          V[i * P + q2.x] = ja.x * vp - ja.y * vq;
+          V[i * P + q2.y] = ja.y * vp + ja.x * vq;
+        }
       }
       __syncthreads();
     }
-    __syncthreads();
-    if (nrot == 0) break;
-    __syncthreads();
+    if (nrot == 0) { converged = true; break; }
   }
+  if (fuse) {
+    for (int e = tid; e < k * k; e += nt) {
+      const int i = e / k, j = e - i * k;
+      st.VM[size_t(i) * kcap + j] = V[i * P + j];
+    }
+  }
+  for (int j = tid; j < k; j += nt) st.lam[j] = H[j * P + j];
   if (tid == 0) {
-    *st.rounds = round;
-    if (nrot != 0) atomicOr(st.info, 4);
+    *st.rounds = fuse ? -1 : round;
+    if (!converged) atomicOr(st.info, 4);
   }
 }
 
@@ -353,11 +414,12 @@ constexpr int kRepBatch = 16;
 __global__ __launch_bounds__(64) void jacobi_replay_kernel(TruncState st, int kcap) {
   __shared__ double row[kRepRows][SK];
   __shared__ double2 rb[kRepBatch][SK / 2];
-  const int k = *st.k;
+  const int k = *st.kj;
   const int kp = k + (k & 1);
   const int i0 = blockIdx.x * kRepRows;
   if (i0 >= k) return;
   const int T = *st.rounds;
+  if (T < 0) return;                  // the Jacobi kernel already wrote V
   const int lane = threadIdx.x;
   for (int r = 0; r < kRepRows; ++r)
     for (int j = lane; j < kp; j += 64) row[r][j] = (j == i0 + r) ? 1.0 : 0.0;
@@ -400,10 +462,127 @@ void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s) {
   LRC_HIP(hipGetLastError());
 }
 
+// ============================================================== pivoted Cholesky
+// Diagonally pivoted Cholesky of H = M^T M:  Pi^T H Pi = R^T R, stopped once
+// the trace of the remaining Schur complement (the energy of the directions
+// left out) is below max(1e-16, (tol / 10)^2) trace(H): the rounding level of
+// H, or 1% of the truncation's tail budget if that is larger.  With tol = 0
+// every positive pivot is kept.  The rank kj it reveals is the dimension of
+// the eigenproblem solved next, on R R^T, whose eigenvectors Y give H's as
+// Pi R^T Y.  R R^T is close to diagonal after pivoting, so far fewer Jacobi
+// sweeps are needed than on H itself.
+// Pivoting is logical: the trailing matrix stays indexed by the original
+// columns (a step updates the entries of the columns not yet chosen), rows of
+// R are first written by original column to st.VP, and R R^T (which does not
+// depend on the column order) is formed from those rows.  Two barriers per
+// step.  Outputs: R (kj x k, upper trapezoidal in pivot order, zero rows below
+// kj) in st.W, R R^T (kj x kj) in st.H, the pivot order in st.piv, kj in st.kj.
+constexpr int kPivThreads = 1024;
+__global__ __launch_bounds__(kPivThreads) void pivchol_kernel(TruncState st, int kcap, double tol) {
+  __shared__ double A[SK * kJL];
+  __shared__ double dg[SK];
+  __shared__ int pos[SK];
+  __shared__ unsigned char rem[SK];
+  __shared__ int s_p, s_stop;
+  __shared__ double s_thr;
+  const int k = *st.k;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* Ro = st.VP;   // rows of R by original column (scratch)
+  for (int e = tid; e < k * k; e += nt) {
+    const int i = e / k, j = e - i * k;
+    A[i * kJL + j] = st.H[size_t(i) * kcap + j];
+  }
+  for (int i = tid; i < k; i += nt) {
+    dg[i] = st.H[size_t(i) * kcap + i];
+    rem[i] = 1;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double tr = 0.0;
+    for (int i = tid; i < k; i += 64) tr += fabs(dg[i]);
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+    if (tid == 0) s_thr = tol > 0.0 ? fmax(1e-16, 0.01 * tol * tol) * tr : 0.0;
+  }
+  int r = k;
+  for (int j = 0; j < k; ++j) {
+    if (tid < 64) {
+      double best = -1.0, sum = 0.0;
+      int bi = k;
+      for (int i = tid; i < k; i += 64) {
+        if (!rem[i]) continue;
+        const double v = dg[i];
+        sum += v;
+        if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o);
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        const bool stop = !(sum > s_thr) || !(best > 0.0) || bi >= k;
+        s_stop = stop ? 1 : 0;
+        s_p = bi;
+        if (!stop) {
+          pos[j] = bi;
+          rem[bi] = 0;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_stop) { r = j; break; }
+    const int p = s_p;
+    const double d = dg[p];
+    const double inv = 1.0 / sqrt(d);
+    // row j of R by original column: R[j][p] = sqrt(d), R[j][x] = A[p][x] / sqrt(d)
+    // for columns not chosen yet, 0 for those chosen before
+    for (int x = tid; x < k; x += nt)
+      Ro[size_t(j) * kcap + x] = x == p ? d * inv : (rem[x] ? A[p * kJL + x] * inv : 0.0);
+    // trailing update of the remaining columns (row p is only read)
+    const double id = 1.0 / d;
+    for (int e = tid; e < k * k; e += nt) {
+      const int x = e / k, y = e - x * k;
+      if (!rem[x] || !rem[y]) continue;
+      const double v = A[x * kJL + y] - A[p * kJL + x] * A[p * kJL + y] * id;
+      A[x * kJL + y] = v;
+      if (x == y) dg[x] = v;
+    }
+    __syncthreads();
+  }
+  // the columns never chosen follow in original order
+  if (tid == 0) {
+    int q = r;
+    for (int x = 0; x < k; ++x)
+      if (rem[x]) pos[q++] = x;
+  }
+  __syncthreads();
+  // R in pivot order, and R R^T from the rows by original column (staged in LDS)
+  for (int e = tid; e < k * k; e += nt) {
+    const int a = e / k, c = e - a * k;
+    const double v = (a < r && c >= a) ? Ro[size_t(a) * kcap + pos[c]] : 0.0;
+    st.W[size_t(a) * kcap + c] = v;
+    A[a * kJL + c] = a < r ? Ro[size_t(a) * kcap + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += nt) {
+    const int a = e / r, b = e - a * r;
+    if (b < a) continue;
+    double acc = 0.0;
+    for (int x = 0; x < k; ++x) acc += A[a * kJL + x] * A[b * kJL + x];
+    st.H[size_t(a) * kcap + b] = acc;
+    st.H[size_t(b) * kcap + a] = acc;
+  }
+  for (int i = tid; i < k; i += nt) st.piv[i] = pos[i];
+  if (tid == 0) *st.kj = r;
+}
+
 // ============================================================== core + Jacobi
 // R_A = R2_A R1_A, R_B = R2_B R1_B;  M = R_A diag(core) R_B^T;  H = M^T M;
-// then the Jacobi rounds.  Scratch: R1 buffers are overwritten by R_A, R_B.
-void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, hipStream_t s) {
+// pivoted Cholesky of H, then the Jacobi rounds on R R^T.  Scratch: R1
+// buffers are overwritten by R_A, R_B; H by R R^T.
+void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, double tol,
+                        hipStream_t s) {
   LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
   // R_A, R_B into the G buffers (the Grams are no longer needed)
   SmallGemm j2[2];
@@ -417,8 +596,12 @@ void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, 
   // H = M^T M
   SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
   small_gemm(&jh, 1, core, st.k, kcap, s);
+  {
+    ProfScope ps(kcls(K_PIVCHOL, false), s);
+    hipLaunchKernelGGL(pivchol_kernel, dim3(1), dim3(kPivThreads), 0, s, st, kcap, tol);
+  }
   ProfScope ps(kcls(K_JACOBI, false), s);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, st, kcap, max_rounds);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacThreads), 0, s, st, kcap, max_rounds);
   LRC_HIP(hipGetLastError());
 }
 
@@ -433,15 +616,33 @@ __global__ __launch_bounds__(256) void select_kernel(TruncState st, int kcap, in
   __shared__ double srt[SK];
   __shared__ int ord[SK];
   __shared__ int rsel;
-  const int k = *st.k;
+  __shared__ double om[SK], nu[SK];
+  __shared__ double s_lfloor;
+  const int kr = *st.k;          // rows of W and VP
+  const int k = *st.kj;          // candidate singular directions
   const int tid = threadIdx.x;
+  if (tid < 64) {
+    double tr = 0.0;
+    for (int j = tid; j < k; j += 64) tr += fabs(st.lam[j]);
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+    if (tid == 0) s_lfloor = 64.0 * 1e-16 * tr;
+  }
+  __syncthreads();
+  // sigma_j = ||M VP_j|| / ||VP_j|| (= lambda_j / sqrt(lambda_j)) is the more
+  // accurate value where lambda_j is well above the Jacobi floor; at the
+  // rounding level both norms are noise, and sqrt(lambda_j) is used instead.
   for (int j = tid; j < k; j += blockDim.x) {
-    double a = 0.0;
-    for (int i = 0; i < k; ++i) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < kr; ++i) {
       const double w = st.W[size_t(i) * kcap + j];
+      const double v = st.VP[size_t(i) * kcap + j];
       a += w * w;
+      b += v * v;
     }
-    sig[j] = sqrt(a);
+    om[j] = sqrt(a);
+    nu[j] = sqrt(b);
+    const double lj = st.lam[j];
+    sig[j] = (lj > s_lfloor && nu[j] > 0.0) ? om[j] / nu[j] : sqrt(fmax(lj, 0.0));
   }
   __syncthreads();
   for (int j = tid; j < k; j += blockDim.x) {
@@ -478,8 +679,10 @@ __global__ __launch_bounds__(256) void select_kernel(TruncState st, int kcap, in
   __syncthreads();
   const int r = rsel;
   for (int j = tid; j < k; j += blockDim.x) {
-    st.order[j] = ord[j];
-    st.invsig[j] = srt[j] > 0.0 ? 1.0 / srt[j] : 0.0;
+    const int o = ord[j];
+    st.order[j] = o;
+    st.invsig[j] = om[o] > 0.0 ? 1.0 / om[o] : 0.0;
+    st.invnu[j] = nu[o] > 0.0 ? 1.0 / nu[o] : 0.0;
     if (j < r) s_out[j] = srt[j];
   }
 }
@@ -488,17 +691,20 @@ void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, doub
                          int* rank_out, double* norm_out, hipStream_t s) {
   CoreView none{};
   none.nb = 0;
-  SmallGemm jw{st.M, st.VM, st.W, nullptr, nullptr, nullptr, 0, 0, 0};
+  // VP = Pi R^T Y (k x kj), then W = M VP
+  SmallGemm jv{st.W, st.VM, st.VP, nullptr, nullptr, st.kj, 1, 0, 0, st.piv, st.kj};
+  small_gemm(&jv, 1, none, st.k, kcap, s);
+  SmallGemm jw{st.M, st.VP, st.W, nullptr, nullptr, st.kj, 0, 0, 0};
   small_gemm(&jw, 1, none, st.k, kcap, s);
   {
     ProfScope ps(kcls(K_SELECT, false), s);
     hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, st, kcap, rank_cap, tol, s_out,
                        rank_out, norm_out);
   }
-  // XA = R2i_A W[:, order] diag(1 / sigma),  XB = R2i_B V[:, order]
+  // XA = R2i_A W[:, order] diag(1 / ||W_j||),  XB = R2i_B VP[:, order] diag(1 / ||VP_j||)
   SmallGemm jx[2];
   jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, st.invsig, rank_out, 0, 0, 0};
-  jx[1] = SmallGemm{st.R2i[1], st.VM, st.XB, st.order, nullptr, rank_out, 0, 0, 0};
+  jx[1] = SmallGemm{st.R2i[1], st.VP, st.XB, st.order, st.invnu, rank_out, 0, 0, 0};
   small_gemm(jx, 2, none, st.k, kcap, s);
   LRC_HIP(hipGetLastError());
 }

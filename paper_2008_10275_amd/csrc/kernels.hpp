@@ -108,12 +108,17 @@ struct TruncState {
   double* R2i[2];    // R2^{-1}
   double* M;         // core
   double* H;         // M^T M
-  double* VM;        // right singular vectors (k x k)
-  double* W;         // M V_M  (columns sigma_j u_j)
+  double* VM;        // eigenvectors Y of the preconditioned Gram R R^T (kj x kj)
+  double* W;         // pivoted Cholesky factor R, then M V (columns ~ sigma_j u_j)
+  double* VP;        // V = Pi R^T Y (k x kj, column norms sqrt(lambda_j))
   double* XA;        // R2A^{-1} U_M(:, :r)   (k x r, ld kcap)
   double* XB;        // R2B^{-1} V_M(:, :r)
   int* order;        // columns by decreasing sigma
-  double* invsig;    // 1 / sigma in that order
+  double* invsig;    // 1 / ||W_j|| in that order
+  double* invnu;     // 1 / ||VP_j|| in that order
+  double* lam;       // eigenvalues of R R^T from the Jacobi rounds (kj values)
+  int* piv;          // pivot order of the Cholesky of M^T M
+  int* kj;           // numerical rank found by that Cholesky (Jacobi dimension)
   double* rot;       // rotation log (c, s) per round and pair
   int* rounds;       // number of logged rounds
   int* k;            // total width (A and B have the same column count)
@@ -121,7 +126,8 @@ struct TruncState {
 };
 
 void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s);
-void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, hipStream_t s);
+void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, double tol,
+                        hipStream_t s);
 void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s);
 void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, double* s_out,
                          int* rank_out, double* norm_out, hipStream_t s);

@@ -62,6 +62,7 @@ BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double
   v.wdev[0] = wdev;
   v.wconst[0] = wconst;
   v.rowscale[0] = rowscale;
+  v.cap[0] = wdev ? ld : wconst;
   return v;
 }
 template BlockView<double> view1(const double*, int, const int*, int, const double*);
@@ -77,6 +78,7 @@ static void add_block(BlockView<T>& v, const T* p, int ld, const int* wdev, int 
   v.wdev[b] = wdev;
   v.wconst[b] = wconst;
   v.rowscale[b] = rowscale;
+  v.cap[b] = wdev ? ld : wconst;
 }
 
 static void add_core(CoreView& c, const double* s, double coef, const int* wdev, int wconst) {
@@ -98,8 +100,8 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
   ldq = kTruncCap;
   max_rounds = 30 * (kcap - 1);
   const size_t kk = size_t(kcap) * kcap;
-  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, XA, XB + invsig
-  const size_t arena = 16 * kk + kcap;
+  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, VP, XA, XB + invsig, invnu, lam
+  const size_t arena = 17 * kk + 3 * size_t(kcap);
   small.alloc(arena * sizeof(double));
   double* b = small.as<double>();
   for (int x = 0; x < 2; ++x) {
@@ -113,18 +115,23 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
   st.H = b; b += kk;
   st.VM = b; b += kk;
   st.W = b; b += kk;
+  st.VP = b; b += kk;
   st.XA = b; b += kk;
   st.XB = b; b += kk;
   st.invsig = b; b += kcap;
+  st.invnu = b; b += kcap;
+  st.lam = b; b += kcap;
   LRC_CHECK(size_t(b - small.as<double>()) == arena, ST_EINVAL, "truncation arena layout");
   rot.alloc(size_t(max_rounds) * 64 * 2 * sizeof(double));
   st.rot = rot.as<double>();
-  ints.alloc((kcap + 16) * sizeof(int));
+  ints.alloc((2 * kcap + 16) * sizeof(int));
   int* ib = ints.as<int>();
   st.order = ib;
-  st.rounds = ib + kcap;
-  st.k = ib + kcap + 1;
-  st.info = ib + kcap + 2;
+  st.piv = ib + kcap;
+  st.rounds = ib + 2 * kcap;
+  st.k = ib + 2 * kcap + 1;
+  st.info = ib + 2 * kcap + 2;
+  st.kj = ib + 2 * kcap + 3;
   LRC_HIP(hipMemsetAsync(small.p, 0, small.bytes, s));
   LRC_HIP(hipMemsetAsync(ints.p, 0, ints.bytes, s));
   gram_bytes = gram_workspace_bytes(nmax, mmax, kcap, sizeof(T) == 8);
@@ -149,27 +156,74 @@ void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, 
   launch_chol(st, 1, kcap, eps, s);
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
   launch_tsmm<T>(t1, 2, kcap, kcap, s);
-  const BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
+  BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
+  va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
   launch_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info, s);
   launch_chol(st, 2, kcap, eps, s);
-  launch_core_jacobi(st, core, kcap, max_rounds, s);
+  launch_core_jacobi(st, core, kcap, max_rounds, tol, s);
   launch_jacobi_replay(st, kcap, s);
   launch_trunc_finish(st, kcap, rank_cap, tol, s_out, rank_out, norm_out, s);
   TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
                       {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
   launch_tsmm<T>(t2, 2, kcap, rank_cap, s);
   if (log_enabled()) {
-    int hk[4] = {0, 0, 0, 0};
+    int hk[5] = {0, 0, 0, 0, 0};
     double hn = 0.0;
+    LRC_HIP(hipMemcpyAsync(&hk[4], st.kj, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[0], st.k, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[1], rank_out, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[2], st.info, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[3], st.rounds, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hn, norm_out, 8, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipStreamSynchronize(s));
-    std::fprintf(stderr, "{\"trunc\": %d, \"k\": %d, \"rank\": %d, \"norm\": %.9e, \"info\": %d, \"rounds\": %d}\n",
-                 int(sizeof(T)), hk[0], hk[1], hn, hk[2], hk[3]);
+    std::fprintf(stderr, "{\"trunc\": %d, \"k\": %d, \"kj\": %d, \"rank\": %d, \"norm\": %.9e, \"info\": %d, \"rounds\": %d}\n",
+                 int(sizeof(T)), hk[0], hk[4], hk[1], hn, hk[2], hk[3]);
+    if (hk[0] > 0 && hk[4] == 0) {
+      // diagnostics of a truncation whose core came out empty
+      const int kk = hk[0];
+      std::vector<double> buf(size_t(kcap) * kcap);
+      auto diag = [&](const double* dp, const char* name) {
+        LRC_HIP(hipMemcpy(buf.data(), dp, buf.size() * 8, hipMemcpyDeviceToHost));
+        double mn = 1e300, mx = -1e300;
+        int nan = 0;
+        for (int i = 0; i < kk; ++i) {
+          const double v = buf[size_t(i) * kcap + i];
+          if (!(v == v)) ++nan;
+          else { mn = std::min(mn, v); mx = std::max(mx, v); }
+        }
+        std::fprintf(stderr, "  %s diag: min %.3e max %.3e nan %d  (0,1)=%.3e\n", name, mn, mx, nan,
+                     kk > 1 ? buf[1] : 0.0);
+      };
+      diag(st.G[0], "G_A(pass2)");
+      diag(st.G[1], "G_B(pass2)");
+      diag(st.R1[0], "R_A");
+      diag(st.R1[1], "R_B");
+      diag(st.R2[0], "R2_A");
+      diag(st.R2[1], "R2_B");
+      diag(st.M, "M");
+      diag(st.H, "H");
+      {
+        LRC_HIP(hipMemcpy(buf.data(), st.T1[0], buf.size() * 8, hipMemcpyDeviceToHost));
+        int nan = 0, big = 0;
+        for (int i = 0; i < kk; ++i)
+          for (int j = 0; j < kk; ++j) {
+            const double v = buf[size_t(i) * kcap + j];
+            if (!(v == v)) ++nan;
+            else if (std::fabs(v) > 1e30) ++big;
+          }
+        std::fprintf(stderr, "  T1_A: nan %d big %d\n", nan, big);
+        std::vector<T> q(size_t(n) * ldq);
+        LRC_HIP(hipMemcpy(q.data(), Q1A.p, q.size() * sizeof(T), hipMemcpyDeviceToHost));
+        std::vector<int> colnan(kk, 0);
+        for (int64_t i = 0; i < n; ++i)
+          for (int j = 0; j < kk; ++j)
+            if (!(q[size_t(i) * ldq + j] == q[size_t(i) * ldq + j])) ++colnan[j];
+        std::fprintf(stderr, "  Q1_A nan per column:");
+        for (int j = 0; j < kk; ++j) std::fprintf(stderr, " %d", colnan[j]);
+        std::fprintf(stderr, "\n");
+      }
+    }
   }
 }
 template struct Truncator<double>;

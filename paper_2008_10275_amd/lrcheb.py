@@ -80,6 +80,9 @@ _SIGS = {
     "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
                                    _P, C.c_int, C.c_int, C.c_double, _P, C.c_int, _P, _P,
                                    C.c_int, C.POINTER(C.c_int)]),
+    "lrc_truncate_scaled_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, _P,
+                                          C.c_int, _P, _P, C.c_int, _P, C.c_int, C.c_double, _P,
+                                          C.c_int, _P, _P, C.c_int, C.POINTER(C.c_int)]),
     "lrc_profile_enable": (C.c_int, [C.c_int]),
     "lrc_profile_read": (C.c_int, [C.c_int, _P, _P, _P, _P]),
     "lrc_profile_class_name": (C.c_char_p, [C.c_int]),
@@ -356,6 +359,27 @@ def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V):
                                                A.stride(0), _ptr(cc), _dev_ptr(B), B.stride(0),
                                                rank_cap, tol, _dev_ptr(U), U.stride(0), _ptr(s),
                                                _dev_ptr(V), V.stride(0), C.byref(r)))
+    return s[:r.value].copy(), r.value
+
+
+def truncate_scaled_dev(ctx, A, c, B, k1, w, rank_cap, tol, U, V):
+    """lrc_truncate_scaled_dev: truncation of A diag(c) [B1 | diag(w) B2]^T
+    (B1 = B[:, :k1]); w is an fp64 device tensor of m values.  Returns (s, rank)."""
+    import torch
+    dtype = 0 if A.dtype == torch.float64 else 1
+    cc = _f64(np.ravel(c))
+    n, k = A.shape[0], cc.size
+    m = B.shape[0]
+    if A.shape[1] < k or B.shape[1] < k:
+        raise ValueError("A and B need at least len(c) columns")
+    if w.dtype != torch.float64 or w.numel() != m:
+        raise ValueError("w must hold m fp64 values")
+    s = np.zeros(64)
+    r = C.c_int()
+    _check(ctx.handle, load().lrc_truncate_scaled_dev(
+        ctx.handle, dtype, n, m, k, int(k1), _dev_ptr(A), A.stride(0), _ptr(cc), _dev_ptr(B),
+        B.stride(0), _dev_ptr(w), rank_cap, tol, _dev_ptr(U), U.stride(0), _ptr(s), _dev_ptr(V),
+        V.stride(0), C.byref(r)))
     return s[:r.value].copy(), r.value
 
 
