@@ -172,6 +172,37 @@ lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m,
                                    int ldb, const double* w_dev, int rank_cap, double tol,
                                    void* U_dev, int ldu, double* s, void* V_dev, int ldv, int* rank);
 
+/* --------------------------------------------------------------- surrogate
+ * Learned initial guess (not in the paper; the initial guess is the upper
+ * median's solution, Sec. 3.3): a perceptron d0 -> d1 -> d2 -> d3 with exact
+ * erf GELU after the two hidden layers, mapping parameters (mu, lambda) to
+ * coefficients on a snapshot (POD) basis.  bf16 weights and activations, fp32
+ * accumulation on MFMA, fp32 master weights and Adam.  Sizes: d0 <= 32,
+ * d1, d2 in {32, 64}, d3 <= 32.  params: the d1 d0 + d1 + d2 d1 + d2 + d3 d2 +
+ * d3 initial values packed as W1, b1, W2, b2, W3, b3 (W row-major, out x in).
+ * Device arrays (row-major fp64): X (B x d0, raw parameters), T (B x d3, raw
+ * coefficients), Y (B x d3).  The scaling starts as the identity (inputs taken
+ * as already in [-1, 1], targets as already standardised); lrc_mlp_fit_scaling
+ * sets it from data: inputs mapped affinely from their range onto [-1, 1],
+ * targets standardised per column (mean, population deviation).  The loss is
+ * the mean squared error over B x d3 standardised entries.  B <= 4096. */
+typedef struct lrc_mlp_s* lrc_mlp;
+lrc_status lrc_mlp_create(lrc_ctx ctx, const int sizes[4], const float* params, lrc_mlp* mlp);
+void lrc_mlp_destroy(lrc_mlp mlp);
+lrc_status lrc_mlp_fit_scaling(lrc_mlp mlp, int B, const double* X_dev, const double* T_dev);
+/* One forward and backward pass without an update: *loss and the packed
+ * gradients (host, same layout as params; either may be NULL). */
+lrc_status lrc_mlp_grad(lrc_mlp mlp, int B, const double* X_dev, const double* T_dev, float* loss,
+                        float* grads);
+/* `steps` full-batch Adam steps (bias-corrected); loss_hist (host, steps
+ * values, may be NULL) receives the loss before each step. */
+lrc_status lrc_mlp_train(lrc_mlp mlp, int B, const double* X_dev, const double* T_dev, int steps,
+                         float lr, float beta1, float beta2, float eps, float* loss_hist);
+/* Y = network(X) in coefficient units (unstandardised). */
+lrc_status lrc_mlp_predict(lrc_mlp mlp, int B, const double* X_dev, double* Y_dev);
+/* Current fp32 master parameters (packed like params). */
+lrc_status lrc_mlp_get_params(lrc_mlp mlp, float* params);
+
 /* --------------------------------------------------------------- timing
  * Per-kernel-class timing with HIP events recorded on the stream each kernel
  * is launched on (process-wide, not thread-safe).  A class is a kernel family

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "mlp.hpp"
 #include "prof.hpp"
 #include "solver.hpp"
 
@@ -18,6 +19,10 @@ struct lrc_ops_s {
 struct lrc_prob_s {
   Prob p;
   std::unique_ptr<lrc_ops_s> owned_ops;
+};
+struct lrc_mlp_s {
+  lrc_ctx ctx;
+  lrc::Mlp m;
 };
 
 namespace {
@@ -196,6 +201,101 @@ void upload_prec(Prec& pr, hipStream_t s) {
 }  // namespace
 
 extern "C" {
+
+lrc_status lrc_mlp_create(lrc_ctx ctx, const int sizes[4], const float* params, lrc_mlp* out) {
+  if (!ctx || !out) return LRC_EINVAL;
+  *out = nullptr;
+  return guarded(&ctx->c, [&]() -> lrc_status {
+    LRC_CHECK(sizes && params, ST_EINVAL, "mlp: sizes and params are required");
+    auto h = std::make_unique<lrc_mlp_s>();
+    h->ctx = ctx;
+    h->m.init(sizes, params, ctx->c.stream);
+    *out = h.release();
+    return LRC_OK;
+  });
+}
+
+void lrc_mlp_destroy(lrc_mlp mlp) {
+  if (!mlp) return;
+  (void)hipStreamSynchronize(mlp->ctx->c.stream);
+  delete mlp;
+}
+
+static void mlp_check_batch(int B) {
+  LRC_CHECK(B >= 1 && B <= 4096, ST_EINVAL, "mlp: batch size must be in [1, 4096]");
+}
+
+lrc_status lrc_mlp_fit_scaling(lrc_mlp mlp, int B, const double* X, const double* T) {
+  if (!mlp) return LRC_EINVAL;
+  return guarded(&mlp->ctx->c, [&]() -> lrc_status {
+    mlp_check_batch(B);
+    LRC_CHECK(X && T, ST_EINVAL, "mlp: null data");
+    mlp->m.fit(B, X, T, mlp->ctx->c.stream);
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_mlp_grad(lrc_mlp mlp, int B, const double* X, const double* T, float* loss,
+                        float* grads) {
+  if (!mlp) return LRC_EINVAL;
+  return guarded(&mlp->ctx->c, [&]() -> lrc_status {
+    mlp_check_batch(B);
+    LRC_CHECK(X && T, ST_EINVAL, "mlp: null data");
+    hipStream_t s = mlp->ctx->c.stream;
+    mlp->m.targets(B, T, s);
+    mlp->m.forward(B, X, s);
+    mlp->m.backward(B, s);
+    if (loss) LRC_HIP(hipMemcpyAsync(loss, mlp->m.lossd.p, 4, hipMemcpyDeviceToHost, s));
+    if (grads)
+      LRC_HIP(hipMemcpyAsync(grads, mlp->m.Gr.p, size_t(mlp->m.np) * 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipStreamSynchronize(s));
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_mlp_train(lrc_mlp mlp, int B, const double* X, const double* T, int steps,
+                         float lr, float beta1, float beta2, float eps, float* loss_hist) {
+  if (!mlp) return LRC_EINVAL;
+  return guarded(&mlp->ctx->c, [&]() -> lrc_status {
+    mlp_check_batch(B);
+    LRC_CHECK(X && T && steps >= 0, ST_EINVAL, "mlp: null data or negative step count");
+    hipStream_t s = mlp->ctx->c.stream;
+    DevBuf hist(size_t(std::max(steps, 1)) * 4);
+    mlp->m.targets(B, T, s);
+    for (int it = 0; it < steps; ++it) {
+      mlp->m.forward(B, X, s);
+      mlp->m.backward(B, s);
+      LRC_HIP(hipMemcpyAsync(hist.as<float>() + it, mlp->m.lossd.p, 4, hipMemcpyDeviceToDevice, s));
+      mlp->m.adam(lr, beta1, beta2, eps, s);
+    }
+    if (loss_hist && steps > 0)
+      LRC_HIP(hipMemcpyAsync(loss_hist, hist.p, size_t(steps) * 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipStreamSynchronize(s));
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_mlp_predict(lrc_mlp mlp, int B, const double* X, double* Y) {
+  if (!mlp) return LRC_EINVAL;
+  return guarded(&mlp->ctx->c, [&]() -> lrc_status {
+    mlp_check_batch(B);
+    LRC_CHECK(X && Y, ST_EINVAL, "mlp: null data");
+    hipStream_t s = mlp->ctx->c.stream;
+    mlp->m.forward(B, X, s);
+    mlp->m.outputs(B, Y, s);
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_mlp_get_params(lrc_mlp mlp, float* params) {
+  if (!mlp || !params) return LRC_EINVAL;
+  return guarded(&mlp->ctx->c, [&]() -> lrc_status {
+    hipStream_t s = mlp->ctx->c.stream;
+    LRC_HIP(hipMemcpyAsync(params, mlp->m.P.p, size_t(mlp->m.np) * 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipStreamSynchronize(s));
+    return LRC_OK;
+  });
+}
 
 lrc_status lrc_profile_enable(int mode) {
   if (mode < 0 || mode > 2) return LRC_EINVAL;

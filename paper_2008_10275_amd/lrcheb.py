@@ -83,6 +83,14 @@ _SIGS = {
     "lrc_truncate_scaled_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, _P,
                                           C.c_int, _P, _P, C.c_int, _P, C.c_int, C.c_double, _P,
                                           C.c_int, _P, _P, C.c_int, C.POINTER(C.c_int)]),
+    "lrc_mlp_create": (C.c_int, [_P, _P, _P, C.POINTER(_P)]),
+    "lrc_mlp_destroy": (None, [_P]),
+    "lrc_mlp_fit_scaling": (C.c_int, [_P, C.c_int, _P, _P]),
+    "lrc_mlp_grad": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
+    "lrc_mlp_train": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, C.c_float, C.c_float, C.c_float,
+                                C.c_float, _P]),
+    "lrc_mlp_predict": (C.c_int, [_P, C.c_int, _P, _P]),
+    "lrc_mlp_get_params": (C.c_int, [_P, _P]),
     "lrc_profile_enable": (C.c_int, [C.c_int]),
     "lrc_profile_read": (C.c_int, [C.c_int, _P, _P, _P, _P]),
     "lrc_profile_class_name": (C.c_char_p, [C.c_int]),
@@ -311,6 +319,82 @@ class Problem:
         if self.handle:
             load().lrc_prob_destroy(self.handle)
             self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Surrogate perceptron (lrc_mlp_*).  params: list [W1, b1, W2, b2, W3, b3]
+    (W out x in, as in the oracle).  Data are fp64 torch tensors on the device:
+    X (B x d0), T (B x d3)."""
+
+    def __init__(self, ctx, params):
+        self.ctx = ctx
+        self.sizes = [params[0].shape[1], params[0].shape[0], params[2].shape[0],
+                      params[4].shape[0]]
+        self.shapes = [np.shape(p) for p in params]
+        packed = np.concatenate([np.ravel(np.asarray(p, dtype=np.float64)) for p in params])
+        packed = np.ascontiguousarray(packed, dtype=np.float32)
+        sz = np.ascontiguousarray(self.sizes, dtype=np.int32)
+        h = C.c_void_p()
+        _check(ctx.handle, load().lrc_mlp_create(ctx.handle, _ptr(sz), _ptr(packed), C.byref(h)))
+        self.handle = h
+        self.np = packed.size
+
+    def _unpack(self, flat):
+        out, o = [], 0
+        for sh in self.shapes:
+            k = int(np.prod(sh))
+            out.append(flat[o:o + k].reshape(sh).astype(np.float64))
+            o += k
+        return out
+
+    @staticmethod
+    def _dev(t):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("MLP data must be contiguous fp64 device tensors")
+        return _dev_ptr(t)
+
+    def fit_scaling(self, X, T):
+        _check(self.ctx.handle, load().lrc_mlp_fit_scaling(self.handle, X.shape[0], self._dev(X),
+                                                           self._dev(T)))
+
+    def grad(self, X, T):
+        """(loss, gradients as a list like params) of one forward/backward pass."""
+        loss = C.c_float()
+        g = np.zeros(self.np, dtype=np.float32)
+        _check(self.ctx.handle, load().lrc_mlp_grad(self.handle, X.shape[0], self._dev(X),
+                                                    self._dev(T), C.byref(loss), _ptr(g)))
+        return float(loss.value), self._unpack(g)
+
+    def train(self, X, T, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        hist = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(self.ctx.handle, load().lrc_mlp_train(self.handle, X.shape[0], self._dev(X),
+                                                     self._dev(T), steps, lr, beta1, beta2, eps,
+                                                     _ptr(hist)))
+        return hist[:steps].astype(np.float64)
+
+    def predict(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.sizes[3]), dtype=torch.float64, device=X.device)
+        _check(self.ctx.handle, load().lrc_mlp_predict(self.handle, X.shape[0], self._dev(X),
+                                                       _dev_ptr(Y)))
+        return Y
+
+    def params(self):
+        p = np.zeros(self.np, dtype=np.float32)
+        _check(self.ctx.handle, load().lrc_mlp_get_params(self.handle, _ptr(p)))
+        return self._unpack(p)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lrc_mlp_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

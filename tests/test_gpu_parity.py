@@ -180,3 +180,32 @@ def test_c2_small_mixed_precision_reaches_1e6(torch, L, ctx):
     X = U @ np.diag(s) @ V.T
     Fd = np.outer(f, np.ones(m))
     assert olr.relres_dense(K, d, X, Fd) <= 1.01e-6
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,m,k,k1,cap", [(3000, 100, 4, 1, 5), (3000, 400, 61, 1, 20),
+                                          (3000, 200, 110, 8, 29), (2000, 300, 100, 70, 40)])
+def test_scaled_truncation_matches_oracle(torch, L, ctx, dt, n, m, k, k1, cap):
+    """The residual's V side [V_F | D_i V_S]: a two-block concatenation whose
+    second block is row-scaled (the layout every solver truncation uses)."""
+    say("truncate scaled", dt, n, m, k, k1, cap)
+    rng = np.random.default_rng(k + 7)
+    A = rng.standard_normal((n, k))
+    B = rng.standard_normal((m, k))
+    w = rng.uniform(0.5e4, 2e4, m)
+    c = np.logspace(0, -9, k)
+    Bw = B.copy()
+    Bw[:, k1:] *= w[:, None]
+    Uo, so, Vo = olr.truncate(A, np.diag(c), Bw, cap, 1e-8)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Ad, Bd = _dev(torch, A, tdt), _dev(torch, B, tdt)
+    wd = torch.from_numpy(w).cuda()
+    ld = max(8, (cap + 7) // 8 * 8)
+    Ud = torch.zeros((n, ld), dtype=tdt, device="cuda")
+    Vd = torch.zeros((m, ld), dtype=tdt, device="cuda")
+    s, r = L.truncate_scaled_dev(ctx, Ad, c, Bd, k1, wd, cap, 1e-8, Ud, Vd)
+    X = Ud.double().cpu().numpy()[:, :r] @ np.diag(s) @ Vd.double().cpu().numpy()[:, :r].T
+    Xo = Uo @ np.diag(so) @ Vo.T
+    tol = 1e-9 if dt == "f64" else 1e-5
+    assert abs(r - so.size) <= 1
+    assert np.linalg.norm(X - Xo) <= tol * np.linalg.norm(Xo)
