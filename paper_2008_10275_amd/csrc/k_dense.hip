@@ -81,13 +81,6 @@ constexpr int kGT = kGK / 16;                  // 8 tiles per dimension
 constexpr int kGN = kGT * (kGT + 1) / 2;       // 36 upper tiles
 constexpr int kGramWgMax = 512;
 
-template <class T>
-struct GramArgs {
-  BlockView<T> X[2];
-  int64_t rows[2];
-  int nwg0;          // workgroups of job 0; the rest belong to job 1
-  int nwg1;
-};
 
 template <class T>
 __device__ inline int view_width(const BlockView<T>& v) {
@@ -242,7 +235,12 @@ __device__ inline void gram_rows_g(int g, const ColRef<T>* cr, int KT, int64_t r
 }
 
 template <class T, int KTM, int NG, int PD, bool SCALED1>
-__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a, T* __restrict__ partial) {
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a0, const GramArgs<T>* ab,
+                                                   const int* done) {
+  if (done && done[blockIdx.z]) return;
+  const GramArgs<T>& a = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
+  T* __restrict__ partial = a.partial;
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr TileTab<KTM> tt{};
   constexpr int NTM = TileTab<KTM>::N;
@@ -302,10 +300,19 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a, T* __restrict_
 // written; also publishes the width k = min(width, kcap) and flags widths
 // beyond the capacity (info bit 8).
 template <class T>
-__global__ __launch_bounds__(1024) void gram_reduce_kernel(GramArgs<T> a, const T* __restrict__ partial,
-                                                           double* G0, double* G1, int kcap,
-                                                           int* k0, int* k1, int* info) {
+__global__ __launch_bounds__(1024) void gram_reduce_kernel(GramRedArgs<T> r0, const GramRedArgs<T>* rb,
+                                                           const int* done) {
   __shared__ double sh[16][64];
+  if (done && done[blockIdx.z]) return;
+  const GramRedArgs<T>& ra = rb ? rb[blockIdx.z] : r0;
+  const GramArgs<T>& a = ra.g;
+  const T* __restrict__ partial = a.partial;
+  double* G0 = ra.G0;
+  double* G1 = ra.G1;
+  const int kcap = ra.kcap;
+  int* k0 = ra.k0;
+  int* k1 = ra.k1;
+  int* info = ra.info;
   const int job = blockIdx.y;
   const int ktot = view_width(a.X[job]);
   const int kg = min(ktot, kGK);
@@ -351,11 +358,12 @@ size_t gram_workspace_bytes(int64_t rows_a, int64_t rows_b, int kcap, bool fp64)
 }
 
 template <class T>
-void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial, size_t ws_bytes,
-                 int* info, hipStream_t s) {
+GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial,
+                        size_t ws_bytes, int* info) {
   LRC_CHECK(njobs >= 1 && njobs <= 2, ST_EINVAL, "gram: one or two jobs");
   LRC_CHECK(kcap <= kGK, ST_EINVAL, "gram: at most 128 columns");
-  GramArgs<T> a;
+  GramLaunch<T> l;
+  GramArgs<T>& a = l.g;
   a.X[0] = jobs[0].X;
   a.rows[0] = jobs[0].rows;
   a.nwg0 = gram_wgs(jobs[0].rows);
@@ -368,47 +376,68 @@ void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial
     a.rows[1] = 0;
     a.nwg1 = 0;
   }
+  a.partial = reinterpret_cast<T*>(ws_partial);
   const size_t need = size_t(a.nwg0 + a.nwg1) * kGN * 256 * sizeof(T);
   LRC_CHECK(need <= ws_bytes, ST_EINVAL, "gram: workspace too small");
+  LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "gram: the first operand cannot be row-scaled");
+  l.r = GramRedArgs<T>{a, jobs[0].G, njobs == 2 ? jobs[1].G : jobs[0].G, kcap, jobs[0].kout,
+                       njobs == 2 ? jobs[1].kout : nullptr, info};
+  l.njobs = njobs;
+  l.grid = a.nwg0 + a.nwg1;
+  l.kb = std::min(kGK, std::max(view_cap(jobs[0].X), njobs > 1 ? view_cap(jobs[1].X) : 0));
+  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
+  // algorithmic flops: the k(k+1)/2 distinct entries of each Gram matrix, 2 flops per row each
+  l.work.bytes = false;
+  const double r0 = double(a.rows[0]), r1 = double(a.rows[1]);
+  l.work.groups = {view_terms(jobs[0].X), view_terms(njobs > 1 ? jobs[1].X : jobs[0].X)};
+  l.work.f = [=](const std::vector<double>& v) {
+    return r0 * v[0] * (v[0] + 1.0) + r1 * v[1] * (v[1] + 1.0);
+  };
+  return l;
+}
+
+template <class T>
+void enqueue_gram(const GramLaunch<T>& l, Batched<GramArgs<T>> bg, Batched<GramRedArgs<T>> br,
+                  hipStream_t s) {
   {
-    // algorithmic flops: the k(k+1)/2 distinct entries of each Gram matrix,
-    // 2 flops per row each
-    Work w;
-    w.bytes = false;
-    const double r0 = double(a.rows[0]), r1 = double(a.rows[1]);
-    w.groups = {view_terms(jobs[0].X), view_terms(njobs > 1 ? jobs[1].X : jobs[0].X)};
-    w.f = [=](const std::vector<double>& v) {
-      return r0 * v[0] * (v[0] + 1.0) + r1 * v[1] * (v[1] + 1.0);
-    };
-    ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, w);
-    // tile grid sized by the host-known width bound of the operands
-    const int kb = std::min(kGK, std::max(view_cap(jobs[0].X),
-                                          njobs > 1 ? view_cap(jobs[1].X) : 0));
-    const dim3 grid(a.nwg0 + a.nwg1), blk(256);
-    T* part = reinterpret_cast<T*>(ws_partial);
+    ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, bg.dev ? Work() : l.work);
+    const GramArgs<T>& a = l.g;
+    const dim3 grid(l.grid, 1, bg.n), blk(256);
     // (tile grid, wave groups sharing the tiles, prefetch depth) per width
     // class, chosen so that accumulators + operand ring fit the registers
     constexpr bool F64 = sizeof(T) == 8;
-    const bool sc1 = njobs > 1 && view_scaled(jobs[1].X);
-    LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "gram: the first operand cannot be row-scaled");
-#define LRC_GRAM(KTM, NG, PD)                                                                \
-  do {                                                                                      \
-    if (sc1) hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, true>), grid, blk, 0, s, a, part); \
-    else hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, false>), grid, blk, 0, s, a, part);    \
+#define LRC_GRAM(KTM, NG, PD)                                                                     \
+  do {                                                                                           \
+    if (l.sc1)                                                                                   \
+      hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, true>), grid, blk, 0, s, a, bg.dev, bg.done); \
+    else                                                                                         \
+      hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, false>), grid, blk, 0, s, a, bg.dev, bg.done); \
   } while (0)
-    if (kb <= 32) LRC_GRAM(2, 1, 4);
-    else if (kb <= 64) LRC_GRAM(4, 1, F64 ? 2 : 4);
-    else if (kb <= 96) LRC_GRAM(6, 2, F64 ? 2 : 4);
+    if (l.kb <= 32) LRC_GRAM(2, 1, 4);
+    else if (l.kb <= 64) LRC_GRAM(4, 1, F64 ? 2 : 4);
+    else if (l.kb <= 96) LRC_GRAM(6, 2, F64 ? 2 : 4);
     else LRC_GRAM(8, F64 ? 4 : 2, 2);
 #undef LRC_GRAM
   }
   ProfScope ps(kcls(K_GRAM_REDUCE, is_f32<T>()), s);
-  hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3(kGN * 256 / 64, njobs), dim3(1024), 0, s, a,
-                     reinterpret_cast<const T*>(ws_partial), jobs[0].G,
-                     njobs == 2 ? jobs[1].G : jobs[0].G, kcap, jobs[0].kout,
-                     njobs == 2 ? jobs[1].kout : nullptr, info);
+  hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3(kGN * 256 / 64, l.njobs, br.n), dim3(1024), 0,
+                     s, l.r, br.dev, br.done);
   LRC_HIP(hipGetLastError());
 }
+
+template <class T>
+void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial, size_t ws_bytes,
+                 int* info, hipStream_t s) {
+  enqueue_gram(make_gram(jobs, njobs, kcap, ws_partial, ws_bytes, info), Batched<GramArgs<T>>(),
+               Batched<GramRedArgs<T>>(), s);
+}
+template GramLaunch<float> make_gram<float>(const GramJob<float>*, int, int, double*, size_t, int*);
+template GramLaunch<double> make_gram<double>(const GramJob<double>*, int, int, double*, size_t,
+                                              int*);
+template void enqueue_gram<float>(const GramLaunch<float>&, Batched<GramArgs<float>>,
+                                  Batched<GramRedArgs<float>>, hipStream_t);
+template void enqueue_gram<double>(const GramLaunch<double>&, Batched<GramArgs<double>>,
+                                   Batched<GramRedArgs<double>>, hipStream_t);
 template void launch_gram<float>(const GramJob<float>*, int, int, double*, size_t, int*,
                                  hipStream_t);
 template void launch_gram<double>(const GramJob<double>*, int, int, double*, size_t, int*,
@@ -424,11 +453,6 @@ constexpr int kTsRows = 64;
 constexpr int kTsSlice = 64;
 constexpr int kTsKCAP = kGK;
 
-template <class T>
-struct TsmmArgs {
-  TsmmJob<T> job[2];
-  int nwg0, nwg1;
-};
 
 // Rows past the end are clamped (their products are never stored); columns
 // past the width meet zero rows of M.
@@ -445,7 +469,11 @@ __device__ inline void tsmm_load(T (&v0)[kTsRows / 4], T (&v1)[kTsRows / 4], con
 }
 
 template <class T, bool SCALED1>
-__global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a) {
+__global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a0, const TsmmArgs<T>* ab,
+                                                   const int* done) {
+  if (done && done[blockIdx.z]) return;
+  const TsmmArgs<T>& a = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T Ms[kTsKCAP][kTsSlice + 4];
   __shared__ T Xs[kTsRows][kTsKCAP + 1];
@@ -516,10 +544,12 @@ __global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a) {
 }
 
 template <class T>
-void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStream_t s) {
+TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
   LRC_CHECK(njobs >= 1 && njobs <= 2, ST_EINVAL, "tsmm: one or two jobs");
   LRC_CHECK(kcap <= kTsKCAP && rcap <= kTsKCAP, ST_EINVAL, "tsmm: capacity exceeded");
-  TsmmArgs<T> a;
+  LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "tsmm: the first operand cannot be row-scaled");
+  TsmmLaunch<T> l;
+  TsmmArgs<T>& a = l.a;
   const int cap_wg = sizeof(T) == 8 ? 256 : 512;
   a.job[0] = jobs[0];
   a.nwg0 = int(std::min<int64_t>(cap_wg, std::max<int64_t>(1, ceil_div(jobs[0].rows, kTsRows))));
@@ -530,25 +560,40 @@ void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStrea
     a.job[1] = jobs[0];
     a.nwg1 = 0;
   }
-  const int slices = int(ceil_div(rcap, kTsSlice));
-  // algorithmic bytes: X read once per output slice is not counted; X once
-  // plus Y once per job
-  Work w;
+  l.grid = a.nwg0 + a.nwg1;
+  l.slices = int(ceil_div(rcap, kTsSlice));
+  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
+  // algorithmic bytes: X read once plus Y written once per job
   const double r0 = double(jobs[0].rows), r1 = double(njobs > 1 ? jobs[1].rows : 0);
-  w.groups = {view_terms(jobs[0].X), {{jobs[0].r_dev, 0}},
-              view_terms(njobs > 1 ? jobs[1].X : jobs[0].X),
-              {{njobs > 1 ? jobs[1].r_dev : jobs[0].r_dev, 0}}};
-  w.f = [=](const std::vector<double>& v) {
+  l.work.groups = {view_terms(jobs[0].X), {{jobs[0].r_dev, 0}},
+                   view_terms(njobs > 1 ? jobs[1].X : jobs[0].X),
+                   {{njobs > 1 ? jobs[1].r_dev : jobs[0].r_dev, 0}}};
+  l.work.f = [=](const std::vector<double>& v) {
     return double(sizeof(T)) * (r0 * (v[0] + v[1]) + r1 * (v[2] + v[3]));
   };
-  ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, w);
-  LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "tsmm: the first operand cannot be row-scaled");
-  if (njobs > 1 && view_scaled(jobs[1].X))
-    hipLaunchKernelGGL((tsmm_kernel<T, true>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
+  return l;
+}
+
+template <class T>
+void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s) {
+  ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, b.dev ? Work() : l.work);
+  const dim3 grid(l.grid, l.slices, b.n);
+  if (l.sc1)
+    hipLaunchKernelGGL((tsmm_kernel<T, true>), grid, dim3(256), 0, s, l.a, b.dev, b.done);
   else
-    hipLaunchKernelGGL((tsmm_kernel<T, false>), dim3(a.nwg0 + a.nwg1, slices), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((tsmm_kernel<T, false>), grid, dim3(256), 0, s, l.a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
+
+template <class T>
+void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStream_t s) {
+  enqueue_tsmm(make_tsmm(jobs, njobs, kcap, rcap), Batched<TsmmArgs<T>>(), s);
+}
+template TsmmLaunch<float> make_tsmm<float>(const TsmmJob<float>*, int, int, int);
+template TsmmLaunch<double> make_tsmm<double>(const TsmmJob<double>*, int, int, int);
+template void enqueue_tsmm<float>(const TsmmLaunch<float>&, Batched<TsmmArgs<float>>, hipStream_t);
+template void enqueue_tsmm<double>(const TsmmLaunch<double>&, Batched<TsmmArgs<double>>,
+                                   hipStream_t);
 template void launch_tsmm<float>(const TsmmJob<float>*, int, int, int, hipStream_t);
 template void launch_tsmm<double>(const TsmmJob<double>*, int, int, int, hipStream_t);
 

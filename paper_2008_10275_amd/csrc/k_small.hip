@@ -10,6 +10,11 @@
 
 namespace lrc {
 
+// Batched launches: item = blockIdx.z; a done item does nothing.
+#define LRC_ITEM(Type, name, a0, ab, done)        \
+  if ((done) && (done)[blockIdx.z]) return;        \
+  const Type& name = (ab) ? (ab)[blockIdx.z] : (a0);
+
 constexpr int SK = 128;                         // capacity of the small kernels
 constexpr int SKP = SK * (SK + 1) / 2;          // packed upper triangle
 
@@ -29,8 +34,12 @@ __device__ inline int pu(int i, int j, int k) {   // packed upper by rows, i <= 
 }
 
 constexpr int kCholThreads = 512;
-__global__ __launch_bounds__(kCholThreads) void chol_kernel(TruncState st, int pass, int kcap,
-                                                            double eps) {
+__global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const CholArgs* ab,
+                                                            const int* done) {
+  LRC_ITEM(CholArgs, ca, a0, ab, done)
+  const TruncState& st = ca.st;
+  const int pass = ca.pass, kcap = ca.kcap;
+  const double eps = ca.eps;
   __shared__ double Rp[SKP];
   __shared__ double Xp[SKP];
   __shared__ double Wt[(SK / 16) * 256];
@@ -176,41 +185,27 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(TruncState st, int p
   }
 }
 
-void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s) {
-  LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
+void enqueue_chol(const CholArgs& a, Batched<CholArgs> b, hipStream_t s) {
+  LRC_CHECK(a.kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
   ProfScope ps(kcls(K_CHOL, false), s);
-  hipLaunchKernelGGL(chol_kernel, dim3(2), dim3(kCholThreads), 0, s, st, pass, kcap, eps_gram);
+  hipLaunchKernelGGL(chol_kernel, dim3(2, 1, b.n), dim3(kCholThreads), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 
 // ============================================================== small products
 // C = op(A) diag(mid) op(B)[:, colperm] diag(colscale), all k x k (or k x r
 // output columns), fp64, ld kcap.  One 16 x 16 output tile per workgroup.
-struct SmallGemm {
-  const double* A;
-  const double* B;
-  double* C;
-  const int* colperm;        // optional
-  const double* colscale;    // optional (per output column)
-  const int* ncols_dev;      // optional: output columns (default k)
-  int transA, transB;
-  int use_core;              // mid = core coefficients
-  const int* rowperm;        // optional: output row i goes to row rowperm[i]
-  const int* inner_dev;      // optional: contraction length (default k)
-};
-
-struct SmallGemmArgs {
-  SmallGemm g[2];
-  CoreView core;
-  const int* k;
-  int kcap;
-};
-
-__global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a) {
+__global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a0, const SmallGemmArgs* ab,
+                                                         const int* done) {
   __shared__ double As[16][17];
   __shared__ double Bs[16][17];
   __shared__ double mid[SK];
-  const SmallGemm& g = a.g[blockIdx.z];
+  // blockIdx.z = item * 2 + job
+  const int item = blockIdx.z >> 1;
+  if (done && done[item]) return;
+  const SmallGemmArgs& a = ab ? ab[item] : a0;
+  if (int(blockIdx.z & 1) >= a.njobs) return;
+  const SmallGemm& g = a.g[blockIdx.z & 1];
   const int k = *a.k;
   const int ncols = g.ncols_dev ? *g.ncols_dev : k;
   const int kin = g.inner_dev ? *g.inner_dev : k;
@@ -253,17 +248,23 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a) {
   }
 }
 
-static void small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const int* k, int kcap,
-                       hipStream_t s) {
+SmallGemmArgs make_small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const int* k,
+                              int kcap) {
   SmallGemmArgs a;
   a.g[0] = jobs[0];
   a.g[1] = njobs > 1 ? jobs[1] : jobs[0];
   a.core = core;
   a.k = k;
   a.kcap = kcap;
-  const int t = (kcap + 15) / 16;
+  a.njobs = njobs;
+  return a;
+}
+
+void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStream_t s) {
+  const int t = (a.kcap + 15) / 16;
   ProfScope ps(kcls(K_SMALL_GEMM, false), s);
-  hipLaunchKernelGGL(small_gemm_kernel, dim3(t, t, njobs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(small_gemm_kernel, dim3(t, t, 2 * b.n), dim3(256), 0, s, a, b.dev, b.done);
+  LRC_HIP(hipGetLastError());
 }
 
 // ============================================================== Jacobi
@@ -286,7 +287,11 @@ __device__ inline int rr_player(int pos, int t, int kp) {
 constexpr int kJL = SK + 1;
 constexpr int kJFuse = 88;
 constexpr int kJacThreads = 1024;
-__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(TruncState st, int kcap, int max_rounds) {
+__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const JacArgs* ab,
+                                                            const int* done) {
+  LRC_ITEM(JacArgs, ja_, a0, ab, done)
+  const TruncState& st = ja_.st;
+  const int kcap = ja_.kcap, max_rounds = ja_.max_rounds;
   __shared__ double Ls[SK * kJL];
   __shared__ double2 csw[kJacThreads / 64][SK / 2];
   __shared__ short2 pqw[kJacThreads / 64][SK / 2];
@@ -411,7 +416,11 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(TruncState st, int 
 // rotation log is staged through LDS in batches of kRepBatch rounds.
 constexpr int kRepRows = 4;
 constexpr int kRepBatch = 16;
-__global__ __launch_bounds__(64) void jacobi_replay_kernel(TruncState st, int kcap) {
+__global__ __launch_bounds__(64) void jacobi_replay_kernel(RepArgs a0, const RepArgs* ab,
+                                                           const int* done) {
+  LRC_ITEM(RepArgs, ra_, a0, ab, done)
+  const TruncState& st = ra_.st;
+  const int kcap = ra_.kcap;
   __shared__ double row[kRepRows][SK];
   __shared__ double2 rb[kRepBatch][SK / 2];
   const int k = *st.kj;
@@ -455,10 +464,10 @@ __global__ __launch_bounds__(64) void jacobi_replay_kernel(TruncState st, int kc
   }
 }
 
-void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s) {
+void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s) {
   ProfScope ps(kcls(K_REPLAY, false), s);
-  hipLaunchKernelGGL(jacobi_replay_kernel, dim3((kcap + kRepRows - 1) / kRepRows), dim3(64), 0, s,
-                     st, kcap);
+  hipLaunchKernelGGL(jacobi_replay_kernel, dim3((a.kcap + kRepRows - 1) / kRepRows, 1, b.n),
+                     dim3(64), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 
@@ -478,7 +487,12 @@ void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s) {
 // step.  Outputs: R (kj x k, upper trapezoidal in pivot order, zero rows below
 // kj) in st.W, R R^T (kj x kj) in st.H, the pivot order in st.piv, kj in st.kj.
 constexpr int kPivThreads = 1024;
-__global__ __launch_bounds__(kPivThreads) void pivchol_kernel(TruncState st, int kcap, double tol) {
+__global__ __launch_bounds__(kPivThreads) void pivchol_kernel(PivArgs a0, const PivArgs* ab,
+                                                              const int* done) {
+  LRC_ITEM(PivArgs, pa_, a0, ab, done)
+  const TruncState& st = pa_.st;
+  const int kcap = pa_.kcap;
+  const double tol = pa_.tol;
   __shared__ double A[SK * kJL];
   __shared__ double dg[SK];
   __shared__ int pos[SK];
@@ -581,37 +595,58 @@ __global__ __launch_bounds__(kPivThreads) void pivchol_kernel(TruncState st, int
 // R_A = R2_A R1_A, R_B = R2_B R1_B;  M = R_A diag(core) R_B^T;  H = M^T M;
 // pivoted Cholesky of H, then the Jacobi rounds on R R^T.  Scratch: R1
 // buffers are overwritten by R_A, R_B; H by R R^T.
-void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, double tol,
-                        hipStream_t s) {
-  LRC_CHECK(kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
-  // R_A, R_B into the G buffers (the Grams are no longer needed)
-  SmallGemm j2[2];
-  for (int x = 0; x < 2; ++x) {
-    j2[x] = SmallGemm{st.R2[x], st.R1[x], st.G[x], nullptr, nullptr, nullptr, 0, 0, 0};
-  }
-  small_gemm(j2, 2, core, st.k, kcap, s);
-  // M = R_A diag(core) R_B^T
-  SmallGemm jm{st.G[0], st.G[1], st.M, nullptr, nullptr, nullptr, 0, 1, 1};
-  small_gemm(&jm, 1, core, st.k, kcap, s);
-  // H = M^T M
-  SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
-  small_gemm(&jh, 1, core, st.k, kcap, s);
-  {
-    ProfScope ps(kcls(K_PIVCHOL, false), s);
-    hipLaunchKernelGGL(pivchol_kernel, dim3(1), dim3(kPivThreads), 0, s, st, kcap, tol);
-  }
-  ProfScope ps(kcls(K_JACOBI, false), s);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacThreads), 0, s, st, kcap, max_rounds);
+void enqueue_pivchol(const PivArgs& a, Batched<PivArgs> b, hipStream_t s) {
+  LRC_CHECK(a.kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
+  ProfScope ps(kcls(K_PIVCHOL, false), s);
+  hipLaunchKernelGGL(pivchol_kernel, dim3(1, 1, b.n), dim3(kPivThreads), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
+}
+
+void enqueue_jacobi(const JacArgs& a, Batched<JacArgs> b, hipStream_t s) {
+  ProfScope ps(kcls(K_JACOBI, false), s);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1, 1, b.n), dim3(kJacThreads), 0, s, a, b.dev, b.done);
+  LRC_HIP(hipGetLastError());
+}
+
+// R_A = R2_A R1_A, R_B = R2_B R1_B (into the G buffers); M = R_A diag(core) R_B^T; H = M^T M
+void make_core_gemms(const TruncState& st, const CoreView& core, int kcap, SmallGemmArgs* out) {
+  SmallGemm j2[2];
+  for (int x = 0; x < 2; ++x) j2[x] = SmallGemm{st.R2[x], st.R1[x], st.G[x], nullptr, nullptr, nullptr, 0, 0, 0};
+  out[0] = make_small_gemm(j2, 2, core, st.k, kcap);
+  SmallGemm jm{st.G[0], st.G[1], st.M, nullptr, nullptr, nullptr, 0, 1, 1};
+  out[1] = make_small_gemm(&jm, 1, core, st.k, kcap);
+  SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
+  out[2] = make_small_gemm(&jh, 1, core, st.k, kcap);
+}
+
+// VP = Pi R^T Y, W = M VP; after the selection XA = R2i_A W[:, order] diag(1 / ||W_j||),
+// XB = R2i_B VP[:, order] diag(1 / ||VP_j||)
+void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, SmallGemmArgs* out) {
+  CoreView none{};
+  none.nb = 0;
+  SmallGemm jv{st.W, st.VM, st.VP, nullptr, nullptr, st.kj, 1, 0, 0, st.piv, st.kj};
+  out[0] = make_small_gemm(&jv, 1, none, st.k, kcap);
+  SmallGemm jw{st.M, st.VP, st.W, nullptr, nullptr, st.kj, 0, 0, 0};
+  out[1] = make_small_gemm(&jw, 1, none, st.k, kcap);
+  SmallGemm jx[2];
+  jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, st.invsig, rank_out, 0, 0, 0};
+  jx[1] = SmallGemm{st.R2i[1], st.VP, st.XB, st.order, st.invnu, rank_out, 0, 0, 0};
+  out[2] = make_small_gemm(jx, 2, none, st.k, kcap);
 }
 
 // ============================================================== rank selection
 // W = M V (columns: M v_j = sigma_j u_j); sigma_j = ||W[:, j]||; order by
 // decreasing sigma; r' = min(cap, smallest r with tail <= tol * ||sigma||).
 // Then XA = R2i_A * W[:, order] diag(1/sigma), XB = R2i_B * V[:, order].
-__global__ __launch_bounds__(256) void select_kernel(TruncState st, int kcap, int rank_cap,
-                                                     double tol, double* s_out, int* rank_out,
-                                                     double* norm_out) {
+__global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* ab,
+                                                     const int* done) {
+  LRC_ITEM(SelArgs, sa_, a0, ab, done)
+  const TruncState& st = sa_.st;
+  const int kcap = sa_.kcap, rank_cap = sa_.rank_cap;
+  const double tol = sa_.tol;
+  double* s_out = sa_.s_out;
+  int* rank_out = sa_.rank_out;
+  double* norm_out = sa_.norm_out;
   __shared__ double sig[SK];
   __shared__ double srt[SK];
   __shared__ int ord[SK];
@@ -687,25 +722,9 @@ __global__ __launch_bounds__(256) void select_kernel(TruncState st, int kcap, in
   }
 }
 
-void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, double* s_out,
-                         int* rank_out, double* norm_out, hipStream_t s) {
-  CoreView none{};
-  none.nb = 0;
-  // VP = Pi R^T Y (k x kj), then W = M VP
-  SmallGemm jv{st.W, st.VM, st.VP, nullptr, nullptr, st.kj, 1, 0, 0, st.piv, st.kj};
-  small_gemm(&jv, 1, none, st.k, kcap, s);
-  SmallGemm jw{st.M, st.VP, st.W, nullptr, nullptr, st.kj, 0, 0, 0};
-  small_gemm(&jw, 1, none, st.k, kcap, s);
-  {
-    ProfScope ps(kcls(K_SELECT, false), s);
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, st, kcap, rank_cap, tol, s_out,
-                       rank_out, norm_out);
-  }
-  // XA = R2i_A W[:, order] diag(1 / ||W_j||),  XB = R2i_B VP[:, order] diag(1 / ||VP_j||)
-  SmallGemm jx[2];
-  jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, st.invsig, rank_out, 0, 0, 0};
-  jx[1] = SmallGemm{st.R2i[1], st.VP, st.XB, st.order, st.invnu, rank_out, 0, 0, 0};
-  small_gemm(jx, 2, none, st.k, kcap, s);
+void enqueue_select(const SelArgs& a, Batched<SelArgs> b, hipStream_t s) {
+  ProfScope ps(kcls(K_SELECT, false), s);
+  hipLaunchKernelGGL(select_kernel, dim3(1, 1, b.n), dim3(256), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 

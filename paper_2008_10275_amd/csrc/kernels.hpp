@@ -4,8 +4,19 @@
 // to synchronise to size a launch: grids are sized by capacities.
 #pragma once
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace lrc {
+
+// Batched launches: `dev` holds one argument struct per item (blockIdx.z), and
+// items whose `done` flag is set do nothing.  dev == nullptr: a single item
+// with the by-value arguments.
+template <class A>
+struct Batched {
+  const A* dev = nullptr;
+  const int* done = nullptr;
+  int n = 1;
+};
 
 // ----------------------------------------------------------------- sparse
 // One CSR operator on the device (int32 row pointers and columns).
@@ -81,6 +92,41 @@ struct GramJob {
 template <class T>
 void launch_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial,
                  size_t ws_bytes, int* info, hipStream_t s);
+template <class T>
+struct GramArgs {
+  BlockView<T> X[2];
+  int64_t rows[2];
+  int nwg0;          // workgroups of job 0; the rest belong to job 1
+  int nwg1;
+  T* partial;        // one partial per workgroup
+};
+template <class T>
+struct GramRedArgs {
+  GramArgs<T> g;
+  double* G0;
+  double* G1;
+  int kcap;
+  int* k0;
+  int* k1;
+  int* info;
+};
+// Host-built arguments of one Gram launch pair (partials, reduction).
+template <class T>
+struct GramLaunch {
+  GramArgs<T> g;
+  GramRedArgs<T> r;
+  int njobs = 1;
+  int grid = 0;      // partial workgroups
+  int kb = 0;        // host bound of the width (selects the tile class)
+  bool sc1 = false;  // second operand row-scaled
+  Work work;
+};
+template <class T>
+GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_partial,
+                        size_t ws_bytes, int* info);
+template <class T>
+void enqueue_gram(const GramLaunch<T>& l, Batched<GramArgs<T>> bg, Batched<GramRedArgs<T>> br,
+                  hipStream_t s);
 size_t gram_workspace_bytes(int64_t rows_a, int64_t rows_b, int kcap, bool fp64);
 
 // Y = X * M  with X a block view (rows x k), M (k x r) fp64 row-major with ld kcapM,
@@ -97,6 +143,23 @@ struct TsmmJob {
 };
 template <class T>
 void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStream_t s);
+template <class T>
+struct TsmmArgs {
+  TsmmJob<T> job[2];
+  int nwg0, nwg1;
+};
+template <class T>
+struct TsmmLaunch {
+  TsmmArgs<T> a;
+  int grid = 0;
+  int slices = 0;
+  bool sc1 = false;
+  Work work;
+};
+template <class T>
+TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap);
+template <class T>
+void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s);
 
 // ----------------------------------------------------------------- small fp64 (one workgroup)
 // State of one truncation on the device (all k x k blocks have ld = kcap).
@@ -125,12 +188,69 @@ struct TruncState {
   int* info;         // bit 0: shifted Cholesky, 1: breakdown, 2: Jacobi not converged, 3: capacity
 };
 
-void launch_chol(TruncState st, int pass, int kcap, double eps_gram, hipStream_t s);
-void launch_core_jacobi(TruncState st, CoreView core, int kcap, int max_rounds, double tol,
-                        hipStream_t s);
-void launch_jacobi_replay(TruncState st, int kcap, hipStream_t s);
-void launch_trunc_finish(TruncState st, int kcap, int rank_cap, double tol, double* s_out,
-                         int* rank_out, double* norm_out, hipStream_t s);
+struct CholArgs {
+  TruncState st;
+  int pass;
+  int kcap;
+  double eps;
+};
+struct PivArgs {
+  TruncState st;
+  int kcap;
+  double tol;
+};
+struct JacArgs {
+  TruncState st;
+  int kcap;
+  int max_rounds;
+};
+struct RepArgs {
+  TruncState st;
+  int kcap;
+};
+struct SelArgs {
+  TruncState st;
+  int kcap;
+  int rank_cap;
+  double tol;
+  double* s_out;
+  int* rank_out;
+  double* norm_out;
+};
+// C = op(A) diag(mid) op(B)[:, colperm] diag(colscale), all k x k (or k x r
+// output columns), fp64, ld kcap.
+struct SmallGemm {
+  const double* A;
+  const double* B;
+  double* C;
+  const int* colperm;        // optional
+  const double* colscale;    // optional (per output column)
+  const int* ncols_dev;      // optional: output columns (default k)
+  int transA, transB;
+  int use_core;              // mid = core coefficients
+  const int* rowperm;        // optional: output row i goes to row rowperm[i]
+  const int* inner_dev;      // optional: contraction length (default k)
+};
+struct SmallGemmArgs {
+  SmallGemm g[2];
+  CoreView core;
+  const int* k;
+  int kcap;
+  int njobs;
+};
+
+void enqueue_chol(const CholArgs& a, Batched<CholArgs> b, hipStream_t s);
+void enqueue_pivchol(const PivArgs& a, Batched<PivArgs> b, hipStream_t s);
+void enqueue_jacobi(const JacArgs& a, Batched<JacArgs> b, hipStream_t s);
+void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s);
+void enqueue_select(const SelArgs& a, Batched<SelArgs> b, hipStream_t s);
+SmallGemmArgs make_small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const int* k,
+                              int kcap);
+void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStream_t s);
+// the three products before the eigen-decomposition (R_A R_B, M, H) and the
+// three after it (VP, W, XA / XB)
+void make_core_gemms(const TruncState& st, const CoreView& core, int kcap, SmallGemmArgs* out);
+void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, SmallGemmArgs* out);
 
 // ----------------------------------------------------------------- residual (fp64)
 // Per-column squared norms of  R = A B^T  (A: n x K view, B: m x K view scaled by

@@ -141,32 +141,163 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
 }
 
 template <class T>
-void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
-                       const CoreView& core, int rank_cap, double tol, T* Uout, int ldu,
-                       T* Vout, int ldv, double* s_out, int* rank_out, double* norm_out,
-                       hipStream_t s) {
+TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockView<T>& B,
+                                int64_t m, const CoreView& core, int rank_cap, double tol,
+                                T* Uout, int ldu, T* Vout, int ldv, double* s_out, int* rank_out,
+                                double* norm_out) const {
   LRC_CHECK(n <= nmax && m <= mmax, ST_EINVAL, "truncation workspace too small");
   LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
             "truncation: rank cap must be in [1, 64] and fit the output leading dimensions");
   const double eps = sizeof(T) == 8 ? 1e-14 : 1e-6;
   T* qa = Q1A.as<T>();
   T* qb = Q1B.as<T>();
+  TruncPlan<T> p;
   GramJob<T> g1[2] = {{A, n, st.G[0], st.k}, {B, m, st.G[1], nullptr}};
-  launch_gram<T>(g1, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info, s);
-  launch_chol(st, 1, kcap, eps, s);
+  p.g1 = make_gram<T>(g1, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
+  p.c1 = CholArgs{st, 1, kcap, eps};
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
-  launch_tsmm<T>(t1, 2, kcap, kcap, s);
+  p.t1 = make_tsmm<T>(t1, 2, kcap, kcap);
   BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
   va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
-  launch_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info, s);
-  launch_chol(st, 2, kcap, eps, s);
-  launch_core_jacobi(st, core, kcap, max_rounds, tol, s);
-  launch_jacobi_replay(st, kcap, s);
-  launch_trunc_finish(st, kcap, rank_cap, tol, s_out, rank_out, norm_out, s);
+  p.g2 = make_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
+  p.c2 = CholArgs{st, 2, kcap, eps};
+  make_core_gemms(st, core, kcap, p.core);
+  p.piv = PivArgs{st, kcap, tol};
+  p.jac = JacArgs{st, kcap, max_rounds};
+  p.rep = RepArgs{st, kcap};
+  SmallGemmArgs fin[3];
+  make_finish_gemms(st, kcap, rank_out, fin);
+  p.fin[0] = fin[0];
+  p.fin[1] = fin[1];
+  p.xab = fin[2];
+  p.sel = SelArgs{st, kcap, rank_cap, tol, s_out, rank_out, norm_out};
   TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
                       {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
-  launch_tsmm<T>(t2, 2, kcap, rank_cap, s);
+  p.t2 = make_tsmm<T>(t2, 2, kcap, rank_cap);
+  return p;
+}
+
+template <class T>
+void enqueue_trunc(const TruncPlan<T>& p, const TruncBatch<T>& b, hipStream_t s) {
+  enqueue_gram(p.g1, b.g1, b.r1, s);
+  enqueue_chol(p.c1, b.c1, s);
+  enqueue_tsmm(p.t1, b.t1, s);
+  enqueue_gram(p.g2, b.g2, b.r2, s);
+  enqueue_chol(p.c2, b.c2, s);
+  for (int i = 0; i < 3; ++i) enqueue_small_gemm(p.core[i], b.core[i], s);
+  enqueue_pivchol(p.piv, b.piv, s);
+  enqueue_jacobi(p.jac, b.jac, s);
+  enqueue_replay(p.rep, b.rep, s);
+  for (int i = 0; i < 2; ++i) enqueue_small_gemm(p.fin[i], b.fin[i], s);
+  enqueue_select(p.sel, b.sel, s);
+  enqueue_small_gemm(p.xab, b.xab, s);
+  enqueue_tsmm(p.t2, b.t2, s);
+}
+
+template <class T>
+static void merge_gram(GramLaunch<T>& a, const GramLaunch<T>& b) {
+  LRC_CHECK(a.sc1 == b.sc1 && a.njobs == b.njobs, ST_EINVAL,
+            "batched truncation: items differ in operand structure");
+  a.grid = std::max(a.grid, b.grid);
+  a.kb = std::max(a.kb, b.kb);
+}
+template <class T>
+static void merge_tsmm(TsmmLaunch<T>& a, const TsmmLaunch<T>& b) {
+  LRC_CHECK(a.sc1 == b.sc1, ST_EINVAL, "batched truncation: items differ in operand structure");
+  a.grid = std::max(a.grid, b.grid);
+  a.slices = std::max(a.slices, b.slices);
+}
+
+template <class T>
+TruncPlan<T> merge_plans(const std::vector<TruncPlan<T>>& v) {
+  LRC_CHECK(!v.empty(), ST_EINVAL, "batched truncation: no items");
+  TruncPlan<T> p = v[0];
+  for (size_t i = 1; i < v.size(); ++i) {
+    merge_gram(p.g1, v[i].g1);
+    merge_gram(p.g2, v[i].g2);
+    merge_tsmm(p.t1, v[i].t1);
+    merge_tsmm(p.t2, v[i].t2);
+    for (int j = 0; j < 3; ++j)
+      LRC_CHECK(p.core[j].njobs == v[i].core[j].njobs, ST_EINVAL, "batched truncation: jobs differ");
+  }
+  return p;
+}
+
+// Appends one launch's per-item arguments (256-byte aligned) to the host image
+// of the argument buffer whose device base is `base`.
+template <class A, class Get>
+static Batched<A> put(std::vector<unsigned char>& h, size_t& off, size_t nb, const int* done,
+                      const char* base, Get get) {
+  off = (off + 255) / 256 * 256;
+  const size_t at = off;
+  off += nb * sizeof(A);
+  if (h.size() < off) h.resize(off);
+  for (size_t i = 0; i < nb; ++i) {
+    const A& a = get(i);
+    std::memcpy(h.data() + at + i * sizeof(A), &a, sizeof(A));
+  }
+  Batched<A> b;
+  b.dev = reinterpret_cast<const A*>(base + at);
+  b.done = done;
+  b.n = int(nb);
+  return b;
+}
+
+template <class T>
+TruncBatch<T> upload_plans(const std::vector<TruncPlan<T>>& v, const int* done, DevBuf& buf,
+                           hipStream_t s) {
+  const size_t nb = v.size();
+  const size_t per = sizeof(GramArgs<T>) * 2 + sizeof(GramRedArgs<T>) * 2 + sizeof(CholArgs) * 2 +
+                     sizeof(TsmmArgs<T>) * 2 + sizeof(SmallGemmArgs) * 6 + sizeof(PivArgs) +
+                     sizeof(JacArgs) + sizeof(RepArgs) + sizeof(SelArgs);
+  const size_t need = nb * per + 20 * 256;
+  if (buf.bytes < need) buf.alloc(need);
+  const char* base = reinterpret_cast<const char*>(buf.p);
+  std::vector<unsigned char> h;
+  size_t off = 0;
+  TruncBatch<T> b;
+#define LRC_PUT(field, expr, type) \
+  b.field = put<type>(h, off, nb, done, base, [&](size_t i) -> const type& { return v[i].expr; })
+  LRC_PUT(g1, g1.g, GramArgs<T>);
+  LRC_PUT(r1, g1.r, GramRedArgs<T>);
+  LRC_PUT(c1, c1, CholArgs);
+  LRC_PUT(t1, t1.a, TsmmArgs<T>);
+  LRC_PUT(g2, g2.g, GramArgs<T>);
+  LRC_PUT(r2, g2.r, GramRedArgs<T>);
+  LRC_PUT(c2, c2, CholArgs);
+  for (int j = 0; j < 3; ++j) LRC_PUT(core[j], core[j], SmallGemmArgs);
+  LRC_PUT(piv, piv, PivArgs);
+  LRC_PUT(jac, jac, JacArgs);
+  LRC_PUT(rep, rep, RepArgs);
+  for (int j = 0; j < 2; ++j) LRC_PUT(fin[j], fin[j], SmallGemmArgs);
+  LRC_PUT(sel, sel, SelArgs);
+  LRC_PUT(xab, xab, SmallGemmArgs);
+  LRC_PUT(t2, t2.a, TsmmArgs<T>);
+#undef LRC_PUT
+  LRC_CHECK(off <= buf.bytes, ST_EINVAL, "batched truncation: argument buffer layout");
+  LRC_HIP(hipMemcpyAsync(buf.p, h.data(), off, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipStreamSynchronize(s));   // h is a temporary
+  return b;
+}
+
+template void enqueue_trunc<double>(const TruncPlan<double>&, const TruncBatch<double>&, hipStream_t);
+template void enqueue_trunc<float>(const TruncPlan<float>&, const TruncBatch<float>&, hipStream_t);
+template TruncPlan<double> merge_plans<double>(const std::vector<TruncPlan<double>>&);
+template TruncPlan<float> merge_plans<float>(const std::vector<TruncPlan<float>>&);
+template TruncBatch<double> upload_plans<double>(const std::vector<TruncPlan<double>>&, const int*,
+                                                 DevBuf&, hipStream_t);
+template TruncBatch<float> upload_plans<float>(const std::vector<TruncPlan<float>>&, const int*,
+                                               DevBuf&, hipStream_t);
+
+template <class T>
+void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
+                       const CoreView& core, int rank_cap, double tol, T* Uout, int ldu,
+                       T* Vout, int ldv, double* s_out, int* rank_out, double* norm_out,
+                       hipStream_t s) {
+  enqueue_trunc(plan(A, n, B, m, core, rank_cap, tol, Uout, ldu, Vout, ldv, s_out, rank_out,
+                     norm_out),
+                TruncBatch<T>(), s);
   if (log_enabled()) {
     int hk[5] = {0, 0, 0, 0, 0};
     double hn = 0.0;

@@ -65,6 +65,48 @@ struct LR {
   int* r() const { return rank.as<int>(); }
 };
 
+// Host-built arguments of every launch of one truncation, in launch order.
+template <class T>
+struct TruncPlan {
+  GramLaunch<T> g1;
+  CholArgs c1;
+  TsmmLaunch<T> t1;
+  GramLaunch<T> g2;
+  CholArgs c2;
+  SmallGemmArgs core[3];
+  PivArgs piv;
+  JacArgs jac;
+  RepArgs rep;
+  SmallGemmArgs fin[2];
+  SelArgs sel;
+  SmallGemmArgs xab;
+  TsmmLaunch<T> t2;
+};
+// Per-item device copies of a batch of plans, one array per launch.  All
+// default (dev == nullptr): the single truncation of the plan itself.
+template <class T>
+struct TruncBatch {
+  Batched<GramArgs<T>> g1, g2;
+  Batched<GramRedArgs<T>> r1, r2;
+  Batched<CholArgs> c1, c2;
+  Batched<TsmmArgs<T>> t1, t2;
+  Batched<SmallGemmArgs> core[3], fin[2], xab;
+  Batched<PivArgs> piv;
+  Batched<JacArgs> jac;
+  Batched<RepArgs> rep;
+  Batched<SelArgs> sel;
+};
+template <class T>
+void enqueue_trunc(const TruncPlan<T>& p, const TruncBatch<T>& b, hipStream_t s);
+// The launch shape of a batch: every grid covers the largest item.
+template <class T>
+TruncPlan<T> merge_plans(const std::vector<TruncPlan<T>>& v);
+// Uploads the per-item arguments into `buf` (reallocated when too small) and
+// returns the batch view with the given per-item done flags.
+template <class T>
+TruncBatch<T> upload_plans(const std::vector<TruncPlan<T>>& v, const int* done, DevBuf& buf,
+                           hipStream_t s);
+
 // Workspace + state of the truncation T_{R,eps}(A diag(c) B^T).
 template <class T>
 struct Truncator {
@@ -78,6 +120,9 @@ struct Truncator {
   void run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
            const CoreView& core, int rank_cap, double tol, T* Uout, int ldu, T* Vout, int ldv,
            double* s_out, int* rank_out, double* norm_out, hipStream_t s);
+  TruncPlan<T> plan(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
+                    const CoreView& core, int rank_cap, double tol, T* Uout, int ldu, T* Vout,
+                    int ldv, double* s_out, int* rank_out, double* norm_out) const;
 };
 
 struct Prob;
