@@ -85,6 +85,7 @@ typedef struct {
   double seconds_setup;  /* factorisation of the preconditioner (host + upload)  */
   double seconds_solve;  /* lrc_solve wall time                                  */
   int info_flags;        /* bit 0: shifted Cholesky used; bit 1: breakdown; bit 2: eigen not converged */
+  int status;            /* this problem's outcome: LRC_OK or LRC_ENOTCONV       */
 } lrc_info;
 
 /* Default options (rank cap 20, tol 1e-8, res_tol 1e-8, restart 6, fp64). */
@@ -146,6 +147,20 @@ lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* 
  * S with L(S) = F - L(X0) is computed by ChebyshevT.  info may be NULL. */
 lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0,
                      const double* s0, const double* V0, lrc_info* info);
+/* Batched solve of K preconditioned problems of one context (Algorithm 1
+ * treats the parameter subsets independently, so their Newton steps can run
+ * together).  Same options and results as K calls of lrc_solve with
+ * opts->init LRC_INIT_MEDIAN or LRC_INIT_ZERO (LRC_INIT_GIVEN is refused);
+ * opts->restart must be in [1, 64]: one restart cycle of the ChebyshevT
+ * recurrence for all problems is captured once as a HIP graph and replayed
+ * until every problem has converged or stopped, each step being one launch
+ * over all problems, with finished problems skipped on the device.  Problems
+ * may differ in m, F, the operator values and the preconditioner; problems
+ * whose factorisations share one supernode structure (same sparsity pattern)
+ * share each preconditioner launch as well.  infos (K entries, may be NULL)
+ * receives per-problem results, infos[k].status its outcome.  Returns the
+ * worst per-problem status, or an error (nothing solved) for invalid input. */
+lrc_status lrc_solve_batched(lrc_prob* probs, int K, const lrc_opts* opts, lrc_info* infos);
 /* Solution X = [U0 | U] diag([s0, s]) [V0 | V]^T as host arrays (column-major):
  * pass NULL pointers to query *rank (total columns).  U: n x rank, V: m x rank. */
 lrc_status lrc_get_solution(lrc_prob prob, int* rank, double* U, double* s, double* V);

@@ -21,8 +21,8 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Wno-unused-result"]
 HOST_FLAGS = ["-O3", "-mavx2", "-mfma", "-fopenmp", "-fPIC", "-std=c++17"]
 
-HIP_SOURCES = ["k_sparse.hip", "k_dense.hip", "k_small.hip", "k_mlp.hip", "solver.cpp", "capi.cpp",
-               "prof.cpp"]
+HIP_SOURCES = ["k_sparse.hip", "k_dense.hip", "k_small.hip", "k_mlp.hip", "solver.cpp", "batch.cpp",
+               "capi.cpp", "prof.cpp"]
 HOST_SOURCES = ["host/ndfact.cpp"]
 
 

@@ -628,6 +628,29 @@ lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* 
   });
 }
 
+lrc_status lrc_solve_batched(lrc_prob* probs, int K, const lrc_opts* opts, lrc_info* infos) {
+  if (!probs || K < 1 || !opts) return LRC_EINVAL;
+  for (int k = 0; k < K; ++k)
+    if (!probs[k]) return LRC_EINVAL;
+  Ctx* cx = probs[0]->p.ctx;
+  return guarded(cx, [&]() -> lrc_status {
+    LRC_HIP(hipSetDevice(cx->device));
+    LRC_CHECK(opts->init != LRC_INIT_GIVEN, ST_EINVAL,
+              "lrc_solve_batched: LRC_INIT_GIVEN is not supported (use lrc_solve)");
+    std::vector<Prob*> ps(K);
+    for (int k = 0; k < K; ++k) ps[k] = &probs[k]->p;
+    std::vector<lrc_info> inf(K);
+    const auto st = solve_batched(ps, *opts, inf.data());
+    lrc_status worst = LRC_OK;
+    for (int k = 0; k < K; ++k) {
+      inf[k].status = st[k];
+      worst = std::max(worst, lrc_status(st[k]));
+      if (infos) infos[k] = inf[k];
+    }
+    return worst;
+  });
+}
+
 lrc_status lrc_get_solution(lrc_prob prob, int* rank, double* U, double* s, double* V) {
   if (!prob || !rank) return LRC_EINVAL;
   Prob& P = prob->p;

@@ -728,4 +728,40 @@ void enqueue_select(const SelArgs& a, Batched<SelArgs> b, hipStream_t s) {
   LRC_HIP(hipGetLastError());
 }
 
+// ============================================================== batch control
+__global__ __launch_bounds__(64) void batch_check_kernel(BCtl* __restrict__ ctl,
+                                                        int* __restrict__ done, int nb,
+                                                        int after_update) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb || done[j]) return;
+  BCtl c = ctl[j];
+  const double nr = *c.norm;
+  c.last = nr;
+  if (after_update) {
+    ++c.iters;
+    if (nr < 0.7 * c.best) {
+      c.best = nr;
+      c.stall = 0;
+    } else {
+      c.best = fmin(c.best, nr);
+      ++c.stall;
+    }
+  } else {
+    c.best = nr;
+    c.stall = 0;
+  }
+  if (!isfinite(nr)) c.state = 2;
+  else if (nr <= c.target) c.state = 1;
+  else if (c.iters >= c.max_iter || c.stall >= c.stall_limit) c.state = 2;
+  ctl[j] = c;
+  if (c.state) done[j] = 1;
+}
+
+void launch_batch_check(BCtl* ctl, int* done, int nb, int after_update, hipStream_t s) {
+  ProfScope ps(K_VECTOR * 2, s);
+  hipLaunchKernelGGL(batch_check_kernel, dim3(unsigned(ceil_div(nb, 64))), dim3(64), 0, s, ctl,
+                     done, nb, after_update);
+  LRC_HIP(hipGetLastError());
+}
+
 }  // namespace lrc

@@ -9,23 +9,21 @@
 namespace lrc {
 
 // ============================================================== SpMM
-template <class T>
-struct SpmmArgs {
-  DevCsr<T> op[kMaxOps];
-  T* W[kMaxOps];
-};
-
 // Every row of K_i is handled by `lpr` consecutive lanes; each lane owns CPL
 // consecutive columns of the factor.  Rows of U are contiguous (row-major), so
 // each nonzero K_i(row, j) costs one coalesced read of row j of U.  The grid's
 // y dimension runs over the q operators that share U.
 template <class T, int CPL>
-__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> args, const T* __restrict__ U,
-                                                   int ldu, const int* __restrict__ r_dev,
-                                                   int r_const, int lpr, int ldw) {
+__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
+                                                   const int* done, int lpr) {
+  if (done && done[blockIdx.z]) return;
+  const SpmmArgs<T>& args = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.y) >= args.q) return;
   const DevCsr<T> K = args.op[blockIdx.y];
   T* __restrict__ W = args.W[blockIdx.y];
-  const int r = r_dev ? *r_dev : r_const;
+  const T* __restrict__ U = args.U;
+  const int ldu = args.ldu, ldw = args.ldw;
+  const int r = args.r_dev ? *args.r_dev : args.r_const;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rpw = 64 / lpr;                       // rows per wave
@@ -59,58 +57,80 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> args, const T* __
 }
 
 template <class T>
-void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev, int r_const,
-                 int rcap, T* const* W, int ldw, int cpl, hipStream_t s) {
+SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
+                        int r_const, int rcap, T* const* W, int ldw, int cpl) {
   LRC_CHECK(q >= 1 && q <= kMaxOps, ST_EINVAL, "spmm: bad operator count");
   LRC_CHECK(rcap >= 1, ST_EINVAL, "spmm: rank capacity must be positive");
   LRC_CHECK(ldu % 8 == 0 && ldw % 8 == 0 && ldu >= rcap && ldw >= rcap, ST_EINVAL,
             "spmm: leading dimensions must be multiples of 8 and cover the rank capacity");
+  LRC_CHECK(cpl == 2 || cpl == 4 || cpl == 8, ST_EINVAL, "spmm: columns per lane must be 2, 4 or 8");
   const int lpr = int(ceil_div(rcap, cpl));
   LRC_CHECK(lpr <= 64, ST_EINVAL, "spmm: rank capacity too large for the lane mapping");
-  SpmmArgs<T> a;
+  SpmmLaunch<T> l;
+  SpmmArgs<T>& a = l.a;
   int64_t n = 0;
   for (int i = 0; i < q; ++i) {
     a.op[i] = ops[i];
     a.W[i] = W[i];
     n = std::max(n, ops[i].n);
   }
+  a.q = q;
+  a.U = U;
+  a.ldu = ldu;
+  a.r_dev = r_dev;
+  a.r_const = r_const;
+  a.ldw = ldw;
+  l.cpl = cpl;
+  l.lpr = lpr;
   const int rpw = 64 / lpr;
   const int64_t rows_per_block = int64_t(rpw) * 4;
-  const int64_t blocks = std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32);
-  dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(q));
+  l.blocks = int(std::max<int64_t>(std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32), 1));
+  l.q = q;
   // algorithmic bytes: values + int32 columns + row pointers of every operator,
   // U read once, every W_i written (all n rows)
-  Work w;
-  {
-    double fixed = 0.0, wrows = 0.0;
-    for (int i = 0; i < q; ++i) {
-      fixed += double(ops[i].nnz) * (sizeof(T) + 4) + double(ops[i].n + 1) * 4;
-      wrows += double(ops[i].n);
-    }
-    const double nr = double(n);
-    w.groups = {{{r_dev, r_const}}};
-    w.f = [=](const std::vector<double>& v) { return fixed + (nr + wrows) * v[0] * sizeof(T); };
+  double fixed = 0.0, wrows = 0.0;
+  for (int i = 0; i < q; ++i) {
+    fixed += double(ops[i].nnz) * (sizeof(T) + 4) + double(ops[i].n + 1) * 4;
+    wrows += double(ops[i].n);
   }
-  ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, w);
-  switch (cpl) {
+  const double nr = double(n);
+  l.work.groups = {{{r_dev, r_const}}};
+  l.work.f = [=](const std::vector<double>& v) { return fixed + (nr + wrows) * v[0] * sizeof(T); };
+  return l;
+}
+
+template <class T>
+void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s) {
+  ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, b.dev ? Work() : l.work);
+  const dim3 grid(unsigned(l.blocks), unsigned(l.q), unsigned(b.n));
+  switch (l.cpl) {
     case 2:
-      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
-                         lpr, ldw);
+      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
       break;
     case 4:
-      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
-                         lpr, ldw);
-      break;
-    case 8:
-      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, dim3(256), 0, s, a, U, ldu, r_dev, r_const,
-                         lpr, ldw);
+      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
       break;
     default:
-      throw Error(ST_EINVAL, "spmm: columns per lane must be 2, 4 or 8");
+      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
+      break;
   }
   LRC_HIP(hipGetLastError());
 }
 
+template <class T>
+void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev, int r_const,
+                 int rcap, T* const* W, int ldw, int cpl, hipStream_t s) {
+  enqueue_spmm(make_spmm(ops, q, U, ldu, r_dev, r_const, rcap, W, ldw, cpl), Batched<SpmmArgs<T>>(),
+               s);
+}
+
+template SpmmLaunch<float> make_spmm<float>(const DevCsr<float>*, int, const float*, int,
+                                            const int*, int, int, float* const*, int, int);
+template SpmmLaunch<double> make_spmm<double>(const DevCsr<double>*, int, const double*, int,
+                                              const int*, int, int, double* const*, int, int);
+template void enqueue_spmm<float>(const SpmmLaunch<float>&, Batched<SpmmArgs<float>>, hipStream_t);
+template void enqueue_spmm<double>(const SpmmLaunch<double>&, Batched<SpmmArgs<double>>,
+                                   hipStream_t);
 template void launch_spmm<float>(const DevCsr<float>*, int, const float*, int, const int*, int,
                                  int, float* const*, int, int, hipStream_t);
 template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int, const int*,
@@ -148,13 +168,17 @@ constexpr int kPT = 16;        // output rows per product workgroup
 template <class T, bool FWD>
 __global__ __launch_bounds__(256) void prec_gather_kernel(PrecDev<T> P, const int2* __restrict__ rows,
                                                           int nrows, const int64_t* __restrict__ soff,
-                                                          const T* __restrict__ R, int ldr,
-                                                          const T* __restrict__ y,
-                                                          const T* __restrict__ x,
-                                                          const T* __restrict__ cb, int ldw,
-                                                          const int* __restrict__ k_dev, int k_const,
-                                                          int kcap, T* __restrict__ stage) {
-  const int k = k_dev ? *k_dev : k_const;
+                                                          PrecItem<T> a0, const PrecItem<T>* ab,
+                                                          const int* done, int ldw, int kcap) {
+  if (done && done[blockIdx.z]) return;
+  const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
+  const T* __restrict__ R = it.R;
+  const int ldr = it.ldr;
+  const T* __restrict__ y = it.y;
+  const T* __restrict__ x = it.x;
+  const T* __restrict__ cb = it.cb;
+  T* __restrict__ stage = it.stage;
+  const int k = it.k_dev ? *it.k_dev : it.k_const;
   const int64_t total = int64_t(nrows) * kcap;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
@@ -180,21 +204,26 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(PrecDev<T> P, const in
 template <class T, bool FWD>
 __global__ __launch_bounds__(256) void prec_product_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
                                                            const int64_t* __restrict__ soff,
-                                                           const T* __restrict__ stage, int ldw,
-                                                           const int* __restrict__ k_dev, int k_const,
-                                                           T* __restrict__ y, T* __restrict__ x,
-                                                           T* __restrict__ cb, T* __restrict__ Z,
-                                                           int ldz) {
+                                                           PrecItem<T> a0, const PrecItem<T>* ab,
+                                                           const int* done, int ldw) {
   typedef typename PMfma<T>::acc_t acc_t;
   __shared__ T red[4][kPT][kKMAX + 1];
+  if (done && done[blockIdx.z]) return;
+  const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
+  const T* __restrict__ stage = it.stage;
+  T* __restrict__ y = it.y;
+  T* __restrict__ x = it.x;
+  T* __restrict__ cb = it.cb;
+  T* __restrict__ Z = it.Z;
+  const int ldz = it.ldz;
   const int2 task = tasks[blockIdx.x];
   const int sn = task.x, row0 = task.y;
-  const int k = k_dev ? *k_dev : k_const;
+  const int k = it.k_dev ? *it.k_dev : it.k_const;
   const int KT = (k + 15) / 16;
   const int ns = P.ns[sn], f = ns + P.nb[sn], j0 = P.j0[sn];
   const int nin = FWD ? ns : f;
   const int nout = FWD ? f : ns;
-  const T* __restrict__ M = FWD ? P.fw + P.fw_off[sn] : P.bw + P.bw_off[sn];
+  const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
   const int ldM = FWD ? f : ns;                  // column-major: element (row, i) at i * ldM + row
   const T* __restrict__ In = stage + soff[sn] * ldw;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -259,49 +288,63 @@ static Work product_work(const LevelTasks& L, const int* k_dev, int k_const) {
 }
 
 template <class T>
-void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
-                       const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
-                       const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
-                       T* ws_stage, int ldw, hipStream_t s) {
+void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                        const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
+                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s) {
   LRC_CHECK(kcap >= 1 && kcap <= kKMAX, ST_EINVAL,
             "preconditioner apply: at most 64 right-hand sides per call");
-  LRC_CHECK(ldw >= kcap && ldr >= kcap && ldz >= kcap, ST_EINVAL,
+  LRC_CHECK(ldw >= kcap && it.ldr >= kcap && it.ldz >= kcap, ST_EINVAL,
             "preconditioner apply: leading dimension smaller than the column capacity");
   auto gblocks = [&](int nrows) {
     return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(int64_t(nrows) * kcap, 256), 1), 65535));
   };
-  for (const auto& L : fwd) {
-    if (L.count == 0) continue;
-    {
-      ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, k_dev, k_const));
-      hipLaunchKernelGGL((prec_gather_kernel<T, true>), dim3(gblocks(L.nrows)), dim3(256), 0, s, P,
-                         L.rows, L.nrows, P.soff_fwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev, k_const,
-                         kcap, ws_stage);
-    }
-    {
-      ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, k_dev, k_const));
-      hipLaunchKernelGGL((prec_product_kernel<T, true>), dim3(L.count), dim3(256), 0, s, P, L.tasks,
-                         P.soff_fwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z, ldz);
-    }
-  }
-  for (const auto& L : bwd) {
-    if (L.count == 0) continue;
-    {
-      ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, k_dev, k_const));
-      hipLaunchKernelGGL((prec_gather_kernel<T, false>), dim3(gblocks(L.nrows)), dim3(256), 0, s,
-                         P, L.rows, L.nrows, P.soff_bwd, R, ldr, ws_y, ws_x, ws_cb, ldw, k_dev,
-                         k_const, kcap, ws_stage);
-    }
-    {
-      ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, k_dev, k_const));
-      hipLaunchKernelGGL((prec_product_kernel<T, false>), dim3(L.count), dim3(256), 0, s, P,
-                         L.tasks, P.soff_bwd, ws_stage, ldw, k_dev, k_const, ws_y, ws_x, ws_cb, Z,
-                         ldz);
+  const bool batched = b.dev != nullptr;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fw = pass == 0;
+    for (const auto& L : fw ? fwd : bwd) {
+      if (L.count == 0) continue;
+      {
+        ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s,
+                     batched ? Work() : gather_work<T>(L, it.k_dev, it.k_const));
+        const dim3 grid(gblocks(L.nrows), 1, b.n);
+        if (fw)
+          hipLaunchKernelGGL((prec_gather_kernel<T, true>), grid, dim3(256), 0, s, P, L.rows,
+                             L.nrows, P.soff_fwd, it, b.dev, b.done, ldw, kcap);
+        else
+          hipLaunchKernelGGL((prec_gather_kernel<T, false>), grid, dim3(256), 0, s, P, L.rows,
+                             L.nrows, P.soff_bwd, it, b.dev, b.done, ldw, kcap);
+      }
+      {
+        ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s,
+                     batched ? Work() : product_work<T>(L, it.k_dev, it.k_const));
+        const dim3 grid(L.count, 1, b.n);
+        if (fw)
+          hipLaunchKernelGGL((prec_product_kernel<T, true>), grid, dim3(256), 0, s, P, L.tasks,
+                             P.soff_fwd, it, b.dev, b.done, ldw);
+        else
+          hipLaunchKernelGGL((prec_product_kernel<T, false>), grid, dim3(256), 0, s, P, L.tasks,
+                             P.soff_bwd, it, b.dev, b.done, ldw);
+      }
     }
   }
   LRC_HIP(hipGetLastError());
 }
 
+template <class T>
+void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                       const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
+                       const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
+                       T* ws_stage, int ldw, hipStream_t s) {
+  const PrecItem<T> it{P.fw, P.bw, R, ldr, Z, ldz, k_dev, k_const, ws_y, ws_x, ws_cb, ws_stage};
+  enqueue_prec_apply(P, fwd, bwd, it, Batched<PrecItem<T>>(), kcap, ldw, s);
+}
+
+template void enqueue_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
+                                        const std::vector<LevelTasks>&, const PrecItem<float>&,
+                                        Batched<PrecItem<float>>, int, int, hipStream_t);
+template void enqueue_prec_apply<double>(const PrecDev<double>&, const std::vector<LevelTasks>&,
+                                         const std::vector<LevelTasks>&, const PrecItem<double>&,
+                                         Batched<PrecItem<double>>, int, int, hipStream_t);
 template void launch_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
                                        const std::vector<LevelTasks>&, const float*, int, float*,
                                        int, const int*, int, int, float*, float*, float*, float*,

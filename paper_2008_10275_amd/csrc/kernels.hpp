@@ -36,6 +36,31 @@ constexpr int kMaxOps = 8;
 template <class T>
 void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
                  int r_const, int rcap, T* const* W, int ldw, int cpl, hipStream_t s);
+template <class T>
+struct SpmmArgs {
+  DevCsr<T> op[kMaxOps];
+  T* W[kMaxOps];
+  const T* U;
+  const int* r_dev;
+  int r_const;
+  int q;
+  int ldu;
+  int ldw;
+};
+template <class T>
+struct SpmmLaunch {
+  SpmmArgs<T> a;
+  int cpl = 4;     // columns per lane
+  int lpr = 1;     // lanes per row
+  int blocks = 1;
+  int q = 1;
+  Work work;
+};
+template <class T>
+SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
+                        int r_const, int rcap, T* const* W, int ldw, int cpl);
+template <class T>
+void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s);
 
 // Level-scheduled supernodal triangular solves (data from nd_factor).
 struct LevelTasks {
@@ -77,6 +102,27 @@ void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                        const std::vector<LevelTasks>& bwd, const T* R, int ldr, T* Z, int ldz,
                        const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
                        T* ws_stage, int ldw, hipStream_t s);
+// The per-item operands of a batched apply: items share the supernode
+// structure (and the level tasks) of `P` and bring their own factor values.
+template <class T>
+struct PrecItem {
+  const T* fw;
+  const T* bw;
+  const T* R;
+  int ldr;
+  T* Z;
+  int ldz;
+  const int* k_dev;
+  int k_const;
+  T* y;
+  T* x;
+  T* cb;
+  T* stage;
+};
+template <class T>
+void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                        const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
+                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s);
 
 // ----------------------------------------------------------------- dense tall-skinny
 // Partial Gram products G = X^T X for up to two operands in one launch; the
@@ -251,6 +297,24 @@ void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStr
 // three after it (VP, W, XA / XB)
 void make_core_gemms(const TruncState& st, const CoreView& core, int kcap, SmallGemmArgs* out);
 void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, SmallGemmArgs* out);
+
+// ----------------------------------------------------------------- batch control
+// Convergence state of one item of a lockstep batch of ChebyshevT solves.
+struct BCtl {
+  const double* norm;   // the item's residual norm (device)
+  double target;        // absolute residual target
+  double best;          // best residual so far (stagnation test)
+  double last;          // last residual read
+  int iters;            // updates done
+  int max_iter;
+  int stall;            // consecutive checks without a 30% gain over `best`
+  int stall_limit;
+  int state;            // 0 running, 1 converged, 2 stopped (limit, stagnation, non-finite)
+  int pad;
+};
+// After a residual: reads every running item's norm, counts the update when
+// `after_update`, and sets done[j] once item j converged or must stop.
+void launch_batch_check(BCtl* ctl, int* done, int nb, int after_update, hipStream_t s);
 
 // ----------------------------------------------------------------- residual (fp64)
 // Per-column squared norms of  R = A B^T  (A: n x K view, B: m x K view scaled by

@@ -8,7 +8,8 @@ namespace lrc {
 const char* kclass_name(int c) {
   static const char* names[K_NBASE] = {"spmm", "gram", "gram_reduce", "chol", "tsmm", "jacobi",
                                        "jacobi_replay", "small_gemm", "select", "prec_gather",
-                                       "prec_product", "residual", "vector", "pivchol", "mlp"};
+                                       "prec_product", "residual", "vector", "pivchol", "mlp",
+                                       "graph"};
   static std::vector<std::string> full;
   if (full.empty())
     for (int k = 0; k < K_COUNT; ++k)
@@ -68,7 +69,7 @@ void Profiler::read(double* ms, int* count, double* work, int* unit) {
 
 ProfScope::ProfScope(int cls, hipStream_t s_, Work w) : s(s_) {
   Profiler& p = profiler();
-  if (p.mode == 0 || cls < 0 || cls >= K_COUNT) return;
+  if (p.mode == 0 || p.suspended > 0 || cls < 0 || cls >= K_COUNT) return;
   Profiler::Launch l;
   if (p.mode == 2 && w.valid()) {
     for (auto& g : w.groups) {

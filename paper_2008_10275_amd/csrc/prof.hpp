@@ -14,7 +14,8 @@ namespace lrc {
 
 enum KClass {
   K_SPMM = 0, K_GRAM, K_GRAM_REDUCE, K_CHOL, K_TSMM, K_JACOBI, K_REPLAY, K_SMALL_GEMM,
-  K_SELECT, K_PREC_GATHER, K_PREC_PRODUCT, K_RESIDUAL, K_VECTOR, K_PIVCHOL, K_MLP, K_NBASE
+  K_SELECT, K_PREC_GATHER, K_PREC_PRODUCT, K_RESIDUAL, K_VECTOR, K_PIVCHOL, K_MLP, K_GRAPH,
+  K_NBASE
 };
 // class index = base * 2 + (fp32 ? 1 : 0)
 constexpr int K_COUNT = 2 * K_NBASE;
@@ -37,6 +38,7 @@ struct Work {
 
 struct Profiler {
   int mode = 0;   // 0 off, 1 events, 2 events + work
+  int suspended = 0;   // > 0 while a stream is being captured into a graph
   struct Launch {
     hipEvent_t e0, e1;
     Work w;

@@ -20,7 +20,7 @@ static bool log_enabled() {
   static const bool on = std::getenv("LRC_LOG") != nullptr;
   return on;
 }
-static void log_line(const char* phase, int it, double norm, double ref) {
+void log_line(const char* phase, int it, double norm, double ref) {
   if (!log_enabled()) return;
   std::fprintf(stderr, "{\"phase\": \"%s\", \"iter\": %d, \"norm\": %.6e, \"rel\": %.6e}\n",
                phase, it, norm, ref > 0 ? norm / ref : 0.0);
@@ -388,20 +388,20 @@ void Cheb<T>::alloc(Prob* p, int cap_) {
 }
 
 template <class T>
-void Cheb<T>::spmm(const T* U, int ldu, const int* r_dev) {
+SpmmLaunch<T> Cheb<T>::spmm_plan(const T* U, int ldu, const int* r_dev) const {
   const Ops& o = *P->ops;
   const int ld = ld_for(cap);
   T* Wp[kMaxOps];
   for (int i = 0; i < o.q; ++i) Wp[i] = W.as<T>() + size_t(i) * o.n * ld;
-  launch_spmm<T>(ops_dev<T>(o).data(), o.q, U, ldu, r_dev, 0, cap, Wp, ld,
-                 sizeof(T) == 8 ? 2 : 4, P->ctx->stream);
+  return make_spmm<T>(ops_dev<T>(o).data(), o.q, U, ldu, r_dev, 0, cap, Wp, ld,
+                      sizeof(T) == 8 ? 2 : 4);
 }
 
+// R = T(B - sum_i K_i S D_i): blocks [B | K_0 S | ... ] and [B_V | D_0 S_V | ...]
 template <class T>
-void Cheb<T>::residual(const LR<T>& B, double* norm_dev, double tol) {
+TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol) const {
   const Ops& o = *P->ops;
   const int ld = ld_for(cap);
-  spmm(S.u(), S.ld, S.r());
   BlockView<T> A{}, Bv{};
   CoreView c{};
   add_block(A, B.u(), B.ld, B.r(), 0);
@@ -412,15 +412,71 @@ void Cheb<T>::residual(const LR<T>& B, double* norm_dev, double tol) {
     add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
     add_core(c, S.sv(), -1.0, S.r(), 0);
   }
-  tr.run(A, o.n, Bv, P->m, c, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev,
-         P->ctx->stream);
+  return tr.plan(A, o.n, Bv, P->m, c, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev);
+}
+
+// D = T(Z R_V^T / dc) with Z = P^{-1} R_U diag(s_R)
+template <class T>
+TruncPlan<T> Cheb<T>::dstart_plan(double dc) const {
+  const int ld = ld_for(cap);
+  BlockView<T> A = view1<T>(Z.as<T>(), ld, R.r(), 0);
+  BlockView<T> Bv = view1<T>(R.v(), R.ld, R.r(), 0);
+  CoreView cv{};
+  add_core(cv, R.sv(), 1.0 / dc, R.r(), 0);
+  return tr.plan(A, P->ops->n, Bv, P->m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(),
+                 norm.as<double>() + 1);
+}
+
+// S = T(S + D)
+template <class T>
+TruncPlan<T> Cheb<T>::supd_plan() const {
+  BlockView<T> A{}, Bv{};
+  CoreView cv{};
+  add_block(A, S.u(), S.ld, S.r(), 0);
+  add_block(A, D.u(), D.ld, D.r(), 0);
+  add_block(Bv, S.v(), S.ld, S.r(), 0);
+  add_block(Bv, D.v(), D.ld, D.r(), 0);
+  add_core(cv, S.sv(), 1.0, S.r(), 0);
+  add_core(cv, D.sv(), 1.0, D.r(), 0);
+  return tr.plan(A, P->ops->n, Bv, P->m, cv, cap, tol, S.u(), S.ld, S.v(), S.ld, S.sv(), S.r(),
+                 norm.as<double>() + 2);
+}
+
+// D = T(alpha D + beta Z R_V^T)
+template <class T>
+TruncPlan<T> Cheb<T>::dstep_plan(double alpha, double beta) const {
+  const int ld = ld_for(cap);
+  BlockView<T> A{}, Bv{};
+  CoreView cv{};
+  add_block(A, D.u(), D.ld, D.r(), 0);
+  add_block(A, Z.as<T>(), ld, R.r(), 0);
+  add_block(Bv, D.v(), D.ld, D.r(), 0);
+  add_block(Bv, R.v(), R.ld, R.r(), 0);
+  add_core(cv, D.sv(), alpha, D.r(), 0);
+  add_core(cv, R.sv(), beta, R.r(), 0);
+  return tr.plan(A, P->ops->n, Bv, P->m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(),
+                 norm.as<double>() + 1);
+}
+
+// Z = P^{-1} R_U
+template <class T>
+PrecItem<T> Cheb<T>::prec_item() const {
+  const PrecDev<T>& pd = P->prec->dev<T>();
+  return PrecItem<T>{pd.fw, pd.bw, R.u(), R.ld, Z.as<T>(), ld_for(cap), R.r(), 0,
+                     py.as<T>(), px.as<T>(), pcb.as<T>(), pst.as<T>()};
 }
 
 template <class T>
-void Cheb<T>::precond(const T* Rm, int ldr, const int* k_dev, T* Zm, int ldz) {
-  const int ld = ld_for(cap);
-  launch_prec_apply<T>(P->prec->dev<T>(), P->prec->fwd, P->prec->bwd, Rm, ldr, Zm, ldz, k_dev, 0,
-                       cap, py.as<T>(), px.as<T>(), pcb.as<T>(), pst.as<T>(), ld, P->ctx->stream);
+void Cheb<T>::precond() {
+  enqueue_prec_apply<T>(P->prec->dev<T>(), P->prec->fwd, P->prec->bwd, prec_item(),
+                        Batched<PrecItem<T>>(), cap, ld_for(cap), P->ctx->stream);
+}
+
+template <class T>
+void Cheb<T>::residual(const LR<T>& B, double* norm_dev, double tol_) {
+  hipStream_t s = P->ctx->stream;
+  enqueue_spmm(spmm_plan(S.u(), S.ld, S.r()), Batched<SpmmArgs<T>>(), s);
+  enqueue_trunc(resid_plan(B, norm_dev, tol_), TruncBatch<T>(), s);
 }
 
 template <class T>
@@ -429,9 +485,7 @@ int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c,
                    int* flags, double abs_target, int stall_limit) {
   Ctx& ctx = *P->ctx;
   hipStream_t s = ctx.stream;
-  const int64_t n = P->ops->n, m = P->m;
-  const int ld = ld_for(cap);
-  const double tol = o.trunc_tol;
+  tol = o.trunc_tol;
   c = std::max(c, 1e-12 * dc);
   const double sigma = dc / c;
   LRC_HIP(hipMemsetAsync(S.rank.p, 0, 16, s));
@@ -442,21 +496,10 @@ int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c,
     ctx.sync();
     return ctx.pinned[0];
   };
+  const TruncBatch<T> one;
   // residual truncation uses the solver's tolerance relative to the residual
   auto resid = [&]() {
-    const Ops& op = *P->ops;
-    spmm(S.u(), S.ld, S.r());
-    BlockView<T> A{}, Bv{};
-    CoreView cv{};
-    add_block(A, B.u(), B.ld, B.r(), 0);
-    add_block(Bv, B.v(), B.ld, B.r(), 0);
-    add_core(cv, B.sv(), 1.0, B.r(), 0);
-    for (int i = 0; i < op.q; ++i) {
-      add_block(A, W.as<T>() + size_t(i) * op.n * ld, ld, S.r(), 0);
-      add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
-      add_core(cv, S.sv(), -1.0, S.r(), 0);
-    }
-    tr.run(A, n, Bv, m, cv, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), nd, s);
+    residual(B, nd, tol);
     return read_norm();
   };
   int iters = 0;
@@ -470,31 +513,16 @@ int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c,
   double best = nr;
   int stall = 0;
   while (true) {
-    if (!(nr > target)) { *converged = true; break; }
-    if (iters >= max_iter || !std::isfinite(nr) || stall >= stall_limit) break;
+    if (!std::isfinite(nr)) break;
+    if (nr <= target) { *converged = true; break; }
+    if (iters >= max_iter || stall >= stall_limit) break;
     // (re)start
-    precond(R.u(), R.ld, R.r(), Z.as<T>(), ld);
+    precond();
     ++*prec_applies;
-    {
-      BlockView<T> A = view1<T>(Z.as<T>(), ld, R.r(), 0);
-      BlockView<T> Bv = view1<T>(R.v(), R.ld, R.r(), 0);
-      CoreView cv{};
-      add_core(cv, R.sv(), 1.0 / dc, R.r(), 0);
-      tr.run(A, n, Bv, m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(), nd + 1, s);
-    }
+    enqueue_trunc(dstart_plan(dc), one, s);
     double rho = c / dc;
     for (int k = 0; k < cycle; ++k) {
-      {   // S <- T(S + D)
-        BlockView<T> A{}, Bv{};
-        CoreView cv{};
-        add_block(A, S.u(), S.ld, S.r(), 0);
-        add_block(A, D.u(), D.ld, D.r(), 0);
-        add_block(Bv, S.v(), S.ld, S.r(), 0);
-        add_block(Bv, D.v(), D.ld, D.r(), 0);
-        add_core(cv, S.sv(), 1.0, S.r(), 0);
-        add_core(cv, D.sv(), 1.0, D.r(), 0);
-        tr.run(A, n, Bv, m, cv, cap, tol, S.u(), S.ld, S.v(), S.ld, S.sv(), S.r(), nd + 2, s);
-      }
+      enqueue_trunc(supd_plan(), one, s);   // S <- T(S + D)
       ++iters;
       nr = resid();
       *last_norm = nr;
@@ -506,19 +534,10 @@ int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c,
           stall >= stall_limit)
         break;
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      precond(R.u(), R.ld, R.r(), Z.as<T>(), ld);
+      precond();
       ++*prec_applies;
-      {   // D <- T(rho' rho D + (2 rho' / c) P^-1 R)
-        BlockView<T> A{}, Bv{};
-        CoreView cv{};
-        add_block(A, D.u(), D.ld, D.r(), 0);
-        add_block(A, Z.as<T>(), ld, R.r(), 0);
-        add_block(Bv, D.v(), D.ld, D.r(), 0);
-        add_block(Bv, R.v(), R.ld, R.r(), 0);
-        add_core(cv, D.sv(), rho_new * rho, D.r(), 0);
-        add_core(cv, R.sv(), 2.0 * rho_new / c, R.r(), 0);
-        tr.run(A, n, Bv, m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(), nd + 1, s);
-      }
+      // D <- T(rho' rho D + (2 rho' / c) P^-1 R)
+      enqueue_trunc(dstep_plan(rho_new * rho, 2.0 * rho_new / c), one, s);
       rho = rho_new;
     }
   }
@@ -549,13 +568,16 @@ static void upload_lr(LR<double>& X, int r, const double* Uh, const double* sh, 
 }
 
 template <class Tin, class Tout>
-static void cast_lr(const LR<Tin>& a, LR<Tout>& b, hipStream_t s) {
+void cast_lr(const LR<Tin>& a, LR<Tout>& b, hipStream_t s) {
   const int cap = std::min(a.cap, b.cap);
   launch_cast<Tin, Tout>(a.u(), a.ld, b.u(), b.ld, a.n, a.r(), 0, cap, s);
   launch_cast<Tin, Tout>(a.v(), a.ld, b.v(), b.ld, a.m, a.r(), 0, cap, s);
   LRC_HIP(hipMemcpyAsync(b.s.p, a.s.p, size_t(cap) * 8, hipMemcpyDeviceToDevice, s));
   LRC_HIP(hipMemcpyAsync(b.rank.p, a.rank.p, sizeof(int), hipMemcpyDeviceToDevice, s));
 }
+template void cast_lr<double, float>(const LR<double>&, LR<float>&, hipStream_t);
+template void cast_lr<float, double>(const LR<float>&, LR<double>&, hipStream_t);
+template void cast_lr<double, double>(const LR<double>&, LR<double>&, hipStream_t);
 
 static int read_rank(Ctx& ctx, const int* r) {
   LRC_HIP(hipMemcpyAsync(ctx.pinned_i, r, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
@@ -729,165 +751,197 @@ static int median_solve(Prob& P, int jmed, double c, double dc, double tol, int 
 }
 
 // ------------------------------------------------------------------ solve
-lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
-                         const double* V0, lrc_info* info) {
-  auto t0 = clk::now();
-  Ctx& ctx = *P.ctx;
+void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
+                       const double* V0) {
+  t0 = clk::now();
+  P = &P_;
+  Prob& Pr = *P;
+  Ctx& ctx = *Pr.ctx;
   hipStream_t s = ctx.stream;
-  const Ops& op = *P.ops;
-  const int64_t n = op.n, m = P.m;
-  LRC_CHECK(P.prec != nullptr, ST_EINVAL, "lrc_solve: call lrc_prob_precondition first");
+  const Ops& op = *Pr.ops;
+  const int64_t n = op.n, m = Pr.m;
+  LRC_CHECK(Pr.prec != nullptr, ST_EINVAL, "lrc_solve: call lrc_prob_precondition first");
   LRC_CHECK(o.rank_cap >= 1 && o.rank_cap <= kPrecCols, ST_EINVAL,
             "lrc_solve: rank_cap must be in [1, 64]");
   LRC_CHECK(o.trunc_tol >= 0.0 && o.res_tol >= 0.0, ST_EINVAL, "lrc_solve: negative tolerance");
-  double c = o.cheb_c, dc = o.cheb_d;
+  c = o.cheb_c;
+  dc = o.cheb_d;
   if (!(c > 0.0) || !(dc > 0.0)) {
     double lo = 1.0, hi = 1.0;
     for (int64_t j = 0; j < m; ++j)
       for (int i = 0; i < op.q; ++i) {
-        const double rt = P.d[size_t(j) * op.q + i] / P.dbar[i];
+        const double rt = Pr.d[size_t(j) * op.q + i] / Pr.dbar[i];
         lo = std::min(lo, rt);
         hi = std::max(hi, rt);
       }
     c = 0.5 * (hi - lo);
     dc = 0.5 * (hi + lo);
   }
-  lrc_info inf{};
+  inf = lrc_info{};
   // fixed initial term X0
-  P.X0 = LR<double>();
-  P.rank_x0 = 0;
+  Pr.X0 = LR<double>();
+  Pr.rank_x0 = 0;
   if (o.init == LRC_INIT_MEDIAN) {
     const int jmed = int(m / 2);
     // the single median column has its own, much narrower, spectrum interval
     double lo = 1.0, hi = 1.0;
     for (int i = 0; i < op.q; ++i) {
-      const double rt = P.d[size_t(jmed) * op.q + i] / P.dbar[i];
+      const double rt = Pr.d[size_t(jmed) * op.q + i] / Pr.dbar[i];
       lo = std::min(lo, rt);
       hi = std::max(hi, rt);
     }
     const double cm = std::max(0.5 * (hi - lo), 1e-3 * 0.5 * (hi + lo)), dm = 0.5 * (hi + lo);
-    inf.median_iters = median_solve(P, jmed, cm, dm, o.median_tol > 0 ? o.median_tol : 1e-10,
-                                    1000, P.X0);
-    P.rank_x0 = 1;
+    inf.median_iters = median_solve(Pr, jmed, cm, dm, o.median_tol > 0 ? o.median_tol : 1e-10,
+                                    1000, Pr.X0);
+    Pr.rank_x0 = 1;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
     LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
-    P.X0.alloc(n, m, r0, s);
-    upload_lr(P.X0, r0, U0, s0, V0, s);
-    P.rank_x0 = r0;
+    Pr.X0.alloc(n, m, r0, s);
+    upload_lr(Pr.X0, r0, U0, s0, V0, s);
+    Pr.rank_x0 = r0;
   } else {
-    P.X0.alloc(n, m, 1, s);
+    Pr.X0.alloc(n, m, 1, s);
   }
-  const int cap = o.rank_cap;
+  cap = o.rank_cap;
   // room left for the right-hand side in the residual concatenation
   // [B | K_0 S | ... | K_{q-1} S] of at most 128 columns
   const int room = std::max(8, kTruncCap - op.q * cap);
-  const int bcap = std::min(std::min(64, room), std::max(P.rF + op.q, o.init == LRC_INIT_GIVEN ? 64 : 1));
-  Cheb<double> c64;
-  c64.alloc(&P, cap);
-  LR<double> B64;
+  const int bcap = std::min(std::min(64, room), std::max(Pr.rF + op.q, o.init == LRC_INIT_GIVEN ? 64 : 1));
+  c64 = std::make_unique<Cheb<double>>();
+  c64->alloc(P, cap);
   B64.alloc(n, m, bcap, s);
-  build_rhs(P, P.X0, P.rank_x0, B64, o, c64.tr);
-  int flags = 0, iters = 0, papp = 0, refinements = 0;
-  bool conv = false;
-  double last = 0.0;
-  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  build_rhs(Pr, Pr.X0, Pr.rank_x0, B64, o, c64->tr);
+  max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  // mixed precision: the inner correction's own cap keeps [rhs | K_i E] within 128 columns
+  inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
+  target = o.res_tol * Pr.fnorm;
+  refine_max = o.refine_max > 0 ? o.refine_max : 8;
+  rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
+}
+
+void SolveRun::alloc_mixed() {
+  hipStream_t s = P->ctx->stream;
+  const int64_t n = P->ops->n, m = P->m;
+  c32 = std::make_unique<Cheb<float>>();
+  c32->alloc(P, inner_cap);
+  Bin.alloc(n, m, cap, s);
+  E64.alloc(n, m, inner_cap, s);
+  LRC_HIP(hipMemsetAsync(c64->S.rank.p, 0, 16, s));
+}
+
+// S64 <- T(S64 + E64), E64 = fp64 copy of the inner correction
+void SolveRun::accumulate_plan_inputs(hipStream_t s) {
+  cast_lr<float, double>(c32->S, E64, s);
+}
+TruncPlan<double> SolveRun::accumulate_plan(const lrc_opts& o) const {
+  const LR<double>& S64 = c64->S;
+  BlockView<double> A{}, Bv{};
+  CoreView cv{};
+  add_block(A, S64.u(), S64.ld, S64.r(), 0);
+  add_block(A, E64.u(), E64.ld, E64.r(), 0);
+  add_block(Bv, S64.v(), S64.ld, S64.r(), 0);
+  add_block(Bv, E64.v(), E64.ld, E64.r(), 0);
+  add_core(cv, S64.sv(), 1.0, S64.r(), 0);
+  add_core(cv, E64.sv(), 1.0, E64.r(), 0);
+  return c64->tr.plan(A, P->ops->n, Bv, P->m, cv, cap, o.trunc_tol, S64.u(), S64.ld, S64.v(),
+                      S64.ld, S64.sv(), S64.r(), c64->norm.as<double>() + 3);
+}
+
+void SolveRun::iterate(const lrc_opts& o) {
+  Prob& Pr = *P;
+  Ctx& ctx = *Pr.ctx;
+  hipStream_t s = ctx.stream;
   if (o.precision == LRC_FP64) {
-    iters = c64.solve(B64, P.fnorm, o, c, dc, max_iter, &conv, &last, &papp, &flags);
-    P.S = std::move(c64.S);
-  } else {
-    // fp32 inner ChebyshevT wrapped in fp64 iterative refinement.  The inner
-    // right-hand side is the fp64 residual truncated to rank <= cap, so the
-    // inner correction gets its own cap to keep [rhs | K_i E] within 128 columns.
-    const int inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
-    Cheb<float> c32;
-    c32.alloc(&P, inner_cap);
-    LR<float> Bin;
-    Bin.alloc(n, m, cap, s);
-    LR<double> E64;
-    E64.alloc(n, m, inner_cap, s);
-    LR<double>& S64 = c64.S;
-    LRC_HIP(hipMemsetAsync(S64.rank.p, 0, 16, s));
-    double* nd = c64.norm.as<double>();
-    const double target = o.res_tol * P.fnorm;
-    const int refine_max = o.refine_max > 0 ? o.refine_max : 8;
-    const double rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
-    while (true) {
-      // fp64 residual, truncated to the inner solve's accuracy: the correction's rhs
-      c64.residual(B64, nd, rhs_tol);
-      LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, 8, hipMemcpyDeviceToHost, s));
-      ctx.sync();
-      last = ctx.pinned[0];
-      log_line("refine64", refinements, last, P.fnorm);
-      if (!(last > target)) { conv = true; break; }
-      if (refinements >= refine_max || iters >= max_iter || !std::isfinite(last)) break;
-      cast_lr<double, float>(c64.R, Bin, s);
-      lrc_opts oi = o;
-      oi.res_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
-      bool cin = false;
-      double lin = 0.0;
-      // stop the inner solve at its relative tolerance, at a fraction of the
-      // outer target, or when the fp32 residual stagnates at its rounding floor
-      iters += c32.solve(Bin, last, oi, c, dc, max_iter - iters, &cin, &lin, &papp, &flags,
-                         0.5 * target, 2);
-      ++refinements;
-      cast_lr<float, double>(c32.S, E64, s);
-      BlockView<double> A{}, Bv{};
-      CoreView cv{};
-      add_block(A, S64.u(), S64.ld, S64.r(), 0);
-      add_block(A, E64.u(), E64.ld, E64.r(), 0);
-      add_block(Bv, S64.v(), S64.ld, S64.r(), 0);
-      add_block(Bv, E64.v(), E64.ld, E64.r(), 0);
-      add_core(cv, S64.sv(), 1.0, S64.r(), 0);
-      add_core(cv, E64.sv(), 1.0, E64.r(), 0);
-      c64.tr.run(A, n, Bv, m, cv, cap, o.trunc_tol, S64.u(), S64.ld, S64.v(), S64.ld, S64.sv(),
-                 S64.r(), nd + 3, s);
-    }
-    LRC_HIP(hipMemcpyAsync(ctx.pinned_i, c64.tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    ctx.sync();
-    flags |= ctx.pinned_i[0];
-    P.S = std::move(c64.S);
+    iters = c64->solve(B64, Pr.fnorm, o, c, dc, max_iter, &conv, &last, &papp, &flags);
+    return;
   }
-  P.rank_s = read_rank(ctx, P.S.r());
-  inf.rank = P.rank_s;
-  inf.rank_x0 = P.rank_x0;
+  // fp32 inner ChebyshevT wrapped in fp64 iterative refinement.  The inner
+  // right-hand side is the fp64 residual truncated to rank <= cap.
+  alloc_mixed();
+  double* nd = c64->norm.as<double>();
+  while (true) {
+    // fp64 residual, truncated to the inner solve's accuracy: the correction's rhs
+    c64->residual(B64, nd, rhs_tol);
+    LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, 8, hipMemcpyDeviceToHost, s));
+    ctx.sync();
+    last = ctx.pinned[0];
+    log_line("refine64", refinements, last, Pr.fnorm);
+    if (!std::isfinite(last)) break;
+    if (last <= target) { conv = true; break; }
+    if (refinements >= refine_max || iters >= max_iter) break;
+    cast_lr<double, float>(c64->R, Bin, s);
+    lrc_opts oi = o;
+    oi.res_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+    bool cin = false;
+    double lin = 0.0;
+    // stop the inner solve at its relative tolerance, at a fraction of the
+    // outer target, or when the fp32 residual stagnates at its rounding floor
+    iters += c32->solve(Bin, last, oi, c, dc, max_iter - iters, &cin, &lin, &papp, &flags,
+                        0.5 * target, 2);
+    ++refinements;
+    accumulate_plan_inputs(s);
+    enqueue_trunc(accumulate_plan(o), TruncBatch<double>(), s);
+  }
+  LRC_HIP(hipMemcpyAsync(ctx.pinned_i, c64->tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  ctx.sync();
+  flags |= ctx.pinned_i[0];
+}
+
+lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
+  Prob& Pr = *P;
+  Ctx& ctx = *Pr.ctx;
+  const int64_t n = Pr.ops->n, m = Pr.m;
+  Pr.S = std::move(c64->S);
+  Pr.rank_s = read_rank(ctx, Pr.S.r());
+  inf.rank = Pr.rank_s;
+  inf.rank_x0 = Pr.rank_x0;
   inf.iters = iters;
   inf.prec_applies = papp;
   inf.refinements = refinements;
-  inf.relres_est = last / P.fnorm;
+  inf.relres_est = last / Pr.fnorm;
   inf.relres = inf.relres_est;
   inf.info_flags = flags;
   if (o.verify_fp64) {
     std::vector<double> col(m);
-    const double nr = residual_fp64(P, P.X0, P.rank_x0, P.S, col.data());
-    inf.relres = nr / P.fnorm;
+    const double nr = residual_fp64(Pr, Pr.X0, Pr.rank_x0, Pr.S, col.data());
+    inf.relres = nr / Pr.fnorm;
     // per-column relative residuals against ||F_j||, with G = FU^T FU
-    std::vector<double> g(size_t(P.rF) * P.rF, 0.0);
-    for (int a = 0; a < P.rF; ++a)
-      for (int b = 0; b < P.rF; ++b) {
+    std::vector<double> g(size_t(Pr.rF) * Pr.rF, 0.0);
+    for (int a = 0; a < Pr.rF; ++a)
+      for (int b = 0; b < Pr.rF; ++b) {
         double acc = 0.0;
-        for (int64_t i = 0; i < n; ++i) acc += P.FU[size_t(a) * n + i] * P.FU[size_t(b) * n + i];
-        g[size_t(a) * P.rF + b] = acc;
+        for (int64_t i = 0; i < n; ++i) acc += Pr.FU[size_t(a) * n + i] * Pr.FU[size_t(b) * n + i];
+        g[size_t(a) * Pr.rF + b] = acc;
       }
     double mx = 0.0;
     for (int64_t j = 0; j < m; ++j) {
       double fj = 0.0;
-      for (int a = 0; a < P.rF; ++a)
-        for (int b = 0; b < P.rF; ++b)
-          fj += P.FV[size_t(a) * m + j] * P.Fs[a] * g[size_t(a) * P.rF + b] * P.Fs[b] *
-                P.FV[size_t(b) * m + j];
+      for (int a = 0; a < Pr.rF; ++a)
+        for (int b = 0; b < Pr.rF; ++b)
+          fj += Pr.FV[size_t(a) * m + j] * Pr.Fs[a] * g[size_t(a) * Pr.rF + b] * Pr.Fs[b] *
+                Pr.FV[size_t(b) * m + j];
       if (fj > 0) mx = std::max(mx, col[j] / std::sqrt(fj));
     }
     inf.max_col_relres = mx;
   }
-  inf.seconds_setup = P.seconds_setup;
+  inf.seconds_setup = Pr.seconds_setup;
   inf.seconds_solve = secs_since(t0);
+  const bool ok = conv && (!o.verify_fp64 || inf.relres <= o.res_tol);
+  inf.status = ok ? ST_OK : ST_NOTCONV;
   if (info) *info = inf;
   if (flags & 8)
     throw Error(ST_EINVAL, "truncation capacity exceeded: more than 128 concatenated columns "
                            "(reduce rank_cap or the rank of the right-hand side)");
-  const bool ok = conv && (!o.verify_fp64 || inf.relres <= o.res_tol);
   return ok ? ST_OK : ST_NOTCONV;
+}
+
+lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
+                         const double* V0, lrc_info* info) {
+  SolveRun run;
+  run.prepare(P, o, r0, U0, s0, V0);
+  run.iterate(o);
+  return run.finish(o, info);
 }
 
 }  // namespace lrc

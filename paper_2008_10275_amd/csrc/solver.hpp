@@ -1,6 +1,7 @@
 // Solver core: operators, preconditioner, truncation engine and the
 // ChebyshevT iteration (host orchestration of the HIP kernels).
 #pragma once
+#include <chrono>
 #include <memory>
 #include <string>
 #include <vector>
@@ -141,8 +142,16 @@ struct Cheb {
             int max_iter, bool* converged, double* last_norm, int* prec_applies, int* flags,
             double abs_target = 0.0, int stall_limit = 1 << 30);
   void residual(const LR<T>& B, double* norm_dev, double tol = 0.0);
-  void precond(const T* R, int ldr, const int* k_dev, T* Z, int ldz);
-  void spmm(const T* U, int ldu, const int* r_dev);
+  void precond();   // Z = P^{-1} R_U
+  // launch arguments of the steps (truncation tolerance `tol`; norms go to
+  // norm[0] residual, norm[1] direction, norm[2] iterate)
+  double tol = 0.0;
+  SpmmLaunch<T> spmm_plan(const T* U, int ldu, const int* r_dev) const;
+  TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol) const;
+  TruncPlan<T> dstart_plan(double dc) const;
+  TruncPlan<T> supd_plan() const;
+  TruncPlan<T> dstep_plan(double alpha, double beta) const;
+  PrecItem<T> prec_item() const;
 };
 
 struct Prob {
@@ -165,6 +174,9 @@ struct Prob {
 };
 
 // helpers
+void log_line(const char* phase, int it, double norm, double ref);   // LRC_LOG set: one JSON line
+template <class Tin, class Tout>
+void cast_lr(const LR<Tin>& a, LR<Tout>& b, hipStream_t s);
 template <class T>
 BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double* rowscale = nullptr);
 
@@ -172,5 +184,39 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
 
 lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
                          const double* V0, lrc_info* info);
+
+// One solve split into set-up (spectrum bounds, initial term X0, right-hand
+// side B = F - L(X0)), iteration and report, so that a batch of problems can
+// share the iteration phase.
+struct SolveRun {
+  Prob* P = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  double c = 0.0, dc = 0.0;
+  int cap = 0, inner_cap = 0, max_iter = 0, refine_max = 0;
+  double target = 0.0, rhs_tol = 0.0;
+  lrc_info inf{};
+  std::unique_ptr<Cheb<double>> c64;
+  std::unique_ptr<Cheb<float>> c32;
+  LR<double> B64, E64;
+  LR<float> Bin;
+  int flags = 0, iters = 0, papp = 0, refinements = 0;
+  bool conv = false;
+  double last = 0.0;
+  void prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
+               const double* V0);
+  void iterate(const lrc_opts& o);
+  lrc_status finish(const lrc_opts& o, lrc_info* info);
+  // mixed precision pieces
+  void alloc_mixed();
+  void accumulate_plan_inputs(hipStream_t s);
+  TruncPlan<double> accumulate_plan(const lrc_opts& o) const;
+};
+
+// Solves several problems in lockstep: every step is one launch for all of
+// them, and each restart cycle of the ChebyshevT iteration is replayed from a
+// captured HIP graph.  Set-up and reports run on the problems' context stream,
+// the lockstep phase on a stream of its own (synchronised at both ends).
+std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc_opts& o,
+                                      lrc_info* infos);
 
 }  // namespace lrc

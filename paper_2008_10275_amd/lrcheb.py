@@ -46,7 +46,7 @@ class lrc_info(C.Structure):
                 ("prec_applies", C.c_int), ("refinements", C.c_int), ("median_iters", C.c_int),
                 ("relres", C.c_double), ("relres_est", C.c_double),
                 ("max_col_relres", C.c_double), ("seconds_setup", C.c_double),
-                ("seconds_solve", C.c_double), ("info_flags", C.c_int)]
+                ("seconds_solve", C.c_double), ("info_flags", C.c_int), ("status", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +75,7 @@ _SIGS = {
     "lrc_prob_prec_apply_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int]),
     "lrc_solve": (C.c_int, [_P, C.POINTER(lrc_opts), C.c_int, _P, _P, _P,
                             C.POINTER(lrc_info)]),
+    "lrc_solve_batched": (C.c_int, [_P, C.c_int, C.POINTER(lrc_opts), C.POINTER(lrc_info)]),
     "lrc_get_solution": (C.c_int, [_P, C.POINTER(C.c_int), _P, _P, _P]),
     "lrc_residual": (C.c_int, [_P, C.POINTER(C.c_double), _P]),
     "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
@@ -325,6 +326,21 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def solve_batched(problems, opts=None, **kw):
+    """lrc_solve_batched: all problems (one context, each preconditioned) in
+    lockstep, one launch per step and one HIP graph per restart cycle.
+    Returns (worst status, [info dict per problem])."""
+    if not problems:
+        raise ValueError("solve_batched: no problems")
+    o = opts if opts is not None else default_opts(**kw)
+    K = len(problems)
+    hs = (C.c_void_p * K)(*[p.handle.value for p in problems])
+    infos = (lrc_info * K)()
+    code = load().lrc_solve_batched(hs, K, C.byref(o), infos)
+    _check(problems[0].ctx.handle, code)
+    return code, [infos[k].as_dict() for k in range(K)]
 
 
 class MLP:
