@@ -61,7 +61,7 @@ typedef struct {
   double trunc_tol;    /* relative Frobenius tail of every truncation (eps)     */
   double res_tol;      /* stop at ||F - L(X)||_F <= res_tol * ||F||_F           */
   int max_iter;        /* total Chebyshev updates (all restarts, all refinements) */
-  int restart;         /* restart the recurrence every `restart` updates (0: never) */
+  int restart;         /* restart the recurrence every `restart` updates, in [1, 64] */
   double cheb_c;       /* half-width of the spectrum interval (<= 0: from lrc_prob_spectrum) */
   double cheb_d;       /* centre of the spectrum interval                       */
   int precision;       /* LRC_FP64 or LRC_MIXED_FP32                            */
@@ -70,6 +70,8 @@ typedef struct {
   int init;            /* LRC_INIT_*                                            */
   double median_tol;   /* relative residual of the median-parameter solve       */
   int verify_fp64;     /* 1: finish with the entry-wise fp64 residual           */
+  int eager;           /* 1: launch every step directly instead of replaying the
+                          captured HIP graphs of the iterations (same arithmetic) */
 } lrc_opts;
 
 typedef struct {
@@ -151,7 +153,7 @@ lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* 
  * treats the parameter subsets independently, so their Newton steps can run
  * together).  Same options and results as K calls of lrc_solve with
  * opts->init LRC_INIT_MEDIAN or LRC_INIT_ZERO (LRC_INIT_GIVEN is refused);
- * opts->restart must be in [1, 64]: one restart cycle of the ChebyshevT
+ * opts->restart must be in [1, 64] (as for lrc_solve): one restart cycle of the ChebyshevT
  * recurrence for all problems is captured once as a HIP graph and replayed
  * until every problem has converged or stopped, each step being one launch
  * over all problems, with finished problems skipped on the device.  Problems

@@ -1,9 +1,11 @@
-// Lockstep solves of several problems (parameter subsets, each with its own
-// linearisation point): every step of the ChebyshevT iteration is one launch
-// whose grid's z dimension runs over the problems, per-problem arguments come
-// from device arrays built once per call site, finished problems are skipped
-// through device-side done flags, and one restart cycle is captured into a
-// HIP graph that the host replays until every problem has stopped.
+// Lockstep execution of the iterative phases of one or many solves (parameter
+// subsets, each with its own linearisation point; a single solve is a batch of
+// one): every step is one launch whose grid's z dimension runs over the
+// problems, per-problem arguments come from device arrays built once per call
+// site, finished problems are skipped through device-side done flags, and the
+// iterations (a restart cycle of ChebyshevT, a few steps of the median-column
+// solve) are captured into HIP graphs that the host replays until every
+// problem has stopped.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -71,16 +73,8 @@ struct CaptureGuard {
   hipStream_t s;
   bool active = false;
   explicit CaptureGuard(hipStream_t s_) : s(s_) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    const hipError_t q = hipStreamIsCapturing(s, &cs);
-    const hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-      char msg[256];
-      std::snprintf(msg, sizeof msg,
-                    "hipStreamBeginCapture: %s (stream %p, is-capturing query %s, status %d)",
-                    hipGetErrorString(e), static_cast<void*>(s), hipGetErrorName(q), int(cs));
-      throw Error(ST_EDEVICE, msg);
-    }
+    // thread-local mode: only this thread's unsafe calls end the capture
+    LRC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     profiler().suspended++;
     active = true;
   }
@@ -99,6 +93,190 @@ struct CaptureGuard {
   }
 };
 
+bool log_on() {
+  static const bool on = std::getenv("LRC_LOG") != nullptr;
+  return on;
+}
+
+// Preconditioner applies of a batch: one launch per level for all items when
+// their factorisations share the supernode structure, else one per item.
+template <class T>
+struct PrecBatch {
+  std::vector<const Prec*> pre;
+  std::vector<PrecItem<T>> items;
+  bool shared = true;
+  Batched<PrecItem<T>> all;
+  std::vector<Batched<PrecItem<T>>> one;
+  int kcap = 1, ldw = 8;
+  void setup(const std::vector<const Prec*>& p, const std::vector<PrecItem<T>>& it,
+             const int* done, int kcap_, int ldw_, DevBuf& buf, hipStream_t s) {
+    pre = p;
+    items = it;
+    kcap = kcap_;
+    ldw = ldw_;
+    for (auto* x : pre)
+      if (!same_structure(x->F, pre[0]->F)) shared = false;
+    all = upload_items(items, done, buf, s);
+    one.clear();
+    if (!shared)
+      for (size_t j = 0; j < items.size(); ++j) {
+        Batched<PrecItem<T>> b;
+        b.dev = all.dev + j;
+        b.done = done + j;
+        b.n = 1;
+        one.push_back(b);
+      }
+  }
+  void enqueue(hipStream_t s) const {
+    if (shared) {
+      enqueue_prec_apply<T>(pre[0]->dev<T>(), pre[0]->fwd, pre[0]->bwd, items[0], all, kcap, ldw, s);
+    } else {
+      for (size_t j = 0; j < items.size(); ++j)
+        enqueue_prec_apply<T>(pre[j]->dev<T>(), pre[j]->fwd, pre[j]->bwd, items[j], one[j], kcap,
+                              ldw, s);
+    }
+  }
+};
+
+// Replays `steps` from a captured graph (captured on first use), or launches
+// them directly when eager.
+struct Replay {
+  GraphExec graph;
+  bool eager = false;
+  template <class F>
+  void run(hipStream_t s, int cls, F steps) {
+    if (eager) {
+      steps();
+      return;
+    }
+    if (!graph.x) {
+      CaptureGuard cg(s);
+      steps();
+      graph.g = cg.end();
+      LRC_HIP(hipGraphInstantiate(&graph.x, graph.g, nullptr, nullptr, 0));
+    }
+    ProfScope ps(cls, s);
+    LRC_HIP(hipGraphLaunch(graph.x, s));
+  }
+};
+
+// ------------------------------------------------------------------ median columns
+// Preconditioned Chebyshev on the median parameter's single column, for every
+// item at once; a few iterations per graph replay.
+struct MedianBatch {
+  static constexpr int kIterPerReplay = 4;
+  struct Buf {
+    DevBuf f, coef, x, dl, r, z, W, py, px, pcb, pst, part;
+  };
+  int nb = 0;
+  hipStream_t s = nullptr;
+  std::vector<std::unique_ptr<Buf>> b;
+  std::vector<std::unique_ptr<DevBuf>> bufs;
+  DevBuf items, ctl, done;
+  std::vector<MedCtl> hctl;
+  int64_t nmax = 0;
+  SpmmLaunch<double> sp0;
+  Batched<SpmmArgs<double>> spB;
+  PrecBatch<double> pb;
+  Replay rep;
+
+  DevBuf& newbuf() {
+    bufs.push_back(std::make_unique<DevBuf>());
+    return *bufs.back();
+  }
+
+  void solve(std::vector<SolveRun*>& run, hipStream_t s_, bool eager) {
+    s = s_;
+    nb = int(run.size());
+    rep.eager = eager;
+    std::vector<MedItem> hi(nb);
+    std::vector<SpmmLaunch<double>> sl;
+    std::vector<SpmmArgs<double>> sa;
+    std::vector<PrecItem<double>> pi;
+    std::vector<const Prec*> pre;
+    hctl.assign(nb, MedCtl{});
+    for (int j = 0; j < nb; ++j) {
+      SolveRun& r = *run[j];
+      const Prob& P = *r.P;
+      const Ops& op = *P.ops;
+      const int64_t n = op.n;
+      nmax = std::max(nmax, n);
+      b.push_back(std::make_unique<Buf>());
+      Buf& x = *b.back();
+      const size_t col = size_t(n) * 8 * 8;
+      x.f = upload(r.fmed, s);
+      x.coef = upload(r.coefmed, s);
+      for (DevBuf* d : {&x.x, &x.dl, &x.r, &x.z, &x.py, &x.px}) {
+        d->alloc(col);
+        LRC_HIP(hipMemsetAsync(d->p, 0, col, s));
+      }
+      x.W.alloc(col * op.q);
+      x.pcb.alloc(size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * 8 * 8);
+      x.pst.alloc(size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * 8 * 8);
+      x.part.alloc(size_t(med_partials()) * 8);
+      hi[j] = MedItem{x.f.as<double>(), x.W.as<double>(), x.coef.as<double>(), x.x.as<double>(),
+                      x.dl.as<double>(), x.r.as<double>(), x.z.as<double>(),
+                      x.part.as<double>(), n, op.q};
+      double* Wp[kMaxOps];
+      for (int i = 0; i < op.q; ++i) Wp[i] = x.W.as<double>() + size_t(i) * n * 8;
+      sl.push_back(make_spmm<double>(op.d64.data(), op.q, x.x.as<double>(), 8, nullptr, 1, 1, Wp,
+                                     8, 2));
+      sa.push_back(sl.back().a);
+      pi.push_back(PrecItem<double>{P.prec->p64.fw, P.prec->p64.bw, x.r.as<double>(), 8,
+                                    x.z.as<double>(), 8, nullptr, 1, x.py.as<double>(),
+                                    x.px.as<double>(), x.pcb.as<double>(), x.pst.as<double>()});
+      pre.push_back(P.prec.get());
+      double fn = 0.0;
+      for (double v : r.fmed) fn += v * v;
+      MedCtl& c = hctl[j];
+      c.target = r.median_tol * std::sqrt(fn);
+      c.c = r.cm;
+      c.dc = r.dm;
+      c.max_iter = 1000;
+    }
+    items.alloc(size_t(nb) * sizeof(MedItem));
+    LRC_HIP(hipMemcpyAsync(items.p, hi.data(), hi.size() * sizeof(MedItem), hipMemcpyHostToDevice, s));
+    ctl.alloc(size_t(nb) * sizeof(MedCtl));
+    LRC_HIP(hipMemcpyAsync(ctl.p, hctl.data(), hctl.size() * sizeof(MedCtl), hipMemcpyHostToDevice, s));
+    done.alloc(size_t(nb) * sizeof(int));
+    LRC_HIP(hipMemsetAsync(done.p, 0, done.bytes, s));
+    const int* dn = done.as<int>();
+    sp0 = merge_spmm(sl);
+    spB = upload_items(sa, dn, newbuf(), s);
+    pb.setup(pre, pi, dn, 1, 8, newbuf(), s);
+    const MedItem* it = items.as<MedItem>();
+    MedCtl* ct = ctl.as<MedCtl>();
+    int* dd = done.as<int>();
+    // residual of x = 0, then iterations
+    enqueue_spmm(sp0, spB, s);
+    launch_med_resid(it, dd, nb, s);
+    launch_med_check(it, ct, dd, nb, 0, s);
+    while (true) {
+      LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, hctl.size() * sizeof(MedCtl),
+                             hipMemcpyDeviceToHost, s));
+      LRC_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (const auto& c : hctl) all = all && c.state != 0;
+      if (all) break;
+      rep.run(s, kcls(K_GRAPH, false), [&]() {
+        for (int k = 0; k < kIterPerReplay; ++k) {
+          pb.enqueue(s);
+          launch_med_update(it, ct, dd, nb, nmax, s);
+          enqueue_spmm(sp0, spB, s);
+          launch_med_resid(it, dd, nb, s);
+          launch_med_check(it, ct, dd, nb, 1, s);
+        }
+      });
+    }
+    for (int j = 0; j < nb; ++j) run[j]->set_median_x0(b[j]->x.as<double>(), hctl[j].iters);
+    if (log_on())
+      for (int j = 0; j < nb; ++j)
+        std::fprintf(stderr, "{\"median\": %d, \"iters\": %d, \"norm\": %.6e, \"state\": %d}\n", j,
+                     hctl[j].iters, hctl[j].norm, hctl[j].state);
+  }
+};
+
+// ------------------------------------------------------------------ ChebyshevT
 // Lockstep ChebyshevT over the items' Cheb<T> objects (one per problem).
 template <class T>
 struct BatchCheb {
@@ -114,15 +292,12 @@ struct BatchCheb {
   std::vector<std::unique_ptr<DevBuf>> bufs;
   SpmmLaunch<T> spmm0;
   Batched<SpmmArgs<T>> spmmB;
-  bool shared_prec = true;
-  PrecItem<T> prec0{};
-  Batched<PrecItem<T>> precB;
-  std::vector<Batched<PrecItem<T>>> precOne;   // per item when the structures differ
+  PrecBatch<T> pb;
   TruncPlan<T> resid0, dstart0, supd0;
   TruncBatch<T> residB, dstartB, supdB;
   std::vector<TruncPlan<T>> dstep0;
   std::vector<TruncBatch<T>> dstepB;
-  GraphExec graph;
+  Replay rep;
 
   DevBuf& newbuf() {
     bufs.push_back(std::make_unique<DevBuf>());
@@ -131,13 +306,14 @@ struct BatchCheb {
 
   void setup(const std::vector<Cheb<T>*>& items, const std::vector<const LR<T>*>& rhs,
              const std::vector<double>& c_, const std::vector<double>& dc_, double tol,
-             int cycle_, hipStream_t s_) {
+             int cycle_, bool eager, hipStream_t s_) {
     it = items;
     B = rhs;
     c = c_;
     dc = dc_;
     cycle = cycle_;
     s = s_;
+    rep.eager = eager;
     nb = int(it.size());
     done.alloc(size_t(nb) * sizeof(int));
     ctl.alloc(size_t(nb) * sizeof(BCtl));
@@ -158,29 +334,20 @@ struct BatchCheb {
       spmm0 = merge_spmm(v);
       spmmB = upload_items(a, dn, newbuf(), s);
     }
-    // preconditioner: one batched apply when all structures agree
     {
       std::vector<PrecItem<T>> a;
-      for (auto* x : it) a.push_back(x->prec_item());
-      prec0 = a[0];
-      for (auto* x : it)
-        if (!same_structure(x->P->prec->F, it[0]->P->prec->F)) shared_prec = false;
-      DevBuf& pb = newbuf();
-      precB = upload_items(a, dn, pb, s);
-      if (!shared_prec)
-        for (int j = 0; j < nb; ++j) {
-          Batched<PrecItem<T>> b;
-          b.dev = pb.as<PrecItem<T>>() + j;
-          b.done = dn + j;
-          b.n = 1;
-          precOne.push_back(b);
-        }
+      std::vector<const Prec*> pre;
+      for (auto* x : it) {
+        a.push_back(x->prec_item());
+        pre.push_back(x->P->prec.get());
+      }
+      pb.setup(pre, a, dn, it[0]->cap, ld_for(it[0]->cap), newbuf(), s);
     }
-    auto site = [&](auto make, TruncPlan<T>& p0, TruncBatch<T>& b) {
+    auto site = [&](auto make, TruncPlan<T>& p0, TruncBatch<T>& bt) {
       std::vector<TruncPlan<T>> v;
       for (int j = 0; j < nb; ++j) v.push_back(make(j));
       p0 = merge_plans(v);
-      b = upload_plans(v, dn, newbuf(), s);
+      bt = upload_plans(v, dn, newbuf(), s);
     };
     site([&](int j) { return it[j]->resid_plan(*B[j], it[j]->norm.template as<double>(), tol); },
          resid0, residB);
@@ -201,48 +368,28 @@ struct BatchCheb {
     }
   }
 
-  void precond() {
-    if (shared_prec) {
-      const Prec& P0 = *it[0]->P->prec;
-      enqueue_prec_apply<T>(P0.dev<T>(), P0.fwd, P0.bwd, prec0, precB, it[0]->cap,
-                            ld_for(it[0]->cap), s);
-    } else {
-      for (int j = 0; j < nb; ++j) {
-        const Prec& Pj = *it[j]->P->prec;
-        enqueue_prec_apply<T>(Pj.dev<T>(), Pj.fwd, Pj.bwd, it[j]->prec_item(), precOne[j],
-                              it[j]->cap, ld_for(it[j]->cap), s);
-      }
-    }
-  }
-
   void resid(int after_update) {
     enqueue_spmm(spmm0, spmmB, s);
     enqueue_trunc(resid0, residB, s);
     launch_batch_check(ctl.as<BCtl>(), done.as<int>(), nb, after_update, s);
   }
 
+  // one restart cycle: D = T(P^-1 R / dc), then `cycle` updates
+  // S = T(S + D), each followed by the residual and, before the next, the
+  // direction D = T(alpha D + beta P^-1 R)
   void cycle_steps() {
-    precond();
+    pb.enqueue(s);
     enqueue_trunc(dstart0, dstartB, s);
     for (int k = 0; k < cycle; ++k) {
       enqueue_trunc(supd0, supdB, s);
       resid(1);
       if (k + 1 == cycle) break;
-      precond();
+      pb.enqueue(s);
       enqueue_trunc(dstep0[k], dstepB[k], s);
     }
   }
 
-  void capture() {
-    graph.reset();
-    CaptureGuard cg(s);
-    cycle_steps();
-    graph.g = cg.end();
-    LRC_HIP(hipGraphInstantiate(&graph.x, graph.g, nullptr, nullptr, 0));
-  }
-
   // Runs the lockstep iteration.  Items with init_done[j] set do nothing.
-  // target/max_iter/stall_limit per item; returns the final control states.
   void run(const std::vector<int>& init_done, const std::vector<double>& target,
            const std::vector<int>& max_iter, int stall_limit) {
     for (int j = 0; j < nb; ++j) {
@@ -261,7 +408,6 @@ struct BatchCheb {
     LRC_HIP(hipMemcpyAsync(done.p, init_done.data(), size_t(nb) * sizeof(int),
                            hipMemcpyHostToDevice, s));
     resid(0);
-    if (!graph.x) capture();
     while (true) {
       LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, size_t(nb) * sizeof(BCtl),
                              hipMemcpyDeviceToHost, s));
@@ -269,19 +415,13 @@ struct BatchCheb {
       bool all = true;
       for (const auto& h : hctl) all = all && h.state != 0;
       if (all) break;
-      ProfScope ps(kcls(K_GRAPH, is_f32<T>()), s);
-      LRC_HIP(hipGraphLaunch(graph.x, s));
+      rep.run(s, kcls(K_GRAPH, is_f32<T>()), [&]() { cycle_steps(); });
     }
     if (log_on())
       for (int j = 0; j < nb; ++j)
         std::fprintf(stderr,
-                     "{\"batch\": %d, \"item\": %d, \"iters\": %d, \"norm\": %.6e, \"state\": %d}\n",
+                     "{\"cheb\": %d, \"item\": %d, \"iters\": %d, \"norm\": %.6e, \"state\": %d}\n",
                      int(sizeof(T)), j, hctl[j].iters, hctl[j].last, hctl[j].state);
-  }
-
-  static bool log_on() {
-    static const bool on = std::getenv("LRC_LOG") != nullptr;
-    return on;
   }
 };
 
@@ -307,58 +447,114 @@ struct OwnStream {
   }
 };
 
+// B = F - L(X0) for every item with an initial term (one SpMM + one
+// truncation launch for all of them); F itself otherwise.
+void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
+  const int nb = int(run.size());
+  std::vector<int> hd(nb, 1);
+  bool any = false;
+  for (int j = 0; j < nb; ++j) {
+    SolveRun& r = *run[j];
+    if (r.P->rank_x0 == 0) {
+      LRC_CHECK(r.P->rF <= r.B64.cap, ST_EINVAL,
+                "right-hand side rank exceeds the room left by q * rank_cap in 128 columns");
+      cast_lr<double, double>(r.P->F64, r.B64, s);
+    } else {
+      hd[j] = 0;
+      any = true;
+    }
+  }
+  if (!any) return;
+  DevBuf done = upload(hd, s);
+  std::vector<DevBuf> W0(nb);
+  std::vector<SpmmLaunch<double>> sl;
+  std::vector<SpmmArgs<double>> sa;
+  std::vector<TruncPlan<double>> tp;
+  for (int j = 0; j < nb; ++j) {
+    SolveRun& r = *run[j];
+    const Prob& P = *r.P;
+    const Ops& op = *P.ops;
+    const LR<double>& X0 = P.X0;
+    W0[j].alloc(size_t(op.q) * op.n * X0.ld * 8);
+    double* Wp[kMaxOps];
+    for (int i = 0; i < op.q; ++i) Wp[i] = W0[j].as<double>() + size_t(i) * op.n * X0.ld;
+    sl.push_back(make_spmm<double>(op.d64.data(), op.q, X0.u(), X0.ld, X0.r(), 0, X0.cap, Wp,
+                                   X0.ld, 2));
+    sa.push_back(sl.back().a);
+    tp.push_back(r.rhs_plan(o, Wp));
+  }
+  DevBuf sb, tb;
+  enqueue_spmm(merge_spmm(sl), upload_items(sa, done.as<int>(), sb, s), s);
+  enqueue_trunc(merge_plans(tp), upload_plans(tp, done.as<int>(), tb, s), s);
+  LRC_HIP(hipStreamSynchronize(s));   // the temporaries above are released on return
+}
+
 }  // namespace
 
-std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc_opts& o,
-                                      lrc_info* infos) {
-  const int nb = int(probs.size());
-  LRC_CHECK(nb >= 1, ST_EINVAL, "lrc_solve_batched: no problems");
-  LRC_CHECK(o.restart >= 1 && o.restart <= 64, ST_EINVAL,
-            "lrc_solve_batched: restart must be in [1, 64] (one cycle is one graph)");
-  Ctx& cx = *probs[0]->ctx;
-  for (auto* P : probs)
-    LRC_CHECK(P->ctx == probs[0]->ctx, ST_EINVAL,
+void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
+  const int nb = int(run.size());
+  LRC_CHECK(nb >= 1, ST_EINVAL, "lockstep: no problems");
+  Ctx& cx = *run[0]->P->ctx;
+  for (auto* r : run)
+    LRC_CHECK(r->P->ctx == run[0]->P->ctx, ST_EINVAL,
               "lrc_solve_batched: all problems must belong to one context");
-  std::vector<SolveRun> run(nb);
-  for (int j = 0; j < nb; ++j) run[j].prepare(*probs[j], o, 0, nullptr, nullptr, nullptr);
-  for (auto& r : run)
-    if (o.precision != LRC_FP64) r.alloc_mixed();
+  const bool eager = o.eager != 0;
   cx.sync();
   OwnStream own;
   hipStream_t s = own.s;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto since = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  };
+  // 1. median-parameter columns (init LRC_INIT_MEDIAN)
+  {
+    std::vector<SolveRun*> med;
+    for (auto* r : run)
+      if (r->jmed >= 0) med.push_back(r);
+    if (!med.empty()) {
+      MedianBatch mb;
+      mb.solve(med, s, eager);
+      LRC_HIP(hipStreamSynchronize(s));
+      cx.sync();
+    }
+  }
+  const double t_median = since();
+  // 2. right-hand sides B = F - L(X0)
+  build_rhs(run, o, s);
+  const double t_rhs = since();
+  // 3. ChebyshevT (fp64), or fp32 ChebyshevT inside fp64 refinement
   std::vector<double> c(nb), dc(nb), tgt(nb);
   std::vector<int> mi(nb);
   for (int j = 0; j < nb; ++j) {
-    c[j] = std::max(run[j].c, 1e-12 * run[j].dc);
-    dc[j] = run[j].dc;
-    tgt[j] = run[j].target;
-    mi[j] = run[j].max_iter;
+    c[j] = run[j]->c;
+    dc[j] = run[j]->dc;
+    tgt[j] = run[j]->target;
+    mi[j] = run[j]->max_iter;
   }
   if (o.precision == LRC_FP64) {
     BatchCheb<double> bc;
     std::vector<Cheb<double>*> items;
     std::vector<const LR<double>*> rhs;
-    for (auto& r : run) {
-      items.push_back(r.c64.get());
-      rhs.push_back(&r.B64);
+    for (auto* r : run) {
+      items.push_back(r->c64.get());
+      rhs.push_back(&r->B64);
     }
-    bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, s);
+    bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
     bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30);
     for (int j = 0; j < nb; ++j) {
-      run[j].iters = bc.hctl[j].iters;
-      run[j].papp = bc.hctl[j].iters;
-      run[j].conv = bc.hctl[j].state == 1;
-      run[j].last = bc.hctl[j].last;
-      run[j].flags |= read_info(run[j].c64->tr.st.info, s);
+      run[j]->iters = bc.hctl[j].iters;
+      run[j]->papp = bc.hctl[j].iters;
+      run[j]->conv = bc.hctl[j].state == 1;
+      run[j]->last = bc.hctl[j].last;
+      run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
     }
   } else {
-    // fp32 inner ChebyshevT in lockstep, wrapped in lockstep fp64 refinement
     DevBuf odone(size_t(nb) * sizeof(int)), octl(size_t(nb) * sizeof(BCtl));
     std::vector<BCtl> ho(nb);
     std::vector<int> hd(nb, 0);
     for (int j = 0; j < nb; ++j) {
       ho[j] = BCtl{};
-      ho[j].norm = run[j].c64->norm.as<double>();
+      ho[j].norm = run[j]->c64->norm.as<double>();
       ho[j].target = tgt[j];
       ho[j].max_iter = 1 << 30;
       ho[j].stall_limit = 1 << 30;
@@ -380,12 +576,12 @@ std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc
       std::vector<SpmmLaunch<double>> v;
       std::vector<SpmmArgs<double>> a;
       std::vector<TruncPlan<double>> vr, va;
-      for (auto& r : run) {
-        Cheb<double>& C = *r.c64;
+      for (auto* r : run) {
+        Cheb<double>& C = *r->c64;
         v.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
         a.push_back(v.back().a);
-        vr.push_back(C.resid_plan(r.B64, C.norm.as<double>(), r.rhs_tol));
-        va.push_back(r.accumulate_plan(o));
+        vr.push_back(C.resid_plan(r->B64, C.norm.as<double>(), r->rhs_tol));
+        va.push_back(r->accumulate_plan(o));
       }
       sp0 = merge_spmm(v);
       spB = upload_items(a, od, nbuf(), s);
@@ -398,11 +594,11 @@ std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc
     {
       std::vector<Cheb<float>*> items;
       std::vector<const LR<float>*> rhs;
-      for (auto& r : run) {
-        items.push_back(r.c32.get());
-        rhs.push_back(&r.Bin);
+      for (auto* r : run) {
+        items.push_back(r->c32.get());
+        rhs.push_back(&r->Bin);
       }
-      bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, s);
+      bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
     }
     const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
     while (true) {
@@ -416,45 +612,62 @@ std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc
       std::vector<int> idone(nb, 1), imax(nb, 0);
       std::vector<double> itgt(nb, 0.0);
       for (int j = 0; j < nb; ++j) {
-        SolveRun& r = run[j];
-        if (ho[j].state == 0 && hd[j] == 0) {
-          r.last = ho[j].last;
-          log_line("refine64", r.refinements, r.last, r.P->fnorm);
-          if (r.refinements >= r.refine_max || r.iters >= r.max_iter) {
-            hd[j] = 1;
-            continue;
-          }
+        SolveRun& r = *run[j];
+        if (hd[j]) continue;
+        r.last = ho[j].last;
+        log_line("refine64", r.refinements, r.last, r.P->fnorm);
+        if (ho[j].state != 0) {
+          r.conv = ho[j].state == 1;
+          hd[j] = 1;
+        } else if (r.refinements >= r.refine_max || r.iters >= r.max_iter) {
+          hd[j] = 1;
+        } else {
+          // inner solve: to its relative tolerance, to half the outer target,
+          // or until the fp32 residual stagnates at its rounding floor
           idone[j] = 0;
           imax[j] = r.max_iter - r.iters;
           itgt[j] = std::max(itol * r.last, 0.5 * r.target);
           any = true;
-        } else if (hd[j] == 0) {
-          r.last = ho[j].last;
-          r.conv = ho[j].state == 1;
-          hd[j] = 1;
         }
       }
       LRC_HIP(hipMemcpyAsync(odone.p, hd.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice,
                              s));
       if (!any) break;
       for (int j = 0; j < nb; ++j)
-        if (!idone[j]) cast_lr<double, float>(run[j].c64->R, run[j].Bin, s);
+        if (!idone[j]) cast_lr<double, float>(run[j]->c64->R, run[j]->Bin, s);
       bc.run(idone, itgt, imax, 2);
       for (int j = 0; j < nb; ++j) {
         if (idone[j]) continue;
-        run[j].iters += bc.hctl[j].iters;
-        run[j].papp += bc.hctl[j].iters;
-        ++run[j].refinements;
-        run[j].accumulate_plan_inputs(s);
+        run[j]->iters += bc.hctl[j].iters;
+        run[j]->papp += bc.hctl[j].iters;
+        ++run[j]->refinements;
+        run[j]->accumulate_plan_inputs(s);
       }
       enqueue_trunc(acc0, accB, s);
     }
     for (int j = 0; j < nb; ++j) {
-      run[j].flags |= read_info(run[j].c64->tr.st.info, s);
-      run[j].flags |= read_info(run[j].c32->tr.st.info, s);
+      run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
+      run[j]->flags |= read_info(run[j]->c32->tr.st.info, s);
     }
   }
   LRC_HIP(hipStreamSynchronize(s));
+  if (log_on())
+    std::fprintf(stderr,
+                 "{\"lockstep_s\": {\"items\": %d, \"median\": %.4f, \"rhs\": %.4f, \"cheb\": %.4f}}\n",
+                 nb, t_median, t_rhs - t_median, since() - t_rhs);
+}
+
+std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc_opts& o,
+                                      lrc_info* infos) {
+  const int nb = int(probs.size());
+  LRC_CHECK(nb >= 1, ST_EINVAL, "lrc_solve_batched: no problems");
+  std::vector<SolveRun> run(nb);
+  std::vector<SolveRun*> ptr(nb);
+  for (int j = 0; j < nb; ++j) {
+    run[j].prepare(*probs[j], o, 0, nullptr, nullptr, nullptr);
+    ptr[j] = &run[j];
+  }
+  lockstep(ptr, o);
   std::vector<lrc_status> st(nb);
   for (int j = 0; j < nb; ++j) st[j] = run[j].finish(o, infos ? infos + j : nullptr);
   return st;

@@ -386,84 +386,112 @@ template void launch_cast<double, double>(const double*, int, double*, int, int6
 template void launch_cast<float, float>(const float*, int, float*, int, int64_t, const int*, int,
                                         int, hipStream_t);
 
-// sum of squares of a vector in fixed order: blocks write partials, the last
-// stage (one block) adds them.
-__global__ void sumsq_partial(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+// ============================================================== median-parameter solve
+// Lockstep preconditioned Chebyshev iteration on one column per item (the
+// upper-median parameter's system): every kernel's grid z runs over the items.
+constexpr int kMedBlocks = 256;   // residual partial sums per item (fixed: deterministic sums)
+
+// dl = alpha dl + beta z ; x += dl   (alpha, beta from the item's control state)
+__global__ __launch_bounds__(256) void med_update_kernel(const MedItem* __restrict__ items,
+                                                         const MedCtl* __restrict__ ctl,
+                                                         const int* __restrict__ done) {
+  const int j = blockIdx.z;
+  if (done[j]) return;
+  const MedItem& a = items[j];
+  const double al = ctl[j].alpha, be = ctl[j].beta;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double d = al * a.dl[i * 8] + be * a.z[i * 8];
+    a.dl[i * 8] = d;
+    a.x[i * 8] += d;
+  }
+}
+
+// r = f - sum_t coef_t W_t, and per-block partial sums of r^2
+__global__ __launch_bounds__(256) void med_resid_kernel(const MedItem* __restrict__ items,
+                                                        const int* __restrict__ done) {
   __shared__ double sh[256];
-  double a = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    a += x[i] * x[i];
-  sh[threadIdx.x] = a;
+  const int j = blockIdx.z;
+  if (done[j]) return;
+  const MedItem& a = items[j];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    double v = a.f[i];
+    for (int t = 0; t < a.q; ++t) v -= a.coef[t] * a.W[(int64_t(t) * a.n + i) * 8];
+    a.r[i * 8] = v;
+    acc += v * v;
+  }
+  sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) a.part[blockIdx.x] = sh[0];
 }
-__global__ void sumsq_final(const double* __restrict__ part, int np, double* out) {
+
+// One workgroup per item: the residual norm, the stopping test, and the next
+// step's coefficients (rho_0 = c/dc with (alpha, beta) = (0, 1/dc); then
+// rho' = 1 / (2 dc/c - rho), alpha = rho' rho, beta = 2 rho' / c).
+__global__ __launch_bounds__(256) void med_check_kernel(const MedItem* __restrict__ items,
+                                                        MedCtl* __restrict__ ctl,
+                                                        int* __restrict__ done, int after_update) {
   __shared__ double sh[256];
-  double a = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) a += part[i];
-  sh[threadIdx.x] = a;
+  const int j = blockIdx.x;
+  if (done[j]) return;
+  const MedItem& a = items[j];
+  sh[threadIdx.x] = threadIdx.x < kMedBlocks ? a.part[threadIdx.x] : 0.0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
-}
-void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s) {
-  // `out` must hold 1 + 256 doubles: out[0] result, out[1..256] partials
-  hipLaunchKernelGGL(sumsq_partial, dim3(256), dim3(256), 0, s, x, n, out + 1);
-  hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, s, out + 1, 256, out);
-  LRC_HIP(hipGetLastError());
+  if (threadIdx.x != 0) return;
+  MedCtl c = ctl[j];
+  c.norm = sqrt(sh[0]);
+  if (after_update) ++c.iters;
+  if (!isfinite(c.norm)) c.state = 2;
+  else if (c.norm <= c.target) c.state = 1;
+  else if (c.iters >= c.max_iter) c.state = 2;
+  if (c.state == 0) {
+    if (!after_update) {
+      c.rho = c.c / c.dc;
+      c.alpha = 0.0;
+      c.beta = 1.0 / c.dc;
+    } else {
+      const double rn = 1.0 / (2.0 * c.dc / c.c - c.rho);
+      c.alpha = rn * c.rho;
+      c.beta = 2.0 * rn / c.c;
+      c.rho = rn;
+    }
+  }
+  ctl[j] = c;
+  if (c.state) done[j] = 1;
 }
 
-// r = f - sum_i coef_i W_i   (single column)
-struct VecPtrs {
-  double* W[kMaxOps];
-};
-__global__ void vec_resid_kernel(const double* __restrict__ f, VecPtrs Wp,
-                                 const double* __restrict__ coef, int q, int64_t n,
-                                 double* __restrict__ r) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    double v = f[i];
-    for (int t = 0; t < q; ++t) v -= coef[t] * Wp.W[t][i * 8];
-    r[i * 8] = v;
-  }
-}
-void launch_vec_resid(const double* f, double* const* W, const double* coef, int q, int64_t n,
-                      double* r, hipStream_t s) {
-  VecPtrs p;
-  for (int i = 0; i < q; ++i) p.W[i] = W[i];
-  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 4096);
-  hipLaunchKernelGGL(vec_resid_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, f, p, coef, q, n,
-                     r);
+void launch_med_update(const MedItem* items, const MedCtl* ctl, const int* done, int nb,
+                       int64_t nmax, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(ceil_div(nmax, 256), 1), 2048);
+  ProfScope ps(kcls(K_VECTOR, false), s);
+  hipLaunchKernelGGL(med_update_kernel, dim3(unsigned(blocks), 1, unsigned(nb)), dim3(256), 0, s,
+                     items, ctl, done);
   LRC_HIP(hipGetLastError());
 }
-
-// Chebyshev step on single columns stored with stride 8:
-//   dl = alpha * dl + beta * z ;  x += dl
-__global__ void vec_cheb_kernel(double* __restrict__ x, double* __restrict__ dl,
-                                const double* __restrict__ z, int64_t n, double alpha,
-                                double beta) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const double d = alpha * dl[i * 8] + beta * z[i * 8];
-    dl[i * 8] = d;
-    x[i * 8] += d;
-  }
-}
-void launch_vec_cheb_update(double* x, double* dl, const double* z, int64_t n, double alpha,
-                            double beta, hipStream_t s) {
-  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 4096);
-  hipLaunchKernelGGL(vec_cheb_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, dl, z, n, alpha,
-                     beta);
+void launch_med_resid(const MedItem* items, const int* done, int nb, hipStream_t s) {
+  ProfScope ps(kcls(K_VECTOR, false), s);
+  hipLaunchKernelGGL(med_resid_kernel, dim3(kMedBlocks, 1, unsigned(nb)), dim3(256), 0, s, items,
+                     done);
   LRC_HIP(hipGetLastError());
 }
+void launch_med_check(const MedItem* items, MedCtl* ctl, int* done, int nb, int after_update,
+                      hipStream_t s) {
+  ProfScope ps(kcls(K_VECTOR, false), s);
+  hipLaunchKernelGGL(med_check_kernel, dim3(unsigned(nb)), dim3(256), 0, s, items, ctl, done,
+                     after_update);
+  LRC_HIP(hipGetLastError());
+}
+int med_partials() { return kMedBlocks; }
 
 __global__ void fill_kernel(double* p, int64_t count, double v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;

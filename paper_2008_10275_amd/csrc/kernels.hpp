@@ -328,12 +328,35 @@ size_t residual_workspace_bytes(int64_t n, int64_t m);
 template <class Tin, class Tout>
 void launch_cast(const Tin* x, int ldx, Tout* y, int ldy, int64_t rows, const int* cols_dev,
                  int cols_const, int colcap, hipStream_t s);
-// out[j] = sum over rows of x[j]^2 per column, fp64 (rows x cols) -> host-visible buffer
-void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
-void launch_vec_resid(const double* f, double* const* W, const double* coef, int q, int64_t n,
-                      double* r, hipStream_t s);
-void launch_vec_cheb_update(double* x, double* dl, const double* z, int64_t n, double alpha,
-                            double beta, hipStream_t s);
+// Lockstep single-column Chebyshev solves (the median-parameter systems).
+// Vectors are column 0 of n x 8 row-major blocks.
+struct MedItem {
+  const double* f;      // n: right-hand side column
+  const double* W;      // q blocks of n x 8: K_t x (block t at W + t * n * 8)
+  const double* coef;   // q: the median parameter's diagonal entries d_t
+  double* x;            // iterate
+  double* dl;           // last step
+  double* r;            // residual f - sum_t coef_t K_t x
+  const double* z;      // preconditioned residual
+  double* part;         // med_partials() partial sums of r^2
+  int64_t n;
+  int q;
+};
+struct MedCtl {
+  double target;        // absolute residual target
+  double c, dc;         // spectrum half-width and centre
+  double rho, alpha, beta;
+  double norm;          // last residual norm
+  int iters, max_iter;
+  int state;            // 0 running, 1 converged, 2 stopped
+  int pad;
+};
+int med_partials();
+void launch_med_update(const MedItem* items, const MedCtl* ctl, const int* done, int nb,
+                       int64_t nmax, hipStream_t s);
+void launch_med_resid(const MedItem* items, const int* done, int nb, hipStream_t s);
+void launch_med_check(const MedItem* items, MedCtl* ctl, int* done, int nb, int after_update,
+                      hipStream_t s);
 void launch_fill(double* p, int64_t count, double v, hipStream_t s);
 void launch_copy_cols(const double* src, int lds, double* dst, int ldd, int64_t rows, int cols,
                       hipStream_t s);

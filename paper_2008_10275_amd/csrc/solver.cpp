@@ -466,86 +466,6 @@ PrecItem<T> Cheb<T>::prec_item() const {
                      py.as<T>(), px.as<T>(), pcb.as<T>(), pst.as<T>()};
 }
 
-template <class T>
-void Cheb<T>::precond() {
-  enqueue_prec_apply<T>(P->prec->dev<T>(), P->prec->fwd, P->prec->bwd, prec_item(),
-                        Batched<PrecItem<T>>(), cap, ld_for(cap), P->ctx->stream);
-}
-
-template <class T>
-void Cheb<T>::residual(const LR<T>& B, double* norm_dev, double tol_) {
-  hipStream_t s = P->ctx->stream;
-  enqueue_spmm(spmm_plan(S.u(), S.ld, S.r()), Batched<SpmmArgs<T>>(), s);
-  enqueue_trunc(resid_plan(B, norm_dev, tol_), TruncBatch<T>(), s);
-}
-
-template <class T>
-int Cheb<T>::solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c, double dc,
-                   int max_iter, bool* converged, double* last_norm, int* prec_applies,
-                   int* flags, double abs_target, int stall_limit) {
-  Ctx& ctx = *P->ctx;
-  hipStream_t s = ctx.stream;
-  tol = o.trunc_tol;
-  c = std::max(c, 1e-12 * dc);
-  const double sigma = dc / c;
-  LRC_HIP(hipMemsetAsync(S.rank.p, 0, 16, s));
-  LRC_HIP(hipMemsetAsync(D.rank.p, 0, 16, s));
-  double* nd = norm.as<double>();
-  auto read_norm = [&]() {
-    LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, sizeof(double), hipMemcpyDeviceToHost, s));
-    ctx.sync();
-    return ctx.pinned[0];
-  };
-  const TruncBatch<T> one;
-  // residual truncation uses the solver's tolerance relative to the residual
-  auto resid = [&]() {
-    residual(B, nd, tol);
-    return read_norm();
-  };
-  int iters = 0;
-  *converged = false;
-  const char* phase = sizeof(T) == 8 ? "cheb64" : "cheb32";
-  double nr = resid();
-  *last_norm = nr;
-  log_line(phase, iters, nr, ref_norm);
-  const double target = std::max(o.res_tol * ref_norm, abs_target);
-  const int cycle = o.restart > 0 ? o.restart : (1 << 30);
-  double best = nr;
-  int stall = 0;
-  while (true) {
-    if (!std::isfinite(nr)) break;
-    if (nr <= target) { *converged = true; break; }
-    if (iters >= max_iter || stall >= stall_limit) break;
-    // (re)start
-    precond();
-    ++*prec_applies;
-    enqueue_trunc(dstart_plan(dc), one, s);
-    double rho = c / dc;
-    for (int k = 0; k < cycle; ++k) {
-      enqueue_trunc(supd_plan(), one, s);   // S <- T(S + D)
-      ++iters;
-      nr = resid();
-      *last_norm = nr;
-      log_line(phase, iters, nr, ref_norm);
-      // stagnation: no 30% gain over the best residual for `stall_limit` checks
-      if (nr < 0.7 * best) { best = nr; stall = 0; }
-      else { best = std::min(best, nr); ++stall; }
-      if (!(nr > target) || iters >= max_iter || k == cycle - 1 || !std::isfinite(nr) ||
-          stall >= stall_limit)
-        break;
-      const double rho_new = 1.0 / (2.0 * sigma - rho);
-      precond();
-      ++*prec_applies;
-      // D <- T(rho' rho D + (2 rho' / c) P^-1 R)
-      enqueue_trunc(dstep_plan(rho_new * rho, 2.0 * rho_new / c), one, s);
-      rho = rho_new;
-    }
-  }
-  LRC_HIP(hipMemcpyAsync(ctx.pinned_i, tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
-  ctx.sync();
-  *flags |= ctx.pinned_i[0];
-  return iters;
-}
 template struct Cheb<double>;
 template struct Cheb<float>;
 
@@ -633,137 +553,21 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
   return std::sqrt(tot);
 }
 
-// Right-hand side B = F - L(X0) in factored fp64 form (not truncated by rank
-// beyond the truncation capacity), into Bout.
-static void build_rhs(Prob& P, const LR<double>& X0, int r0, LR<double>& Bout, const lrc_opts& o,
-                      Truncator<double>& tr) {
-  Ctx& ctx = *P.ctx;
-  hipStream_t s = ctx.stream;
-  const Ops& op = *P.ops;
-  const int64_t n = op.n, m = P.m;
-  if (r0 == 0) {
-    LRC_CHECK(P.rF <= Bout.cap, ST_EINVAL,
-              "right-hand side rank exceeds the room left by q * rank_cap in 128 columns");
-    cast_lr<double, double>(P.F64, Bout, s);
-    return;
-  }
-  const int ld0 = X0.ld;
-  DevBuf W0(size_t(op.q) * n * ld0 * 8);
-  double* W0p[kMaxOps];
-  for (int i = 0; i < op.q; ++i) W0p[i] = W0.as<double>() + size_t(i) * n * ld0;
-  launch_spmm<double>(op.d64.data(), op.q, X0.u(), ld0, X0.r(), 0, X0.cap, W0p, ld0, 2, s);
-  BlockView<double> A{}, B{};
-  CoreView c{};
-  add_block(A, P.F64.u(), P.F64.ld, P.F64.r(), 0);
-  add_block(B, P.F64.v(), P.F64.ld, P.F64.r(), 0);
-  add_core(c, P.F64.sv(), 1.0, P.F64.r(), 0);
-  for (int i = 0; i < op.q; ++i) {
-    add_block(A, W0p[i], ld0, X0.r(), 0);
-    add_block(B, X0.v(), ld0, X0.r(), 0, P.drow(i));
-    add_core(c, X0.sv(), -1.0, X0.r(), 0);
-  }
-  DevBuf nrm(16);
-  const int cap = std::min(Bout.cap, 64);
-  tr.run(A, n, B, m, c, cap, std::min(1e-14, o.trunc_tol * 1e-3), Bout.u(), Bout.ld, Bout.v(),
-         Bout.ld, Bout.sv(), Bout.r(), nrm.as<double>(), s);
-}
-
-// Median-parameter solve  A(d_med) x = F[:, jmed]  by preconditioned Chebyshev
-// on one column (fp64, no truncation needed).
-static int median_solve(Prob& P, int jmed, double c, double dc, double tol, int max_iter,
-                        LR<double>& X0) {
-  Ctx& ctx = *P.ctx;
-  hipStream_t s = ctx.stream;
-  const Ops& op = *P.ops;
-  const int64_t n = op.n, m = P.m;
-  // f = FU diag(Fs) FV[jmed, :]^T
-  std::vector<double> f(n, 0.0);
-  for (int a = 0; a < P.rF; ++a) {
-    const double w = P.Fs[a] * P.FV[size_t(a) * m + jmed];
-    for (int64_t i = 0; i < n; ++i) f[i] += w * P.FU[size_t(a) * n + i];
-  }
-  double fn = 0.0;
-  for (double v : f) fn += v * v;
-  fn = std::sqrt(fn);
-  std::vector<double> coef(op.q);
-  for (int i = 0; i < op.q; ++i) coef[i] = P.d[size_t(jmed) * op.q + i];
-  DevBuf fd = upload(f, s), cd = upload(coef, s);
-  const int ld = 8;
-  DevBuf x(size_t(n) * ld * 8), dl(size_t(n) * ld * 8), r(size_t(n) * ld * 8),
-      z(size_t(n) * ld * 8), Wb(size_t(op.q) * n * ld * 8), nrm(300 * 8);
-  LRC_HIP(hipMemsetAsync(x.p, 0, x.bytes, s));
-  LRC_HIP(hipMemsetAsync(dl.p, 0, dl.bytes, s));
-  LRC_HIP(hipMemsetAsync(r.p, 0, r.bytes, s));
-  LRC_HIP(hipMemsetAsync(z.p, 0, z.bytes, s));
-  const int64_t cbr = P.prec->cb_rows;
-  DevBuf py(size_t(n) * ld * 8), px(size_t(n) * ld * 8), pcb(size_t(std::max<int64_t>(cbr, 1)) * ld * 8),
-      pst(size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * ld * 8);
-  double* Wp[kMaxOps];
-  for (int i = 0; i < op.q; ++i) Wp[i] = Wb.as<double>() + size_t(i) * n * ld;
-  auto residual = [&]() {
-    launch_spmm<double>(op.d64.data(), op.q, x.as<double>(), ld, nullptr, 1, 1, Wp, ld, 2, s);
-    launch_vec_resid(fd.as<double>(), Wp, cd.as<double>(), op.q, n, r.as<double>(), s);
-    // norm of column 0 (stride 8): copy to a packed vector via cast (1 column)
-    launch_cast<double, double>(r.as<double>(), ld, z.as<double>(), 1, n, nullptr, 1, 1, s);
-    launch_sumsq(z.as<double>(), n, nrm.as<double>(), s);
-    LRC_HIP(hipMemcpyAsync(ctx.pinned, nrm.p, 8, hipMemcpyDeviceToHost, s));
-    ctx.sync();
-    return std::sqrt(ctx.pinned[0]);
-  };
-  auto prec = [&]() {
-    launch_prec_apply<double>(P.prec->p64, P.prec->fwd, P.prec->bwd, r.as<double>(), ld,
-                              z.as<double>(), ld, nullptr, 1, 1, py.as<double>(), px.as<double>(),
-                              pcb.as<double>(), pst.as<double>(), ld, s);
-  };
-  c = std::max(c, 1e-12 * dc);
-  const double sigma = dc / c;
-  double nr = residual();
-  int it = 0;
-  if (nr > tol * fn) {
-    prec();
-    // dl = z / dc ; x += dl
-    launch_vec_cheb_update(x.as<double>(), dl.as<double>(), z.as<double>(), n, 0.0, 1.0 / dc, s);
-    double rho = c / dc;
-    ++it;
-    nr = residual();
-    while (nr > tol * fn && it < max_iter && std::isfinite(nr)) {
-      const double rho_new = 1.0 / (2.0 * sigma - rho);
-      prec();
-      launch_vec_cheb_update(x.as<double>(), dl.as<double>(), z.as<double>(), n, rho_new * rho,
-                             2.0 * rho_new / c, s);
-      rho = rho_new;
-      ++it;
-      nr = residual();
-    }
-  }
-  // X0 = x 1^T
-  X0.alloc(n, m, 1, s);
-  launch_copy_cols(x.as<double>(), ld, X0.u(), X0.ld, n, 1, s);
-  std::vector<double> ones(size_t(m) * X0.ld, 0.0);
-  for (int64_t j = 0; j < m; ++j) ones[size_t(j) * X0.ld] = 1.0;
-  const double one = 1.0;
-  const int r1 = 1;
-  LRC_HIP(hipMemcpyAsync(X0.V.p, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
-  LRC_HIP(hipMemcpyAsync(X0.s.p, &one, 8, hipMemcpyHostToDevice, s));
-  LRC_HIP(hipMemcpyAsync(X0.rank.p, &r1, 4, hipMemcpyHostToDevice, s));
-  ctx.sync();
-  return it;
-}
-
 // ------------------------------------------------------------------ solve
 void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
                        const double* V0) {
   t0 = clk::now();
   P = &P_;
   Prob& Pr = *P;
-  Ctx& ctx = *Pr.ctx;
-  hipStream_t s = ctx.stream;
+  hipStream_t s = Pr.ctx->stream;
   const Ops& op = *Pr.ops;
   const int64_t n = op.n, m = Pr.m;
   LRC_CHECK(Pr.prec != nullptr, ST_EINVAL, "lrc_solve: call lrc_prob_precondition first");
   LRC_CHECK(o.rank_cap >= 1 && o.rank_cap <= kPrecCols, ST_EINVAL,
             "lrc_solve: rank_cap must be in [1, 64]");
   LRC_CHECK(o.trunc_tol >= 0.0 && o.res_tol >= 0.0, ST_EINVAL, "lrc_solve: negative tolerance");
+  LRC_CHECK(o.restart >= 1 && o.restart <= 64, ST_EINVAL,
+            "lrc_solve: restart must be in [1, 64] (one restart cycle is one graph)");
   c = o.cheb_c;
   dc = o.cheb_d;
   if (!(c > 0.0) || !(dc > 0.0)) {
@@ -777,23 +581,32 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     c = 0.5 * (hi - lo);
     dc = 0.5 * (hi + lo);
   }
+  c = std::max(c, 1e-12 * dc);
   inf = lrc_info{};
   // fixed initial term X0
   Pr.X0 = LR<double>();
   Pr.rank_x0 = 0;
+  jmed = -1;
   if (o.init == LRC_INIT_MEDIAN) {
-    const int jmed = int(m / 2);
-    // the single median column has its own, much narrower, spectrum interval
+    // upper-median column (Sec. 3.3): its system A(d_jmed) x = F e_jmed is
+    // solved by the lockstep driver; its own, much narrower, spectrum interval
+    jmed = int(m / 2);
     double lo = 1.0, hi = 1.0;
     for (int i = 0; i < op.q; ++i) {
       const double rt = Pr.d[size_t(jmed) * op.q + i] / Pr.dbar[i];
       lo = std::min(lo, rt);
       hi = std::max(hi, rt);
     }
-    const double cm = std::max(0.5 * (hi - lo), 1e-3 * 0.5 * (hi + lo)), dm = 0.5 * (hi + lo);
-    inf.median_iters = median_solve(Pr, jmed, cm, dm, o.median_tol > 0 ? o.median_tol : 1e-10,
-                                    1000, Pr.X0);
-    Pr.rank_x0 = 1;
+    cm = std::max(0.5 * (hi - lo), 1e-3 * 0.5 * (hi + lo));
+    dm = 0.5 * (hi + lo);
+    fmed.assign(n, 0.0);
+    for (int a = 0; a < Pr.rF; ++a) {
+      const double w = Pr.Fs[a] * Pr.FV[size_t(a) * m + jmed];
+      for (int64_t i = 0; i < n; ++i) fmed[i] += w * Pr.FU[size_t(a) * n + i];
+    }
+    coefmed.resize(op.q);
+    for (int i = 0; i < op.q; ++i) coefmed[i] = Pr.d[size_t(jmed) * op.q + i];
+    median_tol = o.median_tol > 0 ? o.median_tol : 1e-10;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
     LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
@@ -811,13 +624,53 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   c64 = std::make_unique<Cheb<double>>();
   c64->alloc(P, cap);
   B64.alloc(n, m, bcap, s);
-  build_rhs(Pr, Pr.X0, Pr.rank_x0, B64, o, c64->tr);
   max_iter = o.max_iter > 0 ? o.max_iter : 200;
   // mixed precision: the inner correction's own cap keeps [rhs | K_i E] within 128 columns
   inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
   target = o.res_tol * Pr.fnorm;
   refine_max = o.refine_max > 0 ? o.refine_max : 8;
   rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
+  if (o.precision != LRC_FP64) alloc_mixed();
+}
+
+// X0 = x 1^T from the median column's solution x (column 0 of an n x 8 block)
+void SolveRun::set_median_x0(const double* x, int iters) {
+  Prob& Pr = *P;
+  hipStream_t s = Pr.ctx->stream;
+  const int64_t n = Pr.ops->n, m = Pr.m;
+  Pr.X0.alloc(n, m, 1, s);
+  launch_copy_cols(x, 8, Pr.X0.u(), Pr.X0.ld, n, 1, s);
+  std::vector<double> ones(size_t(m) * Pr.X0.ld, 0.0);
+  for (int64_t j = 0; j < m; ++j) ones[size_t(j) * Pr.X0.ld] = 1.0;
+  const double one = 1.0;
+  const int r1 = 1;
+  LRC_HIP(hipMemcpyAsync(Pr.X0.V.p, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(Pr.X0.s.p, &one, 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(Pr.X0.rank.p, &r1, 4, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipStreamSynchronize(s));   // `ones` is a temporary
+  Pr.rank_x0 = 1;
+  inf.median_iters = iters;
+}
+
+// Right-hand side B = F - L(X0), truncated to the rhs capacity at a tolerance
+// far below the solver's: blocks [F_U | K_i X0_U] and [F_V | D_i X0_V].
+TruncPlan<double> SolveRun::rhs_plan(const lrc_opts& o, double* const* W0) const {
+  const Prob& Pr = *P;
+  const Ops& op = *Pr.ops;
+  const LR<double>& X0 = Pr.X0;
+  BlockView<double> A{}, B{};
+  CoreView cv{};
+  add_block(A, Pr.F64.u(), Pr.F64.ld, Pr.F64.r(), 0);
+  add_block(B, Pr.F64.v(), Pr.F64.ld, Pr.F64.r(), 0);
+  add_core(cv, Pr.F64.sv(), 1.0, Pr.F64.r(), 0);
+  for (int i = 0; i < op.q; ++i) {
+    add_block(A, W0[i], X0.ld, X0.r(), 0);
+    add_block(B, X0.v(), X0.ld, X0.r(), 0, Pr.drow(i));
+    add_core(cv, X0.sv(), -1.0, X0.r(), 0);
+  }
+  const int rcap = std::min(B64.cap, 64);
+  return c64->tr.plan(A, op.n, B, Pr.m, cv, rcap, std::min(1e-14, o.trunc_tol * 1e-3), B64.u(),
+                      B64.ld, B64.v(), B64.ld, B64.sv(), B64.r(), c64->norm.as<double>() + 4);
 }
 
 void SolveRun::alloc_mixed() {
@@ -846,46 +699,6 @@ TruncPlan<double> SolveRun::accumulate_plan(const lrc_opts& o) const {
   add_core(cv, E64.sv(), 1.0, E64.r(), 0);
   return c64->tr.plan(A, P->ops->n, Bv, P->m, cv, cap, o.trunc_tol, S64.u(), S64.ld, S64.v(),
                       S64.ld, S64.sv(), S64.r(), c64->norm.as<double>() + 3);
-}
-
-void SolveRun::iterate(const lrc_opts& o) {
-  Prob& Pr = *P;
-  Ctx& ctx = *Pr.ctx;
-  hipStream_t s = ctx.stream;
-  if (o.precision == LRC_FP64) {
-    iters = c64->solve(B64, Pr.fnorm, o, c, dc, max_iter, &conv, &last, &papp, &flags);
-    return;
-  }
-  // fp32 inner ChebyshevT wrapped in fp64 iterative refinement.  The inner
-  // right-hand side is the fp64 residual truncated to rank <= cap.
-  alloc_mixed();
-  double* nd = c64->norm.as<double>();
-  while (true) {
-    // fp64 residual, truncated to the inner solve's accuracy: the correction's rhs
-    c64->residual(B64, nd, rhs_tol);
-    LRC_HIP(hipMemcpyAsync(ctx.pinned, nd, 8, hipMemcpyDeviceToHost, s));
-    ctx.sync();
-    last = ctx.pinned[0];
-    log_line("refine64", refinements, last, Pr.fnorm);
-    if (!std::isfinite(last)) break;
-    if (last <= target) { conv = true; break; }
-    if (refinements >= refine_max || iters >= max_iter) break;
-    cast_lr<double, float>(c64->R, Bin, s);
-    lrc_opts oi = o;
-    oi.res_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
-    bool cin = false;
-    double lin = 0.0;
-    // stop the inner solve at its relative tolerance, at a fraction of the
-    // outer target, or when the fp32 residual stagnates at its rounding floor
-    iters += c32->solve(Bin, last, oi, c, dc, max_iter - iters, &cin, &lin, &papp, &flags,
-                        0.5 * target, 2);
-    ++refinements;
-    accumulate_plan_inputs(s);
-    enqueue_trunc(accumulate_plan(o), TruncBatch<double>(), s);
-  }
-  LRC_HIP(hipMemcpyAsync(ctx.pinned_i, c64->tr.st.info, sizeof(int), hipMemcpyDeviceToHost, s));
-  ctx.sync();
-  flags |= ctx.pinned_i[0];
 }
 
 lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
@@ -940,7 +753,8 @@ lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, c
                          const double* V0, lrc_info* info) {
   SolveRun run;
   run.prepare(P, o, r0, U0, s0, V0);
-  run.iterate(o);
+  std::vector<SolveRun*> one{&run};
+  lockstep(one, o);
   return run.finish(o, info);
 }
 

@@ -128,7 +128,8 @@ struct Truncator {
 
 struct Prob;
 
-// One ChebyshevT solve in precision T of  L(S) = B  (B given as an LR<T>).
+// State and workspace of one ChebyshevT solve in precision T of L(S) = B, and
+// the launch arguments of its steps (the lockstep driver runs them).
 template <class T>
 struct Cheb {
   Prob* P = nullptr;
@@ -137,14 +138,8 @@ struct Cheb {
   DevBuf W, Z, py, px, pcb, pst, norm;
   Truncator<T> tr;
   void alloc(Prob* p, int cap_);
-  // returns iterations; sets converged
-  int solve(const LR<T>& B, double ref_norm, const lrc_opts& o, double c, double dc,
-            int max_iter, bool* converged, double* last_norm, int* prec_applies, int* flags,
-            double abs_target = 0.0, int stall_limit = 1 << 30);
-  void residual(const LR<T>& B, double* norm_dev, double tol = 0.0);
-  void precond();   // Z = P^{-1} R_U
-  // launch arguments of the steps (truncation tolerance `tol`; norms go to
-  // norm[0] residual, norm[1] direction, norm[2] iterate)
+  // truncation tolerance of the steps; norms go to norm[0] residual,
+  // norm[1] direction, norm[2] iterate, norm[3] refinement, norm[4] rhs
   double tol = 0.0;
   SpmmLaunch<T> spmm_plan(const T* U, int ldu, const int* r_dev) const;
   TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol) const;
@@ -185,9 +180,10 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
 lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
                          const double* V0, lrc_info* info);
 
-// One solve split into set-up (spectrum bounds, initial term X0, right-hand
-// side B = F - L(X0)), iteration and report, so that a batch of problems can
-// share the iteration phase.
+// One solve split into set-up (spectrum bounds, workspaces, the median
+// column's system), the iterative phases (run by `lockstep` for one or many
+// problems: median solve, right-hand side B = F - L(X0), ChebyshevT with
+// refinement) and the report.
 struct SolveRun {
   Prob* P = nullptr;
   std::chrono::steady_clock::time_point t0;
@@ -202,9 +198,14 @@ struct SolveRun {
   int flags = 0, iters = 0, papp = 0, refinements = 0;
   bool conv = false;
   double last = 0.0;
+  // median column (init LRC_INIT_MEDIAN): index, interval, right-hand side, coefficients
+  int jmed = -1;
+  double cm = 0.0, dm = 0.0, median_tol = 0.0;
+  std::vector<double> fmed, coefmed;
   void prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
                const double* V0);
-  void iterate(const lrc_opts& o);
+  void set_median_x0(const double* x, int iters);
+  TruncPlan<double> rhs_plan(const lrc_opts& o, double* const* W0) const;
   lrc_status finish(const lrc_opts& o, lrc_info* info);
   // mixed precision pieces
   void alloc_mixed();
@@ -212,10 +213,13 @@ struct SolveRun {
   TruncPlan<double> accumulate_plan(const lrc_opts& o) const;
 };
 
-// Solves several problems in lockstep: every step is one launch for all of
-// them, and each restart cycle of the ChebyshevT iteration is replayed from a
-// captured HIP graph.  Set-up and reports run on the problems' context stream,
-// the lockstep phase on a stream of its own (synchronised at both ends).
+// The iterative phases of prepared solves in lockstep: every step is one
+// launch over all of them, finished problems are skipped on the device, and
+// the iterations are replayed from captured HIP graphs (opts.eager: launched
+// directly instead).  Runs on a stream of its own, synchronised with the
+// problems' context stream at both ends.
+void lockstep(std::vector<SolveRun*>& runs, const lrc_opts& o);
+
 std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc_opts& o,
                                       lrc_info* infos);
 

@@ -38,7 +38,7 @@ class lrc_opts(C.Structure):
                 ("max_iter", C.c_int), ("restart", C.c_int), ("cheb_c", C.c_double),
                 ("cheb_d", C.c_double), ("precision", C.c_int), ("refine_max", C.c_int),
                 ("inner_tol", C.c_double), ("init", C.c_int), ("median_tol", C.c_double),
-                ("verify_fp64", C.c_int)]
+                ("verify_fp64", C.c_int), ("eager", C.c_int)]
 
 
 class lrc_info(C.Structure):

@@ -129,3 +129,21 @@ def test_batched_rejects_unbounded_cycle(torch, L, ctx, c3):
     _, subs = c3
     with pytest.raises(L.LrcError):
         L.solve_batched([subs[0]["prob"]], **dict(_kw(L, "fp64"), restart=0))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager_launches(torch, L, ctx, c3, precision):
+    """The captured graphs (replayed several times per solve, with host reads
+    of the device flags between replays) against the same steps launched
+    directly: identical iteration counts and solutions."""
+    _, subs = c3
+    probs = [subs[j]["prob"] for j in (1, 4, 8)]
+    kw = _kw(L, precision)
+    code_e, inf_e = L.solve_batched(probs, **dict(kw, eager=1))
+    X_e = [_dense(p.solution()) for p in probs]
+    code_g, inf_g = L.solve_batched(probs, **kw)
+    X_g = [_dense(p.solution()) for p in probs]
+    assert code_e == 0 and code_g == 0
+    for a, b, xe, xg in zip(inf_e, inf_g, X_e, X_g):
+        assert a["iters"] == b["iters"] and a["median_iters"] == b["median_iters"]
+        assert np.linalg.norm(xe - xg) <= 1e-12 * np.linalg.norm(xe)
