@@ -72,6 +72,8 @@ typedef struct {
   int verify_fp64;     /* 1: finish with the entry-wise fp64 residual           */
   int eager;           /* 1: launch every step directly instead of replaying the
                           captured HIP graphs of the iterations (same arithmetic) */
+  double inner_trunc_tol; /* mixed: truncation tolerance of the fp32 inner solve
+                          (<= 0: max(trunc_tol, 1e-2 * inner_tol))               */
 } lrc_opts;
 
 typedef struct {
@@ -117,6 +119,21 @@ void lrc_ops_destroy(lrc_ops ops);
  * W + i * n * ldw.  ldu, ldw multiples of 8, r <= min(ldu, ldw) <= 256. */
 lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U_dev, int ldu,
                             void* W_dev, int ldw);
+/* SpMM autotuning for this operator set at width r (dtype 0/1): times every
+ * candidate launch shape (columns per lane 1/2/4/8, 2/4/8 waves per
+ * workgroup, grid caps 2048/8192/32768) on the device and caches the fastest
+ * in the context for (precision, n, q, nnz, r); every later SpMM of that shape
+ * (solver steps included) uses it, and the solver tunes on first use anyway.
+ * cfg (may be NULL) receives {columns per lane, waves, grid cap}; times_us
+ * (may be NULL) {best, default shape} in microseconds per launch.  Results do
+ * not depend on the shape: each row is summed in the same order by one lane
+ * group whatever the choice. */
+lrc_status lrc_ops_spmm_tune(lrc_ops ops, int dtype, int r, int cfg[3], double times_us[2]);
+/* lrc_ops_spmm_dev with an explicit launch shape cfg = {columns per lane (1, 2,
+ * 4 or 8; 0 = default), waves per workgroup (1..8), grid cap (>= 1)};
+ * LRC_EINVAL for a shape that cannot cover r (r / columns per lane > 64). */
+lrc_status lrc_ops_spmm_shape_dev(lrc_ops ops, int dtype, int r, const void* U_dev, int ldu,
+                                  void* W_dev, int ldw, const int cfg[3]);
 
 /* --------------------------------------------------------------- problem
  * One subset: m parameter columns, the table d (q x m, column-major, i.e.

@@ -34,9 +34,12 @@ Batched<A> upload_items(const std::vector<A>& v, const int* done, DevBuf& buf, h
 template <class T>
 SpmmLaunch<T> merge_spmm(const std::vector<SpmmLaunch<T>>& v) {
   SpmmLaunch<T> l = v[0];
+  std::vector<Work> ws;
+  for (const auto& x : v) ws.push_back(x.work);
+  l.work = combine_work(ws);
   for (const auto& x : v) {
-    LRC_CHECK(x.cpl == l.cpl && x.lpr == l.lpr, ST_EINVAL,
-              "batched solve: problems differ in the factor capacity");
+    LRC_CHECK(x.cpl == l.cpl && x.lpr == l.lpr && x.waves == l.waves, ST_EINVAL,
+              "batched solve: problems differ in the SpMM launch shape");
     l.blocks = std::max(l.blocks, x.blocks);
     l.q = std::max(l.q, x.q);
   }
@@ -116,6 +119,7 @@ struct PrecBatch {
     ldw = ldw_;
     for (auto* x : pre)
       if (!same_structure(x->F, pre[0]->F)) shared = false;
+    for (const auto& x : items) check_prec_item(x, kcap, ldw);
     all = upload_items(items, done, buf, s);
     one.clear();
     if (!shared)
@@ -129,7 +133,10 @@ struct PrecBatch {
   }
   void enqueue(hipStream_t s) const {
     if (shared) {
-      enqueue_prec_apply<T>(pre[0]->dev<T>(), pre[0]->fwd, pre[0]->bwd, items[0], all, kcap, ldw, s);
+      std::vector<WTerm> kt;
+      for (const auto& x : items) kt.push_back(WTerm{x.k_dev, x.k_const});
+      enqueue_prec_apply<T>(pre[0]->dev<T>(), pre[0]->fwd, pre[0]->bwd, items[0], all, kcap, ldw, s,
+                            &kt);
     } else {
       for (size_t j = 0; j < items.size(); ++j)
         enqueue_prec_apply<T>(pre[j]->dev<T>(), pre[j]->fwd, pre[j]->bwd, items[j], one[j], kcap,
@@ -220,7 +227,7 @@ struct MedianBatch {
       double* Wp[kMaxOps];
       for (int i = 0; i < op.q; ++i) Wp[i] = x.W.as<double>() + size_t(i) * n * 8;
       sl.push_back(make_spmm<double>(op.d64.data(), op.q, x.x.as<double>(), 8, nullptr, 1, 1, Wp,
-                                     8, 2));
+                                     8, spmm_config<double>(op, 1)));
       sa.push_back(sl.back().a);
       pi.push_back(PrecItem<double>{P.prec->p64.fw, P.prec->p64.bw, x.r.as<double>(), 8,
                                     x.z.as<double>(), 8, nullptr, 1, x.py.as<double>(),
@@ -390,8 +397,15 @@ struct BatchCheb {
   }
 
   // Runs the lockstep iteration.  Items with init_done[j] set do nothing.
+  // With S = 0 the first residual is the right-hand side itself: when
+  // `r0_norm` is given (its Frobenius norm per item) and every B fits R, R is
+  // a copy of B instead of a truncation of [B].
   void run(const std::vector<int>& init_done, const std::vector<double>& target,
-           const std::vector<int>& max_iter, int stall_limit) {
+           const std::vector<int>& max_iter, int stall_limit,
+           const std::vector<double>* r0_norm = nullptr) {
+    bool copy = r0_norm != nullptr;
+    for (int j = 0; j < nb; ++j) copy = copy && B[j]->cap <= it[j]->R.cap;
+    std::vector<int> dn(init_done);
     for (int j = 0; j < nb; ++j) {
       BCtl& h = hctl[j];
       h = BCtl{};
@@ -402,12 +416,22 @@ struct BatchCheb {
       h.state = init_done[j] ? 2 : 0;
       LRC_HIP(hipMemsetAsync(it[j]->S.rank.p, 0, 16, s));
       LRC_HIP(hipMemsetAsync(it[j]->D.rank.p, 0, 16, s));
+      if (copy && !init_done[j]) {
+        // the checks of the first residual, as the device does them
+        const double nr = (*r0_norm)[j];
+        h.last = h.best = nr;
+        if (!std::isfinite(nr)) h.state = 2;
+        else if (nr <= h.target) h.state = 1;
+        else if (h.max_iter <= 0) h.state = 2;
+        if (h.state) dn[j] = 1;
+        cast_lr<T, T>(*B[j], it[j]->R, s);
+      }
     }
     LRC_HIP(hipMemcpyAsync(ctl.p, hctl.data(), size_t(nb) * sizeof(BCtl), hipMemcpyHostToDevice,
                            s));
-    LRC_HIP(hipMemcpyAsync(done.p, init_done.data(), size_t(nb) * sizeof(int),
-                           hipMemcpyHostToDevice, s));
-    resid(0);
+    LRC_HIP(hipMemcpyAsync(done.p, dn.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice,
+                           s));
+    if (!copy) resid(0);
     while (true) {
       LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, size_t(nb) * sizeof(BCtl),
                              hipMemcpyDeviceToHost, s));
@@ -479,7 +503,7 @@ void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
     double* Wp[kMaxOps];
     for (int i = 0; i < op.q; ++i) Wp[i] = W0[j].as<double>() + size_t(i) * op.n * X0.ld;
     sl.push_back(make_spmm<double>(op.d64.data(), op.q, X0.u(), X0.ld, X0.r(), 0, X0.cap, Wp,
-                                   X0.ld, 2));
+                                   X0.ld, spmm_config<double>(op, X0.cap)));
     sa.push_back(sl.back().a);
     tp.push_back(r.rhs_plan(o, Wp));
   }
@@ -540,7 +564,18 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       rhs.push_back(&r->B64);
     }
     bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
-    bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30);
+    // ||B||: from the right-hand side's truncation, or ||F|| when B = F
+    std::vector<double> bn(nb);
+    for (int j = 0; j < nb; ++j) {
+      if (run[j]->P->rank_x0 == 0) {
+        bn[j] = run[j]->P->fnorm;
+      } else {
+        LRC_HIP(hipMemcpyAsync(&bn[j], run[j]->c64->norm.as<double>() + 4, 8,
+                               hipMemcpyDeviceToHost, s));
+      }
+    }
+    LRC_HIP(hipStreamSynchronize(s));
+    bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30, &bn);
     for (int j = 0; j < nb; ++j) {
       run[j]->iters = bc.hctl[j].iters;
       run[j]->papp = bc.hctl[j].iters;
@@ -580,7 +615,8 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
         Cheb<double>& C = *r->c64;
         v.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
         a.push_back(v.back().a);
-        vr.push_back(C.resid_plan(r->B64, C.norm.as<double>(), r->rhs_tol));
+        // truncated straight to the inner solve's cap: its first residual
+        vr.push_back(C.resid_plan(r->B64, C.norm.as<double>(), r->rhs_tol, r->inner_cap));
         va.push_back(r->accumulate_plan(o));
       }
       sp0 = merge_spmm(v);
@@ -598,7 +634,7 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
         items.push_back(r->c32.get());
         rhs.push_back(&r->Bin);
       }
-      bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
+      bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, o.restart, eager, s);
     }
     const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
     while (true) {
@@ -633,9 +669,12 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       LRC_HIP(hipMemcpyAsync(odone.p, hd.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice,
                              s));
       if (!any) break;
-      for (int j = 0; j < nb; ++j)
+      std::vector<double> r0n(nb, 0.0);
+      for (int j = 0; j < nb; ++j) {
+        r0n[j] = run[j]->last;
         if (!idone[j]) cast_lr<double, float>(run[j]->c64->R, run[j]->Bin, s);
-      bc.run(idone, itgt, imax, 2);
+      }
+      bc.run(idone, itgt, imax, 2, &r0n);
       for (int j = 0; j < nb; ++j) {
         if (idone[j]) continue;
         run[j]->iters += bc.hctl[j].iters;

@@ -99,6 +99,8 @@ void build_levels(Prec& pr, hipStream_t s) {
   std::vector<int64_t> soff_f(F.nsn, 0), soff_b(F.nsn, 0), lf(F.nlev_fwd, 0), lb(F.nlev_bwd, 0);
   std::vector<double> blk_f(F.nlev_fwd, 0.0), blk_b(F.nlev_bwd, 0.0);
   std::vector<int64_t> ns_f(F.nlev_fwd, 0), ns_b(F.nlev_bwd, 0);
+  std::vector<int> nin_f(F.nlev_fwd, 0), nin_b(F.nlev_bwd, 0);
+  std::vector<std::vector<GatherRow>> gf(F.nlev_fwd), gb(F.nlev_bwd);
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
     const int hf = F.height[sn], db = F.depth[sn];
@@ -106,6 +108,8 @@ void build_levels(Prec& pr, hipStream_t s) {
     blk_b[db] += double(f) * F.ns[sn];
     ns_f[hf] += F.ns[sn];
     ns_b[db] += F.ns[sn];
+    nin_f[hf] = std::max(nin_f[hf], F.ns[sn]);
+    nin_b[db] = std::max(nin_b[db], f);
     for (int r0 = 0; r0 < f; r0 += TR) ft[hf].push_back(make_int2(sn, r0));
     for (int r0 = 0; r0 < F.ns[sn]; r0 += TR) bt[db].push_back(make_int2(sn, r0));
     soff_f[sn] = lf[hf];
@@ -113,6 +117,13 @@ void build_levels(Prec& pr, hipStream_t s) {
     for (int p = 0; p < f; ++p) {
       fr[hf].push_back(make_int2(sn, p));
       br[db].push_back(make_int2(sn, p));
+      const int64_t q = F.front_off[sn] + p;
+      LRC_CHECK(F.asm_ptr[q + 1] - F.asm_ptr[q] < (int64_t(1) << 30), ST_EINVAL,
+                "preconditioner: too many contributions to one front row");
+      gf[hf].push_back(GatherRow{p < F.ns[sn] ? F.perm[F.j0[sn] + p] : -1,
+                                 int(F.asm_ptr[q + 1] - F.asm_ptr[q]), F.asm_ptr[q]});
+      gb[db].push_back(GatherRow{p < F.ns[sn] ? F.j0[sn] + p : -F.bnd[F.bnd_off[sn] + p - F.ns[sn]] - 1,
+                                 0, 0});
     }
     lf[hf] += f;
     lb[db] += f;
@@ -128,17 +139,23 @@ void build_levels(Prec& pr, hipStream_t s) {
   pr.fwd_tasks = upload(all, s);
   pr.soff_fwd = upload(soff_f, s);
   pr.soff_bwd = upload(soff_b, s);
+  std::vector<GatherRow> gall;
+  std::vector<size_t> gfo, gbo;
+  for (auto& L : gf) { gfo.push_back(gall.size()); gall.insert(gall.end(), L.begin(), L.end()); }
+  for (auto& L : gb) { gbo.push_back(gall.size()); gall.insert(gall.end(), L.begin(), L.end()); }
+  pr.grows = upload(gall, s);
   const int2* base = pr.fwd_tasks.as<int2>();
+  const GatherRow* gbase = pr.grows.as<GatherRow>();
   pr.fwd.clear();
   pr.bwd.clear();
   // forward products read the ns own rows of each front and write all f rows;
   // backward products read all f rows and write the ns own rows twice (x, Z)
   for (size_t l = 0; l < ft.size(); ++l)
     pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size()),
-                      blk_f[l], ns_f[l], lf[l]});
+                      gbase + gfo[l], nin_f[l], blk_f[l], ns_f[l], lf[l]});
   for (size_t l = 0; l < bt.size(); ++l)
     pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size()),
-                      blk_b[l], lb[l], 2 * ns_b[l]});
+                      gbase + gbo[l], nin_b[l], blk_b[l], lb[l], 2 * ns_b[l]});
   LRC_HIP(hipStreamSynchronize(s));
 }
 
@@ -448,13 +465,61 @@ lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U, int ld
     if (dtype == 0) {
       double* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
-      launch_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu, nullptr, r, r,
-                          Wp, ldw, 2, o.ctx->stream);
+      enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu,
+                                     nullptr, r, r, Wp, ldw, spmm_config<double>(o, r)),
+                   Batched<SpmmArgs<double>>(), o.ctx->stream);
     } else {
       float* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
-      launch_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr, r, r, Wp,
-                         ldw, 4, o.ctx->stream);
+      enqueue_spmm(make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr,
+                                    r, r, Wp, ldw, spmm_config<float>(o, r)),
+                   Batched<SpmmArgs<float>>(), o.ctx->stream);
+    }
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_ops_spmm_shape_dev(lrc_ops ops, int dtype, int r, const void* U, int ldu, void* W,
+                                  int ldw, const int cfg[3]) {
+  if (!ops || !cfg) return LRC_EINVAL;
+  return guarded(ops->o.ctx, [&]() -> lrc_status {
+    const Ops& o = ops->o;
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "spmm: dtype must be 0 (fp64) or 1 (fp32)");
+    LRC_CHECK(r >= 1 && r <= (dtype == 0 ? 128 : 256), ST_EINVAL, "spmm: r out of range");
+    LRC_CHECK(U && W, ST_EINVAL, "spmm: null pointer");
+    const SpmmCfg c{cfg[0], cfg[1], cfg[2]};
+    if (dtype == 0) {
+      double* Wp[kMaxOps];
+      for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
+      enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu,
+                                     nullptr, r, r, Wp, ldw, c),
+                   Batched<SpmmArgs<double>>(), o.ctx->stream);
+    } else {
+      float* Wp[kMaxOps];
+      for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
+      enqueue_spmm(make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr,
+                                    r, r, Wp, ldw, c),
+                   Batched<SpmmArgs<float>>(), o.ctx->stream);
+    }
+    return LRC_OK;
+  });
+}
+
+lrc_status lrc_ops_spmm_tune(lrc_ops ops, int dtype, int r, int cfg[3], double times_us[2]) {
+  if (!ops) return LRC_EINVAL;
+  return guarded(ops->o.ctx, [&]() -> lrc_status {
+    const Ops& o = ops->o;
+    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "spmm tune: dtype must be 0 (fp64) or 1 (fp32)");
+    LRC_CHECK(r >= 1 && r <= (dtype == 0 ? 128 : 256), ST_EINVAL, "spmm tune: r out of range");
+    const SpmmTuneResult res = dtype == 0 ? tune_spmm<double>(o, r) : tune_spmm<float>(o, r);
+    if (cfg) {
+      cfg[0] = res.best.cpl;
+      cfg[1] = res.best.waves;
+      cfg[2] = res.best.max_blocks;
+    }
+    if (times_us) {
+      times_us[0] = res.best_us;
+      times_us[1] = res.default_us;
     }
     return LRC_OK;
   });

@@ -400,7 +400,7 @@ template <class T>
 void enqueue_gram(const GramLaunch<T>& l, Batched<GramArgs<T>> bg, Batched<GramRedArgs<T>> br,
                   hipStream_t s) {
   {
-    ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, bg.dev ? Work() : l.work);
+    ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, l.work);
     const GramArgs<T>& a = l.g;
     const dim3 grid(l.grid, 1, bg.n), blk(256);
     // (tile grid, wave groups sharing the tiles, prefetch depth) per width
@@ -576,7 +576,7 @@ TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
 
 template <class T>
 void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s) {
-  ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, b.dev ? Work() : l.work);
+  ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, l.work);
   const dim3 grid(l.grid, l.slices, b.n);
   if (l.sc1)
     hipLaunchKernelGGL((tsmm_kernel<T, true>), grid, dim3(256), 0, s, l.a, b.dev, b.done);

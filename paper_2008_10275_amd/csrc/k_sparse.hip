@@ -14,7 +14,7 @@ namespace lrc {
 // each nonzero K_i(row, j) costs one coalesced read of row j of U.  The grid's
 // y dimension runs over the q operators that share U.
 template <class T, int CPL>
-__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
+__global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
                                                    const int* done, int lpr) {
   if (done && done[blockIdx.z]) return;
   const SpmmArgs<T>& args = ab ? ab[blockIdx.z] : a0;
@@ -58,12 +58,16 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
 
 template <class T>
 SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
-                        int r_const, int rcap, T* const* W, int ldw, int cpl) {
+                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg) {
+  const int cpl = cfg.cpl > 0 ? cfg.cpl : (sizeof(T) == 8 ? 2 : 4);
   LRC_CHECK(q >= 1 && q <= kMaxOps, ST_EINVAL, "spmm: bad operator count");
   LRC_CHECK(rcap >= 1, ST_EINVAL, "spmm: rank capacity must be positive");
   LRC_CHECK(ldu % 8 == 0 && ldw % 8 == 0 && ldu >= rcap && ldw >= rcap, ST_EINVAL,
             "spmm: leading dimensions must be multiples of 8 and cover the rank capacity");
-  LRC_CHECK(cpl == 2 || cpl == 4 || cpl == 8, ST_EINVAL, "spmm: columns per lane must be 2, 4 or 8");
+  LRC_CHECK(cpl == 1 || cpl == 2 || cpl == 4 || cpl == 8, ST_EINVAL,
+            "spmm: columns per lane must be 1, 2, 4 or 8");
+  LRC_CHECK(cfg.waves >= 1 && cfg.waves <= 8 && cfg.max_blocks >= 1, ST_EINVAL,
+            "spmm: 1..8 waves per workgroup");
   const int lpr = int(ceil_div(rcap, cpl));
   LRC_CHECK(lpr <= 64, ST_EINVAL, "spmm: rank capacity too large for the lane mapping");
   SpmmLaunch<T> l;
@@ -82,9 +86,10 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
   a.ldw = ldw;
   l.cpl = cpl;
   l.lpr = lpr;
+  l.waves = cfg.waves;
   const int rpw = 64 / lpr;
-  const int64_t rows_per_block = int64_t(rpw) * 4;
-  l.blocks = int(std::max<int64_t>(std::min<int64_t>(ceil_div(n, rows_per_block), 256 * 32), 1));
+  const int64_t rows_per_block = int64_t(rpw) * cfg.waves;
+  l.blocks = int(std::max<int64_t>(std::min<int64_t>(ceil_div(n, rows_per_block), cfg.max_blocks), 1));
   l.q = q;
   // algorithmic bytes: values + int32 columns + row pointers of every operator,
   // U read once, every W_i written (all n rows)
@@ -101,17 +106,20 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
 
 template <class T>
 void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s) {
-  ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, b.dev ? Work() : l.work);
-  const dim3 grid(unsigned(l.blocks), unsigned(l.q), unsigned(b.n));
+  ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, l.work);
+  const dim3 grid(unsigned(l.blocks), unsigned(l.q), unsigned(b.n)), blk(64 * l.waves);
   switch (l.cpl) {
+    case 1:
+      hipLaunchKernelGGL((spmm_kernel<T, 1>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
+      break;
     case 2:
-      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
+      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
     case 4:
-      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
+      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
     default:
-      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, dim3(256), 0, s, l.a, b.dev, b.done, l.lpr);
+      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
   }
   LRC_HIP(hipGetLastError());
@@ -120,14 +128,16 @@ void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s)
 template <class T>
 void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev, int r_const,
                  int rcap, T* const* W, int ldw, int cpl, hipStream_t s) {
-  enqueue_spmm(make_spmm(ops, q, U, ldu, r_dev, r_const, rcap, W, ldw, cpl), Batched<SpmmArgs<T>>(),
+  SpmmCfg cfg;
+  cfg.cpl = cpl;
+  enqueue_spmm(make_spmm(ops, q, U, ldu, r_dev, r_const, rcap, W, ldw, cfg), Batched<SpmmArgs<T>>(),
                s);
 }
 
 template SpmmLaunch<float> make_spmm<float>(const DevCsr<float>*, int, const float*, int,
-                                            const int*, int, int, float* const*, int, int);
+                                            const int*, int, int, float* const*, int, SpmmCfg);
 template SpmmLaunch<double> make_spmm<double>(const DevCsr<double>*, int, const double*, int,
-                                              const int*, int, int, double* const*, int, int);
+                                              const int*, int, int, double* const*, int, SpmmCfg);
 template void enqueue_spmm<float>(const SpmmLaunch<float>&, Batched<SpmmArgs<float>>, hipStream_t);
 template void enqueue_spmm<double>(const SpmmLaunch<double>&, Batched<SpmmArgs<double>>,
                                    hipStream_t);
@@ -140,10 +150,13 @@ template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int
 // Each level of the supernode tree is processed in two launches:
 //  1. gather: every front row of the level's supernodes is assembled into a
 //     dense staging block (forward: b(perm) + children's contribution rows;
-//     backward: [y_own ; x(boundary)]), one thread per entry;
-//  2. product: one workgroup per (supernode, 16 output rows); the 4 waves
-//     split the input dimension, each accumulates a 16 x 64 tile on MFMA
-//     (16x16x4), and the partial tiles are summed through LDS.
+//     backward: [y_own ; x(boundary)]), from a precomputed source descriptor
+//     per row, 16 bytes per thread;
+//  2. product: one task per (supernode, 16 output rows), a 16 x 16k tile
+//     accumulated on MFMA (16x16x4).  Levels whose inputs are short give every
+//     wave its own task; long inputs are split over NW waves of one workgroup
+//     whose partial tiles are summed through LDS.  The input loop issues the
+//     loads of four MFMA steps before their products.
 typedef float floatx4_s __attribute__((ext_vector_type(4)));
 typedef double doublex4_s __attribute__((ext_vector_type(4)));
 template <class T> struct PMfma;
@@ -162,168 +175,231 @@ template <> struct PMfma<double> {
   static __device__ inline int drow(int lane, int i) { return (lane >> 4) + 4 * i; }
 };
 
+// 16-byte vector of T
+template <class T> struct V16;
+template <> struct V16<float> {
+  typedef float4 t;
+  static constexpr int n = 4;
+  static __device__ inline t zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w; }
+};
+template <> struct V16<double> {
+  typedef double2 t;
+  static constexpr int n = 2;
+  static __device__ inline t zero() { return make_double2(0.0, 0.0); }
+  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; }
+};
+
 constexpr int kKMAX = 64;      // max columns per apply
-constexpr int kPT = 16;        // output rows per product workgroup
+constexpr int kPT = 16;        // output rows per product task
 
 template <class T, bool FWD>
-__global__ __launch_bounds__(256) void prec_gather_kernel(PrecDev<T> P, const int2* __restrict__ rows,
-                                                          int nrows, const int64_t* __restrict__ soff,
+__global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __restrict__ rows,
+                                                          int nrows, int vpr,
+                                                          const int64_t* __restrict__ asm_src,
                                                           PrecItem<T> a0, const PrecItem<T>* ab,
-                                                          const int* done, int ldw, int kcap) {
+                                                          const int* done, int ldw) {
+  typedef typename V16<T>::t vec;
+  constexpr int VN = V16<T>::n;
   if (done && done[blockIdx.z]) return;
   const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
-  const T* __restrict__ R = it.R;
-  const int ldr = it.ldr;
-  const T* __restrict__ y = it.y;
-  const T* __restrict__ x = it.x;
-  const T* __restrict__ cb = it.cb;
-  T* __restrict__ stage = it.stage;
-  const int k = it.k_dev ? *it.k_dev : it.k_const;
-  const int64_t total = int64_t(nrows) * kcap;
+  const int64_t total = int64_t(nrows) * vpr;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int item = int(e / kcap);
-    const int c = int(e - int64_t(item) * kcap);
-    if (c >= k) continue;
-    const int2 sp = rows[item];
-    const int sn = sp.x, p = sp.y;
-    const int ns = P.ns[sn], j0 = P.j0[sn];
-    T v;
+    const int row = int(e / vpr);
+    const int c = int(e - int64_t(row) * vpr) * VN;
+    const GatherRow g = rows[row];
+    vec v;
     if (FWD) {
-      v = (p < ns) ? R[int64_t(P.perm[j0 + p]) * ldr + c] : T(0);
-      const int64_t fr = P.front_off[sn] + p;
-      for (int64_t q = P.asm_ptr[fr]; q < P.asm_ptr[fr + 1]; ++q) v += cb[P.asm_src[q] * ldw + c];
+      v = g.src >= 0 ? *reinterpret_cast<const vec*>(it.R + int64_t(g.src) * it.ldr + c)
+                     : V16<T>::zero();
+      for (int q = 0; q < g.na; ++q)
+        V16<T>::add(v, *reinterpret_cast<const vec*>(it.cb + asm_src[g.a0 + q] * ldw + c));
     } else {
-      v = (p < ns) ? y[int64_t(j0 + p) * ldw + c]
-                   : x[int64_t(P.bnd[P.bnd_off[sn] + p - ns]) * ldw + c];
+      v = g.src >= 0 ? *reinterpret_cast<const vec*>(it.y + int64_t(g.src) * ldw + c)
+                     : *reinterpret_cast<const vec*>(it.x + int64_t(-g.src - 1) * ldw + c);
     }
-    stage[(soff[sn] + p) * ldw + c] = v;
+    *reinterpret_cast<vec*>(it.stage + int64_t(row) * ldw + c) = v;
   }
 }
 
-template <class T, bool FWD>
-__global__ __launch_bounds__(256) void prec_product_kernel(PrecDev<T> P, const int2* __restrict__ tasks,
-                                                           const int64_t* __restrict__ soff,
-                                                           PrecItem<T> a0, const PrecItem<T>* ab,
-                                                           const int* done, int ldw) {
+template <class T, bool FWD, int NW, int KTM>
+__global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
+    PrecDev<T> P, const int2* __restrict__ tasks, int ntasks, const int64_t* __restrict__ soff,
+    PrecItem<T> a0, const PrecItem<T>* ab, const int* done, int ldw) {
   typedef typename PMfma<T>::acc_t acc_t;
-  __shared__ T red[4][kPT][kKMAX + 1];
+  constexpr int WPB = NW > 4 ? NW : 4;    // waves per workgroup
+  constexpr int TPB = WPB / NW;           // tasks per workgroup
+  constexpr int U = 4;                    // MFMA steps per unrolled input block
+  __shared__ T red[NW > 1 ? NW : 1][KTM * 4][64];
   if (done && done[blockIdx.z]) return;
   const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
-  const T* __restrict__ stage = it.stage;
-  T* __restrict__ y = it.y;
-  T* __restrict__ x = it.x;
-  T* __restrict__ cb = it.cb;
-  T* __restrict__ Z = it.Z;
-  const int ldz = it.ldz;
-  const int2 task = tasks[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tk = blockIdx.x * TPB + wave / NW;   // uniform per workgroup when NW > 1
+  if (tk >= ntasks) return;
+  const int wv = wave % NW;
+  const int2 task = tasks[tk];
   const int sn = task.x, row0 = task.y;
   const int k = it.k_dev ? *it.k_dev : it.k_const;
-  const int KT = (k + 15) / 16;
   const int ns = P.ns[sn], f = ns + P.nb[sn], j0 = P.j0[sn];
   const int nin = FWD ? ns : f;
   const int nout = FWD ? f : ns;
   const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
   const int ldM = FWD ? f : ns;                  // column-major: element (row, i) at i * ldM + row
-  const T* __restrict__ In = stage + soff[sn] * ldw;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int chunk = ((nin + 3) / 4 + 3) / 4 * 4;
-  const int i0 = wave * chunk, i1 = min(nin, i0 + chunk);
+  const T* __restrict__ In = it.stage + soff[sn] * ldw;
+  const int chunk = NW == 1 ? nin : (nin + 4 * NW - 1) / (4 * NW) * 4;
+  const int i0 = wv * chunk, i1 = min(nin, i0 + chunk);
   const int orow = row0 + (lane & 15);
   const bool rowok = orow < nout;
-  acc_t acc[kKMAX / 16];
+  acc_t acc[KTM];
 #pragma unroll
-  for (int t = 0; t < kKMAX / 16; ++t) acc[t] = acc_t{};
-  for (int kk = i0; kk < i1; kk += 4) {
-    const int i = kk + (lane >> 4);
-    const bool iok = i < i1;
-    const T a = (iok && rowok) ? M[int64_t(i) * ldM + orow] : T(0);
+  for (int t = 0; t < KTM; ++t) acc[t] = acc_t{};
+  for (int kk = i0; kk < i1; kk += 4 * U) {
+    T a[U], b[U][KTM];
 #pragma unroll
-    for (int t = 0; t < kKMAX / 16; ++t) {
-      if (t < KT) {
+    for (int u = 0; u < U; ++u) {
+      const int i = kk + 4 * u + (lane >> 4);
+      const bool iok = i < i1;
+      a[u] = (iok && rowok) ? M[int64_t(i) * ldM + orow] : T(0);
+#pragma unroll
+      for (int t = 0; t < KTM; ++t) {
         const int c = t * 16 + (lane & 15);
-        const T b = (iok && c < k) ? In[int64_t(i) * ldw + c] : T(0);
-        acc[t] = PMfma<T>::op(a, b, acc[t]);
+        b[u][t] = (iok && c < k) ? In[int64_t(i) * ldw + c] : T(0);
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < KTM; ++t) acc[t] = PMfma<T>::op(a[u], b[u][t], acc[t]);
   }
-#pragma unroll
-  for (int t = 0; t < kKMAX / 16; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) red[wave][PMfma<T>::drow(lane, v)][t * 16 + (lane & 15)] = acc[t][v];
-  __syncthreads();
-  for (int e = threadIdx.x; e < kPT * kKMAX; e += blockDim.x) {
-    const int r = e / kKMAX, c = e - r * kKMAX;
+  auto store = [&](int r, int c, T v) {
     const int row = row0 + r;
-    if (c >= k || row >= nout) continue;
-    const T v = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
+    if (c >= k || row >= nout) return;
     if (FWD) {
-      if (row < ns) y[int64_t(j0 + row) * ldw + c] = v;
-      else cb[(P.cb_off[sn] + row - ns) * ldw + c] = v + In[int64_t(row) * ldw + c];
+      if (row < ns) it.y[int64_t(j0 + row) * ldw + c] = v;
+      else it.cb[(P.cb_off[sn] + row - ns) * ldw + c] = v + In[int64_t(row) * ldw + c];
     } else {
-      x[int64_t(j0 + row) * ldw + c] = v;
-      Z[int64_t(P.perm[j0 + row]) * ldz + c] = v;
+      it.x[int64_t(j0 + row) * ldw + c] = v;
+      it.Z[int64_t(P.perm[j0 + row]) * it.ldz + c] = v;
     }
+  };
+  if (NW == 1) {
+#pragma unroll
+    for (int t = 0; t < KTM; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) store(PMfma<T>::drow(lane, v), t * 16 + (lane & 15), acc[t][v]);
+    return;
+  }
+  // partial tiles in lane order; the workgroup sums them in a fixed order
+#pragma unroll
+  for (int t = 0; t < KTM; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][t * 4 + v][lane] = acc[t][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < KTM * 4 * 64; e += blockDim.x) {
+    const int tv = e >> 6, l = e & 63;
+    T sum = red[0][tv][l];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) sum += red[w][tv][l];
+    store(PMfma<T>::drow(l, tv & 3), (tv >> 2) * 16 + (l & 15), sum);
   }
 }
 
 // algorithmic bytes of one level: a staged row is read from its source and
 // written once; a product reads the level's dense blocks once plus the staged
 // input rows, and writes its output rows (k columns each)
+// (kterms: the widths of all items of the launch; their sum is v[0])
 template <class T>
-static Work gather_work(const LevelTasks& L, const int* k_dev, int k_const) {
+static Work gather_work(const LevelTasks& L, const std::vector<WTerm>& kterms) {
   Work w;
   const double rows = double(L.nrows);
-  w.groups = {{{k_dev, k_const}}};
+  w.groups = {kterms};
   w.f = [=](const std::vector<double>& v) { return 2.0 * rows * v[0] * sizeof(T); };
   return w;
 }
 template <class T>
-static Work product_work(const LevelTasks& L, const int* k_dev, int k_const) {
+static Work product_work(const LevelTasks& L, const std::vector<WTerm>& kterms) {
   Work w;
-  const double blk = L.blk, io = double(L.in_rows + L.out_rows);
-  w.groups = {{{k_dev, k_const}}};
+  const double blk = L.blk * double(kterms.size()), io = double(L.in_rows + L.out_rows);
+  w.groups = {kterms};
   w.f = [=](const std::vector<double>& v) { return (blk + io * v[0]) * sizeof(T); };
   return w;
 }
 
 template <class T>
-void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
-                        const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
-                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s) {
+void check_prec_item(const PrecItem<T>& it, int kcap, int ldw) {
+  constexpr int VN = V16<T>::n;
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   LRC_CHECK(kcap >= 1 && kcap <= kKMAX, ST_EINVAL,
             "preconditioner apply: at most 64 right-hand sides per call");
   LRC_CHECK(ldw >= kcap && it.ldr >= kcap && it.ldz >= kcap, ST_EINVAL,
             "preconditioner apply: leading dimension smaller than the column capacity");
+  LRC_CHECK(it.ldr % VN == 0 && ldw % VN == 0 && ldw >= (kcap + VN - 1) / VN * VN &&
+                it.ldr >= (kcap + VN - 1) / VN * VN,
+            ST_EINVAL, "preconditioner apply: leading dimensions must be multiples of 16 bytes");
+  LRC_CHECK(al(it.R) && al(it.y) && al(it.x) && al(it.cb) && al(it.stage), ST_EINVAL,
+            "preconditioner apply: operands must be 16-byte aligned");
+}
+
+template <class T, bool FWD, int NW>
+static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const PrecDev<T>& P,
+                              const LevelTasks& L, const int64_t* soff, const PrecItem<T>& it,
+                              const Batched<PrecItem<T>>& b, int ldw) {
+#define LRC_PP(KT)                                                                             \
+  hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT>), grid, blk, 0, s, P, L.tasks, L.count, \
+                     soff, it, b.dev, b.done, ldw)
+  switch (KTM) {
+    case 1: LRC_PP(1); break;
+    case 2: LRC_PP(2); break;
+    case 3: LRC_PP(3); break;
+    default: LRC_PP(4); break;
+  }
+#undef LRC_PP
+}
+
+template <class T>
+void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                        const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
+                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s,
+                        const std::vector<WTerm>* kterms) {
+  check_prec_item(it, kcap, ldw);
+  const std::vector<WTerm> kt = kterms ? *kterms : std::vector<WTerm>{{it.k_dev, it.k_const}};
+  constexpr int VN = V16<T>::n;
+  const int vpr = (kcap + VN - 1) / VN;
+  const int KTM = (kcap + 15) / 16;
   auto gblocks = [&](int nrows) {
-    return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(int64_t(nrows) * kcap, 256), 1), 65535));
+    return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(int64_t(nrows) * vpr, 256), 1), 65535));
   };
-  const bool batched = b.dev != nullptr;
   for (int pass = 0; pass < 2; ++pass) {
     const bool fw = pass == 0;
     for (const auto& L : fw ? fwd : bwd) {
       if (L.count == 0) continue;
       {
-        ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s,
-                     batched ? Work() : gather_work<T>(L, it.k_dev, it.k_const));
+        ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, kt));
         const dim3 grid(gblocks(L.nrows), 1, b.n);
         if (fw)
-          hipLaunchKernelGGL((prec_gather_kernel<T, true>), grid, dim3(256), 0, s, P, L.rows,
-                             L.nrows, P.soff_fwd, it, b.dev, b.done, ldw, kcap);
+          hipLaunchKernelGGL((prec_gather_kernel<T, true>), grid, dim3(256), 0, s, L.grows,
+                             L.nrows, vpr, P.asm_src, it, b.dev, b.done, ldw);
         else
-          hipLaunchKernelGGL((prec_gather_kernel<T, false>), grid, dim3(256), 0, s, P, L.rows,
-                             L.nrows, P.soff_bwd, it, b.dev, b.done, ldw, kcap);
+          hipLaunchKernelGGL((prec_gather_kernel<T, false>), grid, dim3(256), 0, s, L.grows,
+                             L.nrows, vpr, P.asm_src, it, b.dev, b.done, ldw);
       }
       {
-        ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s,
-                     batched ? Work() : product_work<T>(L, it.k_dev, it.k_const));
-        const dim3 grid(L.count, 1, b.n);
-        if (fw)
-          hipLaunchKernelGGL((prec_product_kernel<T, true>), grid, dim3(256), 0, s, P, L.tasks,
-                             P.soff_fwd, it, b.dev, b.done, ldw);
-        else
-          hipLaunchKernelGGL((prec_product_kernel<T, false>), grid, dim3(256), 0, s, P, L.tasks,
-                             P.soff_bwd, it, b.dev, b.done, ldw);
+        ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, kt));
+        // waves per task by the level's longest input
+        const int NW = L.nin_max <= 64 ? 1 : (L.nin_max <= 512 ? 4 : 8);
+        const int tpb = NW == 1 ? 4 : 1;
+        const dim3 grid(unsigned(ceil_div(L.count, tpb)), 1, b.n), blk(NW == 8 ? 512 : 256);
+        const int64_t* so = fw ? P.soff_fwd : P.soff_bwd;
+        if (fw) {
+          if (NW == 1) launch_product_nw<T, true, 1>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else if (NW == 4) launch_product_nw<T, true, 4>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else launch_product_nw<T, true, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+        } else {
+          if (NW == 1) launch_product_nw<T, false, 1>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else if (NW == 4) launch_product_nw<T, false, 4>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else launch_product_nw<T, false, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+        }
       }
     }
   }
@@ -336,15 +412,19 @@ void launch_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                        const int* k_dev, int k_const, int kcap, T* ws_y, T* ws_x, T* ws_cb,
                        T* ws_stage, int ldw, hipStream_t s) {
   const PrecItem<T> it{P.fw, P.bw, R, ldr, Z, ldz, k_dev, k_const, ws_y, ws_x, ws_cb, ws_stage};
-  enqueue_prec_apply(P, fwd, bwd, it, Batched<PrecItem<T>>(), kcap, ldw, s);
+  enqueue_prec_apply(P, fwd, bwd, it, Batched<PrecItem<T>>(), kcap, ldw, s, nullptr);
 }
 
+template void check_prec_item<float>(const PrecItem<float>&, int, int);
+template void check_prec_item<double>(const PrecItem<double>&, int, int);
 template void enqueue_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
                                         const std::vector<LevelTasks>&, const PrecItem<float>&,
-                                        Batched<PrecItem<float>>, int, int, hipStream_t);
+                                        Batched<PrecItem<float>>, int, int, hipStream_t,
+                                        const std::vector<WTerm>*);
 template void enqueue_prec_apply<double>(const PrecDev<double>&, const std::vector<LevelTasks>&,
                                          const std::vector<LevelTasks>&, const PrecItem<double>&,
-                                         Batched<PrecItem<double>>, int, int, hipStream_t);
+                                         Batched<PrecItem<double>>, int, int, hipStream_t,
+                                         const std::vector<WTerm>*);
 template void launch_prec_apply<float>(const PrecDev<float>&, const std::vector<LevelTasks>&,
                                        const std::vector<LevelTasks>&, const float*, int, float*,
                                        int, const int*, int, int, float*, float*, float*, float*,

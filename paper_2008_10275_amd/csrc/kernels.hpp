@@ -52,22 +52,40 @@ struct SpmmLaunch {
   SpmmArgs<T> a;
   int cpl = 4;     // columns per lane
   int lpr = 1;     // lanes per row
+  int waves = 4;   // waves per workgroup
   int blocks = 1;
   int q = 1;
   Work work;
 };
+// Launch shape of the SpMM: columns per lane (0: the dtype's default), waves
+// per workgroup, and the cap on the grid (rows beyond it are strided).
+struct SpmmCfg {
+  int cpl = 0;
+  int waves = 4;
+  int max_blocks = 8192;
+};
 template <class T>
 SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
-                        int r_const, int rcap, T* const* W, int ldw, int cpl);
+                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg);
 template <class T>
 void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s);
 
 // Level-scheduled supernodal triangular solves (data from nd_factor).
+// Source of one staged front row.  Forward: R row `src` (or none when < 0)
+// plus `na` contribution rows listed from asm_src[a0].  Backward: y row `src`
+// when >= 0, else x row -src - 1 (a boundary row); na = 0.
+struct GatherRow {
+  int src;
+  int na;
+  int64_t a0;
+};
 struct LevelTasks {
-  const int2* tasks;   // product: (supernode, first output row) per workgroup (16 rows)
+  const int2* tasks;   // product: (supernode, first output row) per 16-row task
   int count;
-  const int2* rows;    // gather: (supernode, front row) per staged row
+  const int2* rows;    // (supernode, front row) per staged row
   int nrows;
+  const GatherRow* grows;   // gather source of every staged row (in staging order)
+  int nin_max;         // longest product input (ns forward, ns + nb backward)
   double blk;          // dense block entries the level's products read
   int64_t in_rows;     // staged rows the products read (per column)
   int64_t out_rows;    // rows the products write (per column)
@@ -119,10 +137,16 @@ struct PrecItem {
   T* cb;
   T* stage;
 };
+// kterms: the widths of every item the launch covers, for the work model
+// (nullptr: the single item `it`)
 template <class T>
 void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                         const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
-                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s);
+                        Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s,
+                        const std::vector<WTerm>* kterms = nullptr);
+// Host checks of one item's operands (capacity, 16-byte rows and alignment).
+template <class T>
+void check_prec_item(const PrecItem<T>& it, int kcap, int ldw);
 
 // ----------------------------------------------------------------- dense tall-skinny
 // Partial Gram products G = X^T X for up to two operands in one launch; the

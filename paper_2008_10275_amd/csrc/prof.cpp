@@ -17,6 +17,28 @@ const char* kclass_name(int c) {
   return (c >= 0 && c < K_COUNT) ? full[c].c_str() : "?";
 }
 
+Work combine_work(const std::vector<Work>& items) {
+  Work w;
+  std::vector<std::pair<size_t, size_t>> span;   // group range of each item
+  std::vector<std::function<double(const std::vector<double>&)>> fs;
+  for (const auto& it : items) {
+    if (!it.valid()) return Work();
+    w.bytes = it.bytes;
+    span.emplace_back(w.groups.size(), it.groups.size());
+    w.groups.insert(w.groups.end(), it.groups.begin(), it.groups.end());
+    fs.push_back(it.f);
+  }
+  if (fs.empty()) return Work();
+  w.f = [span, fs](const std::vector<double>& v) {
+    double t = 0.0;
+    for (size_t i = 0; i < fs.size(); ++i)
+      t += fs[i](std::vector<double>(v.begin() + span[i].first,
+                                     v.begin() + span[i].first + span[i].second));
+    return t;
+  };
+  return w;
+}
+
 Profiler& profiler() {
   static Profiler p;
   return p;

@@ -36,6 +36,9 @@ struct Work {
   bool valid() const { return bool(f); }
 };
 
+// Work of a batched launch: the sum of its items' models.
+Work combine_work(const std::vector<Work>& items);
+
 struct Profiler {
   int mode = 0;   // 0 off, 1 events, 2 events + work
   int suspended = 0;   // > 0 while a stream is being captured into a graph

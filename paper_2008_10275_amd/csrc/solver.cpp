@@ -213,6 +213,17 @@ template <class T>
 TruncPlan<T> merge_plans(const std::vector<TruncPlan<T>>& v) {
   LRC_CHECK(!v.empty(), ST_EINVAL, "batched truncation: no items");
   TruncPlan<T> p = v[0];
+  std::vector<Work> w1, w2, w3, w4;
+  for (const auto& x : v) {
+    w1.push_back(x.g1.work);
+    w2.push_back(x.g2.work);
+    w3.push_back(x.t1.work);
+    w4.push_back(x.t2.work);
+  }
+  p.g1.work = combine_work(w1);
+  p.g2.work = combine_work(w2);
+  p.t1.work = combine_work(w3);
+  p.t2.work = combine_work(w4);
   for (size_t i = 1; i < v.size(); ++i) {
     merge_gram(p.g1, v[i].g1);
     merge_gram(p.g2, v[i].g2);
@@ -394,12 +405,12 @@ SpmmLaunch<T> Cheb<T>::spmm_plan(const T* U, int ldu, const int* r_dev) const {
   T* Wp[kMaxOps];
   for (int i = 0; i < o.q; ++i) Wp[i] = W.as<T>() + size_t(i) * o.n * ld;
   return make_spmm<T>(ops_dev<T>(o).data(), o.q, U, ldu, r_dev, 0, cap, Wp, ld,
-                      sizeof(T) == 8 ? 2 : 4);
+                      spmm_config<T>(o, cap));
 }
 
 // R = T(B - sum_i K_i S D_i): blocks [B | K_0 S | ... ] and [B_V | D_0 S_V | ...]
 template <class T>
-TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol) const {
+TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol_, int rank_cap) const {
   const Ops& o = *P->ops;
   const int ld = ld_for(cap);
   BlockView<T> A{}, Bv{};
@@ -412,7 +423,8 @@ TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol) c
     add_block(Bv, S.v(), S.ld, S.r(), 0, P->drow(i));
     add_core(c, S.sv(), -1.0, S.r(), 0);
   }
-  return tr.plan(A, o.n, Bv, P->m, c, cap, tol, R.u(), R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev);
+  return tr.plan(A, o.n, Bv, P->m, c, rank_cap > 0 ? std::min(rank_cap, cap) : cap, tol_, R.u(),
+                 R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev);
 }
 
 // D = T(Z R_V^T / dc) with Z = P^{-1} R_U diag(s_R)
@@ -498,6 +510,7 @@ void cast_lr(const LR<Tin>& a, LR<Tout>& b, hipStream_t s) {
 template void cast_lr<double, float>(const LR<double>&, LR<float>&, hipStream_t);
 template void cast_lr<float, double>(const LR<float>&, LR<double>&, hipStream_t);
 template void cast_lr<double, double>(const LR<double>&, LR<double>&, hipStream_t);
+template void cast_lr<float, float>(const LR<float>&, LR<float>&, hipStream_t);
 
 static int read_rank(Ctx& ctx, const int* r) {
   LRC_HIP(hipMemcpyAsync(ctx.pinned_i, r, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
@@ -519,8 +532,13 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
     W0p[i] = W0.as<double>() + size_t(i) * n * ld0;
     WSp[i] = WS.as<double>() + size_t(i) * n * lds;
   }
-  if (r0 > 0) launch_spmm<double>(o.d64.data(), o.q, X0.u(), ld0, X0.r(), 0, X0.cap, W0p, ld0, 2, s);
-  launch_spmm<double>(o.d64.data(), o.q, S.u(), lds, S.r(), 0, S.cap, WSp, lds, 2, s);
+  if (r0 > 0)
+    enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, X0.u(), ld0, X0.r(), 0, X0.cap, W0p, ld0,
+                                   spmm_config<double>(o, X0.cap)),
+                 Batched<SpmmArgs<double>>(), s);
+  enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, S.u(), lds, S.r(), 0, S.cap, WSp, lds,
+                                 spmm_config<double>(o, S.cap)),
+               Batched<SpmmArgs<double>>(), s);
   BlockView<double> A{}, B{};
   CoreView c{};
   add_block(A, P.F64.u(), P.F64.ld, P.F64.r(), 0);
@@ -630,6 +648,11 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   target = o.res_tol * Pr.fnorm;
   refine_max = o.refine_max > 0 ? o.refine_max : 8;
   rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
+  // the fp32 inner solve needs no truncation finer than its own target (and
+  // fp32 data resolves nothing much finer): by default 1e-2 * inner_tol
+  inner_trunc_tol = o.inner_trunc_tol > 0
+                        ? o.inner_trunc_tol
+                        : std::max(o.trunc_tol, 1e-2 * (o.inner_tol > 0 ? o.inner_tol : 1e-3));
   if (o.precision != LRC_FP64) alloc_mixed();
 }
 
@@ -678,7 +701,7 @@ void SolveRun::alloc_mixed() {
   const int64_t n = P->ops->n, m = P->m;
   c32 = std::make_unique<Cheb<float>>();
   c32->alloc(P, inner_cap);
-  Bin.alloc(n, m, cap, s);
+  Bin.alloc(n, m, inner_cap, s);   // the outer residual is truncated to inner_cap
   E64.alloc(n, m, inner_cap, s);
   LRC_HIP(hipMemsetAsync(c64->S.rank.p, 0, 16, s));
 }

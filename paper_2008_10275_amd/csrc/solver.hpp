@@ -1,7 +1,9 @@
 // Solver core: operators, preconditioner, truncation engine and the
 // ChebyshevT iteration (host orchestration of the HIP kernels).
 #pragma once
+#include <array>
 #include <chrono>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -22,6 +24,8 @@ struct Ctx {
   std::string err;
   double* pinned = nullptr;      // small host-visible readback buffer
   int* pinned_i = nullptr;
+  // tuned SpMM launch shapes per (element size, n, q, nnz, width)
+  std::map<std::array<int64_t, 5>, SpmmCfg> spmm_cache;
   void sync() { LRC_HIP(hipStreamSynchronize(stream)); }
 };
 
@@ -41,7 +45,7 @@ struct Prec {
   SupernodalFactor F;   // host copy (blocks freed after upload)
   DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd;
   DevBuf fw64, bw64, fw32, bw32;
-  DevBuf fwd_tasks, bwd_tasks, soff_fwd, soff_bwd;
+  DevBuf fwd_tasks, bwd_tasks, soff_fwd, soff_bwd, grows;
   std::vector<LevelTasks> fwd, bwd;
   int64_t stage_rows = 0;
   PrecDev<double> p64;
@@ -142,7 +146,8 @@ struct Cheb {
   // norm[1] direction, norm[2] iterate, norm[3] refinement, norm[4] rhs
   double tol = 0.0;
   SpmmLaunch<T> spmm_plan(const T* U, int ldu, const int* r_dev) const;
-  TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol) const;
+  // rank_cap <= 0: the solve's cap
+  TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol, int rank_cap = 0) const;
   TruncPlan<T> dstart_plan(double dc) const;
   TruncPlan<T> supd_plan() const;
   TruncPlan<T> dstep_plan(double alpha, double beta) const;
@@ -168,6 +173,20 @@ struct Prob {
   const double* drow(int i) const { return d_rows.as<double>() + size_t(i) * m; }
 };
 
+// SpMM autotuning (tune.cpp): time every candidate launch shape of the fused
+// SpMM of `o` at width `rcap`; spmm_config returns the cached choice, tuning
+// on the first request.
+struct SpmmTuneResult {
+  SpmmCfg best;
+  double best_us = 0.0;
+  double default_us = 0.0;
+  int tried = 0;
+};
+template <class T>
+SpmmTuneResult tune_spmm(const Ops& o, int rcap);
+template <class T>
+SpmmCfg spmm_config(const Ops& o, int rcap);
+
 // helpers
 void log_line(const char* phase, int it, double norm, double ref);   // LRC_LOG set: one JSON line
 template <class Tin, class Tout>
@@ -189,7 +208,7 @@ struct SolveRun {
   std::chrono::steady_clock::time_point t0;
   double c = 0.0, dc = 0.0;
   int cap = 0, inner_cap = 0, max_iter = 0, refine_max = 0;
-  double target = 0.0, rhs_tol = 0.0;
+  double target = 0.0, rhs_tol = 0.0, inner_trunc_tol = 0.0;
   lrc_info inf{};
   std::unique_ptr<Cheb<double>> c64;
   std::unique_ptr<Cheb<float>> c32;

@@ -38,7 +38,7 @@ class lrc_opts(C.Structure):
                 ("max_iter", C.c_int), ("restart", C.c_int), ("cheb_c", C.c_double),
                 ("cheb_d", C.c_double), ("precision", C.c_int), ("refine_max", C.c_int),
                 ("inner_tol", C.c_double), ("init", C.c_int), ("median_tol", C.c_double),
-                ("verify_fp64", C.c_int), ("eager", C.c_int)]
+                ("verify_fp64", C.c_int), ("eager", C.c_int), ("inner_trunc_tol", C.c_double)]
 
 
 class lrc_info(C.Structure):
@@ -67,6 +67,8 @@ _SIGS = {
     "lrc_ops_update_values": (C.c_int, [_P, C.c_int, _P]),
     "lrc_ops_destroy": (None, [_P]),
     "lrc_ops_spmm_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int]),
+    "lrc_ops_spmm_tune": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
+    "lrc_ops_spmm_shape_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int, _P]),
     "lrc_prob_create": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, _P, C.POINTER(_P)]),
     "lrc_prob_destroy": (None, [_P]),
     "lrc_prob_precondition": (C.c_int, [_P, _P, C.c_int]),
@@ -215,6 +217,14 @@ class Operators:
         _check(ctx.handle, lib.lrc_ops_create(ctx.handle, n, self.q, arr(*rp), arr(*cl),
                                               arr(*vl), C.byref(self.handle)))
 
+    def spmm_tune(self, dtype, r):
+        """lrc_ops_spmm_tune: (columns per lane, waves, grid cap), best us, default us."""
+        cfg = np.zeros(3, dtype=np.int32)
+        t = np.zeros(2)
+        _check(self.ctx.handle, load().lrc_ops_spmm_tune(self.handle, int(dtype), int(r),
+                                                         _ptr(cfg), _ptr(t)))
+        return tuple(int(x) for x in cfg), float(t[0]), float(t[1])
+
     def update_values(self, i, val):
         v = np.ascontiguousarray(val, dtype=np.float64)
         _check(self.ctx.handle, load().lrc_ops_update_values(self.handle, i, _ptr(v)))
@@ -226,6 +236,15 @@ class Operators:
         r = U.shape[1] if r is None else r
         _check(self.ctx.handle, load().lrc_ops_spmm_dev(self.handle, dtype, r, _dev_ptr(U),
                                                         U.stride(0), _dev_ptr(W), W.stride(0)))
+
+    def spmm_shape_dev(self, U, W, shape, r=None):
+        """spmm_dev with an explicit launch shape (columns per lane, waves, grid cap)."""
+        import torch
+        dtype = 0 if U.dtype == torch.float64 else 1
+        r = U.shape[1] if r is None else r
+        cfg = np.asarray(shape, dtype=np.int32)
+        _check(self.ctx.handle, load().lrc_ops_spmm_shape_dev(
+            self.handle, dtype, r, _dev_ptr(U), U.stride(0), _dev_ptr(W), W.stride(0), _ptr(cfg)))
 
     def close(self):
         if self.handle:

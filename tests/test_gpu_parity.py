@@ -97,6 +97,45 @@ def test_preconditioner_solve_matches_sparse_lu(torch, L, ctx, dt, name, k):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("r", [1, 30, 40])
+def test_spmm_autotune_shapes_agree(torch, L, ctx, dt, r):
+    """Every candidate launch shape gives the same bits (each row is summed
+    in order by one lane group), the tuner's pick is the fastest it timed,
+    and the solver's SpMM (tuned shape) matches SciPy."""
+    say("spmm autotune", dt, r)
+    K = config("c2", small=True)["ops"].K
+    ops = L.Operators(ctx, K)
+    n = K[0].shape[0]
+    U = np.random.default_rng(r + 3).standard_normal((n, r))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Ud = _dev(torch, U, tdt)
+    ld = Ud.shape[1]
+    ref = None
+    for cpl in (1, 2, 4, 8):
+        if -(-r // cpl) > 64 or (cpl > 1 and cpl > r):
+            continue
+        for waves, cap in ((2, 2048), (4, 8192), (8, 32768), (8, 7)):
+            W = torch.zeros((len(K) * n, ld), dtype=tdt, device="cuda")
+            ops.spmm_shape_dev(Ud, W, (cpl, waves, cap), r)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = W.clone()
+            assert torch.equal(W, ref), (cpl, waves, cap)
+    best, t_best, t_def = ops.spmm_tune(0 if dt == "f64" else 1, r)
+    say("tuned", best, t_best, "us; default", t_def, "us")
+    assert best[0] in (1, 2, 4, 8) and best[1] in (2, 4, 8) and t_best <= t_def
+    W = torch.zeros((len(K) * n, ld), dtype=tdt, device="cuda")
+    ops.spmm_dev(Ud, W, r)
+    torch.cuda.synchronize()
+    assert torch.equal(W, ref)
+    Wh = W.double().cpu().numpy()
+    tol = 1e-14 if dt == "f64" else 2e-6
+    for i, Ki in enumerate(K):
+        scale = (abs(Ki) @ np.abs(U)) + 1e-300
+        assert np.all(np.abs(Wh[i * n:(i + 1) * n, :r] - Ki @ U) <= tol * scale)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n,m,k,cap,tol", [(3000, 400, 50, 20, 1e-8), (1000, 37, 9, 9, 0.0),
                                            (2500, 300, 123, 40, 1e-8), (513, 60, 1, 5, 1e-8)])
 def test_truncation_matches_oracle(torch, L, ctx, dt, n, m, k, cap, tol):
