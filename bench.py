@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--small", action="store_true", help="reduced grid (tests)")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "dir", "fp64"],
+                    help="mixed: fp32 ChebyshevT in fp64 refinement; dir: fp64 iterate and "
+                         "residual with fp32 preconditioner solves and directions")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no event timing in the timed region")
@@ -126,7 +128,7 @@ def main_batched(a, L, torch):
         "value": sec, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": (f"{len(sizes)} parameter subsets of sizes {min(sizes)}..{max(sizes)} "
                                 f"({sum(sizes)} parameters), each with its own perturbed "
                                 f"convection coefficients, {int(round(np.sqrt(n)))}x"
@@ -148,7 +150,8 @@ def main_batched(a, L, torch):
 def solve_opts(L, cfg, precision, eager=0):
     return L.default_opts(rank_cap=cfg["rank_cap"], trunc_tol=cfg["trunc_tol"],
                           res_tol=cfg["res_tol"], init=L.LRC_INIT_MEDIAN, verify_fp64=1,
-                          precision=L.LRC_MIXED_FP32 if precision == "mixed" else L.LRC_FP64,
+                          precision={"mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR,
+                                     "fp64": L.LRC_FP64}[precision],
                           eager=eager)
 
 
@@ -281,7 +284,7 @@ def main():
 
     # plain FP64 form of the same solve, for the time-to-tolerance comparison
     fp64 = None
-    if a.precision == "mixed" and not a.no_fp64_compare:
+    if a.precision != "fp64" and not a.no_fp64_compare:
         o64 = solve_opts(L, cfg, "fp64")
         one_solve(prob, o64, res_tol)
         torch.cuda.synchronize()
@@ -328,14 +331,16 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload_name(cfg, n, m), "n": int(n), "m": int(m),
                    "q": len(cfg["ops"].K),
                    "rank_cap": cfg["rank_cap"], "trunc_tol": cfg["trunc_tol"],
                    "res_tol": res_tol,
-                   "precision": ("fp32 inner ChebyshevT, fp64 residual + refinement"
-                                 if a.precision == "mixed" else "fp64")},
+                   "precision": {"mixed": "fp32 inner ChebyshevT, fp64 residual + refinement",
+                                 "dir": ("fp64 iterate and residual, fp32 preconditioner "
+                                         "solves and direction updates"),
+                                 "fp64": "fp64"}[a.precision]},
         "result": {"relres_fp64": last["relres"], "max_col_relres": last["max_col_relres"],
                    "iters": last["iters"], "refinements": last["refinements"],
                    "rank": last["rank"], "median_iters": last["median_iters"],

@@ -51,8 +51,11 @@ enum {
   LRC_ECALLBACK = -6   /* a user callback returned non-zero                  */
 };
 
-/* precision of the inner iteration */
-enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1 };
+/* precision of the iteration.  LRC_MIXED_FP32: fp32 ChebyshevT on the
+ * correction equation inside fp64 iterative refinement.  LRC_MIXED_FP32_DIR:
+ * one ChebyshevT whose iterate and residual (SpMM and truncation) are fp64
+ * while the preconditioner solves and the direction updates run in fp32. */
+enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2 };
 /* initial guess of lrc_solve */
 enum { LRC_INIT_ZERO = 0, LRC_INIT_MEDIAN = 1, LRC_INIT_GIVEN = 2 };
 
@@ -64,7 +67,7 @@ typedef struct {
   int restart;         /* restart the recurrence every `restart` updates, in [1, 64] */
   double cheb_c;       /* half-width of the spectrum interval (<= 0: from lrc_prob_spectrum) */
   double cheb_d;       /* centre of the spectrum interval                       */
-  int precision;       /* LRC_FP64 or LRC_MIXED_FP32                            */
+  int precision;       /* LRC_FP64, LRC_MIXED_FP32 or LRC_MIXED_FP32_DIR          */
   int refine_max;      /* mixed: maximum fp64 refinement steps                  */
   double inner_tol;    /* mixed: residual reduction asked of each fp32 inner solve */
   int init;            /* LRC_INIT_*                                            */
@@ -72,8 +75,9 @@ typedef struct {
   int verify_fp64;     /* 1: finish with the entry-wise fp64 residual           */
   int eager;           /* 1: launch every step directly instead of replaying the
                           captured HIP graphs of the iterations (same arithmetic) */
-  double inner_trunc_tol; /* mixed: truncation tolerance of the fp32 inner solve
-                          (<= 0: max(trunc_tol, 1e-2 * inner_tol))               */
+  double inner_trunc_tol; /* truncation tolerance of the fp32 steps (<= 0: for
+                          LRC_MIXED_FP32 max(trunc_tol, 1e-2 * inner_tol), for
+                          LRC_MIXED_FP32_DIR max(trunc_tol, 1e-6))                 */
 } lrc_opts;
 
 typedef struct {

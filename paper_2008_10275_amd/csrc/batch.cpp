@@ -449,6 +449,173 @@ struct BatchCheb {
   }
 };
 
+// ------------------------------------------------------------------ mixed directions
+// One ChebyshevT with an fp64 iterate S and fp64 residual R (SpMM and
+// truncation), and fp32 preconditioner solves Z = P^{-1} R and directions D:
+// R is copied to fp32 for the solve and the direction update, D back to fp64
+// for the iterate update.  Same lockstep and graph machinery as BatchCheb.
+struct BatchDir {
+  std::vector<SolveRun*> run;
+  int nb = 0, cycle = 6, cap = 0;
+  hipStream_t s = nullptr;
+  DevBuf done, ctl, castR, castD;
+  std::vector<BCtl> hctl;
+  std::vector<std::unique_ptr<DevBuf>> bufs;
+  int64_t rows_max = 0;
+  SpmmLaunch<double> sp0;
+  Batched<SpmmArgs<double>> spB;
+  PrecBatch<float> pb;
+  TruncPlan<double> resid0, supd0;
+  TruncBatch<double> residB, supdB;
+  TruncPlan<float> dstart0;
+  TruncBatch<float> dstartB;
+  std::vector<TruncPlan<float>> dstep0;
+  std::vector<TruncBatch<float>> dstepB;
+  Replay rep;
+
+  DevBuf& newbuf() {
+    bufs.push_back(std::make_unique<DevBuf>());
+    return *bufs.back();
+  }
+
+  void setup(std::vector<SolveRun*>& r, const lrc_opts& o, bool eager, hipStream_t s_) {
+    run = r;
+    nb = int(run.size());
+    s = s_;
+    cycle = o.restart;
+    rep.eager = eager;
+    cap = run[0]->cap;
+    done.alloc(size_t(nb) * sizeof(int));
+    ctl.alloc(size_t(nb) * sizeof(BCtl));
+    hctl.assign(nb, BCtl{});
+    const int* dn = done.as<int>();
+    std::vector<SpmmLaunch<double>> sl;
+    std::vector<SpmmArgs<double>> sa;
+    std::vector<PrecItem<float>> pi;
+    std::vector<const Prec*> pre;
+    std::vector<CastItem<double, float>> cr;
+    std::vector<CastItem<float, double>> cd;
+    for (auto* x : run) {
+      Cheb<double>& C = *x->c64;
+      Cheb<float>& F = *x->c32;
+      LRC_CHECK(x->cap == cap, ST_EINVAL, "batched solve: problems differ in rank_cap");
+      C.tol = o.trunc_tol;
+      F.tol = x->inner_trunc_tol;
+      rows_max = std::max(rows_max, x->P->ops->n + x->P->m);
+      sl.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
+      sa.push_back(sl.back().a);
+      pi.push_back(F.prec_item());
+      pre.push_back(x->P->prec.get());
+      cr.push_back(CastItem<double, float>{C.R.u(), C.R.v(), C.R.sv(), C.R.r(), F.R.u(), F.R.v(),
+                                           F.R.sv(), F.R.r(), C.R.ld, C.R.ld, F.R.ld, F.R.ld,
+                                           C.R.n, C.R.m, std::min(C.R.cap, F.R.cap)});
+      cd.push_back(CastItem<float, double>{F.D.u(), F.D.v(), F.D.sv(), F.D.r(), C.D.u(), C.D.v(),
+                                           C.D.sv(), C.D.r(), F.D.ld, F.D.ld, C.D.ld, C.D.ld,
+                                           F.D.n, F.D.m, std::min(F.D.cap, C.D.cap)});
+    }
+    sp0 = merge_spmm(sl);
+    spB = upload_items(sa, dn, newbuf(), s);
+    pb.setup(pre, pi, dn, cap, ld_for(cap), newbuf(), s);
+    upload_items(cr, dn, castR, s);
+    upload_items(cd, dn, castD, s);
+    auto site64 = [&](auto make, TruncPlan<double>& p0, TruncBatch<double>& bt) {
+      std::vector<TruncPlan<double>> v;
+      for (int j = 0; j < nb; ++j) v.push_back(make(j));
+      p0 = merge_plans(v);
+      bt = upload_plans(v, dn, newbuf(), s);
+    };
+    auto site32 = [&](auto make, TruncPlan<float>& p0, TruncBatch<float>& bt) {
+      std::vector<TruncPlan<float>> v;
+      for (int j = 0; j < nb; ++j) v.push_back(make(j));
+      p0 = merge_plans(v);
+      bt = upload_plans(v, dn, newbuf(), s);
+    };
+    site64([&](int j) {
+      Cheb<double>& C = *run[j]->c64;
+      return C.resid_plan(run[j]->B64, C.norm.as<double>(), o.trunc_tol);
+    }, resid0, residB);
+    site64([&](int j) { return run[j]->c64->supd_plan(); }, supd0, supdB);
+    site32([&](int j) { return run[j]->c32->dstart_plan(run[j]->dc); }, dstart0, dstartB);
+    std::vector<double> rho(nb);
+    for (int j = 0; j < nb; ++j) rho[j] = run[j]->c / run[j]->dc;
+    dstep0.resize(std::max(cycle - 1, 0));
+    dstepB.resize(std::max(cycle - 1, 0));
+    for (int k = 0; k + 1 < cycle; ++k) {
+      std::vector<double> rn(nb);
+      for (int j = 0; j < nb; ++j) rn[j] = 1.0 / (2.0 * run[j]->dc / run[j]->c - rho[j]);
+      site32([&](int j) {
+        return run[j]->c32->dstep_plan(rn[j] * rho[j], 2.0 * rn[j] / run[j]->c);
+      }, dstep0[k], dstepB[k]);
+      rho = rn;
+    }
+  }
+
+  void cast_r() {
+    launch_cast_lr(castR.as<CastItem<double, float>>(), done.as<int>(), nb, rows_max, cap, s);
+  }
+  void cast_d() {
+    launch_cast_lr(castD.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap, s);
+  }
+  void resid(int after_update) {
+    enqueue_spmm(sp0, spB, s);
+    enqueue_trunc(resid0, residB, s);
+    launch_batch_check(ctl.as<BCtl>(), done.as<int>(), nb, after_update, s);
+    cast_r();
+  }
+  void cycle_steps() {
+    pb.enqueue(s);
+    enqueue_trunc(dstart0, dstartB, s);
+    cast_d();
+    for (int k = 0; k < cycle; ++k) {
+      enqueue_trunc(supd0, supdB, s);
+      resid(1);
+      if (k + 1 == cycle) break;
+      pb.enqueue(s);
+      enqueue_trunc(dstep0[k], dstepB[k], s);
+      cast_d();
+    }
+  }
+
+  void solve(const std::vector<double>& r0_norm) {
+    bool copy = true;
+    for (auto* x : run) copy = copy && x->B64.cap <= x->c64->R.cap;
+    std::vector<int> dn(nb, 0);
+    for (int j = 0; j < nb; ++j) {
+      SolveRun& x = *run[j];
+      BCtl& h = hctl[j];
+      h = BCtl{};
+      h.norm = x.c64->norm.as<double>();
+      h.target = x.target;
+      h.max_iter = x.max_iter;
+      h.stall_limit = 1 << 30;
+      for (DevBuf* rk : {&x.c64->S.rank, &x.c64->D.rank, &x.c32->D.rank})
+        LRC_HIP(hipMemsetAsync(rk->p, 0, 16, s));
+      if (copy) {
+        const double nr = r0_norm[j];
+        h.last = h.best = nr;
+        if (!std::isfinite(nr)) h.state = 2;
+        else if (nr <= h.target) h.state = 1;
+        else if (h.max_iter <= 0) h.state = 2;
+        if (h.state) dn[j] = 1;
+        cast_lr<double, double>(x.B64, x.c64->R, s);
+      }
+    }
+    LRC_HIP(hipMemcpyAsync(ctl.p, hctl.data(), size_t(nb) * sizeof(BCtl), hipMemcpyHostToDevice, s));
+    LRC_HIP(hipMemcpyAsync(done.p, dn.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice, s));
+    if (copy) cast_r();
+    else resid(0);
+    while (true) {
+      LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, size_t(nb) * sizeof(BCtl),
+                             hipMemcpyDeviceToHost, s));
+      LRC_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (const auto& h : hctl) all = all && h.state != 0;
+      if (all) break;
+      rep.run(s, kcls(K_GRAPH, false), [&]() { cycle_steps(); });
+    }
+  }
+};
+
 int read_info(const int* p, hipStream_t s) {
   int v = 0;
   LRC_HIP(hipMemcpyAsync(&v, p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -555,7 +722,30 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
     tgt[j] = run[j]->target;
     mi[j] = run[j]->max_iter;
   }
-  if (o.precision == LRC_FP64) {
+  // ||B||: from the right-hand side's truncation, or ||F|| when B = F
+  std::vector<double> bn(nb);
+  for (int j = 0; j < nb; ++j) {
+    if (run[j]->P->rank_x0 == 0) {
+      bn[j] = run[j]->P->fnorm;
+    } else {
+      LRC_HIP(hipMemcpyAsync(&bn[j], run[j]->c64->norm.as<double>() + 4, 8,
+                             hipMemcpyDeviceToHost, s));
+    }
+  }
+  LRC_HIP(hipStreamSynchronize(s));
+  if (o.precision == LRC_MIXED_FP32_DIR) {
+    BatchDir bd;
+    bd.setup(run, o, eager, s);
+    bd.solve(bn);
+    for (int j = 0; j < nb; ++j) {
+      run[j]->iters = bd.hctl[j].iters;
+      run[j]->papp = bd.hctl[j].iters;
+      run[j]->conv = bd.hctl[j].state == 1;
+      run[j]->last = bd.hctl[j].last;
+      run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
+      run[j]->flags |= read_info(run[j]->c32->tr.st.info, s);
+    }
+  } else if (o.precision == LRC_FP64) {
     BatchCheb<double> bc;
     std::vector<Cheb<double>*> items;
     std::vector<const LR<double>*> rhs;
@@ -564,17 +754,6 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       rhs.push_back(&r->B64);
     }
     bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
-    // ||B||: from the right-hand side's truncation, or ||F|| when B = F
-    std::vector<double> bn(nb);
-    for (int j = 0; j < nb; ++j) {
-      if (run[j]->P->rank_x0 == 0) {
-        bn[j] = run[j]->P->fnorm;
-      } else {
-        LRC_HIP(hipMemcpyAsync(&bn[j], run[j]->c64->norm.as<double>() + 4, 8,
-                               hipMemcpyDeviceToHost, s));
-      }
-    }
-    LRC_HIP(hipStreamSynchronize(s));
     bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30, &bn);
     for (int j = 0; j < nb; ++j) {
       run[j]->iters = bc.hctl[j].iters;

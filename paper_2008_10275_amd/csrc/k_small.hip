@@ -319,14 +319,15 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
     if (fuse) V[i * P + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Off-diagonal entries below 1e-16 * trace(H) are rounding noise of the
-  // squared core and are not rotated; the eigenvalues are then accurate to
-  // that absolute level (singular values to ~1e-8 of the largest).
+  // Off-diagonal entries below max(1e-16, 0.01 tol^2) * trace(H) are not
+  // rotated: 1e-16 is the rounding noise of the squared core, and a truncation
+  // at relative tolerance tol needs the eigenvalues of H = M^T M (squared
+  // singular values) to no better than a small fraction of tol^2 * ||M||_F^2.
   if (tid < 64) {
     double tr = 0.0;
     for (int i = tid; i < k; i += 64) tr += fabs(H[i * P + i]);
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    if (tid == 0) s_floor = 1e-16 * tr;
+    if (tid == 0) s_floor = fmax(1e-16, 0.01 * ja_.tol * ja_.tol) * tr;
   }
   __syncthreads();
   const double floor_abs = s_floor;

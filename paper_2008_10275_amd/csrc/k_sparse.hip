@@ -573,6 +573,44 @@ void launch_med_check(const MedItem* items, MedCtl* ctl, int* done, int nb, int 
 }
 int med_partials() { return kMedBlocks; }
 
+// Batched copy of low-rank factors with a precision change: U (n rows), V (m
+// rows), the core s and the rank, the first min(rank, colcap) columns.
+template <class Tin, class Tout>
+__global__ __launch_bounds__(256) void cast_lr_kernel(const CastItem<Tin, Tout>* __restrict__ items,
+                                                      const int* __restrict__ done) {
+  if (done && done[blockIdx.z]) return;
+  const CastItem<Tin, Tout>& c = items[blockIdx.z];
+  const int cols = min(*c.r, c.colcap);
+  const int64_t total = (c.n + c.m) * c.colcap;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t row = e / c.colcap;
+    const int col = int(e - row * c.colcap);
+    if (col >= cols) continue;
+    if (row < c.n) c.U2[row * c.ldu2 + col] = Tout(c.U[row * c.ldu + col]);
+    else c.V2[(row - c.n) * c.ldv2 + col] = Tout(c.V[(row - c.n) * c.ldv + col]);
+  }
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < cols; t += blockDim.x) c.s2[t] = c.s[t];
+    if (threadIdx.x == 0) *c.r2 = cols;
+  }
+}
+
+template <class Tin, class Tout>
+void launch_cast_lr(const CastItem<Tin, Tout>* items, const int* done, int nb, int64_t rows_max,
+                    int colcap, hipStream_t s) {
+  const int64_t blocks =
+      std::min<int64_t>(std::max<int64_t>(ceil_div(rows_max * colcap, 256), 1), 4096);
+  ProfScope ps(kcls(K_VECTOR, false), s);
+  hipLaunchKernelGGL((cast_lr_kernel<Tin, Tout>), dim3(unsigned(blocks), 1, unsigned(nb)),
+                     dim3(256), 0, s, items, done);
+  LRC_HIP(hipGetLastError());
+}
+template void launch_cast_lr<double, float>(const CastItem<double, float>*, const int*, int,
+                                            int64_t, int, hipStream_t);
+template void launch_cast_lr<float, double>(const CastItem<float, double>*, const int*, int,
+                                            int64_t, int, hipStream_t);
+
 __global__ void fill_kernel(double* p, int64_t count, double v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
        i += int64_t(gridDim.x) * blockDim.x)

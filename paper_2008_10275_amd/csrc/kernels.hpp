@@ -273,6 +273,7 @@ struct JacArgs {
   TruncState st;
   int kcap;
   int max_rounds;
+  double tol;        // truncation tolerance (sets the rotation floor)
 };
 struct RepArgs {
   TruncState st;
@@ -382,6 +383,24 @@ void launch_med_resid(const MedItem* items, const int* done, int nb, hipStream_t
 void launch_med_check(const MedItem* items, MedCtl* ctl, int* done, int nb, int after_update,
                       hipStream_t s);
 void launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// One item of a batched factor copy with a precision change.
+template <class Tin, class Tout>
+struct CastItem {
+  const Tin* U;
+  const Tin* V;
+  const double* s;
+  const int* r;
+  Tout* U2;
+  Tout* V2;
+  double* s2;
+  int* r2;
+  int ldu, ldv, ldu2, ldv2;
+  int64_t n, m;
+  int colcap;        // columns the destination holds
+};
+template <class Tin, class Tout>
+void launch_cast_lr(const CastItem<Tin, Tout>* items, const int* done, int nb, int64_t rows_max,
+                    int colcap, hipStream_t s);
 void launch_copy_cols(const double* src, int lds, double* dst, int ldd, int64_t rows, int cols,
                       hipStream_t s);
 

@@ -164,7 +164,7 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.c2 = CholArgs{st, 2, kcap, eps};
   make_core_gemms(st, core, kcap, p.core);
   p.piv = PivArgs{st, kcap, tol};
-  p.jac = JacArgs{st, kcap, max_rounds};
+  p.jac = JacArgs{st, kcap, max_rounds, tol};
   p.rep = RepArgs{st, kcap};
   SmallGemmArgs fin[3];
   make_finish_gemms(st, kcap, rank_out, fin);
@@ -652,8 +652,18 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   // fp32 data resolves nothing much finer): by default 1e-2 * inner_tol
   inner_trunc_tol = o.inner_trunc_tol > 0
                         ? o.inner_trunc_tol
-                        : std::max(o.trunc_tol, 1e-2 * (o.inner_tol > 0 ? o.inner_tol : 1e-3));
-  if (o.precision != LRC_FP64) alloc_mixed();
+                        : std::max(o.trunc_tol, o.precision == LRC_MIXED_FP32_DIR
+                                                    ? 1e-6
+                                                    : 1e-2 * (o.inner_tol > 0 ? o.inner_tol : 1e-3));
+  LRC_CHECK(o.precision == LRC_FP64 || o.precision == LRC_MIXED_FP32 ||
+                o.precision == LRC_MIXED_FP32_DIR,
+            ST_EINVAL, "lrc_solve: unknown precision");
+  if (o.precision == LRC_MIXED_FP32) alloc_mixed();
+  if (o.precision == LRC_MIXED_FP32_DIR) {
+    // fp32 direction, preconditioned residual and their workspace
+    c32 = std::make_unique<Cheb<float>>();
+    c32->alloc(P, cap);
+  }
 }
 
 // X0 = x 1^T from the median column's solution x (column 0 of an n x 8 block)

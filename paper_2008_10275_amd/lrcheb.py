@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrcheb.h")
 
 LRC_OK, LRC_ENOTCONV, LRC_EINVAL, LRC_ENOMEM, LRC_EDEVICE = 0, 1, -1, -2, -3
 LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
-LRC_FP64, LRC_MIXED_FP32 = 0, 1
+LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR = 0, 1, 2
 LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN = 0, 1, 2
 
 

@@ -64,12 +64,12 @@ def _dense(sol):
 
 
 def _kw(L, precision):
+    prec = {"fp64": L.LRC_FP64, "mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR}[precision]
     return dict(rank_cap=30, trunc_tol=1e-8, res_tol=1e-6, init=L.LRC_INIT_MEDIAN,
-                precision=L.LRC_FP64 if precision == "fp64" else L.LRC_MIXED_FP32,
-                verify_fp64=1)
+                precision=prec, verify_fp64=1)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "dir"])
 def test_batched_matches_subset_solves(torch, L, ctx, c3, precision):
     cfg, subs = c3
     kw = _kw(L, precision)
@@ -131,7 +131,7 @@ def test_batched_rejects_unbounded_cycle(torch, L, ctx, c3):
         L.solve_batched([subs[0]["prob"]], **dict(_kw(L, "fp64"), restart=0))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "dir"])
 def test_graph_replay_matches_eager_launches(torch, L, ctx, c3, precision):
     """The captured graphs (replayed several times per solve, with host reads
     of the device flags between replays) against the same steps launched

@@ -203,8 +203,12 @@ def test_c1_fp64_solve_matches_oracle(torch, L, ctx):
     assert abs(rr - Xd_res) <= 1e-3 * Xd_res
 
 
-def test_c2_small_mixed_precision_reaches_1e6(torch, L, ctx):
-    say("solve c2-small mixed")
+@pytest.mark.parametrize("mode", ["refine", "dir"])
+def test_c2_small_mixed_precision_reaches_1e6(torch, L, ctx, mode):
+    """Both mixed forms: fp32 ChebyshevT inside fp64 refinement, and one
+    ChebyshevT with fp64 iterate/residual and fp32 preconditioner solves and
+    directions; the result is checked against the oracle's dense residual."""
+    say("solve c2-small mixed", mode)
     cfg = config("c2", small=True)
     K, d, f = cfg["ops"].K, cfg["d"], cfg["f"]
     m = d.shape[1]
@@ -212,7 +216,8 @@ def test_c2_small_mixed_precision_reaches_1e6(torch, L, ctx):
     prob = L.Problem(ops, d, f[:, None], np.ones((m, 1)))
     prob.precondition()
     code, info = prob.solve(rank_cap=40, trunc_tol=1e-8, res_tol=1e-6,
-                            precision=L.LRC_MIXED_FP32, init=L.LRC_INIT_MEDIAN)
+                            precision=L.LRC_MIXED_FP32 if mode == "refine" else L.LRC_MIXED_FP32_DIR,
+                            init=L.LRC_INIT_MEDIAN)
     say("info", info)
     assert code == 0 and info["relres"] <= 1e-6
     U, s, V = prob.solution()
