@@ -44,9 +44,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--small", action="store_true", help="reduced grid (tests)")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "dir", "fp64"],
+    ap.add_argument("--precision", default="dir", choices=["mixed", "dir", "fp64"],
                     help="mixed: fp32 ChebyshevT in fp64 refinement; dir: fp64 iterate and "
                          "residual with fp32 preconditioner solves and directions")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -141,6 +141,105 @@ def main_batched(a, L, torch):
                    "setup_s": setup_s},
         "sequential_fp64": seq,
         "speedup_vs_sequential_fp64": (seq["seconds"] / sec) if seq else None,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_surrogate(a, L, torch):
+    """Learned initial guess (surrogate-seeded solve) against the median one on
+    held-out parameters.  Untimed set-up: the training subset is solved on the
+    GPU, its solution gives the POD basis U0 and coefficients (GPU
+    truncation), the network is trained by the library's kernels.  Timed: for
+    the held-out subset, network inference + X0 = U0 C^T + ChebyshevT to 1e-6
+    (learned), against the median-parameter solve + ChebyshevT (median), both
+    in the chosen precision, and the plain FP64 median form."""
+    from workloads import config, mlp_init
+    cfg = config("c4", small=a.small)
+    K, f = cfg["ops"].K, cfg["f"]
+    dtr, dte = cfg["d_train"], cfg["d_test"]
+    r = cfg["basis_rank"]
+    ctx = L.Context(0)
+    ops = L.Operators(ctx, K)
+    n = K[0].shape[0]
+
+    def prob(d):
+        p = L.Problem(ops, d, f[:, None], np.ones((d.shape[1], 1)))
+        p.precondition()
+        return p
+
+    ptr, pte = prob(dtr), prob(dte)
+    res_tol = cfg["res_tol"]
+    base = dict(rank_cap=cfg["rank_cap"], trunc_tol=cfg["trunc_tol"], res_tol=res_tol,
+                verify_fp64=1)
+    code, _ = ptr.solve(L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=L.LRC_FP64))
+    if code != 0:
+        raise RuntimeError("training snapshots did not converge")
+    U, sv, V = ptr.solution()
+    k = U.shape[1]
+    ld = (k + 7) // 8 * 8
+    Ud = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
+    Ud[:, :k] = torch.from_numpy(U).cuda()
+    Vd = torch.zeros((V.shape[0], ld), dtype=torch.float64, device="cuda")
+    Vd[:, :k] = torch.from_numpy(V).cuda()
+    U0 = torch.zeros((n, 32), dtype=torch.float64, device="cuda")
+    V0 = torch.zeros((V.shape[0], 32), dtype=torch.float64, device="cuda")
+    s0, rr = L.truncate_dev(ctx, Ud, sv, Vd, r, 0.0, U0, V0)
+    Ctr = (V0[:, :rr] * torch.from_numpy(s0).cuda()).contiguous()
+    net = L.MLP(ctx, mlp_init(11, sizes=(2, 64, 64, rr)))
+    Xtr = torch.from_numpy(np.ascontiguousarray(dtr[1:].T)).cuda()
+    net.fit_scaling(Xtr, Ctr)
+    hist = net.train(Xtr, Ctr, 2000, lr=3e-3)
+    Xte = torch.from_numpy(np.ascontiguousarray(dte[1:].T)).cuda()
+    U0r = U0[:, :rr].contiguous()
+    prec = {"mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR, "fp64": L.LRC_FP64}[a.precision]
+    o_l = L.default_opts(**base, init=L.LRC_INIT_GIVEN, precision=prec)
+    o_m = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=prec)
+    o_p = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=L.LRC_FP64)
+
+    def learned():
+        C = net.predict(Xte)
+        code, info = pte.solve_x0_dev(U0r, C, opts=o_l)
+        return code, info
+
+    def median(o):
+        return pte.solve(o)
+
+    def timed(fn):
+        for _ in range(max(1, a.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            code, info = fn()
+        torch.cuda.synchronize()
+        if code != 0 or not info["relres"] <= res_tol:
+            raise RuntimeError(f"solve did not reach {res_tol}: {code} {info}")
+        return (time.perf_counter() - t0) / a.steps, info
+
+    t_l, i_l = timed(learned)
+    t_m, i_m = timed(lambda: median(o_m))
+    t_p, i_p = timed(lambda: median(o_p))
+    line = {
+        "metric": "time to rel. residual 1e-6 (s), learned initial guess",
+        "value": t_l, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": t_l * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": (f"learned initial guess on {dte.shape[1]} held-out parameters, "
+                                f"network 2-64-64-{rr} trained on {dtr.shape[1]} GPU solutions "
+                                f"(POD rank {rr}), 3-term stencil equation on a "
+                                f"{int(round(np.sqrt(n)))}x{int(round(np.sqrt(n)))} grid, n={n}"),
+                   "n": int(n), "m_train": int(dtr.shape[1]), "m_test": int(dte.shape[1]),
+                   "rank_cap": cfg["rank_cap"], "pod_rank": int(rr), "precision": a.precision},
+        "result": {"learned": dict(seconds=t_l, iters=i_l["iters"], relres=i_l["relres"]),
+                   "median": dict(seconds=t_m, iters=i_m["iters"], relres=i_m["relres"],
+                                  median_iters=i_m["median_iters"]),
+                   "fp64_median": dict(seconds=t_p, iters=i_p["iters"], relres=i_p["relres"]),
+                   "train_loss": [float(hist[0]), float(hist[-1])]},
+        "speedup_vs_median": t_m / t_l,
+        "speedup_vs_fp64_median": t_p / t_l,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -245,6 +344,9 @@ def main():
     if a.workload == "c3":
         main_batched(a, L, torch)
         return
+    if a.workload == "c4":
+        main_surrogate(a, L, torch)
+        return
 
     cfg, ctx, ops, prob, setup_s = problem_setup(L, a.workload, a.small)
     opts = solve_opts(L, cfg, a.precision)
@@ -293,6 +395,18 @@ def main():
         torch.cuda.synchronize()
         fp64 = dict(seconds=(time.perf_counter() - t1) / a.steps, iters=f_infos[-1]["iters"],
                     relres=f_infos[-1]["relres"])
+
+    # the other mixed form (fp32 ChebyshevT inside fp64 refinement), for reference
+    refine = None
+    if a.precision == "dir" and not a.no_fp64_compare:
+        orf = solve_opts(L, cfg, "mixed")
+        one_solve(prob, orf, res_tol)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        r_infos = [one_solve(prob, orf, res_tol) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        refine = dict(seconds=(time.perf_counter() - t3) / a.steps, iters=r_infos[-1]["iters"],
+                      refinements=r_infos[-1]["refinements"], relres=r_infos[-1]["relres"])
 
     ktab = kernel_table(prof_work, prof_time, a.steps) if prof_time else {}
     roof = None
@@ -347,6 +461,7 @@ def main():
                    "setup_s": setup_s},
         "eager_ms_per_step": eager_ms,
         "fp64_plain": fp64,
+        "mixed_refinement": refine,
         "speedup_vs_fp64": (fp64["seconds"] / (ms / 1e3)) if fp64 else None,
         "roofline": roof,
         "kernels": ktab,

@@ -56,7 +56,10 @@ enum {
  * one ChebyshevT whose iterate and residual (SpMM and truncation) are fp64
  * while the preconditioner solves and the direction updates run in fp32. */
 enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2 };
-/* initial guess of lrc_solve */
+/* initial guess of lrc_solve: none; the upper-median column's solution x~
+ * as the fixed term X0 = x~ 1^T; given factors as the fixed term X0.  The
+ * guess stays a separate exact term (X = X0 + S) so that truncation errors
+ * are relative to the small correction S, not to X. */
 enum { LRC_INIT_ZERO = 0, LRC_INIT_MEDIAN = 1, LRC_INIT_GIVEN = 2 };
 
 typedef struct {
@@ -170,6 +173,14 @@ lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* 
  * S with L(S) = F - L(X0) is computed by ChebyshevT.  info may be NULL. */
 lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0,
                      const double* s0, const double* V0, lrc_info* info);
+/* lrc_solve with the initial term X0 = U0 diag(s0) V0^T given as device
+ * factors (row-major fp64: U0 n x r0 with ld ldu, V0 m x r0 with ld ldv; s0
+ * host, NULL = ones), e.g. a surrogate's prediction that never leaves the
+ * GPU.  opts->init must be LRC_INIT_GIVEN and r0 in [1, 64]; the factors are
+ * copied before the call returns. */
+lrc_status lrc_solve_x0_dev(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0_dev,
+                            int ldu, const double* s0, const double* V0_dev, int ldv,
+                            lrc_info* info);
 /* Batched solve of K preconditioned problems of one context (Algorithm 1
  * treats the parameter subsets independently, so their Newton steps can run
  * together).  Same options and results as K calls of lrc_solve with

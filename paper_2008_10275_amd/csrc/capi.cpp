@@ -693,6 +693,20 @@ lrc_status lrc_solve(lrc_prob prob, const lrc_opts* opts, int r0, const double* 
   });
 }
 
+lrc_status lrc_solve_x0_dev(lrc_prob prob, const lrc_opts* opts, int r0, const double* U0_dev,
+                            int ldu, const double* s0, const double* V0_dev, int ldv,
+                            lrc_info* info) {
+  if (!prob || !opts) return LRC_EINVAL;
+  Prob& P = prob->p;
+  return guarded(P.ctx, [&]() -> lrc_status {
+    LRC_HIP(hipSetDevice(P.ctx->device));
+    LRC_CHECK(opts->init == LRC_INIT_GIVEN && r0 >= 1, ST_EINVAL,
+              "lrc_solve_x0_dev: needs init = LRC_INIT_GIVEN and r0 >= 1");
+    const X0Dev xd{U0_dev, ldu, V0_dev, ldv};
+    return solve_problem(P, *opts, r0, nullptr, s0, nullptr, info, &xd);
+  });
+}
+
 lrc_status lrc_solve_batched(lrc_prob* probs, int K, const lrc_opts* opts, lrc_info* infos) {
   if (!probs || K < 1 || !opts) return LRC_EINVAL;
   for (int k = 0; k < K; ++k)
@@ -701,7 +715,7 @@ lrc_status lrc_solve_batched(lrc_prob* probs, int K, const lrc_opts* opts, lrc_i
   return guarded(cx, [&]() -> lrc_status {
     LRC_HIP(hipSetDevice(cx->device));
     LRC_CHECK(opts->init != LRC_INIT_GIVEN, ST_EINVAL,
-              "lrc_solve_batched: LRC_INIT_GIVEN is not supported (use lrc_solve)");
+              "lrc_solve_batched: given initial terms are not supported (use lrc_solve)");
     std::vector<Prob*> ps(K);
     for (int k = 0; k < K; ++k) ps[k] = &probs[k]->p;
     std::vector<lrc_info> inf(K);

@@ -698,12 +698,13 @@ __global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* 
     const double total = sqrt(tot);
     int r = 0;
     if (total > 0.0) {
-      // smallest r with sqrt(sum_{j >= r} s_j^2) <= tol * total
+      // smallest r with sqrt(sum_{j >= r} s_j^2) <= max(tol * total, abs_tol)
       r = k;
       double tail = 0.0;
+      const double lim = fmax(tol * total, sa_.abs_tol);
       for (int j = k - 1; j >= 0; --j) {
         const double t2 = tail + srt[j] * srt[j];
-        if (sqrt(t2) <= tol * total) { tail = t2; r = j; }
+        if (sqrt(t2) <= lim) { tail = t2; r = j; }
         else break;
       }
     }

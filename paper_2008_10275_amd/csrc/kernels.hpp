@@ -284,6 +284,7 @@ struct SelArgs {
   int kcap;
   int rank_cap;
   double tol;
+  double abs_tol;    // the tail may also reach this absolute Frobenius norm
   double* s_out;
   int* rank_out;
   double* norm_out;

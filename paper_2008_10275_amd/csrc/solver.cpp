@@ -144,7 +144,7 @@ template <class T>
 TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockView<T>& B,
                                 int64_t m, const CoreView& core, int rank_cap, double tol,
                                 T* Uout, int ldu, T* Vout, int ldv, double* s_out, int* rank_out,
-                                double* norm_out) const {
+                                double* norm_out, double abs_tol) const {
   LRC_CHECK(n <= nmax && m <= mmax, ST_EINVAL, "truncation workspace too small");
   LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
             "truncation: rank cap must be in [1, 64] and fit the output leading dimensions");
@@ -171,7 +171,7 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.fin[0] = fin[0];
   p.fin[1] = fin[1];
   p.xab = fin[2];
-  p.sel = SelArgs{st, kcap, rank_cap, tol, s_out, rank_out, norm_out};
+  p.sel = SelArgs{st, kcap, rank_cap, tol, abs_tol, s_out, rank_out, norm_out};
   TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
                       {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
   p.t2 = make_tsmm<T>(t2, 2, kcap, rank_cap);
@@ -573,7 +573,7 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
 
 // ------------------------------------------------------------------ solve
 void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
-                       const double* V0) {
+                       const double* V0, const X0Dev* xd) {
   t0 = clk::now();
   P = &P_;
   Prob& Pr = *P;
@@ -626,10 +626,23 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     for (int i = 0; i < op.q; ++i) coefmed[i] = Pr.d[size_t(jmed) * op.q + i];
     median_tol = o.median_tol > 0 ? o.median_tol : 1e-10;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
-    LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
     Pr.X0.alloc(n, m, r0, s);
-    upload_lr(Pr.X0, r0, U0, s0, V0, s);
+    if (xd) {
+      // device factors (row-major fp64): copied, the core from the host
+      LRC_CHECK(xd->U && xd->V && xd->ldu >= r0 && xd->ldv >= r0, ST_EINVAL,
+                "lrc_solve_x0_dev: U0 and V0 device factors with ld >= r0 required");
+      launch_copy_cols(xd->U, xd->ldu, Pr.X0.u(), Pr.X0.ld, n, r0, s);
+      launch_copy_cols(xd->V, xd->ldv, Pr.X0.v(), Pr.X0.ld, m, r0, s);
+      std::vector<double> sv(size_t(std::max(Pr.X0.cap, 8)), 0.0);
+      for (int j = 0; j < r0; ++j) sv[j] = s0 ? s0[j] : 1.0;
+      LRC_HIP(hipMemcpyAsync(Pr.X0.s.p, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(Pr.X0.rank.p, &r0, sizeof(int), hipMemcpyHostToDevice, s));
+      LRC_HIP(hipStreamSynchronize(s));   // sv is a temporary
+    } else {
+      LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
+      upload_lr(Pr.X0, r0, U0, s0, V0, s);
+    }
     Pr.rank_x0 = r0;
   } else {
     Pr.X0.alloc(n, m, 1, s);
@@ -701,9 +714,13 @@ TruncPlan<double> SolveRun::rhs_plan(const lrc_opts& o, double* const* W0) const
     add_block(B, X0.v(), X0.ld, X0.r(), 0, Pr.drow(i));
     add_core(cv, X0.sv(), -1.0, X0.r(), 0);
   }
+  // B is kept to 1e-14 of its norm, but directions whose total weight stays
+  // below 1e-3 of the final residual target are dropped: they cannot move the
+  // result's residual by more than that
   const int rcap = std::min(B64.cap, 64);
   return c64->tr.plan(A, op.n, B, Pr.m, cv, rcap, std::min(1e-14, o.trunc_tol * 1e-3), B64.u(),
-                      B64.ld, B64.v(), B64.ld, B64.sv(), B64.r(), c64->norm.as<double>() + 4);
+                      B64.ld, B64.v(), B64.ld, B64.sv(), B64.r(), c64->norm.as<double>() + 4,
+                      1e-3 * target);
 }
 
 void SolveRun::alloc_mixed() {
@@ -783,9 +800,9 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
 }
 
 lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
-                         const double* V0, lrc_info* info) {
+                         const double* V0, lrc_info* info, const X0Dev* xd) {
   SolveRun run;
-  run.prepare(P, o, r0, U0, s0, V0);
+  run.prepare(P, o, r0, U0, s0, V0, xd);
   std::vector<SolveRun*> one{&run};
   lockstep(one, o);
   return run.finish(o, info);

@@ -127,7 +127,8 @@ struct Truncator {
            double* s_out, int* rank_out, double* norm_out, hipStream_t s);
   TruncPlan<T> plan(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
                     const CoreView& core, int rank_cap, double tol, T* Uout, int ldu, T* Vout,
-                    int ldv, double* s_out, int* rank_out, double* norm_out) const;
+                    int ldv, double* s_out, int* rank_out, double* norm_out,
+                    double abs_tol = 0.0) const;
 };
 
 struct Prob;
@@ -196,8 +197,16 @@ BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double
 
 double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S, double* colres);
 
+// Initial term given as device factors (row-major fp64).
+struct X0Dev {
+  const double* U;
+  int ldu;
+  const double* V;
+  int ldv;
+};
+
 lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
-                         const double* V0, lrc_info* info);
+                         const double* V0, lrc_info* info, const X0Dev* xd = nullptr);
 
 // One solve split into set-up (spectrum bounds, workspaces, the median
 // column's system), the iterative phases (run by `lockstep` for one or many
@@ -222,7 +231,7 @@ struct SolveRun {
   double cm = 0.0, dm = 0.0, median_tol = 0.0;
   std::vector<double> fmed, coefmed;
   void prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
-               const double* V0);
+               const double* V0, const X0Dev* xd = nullptr);
   void set_median_x0(const double* x, int iters);
   TruncPlan<double> rhs_plan(const lrc_opts& o, double* const* W0) const;
   lrc_status finish(const lrc_opts& o, lrc_info* info);

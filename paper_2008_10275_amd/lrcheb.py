@@ -78,6 +78,8 @@ _SIGS = {
     "lrc_solve": (C.c_int, [_P, C.POINTER(lrc_opts), C.c_int, _P, _P, _P,
                             C.POINTER(lrc_info)]),
     "lrc_solve_batched": (C.c_int, [_P, C.c_int, C.POINTER(lrc_opts), C.POINTER(lrc_info)]),
+    "lrc_solve_x0_dev": (C.c_int, [_P, C.POINTER(lrc_opts), C.c_int, _P, C.c_int, _P, _P, C.c_int,
+                                   C.POINTER(lrc_info)]),
     "lrc_get_solution": (C.c_int, [_P, C.POINTER(C.c_int), _P, _P, _P]),
     "lrc_residual": (C.c_int, [_P, C.POINTER(C.c_double), _P]),
     "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
@@ -313,6 +315,19 @@ class Problem:
             r0 = U0.shape[1]
         code = load().lrc_solve(self.handle, C.byref(o), r0, _ptr(U0), _ptr(s0), _ptr(V0),
                                 C.byref(info))
+        _check(self.ctx.handle, code)
+        return code, info.as_dict()
+
+    def solve_x0_dev(self, U0, V0, s0=None, opts=None, **kw):
+        """lrc_solve_x0_dev: X0 = U0 diag(s0) V0^T from row-major fp64 device
+        tensors (n x r0 and m x r0).  Returns (status, info dict)."""
+        kw.setdefault("init", LRC_INIT_GIVEN)
+        o = opts if opts is not None else default_opts(**kw)
+        info = lrc_info()
+        r0 = U0.shape[1]
+        sv = None if s0 is None else _f64(s0)
+        code = load().lrc_solve_x0_dev(self.handle, C.byref(o), r0, _dev_ptr(U0), U0.stride(0),
+                                       _ptr(sv), _dev_ptr(V0), V0.stride(0), C.byref(info))
         _check(self.ctx.handle, code)
         return code, info.as_dict()
 

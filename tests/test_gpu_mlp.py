@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import lowrank as olr
 from oracle import mlp as omlp
 from workloads import config, mlp_init, param_table
 
@@ -163,6 +164,15 @@ def test_learned_initial_guess_gain(torch, L, ctx):
     pl, code_l, info_l = _solve(L, ops, dte, f, init=L.LRC_INIT_GIVEN, X0=(U0h, np.ones(rr), Cte))
     say("median", info_m["iters"], info_m["relres"], "learned", info_l["iters"], info_l["relres"])
     assert code_m == 0 and code_l == 0
+    # the same guess passed as device factors (lrc_solve_x0_dev)
+    code_d, info_d = pl.solve_x0_dev(U0[:, :rr].contiguous(), torch.from_numpy(Cte).cuda(),
+                                     rank_cap=30, trunc_tol=1e-8, res_tol=1e-6)
+    assert code_d == 0 and info_d["iters"] == info_l["iters"]
+    assert abs(info_d["relres"] - info_l["relres"]) <= 1e-3 * info_l["relres"]
+    Ul, sl, Vl = pl.solution()
+    Xl = Ul @ np.diag(sl) @ Vl.T
+    Fd = np.outer(f, np.ones(dte.shape[1]))
+    assert olr.relres_dense(K, dte, Xl, Fd) <= 1.01e-6
     assert info_l["relres"] <= 1e-6
     # the learned guess starts closer: no more Chebyshev updates than the median one
     assert info_l["iters"] <= info_m["iters"]
