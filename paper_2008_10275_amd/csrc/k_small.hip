@@ -276,29 +276,32 @@ __device__ inline int rr_player(int pos, int t, int kp) {
 }
 
 // Two-sided Jacobi on the symmetric H (k x k, padded to even kp with a zero
-// row/column), stored in full in LDS.  Every round applies kp/2 disjoint
-// rotations H <- J^T H J.  Each wave computes all of a round's rotations
-// itself (into its own LDS slots); a barrier separates those reads of H from
-// the update, and another ends the round.  Rounds without a rotation (the
-// same decision in every wave) skip both.  Up to
-// kJFuse the eigenvectors V = prod J accumulate in LDS next to H and are
-// written to st.VM (st.rounds = -1 marks this); beyond, the (c, s) of every
-// round are logged and V is rebuilt per row by the replay kernel.
-constexpr int kJL = SK + 1;
+// row/column).  H is kept as its packed upper triangle, twice: every round
+// reads one copy and writes the rotated matrix H <- J^T H J into the other,
+// so a single barrier per round separates the rounds.  A round applies kp/2
+// disjoint rotations; each wave computes all of them itself from the copy it
+// reads (no broadcast), and the 2 x 2 blocks (pair a, pair b), a <= b, are
+// rotated once each (the lower triangle is the same storage).  Rounds without
+// a rotation (the same decision in every wave) are skipped.  Up to kJFuse
+// the eigenvectors V = prod J accumulate in LDS next to H and are written to
+// st.VM (st.rounds = -1 marks this); beyond, the (c, s) of every round are
+// logged and V is rebuilt per row by the replay kernel.
 constexpr int kJFuse = 88;
 constexpr int kJacThreads = 1024;
+constexpr int kJacLds = 2 * SKP;            // doubles: two packed copies of H at kp <= 128
+static_assert(2 * (kJFuse * (kJFuse + 1) / 2) + kJFuse * (kJFuse + 1) <= kJacLds,
+              "fused eigenvectors must fit next to the two packed copies");
 __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const JacArgs* ab,
                                                             const int* done) {
   LRC_ITEM(JacArgs, ja_, a0, ab, done)
   const TruncState& st = ja_.st;
   const int kcap = ja_.kcap, max_rounds = ja_.max_rounds;
-  __shared__ double Ls[SK * kJL];
+  __shared__ double lds[kJacLds];
   __shared__ double2 csw[kJacThreads / 64][SK / 2];
   __shared__ short2 pqw[kJacThreads / 64][SK / 2];
   __shared__ double s_floor;
   const int k = *st.kj;
   const int kp = k + (k & 1);
-  const int P = kp + 1;
   const bool fuse = k <= kJFuse;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   if (k <= 1) {
@@ -311,11 +314,13 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
     }
     return;
   }
-  double* H = Ls;
-  double* V = Ls + size_t(kp) * P;
+  const int np = kp * (kp + 1) / 2;
+  double* Hs[2] = {lds, lds + np};
+  double* V = lds + 2 * np;                 // kp x (kp + 1) when fused
+  const int P = kp + 1;
   for (int e = tid; e < kp * kp; e += nt) {
     const int i = e / kp, j = e - i * kp;
-    H[i * P + j] = (i < k && j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
+    if (j >= i) Hs[0][pu(i, j, kp)] = (j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
     if (fuse) V[i * P + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -325,18 +330,31 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
   // singular values) to no better than a small fraction of tol^2 * ||M||_F^2.
   if (tid < 64) {
     double tr = 0.0;
-    for (int i = tid; i < k; i += 64) tr += fabs(H[i * P + i]);
+    for (int i = tid; i < k; i += 64) tr += fabs(Hs[0][pu(i, i, kp)]);
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
     if (tid == 0) s_floor = fmax(1e-16, 0.01 * ja_.tol * ja_.tol) * tr;
   }
   __syncthreads();
   const double floor_abs = s_floor;
   const int npair = kp / 2;
-  int round = 0;
+  const int nblk = npair * (npair + 1) / 2;     // <= 2080: at most 3 blocks per thread
+  // this thread's blocks (pair a, pair b), a <= b, in row-major order of the
+  // upper triangle of the pair grid
+  int ba[3], bb[3], nmy = 0;
+  for (int e = tid; e < nblk; e += nt) {
+    int a = 0, rem = e;
+    while (rem >= npair - a) { rem -= npair - a; ++a; }
+    ba[nmy] = a;
+    bb[nmy] = a + rem;
+    ++nmy;
+  }
+  int round = 0, cur = 0;
   bool converged = false;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
     int nrot = 0;
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
+      const double* H = Hs[cur];
+      double* Hn = Hs[cur ^ 1];
       bool rot = false;
       if (lane < npair) {
         // pair slot `lane` of round t: positions lane and kp-1-lane of the
@@ -344,7 +362,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
         const int x0 = lane == 0 ? 0 : 1 + (lane - 1 + t) % (kp - 1);
         const int x1 = 1 + (kp - 2 - lane + t) % (kp - 1);
         const int p = min(x0, x1), q = max(x0, x1);
-        const double hpp = H[p * P + p], hqq = H[q * P + q], hpq = H[p * P + q];
+        const double hpp = H[pu(p, p, kp)], hqq = H[pu(q, q, kp)], hpq = H[pu(p, q, kp)];
         double c = 1.0, sn = 0.0;
         if (fabs(hpq) > floor_abs) {
           const double zeta = (hqq - hpp) / (2.0 * hpq);
@@ -363,25 +381,26 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
       const int rr = __popcll(__ballot(rot));
       if (rr == 0) continue;          // H unchanged: no update, no barrier
       nrot += rr;
-      __syncthreads();                // every wave has read the pivots of this round
-      // H <- J^T H J as one pass over the 2 x 2 blocks (pair a, pair b)
-      for (int e = tid; e < npair * npair; e += nt) {
-        const int a = e / npair, b = e - a * npair;
+      // Hn <- J^T H J over the blocks (pair a, pair b), a <= b
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (u >= nmy) break;
+        const int a = ba[u], b = bb[u];
         const double2 ja = csw[wave][a], jb = csw[wave][b];
-        if (ja.y == 0.0 && jb.y == 0.0) continue;
         const short2 qa2 = pqw[wave][a], qb2 = pqw[wave][b];
         const int pa = qa2.x, qa = qa2.y, pb = qb2.x, qb = qb2.y;
-        const double h00 = H[pa * P + pb], h01 = H[pa * P + qb];
-        const double h10 = H[qa * P + pb], h11 = H[qa * P + qb];
+        auto at = [&](int x, int y) { return x <= y ? pu(x, y, kp) : pu(y, x, kp); };
+        const int i00 = at(pa, pb), i01 = at(pa, qb), i10 = at(qa, pb), i11 = at(qa, qb);
+        const double h00 = H[i00], h01 = H[i01], h10 = H[i10], h11 = H[i11];
         const double l00 = ja.x * h00 - ja.y * h10, l01 = ja.x * h01 - ja.y * h11;
         const double l10 = ja.y * h00 + ja.x * h10, l11 = ja.y * h01 + ja.x * h11;
         double r00 = jb.x * l00 - jb.y * l01, r01 = jb.y * l00 + jb.x * l01;
         double r10 = jb.x * l10 - jb.y * l11, r11 = jb.y * l10 + jb.x * l11;
-        if (a == b) r01 = r10 = 0.0;      // the rotated pair is diagonalised
-        H[pa * P + pb] = r00;
-        H[pa * P + qb] = r01;
-        H[qa * P + pb] = r10;
-        H[qa * P + qb] = r11;
+        if (a == b && ja.y != 0.0) r01 = r10 = 0.0;   // the rotated pair is diagonalised
+        Hn[i00] = r00;
+        Hn[i01] = r01;
+        Hn[i11] = r11;
+        if (a != b) Hn[i10] = r10;        // a == b: (qa, pa) is (pa, qa)'s storage
       }
       if (fuse) {
         // V <- V J: columns (p_a, q_a) of every row
@@ -395,17 +414,19 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
           V[i * P + q2.y] = ja.y * vp + ja.x * vq;
         }
       }
+      cur ^= 1;
       __syncthreads();
     }
     if (nrot == 0) { converged = true; break; }
   }
+  const double* H = Hs[cur];
   if (fuse) {
     for (int e = tid; e < k * k; e += nt) {
       const int i = e / k, j = e - i * k;
       st.VM[size_t(i) * kcap + j] = V[i * P + j];
     }
   }
-  for (int j = tid; j < k; j += nt) st.lam[j] = H[j * P + j];
+  for (int j = tid; j < k; j += nt) st.lam[j] = H[pu(j, j, kp)];
   if (tid == 0) {
     *st.rounds = fuse ? -1 : round;
     if (!converged) atomicOr(st.info, 4);
@@ -471,6 +492,8 @@ void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s) {
                      dim3(64), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
+
+constexpr int kJL = SK + 1;   // row stride of full k x k matrices in LDS
 
 // ============================================================== pivoted Cholesky
 // Diagonally pivoted Cholesky of H = M^T M:  Pi^T H Pi = R^T R, stopped once
