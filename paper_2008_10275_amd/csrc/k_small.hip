@@ -34,25 +34,45 @@ __device__ inline int pu(int i, int j, int k) {   // packed upper by rows, i <= 
 }
 
 constexpr int kCholThreads = 512;
+constexpr int kCL = SK + 1;   // row stride of the k x k matrix in LDS
+typedef double doublex4_c __attribute__((ext_vector_type(4)));
+__device__ inline doublex4_c mfma64(double a, double b, doublex4_c c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// value of v in lane `src` (uniform), through scalar registers
+__device__ inline double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b & 0xffffffffll), src));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), src));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Blocked right-looking Cholesky in 16-column panels: the diagonal block is
+// factorised (and inverted) by one wave in registers with lane shuffles, the
+// panel row R_IJ = R_II^-T A_IJ and the trailing update A_JL -= R_IJ^T R_IL
+// run as 16 x 16 x 16 fp64 MFMA tile products; three barriers per panel.  The
+// matrix is padded to whole tiles with identity rows.  R^-1 follows by block
+// diagonals: W_IJ = sum_{I<L<=J} R_IL X_LJ, X_IJ = -X_II W_IJ, with the
+// off-diagonal blocks of X kept in the (otherwise unused) lower triangle.
 __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const CholArgs* ab,
                                                             const int* done) {
   LRC_ITEM(CholArgs, ca, a0, ab, done)
   const TruncState& st = ca.st;
   const int pass = ca.pass, kcap = ca.kcap;
   const double eps = ca.eps;
-  __shared__ double Rp[SKP];
-  __shared__ double Xp[SKP];
-  __shared__ double Wt[(SK / 16) * 256];
+  __shared__ double A[SK * kCL];
+  __shared__ double Tb[SK / 16][16][17];    // inverses of the diagonal blocks
   __shared__ double dsc[SK];
-  __shared__ double pivv[SK];
   __shared__ double s_gm;
+  __shared__ int s_fail;
   const int side = blockIdx.x;
   const int k = *st.k;
   const double* G = st.G[side];
   double* Rout = pass == 1 ? st.R1[side] : st.R2[side];
   double* Tout = pass == 1 ? st.T1[side] : st.R2i[side];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int nwv = nt >> 6;
   if (k == 0) return;
+  const int nbk = (k + 15) / 16, kp = nbk * 16;
   if (tid < 64) {
     double gm = 0.0;
     for (int j = tid; j < k; j += 64) gm = fmax(gm, G[size_t(j) * kcap + j]);
@@ -68,45 +88,93 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
   const double tau = eps * k;
   double shift = 0.0;
   bool fail = true;
-  // trailing-update mapping: column slot tid % 128, row phase tid / 128
-  const int tc = tid & 127, tr = tid >> 7, nr = nt >> 7;
+  const int lr = lane >> 4, lc = lane & 15;   // MFMA slice row group, column
   for (int attempt = 0; attempt < 6 && fail; ++attempt) {
-    for (int e = tid; e < k * k; e += nt) {
-      const int i = e / k, j = e - i * k;
-      if (j < i) continue;
-      const double di = dsc[i], dj = dsc[j];
-      Rp[pu(i, j, k)] = (di == 0.0 || dj == 0.0)
-                            ? (i == j ? 1.0 : 0.0)
-                            : di * G[size_t(i) * kcap + j] * dj + (i == j ? shift : 0.0);
+    // equilibrated (and shifted) Gram, identity on dead columns and padding
+    for (int e = tid; e < kp * kp; e += nt) {
+      const int i = e / kp, j = e - i * kp;
+      double v;
+      if (i < k && j < k) {
+        const double di = dsc[i], dj = dsc[j];
+        v = (di == 0.0 || dj == 0.0) ? (i == j ? 1.0 : 0.0)
+                                     : di * G[size_t(i) * kcap + j] * dj + (i == j ? shift : 0.0);
+      } else {
+        v = i == j ? 1.0 : 0.0;
+      }
+      A[i * kCL + j] = v;
     }
+    if (tid == 0) s_fail = 0;
     __syncthreads();
-    fail = false;
-    for (int j = 0; j < k; ++j) {
-      const double p = Rp[pu(j, j, k)];
-      if (!(p > tau)) { fail = true; break; }       // same value in every thread
-      const double ip = 1.0 / p;
-      const int c = j + 1 + tc;
-      if (c < k) {
-        const double ajc = Rp[pu(j, c, k)] * ip;
-        // rows a = j + 1 + tr + nr * u, four at a time (loads before stores)
-        for (int a = j + 1 + tr; a <= c; a += 4 * nr) {
-          double x[4], y[4];
+    for (int I = 0; I < nbk; ++I) {
+      const int o = 16 * I;
+      if (wave == 0) {
+        // lane c < 16 holds column c of the diagonal block (rows 0..15)
+        double a[16], x[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int au = a + u * nr;
-            x[u] = au <= c ? Rp[pu(j, au, k)] : 0.0;
-            y[u] = au <= c ? Rp[pu(au, c, k)] : 0.0;
-          }
+        for (int r = 0; r < 16; ++r) a[r] = lc < 16 ? A[(o + r) * kCL + o + lc] : 0.0;
+        bool bad = false;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int au = a + u * nr;
-            if (au <= c) Rp[pu(au, c, k)] = y[u] - x[u] * ajc;
+        for (int jj = 0; jj < 16; ++jj) {
+          const double piv = lane_bcast(a[jj], jj);
+          if (!(piv > tau) && o + jj < k) bad = true;
+          const double rjj = sqrt(fmax(piv, 1e-300));
+          a[jj] = lane == jj ? rjj : (lane > jj ? a[jj] / rjj : a[jj]);
+#pragma unroll
+          for (int ii = jj + 1; ii < 16; ++ii) {
+            const double t = lane_bcast(a[jj], ii);     // r_{jj, ii}
+            if (lane >= ii) a[ii] -= t * a[jj];
           }
         }
+        // x = column lc of the inverse of the upper-triangular block
+#pragma unroll
+        for (int ii = 15; ii >= 0; --ii) {
+          double acc = 0.0;
+#pragma unroll
+          for (int tt = ii + 1; tt < 16; ++tt) {
+            const double r = lane_bcast(a[ii], tt);     // r_{ii, tt}
+            acc += (tt <= lane) ? r * x[tt] : 0.0;
+          }
+          const double rii = lane_bcast(a[ii], ii);
+          x[ii] = ii == lane ? 1.0 / rii : (ii < lane ? -acc / rii : 0.0);
+        }
+        if (lane < 16) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            A[(o + r) * kCL + o + lane] = r <= lane ? a[r] : 0.0;
+            Tb[I][r][lane] = x[r];
+          }
+        }
+        if (bad && lane == 0) s_fail = 1;
       }
-      if (tid == 0) pivv[j] = p;
+      __syncthreads();
+      if (s_fail) break;                       // same value in every thread
+      // panel row: R_IJ = X_II^T A_IJ, one wave per tile
+      for (int J = I + 1 + wave; J < nbk; J += nwv) {
+        doublex4_c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+          acc = mfma64(Tb[I][kk + lr][lc], A[(o + kk + lr) * kCL + 16 * J + lc], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(o + lr + 4 * v) * kCL + 16 * J + lc] = acc[v];
+      }
+      __syncthreads();
+      // trailing update of the upper tiles: A_JL -= R_IJ^T R_IL, I < J <= L
+      const int nr = nbk - I - 1;
+      for (int tt = wave; tt < nr * (nr + 1) / 2; tt += nwv) {
+        int J = 0, rem = tt;
+        while (rem >= nr - J) { rem -= nr - J; ++J; }
+        const int L = I + 1 + J + rem;
+        J += I + 1;
+        doublex4_c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+          acc = mfma64(A[(o + kk + lr) * kCL + 16 * J + lc], A[(o + kk + lr) * kCL + 16 * L + lc], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * J + lr + 4 * v) * kCL + 16 * L + lc] -= acc[v];
+      }
       __syncthreads();
     }
+    fail = s_fail != 0;
     if (fail) {
       shift = shift == 0.0 ? 10.0 * tau : 100.0 * shift;
       if (tid == 0) atomicOr(st.info, 1);
@@ -116,63 +184,51 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
   if (fail) {
     // give up on factorising: identity factor (the truncation then works on the
     // equilibrated columns as they are) and report the breakdown
-    for (int e = tid; e < k * k; e += nt) {
-      const int i = e / k, j = e - i * k;
-      if (j >= i) Rp[pu(i, j, k)] = (i == j) ? 1.0 : 0.0;
+    for (int e = tid; e < kp * kp; e += nt) {
+      const int i = e / kp, j = e - i * kp;
+      if (j >= i) A[i * kCL + j] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int e = tid; e < nbk * 256; e += nt) {
+      const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      Tb[I][r][c] = r == c ? 1.0 : 0.0;
     }
     if (tid == 0) atomicOr(st.info, 2);
-  } else {
-    // R[i][j] = A[i][j] / sqrt(p_i), R[i][i] = sqrt(p_i)
-    for (int e = tid; e < k * k; e += nt) {
-      const int i = e / k, j = e - i * k;
-      if (j < i) continue;
-      const double sp = sqrt(pivv[i]);
-      Rp[pu(i, j, k)] = (i == j) ? sp : Rp[pu(i, j, k)] / sp;
-    }
   }
   __syncthreads();
   // Rout = R D^{-1}
   for (int e = tid; e < kcap * kcap; e += nt) {
     const int i = e / kcap, j = e - i * kcap;
     double v = 0.0;
-    if (i < k && j < k && j >= i && dsc[j] != 0.0) v = Rp[pu(i, j, k)] / dsc[j];
+    if (i < k && j < k && j >= i && dsc[j] != 0.0) v = A[i * kCL + j] / dsc[j];
     Rout[e] = v;
   }
-  // blocked inverse of the upper-triangular R (16 x 16 blocks): diagonal
-  // blocks by back substitution (one column per thread), then the block
-  // diagonals d = 1, 2, ... from X_IJ = -X_II sum_{r in I+1..J} R_Ir X_rJ
-  const int nbk = (k + 15) / 16;
-  for (int t = tid; t < nbk * 16; t += nt) {
-    const int I = t / 16, J = t;
-    if (J >= k) continue;
-    const int lo = I * 16;
-    for (int i = J; i >= lo; --i) {
-      double sacc = (i == J) ? 1.0 : 0.0;
-      for (int q = i + 1; q <= J; ++q) sacc -= Rp[pu(i, q, k)] * Xp[pu(q, J, k)];
-      Xp[pu(i, J, k)] = sacc / Rp[pu(i, i, k)];
-    }
-  }
-  __syncthreads();
+  // X = R^{-1} by block diagonals; X_IJ (I < J) lives in the lower tile (J, I)
   for (int d = 1; d < nbk; ++d) {
-    const int npairs = nbk - d;
-    for (int e = tid; e < npairs * 256; e += nt) {
-      const int I = e / 256, w = e & 255, J = I + d;
-      const int i = I * 16 + w / 16, j = J * 16 + (w & 15);
-      double sacc = 0.0;
-      if (i < k && j < k)
-        for (int r = (I + 1) * 16; r <= j; ++r) sacc += Rp[pu(i, r, k)] * Xp[pu(r, j, k)];
-      Wt[e] = sacc;
+    // W_IJ = sum_{L = I+1..J} R_IL X_LJ into the tile of X_IJ
+    for (int I = wave; I + d < nbk; I += nwv) {
+      const int J = I + d;
+      doublex4_c acc = {0.0, 0.0, 0.0, 0.0};
+      for (int L = I + 1; L <= J; ++L) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const double xv = L == J ? Tb[J][kk + lr][lc]
+                                   : A[(16 * J + kk + lr) * kCL + 16 * L + lc];
+          acc = mfma64(A[(16 * I + lc) * kCL + 16 * L + kk + lr], xv, acc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(16 * J + lr + 4 * v) * kCL + 16 * I + lc] = acc[v];
     }
     __syncthreads();
-    for (int e = tid; e < npairs * 256; e += nt) {
-      const int I = e / 256, w = e & 255, J = I + d;
-      const int ii = w / 16, jj = w & 15;
-      const int i = I * 16 + ii, j = J * 16 + jj;
-      if (i >= k || j >= k) continue;
-      double sacc = 0.0;
-      for (int q = ii; q < 16 && I * 16 + q < k; ++q)
-        sacc -= Xp[pu(i, I * 16 + q, k)] * Wt[I * 256 + q * 16 + jj];
-      Xp[pu(i, j, k)] = sacc;
+    // X_IJ = -X_II W_IJ, in place
+    for (int I = wave; I + d < nbk; I += nwv) {
+      const int J = I + d;
+      doublex4_c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4)
+        acc = mfma64(Tb[I][lc][kk + lr], A[(16 * J + kk + lr) * kCL + 16 * I + lc], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(16 * J + lr + 4 * v) * kCL + 16 * I + lc] = -acc[v];
     }
     __syncthreads();
   }
@@ -180,7 +236,11 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
   for (int e = tid; e < kcap * kcap; e += nt) {
     const int i = e / kcap, j = e - i * kcap;
     double v = 0.0;
-    if (i < k && j < k && j >= i) v = dsc[i] * Xp[pu(i, j, k)];
+    if (i < k && j < k && j >= i) {
+      const int I = i >> 4, J = j >> 4;
+      const double xv = I == J ? Tb[I][i & 15][j & 15] : A[(16 * J + (i & 15)) * kCL + 16 * I + (j & 15)];
+      v = dsc[i] * xv;
+    }
     Tout[e] = v;
   }
 }
