@@ -17,6 +17,11 @@ namespace lrc {
 
 namespace {
 
+bool log_on() {
+  static const bool on = std::getenv("LRC_LOG") != nullptr;
+  return on;
+}
+
 // Uploads one launch's per-item argument structs.
 template <class A>
 Batched<A> upload_items(const std::vector<A>& v, const int* done, DevBuf& buf, hipStream_t s) {
@@ -96,10 +101,6 @@ struct CaptureGuard {
   }
 };
 
-bool log_on() {
-  static const bool on = std::getenv("LRC_LOG") != nullptr;
-  return on;
-}
 
 // Preconditioner applies of a batch: one launch per level for all items when
 // their factorisations share the supernode structure, else one per item.
@@ -157,10 +158,16 @@ struct Replay {
       return;
     }
     if (!graph.x) {
+      const auto t0 = std::chrono::steady_clock::now();
       CaptureGuard cg(s);
       steps();
       graph.g = cg.end();
+      const auto t1 = std::chrono::steady_clock::now();
       LRC_HIP(hipGraphInstantiate(&graph.x, graph.g, nullptr, nullptr, 0));
+      if (log_on())
+        std::fprintf(stderr, "{\"graph_capture_s\": %.5f, \"instantiate_s\": %.5f}\n",
+                     std::chrono::duration<double>(t1 - t0).count(),
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
     }
     ProfScope ps(cls, s);
     LRC_HIP(hipGraphLaunch(graph.x, s));
@@ -172,12 +179,9 @@ struct Replay {
 // item at once; a few iterations per graph replay.
 struct MedianBatch {
   static constexpr int kIterPerReplay = 4;
-  struct Buf {
-    DevBuf f, coef, x, dl, r, z, W, py, px, pcb, pst, part;
-  };
   int nb = 0;
   hipStream_t s = nullptr;
-  std::vector<std::unique_ptr<Buf>> b;
+  std::vector<MedWork*> b;
   std::vector<std::unique_ptr<DevBuf>> bufs;
   DevBuf items, ctl, done;
   std::vector<MedCtl> hctl;
@@ -208,19 +212,22 @@ struct MedianBatch {
       const Ops& op = *P.ops;
       const int64_t n = op.n;
       nmax = std::max(nmax, n);
-      b.push_back(std::make_unique<Buf>());
-      Buf& x = *b.back();
+      MedWork& x = r.med;
+      b.push_back(&x);
       const size_t col = size_t(n) * 8 * 8;
-      x.f = upload(r.fmed, s);
-      x.coef = upload(r.coefmed, s);
+      ensure(x.f, r.fmed.size() * 8);
+      ensure(x.coef, r.coefmed.size() * 8);
+      LRC_HIP(hipMemcpyAsync(x.f.p, r.fmed.data(), r.fmed.size() * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(x.coef.p, r.coefmed.data(), r.coefmed.size() * 8,
+                             hipMemcpyHostToDevice, s));
       for (DevBuf* d : {&x.x, &x.dl, &x.r, &x.z, &x.py, &x.px}) {
-        d->alloc(col);
+        ensure(*d, col);
         LRC_HIP(hipMemsetAsync(d->p, 0, col, s));
       }
-      x.W.alloc(col * op.q);
-      x.pcb.alloc(size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * 8 * 8);
-      x.pst.alloc(size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * 8 * 8);
-      x.part.alloc(size_t(med_partials()) * 8);
+      ensure(x.W, col * op.q);
+      ensure(x.pcb, size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * 8 * 8);
+      ensure(x.pst, size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * 8 * 8);
+      ensure(x.part, size_t(med_partials()) * 8);
       hi[j] = MedItem{x.f.as<double>(), x.W.as<double>(), x.coef.as<double>(), x.x.as<double>(),
                       x.dl.as<double>(), x.r.as<double>(), x.z.as<double>(),
                       x.part.as<double>(), n, op.q};
@@ -657,7 +664,6 @@ void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
   }
   if (!any) return;
   DevBuf done = upload(hd, s);
-  std::vector<DevBuf> W0(nb);
   std::vector<SpmmLaunch<double>> sl;
   std::vector<SpmmArgs<double>> sa;
   std::vector<TruncPlan<double>> tp;
@@ -666,9 +672,9 @@ void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
     const Prob& P = *r.P;
     const Ops& op = *P.ops;
     const LR<double>& X0 = P.X0;
-    W0[j].alloc(size_t(op.q) * op.n * X0.ld * 8);
+    ensure(r.rhs_w0, size_t(op.q) * op.n * X0.ld * 8);
     double* Wp[kMaxOps];
-    for (int i = 0; i < op.q; ++i) Wp[i] = W0[j].as<double>() + size_t(i) * op.n * X0.ld;
+    for (int i = 0; i < op.q; ++i) Wp[i] = r.rhs_w0.as<double>() + size_t(i) * op.n * X0.ld;
     sl.push_back(make_spmm<double>(op.d64.data(), op.q, X0.u(), X0.ld, X0.r(), 0, X0.cap, Wp,
                                    X0.ld, spmm_config<double>(op, X0.cap)));
     sa.push_back(sl.back().a);
@@ -735,7 +741,11 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   LRC_HIP(hipStreamSynchronize(s));
   if (o.precision == LRC_MIXED_FP32_DIR) {
     BatchDir bd;
+    const auto t0 = std::chrono::steady_clock::now();
     bd.setup(run, o, eager, s);
+    if (log_on())
+      std::fprintf(stderr, "{\"dir_setup_s\": %.5f}\n",
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     bd.solve(bn);
     for (int j = 0; j < nb; ++j) {
       run[j]->iters = bd.hctl[j].iters;
@@ -879,15 +889,16 @@ std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc
                                       lrc_info* infos) {
   const int nb = int(probs.size());
   LRC_CHECK(nb >= 1, ST_EINVAL, "lrc_solve_batched: no problems");
-  std::vector<SolveRun> run(nb);
   std::vector<SolveRun*> ptr(nb);
   for (int j = 0; j < nb; ++j) {
-    run[j].prepare(*probs[j], o, 0, nullptr, nullptr, nullptr);
-    ptr[j] = &run[j];
+    Prob& P = *probs[j];
+    if (!P.run) P.run = std::make_unique<SolveRun>();
+    P.run->prepare(P, o, 0, nullptr, nullptr, nullptr);
+    ptr[j] = P.run.get();
   }
   lockstep(ptr, o);
   std::vector<lrc_status> st(nb);
-  for (int j = 0; j < nb; ++j) st[j] = run[j].finish(o, infos ? infos + j : nullptr);
+  for (int j = 0; j < nb; ++j) st[j] = ptr[j]->finish(o, infos ? infos + j : nullptr);
   return st;
 }
 

@@ -525,7 +525,10 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
   const Ops& o = *P.ops;
   const int64_t n = o.n, m = P.m;
   const int ld0 = X0.ld, lds = S.ld;
-  DevBuf W0(size_t(o.q) * n * ld0 * 8), WS(size_t(o.q) * n * lds * 8);
+  ensure(P.res_w0, size_t(o.q) * n * ld0 * 8);
+  ensure(P.res_ws, size_t(o.q) * n * lds * 8);
+  DevBuf& W0 = P.res_w0;
+  DevBuf& WS = P.res_ws;
   double* W0p[kMaxOps];
   double* WSp[kMaxOps];
   for (int i = 0; i < o.q; ++i) {
@@ -556,9 +559,11 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
   }
   LRC_CHECK(P.rF + o.q * (X0.cap + S.cap) <= 192, ST_EINVAL,
             "fp64 residual: more than 192 concatenated columns");
-  DevBuf colsq(size_t(m) * 8);
+  ensure(P.res_colsq, size_t(m) * 8);
   const size_t wsb = residual_workspace_bytes(n, m);
-  DevBuf ws(wsb);
+  ensure(P.res_tmp, wsb);
+  DevBuf& colsq = P.res_colsq;
+  DevBuf& ws = P.res_tmp;
   launch_residual_fp64(A, n, B, c, m, 192, colsq.as<double>(), ws.as<double>(), wsb, s);
   std::vector<double> h(m);
   LRC_HIP(hipMemcpyAsync(h.data(), colsq.p, size_t(m) * 8, hipMemcpyDeviceToHost, s));
@@ -572,10 +577,40 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
 }
 
 // ------------------------------------------------------------------ solve
+template <class T>
+static void reset_lr(LR<T>& X, int64_t n, int64_t m, int cap, hipStream_t s) {
+  if (X.U.p && X.n == n && X.m == m && X.cap == cap) {
+    LRC_HIP(hipMemsetAsync(X.rank.p, 0, 16, s));
+    LRC_HIP(hipMemsetAsync(X.s.p, 0, X.s.bytes, s));
+  } else {
+    X.alloc(n, m, cap, s);
+  }
+}
+
+template <class T>
+static void ensure_cheb(std::unique_ptr<Cheb<T>>& c, Prob* P, int cap) {
+  if (!c || c->P != P || c->cap != cap || c->S.n != P->ops->n || c->S.m != P->m) {
+    c = std::make_unique<Cheb<T>>();
+    c->alloc(P, cap);
+    return;
+  }
+  if (!c->S.U.p) c->S.alloc(P->ops->n, P->m, cap, P->ctx->stream);   // handed to the problem
+  // the preconditioner may have been refactorised since (other level sizes)
+  const size_t ld = size_t(ld_for(cap)) * sizeof(T);
+  ensure(c->pcb, size_t(std::max<int64_t>(P->prec->cb_rows, 1)) * ld);
+  ensure(c->pst, size_t(std::max<int64_t>(P->prec->stage_rows, 1)) * ld);
+}
+
+Prob::Prob() = default;
+Prob::~Prob() = default;
+
 void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
                        const double* V0, const X0Dev* xd) {
   t0 = clk::now();
   P = &P_;
+  flags = iters = papp = refinements = 0;
+  conv = false;
+  last = 0.0;
   Prob& Pr = *P;
   hipStream_t s = Pr.ctx->stream;
   const Ops& op = *Pr.ops;
@@ -602,7 +637,6 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   c = std::max(c, 1e-12 * dc);
   inf = lrc_info{};
   // fixed initial term X0
-  Pr.X0 = LR<double>();
   Pr.rank_x0 = 0;
   jmed = -1;
   if (o.init == LRC_INIT_MEDIAN) {
@@ -627,7 +661,7 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     median_tol = o.median_tol > 0 ? o.median_tol : 1e-10;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
-    Pr.X0.alloc(n, m, r0, s);
+    reset_lr(Pr.X0, n, m, r0, s);
     if (xd) {
       // device factors (row-major fp64): copied, the core from the host
       LRC_CHECK(xd->U && xd->V && xd->ldu >= r0 && xd->ldv >= r0, ST_EINVAL,
@@ -645,16 +679,15 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     }
     Pr.rank_x0 = r0;
   } else {
-    Pr.X0.alloc(n, m, 1, s);
+    reset_lr(Pr.X0, n, m, 1, s);
   }
   cap = o.rank_cap;
   // room left for the right-hand side in the residual concatenation
   // [B | K_0 S | ... | K_{q-1} S] of at most 128 columns
   const int room = std::max(8, kTruncCap - op.q * cap);
   const int bcap = std::min(std::min(64, room), std::max(Pr.rF + op.q, o.init == LRC_INIT_GIVEN ? 64 : 1));
-  c64 = std::make_unique<Cheb<double>>();
-  c64->alloc(P, cap);
-  B64.alloc(n, m, bcap, s);
+  ensure_cheb(c64, P, cap);
+  reset_lr(B64, n, m, bcap, s);
   max_iter = o.max_iter > 0 ? o.max_iter : 200;
   // mixed precision: the inner correction's own cap keeps [rhs | K_i E] within 128 columns
   inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
@@ -672,11 +705,7 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
                 o.precision == LRC_MIXED_FP32_DIR,
             ST_EINVAL, "lrc_solve: unknown precision");
   if (o.precision == LRC_MIXED_FP32) alloc_mixed();
-  if (o.precision == LRC_MIXED_FP32_DIR) {
-    // fp32 direction, preconditioned residual and their workspace
-    c32 = std::make_unique<Cheb<float>>();
-    c32->alloc(P, cap);
-  }
+  if (o.precision == LRC_MIXED_FP32_DIR) ensure_cheb(c32, P, cap);   // fp32 direction and Z
 }
 
 // X0 = x 1^T from the median column's solution x (column 0 of an n x 8 block)
@@ -684,7 +713,7 @@ void SolveRun::set_median_x0(const double* x, int iters) {
   Prob& Pr = *P;
   hipStream_t s = Pr.ctx->stream;
   const int64_t n = Pr.ops->n, m = Pr.m;
-  Pr.X0.alloc(n, m, 1, s);
+  reset_lr(Pr.X0, n, m, 1, s);
   launch_copy_cols(x, 8, Pr.X0.u(), Pr.X0.ld, n, 1, s);
   std::vector<double> ones(size_t(m) * Pr.X0.ld, 0.0);
   for (int64_t j = 0; j < m; ++j) ones[size_t(j) * Pr.X0.ld] = 1.0;
@@ -726,10 +755,9 @@ TruncPlan<double> SolveRun::rhs_plan(const lrc_opts& o, double* const* W0) const
 void SolveRun::alloc_mixed() {
   hipStream_t s = P->ctx->stream;
   const int64_t n = P->ops->n, m = P->m;
-  c32 = std::make_unique<Cheb<float>>();
-  c32->alloc(P, inner_cap);
-  Bin.alloc(n, m, inner_cap, s);   // the outer residual is truncated to inner_cap
-  E64.alloc(n, m, inner_cap, s);
+  ensure_cheb(c32, P, inner_cap);
+  reset_lr(Bin, n, m, inner_cap, s);   // the outer residual is truncated to inner_cap
+  reset_lr(E64, n, m, inner_cap, s);
   LRC_HIP(hipMemsetAsync(c64->S.rank.p, 0, 16, s));
 }
 
@@ -755,7 +783,10 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
   Prob& Pr = *P;
   Ctx& ctx = *Pr.ctx;
   const int64_t n = Pr.ops->n, m = Pr.m;
-  Pr.S = std::move(c64->S);
+  // the solution takes the iterate's buffers; the iterate gets the previous
+  // solution's (reused next time when the shapes agree)
+  std::swap(Pr.S, c64->S);
+  if (c64->S.U.p && (c64->S.cap != c64->cap || c64->S.n != n || c64->S.m != m)) c64->S = LR<double>();
   Pr.rank_s = read_rank(ctx, Pr.S.r());
   inf.rank = Pr.rank_s;
   inf.rank_x0 = Pr.rank_x0;
@@ -801,11 +832,19 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
 
 lrc_status solve_problem(Prob& P, const lrc_opts& o, int r0, const double* U0, const double* s0,
                          const double* V0, lrc_info* info, const X0Dev* xd) {
-  SolveRun run;
+  const auto t0 = clk::now();
+  if (!P.run) P.run = std::make_unique<SolveRun>();
+  SolveRun& run = *P.run;
   run.prepare(P, o, r0, U0, s0, V0, xd);
+  const double tp = secs_since(t0);
   std::vector<SolveRun*> one{&run};
   lockstep(one, o);
-  return run.finish(o, info);
+  const double tl = secs_since(t0);
+  const lrc_status st = run.finish(o, info);
+  if (log_enabled())
+    std::fprintf(stderr, "{\"solve_s\": {\"prepare\": %.5f, \"lockstep\": %.5f, \"finish\": %.5f}}\n",
+                 tp, tl - tp, secs_since(t0) - tl);
+  return st;
 }
 
 }  // namespace lrc

@@ -155,7 +155,13 @@ struct Cheb {
   PrecItem<T> prec_item() const;
 };
 
+struct SolveRun;
+
 struct Prob {
+  Prob();
+  ~Prob();
+  Prob(const Prob&) = delete;
+  Prob& operator=(const Prob&) = delete;
   Ops* ops = nullptr;
   Ctx* ctx = nullptr;
   int64_t m = 0;
@@ -171,7 +177,19 @@ struct Prob {
   LR<double> X0, S;
   int rank_x0 = 0, rank_s = 0;
   LR<double> F64;                  // F as a device LR (fp64)
+  // workspaces kept between solves (reallocated only when a shape changes)
+  std::unique_ptr<SolveRun> run;
+  DevBuf res_w0, res_ws, res_colsq, res_tmp;   // fp64 residual scratch
   const double* drow(int i) const { return d_rows.as<double>() + size_t(i) * m; }
+};
+
+// Grow-only device buffer.
+inline void ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes < bytes) b.alloc(bytes);
+}
+// Median-column solve workspace (column 0 of n x 8 blocks).
+struct MedWork {
+  DevBuf f, coef, x, dl, r, z, W, py, px, pcb, pst, part;
 };
 
 // SpMM autotuning (tune.cpp): time every candidate launch shape of the fused
@@ -225,6 +243,8 @@ struct SolveRun {
   LR<float> Bin;
   int flags = 0, iters = 0, papp = 0, refinements = 0;
   bool conv = false;
+  MedWork med;          // median-column workspace
+  DevBuf rhs_w0;        // K_i X0 for the right-hand side
   double last = 0.0;
   // median column (init LRC_INIT_MEDIAN): index, interval, right-hand side, coefficients
   int jmed = -1;
