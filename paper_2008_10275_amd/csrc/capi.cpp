@@ -100,6 +100,7 @@ void build_levels(Prec& pr, hipStream_t s) {
   std::vector<double> blk_f(F.nlev_fwd, 0.0), blk_b(F.nlev_bwd, 0.0);
   std::vector<int64_t> ns_f(F.nlev_fwd, 0), ns_b(F.nlev_bwd, 0);
   std::vector<int> nin_f(F.nlev_fwd, 0), nin_b(F.nlev_bwd, 0);
+  std::vector<int> contrib_f(F.nlev_fwd, 0);
   std::vector<std::vector<GatherRow>> gf(F.nlev_fwd), gb(F.nlev_bwd);
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
@@ -122,6 +123,7 @@ void build_levels(Prec& pr, hipStream_t s) {
                 "preconditioner: too many contributions to one front row");
       gf[hf].push_back(GatherRow{p < F.ns[sn] ? F.perm[F.j0[sn] + p] : -1,
                                  int(F.asm_ptr[q + 1] - F.asm_ptr[q]), F.asm_ptr[q]});
+      if (F.asm_ptr[q + 1] > F.asm_ptr[q]) contrib_f[hf] = 1;
       gb[db].push_back(GatherRow{p < F.ns[sn] ? F.j0[sn] + p : -F.bnd[F.bnd_off[sn] + p - F.ns[sn]] - 1,
                                  0, 0});
     }
@@ -152,10 +154,10 @@ void build_levels(Prec& pr, hipStream_t s) {
   // backward products read all f rows and write the ns own rows twice (x, Z)
   for (size_t l = 0; l < ft.size(); ++l)
     pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size()),
-                      gbase + gfo[l], nin_f[l], blk_f[l], ns_f[l], lf[l]});
+                      gbase + gfo[l], nin_f[l], contrib_f[l] ? 0 : 1, blk_f[l], ns_f[l], lf[l]});
   for (size_t l = 0; l < bt.size(); ++l)
     pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size()),
-                      gbase + gbo[l], nin_b[l], blk_b[l], lb[l], 2 * ns_b[l]});
+                      gbase + gbo[l], nin_b[l], 1, blk_b[l], lb[l], 2 * ns_b[l]});
   LRC_HIP(hipStreamSynchronize(s));
 }
 

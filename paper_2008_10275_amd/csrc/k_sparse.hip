@@ -223,7 +223,10 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __res
   }
 }
 
-template <class T, bool FWD, int NW, int KTM>
+// DIRECT: the inputs are read where they live instead of from the staged
+// front (backward: y rows and x boundary rows; forward levels without
+// contributions: R rows by the permutation), so the level needs no gather.
+template <class T, bool FWD, int NW, int KTM, bool DIRECT>
 __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     PrecDev<T> P, const int2* __restrict__ tasks, int ntasks, const int64_t* __restrict__ soff,
     PrecItem<T> a0, const PrecItem<T>* ab, const int* done, int ldw) {
@@ -246,7 +249,14 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   const int nout = FWD ? f : ns;
   const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
   const int ldM = FWD ? f : ns;                  // column-major: element (row, i) at i * ldM + row
-  const T* __restrict__ In = it.stage + soff[sn] * ldw;
+  const T* __restrict__ In = DIRECT ? nullptr : it.stage + soff[sn] * ldw;
+  // input row i of the product (i < nin)
+  auto in_row = [&](int i) -> const T* {
+    if (!DIRECT) return In + int64_t(i) * ldw;
+    if (FWD) return it.R + int64_t(P.perm[j0 + i]) * it.ldr;
+    return i < ns ? it.y + int64_t(j0 + i) * ldw
+                  : it.x + int64_t(P.bnd[P.bnd_off[sn] + i - ns]) * ldw;
+  };
   const int chunk = NW == 1 ? nin : (nin + 4 * NW - 1) / (4 * NW) * 4;
   const int i0 = wv * chunk, i1 = min(nin, i0 + chunk);
   const int orow = row0 + (lane & 15);
@@ -256,6 +266,12 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   for (int t = 0; t < KTM; ++t) acc[t] = acc_t{};
   for (int kk = i0; kk < i1; kk += 4 * U) {
     T a[U], b[U][KTM];
+    const T* rp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = kk + 4 * u + (lane >> 4);
+      rp[u] = i < i1 ? in_row(i) : nullptr;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = kk + 4 * u + (lane >> 4);
@@ -264,7 +280,7 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
 #pragma unroll
       for (int t = 0; t < KTM; ++t) {
         const int c = t * 16 + (lane & 15);
-        b[u][t] = (iok && c < k) ? In[int64_t(i) * ldw + c] : T(0);
+        b[u][t] = (iok && c < k) ? rp[u][c] : T(0);
       }
     }
 #pragma unroll
@@ -277,7 +293,7 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     if (c >= k || row >= nout) return;
     if (FWD) {
       if (row < ns) it.y[int64_t(j0 + row) * ldw + c] = v;
-      else it.cb[(P.cb_off[sn] + row - ns) * ldw + c] = v + In[int64_t(row) * ldw + c];
+      else it.cb[(P.cb_off[sn] + row - ns) * ldw + c] = DIRECT ? v : v + In[int64_t(row) * ldw + c];
     } else {
       it.x[int64_t(j0 + row) * ldw + c] = v;
       it.Z[int64_t(P.perm[j0 + row]) * it.ldz + c] = v;
@@ -345,9 +361,15 @@ template <class T, bool FWD, int NW>
 static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const PrecDev<T>& P,
                               const LevelTasks& L, const int64_t* soff, const PrecItem<T>& it,
                               const Batched<PrecItem<T>>& b, int ldw) {
-#define LRC_PP(KT)                                                                             \
-  hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT>), grid, blk, 0, s, P, L.tasks, L.count, \
-                     soff, it, b.dev, b.done, ldw)
+#define LRC_PP(KT)                                                                                \
+  do {                                                                                            \
+    if (L.direct)                                                                                 \
+      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, true>), grid, blk, 0, s, P, L.tasks, \
+                         L.count, soff, it, b.dev, b.done, ldw);                                  \
+    else                                                                                          \
+      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, false>), grid, blk, 0, s, P,         \
+                         L.tasks, L.count, soff, it, b.dev, b.done, ldw);                         \
+  } while (0)
   switch (KTM) {
     case 1: LRC_PP(1); break;
     case 2: LRC_PP(2); break;
@@ -374,7 +396,7 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
     const bool fw = pass == 0;
     for (const auto& L : fw ? fwd : bwd) {
       if (L.count == 0) continue;
-      {
+      if (!L.direct) {
         ProfScope ps(kcls(K_PREC_GATHER, is_f32<T>()), s, gather_work<T>(L, kt));
         const dim3 grid(gblocks(L.nrows), 1, b.n);
         if (fw)
