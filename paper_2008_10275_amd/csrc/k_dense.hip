@@ -600,90 +600,137 @@ template void launch_tsmm<double>(const TsmmJob<double>*, int, int, int, hipStre
 // ============================================================== fp64 residual
 // R = A * (core-scaled B)^T entry by entry on fp64 MFMA; only the per-column
 // sums of squares leave the kernel (R itself is never stored).
-constexpr int kResCols = 64;
-constexpr int kResRows = 64;
-constexpr int kResK = 32;
-constexpr int kResRowGroups = 64;
+//
+// A workgroup owns NC = 16 NT columns of R and a contiguous range of 16-row
+// tiles.  The scaled B block (K x NC) sits in LDS for the whole launch; each
+// wave streams its row tiles straight from HBM into the MFMA A-operand layout
+// (lane l: row l % 16, column 4 q + l / 16 at step q), loading the next tile
+// while the current one multiplies, so the row loop has no barrier.  Workgroups
+// of one row range but different column blocks are placed on the same XCD so
+// that they share its L2 copy of those rows.
+constexpr int kResThreads = 256;
+constexpr int kResRowGroups = 128;   // most partial rows per column
+constexpr int kResBPad = 16;          // LDS row padding of B (doubles)
 
-__global__ __launch_bounds__(256) void residual_kernel(BlockView<double> A, int64_t n,
-                                                       BlockView<double> B, CoreView core,
-                                                       int64_t m, double* __restrict__ part) {
-  __shared__ double Bs[kResCols][kKCAP + 1];
-  __shared__ double As[kResRows][kResK + 1];
+struct ResCol {
+  const double* p;   // first element of the column
+  int64_t ld;        // row stride
+};
+
+template <int KQ>
+__device__ __forceinline__ void res_load(double (&a)[KQ], const ResCol* acol, int kq, int g,
+                                         int64_t row, bool ok) {
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+    if (q < kq) {
+      const ResCol e = acol[4 * q + g];
+      a[q] = (ok && e.p) ? e.p[row * e.ld] : 0.0;
+    }
+}
+
+template <int NT, int KQ>
+__device__ __forceinline__ void res_tile(const double (&a)[KQ], const double* Bs, int kq, int g,
+                                         int rl, double (&csum)[NT]) {
+  constexpr int S = 16 * NT + kResBPad;
+  doublex4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = doublex4{};
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+    if (q < kq) {
+      const double* br = Bs + (4 * q + g) * S + rl;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], br[16 * t], acc[t], 0, 0, 0);
+    }
+  // every lane holds four rows of column 16 t + (lane % 16)
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) csum[t] += acc[t][i] * acc[t][i];
+}
+
+template <int NT, int KQ>
+__global__ __launch_bounds__(kResThreads) void residual_kernel(BlockView<double> A, int64_t n,
+                                                               BlockView<double> B, CoreView core,
+                                                               int64_t m, int gx, int gy,
+                                                               double* __restrict__ part) {
+  constexpr int NC = 16 * NT, KP = 4 * KQ, S = NC + kResBPad;
+  static_assert(KP <= kKCAP, "residual: width beyond the column tables");
+  __shared__ double Bs[KP * S];
+  __shared__ ResCol acol[KP];
+  __shared__ double coef[KP];
   __shared__ unsigned char blk[kKCAP];
   __shared__ short loc[kKCAP];
-  __shared__ double coef[kKCAP];
-  __shared__ double colacc[4][kResCols];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // core coefficients per concatenated column
+  const int g = lane >> 4, rl = lane & 15;
+  // XCD-aware placement: consecutive workgroups of one XCD take the column
+  // blocks of one row range (gx * gy is a multiple of 8)
+  const int tot = gx * gy, L = blockIdx.x;
+  const int id = (L & 7) * (tot >> 3) + (L >> 3);
+  const int cb = id % gx, rg = id / gx;
+  const int64_t j0 = int64_t(cb) * NC;
   {
     int k = 0;
     for (int b = 0; b < core.nb; ++b) {
       const int w = core_width(core, b);
-      for (int c = threadIdx.x; c < w && k + c < kKCAP; c += blockDim.x)
+      for (int c = threadIdx.x; c < w && k + c < KP; c += blockDim.x)
         coef[k + c] = core.coef[b] * (core.s[b] ? core.s[b][c] : 1.0);
       k += w;
     }
   }
-  const int kB = build_coltab(B, blk, loc);
-  const int64_t j0 = int64_t(blockIdx.x) * kResCols;
-  const int kp = (kB + 3) / 4 * 4;
+  const int kb = min(build_coltab(B, blk, loc), KP);
+  const int kp = (kb + 3) & ~3, kq = kp >> 2;
   __syncthreads();
-  for (int e = threadIdx.x; e < kResCols * kp; e += blockDim.x) {
+  for (int e = threadIdx.x; e < NC * kp; e += blockDim.x) {
     const int jj = e / kp, c = e - jj * kp;
     double v = 0.0;
-    if (j0 + jj < m && c < kB) v = view_at(B, blk[c], loc[c], j0 + jj) * coef[c];
-    Bs[jj][c] = v;
+    if (j0 + jj < m && c < kb) v = view_at(B, blk[c], loc[c], j0 + jj) * coef[c];
+    Bs[c * S + jj] = v;
   }
   __syncthreads();
-  const int kA = build_coltab(A, blk, loc);   // same total width as B
-  (void)kA;
+  build_coltab(A, blk, loc);   // same total width as B; A carries no row scaling
   __syncthreads();
-  double csum[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t per = ceil_div(ceil_div(n, kResRows), gridDim.y) * kResRows;
-  const int64_t r0 = int64_t(blockIdx.y) * per, r1 = std::min<int64_t>(n, r0 + per);
-  for (int64_t row0 = r0; row0 < r1; row0 += kResRows) {
-    const int nr = int(std::min<int64_t>(kResRows, r1 - row0));
-    doublex4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = doublex4{};
-    for (int k0 = 0; k0 < kp; k0 += kResK) {
-      const int kc = std::min(kResK, kp - k0);
-      for (int e = threadIdx.x; e < kResRows * kResK; e += blockDim.x) {
-        const int rr = e / kResK, c = e - rr * kResK;
-        double v = 0.0;
-        if (rr < nr && c < kc && k0 + c < kB) v = view_at(A, blk[k0 + c], loc[k0 + c], row0 + rr);
-        As[rr][c] = v;
-      }
-      __syncthreads();
-      for (int kk = 0; kk < kc; kk += 4) {
-        const double xa = As[wave * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              xa, Bs[t * 16 + (lane & 15)][k0 + kk + (lane >> 4)], acc[t], 0, 0, 0);
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) csum[t] += acc[t][i] * acc[t][i];
+  for (int c = threadIdx.x; c < KP; c += blockDim.x) {
+    ResCol e{nullptr, 0};
+    if (c < kb) e = ResCol{A.ptr[blk[c]] + loc[c], int64_t(A.ld[blk[c]])};
+    acol[c] = e;
   }
-  // reduce lanes with the same column (l, l+16, l+32, l+48), then waves
+  __syncthreads();
+
+  const int64_t nrt = (n + 15) / 16;
+  const int64_t per = (nrt + gy - 1) / gy;
+  const int64_t t0 = int64_t(rg) * per, t1 = min(nrt, t0 + per);
+  double csum[NT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < NT; ++t) csum[t] = 0.0;
+  double a0[KQ], a1[KQ];
+  const int nw = kResThreads / 64;
+  int64_t tile = t0 + wave;
+  res_load<KQ>(a0, acol, kq, g, tile * 16 + rl, tile < t1 && tile * 16 + rl < n);
+  for (; tile < t1; tile += 2 * nw) {
+    const int64_t tb = tile + nw, tc = tile + 2 * nw;
+    res_load<KQ>(a1, acol, kq, g, tb * 16 + rl, tb < t1 && tb * 16 + rl < n);
+    res_tile<NT, KQ>(a0, Bs, kq, g, rl, csum);
+    if (tb >= t1) break;
+    res_load<KQ>(a0, acol, kq, g, tc * 16 + rl, tc < t1 && tc * 16 + rl < n);
+    res_tile<NT, KQ>(a1, Bs, kq, g, rl, csum);
+  }
+  // lanes l, l+16, l+32, l+48 share a column; then the waves
+  __syncthreads();   // Bs is reused for the wave partials
+  double* colacc = Bs;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
     double v = csum[t];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
-    if (lane < 16) colacc[wave][t * 16 + lane] = v;
+    if (lane < 16) colacc[wave * NC + t * 16 + lane] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kResCols) {
-    const double v = colacc[0][threadIdx.x] + colacc[1][threadIdx.x] + colacc[2][threadIdx.x] +
-                     colacc[3][threadIdx.x];
-    const int64_t j = j0 + threadIdx.x;
-    if (j < m) part[size_t(blockIdx.y) * m + j] = v;
+  for (int jj = threadIdx.x; jj < NC; jj += blockDim.x) {
+    double v = 0.0;
+    for (int w = 0; w < nw; ++w) v += colacc[w * NC + jj];
+    if (j0 + jj < m) part[size_t(rg) * m + j0 + jj] = v;
   }
 }
 
@@ -701,13 +748,29 @@ size_t residual_workspace_bytes(int64_t n, int64_t m) {
   return size_t(kResRowGroups) * size_t(m) * sizeof(double);
 }
 
+template <int NT, int KQ>
+static void launch_res(const BlockView<double>& A, int64_t n, const BlockView<double>& B,
+                       const CoreView& core, int64_t m, double* ws, hipStream_t s, int* gy_out) {
+  constexpr int NC = 16 * NT;
+  const int gx = int(ceil_div(m, NC));
+  // about 1024 workgroups, a multiple of 8 row groups
+  int gy = int(ceil_div(int64_t(1024), int64_t(gx)));
+  gy = std::min(kResRowGroups, std::max(8, (gy + 7) / 8 * 8));
+  *gy_out = gy;
+  hipLaunchKernelGGL((residual_kernel<NT, KQ>), dim3(unsigned(gx * gy)), dim3(kResThreads), 0, s,
+                     A, n, B, core, m, gx, gy, ws);
+}
+
 void launch_residual_fp64(const BlockView<double>& A, int64_t n, const BlockView<double>& B,
                           CoreView core, int64_t m, int kcap, double* colsq, double* ws,
                           size_t ws_bytes, hipStream_t s) {
-  LRC_CHECK(kcap <= kKCAP, ST_EINVAL, "residual: at most 192 columns");
+  LRC_CHECK(kcap >= 0 && kcap <= kKCAP, ST_EINVAL, "residual: at most 192 columns");
+  LRC_CHECK(view_cap(A) <= kKCAP && A.nb == B.nb && B.nb == core.nb, ST_EINVAL,
+            "residual: inconsistent views");
+  for (int b = 0; b < A.nb; ++b)
+    LRC_CHECK(!A.rowscale[b], ST_EINVAL, "residual: row scaling of the left factor");
   LRC_CHECK(ws_bytes >= residual_workspace_bytes(n, m), ST_EINVAL, "residual: workspace too small");
-  const int groups = int(std::min<int64_t>(kResRowGroups, std::max<int64_t>(1, ceil_div(n, kResRows))));
-  dim3 grid(unsigned(ceil_div(m, kResCols)), unsigned(groups));
+  if (m <= 0) return;
   // algorithmic flops: every entry of the n x m residual is a k-term dot product
   Work w;
   w.bytes = false;
@@ -715,9 +778,22 @@ void launch_residual_fp64(const BlockView<double>& A, int64_t n, const BlockView
   w.groups = {view_terms(A)};
   w.f = [=](const std::vector<double>& v) { return 2.0 * nm * v[0]; };
   ProfScope ps(kcls(K_RESIDUAL, false), s, w);
-  hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, A, n, B, core, m, ws);
+  // kcap bounds the device widths; the tile shape follows it and m
+  const int need = int(std::min<int64_t>(8, ceil_div(m, 16)));
+  int gy = 8;
+  if (kcap <= 64) {
+    if (need > 4) launch_res<8, 16>(A, n, B, core, m, ws, s, &gy);
+    else if (need > 2) launch_res<4, 16>(A, n, B, core, m, ws, s, &gy);
+    else launch_res<2, 16>(A, n, B, core, m, ws, s, &gy);
+  } else if (kcap <= 128) {
+    if (need > 2) launch_res<4, 32>(A, n, B, core, m, ws, s, &gy);
+    else launch_res<2, 32>(A, n, B, core, m, ws, s, &gy);
+  } else {
+    if (need > 2) launch_res<4, 48>(A, n, B, core, m, ws, s, &gy);
+    else launch_res<2, 48>(A, n, B, core, m, ws, s, &gy);
+  }
   hipLaunchKernelGGL(residual_reduce_kernel, dim3(unsigned(ceil_div(m, 256))), dim3(256), 0, s, ws,
-                     groups, m, colsq);
+                     gy, m, colsq);
   LRC_HIP(hipGetLastError());
 }
 

@@ -564,7 +564,9 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
   ensure(P.res_tmp, wsb);
   DevBuf& colsq = P.res_colsq;
   DevBuf& ws = P.res_tmp;
-  launch_residual_fp64(A, n, B, c, m, 192, colsq.as<double>(), ws.as<double>(), wsb, s);
+  // the exact concatenated width picks the residual's tile shape
+  const int width = P.rF + o.q * ((r0 > 0 ? read_rank(ctx, X0.r()) : 0) + read_rank(ctx, S.r()));
+  launch_residual_fp64(A, n, B, c, m, width, colsq.as<double>(), ws.as<double>(), wsb, s);
   std::vector<double> h(m);
   LRC_HIP(hipMemcpyAsync(h.data(), colsq.p, size_t(m) * 8, hipMemcpyDeviceToHost, s));
   ctx.sync();
