@@ -7,6 +7,9 @@
 //   D, f64     lane l, value i -> D[(l / 16) + 4 i][l % 16]   (rows interleaved)
 // (both result layouts were checked on gfx950 with a one-wave probe).
 #include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -20,6 +23,26 @@ static std::vector<WTerm> view_terms(const BlockView<T>& v) {
   return t;
 }
 
+
+// Workgroups of kernel `fn` (block of `threads`) resident on the whole current
+// device at once, cached per kernel and device: grids sized to this run in a
+// single round.
+static int resident_wgs(const void* fn, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  LRC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(fn, dev);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  LRC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0));
+  LRC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int v = std::max(1, per_cu) * std::max(1, cus);
+  cache[key] = v;
+  return v;
+}
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -234,26 +257,32 @@ __device__ inline void gram_rows_g(int g, const ColRef<T>* cr, int KT, int64_t r
   }
 }
 
-template <class T, int KTM, int NG, int PD, bool SCALED1>
-__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a0, const GramArgs<T>* ab,
-                                                   const int* done) {
-  if (done && done[blockIdx.z]) return;
-  const GramArgs<T>& a = ab ? ab[blockIdx.z] : a0;
-  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
-  T* __restrict__ partial = a.partial;
+// (wave groups sharing the tiles, prefetch depth) of a tile grid, chosen so
+// that accumulators + operand ring fit the registers
+// (KTK: the kernel's own grid bound; a narrow grid inside a wide kernel keeps
+// the wide kernel's register budget, so only narrow kernels go deeper)
+template <class T, int KTM, int KTK>
+struct GramCfg {
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr int NG = KTM <= 4 ? 1 : KTM <= 6 ? 2 : (F64 ? 4 : 2);
+  static constexpr int PD = KTM <= 2 ? (KTK <= 4 ? 8 : 4)
+                          : KTM <= 4 ? (KTK <= 4 || !F64 ? 4 : 2)
+                          : KTM <= 6 ? (F64 ? 2 : 4) : 2;
+};
+
+// One workgroup's share of one operand for a KTM x KTM tile grid: stream
+// the rows, sum the waves' tiles in LDS (fixed order), write the partial.
+template <class T, int KTM, int KTK, bool SCALED1>
+__device__ __forceinline__ void gram_body(const GramArgs<T>& a, int job, int wg, int nwg, int KT,
+                                          T* red) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int NG = GramCfg<T, KTM, KTK>::NG, PD = GramCfg<T, KTM, KTK>::PD;
   constexpr TileTab<KTM> tt{};
   constexpr int NTM = TileTab<KTM>::N;
   constexpr int MAXT = (NTM + NG - 1) / NG;
   constexpr int NS = 4 / NG;                 // row streams per workgroup
-  __shared__ T red[NTM * 256];
-  const int job = blockIdx.x < a.nwg0 ? 0 : 1;
-  const int wg = job == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
-  const int nwg = job == 0 ? a.nwg0 : a.nwg1;
   const BlockView<T>& X = a.X[job];
   const int64_t rows = a.rows[job];
-  const int k = min(view_width(X), 16 * KTM);
-  const int KT = (k + 15) / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = wave % NG, stream = wave / NG;
   ColRef<T> cr[KTM];
@@ -289,11 +318,35 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a0, const GramArg
     __syncthreads();
   }
   // partial layout: tiles of the full 8 x 8 grid (ids of gtile_id)
-  T* out = partial + size_t(blockIdx.x) * kGN * 256;
+  T* out = a.partial + size_t(blockIdx.x) * kGN * 256;
   for (int e = threadIdx.x; e < NTM * 256; e += blockDim.x) {
     const int u = e >> 8;
     if (tt.bj[u] < KT) out[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
   }
+}
+
+// The host bound KTM of the width sizes LDS; the tile grid actually used
+// follows the device width (a wave-uniform branch), so that a wide capacity
+// with a narrow operand runs the narrow grid's schedule.
+template <class T, int KTM, bool SCALED1>
+__global__ __launch_bounds__(256, 2) void gram_kernel(GramArgs<T> a0, const GramArgs<T>* ab,
+                                                   const int* done) {
+  if (done && done[blockIdx.z]) return;
+  const GramArgs<T>& a = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
+  __shared__ T red[TileTab<KTM>::N * 256];
+  const int job = int(blockIdx.x) < a.nwg0 ? 0 : 1;
+  const int wg = job == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
+  const int nwg = job == 0 ? a.nwg0 : a.nwg1;
+  const int k = min(view_width(a.X[job]), 16 * KTM);
+  const int KT = __builtin_amdgcn_readfirstlane((k + 15) / 16);
+  if constexpr (KTM >= 8)
+    if (KT > 6) return gram_body<T, 8, KTM, SCALED1>(a, job, wg, nwg, KT, red);
+  if constexpr (KTM >= 6)
+    if (KT > 4) return gram_body<T, 6, KTM, SCALED1>(a, job, wg, nwg, KT, red);
+  if constexpr (KTM >= 4)
+    if (KT > 2) return gram_body<T, 4, KTM, SCALED1>(a, job, wg, nwg, KT, red);
+  gram_body<T, 2, KTM, SCALED1>(a, job, wg, nwg, KT, red);
 }
 
 // G[r][c] = sum over the job's workgroup partials (fixed order), both triangles
@@ -347,9 +400,23 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(GramRedArgs<T> r0, co
   G[size_t(c) * kcap + r] = t;
 }
 
+template <class T>
+using GramFn = void (*)(GramArgs<T>, const GramArgs<T>*, const int*);
+
+// the width bound picks the LDS class; the kernel follows the device width
+template <class T>
+static GramFn<T> gram_fn(int kb, bool sc1) {
+  if (kb <= 32) return sc1 ? gram_kernel<T, 2, true> : gram_kernel<T, 2, false>;
+  if (kb <= 64) return sc1 ? gram_kernel<T, 4, true> : gram_kernel<T, 4, false>;
+  if (kb <= 96) return sc1 ? gram_kernel<T, 6, true> : gram_kernel<T, 6, false>;
+  return sc1 ? gram_kernel<T, 8, true> : gram_kernel<T, 8, false>;
+}
+
 static int gram_wgs(int64_t rows) {
+  // about 128 rows per workgroup for short operands (so that their serial
+  // load chains stay short), at most kGramWgMax workgroups for long ones
   if (rows <= 0) return 1;
-  return int(std::min<int64_t>(kGramWgMax, std::max<int64_t>(1, ceil_div(rows, int64_t(512)))));
+  return int(std::min<int64_t>(kGramWgMax, std::max<int64_t>(1, ceil_div(rows, int64_t(128)))));
 }
 
 size_t gram_workspace_bytes(int64_t rows_a, int64_t rows_b, int kcap, bool fp64) {
@@ -364,9 +431,10 @@ GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_
   LRC_CHECK(kcap <= kGK, ST_EINVAL, "gram: at most 128 columns");
   GramLaunch<T> l;
   GramArgs<T>& a = l.g;
+  l.kb = std::min(kGK, std::max(view_cap(jobs[0].X), njobs > 1 ? view_cap(jobs[1].X) : 0));
+  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
   a.X[0] = jobs[0].X;
   a.rows[0] = jobs[0].rows;
-  a.nwg0 = gram_wgs(jobs[0].rows);
   if (njobs == 2) {
     a.X[1] = jobs[1].X;
     a.rows[1] = jobs[1].rows;
@@ -376,6 +444,9 @@ GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_
     a.rows[1] = 0;
     a.nwg1 = 0;
   }
+  // the long operand takes the resident slots the short one leaves
+  const int slots = resident_wgs(reinterpret_cast<const void*>(gram_fn<T>(l.kb, l.sc1)), 256);
+  a.nwg0 = std::min(gram_wgs(jobs[0].rows), std::max(1, slots - a.nwg1));
   a.partial = reinterpret_cast<T*>(ws_partial);
   const size_t need = size_t(a.nwg0 + a.nwg1) * kGN * 256 * sizeof(T);
   LRC_CHECK(need <= ws_bytes, ST_EINVAL, "gram: workspace too small");
@@ -384,8 +455,6 @@ GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_
                        njobs == 2 ? jobs[1].kout : nullptr, info};
   l.njobs = njobs;
   l.grid = a.nwg0 + a.nwg1;
-  l.kb = std::min(kGK, std::max(view_cap(jobs[0].X), njobs > 1 ? view_cap(jobs[1].X) : 0));
-  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
   // algorithmic flops: the k(k+1)/2 distinct entries of each Gram matrix, 2 flops per row each
   l.work.bytes = false;
   const double r0 = double(a.rows[0]), r1 = double(a.rows[1]);
@@ -403,21 +472,7 @@ void enqueue_gram(const GramLaunch<T>& l, Batched<GramArgs<T>> bg, Batched<GramR
     ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, l.work);
     const GramArgs<T>& a = l.g;
     const dim3 grid(l.grid, 1, bg.n), blk(256);
-    // (tile grid, wave groups sharing the tiles, prefetch depth) per width
-    // class, chosen so that accumulators + operand ring fit the registers
-    constexpr bool F64 = sizeof(T) == 8;
-#define LRC_GRAM(KTM, NG, PD)                                                                     \
-  do {                                                                                           \
-    if (l.sc1)                                                                                   \
-      hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, true>), grid, blk, 0, s, a, bg.dev, bg.done); \
-    else                                                                                         \
-      hipLaunchKernelGGL((gram_kernel<T, KTM, NG, PD, false>), grid, blk, 0, s, a, bg.dev, bg.done); \
-  } while (0)
-    if (l.kb <= 32) LRC_GRAM(2, 1, 4);
-    else if (l.kb <= 64) LRC_GRAM(4, 1, F64 ? 2 : 4);
-    else if (l.kb <= 96) LRC_GRAM(6, 2, F64 ? 2 : 4);
-    else LRC_GRAM(8, F64 ? 4 : 2, 2);
-#undef LRC_GRAM
+    gram_fn<T>(l.kb, l.sc1)<<<grid, blk, 0, s>>>(a, bg.dev, bg.done);
   }
   ProfScope ps(kcls(K_GRAM_REDUCE, is_f32<T>()), s);
   hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3(kGN * 256 / 64, l.njobs, br.n), dim3(1024), 0,
@@ -444,103 +499,177 @@ template void launch_gram<double>(const GramJob<double>*, int, int, double*, siz
                                   hipStream_t);
 
 // ============================================================== TSMM  Y = X * M
-// Output columns in slices of 64 (grid.y).  A workgroup keeps its k x 64 slice
-// of M in LDS and walks 64-row blocks of X: each block is loaded coalesced
-// (64 consecutive columns of one row per wave instruction, the next block
-// prefetched into registers while the current one is multiplied) and staged
-// in LDS, from where the waves read the MFMA operands (wave w: rows 16 w ..).
-constexpr int kTsRows = 64;
-constexpr int kTsSlice = 64;
+// Each wave streams 16-row tiles of X straight from HBM into the MFMA
+// A-operand layout (lane l: row l % 16, column 4 q + l / 16 at step q),
+// loading the next tile while the current one multiplies; M (k x r, at most
+// 16 NT columns) sits in LDS for the whole launch, and the accumulators are
+// stored to Y directly, so the row loop has no barrier.  The device widths
+// (k of the view, r of *r_dev) bound the steps and tiles at run time; the
+// template bounds (KQ, NT) only size registers and LDS.
+constexpr int kTsThreads = 512;
+constexpr int kTsPad = 16;
 constexpr int kTsKCAP = kGK;
 
-
-// Rows past the end are clamped (their products are never stored); columns
-// past the width meet zero rows of M.
-template <class T, bool SCALED>
-__device__ inline void tsmm_load(T (&v0)[kTsRows / 4], T (&v1)[kTsRows / 4], const ColRef<T>& c0,
-                                 const ColRef<T>& c1, bool two, int64_t b0, int lr,
-                                 int64_t rows) {
+template <class T, int KQ, bool SCALED>
+__device__ __forceinline__ void ts_load(T (&a)[KQ], const ColRef<T>* cols, int kq, int k, int g,
+                                        int64_t row, int64_t rows) {
+  // addresses are always valid (rows clamped, absent columns alias a real
+  // one); entries outside the operand are zeroed at the select, so that all
+  // loads stay in flight together
 #pragma unroll
-  for (int j = 0; j < kTsRows / 4; ++j) {
-    const int64_t row = b0 + lr + 4 * j;
-    v0[j] = col_load<T, SCALED>(c0, row, rows - 1);
-    if (two) v1[j] = col_load<T, SCALED>(c1, row, rows - 1);
-  }
+  for (int q = 0; q < KQ; ++q)
+    if (q < kq) {
+      const int c = 4 * q + g;
+      const T x = col_load<T, SCALED>(cols[c], row, rows - 1);
+      a[q] = (c < k && row < rows) ? x : T(0);
+    }
 }
 
-template <class T, bool SCALED1>
-__global__ __launch_bounds__(256) void tsmm_kernel(TsmmArgs<T> a0, const TsmmArgs<T>* ab,
-                                                   const int* done) {
-  if (done && done[blockIdx.z]) return;
-  const TsmmArgs<T>& a = ab ? ab[blockIdx.z] : a0;
-  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
+// NTU (<= NT) output tiles are multiplied; the caller picks NTU from the
+// uniform tile count so that no accumulator update is guarded
+template <class T, int KQ, int NT, int NTU>
+__device__ __forceinline__ void ts_tile(const T (&a)[KQ], const T* Ms, int kq, int g, int rl,
+                                        int lane, int64_t row0, int64_t rows, int r,
+                                        T* __restrict__ Y, int64_t ldy) {
+  constexpr int S = 16 * NT + kTsPad;
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T Ms[kTsKCAP][kTsSlice + 4];
-  __shared__ T Xs[kTsRows][kTsKCAP + 1];
-  const int jb = blockIdx.x < a.nwg0 ? 0 : 1;
-  const int wg = jb == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
-  const int nwg = jb == 0 ? a.nwg0 : a.nwg1;
-  const TsmmJob<T>& J = a.job[jb];
-  const int k = min(view_width(J.X), kTsKCAP);
-  const int r = *J.r_dev;
-  const int cs0 = blockIdx.y * kTsSlice;
-  if (cs0 >= r) return;
-  const int rs = min(kTsSlice, r - cs0);
-  const int kp = (k + 3) / 4 * 4;
-  const int RT = (rs + 15) / 16;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kp * kTsSlice; e += blockDim.x) {
-    const int i = e / kTsSlice, c = e - i * kTsSlice;
-    Ms[i][c] = (i < k && c < rs) ? T(J.M[size_t(i) * J.ldm + cs0 + c]) : T(0);
-  }
-  // loader: thread -> columns lc, lc + 64 of rows (tid / 64) + 4 j
-  const int lc = tid & 63, lr = tid >> 6;
-  const ColRef<T> c0 = resolve_col(J.X, lc), c1 = resolve_col(J.X, lc + 64);
-  const bool two = kp > 64;
-  const bool scaled = SCALED1 && jb == 1;
-  const int lane = tid & 63, wave = tid >> 6;
-  constexpr int LJ = kTsRows / 4;
-  T v0[LJ], v1[LJ];
+  acc_t acc[NTU];
 #pragma unroll
-  for (int j = 0; j < LJ; ++j) v1[j] = T(0);
-  int64_t row0 = int64_t(wg) * kTsRows;
-  auto load_block = [&](int64_t b0) {
-    if (scaled) tsmm_load<T, true>(v0, v1, c0, c1, two, b0, lr, J.rows);
-    else tsmm_load<T, false>(v0, v1, c0, c1, two, b0, lr, J.rows);
-  };
-  if (row0 < J.rows) load_block(row0);
-  for (; row0 < J.rows; row0 += int64_t(nwg) * kTsRows) {
-    __syncthreads();
+  for (int t = 0; t < NTU; ++t) acc[t] = acc_t{};
 #pragma unroll
-    for (int j = 0; j < LJ; ++j) {
-      Xs[lr + 4 * j][lc] = v0[j];
-      if (two) Xs[lr + 4 * j][lc + 64] = v1[j];
+  for (int q = 0; q < KQ; ++q)
+    if (q < kq) {
+      const T* br = Ms + (4 * q + g) * S + rl;
+#pragma unroll
+      for (int t = 0; t < NTU; ++t) acc[t] = Mfma<T>::op(a[q], br[16 * t], acc[t]);
     }
-    __syncthreads();
-    const int64_t next = row0 + int64_t(nwg) * kTsRows;
-    if (next < J.rows) load_block(next);
-    acc_t acc[kTsSlice / 16];
 #pragma unroll
-    for (int t = 0; t < kTsSlice / 16; ++t) acc[t] = acc_t{};
-    for (int kk = 0; kk < kp; kk += 4) {
-      const T xa = Xs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int t = 0; t < kTsSlice / 16; ++t)
-        if (t < RT) acc[t] = Mfma<T>::op(xa, Ms[kk + (lane >> 4)][t * 16 + (lane & 15)], acc[t]);
-    }
-    const int nr = int(std::min<int64_t>(kTsRows, J.rows - row0));
-#pragma unroll
-    for (int t = 0; t < kTsSlice / 16; ++t) {
-      if (t >= RT) continue;
-      const int c = t * 16 + (lane & 15);
-      if (c >= rs) continue;
+  for (int t = 0; t < NTU; ++t) {
+    const int c = 16 * t + rl;
+    if (c < r) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int rr = wave * 16 + Mfma<T>::drow(lane, i);
-        if (rr < nr) J.Y[(row0 + rr) * J.ldy + cs0 + c] = acc[t][i];
+        const int64_t row = row0 + Mfma<T>::drow(lane, i);
+        if (row < rows) Y[row * ldy + c] = acc[t][i];
       }
     }
   }
+}
+
+// A wave keeps D row tiles in flight in a register ring of D x KQU operands.
+template <class T, int KQU, int NT, int NTU, int D, bool SCALED>
+__device__ __forceinline__ void ts_rows(const ColRef<T>* cols, const T* Ms, int k, int r,
+                                        int64_t t0, int64_t t1, int64_t rows, T* Y, int64_t ldy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int g = lane >> 4, rl = lane & 15;
+  const int kq = (k + 3) >> 2;
+  constexpr int nw = kTsThreads / 64;
+  T buf[D][KQU];
+  const int64_t q0 = t0 + wave;
+  if (q0 >= t1) return;   // also covers an empty operand (no row to clamp to)
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int64_t tt = q0 + int64_t(d) * nw;
+    if (tt < t1) ts_load<T, KQU, SCALED>(buf[d], cols, kq, k, g, tt * 16 + rl, rows);
+  }
+  for (int64_t q = q0; q < t1; q += int64_t(D) * nw) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t tt = q + int64_t(d) * nw;
+      if (tt < t1) {
+        ts_tile<T, KQU, NT, NTU>(buf[d], Ms, kq, g, rl, lane, tt * 16, rows, r, Y, ldy);
+        // re-read the column table from LDS rather than keeping it live
+        __asm__ volatile("" ::: "memory");
+        const int64_t tn = tt + int64_t(D) * nw;
+        if (tn < t1) ts_load<T, KQU, SCALED>(buf[d], cols, kq, k, g, tn * 16 + rl, rows);
+      }
+    }
+  }
+}
+
+template <class T, int KQU, int NT, int D, bool SCALED>
+__device__ __forceinline__ void ts_rows_nt(const ColRef<T>* cols, const T* Ms, int k, int r,
+                                           int64_t t0, int64_t t1, int64_t rows, T* Y,
+                                           int64_t ldy) {
+  const int rt = (r + 15) >> 4;
+  // eight output tiles hold 32 accumulators per lane: half the ring depth
+  constexpr int D8 = D >= 4 ? D / 2 : D;
+  if constexpr (NT >= 8)
+    if (rt > 4) return ts_rows<T, KQU, NT, 8, D8, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+  if constexpr (NT >= 4)
+    if (rt > 2) return ts_rows<T, KQU, NT, 4, D, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+  ts_rows<T, KQU, NT, 2, D, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+}
+
+// The ring holds 2 KQ operands whatever the width: narrow inputs keep more
+// tiles in flight.  (The row-scaled operand is the short V side: one class.)
+template <class T, int KQ, int NT, bool SCALED>
+__device__ __forceinline__ void ts_rows_by_width(const ColRef<T>* cols, const T* Ms, int k, int r,
+                                                 int64_t t0, int64_t t1, int64_t rows, T* Y,
+                                                 int64_t ldy) {
+  const int kq = (k + 3) >> 2;
+  if constexpr (!SCALED) {
+    if constexpr (KQ >= 32) {
+      if (kq <= 8) return ts_rows_nt<T, 8, NT, 8, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+      if (kq <= 16) return ts_rows_nt<T, 16, NT, 4, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+    } else {
+      if (kq <= 8) return ts_rows_nt<T, 8, NT, 4, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+    }
+  }
+  ts_rows_nt<T, KQ, NT, 2, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+}
+
+template <class T, int KQ, int NT, bool SCALED1>
+__global__ __launch_bounds__(kTsThreads) void tsmm_kernel(TsmmArgs<T> a0, const TsmmArgs<T>* ab,
+                                                          const int* done) {
+  if (done && done[blockIdx.z]) return;
+  const TsmmArgs<T>& a = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;   // batched grids take the largest item
+  constexpr int KP = 4 * KQ, NC = 16 * NT, S = NC + kTsPad;
+  __shared__ T Ms[KP * S];
+  __shared__ ColRef<T> cols[KP];
+  const int jb = int(blockIdx.x) < a.nwg0 ? 0 : 1;
+  const int wg = jb == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
+  const int nwg = jb == 0 ? a.nwg0 : a.nwg1;
+  const TsmmJob<T>& J = a.job[jb];
+  // wave-uniform widths (scalar branches on the steps and tile classes)
+  const int k = __builtin_amdgcn_readfirstlane(min(view_width(J.X), KP));
+  const int r = __builtin_amdgcn_readfirstlane(min(*J.r_dev, NC));
+  if (r <= 0) return;
+  const int kp = (k + 3) & ~3;
+  for (int e = threadIdx.x; e < kp * NC; e += blockDim.x) {
+    const int i = e / NC, c = e - i * NC;
+    Ms[i * S + c] = (i < k && c < r) ? T(J.M[size_t(i) * J.ldm + c]) : T(0);
+  }
+  for (int c = threadIdx.x; c < KP; c += blockDim.x) cols[c] = resolve_col(J.X, c);
+  __syncthreads();
+  const int64_t nrt = (J.rows + 15) / 16;
+  const int64_t per = (nrt + nwg - 1) / nwg;
+  const int64_t t0 = int64_t(wg) * per, t1 = min(nrt, t0 + per);
+  if (SCALED1 && jb == 1)
+    ts_rows_by_width<T, KQ, NT, true>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
+  else
+    ts_rows_by_width<T, KQ, NT, false>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
+}
+
+template <class T>
+using TsmmFn = void (*)(TsmmArgs<T>, const TsmmArgs<T>*, const int*);
+
+template <class T>
+static TsmmFn<T> tsmm_fn(int kb, int rb, bool sc1) {
+  if (kb <= 64) {
+    if (rb <= 64) return sc1 ? tsmm_kernel<T, 16, 4, true> : tsmm_kernel<T, 16, 4, false>;
+    return sc1 ? tsmm_kernel<T, 16, 8, true> : tsmm_kernel<T, 16, 8, false>;
+  }
+  if (rb <= 64) return sc1 ? tsmm_kernel<T, 32, 4, true> : tsmm_kernel<T, 32, 4, false>;
+  return sc1 ? tsmm_kernel<T, 32, 8, true> : tsmm_kernel<T, 32, 8, false>;
+}
+
+static int64_t tsmm_tiles(int64_t rows) { return (std::max<int64_t>(rows, 1) + 15) / 16; }
+// at least one row tile per wave
+static int tsmm_wgs_max(int64_t rows) {
+  return int(std::min<int64_t>(1 << 20, ceil_div(tsmm_tiles(rows), kTsThreads / 64)));
 }
 
 template <class T>
@@ -550,19 +679,26 @@ TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
   LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "tsmm: the first operand cannot be row-scaled");
   TsmmLaunch<T> l;
   TsmmArgs<T>& a = l.a;
-  const int cap_wg = sizeof(T) == 8 ? 256 : 512;
+  // host bounds of the device widths select the register / LDS class
+  l.kb = std::min(kcap, std::max(view_cap(jobs[0].X), njobs > 1 ? view_cap(jobs[1].X) : 0));
+  l.rb = rcap;
+  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
+  // one round of resident workgroups, shared by the jobs in proportion to
+  // their row tiles
+  const int slots =
+      resident_wgs(reinterpret_cast<const void*>(tsmm_fn<T>(l.kb, l.rb, l.sc1)), kTsThreads);
   a.job[0] = jobs[0];
-  a.nwg0 = int(std::min<int64_t>(cap_wg, std::max<int64_t>(1, ceil_div(jobs[0].rows, kTsRows))));
   if (njobs == 2) {
     a.job[1] = jobs[1];
-    a.nwg1 = int(std::min<int64_t>(cap_wg, std::max<int64_t>(1, ceil_div(jobs[1].rows, kTsRows))));
+    const double t0 = double(tsmm_tiles(jobs[0].rows)), t1 = double(tsmm_tiles(jobs[1].rows));
+    const int share = int(std::ceil(double(slots) * t1 / (t0 + t1)));
+    a.nwg1 = std::min(tsmm_wgs_max(jobs[1].rows), std::max(1, share));
   } else {
     a.job[1] = jobs[0];
     a.nwg1 = 0;
   }
+  a.nwg0 = std::min(tsmm_wgs_max(jobs[0].rows), std::max(1, slots - a.nwg1));
   l.grid = a.nwg0 + a.nwg1;
-  l.slices = int(ceil_div(rcap, kTsSlice));
-  l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
   // algorithmic bytes: X read once plus Y written once per job
   const double r0 = double(jobs[0].rows), r1 = double(njobs > 1 ? jobs[1].rows : 0);
   l.work.groups = {view_terms(jobs[0].X), {{jobs[0].r_dev, 0}},
@@ -576,12 +712,10 @@ TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
 
 template <class T>
 void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s) {
+  LRC_CHECK(l.kb <= kTsKCAP && l.rb <= kTsKCAP, ST_EINVAL, "tsmm: capacity exceeded");
   ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, l.work);
-  const dim3 grid(l.grid, l.slices, b.n);
-  if (l.sc1)
-    hipLaunchKernelGGL((tsmm_kernel<T, true>), grid, dim3(256), 0, s, l.a, b.dev, b.done);
-  else
-    hipLaunchKernelGGL((tsmm_kernel<T, false>), grid, dim3(256), 0, s, l.a, b.dev, b.done);
+  const dim3 grid(l.grid, 1, b.n), blk(kTsThreads);
+  tsmm_fn<T>(l.kb, l.rb, l.sc1)<<<grid, blk, 0, s>>>(l.a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 

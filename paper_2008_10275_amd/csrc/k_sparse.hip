@@ -156,7 +156,8 @@ template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int
 //     accumulated on MFMA (16x16x4).  Levels whose inputs are short give every
 //     wave its own task; long inputs are split over NW waves of one workgroup
 //     whose partial tiles are summed through LDS.  The input loop issues the
-//     loads of four MFMA steps before their products.
+//     loads of four MFMA steps (eight when waves share a task) before their
+//     products.
 typedef float floatx4_s __attribute__((ext_vector_type(4)));
 typedef double doublex4_s __attribute__((ext_vector_type(4)));
 template <class T> struct PMfma;
@@ -226,14 +227,13 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __res
 // DIRECT: the inputs are read where they live instead of from the staged
 // front (backward: y rows and x boundary rows; forward levels without
 // contributions: R rows by the permutation), so the level needs no gather.
-template <class T, bool FWD, int NW, int KTM, bool DIRECT>
+template <class T, bool FWD, int NW, int KTM, bool DIRECT, int U>
 __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     PrecDev<T> P, const int2* __restrict__ tasks, int ntasks, const int64_t* __restrict__ soff,
     PrecItem<T> a0, const PrecItem<T>* ab, const int* done, int ldw) {
   typedef typename PMfma<T>::acc_t acc_t;
   constexpr int WPB = NW > 4 ? NW : 4;    // waves per workgroup
   constexpr int TPB = WPB / NW;           // tasks per workgroup
-  constexpr int U = 4;                    // MFMA steps per unrolled input block
   __shared__ T red[NW > 1 ? NW : 1][KTM * 4][64];
   if (done && done[blockIdx.z]) return;
   const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
@@ -361,13 +361,15 @@ template <class T, bool FWD, int NW>
 static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const PrecDev<T>& P,
                               const LevelTasks& L, const int64_t* soff, const PrecItem<T>& it,
                               const Batched<PrecItem<T>>& b, int ldw) {
+  // long inputs split over several waves keep eight MFMA steps of loads in flight
+  constexpr int U = NW == 1 ? 4 : 8;
 #define LRC_PP(KT)                                                                                \
   do {                                                                                            \
     if (L.direct)                                                                                 \
-      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, true>), grid, blk, 0, s, P, L.tasks, \
-                         L.count, soff, it, b.dev, b.done, ldw);                                  \
+      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, true, U>), grid, blk, 0, s, P,       \
+                         L.tasks, L.count, soff, it, b.dev, b.done, ldw);                         \
     else                                                                                          \
-      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, false>), grid, blk, 0, s, P,         \
+      hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, false, U>), grid, blk, 0, s, P,      \
                          L.tasks, L.count, soff, it, b.dev, b.done, ldw);                         \
   } while (0)
   switch (KTM) {
@@ -409,18 +411,20 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
       {
         ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, kt));
         // waves per task by the level's longest input
-        const int NW = L.nin_max <= 64 ? 1 : (L.nin_max <= 512 ? 4 : 8);
+        const int NW = L.nin_max <= 64 ? 1 : L.nin_max <= 256 ? 4 : L.nin_max <= 512 ? 8 : 16;
         const int tpb = NW == 1 ? 4 : 1;
-        const dim3 grid(unsigned(ceil_div(L.count, tpb)), 1, b.n), blk(NW == 8 ? 512 : 256);
+        const dim3 grid(unsigned(ceil_div(L.count, tpb)), 1, b.n), blk(NW > 4 ? 64 * NW : 256);
         const int64_t* so = fw ? P.soff_fwd : P.soff_bwd;
         if (fw) {
           if (NW == 1) launch_product_nw<T, true, 1>(KTM, grid, blk, s, P, L, so, it, b, ldw);
           else if (NW == 4) launch_product_nw<T, true, 4>(KTM, grid, blk, s, P, L, so, it, b, ldw);
-          else launch_product_nw<T, true, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else if (NW == 8) launch_product_nw<T, true, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else launch_product_nw<T, true, 16>(KTM, grid, blk, s, P, L, so, it, b, ldw);
         } else {
           if (NW == 1) launch_product_nw<T, false, 1>(KTM, grid, blk, s, P, L, so, it, b, ldw);
           else if (NW == 4) launch_product_nw<T, false, 4>(KTM, grid, blk, s, P, L, so, it, b, ldw);
-          else launch_product_nw<T, false, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else if (NW == 8) launch_product_nw<T, false, 8>(KTM, grid, blk, s, P, L, so, it, b, ldw);
+          else launch_product_nw<T, false, 16>(KTM, grid, blk, s, P, L, so, it, b, ldw);
         }
       }
     }

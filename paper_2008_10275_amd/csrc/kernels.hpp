@@ -224,7 +224,8 @@ template <class T>
 struct TsmmLaunch {
   TsmmArgs<T> a;
   int grid = 0;
-  int slices = 0;
+  int kb = 0;        // host bound of the input width (selects the register class)
+  int rb = 0;        // host bound of the output width
   bool sc1 = false;
   Work work;
 };

@@ -156,7 +156,8 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.g1 = make_gram<T>(g1, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
   p.c1 = CholArgs{st, 1, kcap, eps};
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
-  p.t1 = make_tsmm<T>(t1, 2, kcap, kcap);
+  // the first pass writes st.k <= min(kcap, width bound) columns
+  p.t1 = make_tsmm<T>(t1, 2, kcap, std::min(kcap, std::max(view_cap(A), view_cap(B))));
   BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
   va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
@@ -206,7 +207,8 @@ template <class T>
 static void merge_tsmm(TsmmLaunch<T>& a, const TsmmLaunch<T>& b) {
   LRC_CHECK(a.sc1 == b.sc1, ST_EINVAL, "batched truncation: items differ in operand structure");
   a.grid = std::max(a.grid, b.grid);
-  a.slices = std::max(a.slices, b.slices);
+  a.kb = std::max(a.kb, b.kb);
+  a.rb = std::max(a.rb, b.rb);
 }
 
 template <class T>
