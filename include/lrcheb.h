@@ -74,7 +74,8 @@ typedef struct {
   int refine_max;      /* mixed: maximum fp64 refinement steps                  */
   double inner_tol;    /* mixed: residual reduction asked of each fp32 inner solve */
   int init;            /* LRC_INIT_*                                            */
-  double median_tol;   /* relative residual of the median-parameter solve       */
+  double median_tol;   /* relative residual of the median-parameter solve (the
+                          accuracy eps_N of Sec. 3.1; default 1e-6 as in Sec. 5) */
   int verify_fp64;     /* 1: finish with the entry-wise fp64 residual           */
   int eager;           /* 1: launch every step directly instead of replaying the
                           captured HIP graphs of the iterations (same arithmetic) */

@@ -662,7 +662,7 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     }
     coefmed.resize(op.q);
     for (int i = 0; i < op.q; ++i) coefmed[i] = Pr.d[size_t(jmed) * op.q + i];
-    median_tol = o.median_tol > 0 ? o.median_tol : 1e-10;
+    median_tol = o.median_tol > 0 ? o.median_tol : 1e-6;
   } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
     reset_lr(Pr.X0, n, m, r0, s);
