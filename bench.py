@@ -189,7 +189,9 @@ def main_surrogate(a, L, torch):
     Vd[:, :k] = torch.from_numpy(V).cuda()
     U0 = torch.zeros((n, 32), dtype=torch.float64, device="cuda")
     V0 = torch.zeros((V.shape[0], 32), dtype=torch.float64, device="cuda")
-    s0, rr = L.truncate_dev(ctx, Ud, sv, Vd, r, 0.0, U0, V0)
+    # POD basis: the snapshots truncated at the solver's own tolerance (modes
+    # below it are rounding noise that would only widen the residual)
+    s0, rr = L.truncate_dev(ctx, Ud, sv, Vd, r, cfg["trunc_tol"], U0, V0)
     Ctr = (V0[:, :rr] * torch.from_numpy(s0).cuda()).contiguous()
     net = L.MLP(ctx, mlp_init(11, sizes=(2, 64, 64, rr)))
     Xtr = torch.from_numpy(np.ascontiguousarray(dtr[1:].T)).cuda()

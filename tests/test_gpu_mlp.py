@@ -141,7 +141,8 @@ def test_learned_initial_guess_gain(torch, L, ctx):
     U, s, V = ptr.solution()
     n, mtr = U.shape[0], V.shape[0]
     r = 30
-    # POD of the snapshot matrix U diag(s) V^T by the GPU truncation (rank r, no tail cut)
+    # POD of the snapshot matrix U diag(s) V^T by the GPU truncation (rank <= r,
+    # tail cut at the solver's truncation tolerance)
     k = U.shape[1]
     ld = (k + 7) // 8 * 8
     Ud = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
@@ -150,7 +151,7 @@ def test_learned_initial_guess_gain(torch, L, ctx):
     Vd[:, :k] = torch.from_numpy(V).cuda()
     U0 = torch.zeros((n, 32), dtype=torch.float64, device="cuda")
     V0 = torch.zeros((mtr, 32), dtype=torch.float64, device="cuda")
-    s0, rr = L.truncate_dev(ctx, Ud, s, Vd, r, 0.0, U0, V0)
+    s0, rr = L.truncate_dev(ctx, Ud, s, Vd, r, cfg["trunc_tol"], U0, V0)
     Ctr = V0[:, :rr] * torch.from_numpy(s0).cuda()          # training coefficients
     net = L.MLP(ctx, mlp_init(11, sizes=(2, 64, 64, rr)))
     Xtr = torch.from_numpy(np.ascontiguousarray(dtr[1:].T)).cuda()
