@@ -154,7 +154,8 @@ void lrc_prob_destroy(lrc_prob prob);
 /* Factorise P = sum_i dbar_i K_i (dbar: q values, NULL = arithmetic means of the
  * rows of d).  Nested-dissection ordering + multifrontal LU without pivoting
  * on the host, inverted supernode blocks uploaded for the level-scheduled GPU
- * solves.  leaf_size <= 0 selects the default.  LRC_ESINGULAR on a bad pivot. */
+ * solves.  leaf_size: nodes per nested-dissection leaf (<= 0: the default, 64).
+ * LRC_ESINGULAR on a bad pivot. */
 lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size);
 /* Interval [d - c, d + c] enclosing the preconditioned spectra: the smallest
  * interval holding 1 and every ratio d[i, j] / dbar_i (valid when K_0 + K_0^T

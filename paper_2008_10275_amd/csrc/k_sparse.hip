@@ -11,11 +11,16 @@ namespace lrc {
 // ============================================================== SpMM
 // Every row of K_i is handled by `lpr` consecutive lanes; each lane owns CPL
 // consecutive columns of the factor.  Rows of U are contiguous (row-major), so
-// each nonzero K_i(row, j) costs one coalesced read of row j of U.  The grid's
-// y dimension runs over the q operators that share U.
+// each nonzero K_i(row, j) costs one coalesced read of row j of U.  lpr follows
+// the device rank (lanes past it would idle); the nonzeros of a row are taken
+// four at a time, their column indices loaded before the U rows they select
+// (padding slots reuse the row's first column with a zero value), so that a
+// row costs two dependent load rounds per four nonzeros.  The grid's y
+// dimension runs over the q operators that share U.
 template <class T, int CPL>
 __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
-                                                   const int* done, int lpr) {
+                                                   const int* done, int lpr_cap) {
+  constexpr int NZB = 4;
   if (done && done[blockIdx.z]) return;
   const SpmmArgs<T>& args = ab ? ab[blockIdx.z] : a0;
   if (int(blockIdx.y) >= args.q) return;
@@ -23,7 +28,9 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
   T* __restrict__ W = args.W[blockIdx.y];
   const T* __restrict__ U = args.U;
   const int ldu = args.ldu, ldw = args.ldw;
-  const int r = args.r_dev ? *args.r_dev : args.r_const;
+  const int r = __builtin_amdgcn_readfirstlane(args.r_dev ? *args.r_dev : args.r_const);
+  if (r <= 0) return;
+  const int lpr = min(lpr_cap, (r + CPL - 1) / CPL);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rpw = 64 / lpr;                       // rows per wave
@@ -38,11 +45,23 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] = T(0);
     const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
-    for (int e = e0; e < e1; ++e) {
-      const T v = K.val[e];
-      const T* __restrict__ u = U + int64_t(K.col[e]) * ldu + c0;
+    for (int e = e0; e < e1; e += NZB) {
+      int cj[NZB];
+      T vj[NZB];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) acc[c] += v * u[c];
+      for (int u = 0; u < NZB; ++u) {
+        const bool ok = e + u < e1;
+        const int x = ok ? e + u : e0;
+        cj[u] = K.col[x];
+        const T v = K.val[x];
+        vj[u] = ok ? v : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < NZB; ++u) {
+        const T* __restrict__ ur = U + int64_t(cj[u]) * ldu + c0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] += vj[u] * ur[c];
+      }
     }
     T* w = W + row * ldw + c0;
     if (c0 + CPL <= r) {
@@ -606,15 +625,19 @@ __global__ __launch_bounds__(256) void cast_lr_kernel(const CastItem<Tin, Tout>*
                                                       const int* __restrict__ done) {
   if (done && done[blockIdx.z]) return;
   const CastItem<Tin, Tout>& c = items[blockIdx.z];
-  const int cols = min(*c.r, c.colcap);
-  const int64_t total = (c.n + c.m) * c.colcap;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t row = e / c.colcap;
-    const int col = int(e - row * c.colcap);
-    if (col >= cols) continue;
-    if (row < c.n) c.U2[row * c.ldu2 + col] = Tout(c.U[row * c.ldu + col]);
-    else c.V2[(row - c.n) * c.ldv2 + col] = Tout(c.V[(row - c.n) * c.ldv + col]);
+  const int cols = __builtin_amdgcn_readfirstlane(min(*c.r, c.colcap));
+  if (cols > 0) {
+    // lpr = the power of two >= cols lanes per row (cols <= 64 <= blockDim)
+    int lg = 0;
+    while ((1 << lg) < cols) ++lg;
+    const int rpb = int(blockDim.x) >> lg, col = int(threadIdx.x) & ((1 << lg) - 1);
+    const int64_t rows = c.n + c.m;
+    if (col < cols)
+      for (int64_t row = int64_t(blockIdx.x) * rpb + (threadIdx.x >> lg); row < rows;
+           row += int64_t(gridDim.x) * rpb) {
+        if (row < c.n) c.U2[row * c.ldu2 + col] = Tout(c.U[row * c.ldu + col]);
+        else c.V2[(row - c.n) * c.ldv2 + col] = Tout(c.V[(row - c.n) * c.ldv + col]);
+      }
   }
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < cols; t += blockDim.x) c.s2[t] = c.s[t];
@@ -625,6 +648,7 @@ __global__ __launch_bounds__(256) void cast_lr_kernel(const CastItem<Tin, Tout>*
 template <class Tin, class Tout>
 void launch_cast_lr(const CastItem<Tin, Tout>* items, const int* done, int nb, int64_t rows_max,
                     int colcap, hipStream_t s) {
+  LRC_CHECK(colcap >= 0 && colcap <= 64, ST_EINVAL, "cast: at most 64 columns");
   const int64_t blocks =
       std::min<int64_t>(std::max<int64_t>(ceil_div(rows_max * colcap, 256), 1), 4096);
   ProfScope ps(kcls(K_VECTOR, false), s);

@@ -99,7 +99,7 @@ def test_batched_matches_subset_solves(torch, L, ctx, c3, precision):
 
 def test_batched_mixed_structures(torch, L, ctx, c3):
     """Two subsets whose preconditioners have different supernode structures
-    (leaf sizes 16 and 8) take the per-subset preconditioner launches inside
+    (leaf sizes 64 and 8) take the per-subset preconditioner launches inside
     the batch; a single-problem batch is the degenerate case."""
     cfg, subs = c3
     kw = _kw(L, "mixed")
