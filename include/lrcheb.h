@@ -124,16 +124,19 @@ lrc_status lrc_ops_update_values(lrc_ops ops, int i, const double* val);
 void lrc_ops_destroy(lrc_ops ops);
 /* W_i = K_i U for all i (device, row-major).  dtype 0: fp64, 1: fp32.
  * U: n x r with ld ldu; W: q blocks of n x r with ld ldw, block i at
- * W + i * n * ldw.  ldu, ldw multiples of 8, r <= min(ldu, ldw) <= 256. */
+ * W + i * n * ldw.  ldu, ldw multiples of 8, r <= min(ldu, ldw) <= 256; U and W
+ * 16-byte aligned (LRC_EINVAL otherwise).  Columns of W past r are not written. */
 lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U_dev, int ldu,
                             void* W_dev, int ldw);
 /* SpMM autotuning for this operator set at width r (dtype 0/1): times every
  * candidate launch shape (columns per lane 1/2/4/8, 2/4/8 waves per
- * workgroup, grid caps 2048/8192/32768) on the device and caches the fastest
- * in the context for (precision, n, q, nnz, r); every later SpMM of that shape
- * (solver steps included) uses it, and the solver tunes on first use anyway.
- * cfg (may be NULL) receives {columns per lane, waves, grid cap}; times_us
- * (may be NULL) {best, default shape} in microseconds per launch.  Results do
+ * workgroup, grid caps 2048/8192/32768) on the device at widths r, r/2 and
+ * r/4 (a launch planned for capacity r runs at the device rank, below it) and
+ * caches the fastest in total in the context for (precision, n, q, nnz, r);
+ * every later SpMM of that shape (solver steps included) uses it, and the
+ * solver tunes on first use anyway.  cfg (may be NULL) receives {columns per
+ * lane, waves, grid cap}; times_us (may be NULL) {best, default shape}: the
+ * microseconds per launch summed over the timed widths.  Results do
  * not depend on the shape: each row is summed in the same order by one lane
  * group whatever the choice. */
 lrc_status lrc_ops_spmm_tune(lrc_ops ops, int dtype, int r, int cfg[3], double times_us[2]);

@@ -432,9 +432,13 @@ lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* r
       O.upload_values(i);
     }
     for (int i = 0; i < q; ++i) {
-      const int64_t nnz = O.host[i].rowptr[n];
-      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz});
-      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz});
+      const auto& rp = O.host[i].rowptr;
+      const int64_t nnz = rp[n];
+      int64_t maxrow = 0;
+      for (int64_t r = 0; r < n; ++r) maxrow = std::max<int64_t>(maxrow, rp[r + 1] - rp[r]);
+      const int mr = int(std::min<int64_t>(maxrow, 1 << 30));
+      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz, mr});
+      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz, mr});
     }
     *out = o.release();
     return LRC_OK;
@@ -467,15 +471,17 @@ lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U, int ld
     if (dtype == 0) {
       double* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
-      enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu,
-                                     nullptr, r, r, Wp, ldw, spmm_config<double>(o, r)),
-                   Batched<SpmmArgs<double>>(), o.ctx->stream);
+      auto l = make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu, nullptr,
+                                 r, r, Wp, ldw, spmm_config<double>(o, r));
+      l.a.wpad = 0;   // the caller's W: columns past r are left untouched
+      enqueue_spmm(l, Batched<SpmmArgs<double>>(), o.ctx->stream);
     } else {
       float* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
-      enqueue_spmm(make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr,
-                                    r, r, Wp, ldw, spmm_config<float>(o, r)),
-                   Batched<SpmmArgs<float>>(), o.ctx->stream);
+      auto l = make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr, r,
+                                r, Wp, ldw, spmm_config<float>(o, r));
+      l.a.wpad = 0;
+      enqueue_spmm(l, Batched<SpmmArgs<float>>(), o.ctx->stream);
     }
     return LRC_OK;
   });
@@ -493,15 +499,17 @@ lrc_status lrc_ops_spmm_shape_dev(lrc_ops ops, int dtype, int r, const void* U, 
     if (dtype == 0) {
       double* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
-      enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu,
-                                     nullptr, r, r, Wp, ldw, c),
-                   Batched<SpmmArgs<double>>(), o.ctx->stream);
+      auto l = make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu, nullptr,
+                                 r, r, Wp, ldw, c);
+      l.a.wpad = 0;
+      enqueue_spmm(l, Batched<SpmmArgs<double>>(), o.ctx->stream);
     } else {
       float* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
-      enqueue_spmm(make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr,
-                                    r, r, Wp, ldw, c),
-                   Batched<SpmmArgs<float>>(), o.ctx->stream);
+      auto l = make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr, r,
+                                r, Wp, ldw, c);
+      l.a.wpad = 0;
+      enqueue_spmm(l, Batched<SpmmArgs<float>>(), o.ctx->stream);
     }
     return LRC_OK;
   });

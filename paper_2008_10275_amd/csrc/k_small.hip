@@ -195,12 +195,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
     if (tid == 0) atomicOr(st.info, 2);
   }
   __syncthreads();
-  // Rout = R D^{-1}
-  for (int e = tid; e < kcap * kcap; e += nt) {
-    const int i = e / kcap, j = e - i * kcap;
+  // Rout = R D^{-1} (only the leading k x k block: every consumer reads
+  // within the device width)
+  for (int e = tid; e < k * k; e += nt) {
+    const int i = e / k, j = e - i * k;
     double v = 0.0;
-    if (i < k && j < k && j >= i && dsc[j] != 0.0) v = A[i * kCL + j] / dsc[j];
-    Rout[e] = v;
+    if (j >= i && dsc[j] != 0.0) v = A[i * kCL + j] / dsc[j];
+    Rout[size_t(i) * kcap + j] = v;
   }
   // X = R^{-1} by block diagonals; X_IJ (I < J) lives in the lower tile (J, I)
   for (int d = 1; d < nbk; ++d) {
@@ -232,16 +233,16 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
     }
     __syncthreads();
   }
-  // Tout = D R^{-1}
-  for (int e = tid; e < kcap * kcap; e += nt) {
-    const int i = e / kcap, j = e - i * kcap;
+  // Tout = D R^{-1} (leading k x k block)
+  for (int e = tid; e < k * k; e += nt) {
+    const int i = e / k, j = e - i * k;
     double v = 0.0;
-    if (i < k && j < k && j >= i) {
+    if (j >= i) {
       const int I = i >> 4, J = j >> 4;
       const double xv = I == J ? Tb[I][i & 15][j & 15] : A[(16 * J + (i & 15)) * kCL + 16 * I + (j & 15)];
       v = dsc[i] * xv;
     }
-    Tout[e] = v;
+    Tout[size_t(i) * kcap + j] = v;
   }
 }
 

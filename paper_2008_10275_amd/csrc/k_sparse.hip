@@ -8,70 +8,138 @@
 
 namespace lrc {
 
+// 16-byte vector of T
+template <class T> struct V16;
+template <> struct V16<float> {
+  typedef float4 t;
+  static constexpr int n = 4;
+  static __device__ inline t zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w; }
+  static __device__ inline void fma(t& a, float s, const t& b) {
+    a.x += s * b.x; a.y += s * b.y; a.z += s * b.z; a.w += s * b.w;
+  }
+};
+template <> struct V16<double> {
+  typedef double2 t;
+  static constexpr int n = 2;
+  static __device__ inline t zero() { return make_double2(0.0, 0.0); }
+  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; }
+  static __device__ inline void fma(t& a, double s, const t& b) { a.x += s * b.x; a.y += s * b.y; }
+};
+
 // ============================================================== SpMM
-// Every row of K_i is handled by `lpr` consecutive lanes; each lane owns CPL
-// consecutive columns of the factor.  Rows of U are contiguous (row-major), so
-// each nonzero K_i(row, j) costs one coalesced read of row j of U.  lpr follows
-// the device rank (lanes past it would idle); the nonzeros of a row are taken
-// four at a time, their column indices loaded before the U rows they select
-// (padding slots reuse the row's first column with a zero value), so that a
-// row costs two dependent load rounds per four nonzeros.  The grid's y
-// dimension runs over the q operators that share U.
-template <class T, int CPL>
+// Every row of K_i is handled by `lpr` consecutive lanes; a lane owns NV
+// 16-byte vectors of the factor's columns, interleaved with stride lpr, so
+// that every load of a row of U and every store of a row of W_i is one
+// contiguous span per instruction (whole cache lines, not 8-byte pieces).
+// lpr follows the device rank (lanes past it would idle).  The nonzeros of a
+// row are taken in batches, their column indices loaded before the U rows
+// they select (padding slots reuse the row's first column with a zero value),
+// so that a row costs two dependent load rounds per batch.
+// One row of one operator: acc = K(row, :) U, stored to W.
+template <class T, int NV, int NZB>
+__device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
+                                         const T* __restrict__ U, int ldu, T* __restrict__ W,
+                                         int ldw, int r, int nvec, int lpr, int chunk, bool wpad) {
+  typedef typename V16<T>::t V;
+  constexpr int VW = V16<T>::n;
+  V acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = V16<T>::zero();
+  const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
+  for (int e = e0; e < e1; e += NZB) {
+    int cj[NZB];
+    T vj[NZB];
+#pragma unroll
+    for (int u = 0; u < NZB; ++u) {
+      const bool ok = e + u < e1;
+      const int x = ok ? e + u : e0;
+      cj[u] = K.col[x];
+      const T val = K.val[x];
+      vj[u] = ok ? val : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NZB; ++u) {
+      const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int j = chunk + v * lpr;
+        if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
+      }
+    }
+  }
+  T* __restrict__ wr = W + row * ldw;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int j = chunk + v * lpr;
+    if (j >= nvec) break;
+    if ((j + 1) * VW <= r) {
+      *reinterpret_cast<V*>(wr + j * VW) = acc[v];
+    } else {
+      // the row's last, partial vector (static element indices: the
+      // accumulator stays in registers).  With wpad the columns past the rank
+      // (inside the row's padding: ldw >= the rank rounded up to 8) are written
+      // as zeros, so that the store is one whole vector.
+      T ap[VW];
+      *reinterpret_cast<V*>(ap) = acc[v];
+      if (wpad) {
+#pragma unroll
+        for (int x = 0; x < VW; ++x)
+          if (j * VW + x >= r) ap[x] = T(0);
+        *reinterpret_cast<V*>(wr + j * VW) = *reinterpret_cast<const V*>(ap);
+      } else {
+#pragma unroll
+        for (int x = 0; x < VW; ++x)
+          if (j * VW + x < r) wr[j * VW + x] = ap[x];
+      }
+    }
+  }
+}
+
+// Workgroups per operator and row block: consecutive workgroups of one XCD
+// (hardware workgroup w runs on XCD w mod 8) take the q operators of one row
+// block, so that the rows of U one operator loads serve the others from that
+// XCD's L2 while every row keeps a single dependent chain.  The grid is a
+// multiple of 8 q.  The nonzeros of a row are taken NZB at a time: the
+// operator's longest row when it is 5 or 9 (the stencils' own widths: no
+// padded slot on interior rows), else 4.
+template <class T, int NV>
 __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
                                                    const int* done, int lpr_cap) {
-  constexpr int NZB = 4;
+  constexpr int VW = V16<T>::n;
   if (done && done[blockIdx.z]) return;
   const SpmmArgs<T>& args = ab ? ab[blockIdx.z] : a0;
-  if (int(blockIdx.y) >= args.q) return;
-  const DevCsr<T> K = args.op[blockIdx.y];
-  T* __restrict__ W = args.W[blockIdx.y];
-  const T* __restrict__ U = args.U;
-  const int ldu = args.ldu, ldw = args.ldw;
+  const int q = args.q;
+  const int L = blockIdx.x, xcd = L & 7, kx = L >> 3;
+  const int op = kx % q, rb = (kx / q) * 8 + xcd;   // row block of this workgroup's sweep
+  const int nrb = int(gridDim.x) / q;                // row blocks per sweep
+  if (rb >= nrb) return;
+  const DevCsr<T> K = args.op[op];
   const int r = __builtin_amdgcn_readfirstlane(args.r_dev ? *args.r_dev : args.r_const);
   if (r <= 0) return;
-  const int lpr = min(lpr_cap, (r + CPL - 1) / CPL);
+  const int nvec = (r + VW - 1) / VW;            // vectors per row
+  const int lpr = min(lpr_cap, (nvec + NV - 1) / NV);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rpw = 64 / lpr;                       // rows per wave
   const int sub = lane / lpr;
   const int chunk = lane - sub * lpr;
-  const int c0 = chunk * CPL;
-  if (sub >= rpw || c0 >= r) return;
+  if (sub >= rpw || chunk >= nvec) return;
   const int64_t rows_per_block = int64_t(rpw) * (blockDim.x >> 6);
-  for (int64_t row = int64_t(blockIdx.x) * rows_per_block + int64_t(wave) * rpw + sub; row < K.n;
-       row += int64_t(gridDim.x) * rows_per_block) {
-    T acc[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] = T(0);
-    const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
-    for (int e = e0; e < e1; e += NZB) {
-      int cj[NZB];
-      T vj[NZB];
-#pragma unroll
-      for (int u = 0; u < NZB; ++u) {
-        const bool ok = e + u < e1;
-        const int x = ok ? e + u : e0;
-        cj[u] = K.col[x];
-        const T v = K.val[x];
-        vj[u] = ok ? v : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < NZB; ++u) {
-        const T* __restrict__ ur = U + int64_t(cj[u]) * ldu + c0;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) acc[c] += vj[u] * ur[c];
-      }
-    }
-    T* w = W + row * ldw + c0;
-    if (c0 + CPL <= r) {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) w[c] = acc[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c)
-        if (c0 + c < r) w[c] = acc[c];
-    }
+  const int64_t stride = int64_t(nrb) * rows_per_block;
+  T* __restrict__ W = args.W[op];
+  const int64_t first = int64_t(rb) * rows_per_block + int64_t(wave) * rpw + sub;
+  const int maxrow = __builtin_amdgcn_readfirstlane(K.maxrow);
+  const bool wpad = args.wpad != 0;
+  if (maxrow <= 5) {
+    for (int64_t row = first; row < K.n; row += stride)
+      spmm_row<T, NV, 5>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
+  } else if (maxrow <= 9) {
+    for (int64_t row = first; row < K.n; row += stride)
+      spmm_row<T, NV, 9>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
+  } else {
+    for (int64_t row = first; row < K.n; row += stride)
+      spmm_row<T, NV, 4>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
   }
 }
 
@@ -87,8 +155,15 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
             "spmm: columns per lane must be 1, 2, 4 or 8");
   LRC_CHECK(cfg.waves >= 1 && cfg.waves <= 8 && cfg.max_blocks >= 1, ST_EINVAL,
             "spmm: 1..8 waves per workgroup");
-  const int lpr = int(ceil_div(rcap, cpl));
+  // a lane owns nv 16-byte vectors (cpl columns, at least one vector)
+  constexpr int VW = 16 / int(sizeof(T));
+  const int nv = std::max(1, cpl / VW);
+  const int lpr = int(ceil_div(ceil_div(rcap, VW), nv));
   LRC_CHECK(lpr <= 64, ST_EINVAL, "spmm: rank capacity too large for the lane mapping");
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  LRC_CHECK(al16(U), ST_EINVAL, "spmm: the factor must be 16-byte aligned");
+  for (int i = 0; i < q; ++i)
+    LRC_CHECK(al16(W[i]), ST_EINVAL, "spmm: the products must be 16-byte aligned");
   SpmmLaunch<T> l;
   SpmmArgs<T>& a = l.a;
   int64_t n = 0;
@@ -103,12 +178,18 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
   a.r_dev = r_dev;
   a.r_const = r_const;
   a.ldw = ldw;
+  a.wpad = 1;   // the solver's own product buffers; callers' buffers clear it
   l.cpl = cpl;
+  l.nv = nv;
   l.lpr = lpr;
   l.waves = cfg.waves;
   const int rpw = 64 / lpr;
   const int64_t rows_per_block = int64_t(rpw) * cfg.waves;
-  l.blocks = int(std::max<int64_t>(std::min<int64_t>(ceil_div(n, rows_per_block), cfg.max_blocks), 1));
+  // row blocks per sweep, a multiple of 8; q workgroups each
+  int64_t rbs = std::max<int64_t>(std::min<int64_t>(ceil_div(n, rows_per_block), cfg.max_blocks), 1);
+  rbs = (rbs + 7) / 8 * 8;
+  LRC_CHECK(rbs * q < (int64_t(1) << 31), ST_EINVAL, "spmm: grid too large");
+  l.blocks = int(rbs * q);
   l.q = q;
   // algorithmic bytes: values + int32 columns + row pointers of every operator,
   // U read once, every W_i written (all n rows)
@@ -126,19 +207,16 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
 template <class T>
 void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s) {
   ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, l.work);
-  const dim3 grid(unsigned(l.blocks), unsigned(l.q), unsigned(b.n)), blk(64 * l.waves);
-  switch (l.cpl) {
+  const dim3 grid(unsigned(l.blocks), 1, unsigned(b.n)), blk(64 * l.waves);
+  switch (l.nv) {
     case 1:
       hipLaunchKernelGGL((spmm_kernel<T, 1>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
     case 2:
       hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
-    case 4:
-      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
-      break;
     default:
-      hipLaunchKernelGGL((spmm_kernel<T, 8>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
+      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
       break;
   }
   LRC_HIP(hipGetLastError());
@@ -193,21 +271,6 @@ template <> struct PMfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ inline int drow(int lane, int i) { return (lane >> 4) + 4 * i; }
-};
-
-// 16-byte vector of T
-template <class T> struct V16;
-template <> struct V16<float> {
-  typedef float4 t;
-  static constexpr int n = 4;
-  static __device__ inline t zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w; }
-};
-template <> struct V16<double> {
-  typedef double2 t;
-  static constexpr int n = 2;
-  static __device__ inline t zero() { return make_double2(0.0, 0.0); }
-  static __device__ inline void add(t& a, const t& b) { a.x += b.x; a.y += b.y; }
 };
 
 constexpr int kKMAX = 64;      // max columns per apply

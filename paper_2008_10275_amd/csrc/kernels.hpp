@@ -27,6 +27,7 @@ struct DevCsr {
   const T* val;
   int64_t n;
   int64_t nnz;
+  int maxrow;   // most entries in one row
 };
 
 constexpr int kMaxOps = 8;
@@ -46,11 +47,13 @@ struct SpmmArgs {
   int q;
   int ldu;
   int ldw;
+  int wpad;   // 1: W's columns past the rank, up to 16 bytes, may be overwritten (zeros)
 };
 template <class T>
 struct SpmmLaunch {
   SpmmArgs<T> a;
-  int cpl = 4;     // columns per lane
+  int cpl = 4;     // columns per lane (as requested)
+  int nv = 1;      // 16-byte vectors per lane
   int lpr = 1;     // lanes per row
   int waves = 4;   // waves per workgroup
   int blocks = 1;

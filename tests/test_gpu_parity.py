@@ -100,7 +100,8 @@ def test_preconditioner_solve_matches_sparse_lu(torch, L, ctx, dt, name, k):
 @pytest.mark.parametrize("r", [1, 30, 40])
 def test_spmm_autotune_shapes_agree(torch, L, ctx, dt, r):
     """Every candidate launch shape gives the same bits (each row is summed
-    in order by one lane group), the tuner's pick is the fastest it timed,
+    in order by one lane group), the tuner's pick is the fastest it timed
+    (summed over the widths it scores),
     and the solver's SpMM (tuned shape) matches SciPy."""
     say("spmm autotune", dt, r)
     K = config("c2", small=True)["ops"].K
