@@ -360,6 +360,37 @@ def cpu_baseline(cfg):
                         f"single-threaded, BLAS on {cores} threads)"))
 
 
+def spmm_roofline(L, ops, K, ranks, torch, reps=20):
+    """The solver's SpMM on the workload's own operators, alone, at the given
+    widths (fp64 and fp32; the autotuned shape): algorithmic bytes (entries,
+    column indices and row pointers of every operator, U once, every W_i) per
+    launch over the HIP-event time of a launch."""
+    n, q = K[0].shape[0], len(K)
+    nnz = sum(k.nnz for k in K)
+    out = []
+    for dt, v, name in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
+        for r in ranks:
+            ld = max(8, (r + 7) // 8 * 8)
+            U = torch.randn((n, ld), dtype=dt, device="cuda")
+            W = torch.zeros((q * n, ld), dtype=dt, device="cuda")
+            for _ in range(3):
+                ops.spmm_dev(U, W, r)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ops.spmm_dev(U, W, r)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps * 1e-3
+            b = nnz * (v + 4) + q * (n + 1) * 4 + n * r * v + q * n * r * v
+            out.append(dict(dtype=name, r=int(r), avg_launch_us=t * 1e6, bytes_per_launch=int(b),
+                            achieved=b / t / 1e9, peak=8000.0, unit="GB/s",
+                            frac=b / t / 8e12))
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -476,6 +507,9 @@ def main():
         cpu = cpu_baseline(cfg)
 
     last = infos[-1]
+    # the SpMM alone at the solution's rank and at the rank cap
+    spmm = spmm_roofline(L, ops, cfg["ops"].K, sorted({max(1, int(last["rank"])),
+                                                      int(cfg["rank_cap"])}), torch)
     n, m = cfg["ops"].K[0].shape[0], cfg["d"].shape[1]
     line = {
         "metric": "time to rel. residual 1e-6 (s)" if res_tol == 1e-6 else
@@ -508,6 +542,7 @@ def main():
         "mixed_refinement": refine,
         "speedup_vs_fp64": (fp64["seconds"] / (ms / 1e3)) if fp64 else None,
         "roofline": roof,
+        "spmm_roofline": spmm,
         "kernels": ktab,
         "cpu_baseline": cpu,
     }
