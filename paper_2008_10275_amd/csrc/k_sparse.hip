@@ -252,9 +252,10 @@ template void launch_spmm<double>(const DevCsr<double>*, int, const double*, int
 //  2. product: one task per (supernode, 16 output rows), a 16 x 16k tile
 //     accumulated on MFMA (16x16x4).  Levels whose inputs are short give every
 //     wave its own task; long inputs are split over NW waves of one workgroup
-//     whose partial tiles are summed through LDS.  The input loop issues the
-//     loads of four MFMA steps (eight when waves share a task) before their
-//     products.
+//     whose partial tiles are summed through LDS (levels with more tasks than
+//     resident waves keep one wave per task up to 256 inputs).  The input
+//     loop issues the loads of eight MFMA steps (four in single-wave forward
+//     tasks) before their products.
 typedef float floatx4_s __attribute__((ext_vector_type(4)));
 typedef double doublex4_s __attribute__((ext_vector_type(4)));
 template <class T> struct PMfma;
@@ -443,8 +444,9 @@ template <class T, bool FWD, int NW>
 static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const PrecDev<T>& P,
                               const LevelTasks& L, const int64_t* soff, const PrecItem<T>& it,
                               const Batched<PrecItem<T>>& b, int ldw) {
-  // long inputs split over several waves keep eight MFMA steps of loads in flight
-  constexpr int U = NW == 1 ? 4 : 8;
+  // eight MFMA steps of loads in flight per wave (four for single-wave forward
+  // tasks, whose inputs are at most 64 long: more only costs occupancy there)
+  constexpr int U = (NW == 1 && FWD) ? 4 : 8;
 #define LRC_PP(KT)                                                                                \
   do {                                                                                            \
     if (L.direct)                                                                                 \
@@ -492,8 +494,12 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
       }
       {
         ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, kt));
-        // waves per task by the level's longest input
-        const int NW = L.nin_max <= 64 ? 1 : L.nin_max <= 256 ? 4 : L.nin_max <= 512 ? 8 : 16;
+        // waves per task by the level's longest input; a level with more tasks
+        // than the GPU holds waves is throughput-bound: one wave per task there
+        // (no partial tiles to sum) unless the inputs are long
+        const bool wide = L.count >= 8192;
+        const int NW = (L.nin_max <= 64 || (wide && L.nin_max <= 256)) ? 1
+                       : L.nin_max <= 256 ? 4 : L.nin_max <= 512 ? 8 : 16;
         const int tpb = NW == 1 ? 4 : 1;
         const dim3 grid(unsigned(ceil_div(L.count, tpb)), 1, b.n), blk(NW > 4 ? 64 * NW : 256);
         const int64_t* so = fw ? P.soff_fwd : P.soff_bwd;
