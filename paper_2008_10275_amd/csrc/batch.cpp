@@ -318,9 +318,10 @@ struct BatchCheb {
     return *bufs.back();
   }
 
+  // res_abs: per item, the absolute floor of the residual's truncation
   void setup(const std::vector<Cheb<T>*>& items, const std::vector<const LR<T>*>& rhs,
              const std::vector<double>& c_, const std::vector<double>& dc_, double tol,
-             int cycle_, bool eager, hipStream_t s_) {
+             const std::vector<double>& res_abs, int cycle_, bool eager, hipStream_t s_) {
     it = items;
     B = rhs;
     c = c_;
@@ -363,8 +364,9 @@ struct BatchCheb {
       p0 = merge_plans(v);
       bt = upload_plans(v, dn, newbuf(), s);
     };
-    site([&](int j) { return it[j]->resid_plan(*B[j], it[j]->norm.template as<double>(), tol); },
-         resid0, residB);
+    site([&](int j) {
+      return it[j]->resid_plan(*B[j], it[j]->norm.template as<double>(), tol, 0, res_abs[j]);
+    }, resid0, residB);
     site([&](int j) { return it[j]->dstart_plan(dc[j]); }, dstart0, dstartB);
     site([&](int j) { return it[j]->supd_plan(); }, supd0, supdB);
     // D updates of a cycle: the coefficients follow rho_0 = c/dc,
@@ -539,7 +541,8 @@ struct BatchDir {
     };
     site64([&](int j) {
       Cheb<double>& C = *run[j]->c64;
-      return C.resid_plan(run[j]->B64, C.norm.as<double>(), o.trunc_tol);
+      return C.resid_plan(run[j]->B64, C.norm.as<double>(), o.trunc_tol, 0,
+                          kResFloor * run[j]->target);
     }, resid0, residB);
     site64([&](int j) { return run[j]->c64->supd_plan(); }, supd0, supdB);
     site32([&](int j) { return run[j]->c32->dstart_plan(run[j]->dc); }, dstart0, dstartB);
@@ -763,7 +766,9 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       items.push_back(r->c64.get());
       rhs.push_back(&r->B64);
     }
-    bc.setup(items, rhs, c, dc, o.trunc_tol, o.restart, eager, s);
+    std::vector<double> res_abs;
+    for (auto* r : run) res_abs.push_back(kResFloor * r->target);
+    bc.setup(items, rhs, c, dc, o.trunc_tol, res_abs, o.restart, eager, s);
     bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30, &bn);
     for (int j = 0; j < nb; ++j) {
       run[j]->iters = bc.hctl[j].iters;
@@ -823,7 +828,8 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
         items.push_back(r->c32.get());
         rhs.push_back(&r->Bin);
       }
-      bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, o.restart, eager, s);
+      bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, std::vector<double>(nb, 0.0),
+               o.restart, eager, s);
     }
     const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
     while (true) {

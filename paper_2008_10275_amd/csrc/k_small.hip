@@ -393,7 +393,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
     double tr = 0.0;
     for (int i = tid; i < k; i += 64) tr += fabs(Hs[0][pu(i, i, kp)]);
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    if (tid == 0) s_floor = fmax(1e-16, 0.01 * ja_.tol * ja_.tol) * tr;
+    if (tid == 0)
+      s_floor = fmax(fmax(1e-16, 0.01 * ja_.tol * ja_.tol) * tr, 0.01 * ja_.abs_tol * ja_.abs_tol);
   }
   __syncthreads();
   const double floor_abs = s_floor;
@@ -600,7 +601,10 @@ __global__ __launch_bounds__(kPivThreads) void pivchol_kernel(PivArgs a0, const 
     double tr = 0.0;
     for (int i = tid; i < k; i += 64) tr += fabs(dg[i]);
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    if (tid == 0) s_thr = tol > 0.0 ? fmax(1e-16, 0.01 * tol * tol) * tr : 0.0;
+    // 1% of the tail budget (relative, or absolute when that is larger)
+    if (tid == 0)
+      s_thr = fmax(tol > 0.0 ? fmax(1e-16, 0.01 * tol * tol) * tr : 0.0,
+                   0.01 * pa_.abs_tol * pa_.abs_tol);
   }
   int r = k;
   for (int j = 0; j < k; ++j) {

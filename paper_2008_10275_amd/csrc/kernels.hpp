@@ -274,12 +274,14 @@ struct PivArgs {
   TruncState st;
   int kcap;
   double tol;
+  double abs_tol;    // absolute tail budget of the truncation (0: none)
 };
 struct JacArgs {
   TruncState st;
   int kcap;
   int max_rounds;
   double tol;        // truncation tolerance (sets the rotation floor)
+  double abs_tol;    // absolute tail budget of the truncation (0: none)
 };
 struct RepArgs {
   TruncState st;

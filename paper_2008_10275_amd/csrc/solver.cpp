@@ -164,8 +164,8 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.g2 = make_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
   p.c2 = CholArgs{st, 2, kcap, eps};
   make_core_gemms(st, core, kcap, p.core);
-  p.piv = PivArgs{st, kcap, tol};
-  p.jac = JacArgs{st, kcap, max_rounds, tol};
+  p.piv = PivArgs{st, kcap, tol, abs_tol};
+  p.jac = JacArgs{st, kcap, max_rounds, tol, abs_tol};
   p.rep = RepArgs{st, kcap};
   SmallGemmArgs fin[3];
   make_finish_gemms(st, kcap, rank_out, fin);
@@ -412,7 +412,8 @@ SpmmLaunch<T> Cheb<T>::spmm_plan(const T* U, int ldu, const int* r_dev) const {
 
 // R = T(B - sum_i K_i S D_i): blocks [B | K_0 S | ... ] and [B_V | D_0 S_V | ...]
 template <class T>
-TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol_, int rank_cap) const {
+TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol_, int rank_cap,
+                                 double abs_tol) const {
   const Ops& o = *P->ops;
   const int ld = ld_for(cap);
   BlockView<T> A{}, Bv{};
@@ -426,7 +427,7 @@ TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol_, 
     add_core(c, S.sv(), -1.0, S.r(), 0);
   }
   return tr.plan(A, o.n, Bv, P->m, c, rank_cap > 0 ? std::min(rank_cap, cap) : cap, tol_, R.u(),
-                 R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev);
+                 R.ld, R.v(), R.ld, R.sv(), R.r(), norm_dev, abs_tol);
 }
 
 // D = T(Z R_V^T / dc) with Z = P^{-1} R_U diag(s_R)
@@ -753,7 +754,7 @@ TruncPlan<double> SolveRun::rhs_plan(const lrc_opts& o, double* const* W0) const
   const int rcap = std::min(B64.cap, 64);
   return c64->tr.plan(A, op.n, B, Pr.m, cv, rcap, std::min(1e-14, o.trunc_tol * 1e-3), B64.u(),
                       B64.ld, B64.v(), B64.ld, B64.sv(), B64.r(), c64->norm.as<double>() + 4,
-                      1e-3 * target);
+                      kResFloor * target);
 }
 
 void SolveRun::alloc_mixed() {

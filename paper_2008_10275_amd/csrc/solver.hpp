@@ -15,6 +15,10 @@
 namespace lrc {
 
 constexpr int kTruncCap = 128;   // max concatenated columns of a truncation
+// Right-hand side and residual truncations drop directions whose total weight
+// stays below this fraction of the absolute residual target: they cannot move
+// the result by more than that.
+constexpr double kResFloor = 1e-3;
 constexpr int kPrecCols = 64;    // max right-hand sides per preconditioner apply
 
 struct Ctx {
@@ -148,7 +152,9 @@ struct Cheb {
   double tol = 0.0;
   SpmmLaunch<T> spmm_plan(const T* U, int ldu, const int* r_dev) const;
   // rank_cap <= 0: the solve's cap
-  TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol, int rank_cap = 0) const;
+  // abs_tol: directions whose total weight stays below it are dropped as well
+  TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol, int rank_cap = 0,
+                          double abs_tol = 0.0) const;
   TruncPlan<T> dstart_plan(double dc) const;
   TruncPlan<T> supd_plan() const;
   TruncPlan<T> dstep_plan(double alpha, double beta) const;
