@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no event timing in the timed region")
     ap.add_argument("--eager", action="store_true",
                     help="timed steps launch every kernel directly (no graph replay)")
+    ap.add_argument("--no-spmm-roofline", action="store_true",
+                    help="skip the SpMM-alone measurement (profiler runs of the solve)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -508,8 +510,8 @@ def main():
 
     last = infos[-1]
     # the SpMM alone at the solution's rank and at the rank cap
-    spmm = spmm_roofline(L, ops, cfg["ops"].K, sorted({max(1, int(last["rank"])),
-                                                      int(cfg["rank_cap"])}), torch)
+    spmm = None if a.no_spmm_roofline else spmm_roofline(
+        L, ops, cfg["ops"].K, sorted({max(1, int(last["rank"])), int(cfg["rank_cap"])}), torch)
     n, m = cfg["ops"].K[0].shape[0], cfg["d"].shape[1]
     line = {
         "metric": "time to rel. residual 1e-6 (s)" if res_tol == 1e-6 else
