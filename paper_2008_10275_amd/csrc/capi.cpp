@@ -105,8 +105,11 @@ void build_levels(Prec& pr, hipStream_t s) {
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
     const int hf = F.height[sn], db = F.depth[sn];
-    blk_f[hf] += double(f) * F.ns[sn];
-    blk_b[db] += double(f) * F.ns[sn];
+    // nonzero entries of the dense blocks: a triangle of ns (ns + 1) / 2 and
+    // the ns x nb rectangle (the products skip the triangle's zeros)
+    const double nz = 0.5 * double(F.ns[sn]) * (F.ns[sn] + 1) + double(F.nb[sn]) * F.ns[sn];
+    blk_f[hf] += nz;
+    blk_b[db] += nz;
     ns_f[hf] += F.ns[sn];
     ns_b[db] += F.ns[sn];
     nin_f[hf] = std::max(nin_f[hf], F.ns[sn]);

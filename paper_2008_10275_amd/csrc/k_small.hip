@@ -73,15 +73,19 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
   const int nwv = nt >> 6;
   if (k == 0) return;
   const int nbk = (k + 15) / 16, kp = nbk * 16;
+  // G is read from global memory once: the scale and the first attempt take it from LDS
+  for (int i = wave; i < k; i += nwv)
+    for (int j = lane; j < k; j += 64) A[i * kCL + j] = G[size_t(i) * kcap + j];
+  __syncthreads();
   if (tid < 64) {
     double gm = 0.0;
-    for (int j = tid; j < k; j += 64) gm = fmax(gm, G[size_t(j) * kcap + j]);
+    for (int j = tid; j < k; j += 64) gm = fmax(gm, A[j * kCL + j]);
     for (int o = 32; o > 0; o >>= 1) gm = fmax(gm, __shfl_xor(gm, o));
     if (tid == 0) s_gm = gm;
   }
   __syncthreads();
   for (int j = tid; j < k; j += nt) {
-    const double g = G[size_t(j) * kcap + j];
+    const double g = A[j * kCL + j];
     dsc[j] = (g > 1e-300 && g > 1e-28 * s_gm) ? 1.0 / sqrt(g) : 0.0;
   }
   __syncthreads();
@@ -96,8 +100,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
       double v;
       if (i < k && j < k) {
         const double di = dsc[i], dj = dsc[j];
-        v = (di == 0.0 || dj == 0.0) ? (i == j ? 1.0 : 0.0)
-                                     : di * G[size_t(i) * kcap + j] * dj + (i == j ? shift : 0.0);
+        const double g = attempt == 0 ? A[i * kCL + j] : G[size_t(i) * kcap + j];
+        v = (di == 0.0 || dj == 0.0) ? (i == j ? 1.0 : 0.0) : di * g * dj + (i == j ? shift : 0.0);
       } else {
         v = i == j ? 1.0 : 0.0;
       }
@@ -109,7 +113,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
       const int o = 16 * I;
       if (wave == 0) {
         // lane c < 16 holds column c of the diagonal block (rows 0..15)
-        double a[16], x[16];
+        // (the reciprocal square root of each pivot scales its row and is the
+        // inverse's diagonal: no division on the dependent chain)
+        double a[16], x[16], rinv[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) a[r] = lc < 16 ? A[(o + r) * kCL + o + lc] : 0.0;
         bool bad = false;
@@ -117,32 +123,35 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
         for (int jj = 0; jj < 16; ++jj) {
           const double piv = lane_bcast(a[jj], jj);
           if (!(piv > tau) && o + jj < k) bad = true;
-          const double rjj = sqrt(fmax(piv, 1e-300));
-          a[jj] = lane == jj ? rjj : (lane > jj ? a[jj] / rjj : a[jj]);
+          const double pv = fmax(piv, 1e-300);
+          const double ri = rsqrt(pv);
+          rinv[jj] = ri;
+          a[jj] = lane == jj ? pv * ri : (lane > jj ? a[jj] * ri : a[jj]);
 #pragma unroll
           for (int ii = jj + 1; ii < 16; ++ii) {
             const double t = lane_bcast(a[jj], ii);     // r_{jj, ii}
             if (lane >= ii) a[ii] -= t * a[jj];
           }
         }
-        // x = column lc of the inverse of the upper-triangular block
+        // R_II back to LDS first: the inverse reads its rows there (one
+        // broadcast load per entry, in the wave's own LDS order)
+        if (lane < 16) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) A[(o + r) * kCL + o + lane] = r <= lane ? a[r] : 0.0;
+        }
+        // x = column lc of the inverse of the upper-triangular block (x[t] = 0
+        // for t > lc; the newest x[t] enters the sum last, which keeps the
+        // dependent chain at one product per row)
 #pragma unroll
         for (int ii = 15; ii >= 0; --ii) {
           double acc = 0.0;
 #pragma unroll
-          for (int tt = ii + 1; tt < 16; ++tt) {
-            const double r = lane_bcast(a[ii], tt);     // r_{ii, tt}
-            acc += (tt <= lane) ? r * x[tt] : 0.0;
-          }
-          const double rii = lane_bcast(a[ii], ii);
-          x[ii] = ii == lane ? 1.0 / rii : (ii < lane ? -acc / rii : 0.0);
+          for (int tt = 15; tt > ii; --tt) acc = fma(A[(o + ii) * kCL + o + tt], x[tt], acc);
+          x[ii] = ii == lane ? rinv[ii] : (ii < lane ? -acc * rinv[ii] : 0.0);
         }
         if (lane < 16) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            A[(o + r) * kCL + o + lane] = r <= lane ? a[r] : 0.0;
-            Tb[I][r][lane] = x[r];
-          }
+          for (int r = 0; r < 16; ++r) Tb[I][r][lane] = x[r];
         }
         if (bad && lane == 0) s_fail = 1;
       }
@@ -414,15 +423,17 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
   bool converged = false;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
     int nrot = 0;
+    // pair slot `lane` of round t: positions lane and kp-1-lane of the rotated
+    // list [0, 1 + (t + i) mod (kp - 1)]; the residues advance by one a round
+    int c0 = lane == 0 ? 0 : lane - 1, c1 = kp - 2 - lane;
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
       const double* H = Hs[cur];
       double* Hn = Hs[cur ^ 1];
       bool rot = false;
+      const int x0 = lane == 0 ? 0 : 1 + c0, x1 = 1 + c1;
+      c0 = c0 + 1 == kp - 1 ? 0 : c0 + 1;
+      c1 = c1 + 1 == kp - 1 ? 0 : c1 + 1;
       if (lane < npair) {
-        // pair slot `lane` of round t: positions lane and kp-1-lane of the
-        // rotated list [0, 1 + (t + i) mod (kp - 1)]
-        const int x0 = lane == 0 ? 0 : 1 + (lane - 1 + t) % (kp - 1);
-        const int x1 = 1 + (kp - 2 - lane + t) % (kp - 1);
         const int p = min(x0, x1), q = max(x0, x1);
         const double hpp = H[pu(p, p, kp)], hqq = H[pu(q, q, kp)], hpq = H[pu(p, q, kp)];
         double c = 1.0, sn = 0.0;

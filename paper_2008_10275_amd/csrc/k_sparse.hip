@@ -333,27 +333,66 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
   const int ldM = FWD ? f : ns;                  // column-major: element (row, i) at i * ldM + row
   const T* __restrict__ In = DIRECT ? nullptr : it.stage + soff[sn] * ldw;
-  // input row i of the product (i < nin)
-  auto in_row = [&](int i) -> const T* {
-    if (!DIRECT) return In + int64_t(i) * ldw;
-    if (FWD) return it.R + int64_t(P.perm[j0 + i]) * it.ldr;
-    return i < ns ? it.y + int64_t(j0 + i) * ldw
-                  : it.x + int64_t(P.bnd[P.bnd_off[sn] + i - ns]) * ldw;
+  const int* __restrict__ bnd = DIRECT && !FWD ? P.bnd + P.bnd_off[sn] : nullptr;
+  // source row number of input i: direct inputs look it up (forward: the
+  // permutation; backward: the boundary list past ns), which the loop fetches
+  // one iteration ahead so that an iteration waits on one round of loads
+  auto in_idx = [&](int i) -> int {
+    if (!DIRECT) return i;
+    if (FWD) return P.perm[j0 + i];
+    return i < ns ? j0 + i : bnd[i - ns];
   };
-  const int chunk = NW == 1 ? nin : (nin + 4 * NW - 1) / (4 * NW) * 4;
-  const int i0 = wv * chunk, i1 = min(nin, i0 + chunk);
+  auto in_row = [&](int i, int idx) -> const T* {
+    if (!DIRECT) return In + int64_t(idx) * ldw;
+    if (FWD) return it.R + int64_t(idx) * it.ldr;
+    return (i < ns ? it.y : it.x) + int64_t(idx) * ldw;
+  };
+  // The diagonal parts of the blocks are triangular (forward: L^-1 on the
+  // first ns rows, backward: U^-1 on the first ns columns), so a task whose
+  // 16 output rows lie in the diagonal part reads only the inputs that meet
+  // the triangle: forward i < row0 + 16, backward i >= row0.
+  const int lo = FWD ? 0 : row0;
+  const int hi = (FWD && row0 + kPT <= ns) ? row0 + kPT : nin;
+  const int chunk = NW == 1 ? hi - lo : (hi - lo + 4 * NW - 1) / (4 * NW) * 4;
+  const int i0 = lo + wv * chunk, i1 = min(hi, i0 + chunk);
   const int orow = row0 + (lane & 15);
   const bool rowok = orow < nout;
   acc_t acc[KTM];
 #pragma unroll
   for (int t = 0; t < KTM; ++t) acc[t] = acc_t{};
+  int nidx[DIRECT ? U : 1];
+  if constexpr (DIRECT) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 4 * u + (lane >> 4);
+      nidx[u] = i < i1 ? in_idx(i) : 0;
+    }
+  }
   for (int kk = i0; kk < i1; kk += 4 * U) {
     T a[U], b[U][KTM];
     const T* rp[U];
+    if constexpr (DIRECT) {
+      int cidx[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = kk + 4 * u + (lane >> 4);
-      rp[u] = i < i1 ? in_row(i) : nullptr;
+      for (int u = 0; u < U; ++u) cidx[u] = nidx[u];
+      if (kk + 4 * U < i1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = kk + 4 * U + 4 * u + (lane >> 4);
+          nidx[u] = i < i1 ? in_idx(i) : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = kk + 4 * u + (lane >> 4);
+        rp[u] = i < i1 ? in_row(i, cidx[u]) : nullptr;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = kk + 4 * u + (lane >> 4);
+        rp[u] = i < i1 ? in_row(i, i) : nullptr;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {

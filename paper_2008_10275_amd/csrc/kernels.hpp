@@ -91,7 +91,7 @@ struct LevelTasks {
   int nin_max;         // longest product input (ns forward, ns + nb backward)
   int direct;          // the products read their inputs at the source (no gather):
                        // every backward level, forward levels without contributions
-  double blk;          // dense block entries the level's products read
+  double blk;          // nonzero dense block entries the level's products read
   int64_t in_rows;     // staged rows the products read (per column)
   int64_t out_rows;    // rows the products write (per column)
 };
