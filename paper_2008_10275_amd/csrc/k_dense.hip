@@ -384,9 +384,22 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(GramRedArgs<T> r0, co
   const bool valid = id < kGN && tbj < KT;
   const int w0 = job == 0 ? 0 : a.nwg0;
   const int nw = job == 0 ? a.nwg0 : a.nwg1;
+  // partials p = grp, grp + 16, ... summed in that order; eight loads are
+  // issued before their additions
   double s = 0.0;
-  if (valid)
-    for (int p = grp; p < nw; p += 16) s += double(partial[(size_t(w0 + p) * kGN + id) * 256 + w]);
+  if (valid) {
+    const T* __restrict__ pp = partial + (size_t(w0) * kGN + id) * 256 + w;
+    constexpr size_t st = size_t(kGN) * 256;
+    int p = grp;
+    for (; p + 16 * 7 < nw; p += 16 * 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[size_t(p + 16 * u) * st];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += double(v[u]);
+    }
+    for (; p < nw; p += 16) s += double(pp[size_t(p) * st]);
+  }
   sh[grp][l] = s;
   __syncthreads();
   if (grp != 0 || !valid) return;
@@ -526,8 +539,10 @@ __device__ __forceinline__ void ts_load(T (&a)[KQ], const ColRef<T>* cols, int k
 }
 
 // NTU (<= NT) output tiles are multiplied; the caller picks NTU from the
-// uniform tile count so that no accumulator update is guarded
-template <class T, int KQ, int NT, int NTU>
+// uniform tile count so that no accumulator update is guarded.  TRI: M is
+// upper triangular (the inverse factor of the first pass), so output tile t
+// takes only the input steps q < 4 (t + 1).
+template <class T, int KQ, int NT, int NTU, bool TRI>
 __device__ __forceinline__ void ts_tile(const T (&a)[KQ], const T* Ms, int kq, int g, int rl,
                                         int lane, int64_t row0, int64_t rows, int r,
                                         T* __restrict__ Y, int64_t ldy) {
@@ -541,7 +556,8 @@ __device__ __forceinline__ void ts_tile(const T (&a)[KQ], const T* Ms, int kq, i
     if (q < kq) {
       const T* br = Ms + (4 * q + g) * S + rl;
 #pragma unroll
-      for (int t = 0; t < NTU; ++t) acc[t] = Mfma<T>::op(a[q], br[16 * t], acc[t]);
+      for (int t = 0; t < NTU; ++t)
+        if (!TRI || q < 4 * (t + 1)) acc[t] = Mfma<T>::op(a[q], br[16 * t], acc[t]);
     }
 #pragma unroll
   for (int t = 0; t < NTU; ++t) {
@@ -557,7 +573,7 @@ __device__ __forceinline__ void ts_tile(const T (&a)[KQ], const T* Ms, int kq, i
 }
 
 // A wave keeps D row tiles in flight in a register ring of D x KQU operands.
-template <class T, int KQU, int NT, int NTU, int D, bool SCALED>
+template <class T, int KQU, int NT, int NTU, int D, bool SCALED, bool TRI>
 __device__ __forceinline__ void ts_rows(const ColRef<T>* cols, const T* Ms, int k, int r,
                                         int64_t t0, int64_t t1, int64_t rows, T* Y, int64_t ldy) {
   const int lane = threadIdx.x & 63;
@@ -578,7 +594,7 @@ __device__ __forceinline__ void ts_rows(const ColRef<T>* cols, const T* Ms, int 
     for (int d = 0; d < D; ++d) {
       const int64_t tt = q + int64_t(d) * nw;
       if (tt < t1) {
-        ts_tile<T, KQU, NT, NTU>(buf[d], Ms, kq, g, rl, lane, tt * 16, rows, r, Y, ldy);
+        ts_tile<T, KQU, NT, NTU, TRI>(buf[d], Ms, kq, g, rl, lane, tt * 16, rows, r, Y, ldy);
         // re-read the column table from LDS rather than keeping it live
         __asm__ volatile("" ::: "memory");
         const int64_t tn = tt + int64_t(D) * nw;
@@ -588,7 +604,7 @@ __device__ __forceinline__ void ts_rows(const ColRef<T>* cols, const T* Ms, int 
   }
 }
 
-template <class T, int KQU, int NT, int D, bool SCALED>
+template <class T, int KQU, int NT, int D, bool SCALED, bool TRI>
 __device__ __forceinline__ void ts_rows_nt(const ColRef<T>* cols, const T* Ms, int k, int r,
                                            int64_t t0, int64_t t1, int64_t rows, T* Y,
                                            int64_t ldy) {
@@ -596,31 +612,31 @@ __device__ __forceinline__ void ts_rows_nt(const ColRef<T>* cols, const T* Ms, i
   // eight output tiles hold 32 accumulators per lane: half the ring depth
   constexpr int D8 = D >= 4 ? D / 2 : D;
   if constexpr (NT >= 8)
-    if (rt > 4) return ts_rows<T, KQU, NT, 8, D8, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+    if (rt > 4) return ts_rows<T, KQU, NT, 8, D8, SCALED, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
   if constexpr (NT >= 4)
-    if (rt > 2) return ts_rows<T, KQU, NT, 4, D, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
-  ts_rows<T, KQU, NT, 2, D, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+    if (rt > 2) return ts_rows<T, KQU, NT, 4, D, SCALED, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+  ts_rows<T, KQU, NT, 2, D, SCALED, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
 }
 
 // The ring holds 2 KQ operands whatever the width: narrow inputs keep more
 // tiles in flight.  (The row-scaled operand is the short V side: one class.)
-template <class T, int KQ, int NT, bool SCALED>
+template <class T, int KQ, int NT, bool SCALED, bool TRI>
 __device__ __forceinline__ void ts_rows_by_width(const ColRef<T>* cols, const T* Ms, int k, int r,
                                                  int64_t t0, int64_t t1, int64_t rows, T* Y,
                                                  int64_t ldy) {
   const int kq = (k + 3) >> 2;
   if constexpr (!SCALED) {
     if constexpr (KQ >= 32) {
-      if (kq <= 8) return ts_rows_nt<T, 8, NT, 8, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
-      if (kq <= 16) return ts_rows_nt<T, 16, NT, 4, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+      if (kq <= 8) return ts_rows_nt<T, 8, NT, 8, false, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+      if (kq <= 16) return ts_rows_nt<T, 16, NT, 4, false, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
     } else {
-      if (kq <= 8) return ts_rows_nt<T, 8, NT, 4, false>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+      if (kq <= 8) return ts_rows_nt<T, 8, NT, 4, false, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
     }
   }
-  ts_rows_nt<T, KQ, NT, 2, SCALED>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
+  ts_rows_nt<T, KQ, NT, 2, SCALED, TRI>(cols, Ms, k, r, t0, t1, rows, Y, ldy);
 }
 
-template <class T, int KQ, int NT, bool SCALED1>
+template <class T, int KQ, int NT, bool SCALED1, bool TRI>
 __global__ __launch_bounds__(kTsThreads) void tsmm_kernel(TsmmArgs<T> a0, const TsmmArgs<T>* ab,
                                                           const int* done) {
   if (done && done[blockIdx.z]) return;
@@ -648,22 +664,26 @@ __global__ __launch_bounds__(kTsThreads) void tsmm_kernel(TsmmArgs<T> a0, const 
   const int64_t per = (nrt + nwg - 1) / nwg;
   const int64_t t0 = int64_t(wg) * per, t1 = min(nrt, t0 + per);
   if (SCALED1 && jb == 1)
-    ts_rows_by_width<T, KQ, NT, true>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
+    ts_rows_by_width<T, KQ, NT, true, TRI>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
   else
-    ts_rows_by_width<T, KQ, NT, false>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
+    ts_rows_by_width<T, KQ, NT, false, TRI>(cols, Ms, k, r, t0, t1, J.rows, J.Y, J.ldy);
 }
 
 template <class T>
 using TsmmFn = void (*)(TsmmArgs<T>, const TsmmArgs<T>*, const int*);
 
-template <class T>
-static TsmmFn<T> tsmm_fn(int kb, int rb, bool sc1) {
+template <class T, bool TRI>
+static TsmmFn<T> tsmm_fn_t(int kb, int rb, bool sc1) {
   if (kb <= 64) {
-    if (rb <= 64) return sc1 ? tsmm_kernel<T, 16, 4, true> : tsmm_kernel<T, 16, 4, false>;
-    return sc1 ? tsmm_kernel<T, 16, 8, true> : tsmm_kernel<T, 16, 8, false>;
+    if (rb <= 64) return sc1 ? tsmm_kernel<T, 16, 4, true, TRI> : tsmm_kernel<T, 16, 4, false, TRI>;
+    return sc1 ? tsmm_kernel<T, 16, 8, true, TRI> : tsmm_kernel<T, 16, 8, false, TRI>;
   }
-  if (rb <= 64) return sc1 ? tsmm_kernel<T, 32, 4, true> : tsmm_kernel<T, 32, 4, false>;
-  return sc1 ? tsmm_kernel<T, 32, 8, true> : tsmm_kernel<T, 32, 8, false>;
+  if (rb <= 64) return sc1 ? tsmm_kernel<T, 32, 4, true, TRI> : tsmm_kernel<T, 32, 4, false, TRI>;
+  return sc1 ? tsmm_kernel<T, 32, 8, true, TRI> : tsmm_kernel<T, 32, 8, false, TRI>;
+}
+template <class T>
+static TsmmFn<T> tsmm_fn(int kb, int rb, bool sc1, bool tri) {
+  return tri ? tsmm_fn_t<T, true>(kb, rb, sc1) : tsmm_fn_t<T, false>(kb, rb, sc1);
 }
 
 static int64_t tsmm_tiles(int64_t rows) { return (std::max<int64_t>(rows, 1) + 15) / 16; }
@@ -673,7 +693,7 @@ static int tsmm_wgs_max(int64_t rows) {
 }
 
 template <class T>
-TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
+TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, bool tri) {
   LRC_CHECK(njobs >= 1 && njobs <= 2, ST_EINVAL, "tsmm: one or two jobs");
   LRC_CHECK(kcap <= kTsKCAP && rcap <= kTsKCAP, ST_EINVAL, "tsmm: capacity exceeded");
   LRC_CHECK(!view_scaled(jobs[0].X), ST_EINVAL, "tsmm: the first operand cannot be row-scaled");
@@ -683,10 +703,11 @@ TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap) {
   l.kb = std::min(kcap, std::max(view_cap(jobs[0].X), njobs > 1 ? view_cap(jobs[1].X) : 0));
   l.rb = rcap;
   l.sc1 = njobs > 1 && view_scaled(jobs[1].X);
+  l.tri = tri;
   // one round of resident workgroups, shared by the jobs in proportion to
   // their row tiles
   const int slots =
-      resident_wgs(reinterpret_cast<const void*>(tsmm_fn<T>(l.kb, l.rb, l.sc1)), kTsThreads);
+      resident_wgs(reinterpret_cast<const void*>(tsmm_fn<T>(l.kb, l.rb, l.sc1, l.tri)), kTsThreads);
   a.job[0] = jobs[0];
   if (njobs == 2) {
     a.job[1] = jobs[1];
@@ -715,7 +736,7 @@ void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s)
   LRC_CHECK(l.kb <= kTsKCAP && l.rb <= kTsKCAP, ST_EINVAL, "tsmm: capacity exceeded");
   ProfScope ps(kcls(K_TSMM, is_f32<T>()), s, l.work);
   const dim3 grid(l.grid, 1, b.n), blk(kTsThreads);
-  tsmm_fn<T>(l.kb, l.rb, l.sc1)<<<grid, blk, 0, s>>>(l.a, b.dev, b.done);
+  tsmm_fn<T>(l.kb, l.rb, l.sc1, l.tri)<<<grid, blk, 0, s>>>(l.a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 
@@ -723,8 +744,8 @@ template <class T>
 void launch_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, hipStream_t s) {
   enqueue_tsmm(make_tsmm(jobs, njobs, kcap, rcap), Batched<TsmmArgs<T>>(), s);
 }
-template TsmmLaunch<float> make_tsmm<float>(const TsmmJob<float>*, int, int, int);
-template TsmmLaunch<double> make_tsmm<double>(const TsmmJob<double>*, int, int, int);
+template TsmmLaunch<float> make_tsmm<float>(const TsmmJob<float>*, int, int, int, bool);
+template TsmmLaunch<double> make_tsmm<double>(const TsmmJob<double>*, int, int, int, bool);
 template void enqueue_tsmm<float>(const TsmmLaunch<float>&, Batched<TsmmArgs<float>>, hipStream_t);
 template void enqueue_tsmm<double>(const TsmmLaunch<double>&, Batched<TsmmArgs<double>>,
                                    hipStream_t);

@@ -230,10 +230,11 @@ struct TsmmLaunch {
   int kb = 0;        // host bound of the input width (selects the register class)
   int rb = 0;        // host bound of the output width
   bool sc1 = false;
+  bool tri = false;  // M upper triangular: the products skip its zero blocks
   Work work;
 };
 template <class T>
-TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap);
+TsmmLaunch<T> make_tsmm(const TsmmJob<T>* jobs, int njobs, int kcap, int rcap, bool tri = false);
 template <class T>
 void enqueue_tsmm(const TsmmLaunch<T>& l, Batched<TsmmArgs<T>> b, hipStream_t s);
 

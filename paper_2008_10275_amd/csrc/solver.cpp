@@ -157,7 +157,8 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.c1 = CholArgs{st, 1, kcap, eps};
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
   // the first pass writes st.k <= min(kcap, width bound) columns
-  p.t1 = make_tsmm<T>(t1, 2, kcap, std::min(kcap, std::max(view_cap(A), view_cap(B))));
+  // (T1 = D R1^{-1} is upper triangular)
+  p.t1 = make_tsmm<T>(t1, 2, kcap, std::min(kcap, std::max(view_cap(A), view_cap(B))), true);
   BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
   va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
@@ -205,7 +206,8 @@ static void merge_gram(GramLaunch<T>& a, const GramLaunch<T>& b) {
 }
 template <class T>
 static void merge_tsmm(TsmmLaunch<T>& a, const TsmmLaunch<T>& b) {
-  LRC_CHECK(a.sc1 == b.sc1, ST_EINVAL, "batched truncation: items differ in operand structure");
+  LRC_CHECK(a.sc1 == b.sc1 && a.tri == b.tri, ST_EINVAL,
+            "batched truncation: items differ in operand structure");
   a.grid = std::max(a.grid, b.grid);
   a.kb = std::max(a.kb, b.kb);
   a.rb = std::max(a.rb, b.rb);
