@@ -438,10 +438,17 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
         const double hpp = H[pu(p, p, kp)], hqq = H[pu(q, q, kp)], hpq = H[pu(p, q, kp)];
         double c = 1.0, sn = 0.0;
         if (fabs(hpq) > floor_abs) {
-          const double zeta = (hqq - hpp) / (2.0 * hpq);
-          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          sn = c * tt;
+          // the rotation of angle |theta| <= pi/4 with tan 2 theta = 2 h_pq / (h_qq - h_pp),
+          // from the half-angle formulas: cos 2 theta = |d| / rho >= 0,
+          // sin 2 theta = sign(d) e / rho, c = sqrt((1 + cos 2 theta) / 2),
+          // s = sin 2 theta / (2 c)  (two reciprocal square roots, no division)
+          const double d = hqq - hpp, e = 2.0 * hpq;
+          const double ri = rsqrt(fma(d, d, e * e));
+          const double c2 = fabs(d) * ri, s2 = (d >= 0.0 ? e : -e) * ri;
+          const double h = 0.5 + 0.5 * c2;
+          const double hi = rsqrt(h);
+          c = h * hi;
+          sn = 0.5 * s2 * hi;
           rot = true;
         }
         csw[wave][lane] = make_double2(c, sn);
