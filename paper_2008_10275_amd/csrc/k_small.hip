@@ -264,57 +264,105 @@ void enqueue_chol(const CholArgs& a, Batched<CholArgs> b, hipStream_t s) {
 
 // ============================================================== small products
 // C = op(A) diag(mid) op(B)[:, colperm] diag(colscale), all k x k (or k x r
-// output columns), fp64, ld kcap.  One 16 x 16 output tile per workgroup.
+// output columns), fp64, ld kcap.  One 16 x 16 output tile per workgroup: the
+// tile's 16-row panel of op(A) and 16-column panel of op(B) (inner length at
+// most 128) are staged in LDS with one round of loads, each coalesced along
+// the index that is contiguous in memory, and every thread then sums its
+// entry over the whole inner length.
 __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs a0, const SmallGemmArgs* ab,
                                                          const int* done) {
-  __shared__ double As[16][17];
-  __shared__ double Bs[16][17];
+  __shared__ double As[16][SK + 1];
+  __shared__ double Bs[SK][17];
   __shared__ double mid[SK];
   // blockIdx.z = item * 2 + job
   const int item = blockIdx.z >> 1;
   if (done && done[item]) return;
   const SmallGemmArgs& a = ab ? ab[item] : a0;
   if (int(blockIdx.z & 1) >= a.njobs) return;
-  const SmallGemm& g = a.g[blockIdx.z & 1];
+  const SmallGemm g = a.g[blockIdx.z & 1];   // by value: fields read once
   const int k = *a.k;
   const int ncols = g.ncols_dev ? *g.ncols_dev : k;
   const int kin = g.inner_dev ? *g.inner_dev : k;
   const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
   if (ti >= k || tj >= ncols) return;
+  const int tid = threadIdx.x;
   if (g.use_core) {
     int off = 0;
     for (int b = 0; b < a.core.nb; ++b) {
       const int w = core_width(a.core, b);
-      for (int c = threadIdx.x; c < w && off + c < SK; c += blockDim.x)
+      for (int c = tid; c < w && off + c < SK; c += blockDim.x)
         mid[off + c] = a.core.coef[b] * (a.core.s[b] ? a.core.s[b][c] : 1.0);
       off += w;
     }
   }
-  const int li = threadIdx.x / 16, lj = threadIdx.x & 15;
-  const int i = ti + li, j = tj + lj;
-  const int jc = (j < ncols) ? (g.colperm ? g.colperm[j] : j) : 0;
-  double acc = 0.0;
-  for (int p0 = 0; p0 < kin; p0 += 16) {
-    __syncthreads();
-    {
-      const int p = p0 + lj;
-      double v = 0.0;
-      if (i < k && p < kin) v = g.transA ? g.A[size_t(p) * a.kcap + i] : g.A[size_t(i) * a.kcap + p];
-      As[li][lj] = v;
-      const int pb = p0 + li;
-      double w = 0.0;
-      if (pb < kin && j < ncols) w = g.transB ? g.B[size_t(jc) * a.kcap + pb] : g.B[size_t(pb) * a.kcap + jc];
-      if (g.use_core && pb < kin) w *= mid[pb];
-      Bs[li][lj] = w;
+  const int kc = a.kcap;
+  const double* __restrict__ Ap = g.A;
+  const double* __restrict__ Bp = g.B;
+  const int* __restrict__ cp = g.colperm;
+  const bool ta = g.transA != 0, tb = g.transB != 0;
+  // eight entries of each panel per thread; indices are clamped inside the
+  // leading blocks the producers wrote (finite values), so that every load is
+  // issued at once, and entries outside the operands are zeroed by a product
+  // with a 0/1 mask (a select would let the compiler move each load into a
+  // branch of its own and wait for it there)
+  constexpr int PE = 16 * SK / 256;
+  double va[PE], vb[PE];
+  if (kin > 0) {
+    // the column permutation first (its loads together, outside the panel loop)
+    int jcs[PE];
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = tid + 256 * u;
+      jcs[u] = min(tj + (tb ? e / SK : (e & 15)), ncols - 1);
+    }
+    if (cp) {
+#pragma unroll
+      for (int u = 0; u < PE; ++u) jcs[u] = cp[jcs[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = tid + 256 * u;
+      const int li = ta ? (e & 15) : e / SK, pa = ta ? (e >> 4) : e % SK;
+      const int i = ti + li;
+      const int ic = min(i, k - 1), pc = min(pa, kin - 1);
+      const double x = ta ? Ap[size_t(pc) * kc + ic] : Ap[size_t(ic) * kc + pc];
+      va[u] = x * ((i < k && pa < kin) ? 1.0 : 0.0);
+      const int lj = tb ? e / SK : (e & 15), pb = tb ? e % SK : (e >> 4);
+      const int j = tj + lj;
+      const int qc = min(pb, kin - 1), jc = jcs[u];
+      const double y = tb ? Bp[size_t(jc) * kc + qc] : Bp[size_t(qc) * kc + jc];
+      vb[u] = y * ((pb < kin && j < ncols) ? 1.0 : 0.0);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PE; ++u) va[u] = vb[u] = 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < PE; ++u) {
+    const int e = tid + 256 * u;
+    As[ta ? (e & 15) : e / SK][ta ? (e >> 4) : e % SK] = va[u];
+    Bs[tb ? e % SK : (e >> 4)][tb ? e / SK : (e & 15)] = vb[u];
+  }
+  __syncthreads();
+  if (g.use_core) {
+    for (int e = tid; e < 16 * SK; e += 256) {
+      const int lj = e & 15, p = e >> 4;
+      if (p < kin) Bs[p][lj] *= mid[p];
     }
     __syncthreads();
+  }
+  const int li = tid >> 4, lj = tid & 15;
+  const int i = ti + li, j = tj + lj;
+  double acc = 0.0;
+  // (entries past the inner length were staged as zeros)
+  for (int p0 = 0; p0 < kin; p0 += 16) {
 #pragma unroll
-    for (int p = 0; p < 16; ++p) acc += As[li][p] * Bs[p][lj];
+    for (int q = 0; q < 16; ++q) acc += As[li][p0 + q] * Bs[p0 + q][lj];
   }
   if (i < k && j < ncols) {
     if (g.colscale) acc *= g.colscale[j];
     const int io = g.rowperm ? g.rowperm[i] : i;
-    g.C[size_t(io) * a.kcap + j] = acc;
+    g.C[size_t(io) * kc + j] = acc;
   }
 }
 
@@ -745,8 +793,10 @@ void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, Smal
 // W = M V (columns: M v_j = sigma_j u_j); sigma_j = ||W[:, j]||; order by
 // decreasing sigma; r' = min(cap, smallest r with tail <= tol * ||sigma||).
 // Then XA = R2i_A * W[:, order] diag(1/sigma), XB = R2i_B * V[:, order].
-__global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* ab,
-                                                     const int* done) {
+constexpr int kSelThreads = 1024;
+constexpr int kSelRG = kSelThreads / SK;   // row groups of the column norms
+__global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a0, const SelArgs* ab,
+                                                             const int* done) {
   LRC_ITEM(SelArgs, sa_, a0, ab, done)
   const TruncState& st = sa_.st;
   const int kcap = sa_.kcap, rank_cap = sa_.rank_cap;
@@ -759,6 +809,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* 
   __shared__ int ord[SK];
   __shared__ int rsel;
   __shared__ double om[SK], nu[SK];
+  __shared__ double pw[kSelRG][SK], pv[kSelRG][SK];
   __shared__ double s_lfloor;
   const int kr = *st.k;          // rows of W and VP
   const int k = *st.kj;          // candidate singular directions
@@ -773,13 +824,28 @@ __global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* 
   // sigma_j = ||M VP_j|| / ||VP_j|| (= lambda_j / sqrt(lambda_j)) is the more
   // accurate value where lambda_j is well above the Jacobi floor; at the
   // rounding level both norms are noise, and sqrt(lambda_j) is used instead.
+  // column norms of W and VP: row group g sums rows g, g + kSelRG, ...; the
+  // groups are added in a fixed order
+  {
+    const int j = tid % SK, grp = tid / SK;
+    double a = 0.0, b = 0.0;
+    if (j < k)
+      for (int i = grp; i < kr; i += kSelRG) {
+        const double w = st.W[size_t(i) * kcap + j];
+        const double v = st.VP[size_t(i) * kcap + j];
+        a += w * w;
+        b += v * v;
+      }
+    pw[grp][j] = a;
+    pv[grp][j] = b;
+  }
+  __syncthreads();
   for (int j = tid; j < k; j += blockDim.x) {
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < kr; ++i) {
-      const double w = st.W[size_t(i) * kcap + j];
-      const double v = st.VP[size_t(i) * kcap + j];
-      a += w * w;
-      b += v * v;
+#pragma unroll
+    for (int g = 0; g < kSelRG; ++g) {
+      a += pw[g][j];
+      b += pv[g][j];
     }
     om[j] = sqrt(a);
     nu[j] = sqrt(b);
@@ -832,7 +898,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelArgs a0, const SelArgs* 
 
 void enqueue_select(const SelArgs& a, Batched<SelArgs> b, hipStream_t s) {
   ProfScope ps(kcls(K_SELECT, false), s);
-  hipLaunchKernelGGL(select_kernel, dim3(1, 1, b.n), dim3(256), 0, s, a, b.dev, b.done);
+  hipLaunchKernelGGL(select_kernel, dim3(1, 1, b.n), dim3(kSelThreads), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 
