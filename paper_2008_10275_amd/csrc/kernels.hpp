@@ -94,6 +94,8 @@ struct LevelTasks {
   double blk;          // nonzero dense block entries the level's products read
   int64_t in_rows;     // staged rows the products read (per column)
   int64_t out_rows;    // rows the products write (per column)
+  int xdead;           // backward: every supernode of the level is a leaf, so
+                       // its rows of x are never read (only Z is written)
 };
 
 template <class T>
