@@ -57,7 +57,7 @@ bool same_structure(const SupernodalFactor& a, const SupernodalFactor& b) {
   return a.n == b.n && a.nsn == b.nsn && a.perm == b.perm && a.j0 == b.j0 && a.ns == b.ns &&
          a.nb == b.nb && a.bnd_off == b.bnd_off && a.bnd == b.bnd && a.fw_off == b.fw_off &&
          a.bw_off == b.bw_off && a.front_off == b.front_off && a.cb_off == b.cb_off &&
-         a.asm_ptr == b.asm_ptr && a.asm_src == b.asm_src;
+         a.asm_ptr == b.asm_ptr && a.asm_src == b.asm_src && a.height == b.height;
 }
 
 struct GraphExec {

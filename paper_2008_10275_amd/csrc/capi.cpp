@@ -100,7 +100,8 @@ void build_levels(Prec& pr, hipStream_t s) {
   std::vector<double> blk_f(F.nlev_fwd, 0.0), blk_b(F.nlev_bwd, 0.0);
   std::vector<int64_t> ns_f(F.nlev_fwd, 0), ns_b(F.nlev_bwd, 0);
   std::vector<int> nin_f(F.nlev_fwd, 0), nin_b(F.nlev_bwd, 0);
-  std::vector<int> contrib_f(F.nlev_fwd, 0), inner_b(F.nlev_bwd, 0);
+  std::vector<int> contrib_f(F.nlev_fwd, 0);
+  std::vector<int64_t> out_b(F.nlev_bwd, 0);
   std::vector<std::vector<GatherRow>> gf(F.nlev_fwd), gb(F.nlev_bwd);
   for (int sn = 0; sn < F.nsn; ++sn) {
     const int f = F.ns[sn] + F.nb[sn];
@@ -112,7 +113,8 @@ void build_levels(Prec& pr, hipStream_t s) {
     blk_b[db] += nz;
     ns_f[hf] += F.ns[sn];
     ns_b[db] += F.ns[sn];
-    if (F.height[sn] > 0) inner_b[db] = 1;   // its x rows are boundaries of deeper fronts
+    // x rows only for supernodes with children (they are boundaries of deeper fronts)
+    out_b[db] += int64_t(F.height[sn] > 0 ? 2 : 1) * F.ns[sn];
     nin_f[hf] = std::max(nin_f[hf], F.ns[sn]);
     nin_b[db] = std::max(nin_b[db], f);
     for (int r0 = 0; r0 < f; r0 += TR) ft[hf].push_back(make_int2(sn, r0));
@@ -156,15 +158,13 @@ void build_levels(Prec& pr, hipStream_t s) {
   pr.bwd.clear();
   // forward products read the ns own rows of each front and write all f rows;
   // backward products read all f rows and write the ns own rows twice (x, Z),
-  // once (Z) on levels of leaves only
+  // once (Z) for leaves
   for (size_t l = 0; l < ft.size(); ++l)
     pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size()),
-                      gbase + gfo[l], nin_f[l], contrib_f[l] ? 0 : 1, blk_f[l], ns_f[l], lf[l],
-                      0});
+                      gbase + gfo[l], nin_f[l], contrib_f[l] ? 0 : 1, blk_f[l], ns_f[l], lf[l]});
   for (size_t l = 0; l < bt.size(); ++l)
     pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size()),
-                      gbase + gbo[l], nin_b[l], 1, blk_b[l], lb[l],
-                      (inner_b[l] ? 2 : 1) * ns_b[l], inner_b[l] ? 0 : 1});
+                      gbase + gbo[l], nin_b[l], 1, blk_b[l], lb[l], out_b[l]});
   LRC_HIP(hipStreamSynchronize(s));
 }
 
@@ -183,6 +183,12 @@ void upload_prec(Prec& pr, hipStream_t s) {
   pr.asm_src = upload(F.asm_src, s);
   pr.bnd_off = upload(F.bnd_off, s);
   pr.bnd = upload(F.bnd, s);
+  {
+    std::vector<int> leaf(size_t(F.nsn));
+    for (int sn = 0; sn < F.nsn; ++sn) leaf[sn] = F.height[sn] == 0 ? 1 : 0;
+    pr.leaf = upload(leaf, s);
+    LRC_HIP(hipStreamSynchronize(s));   // leaf is a temporary
+  }
   pr.fw64 = upload(F.fw, s);
   pr.bw64 = upload(F.bw, s);
   {
@@ -213,6 +219,7 @@ void upload_prec(Prec& pr, hipStream_t s) {
     P.bw = static_cast<const TT*>(bw);
     P.soff_fwd = pr.soff_fwd.as<int64_t>();
     P.soff_bwd = pr.soff_bwd.as<int64_t>();
+    P.leaf = pr.leaf.as<int>();
   };
   build_levels(pr, s);
   fill(pr.p64, pr.fw64.p, pr.bw64.p);

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __res
 template <class T, bool FWD, int NW, int KTM, bool DIRECT, int U>
 __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     PrecDev<T> P, const int2* __restrict__ tasks, int ntasks, const int64_t* __restrict__ soff,
-    PrecItem<T> a0, const PrecItem<T>* ab, const int* done, int ldw, int xdead) {
+    PrecItem<T> a0, const PrecItem<T>* ab, const int* done, int ldw) {
   typedef typename PMfma<T>::acc_t acc_t;
   constexpr int WPB = NW > 4 ? NW : 4;    // waves per workgroup
   constexpr int TPB = WPB / NW;           // tasks per workgroup
@@ -328,6 +328,7 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   const int sn = task.x, row0 = task.y;
   const int k = it.k_dev ? *it.k_dev : it.k_const;
   const int ns = P.ns[sn], f = ns + P.nb[sn], j0 = P.j0[sn];
+  const int leaf = FWD ? 0 : P.leaf[sn];
   const int nin = FWD ? ns : f;
   const int nout = FWD ? f : ns;
   const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
       if (row < ns) it.y[int64_t(j0 + row) * ldw + c] = v;
       else it.cb[(P.cb_off[sn] + row - ns) * ldw + c] = DIRECT ? v : v + In[int64_t(row) * ldw + c];
     } else {
-      if (!xdead) it.x[int64_t(j0 + row) * ldw + c] = v;
+      if (!leaf) it.x[int64_t(j0 + row) * ldw + c] = v;
       it.Z[int64_t(P.perm[j0 + row]) * it.ldz + c] = v;
     }
   };
@@ -490,10 +491,10 @@ static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const
   do {                                                                                            \
     if (L.direct)                                                                                 \
       hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, true, U>), grid, blk, 0, s, P,       \
-                         L.tasks, L.count, soff, it, b.dev, b.done, ldw, L.xdead);                \
+                         L.tasks, L.count, soff, it, b.dev, b.done, ldw);                         \
     else                                                                                          \
       hipLaunchKernelGGL((prec_product_kernel<T, FWD, NW, KT, false, U>), grid, blk, 0, s, P,      \
-                         L.tasks, L.count, soff, it, b.dev, b.done, ldw, L.xdead);                \
+                         L.tasks, L.count, soff, it, b.dev, b.done, ldw);                         \
   } while (0)
   switch (KTM) {
     case 1: LRC_PP(1); break;

@@ -94,8 +94,6 @@ struct LevelTasks {
   double blk;          // nonzero dense block entries the level's products read
   int64_t in_rows;     // staged rows the products read (per column)
   int64_t out_rows;    // rows the products write (per column)
-  int xdead;           // backward: every supernode of the level is a leaf, so
-                       // its rows of x are never read (only Z is written)
 };
 
 template <class T>
@@ -117,6 +115,8 @@ struct PrecDev {
   const T* bw;
   const int64_t* soff_fwd;   // staging row offset of each supernode in its forward level
   const int64_t* soff_bwd;   // ... in its backward level
+  const int* leaf;           // 1: the supernode has no children, so no front reads
+                             // its rows of the permuted solution x (backward)
 };
 
 // Z = P^{-1} R  (R, Z: n x k row-major; k read from k_dev or k_const, <= kcap <= 64).

@@ -47,7 +47,7 @@ struct Ops {
 // supernodal factor of the preconditioner on the device
 struct Prec {
   SupernodalFactor F;   // host copy (blocks freed after upload)
-  DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd;
+  DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd, leaf;
   DevBuf fw64, bw64, fw32, bw32;
   DevBuf fwd_tasks, bwd_tasks, soff_fwd, soff_bwd, grows;
   std::vector<LevelTasks> fwd, bwd;
