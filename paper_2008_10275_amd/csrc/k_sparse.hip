@@ -321,7 +321,11 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   if (done && done[blockIdx.z]) return;
   const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tk = blockIdx.x * TPB + wave / NW;   // uniform per workgroup when NW > 1
+  // workgroups are dealt to the 8 XCDs in turn (w -> XCD w % 8): the grid (a
+  // multiple of 8) gives XCD x the contiguous eighth x of the task range, so
+  // that the tasks of one supernode, which all read its input rows, share an L2
+  const int bx = int(blockIdx.x & 7) * int(gridDim.x >> 3) + int(blockIdx.x >> 3);
+  const int tk = bx * TPB + wave / NW;   // uniform per workgroup when NW > 1
   if (tk >= ntasks) return;
   const int wv = wave % NW;
   const int2 task = tasks[tk];
@@ -541,7 +545,8 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
         const int NW = (L.nin_max <= 64 || (wide && L.nin_max <= 256)) ? 1
                        : L.nin_max <= 256 ? 4 : L.nin_max <= 512 ? 8 : 16;
         const int tpb = NW == 1 ? 4 : 1;
-        const dim3 grid(unsigned(ceil_div(L.count, tpb)), 1, b.n), blk(NW > 4 ? 64 * NW : 256);
+        const dim3 grid(unsigned(round_up(ceil_div(L.count, tpb), 8)), 1, b.n),
+            blk(NW > 4 ? 64 * NW : 256);
         const int64_t* so = fw ? P.soff_fwd : P.soff_bwd;
         if (fw) {
           if (NW == 1) launch_product_nw<T, true, 1>(KTM, grid, blk, s, P, L, so, it, b, ldw);
