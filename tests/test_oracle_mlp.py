@@ -80,3 +80,50 @@ def test_pod_basis_projection_error_is_svd_tail():
     assert np.allclose(U0.T @ U0, np.eye(5), atol=1e-12)
     err = np.linalg.norm(S - U0 @ (U0.T @ S))
     assert np.isclose(err, np.sqrt(np.sum(s[5:] ** 2)), rtol=1e-8)
+
+
+def test_normalise_inputs_hand_values():
+    """The affine map sends each range's ends to -1 and +1 and its midpoint to 0
+    (values worked out by hand)."""
+    mu = np.array([0.5e4, 1.25e4, 2.0e4, 0.875e4])
+    lam = np.array([4.0e4, 2.5e4, 1.0e4, 1.75e4])
+    X = mlp.normalise_inputs(mu, lam, (0.5e4, 2.0e4), (1.0e4, 4.0e4))
+    assert X.shape == (4, 2)
+    assert np.allclose(X[:, 0], [-1.0, 0.0, 1.0, -0.5], rtol=0, atol=1e-15)
+    assert np.allclose(X[:, 1], [1.0, 0.0, -1.0, -0.5], rtol=0, atol=1e-15)
+
+
+def test_standardise_population_deviation_and_zero_spread():
+    """Per-column mean and population (ddof = 0) deviation; a constant column
+    gets deviation 1 so that it maps to zeros.  Hand-computed: column 0 of
+    [1, 3, 5, 7] has mean 4 and deviation sqrt(5); column 1 is constant 2."""
+    C = np.array([[1.0, 2.0], [3.0, 2.0], [5.0, 2.0], [7.0, 2.0]])
+    Z, mu, sd = mlp.standardise(C)
+    assert np.allclose(mu, [4.0, 2.0], rtol=0, atol=1e-15)
+    assert np.allclose(sd, [np.sqrt(5.0), 1.0], rtol=1e-15)
+    assert np.allclose(Z[:, 0], np.array([-3.0, -1.0, 1.0, 3.0]) / np.sqrt(5.0), rtol=1e-15)
+    assert np.all(Z[:, 1] == 0.0)
+    # a sample (ddof = 1) deviation would give sqrt(20 / 3) instead
+    assert not np.isclose(sd[0], np.sqrt(20.0 / 3.0))
+
+
+def test_adam_sequence_matches_torch_optimizer():
+    """Five bias-corrected Adam steps against torch.optim.Adam (a library
+    implementation of the same update) on changing gradients: a wrong second
+    moment or bias correction at t >= 2 shows up here, not at t = 1."""
+    rng = np.random.default_rng(8)
+    params = [rng.standard_normal((3, 2)), rng.standard_normal(3)]
+    grads_seq = [[rng.standard_normal((3, 2)) * (t + 1), rng.standard_normal(3) / (t + 1)]
+                 for t in range(5)]
+    opt = mlp.Adam(params, lr=1e-2, beta1=0.8, beta2=0.95, eps=1e-6)
+    tp = [torch.tensor(p, requires_grad=True) for p in params]
+    topt = torch.optim.Adam(tp, lr=1e-2, betas=(0.8, 0.95), eps=1e-6)
+    cur = params
+    for g in grads_seq:
+        cur = opt.step(cur, g)
+        topt.zero_grad()
+        for t, gg in zip(tp, g):
+            t.grad = torch.tensor(gg)
+        topt.step()
+        for a, t in zip(cur, tp):
+            assert np.allclose(a, t.detach().numpy(), rtol=1e-12, atol=1e-15)

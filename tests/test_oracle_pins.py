@@ -242,6 +242,74 @@ def test_planted_low_rank_solution_is_recovered():
     assert np.sum(sv > 1e-8 * sv[0]) == r
 
 
+def test_mean_parameters_asymmetric_table():
+    """On a skewed table the arithmetic mean (the configured centre) and the
+    midrange (Sec. 4.2) differ; both are worked out by hand."""
+    d = np.array([[1.0, 1.0, 1.0, 1.0], [1.0, 2.0, 3.0, 10.0], [4.0, 4.0, 5.0, 7.0]])
+    assert np.allclose(ch.mean_parameters(d), [1.0, 4.0, 5.0], rtol=0, atol=1e-15)
+    assert np.allclose(ch.mean_parameters(d, "midrange"), [1.0, 5.5, 5.5], rtol=0, atol=1e-15)
+
+
+def test_chebyshev_interval_asymmetric_table_hand_values():
+    """Interval from the ratios d_ij / dbar_i and 1 (hand-computed): with the
+    means (1, 4, 5) the ratios span [1/4, 10/4], so c = 1.125, d = 1.375."""
+    d = np.array([[1.0, 1.0, 1.0, 1.0], [1.0, 2.0, 3.0, 10.0], [4.0, 4.0, 5.0, 7.0]])
+    c, dc = ch.chebyshev_interval(d, ch.mean_parameters(d))
+    assert np.isclose(c, 1.125, rtol=1e-15) and np.isclose(dc, 1.375, rtol=1e-15)
+
+
+def test_chebyshev_interval_skewed_grid_encloses_dense_spectrum():
+    """A parameter grid clustered at one end (mean far from the midrange): the
+    interval built from the mean preconditioner encloses every column's dense
+    generalised spectrum, and its ends are attained to within 10%."""
+    ops = three_term_2d(13)
+    mu, lam = grid_params_little_endian(np.array([0.5, 0.55, 0.6, 2.0]) * 1e4,
+                                        np.array([1.0, 1.1, 4.0]) * 1e4)
+    d = param_table(mu, lam)
+    dbar = ch.mean_parameters(d)
+    assert not np.allclose(dbar, ch.mean_parameters(d, "midrange"))
+    c, dc = ch.chebyshev_interval(d, dbar)
+    P = ch.mean_preconditioner(ops.K, dbar).toarray()
+    lo, hi = np.inf, -np.inf
+    for j in range(d.shape[1]):
+        ev = sla.eigvals(lr.column_operator(ops.K, d, j).toarray(), P)
+        assert np.all(ev.real >= dc - c - 1e-8) and np.all(ev.real <= dc + c + 1e-8)
+        lo, hi = min(lo, ev.real.min()), max(hi, ev.real.max())
+    assert hi >= dc + c - 0.1 * 2 * c and lo <= dc - c + 0.1 * 2 * c
+
+
+@pytest.mark.parametrize("iters", [4, 5])
+def test_chebyshev_restart_is_product_of_polynomials(iters):
+    """Restarting every 2 updates without truncation: the recurrence starts
+    again from the current iterate, so after cycles of lengths l_1, l_2, ...
+    each eigencomponent's residual is the product of the scaled Chebyshev
+    polynomials T_l((d - lam)/c) / T_l(d/c) of the cycles."""
+    K, d, rng = _diag_problem(seed=4)
+    n, m = K[0].shape[0], d.shape[1]
+    dbar = d.mean(axis=1)
+    P = ch.mean_preconditioner(K, dbar)
+    lam = np.array([[(K[0][p, p] + d[1, j] * K[1][p, p]) / P[p, p] for j in range(m)]
+                    for p in range(n)])
+    c, dc = 0.5 * (lam.max() - lam.min()) * 1.1, 0.5 * (lam.max() + lam.min())
+    B = (rng.standard_normal((n, 2)), np.eye(2), rng.standard_normal((m, 2)))
+    S, info = ch.chebyshev_t(K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap=1000,
+                             trunc_tol=0.0, res_tol=0.0, ref_norm=1.0, restart=2,
+                             max_iter=iters)
+    assert info.iters == iters
+    R0 = lr.lr_dense(*B)
+    Rk = R0 - lr.apply_L_dense(K, d, lr.lr_dense(*lr.usv(*S)))
+
+    def p(l):
+        e = np.zeros(l + 1)
+        e[l] = 1.0
+        return npcheb.chebval((dc - lam) / c, e) / npcheb.chebval(dc / c, e)
+
+    poly = p(2) * p(2) * (p(1) if iters == 5 else 1.0)
+    assert np.allclose(Rk, poly * R0, rtol=1e-9, atol=1e-12 * np.abs(R0).max())
+    # a single unrestarted cycle of the same length gives a different residual
+    assert not np.allclose(poly, p(iters), rtol=1e-3)
+
+
 # ------------------------------------------------------------------ Newton driver
 def test_median_rhs_equals_dense_definition_and_rank():
     K, d, _ = _tiny(N=6, m=8)
