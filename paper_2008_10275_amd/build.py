@@ -33,8 +33,20 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src, obj, headers_mtime):
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < headers_mtime
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only objects older than their
+    source or than any header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
+    hdr = [os.path.join(r, f) for d in (CSRC, os.path.join(os.path.dirname(HERE), "include"))
+           for r, _, fs in os.walk(d) for f in fs if f.endswith((".h", ".hpp"))]
+    hmt = max(os.path.getmtime(h) for h in hdr)
     jobs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.basename(src).replace(".cpp", ".host.o"))
@@ -43,8 +55,9 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         jobs.append(["hipcc", *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
-        for r in ex.map(_run, jobs):
+    todo = [j for j in jobs if not incremental or _stale(j[-3], j[-1], hmt)]
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(8, len(todo)))) as ex:
+        for r in ex.map(_run, todo):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr, file=sys.stderr)
     objs = [j[-1] for j in jobs]
@@ -55,4 +68,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

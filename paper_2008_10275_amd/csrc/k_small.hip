@@ -1,8 +1,8 @@
 // Small fp64 kernels of the truncation (k x k with k <= 128): equilibrated,
 // shift-guarded Cholesky of a Gram matrix with the inverse of its factor,
-// small matrix products, the symmetric eigen-decomposition of the core's Gram
-// by parallel two-sided Jacobi (rotations logged, then replayed per row), and
-// the rank selection.
+// small matrix products, the SVD of the core (pivoted Householder QR, then
+// one-sided Jacobi on R^T, with the rotations logged and replayed per row when
+// they do not fit in LDS), and the rank selection.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -16,7 +16,6 @@ namespace lrc {
   const Type& name = (ab) ? (ab)[blockIdx.z] : (a0);
 
 constexpr int SK = 128;                         // capacity of the small kernels
-constexpr int SKP = SK * (SK + 1) / 2;          // packed upper triangle
 
 
 // ============================================================== Cholesky + inverse
@@ -29,9 +28,6 @@ constexpr int SKP = SK * (SK + 1) / 2;          // packed upper triangle
 // X R^-1 well conditioned for the second pass.  Columns whose Gram diagonal
 // vanishes are treated as absent.  R^-1 by 16 x 16 blocks.  Outputs (ld = kcap):
 //   Rout = R D^{-1}   (so that X = Q Rout),  Tout = D R^{-1}  (so that Q = X Tout).
-__device__ inline int pu(int i, int j, int k) {   // packed upper by rows, i <= j
-  return i * k - (i * (i - 1)) / 2 + (j - i);
-}
 
 constexpr int kCholThreads = 512;
 constexpr int kCL = SK + 1;   // row stride of the k x k matrix in LDS
@@ -385,7 +381,7 @@ void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStr
   LRC_HIP(hipGetLastError());
 }
 
-// ============================================================== Jacobi
+// ============================================================== one-sided Jacobi
 // Round-robin ("tournament") pairing of kp (even) indices: in round t, slot a
 // pairs positions a and kp-1-a of the rotated list [0, 1 + (t + i) mod (kp-1)].
 __device__ inline int rr_player(int pos, int t, int kp) {
@@ -393,168 +389,135 @@ __device__ inline int rr_player(int pos, int t, int kp) {
   return 1 + (pos - 1 + t) % (kp - 1);
 }
 
-// Two-sided Jacobi on the symmetric H (k x k, padded to even kp with a zero
-// row/column).  H is kept as its packed upper triangle, twice: every round
-// reads one copy and writes the rotated matrix H <- J^T H J into the other,
-// so a single barrier per round separates the rounds.  A round applies kp/2
-// disjoint rotations; each wave computes all of them itself from the copy it
-// reads (no broadcast), and the 2 x 2 blocks (pair a, pair b), a <= b, are
-// rotated once each (the lower triangle is the same storage).  Rounds without
-// a rotation (the same decision in every wave) are skipped.  Up to kJFuse
-// the eigenvectors V = prod J accumulate in LDS next to H and are written to
-// st.VM (st.rounds = -1 marks this); beyond, the (c, s) of every round are
-// logged and V is rebuilt per row by the replay kernel.
-constexpr int kJFuse = 88;
+// One-sided (Hestenes) Jacobi SVD of X = R^T (k x kj), R from the pivoted QR
+// of the core: X Y = Z with orthogonal columns, sigma_a = ||z_a||, so that
+// R = Y diag(sigma) (Z diag(1/sigma))^T.  The QR's column pivoting makes the
+// columns of X graded and nearly orthogonal, so few sweeps are needed.  X is
+// kept in LDS by columns; a round rotates kp/2 disjoint pairs (p, q), one
+// team of 16, 32 or 64 lanes per pair (the three dot products reduced with
+// lane shuffles), chosen so that x_p^T x_q = 0 afterwards:
+//   zeta = (b - a) / (2 g),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1 / sqrt(1 + t^2),  s = c t,  [x_p, x_q] <- [c x_p - s x_q, s x_p + c x_q]
+// with a = ||x_p||^2, b = ||x_q||^2, g = x_p^T x_q; a pair is rotated when
+// |g| > 1e-14 sqrt(a b) (rounding level of the products), so every singular
+// value comes out with an absolute error of a few ulps of ||M|| and the
+// columns of Z are orthogonal to working accuracy whatever their norms.
+// Y accumulates in LDS next to X when both fit; otherwise the (c, s) of every
+// round are logged and the replay kernel rebuilds Y.  Outputs: sigma (st.lam,
+// Jacobi order), V_M = Z diag(1/sigma) (st.VP, k x kj), Y (st.VM) or the log.
 constexpr int kJacThreads = 1024;
-constexpr int kJacLds = 2 * SKP;            // doubles: two packed copies of H at kp <= 128
-static_assert(2 * (kJFuse * (kJFuse + 1) / 2) + kJFuse * (kJFuse + 1) <= kJacLds,
-              "fused eigenvectors must fit next to the two packed copies");
+constexpr int kJacLds = 18432;              // doubles (144 KiB)
+static_assert(SK * SK <= kJacLds, "X must fit in LDS at the largest width");
 __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const JacArgs* ab,
                                                             const int* done) {
   LRC_ITEM(JacArgs, ja_, a0, ab, done)
   const TruncState& st = ja_.st;
   const int kcap = ja_.kcap, max_rounds = ja_.max_rounds;
   __shared__ double lds[kJacLds];
-  __shared__ double2 csw[kJacThreads / 64][SK / 2];
-  __shared__ short2 pqw[kJacThreads / 64][SK / 2];
-  __shared__ double s_floor;
-  const int k = *st.kj;
-  const int kp = k + (k & 1);
-  const bool fuse = k <= kJFuse;
+  __shared__ double s_sig[SK];
+  const int k = *st.k, kj = *st.kj;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
-  if (k <= 1) {
-    if (tid == 0) {
-      if (k == 1) {
-        st.VM[0] = 1.0;
-        st.lam[0] = st.H[0];
-      }
-      *st.rounds = -1;
-    }
+  if (kj <= 0 || k <= 0) {
+    if (tid == 0) *st.rounds = -1;
     return;
   }
-  const int np = kp * (kp + 1) / 2;
-  double* Hs[2] = {lds, lds + np};
-  double* V = lds + 2 * np;                 // kp x (kp + 1) when fused
-  const int P = kp + 1;
-  for (int e = tid; e < kp * kp; e += nt) {
-    const int i = e / kp, j = e - i * kp;
-    if (j >= i) Hs[0][pu(i, j, kp)] = (j < k) ? st.H[size_t(i) * kcap + j] : 0.0;
-    if (fuse) V[i * P + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // Off-diagonal entries below max(1e-16, 0.01 tol^2) * trace(H) are not
-  // rotated: 1e-16 is the rounding noise of the squared core, and a truncation
-  // at relative tolerance tol needs the eigenvalues of H = M^T M (squared
-  // singular values) to no better than a small fraction of tol^2 * ||M||_F^2.
-  if (tid < 64) {
-    double tr = 0.0;
-    for (int i = tid; i < k; i += 64) tr += fabs(Hs[0][pu(i, i, kp)]);
-    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    if (tid == 0)
-      s_floor = fmax(fmax(1e-16, 0.01 * ja_.tol * ja_.tol) * tr, 0.01 * ja_.abs_tol * ja_.abs_tol);
-  }
-  __syncthreads();
-  const double floor_abs = s_floor;
+  const int kp = kj + (kj & 1);
   const int npair = kp / 2;
-  const int nblk = npair * (npair + 1) / 2;     // <= 2080: at most 3 blocks per thread
-  // this thread's blocks (pair a, pair b), a <= b, in row-major order of the
-  // upper triangle of the pair grid
-  int ba[3], bb[3], nmy = 0;
-  for (int e = tid; e < nblk; e += nt) {
-    int a = 0, rem = e;
-    while (rem >= npair - a) { rem -= npair - a; ++a; }
-    ba[nmy] = a;
-    bb[nmy] = a + rem;
-    ++nmy;
+  const bool fuse = kj * k + kj * kj <= kJacLds;
+  double* X = lds;                 // column a at X + a * k
+  double* Y = lds + kj * k;        // column a at Y + a * kj (when fused)
+  for (int e = tid; e < kj * k; e += nt) {
+    const int a = e / k, i = e - a * k;
+    X[e] = st.W[size_t(a) * kcap + i];
   }
-  int round = 0, cur = 0;
+  if (fuse)
+    for (int e = tid; e < kj * kj; e += nt) Y[e] = (e / kj == e % kj) ? 1.0 : 0.0;
+  __syncthreads();
+  // only an underflow guard: pairs of tiny columns are still rotated, so that
+  // the singular vectors of small singular values stay orthogonal
+  const double floor_abs = 1e-300;
+  const double eps = 1e-14;
+  const int TL = npair <= 16 ? 64 : (npair <= 32 ? 32 : 16);   // lanes per pair
+  const int slot = wave * (64 / TL) + lane / TL;
+  const int tl = lane % TL;
+  int round = 0;
   bool converged = false;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
-    int nrot = 0;
-    // pair slot `lane` of round t: positions lane and kp-1-lane of the rotated
-    // list [0, 1 + (t + i) mod (kp - 1)]; the residues advance by one a round
-    int c0 = lane == 0 ? 0 : lane - 1, c1 = kp - 2 - lane;
+    int any = 0;
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
-      const double* H = Hs[cur];
-      double* Hn = Hs[cur ^ 1];
-      bool rot = false;
-      const int x0 = lane == 0 ? 0 : 1 + c0, x1 = 1 + c1;
-      c0 = c0 + 1 == kp - 1 ? 0 : c0 + 1;
-      c1 = c1 + 1 == kp - 1 ? 0 : c1 + 1;
-      if (lane < npair) {
-        const int p = min(x0, x1), q = max(x0, x1);
-        const double hpp = H[pu(p, p, kp)], hqq = H[pu(q, q, kp)], hpq = H[pu(p, q, kp)];
-        double c = 1.0, sn = 0.0;
-        if (fabs(hpq) > floor_abs) {
-          // the rotation of angle |theta| <= pi/4 with tan 2 theta = 2 h_pq / (h_qq - h_pp),
-          // from the half-angle formulas: cos 2 theta = |d| / rho >= 0,
-          // sin 2 theta = sign(d) e / rho, c = sqrt((1 + cos 2 theta) / 2),
-          // s = sin 2 theta / (2 c)  (two reciprocal square roots, no division)
-          const double d = hqq - hpp, e = 2.0 * hpq;
-          const double ri = rsqrt(fma(d, d, e * e));
-          const double c2 = fabs(d) * ri, s2 = (d >= 0.0 ? e : -e) * ri;
-          const double h = 0.5 + 0.5 * c2;
-          const double hi = rsqrt(h);
-          c = h * hi;
-          sn = 0.5 * s2 * hi;
-          rot = true;
+      int rot = 0;
+      if (slot < npair) {
+        int p = rr_player(slot, t, kp), q = rr_player(kp - 1 - slot, t, kp);
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        if (q < kj) {
+          double* xp = X + p * k;
+          double* xq = X + q * k;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = tl; i < k; i += TL) {
+            const double u = xp[i], v = xq[i];
+            al = fma(u, u, al);
+            be = fma(v, v, be);
+            ga = fma(u, v, ga);
+          }
+          for (int o = TL >> 1; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o);
+            be += __shfl_xor(be, o);
+            ga += __shfl_xor(ga, o);
+          }
+          if (fabs(ga) > fmax(eps * sqrt(al * be), floor_abs)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double az = fabs(zeta);
+            // sqrt(1 + zeta^2) without overflow for huge |zeta|
+            const double hyp = az > 1e150 ? az : sqrt(1.0 + az * az);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (az + hyp);
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = c * tt;
+          }
+          if (s != 0.0) {
+            rot = 1;
+            for (int i = tl; i < k; i += TL) {
+              const double u = xp[i], v = xq[i];
+              xp[i] = c * u - s * v;
+              xq[i] = s * u + c * v;
+            }
+            if (fuse) {
+              double* yp = Y + p * kj;
+              double* yq = Y + q * kj;
+              for (int b = tl; b < kj; b += TL) {
+                const double u = yp[b], v = yq[b];
+                yp[b] = c * u - s * v;
+                yq[b] = s * u + c * v;
+              }
+            }
+          }
         }
-        csw[wave][lane] = make_double2(c, sn);
-        pqw[wave][lane] = make_short2(short(p), short(q));
-        if (!fuse && wave == 0) {
-          st.rot[(size_t(round) * (SK / 2) + lane) * 2 + 0] = c;
-          st.rot[(size_t(round) * (SK / 2) + lane) * 2 + 1] = sn;
-        }
-      }
-      const int rr = __popcll(__ballot(rot));
-      if (rr == 0) continue;          // H unchanged: no update, no barrier
-      nrot += rr;
-      // Hn <- J^T H J over the blocks (pair a, pair b), a <= b
-#pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        if (u >= nmy) break;
-        const int a = ba[u], b = bb[u];
-        const double2 ja = csw[wave][a], jb = csw[wave][b];
-        const short2 qa2 = pqw[wave][a], qb2 = pqw[wave][b];
-        const int pa = qa2.x, qa = qa2.y, pb = qb2.x, qb = qb2.y;
-        auto at = [&](int x, int y) { return x <= y ? pu(x, y, kp) : pu(y, x, kp); };
-        const int i00 = at(pa, pb), i01 = at(pa, qb), i10 = at(qa, pb), i11 = at(qa, qb);
-        const double h00 = H[i00], h01 = H[i01], h10 = H[i10], h11 = H[i11];
-        const double l00 = ja.x * h00 - ja.y * h10, l01 = ja.x * h01 - ja.y * h11;
-        const double l10 = ja.y * h00 + ja.x * h10, l11 = ja.y * h01 + ja.x * h11;
-        double r00 = jb.x * l00 - jb.y * l01, r01 = jb.y * l00 + jb.x * l01;
-        double r10 = jb.x * l10 - jb.y * l11, r11 = jb.y * l10 + jb.x * l11;
-        if (a == b && ja.y != 0.0) r01 = r10 = 0.0;   // the rotated pair is diagonalised
-        Hn[i00] = r00;
-        Hn[i01] = r01;
-        Hn[i11] = r11;
-        if (a != b) Hn[i10] = r10;        // a == b: (qa, pa) is (pa, qa)'s storage
-      }
-      if (fuse) {
-        // V <- V J: columns (p_a, q_a) of every row
-        for (int e = tid; e < kp * npair; e += nt) {
-          const int i = e / npair, a = e - i * npair;
-          const double2 ja = csw[wave][a];
-          if (ja.y == 0.0) continue;
-          const short2 q2 = pqw[wave][a];
-          const double vp = V[i * P + q2.x], vq = V[i * P + q2.y];
-          V[i * P + q2.x] = ja.x * vp - ja.y * vq;
-          V[i * P + q2.y] = ja.y * vp + ja.x * vq;
+        if (!fuse && tl == 0) {
+          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 0] = c;
+          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 1] = s;
         }
       }
-      cur ^= 1;
-      __syncthreads();
+      any |= __syncthreads_or(rot);
     }
-    if (nrot == 0) { converged = true; break; }
+    if (!any) { converged = true; break; }
   }
-  const double* H = Hs[cur];
-  if (fuse) {
-    for (int e = tid; e < k * k; e += nt) {
-      const int i = e / k, j = e - i * k;
-      st.VM[size_t(i) * kcap + j] = V[i * P + j];
+  for (int a = tid; a < kj; a += nt) {
+    double sq = 0.0;
+    for (int i = 0; i < k; ++i) sq = fma(X[a * k + i], X[a * k + i], sq);
+    s_sig[a] = sqrt(sq);
+  }
+  __syncthreads();
+  for (int e = tid; e < kj * k; e += nt) {
+    const int c = e / kj, a = e - c * kj;
+    const double sg = s_sig[a];
+    st.VP[size_t(c) * kcap + a] = sg > 0.0 ? X[a * k + c] * (1.0 / sg) : 0.0;
+  }
+  for (int a = tid; a < kj; a += nt) st.lam[a] = s_sig[a];
+  if (fuse)
+    for (int e = tid; e < kj * kj; e += nt) {
+      const int b = e / kj, a = e - b * kj;
+      st.VM[size_t(b) * kcap + a] = Y[a * kj + b];
     }
-  }
-  for (int j = tid; j < k; j += nt) st.lam[j] = H[pu(j, j, kp)];
   if (tid == 0) {
     *st.rounds = fuse ? -1 : round;
     if (!converged) atomicOr(st.info, 4);
@@ -621,139 +584,171 @@ void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s) {
   LRC_HIP(hipGetLastError());
 }
 
-constexpr int kJL = SK + 1;   // row stride of full k x k matrices in LDS
-
-// ============================================================== pivoted Cholesky
-// Diagonally pivoted Cholesky of H = M^T M:  Pi^T H Pi = R^T R, stopped once
-// the trace of the remaining Schur complement (the energy of the directions
-// left out) is below max(1e-16, (tol / 10)^2) trace(H): the rounding level of
-// H, or 1% of the truncation's tail budget if that is larger.  With tol = 0
-// every positive pivot is kept.  The rank kj it reveals is the dimension of
-// the eigenproblem solved next, on R R^T, whose eigenvectors Y give H's as
-// Pi R^T Y.  R R^T is close to diagonal after pivoting, so far fewer Jacobi
-// sweeps are needed than on H itself.
-// Pivoting is logical: the trailing matrix stays indexed by the original
-// columns (a step updates the entries of the columns not yet chosen), rows of
-// R are first written by original column to st.VP, and R R^T (which does not
-// depend on the column order) is formed from those rows.  Two barriers per
-// step.  Outputs: R (kj x k, upper trapezoidal in pivot order, zero rows below
-// kj) in st.W, R R^T (kj x kj) in st.H, the pivot order in st.piv, kj in st.kj.
-constexpr int kPivThreads = 1024;
-__global__ __launch_bounds__(kPivThreads) void pivchol_kernel(PivArgs a0, const PivArgs* ab,
-                                                              const int* done) {
-  LRC_ITEM(PivArgs, pa_, a0, ab, done)
-  const TruncState& st = pa_.st;
-  const int kcap = pa_.kcap;
-  const double tol = pa_.tol;
-  __shared__ double A[SK * kJL];
-  __shared__ double dg[SK];
-  __shared__ int pos[SK];
-  __shared__ unsigned char rem[SK];
-  __shared__ int s_p, s_stop;
-  __shared__ double s_thr;
+// ============================================================== pivoted QR of the core
+// Householder QR with column pivoting of the core M (k x k), M P = Q R, in
+// fp64 and without forming M^T M: 8-lane teams hold one column of M each
+// (rows tl + 8 t), the same threads hold one row of Q each (Q <- Q H_j after
+// every step, so Q's first kj columns are ready at the end).  Step j takes the
+// column with the largest trailing norm (recomputed exactly each step: no
+// downdating), builds the reflector from its rows >= j (beta = -sign(x_j)
+// ||x||, v_j = 1, v_i = x_i / (x_j - beta), tau = (beta - x_j) / beta), and
+// applies it to the other columns and to Q.  It stops once the trailing block's
+// Frobenius norm is at most 1e-3 of the truncation's tail budget
+// max(tol ||M||_F, abs_tol): what is left cannot move the rank decision or any
+// kept singular value by more than (1e-3 budget)^2 / sigma.  Outputs: R (kj x
+// k, by original column, so that M = Q R) in st.W, Q (k x kj) in st.H, the
+// pivot order in st.piv and kj in st.kj.  Two barriers per step; every wave
+// takes the pivot decision itself from the same LDS data (same order of
+// operations, so the same result in every wave).
+constexpr int kQrThreads = 1024;
+constexpr int kQrTeam = 8;
+constexpr int kQrSlots = SK / kQrTeam;
+static_assert(kQrThreads / kQrTeam == SK, "one team per column");
+__device__ inline double team8_sum(double v) {
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
+__global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArgs* ab,
+                                                          const int* done) {
+  LRC_ITEM(QrArgs, qa_, a0, ab, done)
+  const TruncState& st = qa_.st;
+  const int kcap = qa_.kcap;
+  __shared__ double nrm[SK];     // trailing squared norm of each column (-1: chosen or absent)
+  __shared__ double vb[SK];      // reflector of the current step
+  __shared__ double s_tau;
   const int k = *st.k;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* Ro = st.VP;   // rows of R by original column (scratch)
-  for (int e = tid; e < k * k; e += nt) {
-    const int i = e / k, j = e - i * k;
-    A[i * kJL + j] = st.H[size_t(i) * kcap + j];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int team = tid >> 3, tl = tid & 7;
+  const bool inside = team < k;
+  double mc[kQrSlots], qr[kQrSlots];
+  double ss = 0.0;
+#pragma unroll
+  for (int t = 0; t < kQrSlots; ++t) {
+    const int i = tl + kQrTeam * t;
+    mc[t] = (inside && i < k) ? st.M[size_t(i) * kcap + team] : 0.0;   // M[i][team]
+    qr[t] = (inside && i == team) ? 1.0 : 0.0;                          // Q[team][i]
+    ss = fma(mc[t], mc[t], ss);
   }
-  for (int i = tid; i < k; i += nt) {
-    dg[i] = st.H[size_t(i) * kcap + i];
-    rem[i] = 1;
-  }
+  ss = team8_sum(ss);
+  if (tl == 0) nrm[team] = inside ? ss : -1.0;
   __syncthreads();
-  if (tid < 64) {
-    double tr = 0.0;
-    for (int i = tid; i < k; i += 64) tr += fabs(dg[i]);
-    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    // 1% of the tail budget (relative, or absolute when that is larger)
-    if (tid == 0)
-      s_thr = fmax(tol > 0.0 ? fmax(1e-16, 0.01 * tol * tol) * tr : 0.0,
-                   0.01 * pa_.abs_tol * pa_.abs_tol);
-  }
-  int r = k;
+  bool active = inside;
+  double thr2 = 0.0;
+  int kj = 0;
   for (int j = 0; j < k; ++j) {
-    if (tid < 64) {
-      double best = -1.0, sum = 0.0;
-      int bi = k;
-      for (int i = tid; i < k; i += 64) {
-        if (!rem[i]) continue;
-        const double v = dg[i];
-        sum += v;
-        if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    double best = -1.0, tot = 0.0;
+    int bi = SK;
+    for (int c = lane; c < k; c += 64) {
+      const double v = nrm[c];
+      if (v >= 0.0) {
+        tot += v;
+        if (v > best) { best = v; bi = c; }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        sum += __shfl_xor(sum, o);
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      tot += __shfl_xor(tot, o);
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (j == 0) {
+      const double b1 = qa_.tol > 0.0 ? 1e-3 * qa_.tol : 0.0;
+      const double b2 = 1e-3 * qa_.abs_tol;
+      thr2 = fmax(b1 * b1 * tot, b2 * b2);
+    }
+    if (!(tot > thr2) || !(best > 0.0) || bi >= k) break;   // the same in every wave
+    const int p = bi;
+    if (team == p) {
+      double s2 = 0.0, x0 = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int i = tl + kQrTeam * t;
+        if (i >= j && i < k) s2 = fma(mc[t], mc[t], s2);
+        if (i == j) x0 = mc[t];
       }
-      if (tid == 0) {
-        const bool stop = !(sum > s_thr) || !(best > 0.0) || bi >= k;
-        s_stop = stop ? 1 : 0;
-        s_p = bi;
-        if (!stop) {
-          pos[j] = bi;
-          rem[bi] = 0;
+      s2 = team8_sum(s2);
+      x0 = team8_sum(x0);
+      const double nx = sqrt(s2);
+      const double beta = x0 >= 0.0 ? -nx : nx;
+      const double inv = 1.0 / (x0 - beta);     // |x0 - beta| = |x0| + ||x|| > 0
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int i = tl + kQrTeam * t;
+        if (i < k) vb[i] = i < j ? 0.0 : (i == j ? 1.0 : mc[t] * inv);
+      }
+      if (tl == 0) {
+        s_tau = (beta - x0) / beta;
+        st.W[size_t(j) * kcap + p] = beta;
+        st.piv[j] = p;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (active && team != p) {
+      double w = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int i = tl + kQrTeam * t;
+        if (i < k) w = fma(vb[i], mc[t], w);
+      }
+      w = team8_sum(w) * tau;
+      double s2 = 0.0, rj = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int i = tl + kQrTeam * t;
+        if (i < k) {
+          mc[t] = fma(-w, vb[i], mc[t]);
+          if (i > j) s2 = fma(mc[t], mc[t], s2);
+          if (i == j) rj = mc[t];
         }
       }
+      s2 = team8_sum(s2);
+      rj = team8_sum(rj);
+      if (tl == 0) {
+        nrm[team] = s2;
+        st.W[size_t(j) * kcap + team] = rj;
+      }
+    } else if (inside && team != p && tl == 0) {
+      st.W[size_t(j) * kcap + team] = 0.0;       // chosen at an earlier step
     }
-    __syncthreads();
-    if (s_stop) { r = j; break; }
-    const int p = s_p;
-    const double d = dg[p];
-    const double inv = 1.0 / sqrt(d);
-    // row j of R by original column: R[j][p] = sqrt(d), R[j][x] = A[p][x] / sqrt(d)
-    // for columns not chosen yet, 0 for those chosen before
-    for (int x = tid; x < k; x += nt)
-      Ro[size_t(j) * kcap + x] = x == p ? d * inv : (rem[x] ? A[p * kJL + x] * inv : 0.0);
-    // trailing update of the remaining columns (row p is only read)
-    const double id = 1.0 / d;
-    for (int e = tid; e < k * k; e += nt) {
-      const int x = e / k, y = e - x * k;
-      if (!rem[x] || !rem[y]) continue;
-      const double v = A[x * kJL + y] - A[p * kJL + x] * A[p * kJL + y] * id;
-      A[x * kJL + y] = v;
-      if (x == y) dg[x] = v;
+    if (team == p) {
+      active = false;
+      if (tl == 0) nrm[p] = -1.0;
     }
+    // Q <- Q H_j (row `team` of Q)
+    if (inside) {
+      double w = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int c = tl + kQrTeam * t;
+        if (c < k) w = fma(qr[t], vb[c], w);
+      }
+      w = team8_sum(w) * tau;
+#pragma unroll
+      for (int t = 0; t < kQrSlots; ++t) {
+        const int c = tl + kQrTeam * t;
+        if (c < k) qr[t] = fma(-w, vb[c], qr[t]);
+      }
+    }
+    kj = j + 1;
     __syncthreads();
   }
-  // the columns never chosen follow in original order
-  if (tid == 0) {
-    int q = r;
-    for (int x = 0; x < k; ++x)
-      if (rem[x]) pos[q++] = x;
+  if (inside) {
+#pragma unroll
+    for (int t = 0; t < kQrSlots; ++t) {
+      const int c = tl + kQrTeam * t;
+      if (c < kj) st.H[size_t(team) * kcap + c] = qr[t];
+    }
   }
-  __syncthreads();
-  // R in pivot order, and R R^T from the rows by original column (staged in LDS)
-  for (int e = tid; e < k * k; e += nt) {
-    const int a = e / k, c = e - a * k;
-    const double v = (a < r && c >= a) ? Ro[size_t(a) * kcap + pos[c]] : 0.0;
-    st.W[size_t(a) * kcap + c] = v;
-    A[a * kJL + c] = a < r ? Ro[size_t(a) * kcap + c] : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += nt) {
-    const int a = e / r, b = e - a * r;
-    if (b < a) continue;
-    double acc = 0.0;
-    for (int x = 0; x < k; ++x) acc += A[a * kJL + x] * A[b * kJL + x];
-    st.H[size_t(a) * kcap + b] = acc;
-    st.H[size_t(b) * kcap + a] = acc;
-  }
-  for (int i = tid; i < k; i += nt) st.piv[i] = pos[i];
-  if (tid == 0) *st.kj = r;
+  if (tid == 0) *st.kj = kj;
 }
 
-// ============================================================== core + Jacobi
-// R_A = R2_A R1_A, R_B = R2_B R1_B;  M = R_A diag(core) R_B^T;  H = M^T M;
-// pivoted Cholesky of H, then the Jacobi rounds on R R^T.  Scratch: R1
-// buffers are overwritten by R_A, R_B; H by R R^T.
-void enqueue_pivchol(const PivArgs& a, Batched<PivArgs> b, hipStream_t s) {
+void enqueue_qrcp(const QrArgs& a, Batched<QrArgs> b, hipStream_t s) {
   LRC_CHECK(a.kcap <= SK, ST_EINVAL, "truncation: at most 128 concatenated columns");
-  ProfScope ps(kcls(K_PIVCHOL, false), s);
-  hipLaunchKernelGGL(pivchol_kernel, dim3(1, 1, b.n), dim3(kPivThreads), 0, s, a, b.dev, b.done);
+  ProfScope ps(kcls(K_QRCP, false), s);
+  hipLaunchKernelGGL(qrcp_kernel, dim3(1, 1, b.n), dim3(kQrThreads), 0, s, a, b.dev, b.done);
   LRC_HIP(hipGetLastError());
 }
 
@@ -763,43 +758,37 @@ void enqueue_jacobi(const JacArgs& a, Batched<JacArgs> b, hipStream_t s) {
   LRC_HIP(hipGetLastError());
 }
 
-// R_A = R2_A R1_A, R_B = R2_B R1_B (into the G buffers); M = R_A diag(core) R_B^T; H = M^T M
+// R_A = R2_A R1_A, R_B = R2_B R1_B (into the G buffers); M = R_A diag(core) R_B^T
 void make_core_gemms(const TruncState& st, const CoreView& core, int kcap, SmallGemmArgs* out) {
   SmallGemm j2[2];
   for (int x = 0; x < 2; ++x) j2[x] = SmallGemm{st.R2[x], st.R1[x], st.G[x], nullptr, nullptr, nullptr, 0, 0, 0};
   out[0] = make_small_gemm(j2, 2, core, st.k, kcap);
   SmallGemm jm{st.G[0], st.G[1], st.M, nullptr, nullptr, nullptr, 0, 1, 1};
   out[1] = make_small_gemm(&jm, 1, core, st.k, kcap);
-  SmallGemm jh{st.M, st.M, st.H, nullptr, nullptr, nullptr, 1, 0, 0};
-  out[2] = make_small_gemm(&jh, 1, core, st.k, kcap);
 }
 
-// VP = Pi R^T Y, W = M VP; after the selection XA = R2i_A W[:, order] diag(1 / ||W_j||),
-// XB = R2i_B VP[:, order] diag(1 / ||VP_j||)
+// U_M = Q Y (into st.W); after the selection XA = R2i_A U_M[:, order],
+// XB = R2i_B V_M[:, order] (unit columns: no scaling)
 void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, SmallGemmArgs* out) {
   CoreView none{};
   none.nb = 0;
-  SmallGemm jv{st.W, st.VM, st.VP, nullptr, nullptr, st.kj, 1, 0, 0, st.piv, st.kj};
-  out[0] = make_small_gemm(&jv, 1, none, st.k, kcap);
-  SmallGemm jw{st.M, st.VP, st.W, nullptr, nullptr, st.kj, 0, 0, 0};
-  out[1] = make_small_gemm(&jw, 1, none, st.k, kcap);
+  SmallGemm ju{st.H, st.VM, st.W, nullptr, nullptr, st.kj, 0, 0, 0, nullptr, st.kj};
+  out[0] = make_small_gemm(&ju, 1, none, st.k, kcap);
   SmallGemm jx[2];
-  jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, st.invsig, rank_out, 0, 0, 0};
-  jx[1] = SmallGemm{st.R2i[1], st.VP, st.XB, st.order, st.invnu, rank_out, 0, 0, 0};
-  out[2] = make_small_gemm(jx, 2, none, st.k, kcap);
+  jx[0] = SmallGemm{st.R2i[0], st.W, st.XA, st.order, nullptr, rank_out, 0, 0, 0};
+  jx[1] = SmallGemm{st.R2i[1], st.VP, st.XB, st.order, nullptr, rank_out, 0, 0, 0};
+  out[1] = make_small_gemm(jx, 2, none, st.k, kcap);
 }
 
 // ============================================================== rank selection
-// W = M V (columns: M v_j = sigma_j u_j); sigma_j = ||W[:, j]||; order by
-// decreasing sigma; r' = min(cap, smallest r with tail <= tol * ||sigma||).
-// Then XA = R2i_A * W[:, order] diag(1/sigma), XB = R2i_B * V[:, order].
-constexpr int kSelThreads = 1024;
-constexpr int kSelRG = kSelThreads / SK;   // row groups of the column norms
+// sigma from the Jacobi kernel; order by decreasing sigma;
+// r' = min(cap, smallest r with tail <= max(tol * ||sigma||, abs_tol)).
+constexpr int kSelThreads = 256;
 __global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a0, const SelArgs* ab,
                                                              const int* done) {
   LRC_ITEM(SelArgs, sa_, a0, ab, done)
   const TruncState& st = sa_.st;
-  const int kcap = sa_.kcap, rank_cap = sa_.rank_cap;
+  const int rank_cap = sa_.rank_cap;
   const double tol = sa_.tol;
   double* s_out = sa_.s_out;
   int* rank_out = sa_.rank_out;
@@ -808,50 +797,9 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a0, const S
   __shared__ double srt[SK];
   __shared__ int ord[SK];
   __shared__ int rsel;
-  __shared__ double om[SK], nu[SK];
-  __shared__ double pw[kSelRG][SK], pv[kSelRG][SK];
-  __shared__ double s_lfloor;
-  const int kr = *st.k;          // rows of W and VP
   const int k = *st.kj;          // candidate singular directions
   const int tid = threadIdx.x;
-  if (tid < 64) {
-    double tr = 0.0;
-    for (int j = tid; j < k; j += 64) tr += fabs(st.lam[j]);
-    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-    if (tid == 0) s_lfloor = 64.0 * 1e-16 * tr;
-  }
-  __syncthreads();
-  // sigma_j = ||M VP_j|| / ||VP_j|| (= lambda_j / sqrt(lambda_j)) is the more
-  // accurate value where lambda_j is well above the Jacobi floor; at the
-  // rounding level both norms are noise, and sqrt(lambda_j) is used instead.
-  // column norms of W and VP: row group g sums rows g, g + kSelRG, ...; the
-  // groups are added in a fixed order
-  {
-    const int j = tid % SK, grp = tid / SK;
-    double a = 0.0, b = 0.0;
-    if (j < k)
-      for (int i = grp; i < kr; i += kSelRG) {
-        const double w = st.W[size_t(i) * kcap + j];
-        const double v = st.VP[size_t(i) * kcap + j];
-        a += w * w;
-        b += v * v;
-      }
-    pw[grp][j] = a;
-    pv[grp][j] = b;
-  }
-  __syncthreads();
-  for (int j = tid; j < k; j += blockDim.x) {
-    double a = 0.0, b = 0.0;
-#pragma unroll
-    for (int g = 0; g < kSelRG; ++g) {
-      a += pw[g][j];
-      b += pv[g][j];
-    }
-    om[j] = sqrt(a);
-    nu[j] = sqrt(b);
-    const double lj = st.lam[j];
-    sig[j] = (lj > s_lfloor && nu[j] > 0.0) ? om[j] / nu[j] : sqrt(fmax(lj, 0.0));
-  }
+  for (int j = tid; j < k; j += blockDim.x) sig[j] = st.lam[j];
   __syncthreads();
   for (int j = tid; j < k; j += blockDim.x) {
     int pos = 0;
@@ -888,10 +836,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a0, const S
   __syncthreads();
   const int r = rsel;
   for (int j = tid; j < k; j += blockDim.x) {
-    const int o = ord[j];
-    st.order[j] = o;
-    st.invsig[j] = om[o] > 0.0 ? 1.0 / om[o] : 0.0;
-    st.invnu[j] = nu[o] > 0.0 ? 1.0 / nu[o] : 0.0;
+    st.order[j] = ord[j];
     if (j < r) s_out[j] = srt[j];
   }
 }

@@ -249,20 +249,18 @@ struct TruncState {
   double* R2[2];     // second-pass factors
   double* R2i[2];    // R2^{-1}
   double* M;         // core
-  double* H;         // M^T M
-  double* VM;        // eigenvectors Y of the preconditioned Gram R R^T (kj x kj)
-  double* W;         // pivoted Cholesky factor R, then M V (columns ~ sigma_j u_j)
-  double* VP;        // V = Pi R^T Y (k x kj, column norms sqrt(lambda_j))
-  double* XA;        // R2A^{-1} U_M(:, :r)   (k x r, ld kcap)
-  double* XB;        // R2B^{-1} V_M(:, :r)
-  int* order;        // columns by decreasing sigma
-  double* invsig;    // 1 / ||W_j|| in that order
-  double* invnu;     // 1 / ||VP_j|| in that order
-  double* lam;       // eigenvalues of R R^T from the Jacobi rounds (kj values)
-  int* piv;          // pivot order of the Cholesky of M^T M
-  int* kj;           // numerical rank found by that Cholesky (Jacobi dimension)
+  double* H;         // Q of the pivoted QR of the core (k x kj)
+  double* VM;        // Y: rotations of the one-sided Jacobi on R^T (kj x kj)
+  double* W;         // R of the pivoted QR (kj x k, original column order), then U_M = Q Y
+  double* VP;        // V_M: unit right singular vectors of the core (k x kj)
+  double* XA;        // R2A^{-1} U_M(:, order)   (k x r, ld kcap)
+  double* XB;        // R2B^{-1} V_M(:, order)
+  int* order;        // singular directions by decreasing sigma
+  double* lam;       // singular values of the core (kj values, Jacobi order)
+  int* piv;          // pivot order of the QR (diagnostic)
+  int* kj;           // numerical rank kept by the QR (Jacobi dimension)
   double* rot;       // rotation log (c, s) per round and pair
-  int* rounds;       // number of logged rounds
+  int* rounds;       // number of logged rounds (-1: Y written by the Jacobi kernel)
   int* k;            // total width (A and B have the same column count)
   int* info;         // bit 0: shifted Cholesky, 1: breakdown, 2: Jacobi not converged, 3: capacity
 };
@@ -273,7 +271,10 @@ struct CholArgs {
   int kcap;
   double eps;
 };
-struct PivArgs {
+// Pivoted Householder QR of the core, stopped once the trailing block's
+// Frobenius norm is below 1e-3 of the truncation's tail budget
+// (max(tol ||M||_F, abs_tol)).
+struct QrArgs {
   TruncState st;
   int kcap;
   double tol;
@@ -283,8 +284,8 @@ struct JacArgs {
   TruncState st;
   int kcap;
   int max_rounds;
-  double tol;        // truncation tolerance (sets the rotation floor)
-  double abs_tol;    // absolute tail budget of the truncation (0: none)
+  double tol;        // truncation tolerance (unused by the rotations: they go to rounding level)
+  double abs_tol;
 };
 struct RepArgs {
   TruncState st;
@@ -323,15 +324,15 @@ struct SmallGemmArgs {
 };
 
 void enqueue_chol(const CholArgs& a, Batched<CholArgs> b, hipStream_t s);
-void enqueue_pivchol(const PivArgs& a, Batched<PivArgs> b, hipStream_t s);
+void enqueue_qrcp(const QrArgs& a, Batched<QrArgs> b, hipStream_t s);
 void enqueue_jacobi(const JacArgs& a, Batched<JacArgs> b, hipStream_t s);
 void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s);
 void enqueue_select(const SelArgs& a, Batched<SelArgs> b, hipStream_t s);
 SmallGemmArgs make_small_gemm(const SmallGemm* jobs, int njobs, CoreView core, const int* k,
                               int kcap);
 void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStream_t s);
-// the three products before the eigen-decomposition (R_A R_B, M, H) and the
-// three after it (VP, W, XA / XB)
+// the two products before the core SVD (R_A R_B, M) and the two after it
+// (U_M = Q Y; XA / XB)
 void make_core_gemms(const TruncState& st, const CoreView& core, int kcap, SmallGemmArgs* out);
 void make_finish_gemms(const TruncState& st, int kcap, const int* rank_out, SmallGemmArgs* out);
 

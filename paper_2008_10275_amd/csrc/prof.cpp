@@ -8,7 +8,7 @@ namespace lrc {
 const char* kclass_name(int c) {
   static const char* names[K_NBASE] = {"spmm", "gram", "gram_reduce", "chol", "tsmm", "jacobi",
                                        "jacobi_replay", "small_gemm", "select", "prec_gather",
-                                       "prec_product", "residual", "vector", "pivchol", "mlp",
+                                       "prec_product", "residual", "vector", "qrcp", "mlp",
                                        "graph"};
   static std::vector<std::string> full;
   if (full.empty())

@@ -100,8 +100,8 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
   ldq = kTruncCap;
   max_rounds = 30 * (kcap - 1);
   const size_t kk = size_t(kcap) * kcap;
-  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, VP, XA, XB + invsig, invnu, lam
-  const size_t arena = 17 * kk + 3 * size_t(kcap);
+  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, VP, XA, XB + lam
+  const size_t arena = 17 * kk + size_t(kcap);
   small.alloc(arena * sizeof(double));
   double* b = small.as<double>();
   for (int x = 0; x < 2; ++x) {
@@ -118,8 +118,6 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
   st.VP = b; b += kk;
   st.XA = b; b += kk;
   st.XB = b; b += kk;
-  st.invsig = b; b += kcap;
-  st.invnu = b; b += kcap;
   st.lam = b; b += kcap;
   LRC_CHECK(size_t(b - small.as<double>()) == arena, ST_EINVAL, "truncation arena layout");
   rot.alloc(size_t(max_rounds) * 64 * 2 * sizeof(double));
@@ -165,14 +163,13 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   p.g2 = make_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
   p.c2 = CholArgs{st, 2, kcap, eps};
   make_core_gemms(st, core, kcap, p.core);
-  p.piv = PivArgs{st, kcap, tol, abs_tol};
+  p.qr = QrArgs{st, kcap, tol, abs_tol};
   p.jac = JacArgs{st, kcap, max_rounds, tol, abs_tol};
   p.rep = RepArgs{st, kcap};
-  SmallGemmArgs fin[3];
+  SmallGemmArgs fin[2];
   make_finish_gemms(st, kcap, rank_out, fin);
-  p.fin[0] = fin[0];
-  p.fin[1] = fin[1];
-  p.xab = fin[2];
+  p.fin = fin[0];
+  p.xab = fin[1];
   p.sel = SelArgs{st, kcap, rank_cap, tol, abs_tol, s_out, rank_out, norm_out};
   TsmmJob<T> t2[2] = {{va, n, st.XA, kcap, rank_out, Uout, ldu},
                       {vb, m, st.XB, kcap, rank_out, Vout, ldv}};
@@ -187,11 +184,11 @@ void enqueue_trunc(const TruncPlan<T>& p, const TruncBatch<T>& b, hipStream_t s)
   enqueue_tsmm(p.t1, b.t1, s);
   enqueue_gram(p.g2, b.g2, b.r2, s);
   enqueue_chol(p.c2, b.c2, s);
-  for (int i = 0; i < 3; ++i) enqueue_small_gemm(p.core[i], b.core[i], s);
-  enqueue_pivchol(p.piv, b.piv, s);
+  for (int i = 0; i < 2; ++i) enqueue_small_gemm(p.core[i], b.core[i], s);
+  enqueue_qrcp(p.qr, b.qr, s);
   enqueue_jacobi(p.jac, b.jac, s);
   enqueue_replay(p.rep, b.rep, s);
-  for (int i = 0; i < 2; ++i) enqueue_small_gemm(p.fin[i], b.fin[i], s);
+  enqueue_small_gemm(p.fin, b.fin, s);
   enqueue_select(p.sel, b.sel, s);
   enqueue_small_gemm(p.xab, b.xab, s);
   enqueue_tsmm(p.t2, b.t2, s);
@@ -233,7 +230,7 @@ TruncPlan<T> merge_plans(const std::vector<TruncPlan<T>>& v) {
     merge_gram(p.g2, v[i].g2);
     merge_tsmm(p.t1, v[i].t1);
     merge_tsmm(p.t2, v[i].t2);
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 2; ++j)
       LRC_CHECK(p.core[j].njobs == v[i].core[j].njobs, ST_EINVAL, "batched truncation: jobs differ");
   }
   return p;
@@ -264,7 +261,7 @@ TruncBatch<T> upload_plans(const std::vector<TruncPlan<T>>& v, const int* done, 
                            hipStream_t s) {
   const size_t nb = v.size();
   const size_t per = sizeof(GramArgs<T>) * 2 + sizeof(GramRedArgs<T>) * 2 + sizeof(CholArgs) * 2 +
-                     sizeof(TsmmArgs<T>) * 2 + sizeof(SmallGemmArgs) * 6 + sizeof(PivArgs) +
+                     sizeof(TsmmArgs<T>) * 2 + sizeof(SmallGemmArgs) * 4 + sizeof(QrArgs) +
                      sizeof(JacArgs) + sizeof(RepArgs) + sizeof(SelArgs);
   const size_t need = nb * per + 20 * 256;
   if (buf.bytes < need) buf.alloc(need);
@@ -281,11 +278,11 @@ TruncBatch<T> upload_plans(const std::vector<TruncPlan<T>>& v, const int* done, 
   LRC_PUT(g2, g2.g, GramArgs<T>);
   LRC_PUT(r2, g2.r, GramRedArgs<T>);
   LRC_PUT(c2, c2, CholArgs);
-  for (int j = 0; j < 3; ++j) LRC_PUT(core[j], core[j], SmallGemmArgs);
-  LRC_PUT(piv, piv, PivArgs);
+  for (int j = 0; j < 2; ++j) LRC_PUT(core[j], core[j], SmallGemmArgs);
+  LRC_PUT(qr, qr, QrArgs);
   LRC_PUT(jac, jac, JacArgs);
   LRC_PUT(rep, rep, RepArgs);
-  for (int j = 0; j < 2; ++j) LRC_PUT(fin[j], fin[j], SmallGemmArgs);
+  LRC_PUT(fin, fin, SmallGemmArgs);
   LRC_PUT(sel, sel, SelArgs);
   LRC_PUT(xab, xab, SmallGemmArgs);
   LRC_PUT(t2, t2.a, TsmmArgs<T>);

@@ -82,11 +82,11 @@ struct TruncPlan {
   TsmmLaunch<T> t1;
   GramLaunch<T> g2;
   CholArgs c2;
-  SmallGemmArgs core[3];
-  PivArgs piv;
+  SmallGemmArgs core[2];
+  QrArgs qr;
   JacArgs jac;
   RepArgs rep;
-  SmallGemmArgs fin[2];
+  SmallGemmArgs fin;
   SelArgs sel;
   SmallGemmArgs xab;
   TsmmLaunch<T> t2;
@@ -99,8 +99,8 @@ struct TruncBatch {
   Batched<GramRedArgs<T>> r1, r2;
   Batched<CholArgs> c1, c2;
   Batched<TsmmArgs<T>> t1, t2;
-  Batched<SmallGemmArgs> core[3], fin[2], xab;
-  Batched<PivArgs> piv;
+  Batched<SmallGemmArgs> core[2], fin, xab;
+  Batched<QrArgs> qr;
   Batched<JacArgs> jac;
   Batched<RepArgs> rep;
   Batched<SelArgs> sel;

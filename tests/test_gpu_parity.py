@@ -138,8 +138,17 @@ def test_spmm_autotune_shapes_agree(torch, L, ctx, dt, r):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n,m,k,cap,tol", [(3000, 400, 50, 20, 1e-8), (1000, 37, 9, 9, 0.0),
-                                           (2500, 300, 123, 40, 1e-8), (513, 60, 1, 5, 1e-8)])
+                                           (2500, 300, 123, 40, 1e-8), (513, 60, 1, 5, 1e-8),
+                                           (2000, 150, 60, 64, 1e-6)])
 def test_truncation_matches_oracle(torch, L, ctx, dt, n, m, k, cap, tol):
+    """The truncation T (Sec. 5: truncated SVD of the factored product) against
+    the oracle's Householder QR + LAPACK SVD.  fp64: the core SVD (pivoted
+    Householder QR, then one-sided Jacobi) never squares the core, so every
+    kept singular value agrees to 1e-12 of sigma_1 (plus 1e-8 relative), the
+    rank is exact (the cases sit well away from a tie at the cut: the last
+    one is decided by the tolerance, the others by the cap), and all r
+    columns of both factors are orthonormal to 1e-10.  fp32 factors: 24-bit
+    data, so 1e-4 of the product and orthonormality to 1e-4."""
     say("truncate", dt, n, m, k, cap, tol)
     rng = np.random.default_rng(k + n)
     A = rng.standard_normal((n, k)) * rng.uniform(0.1, 10, k)
@@ -154,29 +163,20 @@ def test_truncation_matches_oracle(torch, L, ctx, dt, n, m, k, cap, tol):
     s, r = L.truncate_dev(ctx, Ad, c, Bd, cap, tol, Ud, Vd)
     U = Ud.double().cpu().numpy()[:, :r]
     V = Vd.double().cpu().numpy()[:, :r]
+    X = U @ np.diag(s) @ V.T
+    Xo = Uo @ np.diag(so) @ Vo.T
     if dt == "f64":
-        # The core's SVD comes from the eigen-decomposition of M^T M in fp64, so
-        # singular values are accurate to ~1e-8 * s_1 in absolute terms: the
-        # well-separated ones agree tightly, the tail within that band, and the
-        # rank may differ by one at the cut.
-        assert abs(r - so.size) <= 1
-        rr = min(r, so.size)
-        big = so[:rr] >= 1e-6 * so[0]
-        assert np.allclose(s[:rr][big], so[:rr][big], rtol=1e-8)
-        assert np.all(np.abs(s[:rr] - so[:rr]) <= 2e-8 * so[0])
-        X = U @ np.diag(s) @ V.T
-        Xo = Uo @ np.diag(so) @ Vo.T
-        tail = np.sqrt(np.sum(so[rr:] ** 2)) if r != so.size else 0.0
-        assert np.linalg.norm(X - Xo) <= 1e-7 * np.linalg.norm(Xo) + 2 * tail
-        # singular vectors of sigma_j = eps * sigma_1 carry errors ~ u / eps^2
-        nb = int(np.sum(s >= 1e-3 * s[0]))
-        assert np.allclose(U[:, :nb].T @ U[:, :nb], np.eye(nb), atol=1e-9)
-        assert np.allclose(V[:, :nb].T @ V[:, :nb], np.eye(nb), atol=1e-9)
+        assert r == so.size
+        assert np.allclose(s, so, rtol=1e-8, atol=1e-12 * so[0])
+        assert np.linalg.norm(X - Xo) <= 1e-7 * np.linalg.norm(Xo)
+        assert np.allclose(U.T @ U, np.eye(r), atol=1e-10)
+        assert np.allclose(V.T @ V, np.eye(r), atol=1e-10)
     else:
         assert np.allclose(s[:3], so[:3], rtol=1e-4)
-        X = U @ np.diag(s) @ V.T
-        Xo = Uo @ np.diag(so) @ Vo.T
         assert np.linalg.norm(X - Xo) <= 1e-4 * np.linalg.norm(Xo)
+        nb = min(r, so.size)
+        assert np.allclose(U[:, :nb].T @ U[:, :nb], np.eye(nb), atol=1e-4)
+        assert np.allclose(V[:, :nb].T @ V[:, :nb], np.eye(nb), atol=1e-4)
 
 
 def test_c1_fp64_solve_matches_oracle(torch, L, ctx):
@@ -196,8 +196,9 @@ def test_c1_fp64_solve_matches_oracle(torch, L, ctx):
     U, s, V = prob.solution()
     X = U @ np.diag(s) @ V.T
     Xo = sum(olr.lr_dense(*t) for t in odrv.solution_terms(ref))
-    # both satisfy relres <= 1e-8 with cond(A_j) ~ 1e8: compare within that bound
-    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) < 1e-1
+    # both iterates come from the same recurrence on the same data in fp64:
+    # they agree to far below what the residual bound alone would allow
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) < 1e-9
     rr, col = prob.residual()
     Fd = np.outer(f, np.ones(m))
     Xd_res = olr.relres_dense(K, d, X, Fd)
