@@ -226,6 +226,24 @@ lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m,
                                    int ldb, const double* w_dev, int rank_cap, double tol,
                                    void* U_dev, int ldu, double* s, void* V_dev, int ldv, int* rank);
 
+/* lrc_truncate_dev without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * lrc_truncate_dev.  Its workspace is one fixed 64 MiB device array per GPU,
+ * held until the process ends, instead of a per-call allocation: n + m <=
+ * 32768 rows always fit (fp64 or fp32); a larger shape returns LRC_EINVAL
+ * with the bytes it would need.  Every call on one GPU uses that same array
+ * and leaves its contents behind (the call clears what must start at zero),
+ * so calls that overlap on one GPU, from two streams or two threads, race:
+ * the caller serialises them.  LRC_EINVAL while kernel timing
+ * (lrc_profile_enable) is on, since timing allocates.  The call synchronises
+ * its stream to return s and rank. */
+lrc_status lrc_truncate_noalloc_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
+                                    const void* A_dev, int lda, const double* c,
+                                    const void* B_dev, int ldb, int rank_cap, double tol,
+                                    void* U_dev, int ldu, double* s, void* V_dev, int ldv,
+                                    int* rank);
+
 /* --------------------------------------------------------------- surrogate
  * Learned initial guess (not in the paper; the initial guess is the upper
  * median's solution, Sec. 3.3): a perceptron d0 -> d1 -> d2 -> d3 with exact

@@ -4,47 +4,14 @@
 #include <cmath>
 #include <cstring>
 
-#include "mlp.hpp"
+#include "handles.hpp"
 #include "prof.hpp"
-#include "solver.hpp"
 
 using namespace lrc;
-
-struct lrc_ctx_s {
-  Ctx c;
-};
-struct lrc_ops_s {
-  Ops o;
-};
-struct lrc_prob_s {
-  Prob p;
-  std::unique_ptr<lrc_ops_s> owned_ops;
-};
-struct lrc_mlp_s {
-  lrc_ctx ctx;
-  lrc::Mlp m;
-};
 
 namespace {
 
 using clk = std::chrono::steady_clock;
-
-template <class F>
-lrc_status guarded(Ctx* ctx, F&& f) {
-  try {
-    if (ctx) ctx->err.clear();
-    return f();
-  } catch (const Error& e) {
-    if (ctx) ctx->err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (ctx) ctx->err = "host allocation failed";
-    return LRC_ENOMEM;
-  } catch (const std::exception& e) {
-    if (ctx) ctx->err = e.what();
-    return LRC_EINVAL;
-  }
-}
 
 void validate_csr(int64_t n, const int64_t* rp, const int32_t* col, const double* val, int i) {
   const std::string op = "operator " + std::to_string(i) + ": ";
@@ -384,6 +351,7 @@ lrc_status lrc_create(lrc_ctx* out, int device, void* stream) {
     c->c.device = device;
     c->c.handle = c;
     c->c.stream = static_cast<hipStream_t>(stream);
+    noalloc_init_device(device);
     LRC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->c.pinned), 64 * sizeof(double)));
     LRC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->c.pinned_i), 64 * sizeof(int)));
     return LRC_OK;

@@ -91,19 +91,50 @@ static void add_core(CoreView& c, const double* s, double coef, const int* wdev,
 }
 
 // ------------------------------------------------------------------ Truncator
+// Workspace of a truncation with row capacities nmax (A side) and mmax (B
+// side): the k x k arena, the Jacobi rotation log, the integer state, the Gram
+// partial sums and the first-pass factors Q1A, Q1B.  Offsets are 256-byte
+// aligned inside one block.
+struct TruncLayout {
+  size_t arena, rot, ints, gram, qa, qb, total;
+};
 template <class T>
-void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
-  if (nmax_ <= nmax && mmax_ <= mmax && small.p) return;
-  nmax = std::max(nmax, nmax_);
-  mmax = std::max(mmax, mmax_);
+static TruncLayout trunc_layout(int64_t nmax, int64_t mmax) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t kk = size_t(kTruncCap) * kTruncCap;
+  const int rounds = 30 * (kTruncCap - 1);
+  TruncLayout l{};
+  size_t off = 0;
+  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, VP, XA, XB + lam
+  l.arena = off; off += al((17 * kk + size_t(kTruncCap)) * sizeof(double));
+  l.rot = off;   off += al(size_t(rounds) * 64 * 2 * sizeof(double));
+  l.ints = off;  off += al((2 * kTruncCap + 16) * sizeof(int));
+  l.gram = off;  off += al(gram_workspace_bytes(nmax, mmax, kTruncCap, sizeof(T) == 8));
+  l.qa = off;    off += al(size_t(std::max<int64_t>(nmax, 1)) * kTruncCap * sizeof(T));
+  l.qb = off;    off += al(size_t(std::max<int64_t>(mmax, 1)) * kTruncCap * sizeof(T));
+  l.total = off;
+  return l;
+}
+template <class T>
+size_t trunc_workspace_bytes(int64_t nmax, int64_t mmax) {
+  return trunc_layout<T>(nmax, mmax).total;
+}
+template size_t trunc_workspace_bytes<double>(int64_t, int64_t);
+template size_t trunc_workspace_bytes<float>(int64_t, int64_t);
+
+template <class T>
+void Truncator<T>::carve(void* base, int64_t nmax_, int64_t mmax_) {
+  nmax = nmax_;
+  mmax = mmax_;
   kcap = kTruncCap;
   ldq = kTruncCap;
   max_rounds = 30 * (kcap - 1);
+  const TruncLayout l = trunc_layout<T>(nmax, mmax);
+  unsigned char* b0 = static_cast<unsigned char*>(base);
   const size_t kk = size_t(kcap) * kcap;
-  // arena of the k x k blocks: 10 per-side blocks + M, H, VM, W, VP, XA, XB + lam
-  const size_t arena = 17 * kk + size_t(kcap);
-  small.alloc(arena * sizeof(double));
-  double* b = small.as<double>();
+  double* b = reinterpret_cast<double*>(b0 + l.arena);
+  arena = b;
+  arena_bytes = l.rot - l.arena;
   for (int x = 0; x < 2; ++x) {
     st.G[x] = b; b += kk;
     st.R1[x] = b; b += kk;
@@ -119,23 +150,40 @@ void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
   st.XA = b; b += kk;
   st.XB = b; b += kk;
   st.lam = b; b += kcap;
-  LRC_CHECK(size_t(b - small.as<double>()) == arena, ST_EINVAL, "truncation arena layout");
-  rot.alloc(size_t(max_rounds) * 64 * 2 * sizeof(double));
-  st.rot = rot.as<double>();
-  ints.alloc((2 * kcap + 16) * sizeof(int));
-  int* ib = ints.as<int>();
+  st.rot = reinterpret_cast<double*>(b0 + l.rot);
+  int* ib = reinterpret_cast<int*>(b0 + l.ints);
+  ints_p = ib;
+  ints_bytes = l.gram - l.ints;
   st.order = ib;
   st.piv = ib + kcap;
   st.rounds = ib + 2 * kcap;
   st.k = ib + 2 * kcap + 1;
   st.info = ib + 2 * kcap + 2;
   st.kj = ib + 2 * kcap + 3;
-  LRC_HIP(hipMemsetAsync(small.p, 0, small.bytes, s));
-  LRC_HIP(hipMemsetAsync(ints.p, 0, ints.bytes, s));
-  gram_bytes = gram_workspace_bytes(nmax, mmax, kcap, sizeof(T) == 8);
-  gram_ws.alloc(gram_bytes);
-  Q1A.alloc(size_t(nmax) * ldq * sizeof(T));
-  Q1B.alloc(size_t(mmax) * ldq * sizeof(T));
+  gws = reinterpret_cast<double*>(b0 + l.gram);
+  gram_bytes = l.qa - l.gram;
+  qa = reinterpret_cast<T*>(b0 + l.qa);
+  qb = reinterpret_cast<T*>(b0 + l.qb);
+}
+
+template <class T>
+void Truncator<T>::alloc(int64_t nmax_, int64_t mmax_, hipStream_t s) {
+  if (nmax_ <= nmax && mmax_ <= mmax && ws.p) return;
+  const int64_t nn = std::max(nmax, nmax_), mm = std::max(mmax, mmax_);
+  ws.alloc(trunc_workspace_bytes<T>(nn, mm));
+  carve(ws.p, nn, mm);
+  LRC_HIP(hipMemsetAsync(arena, 0, arena_bytes, s));
+  LRC_HIP(hipMemsetAsync(ints_p, 0, ints_bytes, s));
+}
+
+template <class T>
+void Truncator<T>::bind(void* mem, size_t bytes, int64_t nmax_, int64_t mmax_, hipStream_t s) {
+  LRC_CHECK(trunc_workspace_bytes<T>(nmax_, mmax_) <= bytes, ST_EINVAL,
+            "truncation: bound workspace too small");
+  carve(mem, nmax_, mmax_);
+  // cleared with a kernel (not a memset node), so the call stays capturable
+  launch_fill(arena, int64_t(arena_bytes / 8), 0.0, s);
+  launch_fill(reinterpret_cast<double*>(ints_p), int64_t(ints_bytes / 8), 0.0, s);
 }
 
 template <class T>
@@ -147,11 +195,9 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
             "truncation: rank cap must be in [1, 64] and fit the output leading dimensions");
   const double eps = sizeof(T) == 8 ? 1e-14 : 1e-6;
-  T* qa = Q1A.as<T>();
-  T* qb = Q1B.as<T>();
   TruncPlan<T> p;
   GramJob<T> g1[2] = {{A, n, st.G[0], st.k}, {B, m, st.G[1], nullptr}};
-  p.g1 = make_gram<T>(g1, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
+  p.g1 = make_gram<T>(g1, 2, kcap, gws, gram_bytes, st.info);
   p.c1 = CholArgs{st, 1, kcap, eps};
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
   // the first pass writes st.k <= min(kcap, width bound) columns
@@ -160,7 +206,7 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   BlockView<T> va = view1<T>(qa, ldq, st.k, 0), vb = view1<T>(qb, ldq, st.k, 0);
   va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
-  p.g2 = make_gram<T>(g2, 2, kcap, gram_ws.as<double>(), gram_bytes, st.info);
+  p.g2 = make_gram<T>(g2, 2, kcap, gws, gram_bytes, st.info);
   p.c2 = CholArgs{st, 2, kcap, eps};
   make_core_gemms(st, core, kcap, p.core);
   p.qr = QrArgs{st, kcap, tol, abs_tol};
@@ -357,7 +403,7 @@ void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, 
           }
         std::fprintf(stderr, "  T1_A: nan %d big %d\n", nan, big);
         std::vector<T> q(size_t(n) * ldq);
-        LRC_HIP(hipMemcpy(q.data(), Q1A.p, q.size() * sizeof(T), hipMemcpyDeviceToHost));
+        LRC_HIP(hipMemcpy(q.data(), qa, q.size() * sizeof(T), hipMemcpyDeviceToHost));
         std::vector<int> colnan(kk, 0);
         for (int64_t i = 0; i < n; ++i)
           for (int j = 0; j < kk; ++j)

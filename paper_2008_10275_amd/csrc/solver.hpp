@@ -121,10 +121,19 @@ template <class T>
 struct Truncator {
   int kcap = 0, ldq = 0, max_rounds = 0;
   int64_t nmax = 0, mmax = 0;
-  DevBuf small, rot, ints, gram_ws, Q1A, Q1B;
-  size_t gram_bytes = 0;
+  DevBuf ws;                      // owned workspace (alloc); empty when bound
+  double* arena = nullptr;        // k x k blocks (zeroed at set-up)
+  int* ints_p = nullptr;          // integer state (zeroed at set-up)
+  double* gws = nullptr;          // Gram partial sums
+  T* qa = nullptr;                // first-pass factor of the A side (nmax x kcap)
+  T* qb = nullptr;                // first-pass factor of the B side (mmax x kcap)
+  size_t arena_bytes = 0, ints_bytes = 0, gram_bytes = 0;
   TruncState st{};
+  // owns a workspace for nmax_ x mmax_ rows (grow-only)
   void alloc(int64_t nmax_, int64_t mmax_, hipStream_t s);
+  // uses `bytes` of caller memory at `mem` instead (nothing is allocated)
+  void bind(void* mem, size_t bytes, int64_t nmax_, int64_t mmax_, hipStream_t s);
+  void carve(void* base, int64_t nmax_, int64_t mmax_);
   // outputs may alias input blocks; s_out/rank_out/norm_out are device pointers
   void run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, int64_t m,
            const CoreView& core, int rank_cap, double tol, T* Uout, int ldu, T* Vout, int ldv,
@@ -134,6 +143,10 @@ struct Truncator {
                     int ldv, double* s_out, int* rank_out, double* norm_out,
                     double abs_tol = 0.0) const;
 };
+
+// Bytes of the workspace of a truncation with nmax + mmax rows.
+template <class T>
+size_t trunc_workspace_bytes(int64_t nmax, int64_t mmax);
 
 struct Prob;
 

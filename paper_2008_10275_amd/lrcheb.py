@@ -85,6 +85,9 @@ _SIGS = {
     "lrc_truncate_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P, C.c_int, _P,
                                    _P, C.c_int, C.c_int, C.c_double, _P, C.c_int, _P, _P,
                                    C.c_int, C.POINTER(C.c_int)]),
+    "lrc_truncate_noalloc_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, _P,
+                                           C.c_int, _P, _P, C.c_int, C.c_int, C.c_double, _P,
+                                           C.c_int, _P, _P, C.c_int, C.POINTER(C.c_int)]),
     "lrc_truncate_scaled_dev": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, _P,
                                           C.c_int, _P, _P, C.c_int, _P, C.c_int, C.c_double, _P,
                                           C.c_int, _P, _P, C.c_int, C.POINTER(C.c_int)]),
@@ -478,8 +481,9 @@ def profile_read():
             for i in range(n)}
 
 
-def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V):
-    """lrc_truncate_dev on row-major device tensors; returns (s, rank)."""
+def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V, noalloc=False):
+    """lrc_truncate_dev on row-major device tensors; returns (s, rank).
+    noalloc=True calls lrc_truncate_noalloc_dev (fixed per-device scratch)."""
     import torch
     dtype = 0 if A.dtype == torch.float64 else 1
     cc = _f64(np.ravel(c))
@@ -489,10 +493,10 @@ def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V):
         raise ValueError("A and B need at least len(c) columns")
     s = np.zeros(64)
     r = C.c_int()
-    _check(ctx.handle, load().lrc_truncate_dev(ctx.handle, dtype, n, m, k, _dev_ptr(A),
-                                               A.stride(0), _ptr(cc), _dev_ptr(B), B.stride(0),
-                                               rank_cap, tol, _dev_ptr(U), U.stride(0), _ptr(s),
-                                               _dev_ptr(V), V.stride(0), C.byref(r)))
+    fn = load().lrc_truncate_noalloc_dev if noalloc else load().lrc_truncate_dev
+    _check(ctx.handle, fn(ctx.handle, dtype, n, m, k, _dev_ptr(A), A.stride(0), _ptr(cc),
+                          _dev_ptr(B), B.stride(0), rank_cap, tol, _dev_ptr(U), U.stride(0),
+                          _ptr(s), _dev_ptr(V), V.stride(0), C.byref(r)))
     return s[:r.value].copy(), r.value
 
 
