@@ -56,11 +56,29 @@ enum {
  * one ChebyshevT whose iterate and residual (SpMM and truncation) are fp64
  * while the preconditioner solves and the direction updates run in fp32. */
 enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2 };
+/* low-rank solver of the update equation (Sec. 4.1 names both): the
+ * preconditioned Chebyshev iteration with truncation, or GMREST, restarted
+ * GMRES with truncation on the left-preconditioned operator in the Frobenius
+ * inner product (fp64 only; needs no spectrum interval; restart = the
+ * Krylov dimension of a cycle; iters counts Arnoldi steps). */
+enum { LRC_SOLVER_CHEBYSHEV = 0, LRC_SOLVER_GMREST = 1 };
 /* initial guess of lrc_solve: none; the upper-median column's solution x~
  * as the fixed term X0 = x~ 1^T; given factors as the fixed term X0.  The
  * guess stays a separate exact term (X = X0 + S) so that truncation errors
- * are relative to the small correction S, not to X. */
-enum { LRC_INIT_ZERO = 0, LRC_INIT_MEDIAN = 1, LRC_INIT_GIVEN = 2 };
+ * are relative to the small correction S, not to X.
+ * LRC_INIT_GIVEN_JUDGED: the given X0 (for instance a surrogate's prediction)
+ * is judged column by column against the median guess x~ 1^T, which is
+ * computed as for LRC_INIT_MEDIAN: column j keeps the guess whose fp64
+ * residual ||(F - L(X0))_j|| is smaller, so X0 = [U0 | x~] diag(s0, 1)
+ * [diag(w) V0 | 1 - w]^T with w_j in {0, 1}; lrc_info.median_fallback_cols
+ * counts the columns where the median guess won.
+ * LRC_INIT_NEWTON: the given X0 is the linearisation point of a Newton step
+ * and F is already that step's right-hand side B (eq. newton_matrix1): S
+ * solves L(S) = F and the solution is X = X0 + S (Sec. 3.4,
+ * eq. matrix_nextiterate1); residuals are those of the Newton equation,
+ * ||F - L(S)||. */
+enum { LRC_INIT_ZERO = 0, LRC_INIT_MEDIAN = 1, LRC_INIT_GIVEN = 2, LRC_INIT_GIVEN_JUDGED = 3,
+       LRC_INIT_NEWTON = 4 };
 
 typedef struct {
   int rank_cap;        /* R: maximum rank of every truncated quantity           */
@@ -82,6 +100,12 @@ typedef struct {
   double inner_trunc_tol; /* truncation tolerance of the fp32 steps (<= 0: for
                           LRC_MIXED_FP32 max(trunc_tol, 1e-2 * inner_tol), for
                           LRC_MIXED_FP32_DIR max(trunc_tol, 1e-6))                 */
+  double res_ref;      /* reference norm of the residual tests (> 0), replacing
+                          ||F||_F: stop at ||resid||_F <= res_tol * res_ref,
+                          relres = ||resid||_F / res_ref, max_col_relres per
+                          column against res_ref / sqrt(m); 0: ||F||_F and
+                          ||F_j|| (the Newton driver passes ||b|| sqrt(m))    */
+  int solver;          /* LRC_SOLVER_CHEBYSHEV (default) or LRC_SOLVER_GMREST   */
 } lrc_opts;
 
 typedef struct {
@@ -96,8 +120,16 @@ typedef struct {
   double max_col_relres; /* max_j ||(F - L(X))_j|| / ||F_j|| (fp64 entry-wise)   */
   double seconds_setup;  /* factorisation of the preconditioner (host + upload)  */
   double seconds_solve;  /* lrc_solve wall time                                  */
-  int info_flags;        /* bit 0: shifted Cholesky used; bit 1: breakdown; bit 2: eigen not converged */
+  int info_flags;        /* bit 0: shifted Cholesky used; bit 1: breakdown; bit 2: eigen
+                            not converged; bit 4: the median solve stopped above its
+                            tolerance (its iterate kept as the guess, since it still
+                            reduces the column's residual); bit 5: the median solve
+                            failed (non-finite or no reduction) and the zero guess
+                            was used instead                                       */
   int status;            /* this problem's outcome: LRC_OK or LRC_ENOTCONV       */
+  int newton_steps;      /* Newton steps of the median problem (Algorithm 1 driver) */
+  int median_fallback_cols; /* LRC_INIT_GIVEN_JUDGED: columns where the median guess
+                            replaced the given one                                 */
 } lrc_info;
 
 /* Default options (rank cap 20, tol 1e-8, res_tol 1e-8, restart 6, fp64). */
@@ -125,7 +157,12 @@ void lrc_ops_destroy(lrc_ops ops);
 /* W_i = K_i U for all i (device, row-major).  dtype 0: fp64, 1: fp32.
  * U: n x r with ld ldu; W: q blocks of n x r with ld ldw, block i at
  * W + i * n * ldw.  ldu, ldw multiples of 8, r <= min(ldu, ldw) <= 256; U and W
- * 16-byte aligned (LRC_EINVAL otherwise).  Columns of W past r are not written. */
+ * 16-byte aligned (LRC_EINVAL otherwise).  Columns of W past r are not written.
+ * dtype | LRC_SPMM_SKIP_EMPTY: only the rows of W_i whose row of K_i holds
+ * entries are computed and written (the others are left untouched: the caller
+ * keeps them zero); this is the form the solver's own products use, since
+ * K_1, K_2 of the paper's structure live on the solid part only. */
+enum { LRC_SPMM_SKIP_EMPTY = 4 };
 lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U_dev, int ldu,
                             void* W_dev, int ldw);
 /* SpMM autotuning for this operator set at width r (dtype 0/1): times every
@@ -294,17 +331,77 @@ int lrc_profile_read(int ncls, double* ms, int* count, double* work, int* unit);
 const char* lrc_profile_class_name(int c);
 
 /* --------------------------------------------------------------- Algorithm 1
- * Split m columns into K subsets (sizes NULL: eq. clustering1 of Sec. 3.3),
- * and for each subset k: factorise the centre preconditioner, solve the upper
- * median problem, one low-rank Newton step.  The callback supplies, per subset,
- * the operator values of the linearisation point (val_out[i] has nnz_i
- * entries; leave untouched to keep the current values) and returns 0.
- * Results: out[k] receives the subset's problem (owned by the caller, free with
- * lrc_prob_destroy); info[k] its statistics (may be NULL). */
-typedef int (*lrc_linearize_fn)(void* user, int k, const double* xtilde, double* const* val_out);
+ * Linearisation callback.  stage 0 (Newton, Sec. 3.4): at the point x (n
+ * values) write the values of the Jacobian's operators J_i(x) into val_out[i]
+ * (nnz_i values on operator i's fixed pattern, prefilled with the current
+ * values: leave untouched to keep them) and the factors of the Newton step's
+ * right-hand side B_k(x) = BU BV^T (eq. rhs_matrix1): column j of B_k(x) is
+ * the nonlinear residual b - g(x, p_j) of the subset's parameter column j.
+ * stage 1 (fixed point, Sec. 5.3, eq. picard_matrix1): the operators of the
+ * fixed-point linearisation at x and the right-hand side b 1^T of the
+ * equation for X itself.  *rB in [1, 8] columns: BU is n x rB (column-major,
+ * ld n), BV m_k x rB (column-major, ld m_k), where m_k is the subset's size
+ * and its columns are those of d starting at the subset's offset.  *bnorm
+ * receives ||b||_2, the load vector's norm, against which residuals are
+ * reported relative (||residual_j|| / ||b||).  Returns 0, or non-zero to abort
+ * the driver with LRC_ECALLBACK. */
+typedef int (*lrc_linearize_fn)(void* user, int k, int stage, const double* x,
+                                double* const* val_out, int* rB, double* BU, double* BV,
+                                double* bnorm);
+
+/* Algorithm 1 (Sec. 4.1).  Split the m parameter columns of d (q x m,
+ * column-major) into K consecutive subsets (sizes: K values, NULL = eq.
+ * clustering1 of Sec. 3.3: floor(m / K) each, the remainder on the last),
+ * and for every subset k:
+ *   1. Newton on the upper-median column (Sec. 3.3, 0-based offset
+ *      floor(m_k / 2)) starting from x~^{k-1} (x_init, NULL = zero, for k = 0):
+ *      at each iterate x the callback gives J(x) and B_k(x); the step
+ *      A(x, p_med) dx = B_k(x) e_med is solved on the GPU (preconditioned
+ *      vector Chebyshev to opts->median_tol relative) until
+ *      ||B_k(x) e_med||_2 <= eps_newton (absolute, as Sec. 4.1), at most
+ *      newton_max steps; the last callback's point is x~^k;
+ *   2. the centre preconditioner is factorised for J(x~^k) (re-factorised
+ *      whenever an iterate changes the operator values);
+ *   3. picard = 0: one low-rank Newton step L(S) = B_k(x~^k) with
+ *      X^k = x~^k 1^T + S (LRC_INIT_NEWTON); picard = 1: the fixed-point
+ *      variant, X^k solves L_F(X) = b 1^T directly from zero with the stage-1
+ *      operators (eq. picard_matrix1).
+ * cb NULL: the operators are linear (J = K) and B_k(x) = f 1^T - L(x 1^T),
+ * with f (n values) the load vector; f is ignored when cb is given.
+ * Results: out[k] receives the subset's problem (owned by the caller, free
+ * with lrc_prob_destroy; its solution is X^k); info[k] (may be NULL) its
+ * statistics, relative to ||b|| sqrt(m_k); sizes_out (K values, may be NULL)
+ * the subset sizes used.  Returns the worst per-subset status. */
 lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
-                              const int64_t* sizes, const double* f, lrc_linearize_fn cb,
-                              void* user, const lrc_opts* opts, lrc_prob* out, lrc_info* info);
+                              const int64_t* sizes, const double* f, const double* x_init,
+                              lrc_linearize_fn cb, void* user, double eps_newton,
+                              int newton_max, int picard, const lrc_opts* opts, lrc_prob* out,
+                              lrc_info* info, int64_t* sizes_out);
+
+/* --------------------------------------------------------------- theta-scheme
+ * Time stepping of one parameter subset (Sec. 4.3, eq. timedep_matrix1) for
+ * the linear problem M X'(t) + L(X) = b(t) 1^T with the theta-scheme: step i
+ * solves L_theta(X^i) = F_i with L_theta(X) = (1/dt) M X + theta L(X) (the
+ * q-term solver on K'_0 = M/dt + theta K_0, K'_i = theta K_i, same table d)
+ * and F_i = theta b^i 1^T + (1 - theta) b^{i-1} 1^T + (1/dt) M X^{i-1}
+ * - (1 - theta) G, through lrc_solve with the median initial term, so that
+ * X^i = x~^i 1^T + S^i.  history 0: G = L(X^{i-1}) exactly (rank q times the
+ * iterate's); history 1: G = L(x~^{i-1} 1^T), rank <= q (the paper's
+ * approximation of the previous step's residual term; equal for theta = 1).
+ * M: n x n CSR (rowptr n + 1 int64, col int32 sorted, values), copied.
+ * b: n x (steps + 1) column-major, b(t_0) .. b(t_steps).  X(t_0) = U0
+ * diag(s0) V0^T (host column-major, rank r0 in [0, 64]; r0 = 0: zero).
+ * theta in (0, 1], dt > 0, q <= 6.  The preconditioner of L_theta (centre
+ * parameters) is factorised once.  out receives the last step's problem
+ * (its solution is X^steps; free with lrc_prob_destroy); info (steps entries,
+ * may be NULL) each step's statistics.  LRC_EINVAL when a step's F_i would
+ * exceed rank 64 (lower rank_cap or use history 1).  Returns the worst
+ * per-step status. */
+lrc_status lrc_theta_scheme(lrc_ops ops, const int64_t* M_rowptr, const int32_t* M_col,
+                            const double* M_val, int64_t m, const double* d, int steps,
+                            const double* b, int r0, const double* U0, const double* s0,
+                            const double* V0, double theta, double dt, int history,
+                            const lrc_opts* opts, lrc_prob* out, lrc_info* info);
 
 #ifdef __cplusplus
 }

@@ -196,7 +196,8 @@ struct MedianBatch {
     return *bufs.back();
   }
 
-  void solve(std::vector<SolveRun*>& run, hipStream_t s_, bool eager) {
+  // seed: hand each item's solution to its run as the fixed term X0 = x 1^T
+  void solve(std::vector<SolveRun*>& run, hipStream_t s_, bool eager, bool seed = true) {
     s = s_;
     nb = int(run.size());
     rep.eager = eager;
@@ -224,7 +225,11 @@ struct MedianBatch {
         ensure(*d, col);
         LRC_HIP(hipMemsetAsync(d->p, 0, col, s));
       }
+      // the median SpMM visits only non-empty operator rows: a fresh product
+      // buffer starts as zeros and its other rows stay so
+      const bool fresh_w = x.W.bytes < col * op.q;
       ensure(x.W, col * op.q);
+      if (fresh_w) LRC_HIP(hipMemsetAsync(x.W.p, 0, x.W.bytes, s));
       ensure(x.pcb, size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * 8 * 8);
       ensure(x.pst, size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * 8 * 8);
       ensure(x.part, size_t(med_partials()) * 8);
@@ -234,7 +239,7 @@ struct MedianBatch {
       double* Wp[kMaxOps];
       for (int i = 0; i < op.q; ++i) Wp[i] = x.W.as<double>() + size_t(i) * n * 8;
       sl.push_back(make_spmm<double>(op.d64.data(), op.q, x.x.as<double>(), 8, nullptr, 1, 1, Wp,
-                                     8, spmm_config<double>(op, 1)));
+                                     8, spmm_config<double>(op, 1), true));
       sa.push_back(sl.back().a);
       pi.push_back(PrecItem<double>{P.prec->p64.fw, P.prec->p64.bw, x.r.as<double>(), 8,
                                     x.z.as<double>(), 8, nullptr, 1, x.py.as<double>(),
@@ -282,7 +287,12 @@ struct MedianBatch {
         }
       });
     }
-    for (int j = 0; j < nb; ++j) run[j]->set_median_x0(b[j]->x.as<double>(), hctl[j].iters);
+    for (int j = 0; j < nb && seed; ++j) {
+      double fn = 0.0;
+      for (double v : run[j]->fmed) fn += v * v;
+      run[j]->set_median_x0(b[j]->x.as<double>(), hctl[j].iters, hctl[j].state, hctl[j].norm,
+                            std::sqrt(fn));
+    }
     if (log_on())
       for (int j = 0; j < nb; ++j)
         std::fprintf(stderr, "{\"median\": %d, \"iters\": %d, \"norm\": %.6e, \"state\": %d}\n", j,
@@ -656,7 +666,7 @@ void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
   bool any = false;
   for (int j = 0; j < nb; ++j) {
     SolveRun& r = *run[j];
-    if (r.P->rank_x0 == 0) {
+    if (r.P->rank_x0 == 0 || r.newton_point) {
       LRC_CHECK(r.P->rF <= r.B64.cap, ST_EINVAL,
                 "right-hand side rank exceeds the room left by q * rank_cap in 128 columns");
       cast_lr<double, double>(r.P->F64, r.B64, s);
@@ -691,6 +701,75 @@ void build_rhs(std::vector<SolveRun*>& run, const lrc_opts& o, hipStream_t s) {
 
 }  // namespace
 
+int median_column_solve(Prob& P, const std::vector<double>& rhs, double tol, bool eager,
+                        std::vector<double>& x, int* iters) {
+  LRC_CHECK(P.prec != nullptr, ST_EINVAL, "median solve: the problem has no preconditioner");
+  const Ops& op = *P.ops;
+  const int64_t n = op.n, m = P.m;
+  LRC_CHECK(int64_t(rhs.size()) == n, ST_EINVAL, "median solve: right-hand side length");
+  SolveRun r;
+  r.P = &P;
+  r.jmed = int(m / 2);
+  double lo = 1.0, hi = 1.0;
+  for (int i = 0; i < op.q; ++i) {
+    const double rt = P.d[size_t(r.jmed) * op.q + i] / P.dbar[i];
+    lo = std::min(lo, rt);
+    hi = std::max(hi, rt);
+  }
+  r.cm = std::max(0.5 * (hi - lo), 1e-3 * 0.5 * (hi + lo));
+  r.dm = 0.5 * (hi + lo);
+  r.fmed = rhs;
+  r.coefmed.resize(op.q);
+  for (int i = 0; i < op.q; ++i) r.coefmed[i] = P.d[size_t(r.jmed) * op.q + i];
+  r.median_tol = tol;
+  Ctx& cx = *P.ctx;
+  cx.sync();
+  int state = 0;
+  {
+    OwnStream own;
+    MedianBatch mb;
+    std::vector<SolveRun*> v{&r};
+    mb.solve(v, own.s, eager, false);
+    DevBuf xc(size_t(n) * 8);
+    launch_copy_cols(r.med.x.as<double>(), 8, xc.as<double>(), 1, n, 1, own.s);
+    x.resize(n);
+    LRC_HIP(hipMemcpyAsync(x.data(), xc.p, size_t(n) * 8, hipMemcpyDeviceToHost, own.s));
+    LRC_HIP(hipStreamSynchronize(own.s));
+    if (iters) *iters = mb.hctl[0].iters;
+    state = mb.hctl[0].state;
+  }
+  return state;
+}
+
+void ops_apply_block(Ops& o, const std::vector<double>& X, int w, std::vector<double>& W) {
+  const int64_t n = o.n;
+  LRC_CHECK(w >= 1 && w <= 64 && int64_t(X.size()) == n * w, ST_EINVAL,
+            "operator apply: block shape");
+  hipStream_t s = o.ctx->stream;
+  const int ld = ld_for(w);
+  std::vector<double> xb(size_t(n) * ld, 0.0);
+  for (int a = 0; a < w; ++a)
+    for (int64_t i = 0; i < n; ++i) xb[size_t(i) * ld + a] = X[size_t(a) * n + i];
+  DevBuf xd = upload(xb, s), wd(size_t(o.q) * n * ld * 8);
+  double* Wp[kMaxOps];
+  for (int i = 0; i < o.q; ++i) Wp[i] = wd.as<double>() + size_t(i) * n * ld;
+  enqueue_spmm(make_spmm<double>(o.d64.data(), o.q, xd.as<double>(), ld, nullptr, w, w, Wp, ld,
+                                 spmm_config<double>(o, w)),
+               Batched<SpmmArgs<double>>(), s);
+  std::vector<double> h(size_t(o.q) * n * ld);
+  LRC_HIP(hipMemcpyAsync(h.data(), wd.p, h.size() * 8, hipMemcpyDeviceToHost, s));
+  LRC_HIP(hipStreamSynchronize(s));
+  W.assign(size_t(o.q) * n * w, 0.0);
+  for (int i = 0; i < o.q; ++i)
+    for (int a = 0; a < w; ++a)
+      for (int64_t r = 0; r < n; ++r)
+        W[(size_t(i) * w + a) * n + r] = h[(size_t(i) * n + r) * ld + a];
+}
+
+void ops_apply_vector(Ops& o, const std::vector<double>& x, std::vector<double>& W) {
+  ops_apply_block(o, x, 1, W);
+}
+
 void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   const int nb = int(run.size());
   LRC_CHECK(nb >= 1, ST_EINVAL, "lockstep: no problems");
@@ -718,6 +797,9 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       cx.sync();
     }
   }
+  // judged initial terms: the given guess against the median's, per column
+  for (auto* r : run)
+    if (r->judged) r->judge_guess();
   const double t_median = since();
   // 2. right-hand sides B = F - L(X0)
   build_rhs(run, o, s);
@@ -734,7 +816,7 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   // ||B||: from the right-hand side's truncation, or ||F|| when B = F
   std::vector<double> bn(nb);
   for (int j = 0; j < nb; ++j) {
-    if (run[j]->P->rank_x0 == 0) {
+    if (run[j]->P->rank_x0 == 0 || run[j]->newton_point) {
       bn[j] = run[j]->P->fnorm;
     } else {
       LRC_HIP(hipMemcpyAsync(&bn[j], run[j]->c64->norm.as<double>() + 4, 8,
@@ -757,6 +839,11 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       run[j]->last = bd.hctl[j].last;
       run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
       run[j]->flags |= read_info(run[j]->c32->tr.st.info, s);
+    }
+  } else if (o.precision == LRC_FP64 && o.solver == LRC_SOLVER_GMREST) {
+    for (int j = 0; j < nb; ++j) {
+      gmrest_solve(*run[j], o, s);
+      run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
     }
   } else if (o.precision == LRC_FP64) {
     BatchCheb<double> bc;

@@ -419,8 +419,19 @@ lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* r
       int64_t maxrow = 0;
       for (int64_t r = 0; r < n; ++r) maxrow = std::max<int64_t>(maxrow, rp[r + 1] - rp[r]);
       const int mr = int(std::min<int64_t>(maxrow, 1 << 30));
-      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz, mr});
-      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz, mr});
+      // the rows that hold entries (a list only when some rows are empty)
+      std::vector<int> nz;
+      for (int64_t r = 0; r < n; ++r)
+        if (rp[r + 1] > rp[r]) nz.push_back(int(r));
+      const bool list = int64_t(nz.size()) < n;
+      O.rowlist.push_back(list ? upload(nz, s) : DevBuf());
+      LRC_HIP(hipStreamSynchronize(s));   // nz is a temporary
+      const int* rl = list ? O.rowlist.back().as<int>() : nullptr;
+      const int64_t nr = list ? int64_t(nz.size()) : n;
+      O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz,
+                       mr, rl, nr});
+      O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz,
+                       mr, rl, nr});
     }
     *out = o.release();
     return LRC_OK;
@@ -447,6 +458,8 @@ lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U, int ld
   if (!ops) return LRC_EINVAL;
   return guarded(ops->o.ctx, [&]() -> lrc_status {
     const Ops& o = ops->o;
+    const bool skip = (dtype & LRC_SPMM_SKIP_EMPTY) != 0;
+    dtype &= ~LRC_SPMM_SKIP_EMPTY;
     LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "spmm: dtype must be 0 (fp64) or 1 (fp32)");
     LRC_CHECK(r >= 1 && r <= (dtype == 0 ? 128 : 256), ST_EINVAL, "spmm: r out of range");
     LRC_CHECK(U && W, ST_EINVAL, "spmm: null pointer");
@@ -454,14 +467,14 @@ lrc_status lrc_ops_spmm_dev(lrc_ops ops, int dtype, int r, const void* U, int ld
       double* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<double*>(W) + size_t(i) * o.n * ldw;
       auto l = make_spmm<double>(o.d64.data(), o.q, static_cast<const double*>(U), ldu, nullptr,
-                                 r, r, Wp, ldw, spmm_config<double>(o, r));
+                                 r, r, Wp, ldw, spmm_config<double>(o, r), skip);
       l.a.wpad = 0;   // the caller's W: columns past r are left untouched
       enqueue_spmm(l, Batched<SpmmArgs<double>>(), o.ctx->stream);
     } else {
       float* Wp[kMaxOps];
       for (int i = 0; i < o.q; ++i) Wp[i] = static_cast<float*>(W) + size_t(i) * o.n * ldw;
       auto l = make_spmm<float>(o.d32.data(), o.q, static_cast<const float*>(U), ldu, nullptr, r,
-                                r, Wp, ldw, spmm_config<float>(o, r));
+                                r, Wp, ldw, spmm_config<float>(o, r), skip);
       l.a.wpad = 0;
       enqueue_spmm(l, Batched<SpmmArgs<float>>(), o.ctx->stream);
     }
@@ -694,8 +707,10 @@ lrc_status lrc_solve_x0_dev(lrc_prob prob, const lrc_opts* opts, int r0, const d
   Prob& P = prob->p;
   return guarded(P.ctx, [&]() -> lrc_status {
     LRC_HIP(hipSetDevice(P.ctx->device));
-    LRC_CHECK(opts->init == LRC_INIT_GIVEN && r0 >= 1, ST_EINVAL,
-              "lrc_solve_x0_dev: needs init = LRC_INIT_GIVEN and r0 >= 1");
+    LRC_CHECK((opts->init == LRC_INIT_GIVEN || opts->init == LRC_INIT_GIVEN_JUDGED ||
+               opts->init == LRC_INIT_NEWTON) && r0 >= 1,
+              ST_EINVAL, "lrc_solve_x0_dev: needs a given initial term (init GIVEN, "
+                         "GIVEN_JUDGED or NEWTON) and r0 >= 1");
     const X0Dev xd{U0_dev, ldu, V0_dev, ldv};
     return solve_problem(P, *opts, r0, nullptr, s0, nullptr, info, &xd);
   });
@@ -708,7 +723,7 @@ lrc_status lrc_solve_batched(lrc_prob* probs, int K, const lrc_opts* opts, lrc_i
   Ctx* cx = probs[0]->p.ctx;
   return guarded(cx, [&]() -> lrc_status {
     LRC_HIP(hipSetDevice(cx->device));
-    LRC_CHECK(opts->init != LRC_INIT_GIVEN, ST_EINVAL,
+    LRC_CHECK(opts->init == LRC_INIT_ZERO || opts->init == LRC_INIT_MEDIAN, ST_EINVAL,
               "lrc_solve_batched: given initial terms are not supported (use lrc_solve)");
     std::vector<Prob*> ps(K);
     for (int k = 0; k < K; ++k) ps[k] = &probs[k]->p;
@@ -759,7 +774,10 @@ lrc_status lrc_residual(lrc_prob prob, double* relres, double* colres) {
   Prob& P = prob->p;
   return guarded(P.ctx, [&]() -> lrc_status {
     LRC_CHECK(P.S.U.p != nullptr, ST_EINVAL, "lrc_residual: nothing solved yet");
-    *relres = residual_fp64(P, P.X0, P.rank_x0, P.S, colres) / P.fnorm;
+    // the last solve's convention: a Newton step's linearisation point is not
+    // part of its equation; residuals relative to its reference norm
+    *relres = residual_fp64(P, P.X0, P.newton_point ? 0 : P.rank_x0, P.S, colres) /
+              (P.ref > 0.0 ? P.ref : P.fnorm);
     return LRC_OK;
   });
 }
@@ -870,12 +888,17 @@ lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m,
 }
 
 lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
-                              const int64_t* sizes, const double* f, lrc_linearize_fn cb,
-                              void* user, const lrc_opts* opts, lrc_prob* out, lrc_info* info) {
-  if (!ops || !opts || !out || !d || !f) return LRC_EINVAL;
+                              const int64_t* sizes, const double* f, const double* x_init,
+                              lrc_linearize_fn cb, void* user, double eps_newton,
+                              int newton_max, int picard, const lrc_opts* opts, lrc_prob* out,
+                              lrc_info* info, int64_t* sizes_out) {
+  if (!ops || !opts || !out || !d) return LRC_EINVAL;
   Ops& base = ops->o;
   return guarded(base.ctx, [&]() -> lrc_status {
     LRC_CHECK(K >= 1 && K <= m, ST_EINVAL, "newton_subsets: need 1 <= K <= m");
+    LRC_CHECK(cb || f, ST_EINVAL, "newton_subsets: a callback or the load vector f is required");
+    LRC_CHECK(eps_newton > 0.0 && newton_max >= 1, ST_EINVAL,
+              "newton_subsets: need eps_newton > 0 and newton_max >= 1");
     std::vector<int64_t> sz(K);
     if (sizes) {
       int64_t tot = 0;
@@ -890,15 +913,27 @@ lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
       for (int k = 0; k < K - 1; ++k) sz[k] = m / K;
       sz[K - 1] = m - (K - 1) * (m / K);
     }
+    if (sizes_out) std::copy(sz.begin(), sz.end(), sizes_out);
     for (int k = 0; k < K; ++k) out[k] = nullptr;
     const int q = base.q;
     const int64_t n = base.n;
-    std::vector<double> prev_x;
+    constexpr int kMaxRb = 8;
+    lrc_ctx_s* cx = static_cast<lrc_ctx_s*>(base.ctx->handle);
+    // the point of the first median Newton iteration, then x~^{k-1}
+    std::vector<double> x(n, 0.0);
+    if (x_init) std::copy(x_init, x_init + n, x.begin());
+    double fnrm = 0.0;
+    if (f)
+      for (int64_t i = 0; i < n; ++i) fnrm += f[i] * f[i];
+    fnrm = std::sqrt(fnrm);
     lrc_status worst = LRC_OK;
     int64_t off = 0;
     for (int k = 0; k < K; ++k) {
+      const int64_t mk = sz[k];
+      const double* dk = d + size_t(off) * q;
+      const int jmed = int(mk / 2);   // upper median (Sec. 3.3)
       // private operators for this subset's linearisation point
-      auto so = std::make_unique<lrc_ops_s>();
+      std::unique_ptr<lrc_ops_s> so;
       {
         std::vector<const int64_t*> rp(q);
         std::vector<const int32_t*> cl(q);
@@ -909,48 +944,128 @@ lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
           vl[i] = base.host[i].val.data();
         }
         lrc_ops tmp = nullptr;
-        lrc_ctx_s* cx = static_cast<lrc_ctx_s*>(base.ctx->handle);
         const lrc_status st = lrc_ops_create(cx, n, q, rp.data(), cl.data(), vl.data(), &tmp);
         if (st != LRC_OK) return st;
         so.reset(tmp);
       }
-      if (cb) {
-        std::vector<std::vector<double>> vals(q);
-        std::vector<double*> vp(q);
+      std::vector<std::vector<double>> vals(q);
+      std::vector<double*> vp(q);
+      std::vector<double> BU(size_t(n) * kMaxRb), BV(size_t(mk) * kMaxRb);
+      int rB = 0;
+      double bnorm = 0.0;
+      std::vector<double> W;
+      // one linearisation at x: operator values (uploaded when changed) and
+      // the right-hand side factors; returns whether the values changed
+      auto linearize = [&](int stage) -> bool {
         for (int i = 0; i < q; ++i) {
           vals[i] = so->o.host[i].val;
           vp[i] = vals[i].data();
         }
-        const int rc = cb(user, k, prev_x.empty() ? nullptr : prev_x.data(), vp.data());
-        if (rc != 0) throw Error(ST_ECALLBACK, "newton_subsets: callback returned non-zero");
+        if (cb) {
+          rB = 0;
+          bnorm = 0.0;
+          const int rc = cb(user, k, stage, x.data(), vp.data(), &rB, BU.data(), BV.data(), &bnorm);
+          if (rc != 0) throw Error(ST_ECALLBACK, "newton_subsets: callback returned non-zero");
+          LRC_CHECK(rB >= 1 && rB <= kMaxRb, ST_EINVAL,
+                    "newton_subsets: callback right-hand side rank must be in [1, 8]");
+          LRC_CHECK(std::isfinite(bnorm) && bnorm > 0.0, ST_EINVAL,
+                    "newton_subsets: callback must give a positive ||b||");
+        } else {
+          // linear operators: B_k(x) = f 1^T - sum_i (K_i x) d_i^T (stage 0),
+          // b 1^T = f 1^T (stage 1)
+          bnorm = fnrm;
+          std::copy(f, f + n, BU.begin());
+          for (int64_t j = 0; j < mk; ++j) BV[size_t(j)] = 1.0;
+          rB = 1;
+          bool nz = false;
+          for (int64_t i = 0; i < n && !nz; ++i) nz = x[i] != 0.0;
+          if (stage == 0 && nz) {
+            ops_apply_vector(so->o, x, W);
+            for (int i = 0; i < q; ++i) {
+              for (int64_t r = 0; r < n; ++r) BU[size_t(1 + i) * n + r] = -W[size_t(i) * n + r];
+              for (int64_t j = 0; j < mk; ++j) BV[size_t(1 + i) * mk + j] = dk[size_t(j) * q + i];
+            }
+            rB = 1 + q;
+          }
+        }
+        bool changed = false;
         for (int i = 0; i < q; ++i)
           if (vals[i] != so->o.host[i].val) {
+            for (double v : vals[i])
+              LRC_CHECK(std::isfinite(v), ST_EINVAL, "newton_subsets: non-finite operator value");
             std::copy(vals[i].begin(), vals[i].end(), so->o.host[i].val.begin());
             so->o.upload_values(i);
+            changed = true;
           }
+        return changed;
+      };
+      // a problem on the current operators with F = BU BV^T (rank rB); the
+      // factorisation is carried over from `keep` unless the values changed
+      std::unique_ptr<lrc_prob_s> pb;
+      auto make_prob = [&](bool refactor) {
+        lrc_prob tmp = nullptr;
+        lrc_status st = lrc_prob_create(so.get(), mk, dk, rB, BU.data(), nullptr, BV.data(), &tmp);
+        if (st != LRC_OK) throw Error(st, lrc_last_error(cx));
+        std::unique_ptr<lrc_prob_s> np(tmp);
+        if (refactor || !pb || !pb->p.prec) {
+          st = lrc_prob_precondition(np.get(), nullptr, 0);
+          if (st != LRC_OK) throw Error(st, lrc_last_error(cx));
+        } else {
+          np->p.prec = std::move(pb->p.prec);
+          np->p.seconds_setup = pb->p.seconds_setup;
+        }
+        pb = std::move(np);
+      };
+      // 1. Newton on the upper-median column from x~^{k-1}
+      int steps = 0, med_iters = 0;
+      bool refactor = true;
+      for (;;) {
+        refactor = linearize(0) || refactor;
+        make_prob(refactor);
+        refactor = false;
+        // the median column's nonlinear residual B_k(x) e_med
+        std::vector<double> r(n, 0.0);
+        for (int a = 0; a < rB; ++a) {
+          const double w = BV[size_t(a) * mk + jmed];
+          for (int64_t i = 0; i < n; ++i) r[i] += w * BU[size_t(a) * n + i];
+        }
+        double rn = 0.0;
+        for (double v : r) rn += v * v;
+        rn = std::sqrt(rn);
+        LRC_CHECK(std::isfinite(rn), ST_EINVAL, "newton_subsets: non-finite median residual");
+        if (rn <= eps_newton || steps >= newton_max) break;
+        std::vector<double> dx;
+        int it = 0;
+        median_column_solve(pb->p, r, opts->median_tol > 0 ? opts->median_tol : 1e-6,
+                            opts->eager != 0, dx, &it);
+        med_iters += it;
+        for (int64_t i = 0; i < n; ++i) x[i] += dx[i];
+        ++steps;
       }
-      std::vector<double> ones(sz[k], 1.0);
-      lrc_prob pb = nullptr;
-      lrc_status st = lrc_prob_create(so.get(), sz[k], d + size_t(off) * q, 1, f, nullptr,
-                                      ones.data(), &pb);
-      if (st != LRC_OK) return st;
-      pb->owned_ops = std::move(so);
-      out[k] = pb;
-      st = lrc_prob_precondition(pb, nullptr, 0);
-      if (st != LRC_OK) return st;
+      // 2./3. the subset's step at x~^k
       lrc_opts o = *opts;
-      o.init = LRC_INIT_MEDIAN;
+      o.res_ref = bnorm * std::sqrt(double(mk));
+      lrc_status st;
       lrc_info inf{};
-      st = lrc_solve(pb, &o, 0, nullptr, nullptr, nullptr, &inf);
+      if (!picard) {
+        // Newton: L(S) = B_k(x~^k), X^k = x~^k 1^T + S
+        o.init = LRC_INIT_NEWTON;
+        std::vector<double> ones(size_t(mk), 1.0);
+        st = lrc_solve(pb.get(), &o, 1, x.data(), nullptr, ones.data(), &inf);
+      } else {
+        // fixed point: L_F(X) = b 1^T from zero with the stage-1 operators
+        make_prob(linearize(1));
+        o.init = LRC_INIT_ZERO;
+        st = lrc_solve(pb.get(), &o, 0, nullptr, nullptr, nullptr, &inf);
+      }
       if (st < 0) return st;
       if (st > worst) worst = st;
+      inf.newton_steps = steps;
+      inf.median_iters = med_iters;
       if (info) info[k] = inf;
-      // keep x~ of this subset for the next callback
-      prev_x.resize(n);
-      std::vector<double> u(size_t(n) * pb->p.X0.ld);
-      LRC_HIP(hipMemcpy(u.data(), pb->p.X0.U.p, u.size() * 8, hipMemcpyDeviceToHost));
-      for (int64_t i = 0; i < n; ++i) prev_x[i] = u[size_t(i) * pb->p.X0.ld];
-      off += sz[k];
+      pb->owned_ops = std::move(so);
+      out[k] = pb.release();
+      off += mk;
     }
     return worst;
   });

@@ -131,21 +131,30 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
   const int64_t first = int64_t(rb) * rows_per_block + int64_t(wave) * rpw + sub;
   const int maxrow = __builtin_amdgcn_readfirstlane(K.maxrow);
   const bool wpad = args.wpad != 0;
+  // with a row list only the non-empty rows are visited (the solid box of
+  // K_1, K_2: a sixth of the rows); the list is read in order, so a wave's
+  // lookups are one contiguous span
+  const int* __restrict__ rl = args.skip_empty ? K.rows : nullptr;
+  const int64_t nvis = rl ? K.nrows : K.n;
   if (maxrow <= 5) {
-    for (int64_t row = first; row < K.n; row += stride)
-      spmm_row<T, NV, 5>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
+    for (int64_t x = first; x < nvis; x += stride)
+      spmm_row<T, NV, 5>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
+                         chunk, wpad);
   } else if (maxrow <= 9) {
-    for (int64_t row = first; row < K.n; row += stride)
-      spmm_row<T, NV, 9>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
+    for (int64_t x = first; x < nvis; x += stride)
+      spmm_row<T, NV, 9>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
+                         chunk, wpad);
   } else {
-    for (int64_t row = first; row < K.n; row += stride)
-      spmm_row<T, NV, 4>(K, row, args.U, args.ldu, W, args.ldw, r, nvec, lpr, chunk, wpad);
+    for (int64_t x = first; x < nvis; x += stride)
+      spmm_row<T, NV, 4>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
+                         chunk, wpad);
   }
 }
 
 template <class T>
 SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
-                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg) {
+                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg,
+                        bool skip_empty) {
   const int cpl = cfg.cpl > 0 ? cfg.cpl : (sizeof(T) == 8 ? 2 : 4);
   LRC_CHECK(q >= 1 && q <= kMaxOps, ST_EINVAL, "spmm: bad operator count");
   LRC_CHECK(rcap >= 1, ST_EINVAL, "spmm: rank capacity must be positive");
@@ -179,6 +188,7 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
   a.r_const = r_const;
   a.ldw = ldw;
   a.wpad = 1;   // the solver's own product buffers; callers' buffers clear it
+  a.skip_empty = skip_empty ? 1 : 0;
   l.cpl = cpl;
   l.nv = nv;
   l.lpr = lpr;
@@ -191,12 +201,15 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
   LRC_CHECK(rbs * q < (int64_t(1) << 31), ST_EINVAL, "spmm: grid too large");
   l.blocks = int(rbs * q);
   l.q = q;
-  // algorithmic bytes: values + int32 columns + row pointers of every operator,
-  // U read once, every W_i written (all n rows)
+  // algorithmic bytes: values + int32 columns of every operator, U read once,
+  // and per visited row its row pointers and its row of W_i (all n rows, or
+  // the non-empty rows with their list entries)
   double fixed = 0.0, wrows = 0.0;
   for (int i = 0; i < q; ++i) {
-    fixed += double(ops[i].nnz) * (sizeof(T) + 4) + double(ops[i].n + 1) * 4;
-    wrows += double(ops[i].n);
+    const bool list = skip_empty && ops[i].rows;
+    fixed += double(ops[i].nnz) * (sizeof(T) + 4) +
+             (list ? double(ops[i].nrows) * 12 : double(ops[i].n + 1) * 4);
+    wrows += list ? double(ops[i].nrows) : double(ops[i].n);
   }
   const double nr = double(n);
   l.work.groups = {{{r_dev, r_const}}};
@@ -232,9 +245,11 @@ void launch_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_
 }
 
 template SpmmLaunch<float> make_spmm<float>(const DevCsr<float>*, int, const float*, int,
-                                            const int*, int, int, float* const*, int, SpmmCfg);
+                                            const int*, int, int, float* const*, int, SpmmCfg,
+                                            bool);
 template SpmmLaunch<double> make_spmm<double>(const DevCsr<double>*, int, const double*, int,
-                                              const int*, int, int, double* const*, int, SpmmCfg);
+                                              const int*, int, int, double* const*, int, SpmmCfg,
+                                              bool);
 template void enqueue_spmm<float>(const SpmmLaunch<float>&, Batched<SpmmArgs<float>>, hipStream_t);
 template void enqueue_spmm<double>(const SpmmLaunch<double>&, Batched<SpmmArgs<double>>,
                                    hipStream_t);

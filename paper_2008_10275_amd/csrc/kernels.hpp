@@ -28,6 +28,8 @@ struct DevCsr {
   int64_t n;
   int64_t nnz;
   int maxrow;   // most entries in one row
+  const int* rows;   // the rows that hold entries, ascending (nullptr: every row does)
+  int64_t nrows;     // their number (n when rows is nullptr)
 };
 
 constexpr int kMaxOps = 8;
@@ -48,6 +50,8 @@ struct SpmmArgs {
   int ldu;
   int ldw;
   int wpad;   // 1: W's columns past the rank, up to 16 bytes, may be overwritten (zeros)
+  int skip_empty;   // 1: only the operators' non-empty rows are visited and written
+                    // (W's other rows are zero from the buffer's set-up and stay so)
 };
 template <class T>
 struct SpmmLaunch {
@@ -68,8 +72,11 @@ struct SpmmCfg {
   int max_blocks = 8192;
 };
 template <class T>
+// skip_empty: visit only the operators' non-empty rows (their row lists), for
+// product buffers whose other rows are zero from their set-up
 SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const int* r_dev,
-                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg);
+                        int r_const, int rcap, T* const* W, int ldw, SpmmCfg cfg,
+                        bool skip_empty = false);
 template <class T>
 void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s);
 

@@ -434,6 +434,9 @@ void Cheb<T>::alloc(Prob* p, int cap_) {
   R.alloc(n, m, cap, s);
   const int ld = ld_for(cap);
   W.alloc(size_t(P->ops->q) * n * ld * sizeof(T));
+  // the SpMM of the iterate visits only the operators' non-empty rows: the
+  // other rows of W stay the zeros written here
+  LRC_HIP(hipMemsetAsync(W.p, 0, W.bytes, s));
   Z.alloc(size_t(n) * ld * sizeof(T));
   py.alloc(size_t(n) * ld * sizeof(T));
   px.alloc(size_t(n) * ld * sizeof(T));
@@ -452,7 +455,7 @@ SpmmLaunch<T> Cheb<T>::spmm_plan(const T* U, int ldu, const int* r_dev) const {
   T* Wp[kMaxOps];
   for (int i = 0; i < o.q; ++i) Wp[i] = W.as<T>() + size_t(i) * o.n * ld;
   return make_spmm<T>(ops_dev<T>(o).data(), o.q, U, ldu, r_dev, 0, cap, Wp, ld,
-                      spmm_config<T>(o, cap));
+                      spmm_config<T>(o, cap), true);
 }
 
 // R = T(B - sum_i K_i S D_i): blocks [B | K_0 S | ... ] and [B_V | D_0 S_V | ...]
@@ -686,10 +689,16 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   }
   c = std::max(c, 1e-12 * dc);
   inf = lrc_info{};
+  LRC_CHECK(o.init >= LRC_INIT_ZERO && o.init <= LRC_INIT_NEWTON, ST_EINVAL,
+            "lrc_solve: unknown init");
+  ref = o.res_ref > 0.0 ? o.res_ref : Pr.fnorm;
+  newton_point = o.init == LRC_INIT_NEWTON;
+  judged = o.init == LRC_INIT_GIVEN_JUDGED;
+  rank_g = 0;
   // fixed initial term X0
   Pr.rank_x0 = 0;
   jmed = -1;
-  if (o.init == LRC_INIT_MEDIAN) {
+  if (o.init == LRC_INIT_MEDIAN || judged) {
     // upper-median column (Sec. 3.3): its system A(d_jmed) x = F e_jmed is
     // solved by the lockstep driver; its own, much narrower, spectrum interval
     jmed = int(m / 2);
@@ -709,39 +718,44 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
     coefmed.resize(op.q);
     for (int i = 0; i < op.q; ++i) coefmed[i] = Pr.d[size_t(jmed) * op.q + i];
     median_tol = o.median_tol > 0 ? o.median_tol : 1e-6;
-  } else if (o.init == LRC_INIT_GIVEN && r0 > 0) {
+  }
+  if ((o.init == LRC_INIT_GIVEN || judged || newton_point) && r0 > 0) {
     LRC_CHECK(r0 <= 64, ST_EINVAL, "lrc_solve: initial rank at most 64");
-    reset_lr(Pr.X0, n, m, r0, s);
+    LR<double>& G = judged ? Xg : Pr.X0;
+    reset_lr(G, n, m, r0, s);
     if (xd) {
       // device factors (row-major fp64): copied, the core from the host
       LRC_CHECK(xd->U && xd->V && xd->ldu >= r0 && xd->ldv >= r0, ST_EINVAL,
                 "lrc_solve_x0_dev: U0 and V0 device factors with ld >= r0 required");
-      launch_copy_cols(xd->U, xd->ldu, Pr.X0.u(), Pr.X0.ld, n, r0, s);
-      launch_copy_cols(xd->V, xd->ldv, Pr.X0.v(), Pr.X0.ld, m, r0, s);
-      std::vector<double> sv(size_t(std::max(Pr.X0.cap, 8)), 0.0);
+      launch_copy_cols(xd->U, xd->ldu, G.u(), G.ld, n, r0, s);
+      launch_copy_cols(xd->V, xd->ldv, G.v(), G.ld, m, r0, s);
+      std::vector<double> sv(size_t(std::max(G.cap, 8)), 0.0);
       for (int j = 0; j < r0; ++j) sv[j] = s0 ? s0[j] : 1.0;
-      LRC_HIP(hipMemcpyAsync(Pr.X0.s.p, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, s));
-      LRC_HIP(hipMemcpyAsync(Pr.X0.rank.p, &r0, sizeof(int), hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(G.s.p, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, s));
+      LRC_HIP(hipMemcpyAsync(G.rank.p, &r0, sizeof(int), hipMemcpyHostToDevice, s));
       LRC_HIP(hipStreamSynchronize(s));   // sv is a temporary
     } else {
-      LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for LRC_INIT_GIVEN");
-      upload_lr(Pr.X0, r0, U0, s0, V0, s);
+      LRC_CHECK(U0 && V0, ST_EINVAL, "lrc_solve: U0 and V0 required for a given initial term");
+      upload_lr(G, r0, U0, s0, V0, s);
     }
-    Pr.rank_x0 = r0;
-  } else {
+    if (judged) rank_g = r0;
+    else Pr.rank_x0 = r0;
+  } else if (o.init != LRC_INIT_MEDIAN) {
+    LRC_CHECK(!judged, ST_EINVAL, "lrc_solve: LRC_INIT_GIVEN_JUDGED needs a given term");
     reset_lr(Pr.X0, n, m, 1, s);
   }
   cap = o.rank_cap;
   // room left for the right-hand side in the residual concatenation
   // [B | K_0 S | ... | K_{q-1} S] of at most 128 columns
   const int room = std::max(8, kTruncCap - op.q * cap);
-  const int bcap = std::min(std::min(64, room), std::max(Pr.rF + op.q, o.init == LRC_INIT_GIVEN ? 64 : 1));
+  const int bcap = std::min(std::min(64, room), std::max(Pr.rF + op.q,
+                                                         o.init == LRC_INIT_GIVEN || judged ? 64 : 1));
   ensure_cheb(c64, P, cap);
   reset_lr(B64, n, m, bcap, s);
   max_iter = o.max_iter > 0 ? o.max_iter : 200;
   // mixed precision: the inner correction's own cap keeps [rhs | K_i E] within 128 columns
   inner_cap = std::max(1, std::min(cap, (kTruncCap - cap) / op.q));
-  target = o.res_tol * Pr.fnorm;
+  target = o.res_tol * ref;
   refine_max = o.refine_max > 0 ? o.refine_max : 8;
   rhs_tol = std::max(o.trunc_tol, 0.1 * (o.inner_tol > 0 ? o.inner_tol : 1e-5));
   // the fp32 inner solve needs no truncation finer than its own target (and
@@ -754,16 +768,31 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   LRC_CHECK(o.precision == LRC_FP64 || o.precision == LRC_MIXED_FP32 ||
                 o.precision == LRC_MIXED_FP32_DIR,
             ST_EINVAL, "lrc_solve: unknown precision");
+  LRC_CHECK(o.solver == LRC_SOLVER_CHEBYSHEV ||
+                (o.solver == LRC_SOLVER_GMREST && o.precision == LRC_FP64),
+            ST_EINVAL, "lrc_solve: unknown solver (GMREST runs in fp64)");
   if (o.precision == LRC_MIXED_FP32) alloc_mixed();
   if (o.precision == LRC_MIXED_FP32_DIR) ensure_cheb(c32, P, cap);   // fp32 direction and Z
 }
 
 // X0 = x 1^T from the median column's solution x (column 0 of an n x 8 block)
-void SolveRun::set_median_x0(const double* x, int iters) {
+void SolveRun::set_median_x0(const double* x, int iters, int state, double norm, double fnorm) {
   Prob& Pr = *P;
   hipStream_t s = Pr.ctx->stream;
   const int64_t n = Pr.ops->n, m = Pr.m;
   reset_lr(Pr.X0, n, m, 1, s);
+  inf.median_iters = iters;
+  if (state != 1) {
+    // the median solve stopped above its tolerance: its iterate is still the
+    // better guess if it reduced the column's residual below ||f_med||
+    // (the zero guess's); otherwise (non-finite, no reduction) X0 = 0
+    flags |= 16;
+    if (!(std::isfinite(norm) && norm < fnorm)) {
+      flags |= 32;
+      Pr.rank_x0 = 0;
+      return;
+    }
+  }
   launch_copy_cols(x, 8, Pr.X0.u(), Pr.X0.ld, n, 1, s);
   std::vector<double> ones(size_t(m) * Pr.X0.ld, 0.0);
   for (int64_t j = 0; j < m; ++j) ones[size_t(j) * Pr.X0.ld] = 1.0;
@@ -774,7 +803,56 @@ void SolveRun::set_median_x0(const double* x, int iters) {
   LRC_HIP(hipMemcpyAsync(Pr.X0.rank.p, &r1, 4, hipMemcpyHostToDevice, s));
   LRC_HIP(hipStreamSynchronize(s));   // `ones` is a temporary
   Pr.rank_x0 = 1;
-  inf.median_iters = iters;
+}
+
+void SolveRun::judge_guess() {
+  Prob& Pr = *P;
+  Ctx& ctx = *Pr.ctx;
+  hipStream_t s = ctx.stream;
+  const int64_t n = Pr.ops->n, m = Pr.m;
+  LR<double> none;
+  none.alloc(n, m, 1, s);   // rank 0
+  // fp64 per-column residuals of both guesses (the median's may be zero)
+  std::vector<double> cmed(m), cgiv(m);
+  residual_fp64(Pr, Pr.X0, Pr.rank_x0, none, cmed.data());
+  residual_fp64(Pr, Xg, rank_g, none, cgiv.data());
+  std::vector<char> w(m);
+  int fb = 0;
+  for (int64_t j = 0; j < m; ++j) {
+    w[j] = cgiv[j] <= cmed[j] ? 1 : 0;
+    fb += w[j] ? 0 : 1;
+  }
+  inf.median_fallback_cols = fb;
+  if (fb == 0) {
+    std::swap(Pr.X0, Xg);
+    Pr.rank_x0 = rank_g;
+    return;
+  }
+  // X0 = [Ug | x~] diag(s_g, 1) [diag(w) Vg | 1 - w]^T (the x~ column only
+  // when the median solve produced one)
+  const int rm = Pr.rank_x0;   // 0 or 1
+  const int r = rank_g + rm;
+  LR<double> X;
+  X.alloc(n, m, r, s);
+  launch_copy_cols(Xg.u(), Xg.ld, X.u(), X.ld, n, rank_g, s);
+  if (rm) launch_copy_cols(Pr.X0.u(), Pr.X0.ld, X.u() + rank_g, X.ld, n, 1, s);
+  std::vector<double> vg(size_t(m) * Xg.ld), sg(size_t(std::max(Xg.cap, 8)));
+  LRC_HIP(hipMemcpyAsync(vg.data(), Xg.V.p, vg.size() * 8, hipMemcpyDeviceToHost, s));
+  LRC_HIP(hipMemcpyAsync(sg.data(), Xg.s.p, sg.size() * 8, hipMemcpyDeviceToHost, s));
+  LRC_HIP(hipStreamSynchronize(s));
+  std::vector<double> v(size_t(m) * X.ld, 0.0), sv(size_t(std::max(X.cap, 8)), 0.0);
+  for (int64_t j = 0; j < m; ++j) {
+    for (int a = 0; a < rank_g; ++a) v[size_t(j) * X.ld + a] = w[j] ? vg[size_t(j) * Xg.ld + a] : 0.0;
+    if (rm) v[size_t(j) * X.ld + rank_g] = w[j] ? 0.0 : 1.0;
+  }
+  for (int a = 0; a < rank_g; ++a) sv[a] = sg[a];
+  if (rm) sv[rank_g] = 1.0;
+  LRC_HIP(hipMemcpyAsync(X.V.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X.s.p, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, s));
+  LRC_HIP(hipMemcpyAsync(X.rank.p, &r, sizeof(int), hipMemcpyHostToDevice, s));
+  LRC_HIP(hipStreamSynchronize(s));   // v and sv are temporaries
+  std::swap(Pr.X0, X);
+  Pr.rank_x0 = r;
 }
 
 // Right-hand side B = F - L(X0), truncated to the rhs capacity at a tolerance
@@ -843,13 +921,15 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
   inf.iters = iters;
   inf.prec_applies = papp;
   inf.refinements = refinements;
-  inf.relres_est = last / Pr.fnorm;
+  inf.relres_est = last / ref;
   inf.relres = inf.relres_est;
   inf.info_flags = flags;
+  Pr.newton_point = newton_point;
+  Pr.ref = ref;
   if (o.verify_fp64) {
     std::vector<double> col(m);
-    const double nr = residual_fp64(Pr, Pr.X0, Pr.rank_x0, Pr.S, col.data());
-    inf.relres = nr / Pr.fnorm;
+    const double nr = residual_fp64(Pr, Pr.X0, newton_point ? 0 : Pr.rank_x0, Pr.S, col.data());
+    inf.relres = nr / ref;
     // per-column relative residuals against ||F_j||, with G = FU^T FU
     std::vector<double> g(size_t(Pr.rF) * Pr.rF, 0.0);
     for (int a = 0; a < Pr.rF; ++a)
@@ -859,7 +939,9 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
         g[size_t(a) * Pr.rF + b] = acc;
       }
     double mx = 0.0;
-    for (int64_t j = 0; j < m; ++j) {
+    for (int64_t j = 0; j < m && o.res_ref > 0.0; ++j)
+      mx = std::max(mx, col[j] * std::sqrt(double(m)) / ref);
+    for (int64_t j = 0; j < m && !(o.res_ref > 0.0); ++j) {
       double fj = 0.0;
       for (int a = 0; a < Pr.rF; ++a)
         for (int b = 0; b < Pr.rF; ++b)

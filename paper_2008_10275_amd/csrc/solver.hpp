@@ -39,6 +39,7 @@ struct Ops {
   int q = 0;
   std::vector<CsrHost> host;
   std::vector<DevBuf> rowptr, col, val64, val32;
+  std::vector<DevBuf> rowlist;   // per operator: its non-empty rows (empty when all are)
   std::vector<DevCsr<double>> d64;
   std::vector<DevCsr<float>> d32;
   void upload_values(int i);
@@ -195,6 +196,10 @@ struct Prob {
   // solution: X = X0 + S (fp64 factors)
   LR<double> X0, S;
   int rank_x0 = 0, rank_s = 0;
+  // the last solve's residual convention: X0 is a linearisation point that
+  // L(S) = F does not include (LRC_INIT_NEWTON), and the reference norm
+  bool newton_point = false;
+  double ref = 0.0;
   LR<double> F64;                  // F as a device LR (fp64)
   // workspaces kept between solves (reallocated only when a shape changes)
   std::unique_ptr<SolveRun> run;
@@ -233,6 +238,17 @@ template <class T>
 BlockView<T> view1(const T* p, int ld, const int* wdev, int wconst, const double* rowscale = nullptr);
 
 double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S, double* colres);
+// ChebyshevT-preconditioned solve of the median column's system
+// A(d[:, jmed]) x = rhs of a preconditioned problem to relative residual
+// `tol` (the lockstep driver's median phase on one problem); returns the
+// iterations and the MedCtl state (1 converged, 2 stopped).
+int median_column_solve(Prob& P, const std::vector<double>& rhs, double tol, bool eager,
+                        std::vector<double>& x, int* iters);
+// Device fp64 SpMM W_i = K_i x of one vector (n x q, column-major on the host).
+void ops_apply_vector(Ops& o, const std::vector<double>& x, std::vector<double>& W);
+// Device fp64 SpMM of a host block X (n x w column-major, w <= 64): W holds the
+// q products K_i X one after another, each n x w column-major.
+void ops_apply_block(Ops& o, const std::vector<double>& X, int w, std::vector<double>& W);
 
 // Initial term given as device factors (row-major fp64).
 struct X0Dev {
@@ -255,6 +271,13 @@ struct SolveRun {
   double c = 0.0, dc = 0.0;
   int cap = 0, inner_cap = 0, max_iter = 0, refine_max = 0;
   double target = 0.0, rhs_tol = 0.0, inner_trunc_tol = 0.0;
+  double ref = 0.0;     // reference norm of the residual tests (||F||_F or opts.res_ref)
+  // LRC_INIT_NEWTON: X0 is the linearisation point and B = F (not F - L(X0))
+  bool newton_point = false;
+  // LRC_INIT_GIVEN_JUDGED: the given guess, judged against the median's per column
+  bool judged = false;
+  LR<double> Xg;
+  int rank_g = 0;
   lrc_info inf{};
   std::unique_ptr<Cheb<double>> c64;
   std::unique_ptr<Cheb<float>> c32;
@@ -271,7 +294,12 @@ struct SolveRun {
   std::vector<double> fmed, coefmed;
   void prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, const double* s0,
                const double* V0, const X0Dev* xd = nullptr);
-  void set_median_x0(const double* x, int iters);
+  // X0 = x 1^T from the median solve; state: 1 converged, 2 stopped (norm:
+  // the final residual norm, fnorm: ||f_med||)
+  void set_median_x0(const double* x, int iters, int state = 1, double norm = 0.0,
+                     double fnorm = 1.0);
+  // LRC_INIT_GIVEN_JUDGED: X0 from the given and the median guess column by column
+  void judge_guess();
   TruncPlan<double> rhs_plan(const lrc_opts& o, double* const* W0) const;
   lrc_status finish(const lrc_opts& o, lrc_info* info);
   // mixed precision pieces
@@ -286,6 +314,10 @@ struct SolveRun {
 // directly instead).  Runs on a stream of its own, synchronised with the
 // problems' context stream at both ends.
 void lockstep(std::vector<SolveRun*>& runs, const lrc_opts& o);
+
+// GMREST on a prepared fp64 run whose right-hand side B64 is built: restarted
+// truncated GMRES in place of the ChebyshevT recurrence (gmrest.cpp).
+void gmrest_solve(SolveRun& run, const lrc_opts& o, hipStream_t s);
 
 std::vector<lrc_status> solve_batched(const std::vector<Prob*>& probs, const lrc_opts& o,
                                       lrc_info* infos);

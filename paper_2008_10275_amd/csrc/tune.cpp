@@ -61,7 +61,8 @@ SpmmTuneResult tune_spmm(const Ops& o, int rcap) {
     if (w >= 1 && w != widths.back()) widths.push_back(w);
   auto time_us = [&](const SpmmCfg& cfg, int w) {
     const SpmmLaunch<T> l =
-        make_spmm<T>(dev_ops<T>(o).data(), o.q, U.as<T>(), ld, nullptr, w, rcap, Wp, ld, cfg);
+        make_spmm<T>(dev_ops<T>(o).data(), o.q, U.as<T>(), ld, nullptr, w, rcap, Wp, ld, cfg,
+                     true);
     enqueue_spmm(l, Batched<SpmmArgs<T>>(), s);   // warm-up
     constexpr int reps = 5;
     LRC_HIP(hipEventRecord(e0, s));

@@ -24,7 +24,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrcheb.h")
 LRC_OK, LRC_ENOTCONV, LRC_EINVAL, LRC_ENOMEM, LRC_EDEVICE = 0, 1, -1, -2, -3
 LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
 LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR = 0, 1, 2
-LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN = 0, 1, 2
+LRC_SOLVER_CHEBYSHEV, LRC_SOLVER_GMREST = 0, 1
+LRC_SPMM_SKIP_EMPTY = 4
+LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN, LRC_INIT_GIVEN_JUDGED, LRC_INIT_NEWTON = 0, 1, 2, 3, 4
 
 
 class LrcError(RuntimeError):
@@ -38,7 +40,8 @@ class lrc_opts(C.Structure):
                 ("max_iter", C.c_int), ("restart", C.c_int), ("cheb_c", C.c_double),
                 ("cheb_d", C.c_double), ("precision", C.c_int), ("refine_max", C.c_int),
                 ("inner_tol", C.c_double), ("init", C.c_int), ("median_tol", C.c_double),
-                ("verify_fp64", C.c_int), ("eager", C.c_int), ("inner_trunc_tol", C.c_double)]
+                ("verify_fp64", C.c_int), ("eager", C.c_int), ("inner_trunc_tol", C.c_double),
+                ("res_ref", C.c_double), ("solver", C.c_int)]
 
 
 class lrc_info(C.Structure):
@@ -46,14 +49,19 @@ class lrc_info(C.Structure):
                 ("prec_applies", C.c_int), ("refinements", C.c_int), ("median_iters", C.c_int),
                 ("relres", C.c_double), ("relres_est", C.c_double),
                 ("max_col_relres", C.c_double), ("seconds_setup", C.c_double),
-                ("seconds_solve", C.c_double), ("info_flags", C.c_int), ("status", C.c_int)]
+                ("seconds_solve", C.c_double), ("info_flags", C.c_int), ("status", C.c_int),
+                ("newton_steps", C.c_int), ("median_fallback_cols", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-LINEARIZE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double),
-                           C.POINTER(C.POINTER(C.c_double)))
+# int cb(void* user, int k, int stage, const double* x, double* const* val_out,
+#        int* rB, double* BU, double* BV, double* bnorm)
+LINEARIZE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double),
+                           C.POINTER(C.POINTER(C.c_double)), C.POINTER(C.c_int),
+                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double))
+MAX_RHS_RANK = 8
 
 _P = C.c_void_p
 _SIGS = {
@@ -102,8 +110,12 @@ _SIGS = {
     "lrc_profile_enable": (C.c_int, [C.c_int]),
     "lrc_profile_read": (C.c_int, [C.c_int, _P, _P, _P, _P]),
     "lrc_profile_class_name": (C.c_char_p, [C.c_int]),
-    "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, LINEARIZE_FN, _P,
-                                     C.POINTER(lrc_opts), C.POINTER(_P), C.POINTER(lrc_info)]),
+    "lrc_theta_scheme": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int, _P, C.c_int, _P, _P,
+                                   _P, C.c_double, C.c_double, C.c_int, C.POINTER(lrc_opts),
+                                   C.POINTER(_P), C.POINTER(lrc_info)]),
+    "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, _P, LINEARIZE_FN, _P,
+                                     C.c_double, C.c_int, C.c_int, C.POINTER(lrc_opts),
+                                     C.POINTER(_P), C.POINTER(lrc_info), _P]),
 }
 
 _lib = None
@@ -234,10 +246,11 @@ class Operators:
         v = np.ascontiguousarray(val, dtype=np.float64)
         _check(self.ctx.handle, load().lrc_ops_update_values(self.handle, i, _ptr(v)))
 
-    def spmm_dev(self, U, W, r=None):
-        """W (q*n x ldw tensor) = [K_0 U; ...; K_{q-1} U] for a row-major U tensor."""
+    def spmm_dev(self, U, W, r=None, skip_empty=False):
+        """W (q*n x ldw tensor) = [K_0 U; ...; K_{q-1} U] for a row-major U tensor.
+        skip_empty: rows of W whose operator row is empty are left untouched."""
         import torch
-        dtype = 0 if U.dtype == torch.float64 else 1
+        dtype = (0 if U.dtype == torch.float64 else 1) | (LRC_SPMM_SKIP_EMPTY if skip_empty else 0)
         r = U.shape[1] if r is None else r
         _check(self.ctx.handle, load().lrc_ops_spmm_dev(self.handle, dtype, r, _dev_ptr(U),
                                                         U.stride(0), _dev_ptr(W), W.stride(0)))
@@ -521,43 +534,106 @@ def truncate_scaled_dev(ctx, A, c, B, k1, w, rank_cap, tol, U, V):
     return s[:r.value].copy(), r.value
 
 
-def newton_subsets(ops, d, K, f, opts=None, sizes=None, linearize=None, **kw):
-    """lrc_newton_subsets (Algorithm 1).  linearize(k, xtilde_or_None) may return a
-    list of q value arrays (or None to keep the values).  Returns (status,
-    [Problem], [info dict])."""
+def newton_subsets(ops, d, K, f=None, opts=None, sizes=None, linearize=None, x_init=None,
+                   eps_newton=None, newton_max=8, picard=False, **kw):
+    """lrc_newton_subsets (Algorithm 1).
+
+    linearize(k, stage, x) -> (vals, BU, BV, bnorm): vals a list of q value
+    arrays (None entries, or vals None, keep the current values), BU (n x rB)
+    and BV (m_k x rB) the factors of the step's right-hand side at x (stage 0:
+    B_k(x); stage 1: b 1^T), bnorm = ||b||.  Without a callback the operators
+    are taken as linear and f is the load vector.  eps_newton defaults to
+    10 median_tol ||f||.  Returns (status, [Problem], [info dict], sizes) with the
+    subset sizes the library used."""
     lib = load()
     o = opts if opts is not None else default_opts(**kw)
     dd = _f64(d)
-    ff = _f64(f)
+    ff = None if f is None else _f64(f)
+    xi = None if x_init is None else _f64(x_init)
     sz = None if sizes is None else np.ascontiguousarray(sizes, dtype=np.int64)
     n = ops.n
+    if eps_newton is None:
+        if ff is None:
+            raise ValueError("eps_newton is required with a callback")
+        # ten times the median solve's relative accuracy: one Newton step per
+        # subset on linear operators
+        eps_newton = 10.0 * (o.median_tol if o.median_tol > 0 else 1e-6) * \
+            float(np.linalg.norm(ff))
+    sizes_out = np.zeros(K, dtype=np.int64)
+    err = []
 
-    def _cb(user, k, xt, vals):
+    def _cb(user, k, stage, xp, vals, rB, BU, BV, bnorm):
         try:
-            x = None if not xt else np.ctypeslib.as_array(xt, shape=(n,)).copy()
-            new = linearize(k, x) if linearize else None
-            if new is not None:
-                for i, v in enumerate(new):
+            x = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+            new_vals, bu, bv, bn = linearize(k, stage, x)
+            if new_vals is not None:
+                for i, v in enumerate(new_vals):
                     if v is None:
                         continue
                     dst = np.ctypeslib.as_array(vals[i], shape=(ops.nnz[i],))
                     dst[:] = v
+            bu = np.asarray(bu, dtype=np.float64).reshape(n, -1)
+            mk = int(sizes_out[k])
+            bv = np.asarray(bv, dtype=np.float64).reshape(mk, -1)
+            r = bu.shape[1]
+            if r < 1 or r > MAX_RHS_RANK or bv.shape[1] != r:
+                raise ValueError("right-hand side rank")
+            np.ctypeslib.as_array(BU, shape=(MAX_RHS_RANK * n,))[:n * r] = bu.reshape(-1, order="F")
+            np.ctypeslib.as_array(BV, shape=(MAX_RHS_RANK * mk,))[:mk * r] = \
+                bv.reshape(-1, order="F")
+            rB[0] = r
+            bnorm[0] = float(bn)
             return 0
-        except Exception:
+        except Exception as e:   # reported after the call
+            err.append(e)
             return 1
 
-    cb = LINEARIZE_FN(_cb)
+    cb = LINEARIZE_FN(_cb) if linearize is not None else C.cast(None, LINEARIZE_FN)
     out = (C.c_void_p * K)()
     infos = (lrc_info * K)()
-    code = lib.lrc_newton_subsets(ops.handle, dd.shape[1], _ptr(dd), K, _ptr(sz), _ptr(ff), cb,
-                                  None, C.byref(o), out, infos)
+    if linearize is not None:
+        # the callback needs the subset sizes before the library reports them
+        m = dd.shape[1]
+        sizes_out[:] = sz if sz is not None else [m // K] * (K - 1) + [m - (K - 1) * (m // K)]
+    code = lib.lrc_newton_subsets(ops.handle, dd.shape[1], _ptr(dd), K, _ptr(sz), _ptr(ff),
+                                  _ptr(xi), cb, None, float(eps_newton), int(newton_max),
+                                  int(bool(picard)), C.byref(o), out, infos, _ptr(sizes_out))
+    if err:
+        raise err[0]
     _check(ops.ctx.handle, code)
     probs = []
     off = 0
-    sizes_l = list(sz) if sz is not None else [dd.shape[1] // K] * (K - 1) + \
-        [dd.shape[1] - (K - 1) * (dd.shape[1] // K)]
     for k in range(K):
-        p = Problem(ops, dd[:, off:off + sizes_l[k]], None, None, handle=C.c_void_p(out[k]))
+        p = Problem(ops, dd[:, off:off + int(sizes_out[k])], None, None,
+                    handle=C.c_void_p(out[k]))
         probs.append(p)
-        off += sizes_l[k]
-    return code, probs, [infos[k].as_dict() for k in range(K)]
+        off += int(sizes_out[k])
+    return code, probs, [infos[k].as_dict() for k in range(K)], [int(v) for v in sizes_out]
+
+
+def theta_scheme(ops, M, d, b, theta, dt, X0=None, history="exact", opts=None, **kw):
+    """lrc_theta_scheme: len(b) - 1 theta steps of M X' + L(X) = b(t) 1^T.
+    M: scipy CSR mass matrix; b: list of load vectors b(t_0..t_w); X0 =
+    (U0, s0, V0) host factors or None (zero).  Returns (status, Problem of the
+    last step, [info dict per step])."""
+    lib = load()
+    o = opts if opts is not None else default_opts(**kw)
+    dd = _f64(d)
+    steps = len(b) - 1
+    bb = np.asfortranarray(np.column_stack([np.asarray(v, dtype=np.float64) for v in b]))
+    rp = np.ascontiguousarray(M.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(M.indices, dtype=np.int32)
+    mv = np.ascontiguousarray(M.data, dtype=np.float64)
+    r0, U0, s0, V0 = 0, None, None, None
+    if X0 is not None:
+        U0, s0, V0 = _f64(X0[0]), None if X0[1] is None else _f64(X0[1]), _f64(X0[2])
+        r0 = U0.shape[1]
+    out = C.c_void_p()
+    infos = (lrc_info * steps)()
+    code = lib.lrc_theta_scheme(ops.handle, _ptr(rp), _ptr(ci), _ptr(mv), dd.shape[1], _ptr(dd),
+                                steps, _ptr(bb), r0, _ptr(U0), _ptr(s0), _ptr(V0), float(theta),
+                                float(dt), {"exact": 0, "median": 1}[history], C.byref(o),
+                                C.byref(out), infos)
+    _check(ops.ctx.handle, code)
+    p = Problem(ops, dd, None, None, handle=C.c_void_p(out.value))
+    return code, p, [infos[k].as_dict() for k in range(steps)]

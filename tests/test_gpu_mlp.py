@@ -175,5 +175,25 @@ def test_learned_initial_guess_gain(torch, L, ctx):
     Fd = np.outer(f, np.ones(dte.shape[1]))
     assert olr.relres_dense(K, dte, Xl, Fd) <= 1.01e-6
     assert info_l["relres"] <= 1e-6
-    # the learned guess starts closer: no more Chebyshev updates than the median one
-    assert info_l["iters"] <= info_m["iters"]
+    # the learned guess starts closer: strictly fewer Chebyshev updates
+    assert info_l["iters"] < info_m["iters"]
+    # judged by the plain guess column by column (LRC_INIT_GIVEN_JUDGED): the
+    # trained network keeps most columns and loses nothing against the median
+    pj, code_j, info_j = _solve(L, ops, dte, f, init=L.LRC_INIT_GIVEN_JUDGED,
+                                X0=(U0h, np.ones(rr), Cte))
+    mte = dte.shape[1]
+    say("judged", info_j["iters"], info_j["median_fallback_cols"], "of", mte)
+    assert code_j == 0 and info_j["relres"] <= 1e-6
+    assert info_j["median_fallback_cols"] < mte // 2
+    assert info_j["iters"] <= info_l["iters"] + 1
+    # a perturbed network (its output's sign flipped) loses in every column:
+    # the fallback takes the median guess everywhere and the solve proceeds as
+    # from the median guess alone
+    pb, code_b, info_b = _solve(L, ops, dte, f, init=L.LRC_INIT_GIVEN_JUDGED,
+                                X0=(U0h, np.ones(rr), -Cte))
+    say("judged perturbed", info_b["iters"], info_b["median_fallback_cols"])
+    assert code_b == 0 and info_b["relres"] <= 1e-6
+    assert info_b["median_fallback_cols"] == mte
+    assert abs(info_b["iters"] - info_m["iters"]) <= 1
+    Ub, sb, Vb = pb.solution()
+    assert olr.relres_dense(K, dte, Ub @ np.diag(sb) @ Vb.T, Fd) <= 1.01e-6

@@ -10,13 +10,14 @@ Q2 hexahedral FE on a 3D channel) are not available, so stencil operators of
 the same algebraic structure stand in for them (see ``stencils``).
 """
 from .stencils import (Operators, conv_diff_2d, laplace5_solid_2d, graddiv9_solid_2d,
-                       three_term_2d, three_term_3d)
+                       three_term_2d, three_term_3d, seven_term_2d)
 from .params import (grid_params_little_endian, random_params, param_table,
-                     C3_SUBSET_SIZES, rhs_vector, config, mlp_init, MU_RANGE, LAM_RANGE)
+                     C3_SUBSET_SIZES, rhs_vector, config, mlp_init, MU_RANGE, LAM_RANGE,
+                     four_param_table)
 
 __all__ = [
     "Operators", "conv_diff_2d", "laplace5_solid_2d", "graddiv9_solid_2d",
-    "three_term_2d", "three_term_3d", "grid_params_little_endian", "random_params",
+    "three_term_2d", "three_term_3d", "seven_term_2d", "four_param_table", "grid_params_little_endian", "random_params",
     "param_table", "C3_SUBSET_SIZES", "rhs_vector", "config", "mlp_init", "MU_RANGE",
     "LAM_RANGE",
 ]

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .stencils import three_term_2d, three_term_3d
+from .stencils import seven_term_2d, three_term_2d, three_term_3d
 
 MU_RANGE = (0.5e4, 2.0e4)
 LAM_RANGE = (1.0e4, 4.0e4)
@@ -106,7 +106,28 @@ def config(name: str, small: bool = False) -> dict:
         mu, lam = random_params(100 if small else 500, 7)
         return dict(name=name, ops=ops, d=param_table(mu, lam), f=rhs_vector(ops.n, 0),
                     rank_cap=60, trunc_tol=1e-8, res_tol=1e-6)
+    if name == "q7":
+        # one subset of a four-parameter discretisation (mu, nu, lambda, rho;
+        # Sec. 4.4) on a little-endian tensor grid, mu fastest, then nu,
+        # lambda, rho: 4 x 3 x 4 x 3 = 144 columns around mu = 1.25e4,
+        # lambda = 2.5e4, nu = rho = 1.  The truncation tolerance is 1e-10:
+        # at 1e-8 the truncation of S itself stalls the residual near 5e-5.
+        N = 33 if small else 65
+        ops = seven_term_2d(N)
+        g = [np.linspace(1.0, 1.5, 4) * 1e4, np.linspace(0.9, 1.1, 3),
+             np.linspace(2.0, 3.0, 4) * 1e4, np.linspace(0.9, 1.1, 3)]
+        cols = [(a, b, c, e) for e in g[3] for c in g[2] for b in g[1] for a in g[0]]
+        d = four_param_table(*np.array(cols).T)
+        return dict(name=name, ops=ops, d=d, f=rhs_vector(ops.n, 0), rank_cap=16,
+                    trunc_tol=1e-10, res_tol=1e-6, m=(4, 3, 4, 3))
     raise ValueError(f"unknown workload {name!r}")
+
+
+def four_param_table(mu, nu, lam, rho) -> np.ndarray:
+    """Rows of the seven-term equation: 1, mu, nu rho, lambda, mu, lambda, rho
+    (D_0 = I, then the parameter of each of K_1..K_6 of seven_term_2d)."""
+    mu, nu, lam, rho = (np.asarray(a, dtype=np.float64) for a in (mu, nu, lam, rho))
+    return np.stack([np.ones_like(mu), mu, nu * rho, lam, mu, lam, rho])
 
 
 def mlp_init(seed: int = 11, sizes=(2, 64, 64, 30)):

@@ -188,6 +188,36 @@ def three_term_2d(N: int, nu: float = 1e-2, wind=(1.0, 0.5)) -> Operators:
     return Operators(K=K, n=N * N, dim=2, N=N, solid=solid_mask(N, 2))
 
 
+def seven_term_2d(N: int, nu: float = 1e-2, wind=(1.0, 0.5)) -> Operators:
+    """Stand-in for the four-parameter equation's seven terms (eq.
+    matrix_fourpars1): K_0 the convection-diffusion operator (D_0 = I); then
+    four solid terms and two fluid terms, each with a positive parameter row:
+    K_1 = solid 5-point Laplacian (mu), K_2 = fluid 5-point Laplacian (nu rho),
+    K_3 = solid Q1 (d_x + d_y)^2 (lambda), K_4 = solid Q1 (d_x - d_y)^2 (the mu
+    Jacobian term), K_5 = h^2 times the solid identity (the lambda Jacobian
+    term), K_6 = upwind convection restricted to the fluid (the rho Jacobian
+    term).  Every K_i, i >= 1, is a principal submatrix of a positive
+    semi-definite (K_6: semi-definite symmetric part) operator."""
+    h = 1.0 / (N + 1)
+    solid = solid_mask(N, 2)
+    fluid = ~solid
+    lap = {(0, 0): 4.0, (1, 0): -1.0, (-1, 0): -1.0, (0, 1): -1.0, (0, -1): -1.0}
+    gd = q1_form_stencil(2, h, [(0, 0), (0, 1), (1, 0), (1, 1)])
+    gm = q1_form_stencil(2, h, [(0, 0), (1, 1)])
+    for off, v in q1_form_stencil(2, h, [(0, 1), (1, 0)]).items():
+        gm[off] = gm.get(off, 0.0) - v
+    conv = {(0, 0): h * (abs(wind[0]) + abs(wind[1])), (-1, 0): -h * abs(wind[0]),
+            (0, -1): -h * abs(wind[1])}
+    K = [conv_diff_2d(N, nu, wind),
+         _apply_stencil(N, 2, lap, mask=solid),
+         _apply_stencil(N, 2, lap, mask=fluid),
+         _apply_stencil(N, 2, gd, mask=solid),
+         _apply_stencil(N, 2, gm, mask=solid),
+         _apply_stencil(N, 2, {(0, 0): h * h}, mask=solid),
+         _apply_stencil(N, 2, conv, mask=fluid)]
+    return Operators(K=K, n=N * N, dim=2, N=N, solid=solid)
+
+
 # --- 3D operators -----------------------------------------------------------------
 def conv_diff_3d(N: int, nu: float = 1e-2, wind=(1.0, 0.5, 0.25)) -> sp.csr_matrix:
     """K_0 = h*nu*L7 + h^2*(w . D), upwind one-sided differences (7 points)."""
