@@ -301,6 +301,37 @@ def measured_traffic(kernel):
     return None
 
 
+KTIMES = os.path.join(HERE, "profiles", "solve_dir_c2_kernels.md")
+
+
+def _source_ok(cell):
+    import hashlib
+    if ":" not in cell:
+        return False
+    fname, dig = cell.split(":")
+    try:
+        now = hashlib.sha256(open(os.path.join(HERE, "paper_2008_10275_amd", "csrc", fname),
+                                  "rb").read()).hexdigest()[:12]
+    except OSError:
+        return False
+    return now == dig
+
+
+def rocprof_avg_us(kernel):
+    """Average launch duration of a kernel class in the committed rocprofv3
+    kernel-trace summary, or None when there is none or the kernel's source
+    changed since the trace was taken."""
+    try:
+        lines = open(KTIMES).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0] == kernel and _source_ok(cells[5]):
+            return float(cells[2])
+    return None
+
+
 def kernel_table(prof_work, prof_time, steps):
     """Per class: ms per step, launches per step, achieved rate, fraction of peak."""
     out = {}
@@ -573,8 +604,16 @@ def main():
             _, k = max(modelled)
             r = ktab[k]
             same = a.workload == "c2" and a.precision == "dir" and not a.small
+            rp_us = rocprof_avg_us(k) if same else None
+            rp = None
+            if rp_us:
+                scale = 1e9 if r["unit"] == "GB/s" else 1e12
+                ach = r["work_per_launch"] / (rp_us * 1e-6) / scale
+                rp = dict(avg_launch_us=rp_us, achieved=ach, frac=ach / r["peak"],
+                          source="profiles/solve_dir_c2_kernels.md (rocprofv3 kernel trace)")
             roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
                         frac=r["frac"], traffic=measured_traffic(k) if same else None, kernel=k,
+                        rocprof=rp,
                         work_per_launch=r["work_per_launch"],
                         time_share=r["ms_per_step"] / total,
                         avg_launch_us=r["avg_launch_us"],

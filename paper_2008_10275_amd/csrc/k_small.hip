@@ -386,7 +386,10 @@ void enqueue_small_gemm(const SmallGemmArgs& a, Batched<SmallGemmArgs> b, hipStr
 // pairs positions a and kp-1-a of the rotated list [0, 1 + (t + i) mod (kp-1)].
 __device__ inline int rr_player(int pos, int t, int kp) {
   if (pos == 0) return 0;
-  return 1 + (pos - 1 + t) % (kp - 1);
+  // pos - 1 and t are both below kp - 1: one conditional subtraction
+  // replaces the integer modulo
+  const int x = pos - 1 + t;
+  return 1 + (x >= kp - 1 ? x - (kp - 1) : x);
 }
 
 // One-sided (Hestenes) Jacobi SVD of X = R^T (k x kj), R from the pivoted QR
@@ -405,9 +408,103 @@ __device__ inline int rr_player(int pos, int t, int kp) {
 // Y accumulates in LDS next to X when both fit; otherwise the (c, s) of every
 // round are logged and the replay kernel rebuilds Y.  Outputs: sigma (st.lam,
 // Jacobi order), V_M = Z diag(1/sigma) (st.VP, k x kj), Y (st.VM) or the log.
-constexpr int kJacThreads = 1024;
+constexpr int kJacThreads = 512;
 constexpr int kJacLds = 18432;              // doubles (144 KiB)
+constexpr int kJacE = 16;                   // column entries per lane (k <= 16 * 8)
 static_assert(SK * SK <= kJacLds, "X must fit in LDS at the largest width");
+static_assert(kJacE * 8 >= SK, "a team of 8 lanes must hold a column");
+// One round for the pairs of one team size TL (16 lanes per pair while at
+// most 32 pairs fit the 8 waves, else 8): a lane keeps its E = k / TL entries
+// of both columns in registers between the dot products and the rotation, so
+// that a round reads each column from LDS once and writes it once.
+// Sum of a double over the 16 lanes of a DPP row, in every lane: four
+// rotate-and-add steps (row_ror 8, 4, 2, 1) on the two 32-bit halves, which
+// stay inside the row (no LDS permute).
+template <int ROT>
+__device__ __forceinline__ double row_ror(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), 0x120 + ROT, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x120 + ROT, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double row_sum16(double x) {
+  x += row_ror<8>(x);
+  x += row_ror<4>(x);
+  x += row_ror<2>(x);
+  x += row_ror<1>(x);
+  return x;
+}
+
+template <int TL>
+__device__ __forceinline__ int jacobi_pair(double* X, double* Y, bool fuse, int k, int kj, int p,
+                                           int q, int tl, double* cs, double& dmax) {
+  constexpr int E = SK / TL;
+  double* xp = X + p * k;
+  double* xq = X + q * k;
+  double u[E], v[E];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = tl + e * TL;
+    u[e] = i < k ? xp[i] : 0.0;
+    v[e] = i < k ? xq[i] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    al = fma(u[e], u[e], al);
+    be = fma(v[e], v[e], be);
+    ga = fma(u[e], v[e], ga);
+  }
+  if constexpr (TL == 16) {
+    // a team is one DPP row
+    al = row_sum16(al);
+    be = row_sum16(be);
+    ga = row_sum16(ga);
+  } else {
+#pragma unroll
+    for (int o = TL >> 1; o > 0; o >>= 1) {
+      al += __shfl_xor(al, o);
+      be += __shfl_xor(be, o);
+      ga += __shfl_xor(ga, o);
+    }
+  }
+  double c = 1.0, s = 0.0;
+  const double nab = sqrt(al * be);
+  if (nab > 1e-300) dmax = fmax(dmax, fabs(ga) / nab);
+  // only an underflow guard: pairs of tiny columns are still rotated, so that
+  // the singular vectors of small singular values stay orthogonal
+  if (fabs(ga) > fmax(1e-14 * nab, 1e-300)) {
+    const double zeta = (be - al) / (2.0 * ga);
+    const double az = fabs(zeta);
+    // sqrt(1 + zeta^2) without overflow for huge |zeta|
+    const double hyp = az > 1e150 ? az : sqrt(1.0 + az * az);
+    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (az + hyp);
+    c = 1.0 / sqrt(1.0 + tt * tt);
+    s = c * tt;
+  }
+  cs[0] = c;
+  cs[1] = s;
+  if (s == 0.0) return 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = tl + e * TL;
+    if (i < k) {
+      xp[i] = c * u[e] - s * v[e];
+      xq[i] = s * u[e] + c * v[e];
+    }
+  }
+  if (fuse) {
+    double* yp = Y + p * kj;
+    double* yq = Y + q * kj;
+    for (int b = tl; b < kj; b += TL) {
+      const double a1 = yp[b], a2 = yq[b];
+      yp[b] = c * a1 - s * a2;
+      yq[b] = s * a1 + c * a2;
+    }
+  }
+  return 1;
+}
+
 __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const JacArgs* ab,
                                                             const int* done) {
   LRC_ITEM(JacArgs, ja_, a0, ab, done)
@@ -433,73 +530,42 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
   if (fuse)
     for (int e = tid; e < kj * kj; e += nt) Y[e] = (e / kj == e % kj) ? 1.0 : 0.0;
   __syncthreads();
-  // only an underflow guard: pairs of tiny columns are still rotated, so that
-  // the singular vectors of small singular values stay orthogonal
-  const double floor_abs = 1e-300;
-  const double eps = 1e-14;
-  const int TL = npair <= 16 ? 64 : (npair <= 32 ? 32 : 16);   // lanes per pair
+  const bool wide = npair > (kJacThreads / 16);   // more pairs than 16-lane teams
+  const int TL = wide ? 8 : 16;
   const int slot = wave * (64 / TL) + lane / TL;
   const int tl = lane % TL;
+  // Sweeps end when none rotates, or once the largest relative coupling
+  // |x_p^T x_q| / (||x_p|| ||x_q||) met in a sweep is below 1e-7: convergence
+  // is quadratic, so the next sweep would only meet couplings near 1e-14,
+  // the rounding level of the dot products themselves (a sweep spent on
+  // rounding noise is saved).
+  __shared__ double s_dmax[kJacThreads / 64];
   int round = 0;
   bool converged = false;
   for (int sweep = 0; sweep < 30 && round < max_rounds; ++sweep) {
     int any = 0;
+    double dmax = 0.0;
     for (int t = 0; t < kp - 1 && round < max_rounds; ++t, ++round) {
-      int rot = 0;
       if (slot < npair) {
         int p = rr_player(slot, t, kp), q = rr_player(kp - 1 - slot, t, kp);
         if (p > q) { const int x = p; p = q; q = x; }
-        double c = 1.0, s = 0.0;
-        if (q < kj) {
-          double* xp = X + p * k;
-          double* xq = X + q * k;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = tl; i < k; i += TL) {
-            const double u = xp[i], v = xq[i];
-            al = fma(u, u, al);
-            be = fma(v, v, be);
-            ga = fma(u, v, ga);
-          }
-          for (int o = TL >> 1; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o);
-            be += __shfl_xor(be, o);
-            ga += __shfl_xor(ga, o);
-          }
-          if (fabs(ga) > fmax(eps * sqrt(al * be), floor_abs)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double az = fabs(zeta);
-            // sqrt(1 + zeta^2) without overflow for huge |zeta|
-            const double hyp = az > 1e150 ? az : sqrt(1.0 + az * az);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (az + hyp);
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = c * tt;
-          }
-          if (s != 0.0) {
-            rot = 1;
-            for (int i = tl; i < k; i += TL) {
-              const double u = xp[i], v = xq[i];
-              xp[i] = c * u - s * v;
-              xq[i] = s * u + c * v;
-            }
-            if (fuse) {
-              double* yp = Y + p * kj;
-              double* yq = Y + q * kj;
-              for (int b = tl; b < kj; b += TL) {
-                const double u = yp[b], v = yq[b];
-                yp[b] = c * u - s * v;
-                yq[b] = s * u + c * v;
-              }
-            }
-          }
-        }
+        double cs[2] = {1.0, 0.0};
+        if (q < kj)
+          any |= wide ? jacobi_pair<8>(X, Y, fuse, k, kj, p, q, tl, cs, dmax)
+                      : jacobi_pair<16>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
         if (!fuse && tl == 0) {
-          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 0] = c;
-          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 1] = s;
+          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 0] = cs[0];
+          st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 1] = cs[1];
         }
       }
-      any |= __syncthreads_or(rot);
+      __syncthreads();
     }
-    if (!any) { converged = true; break; }
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
+    if (lane == 0) s_dmax[wave] = dmax;
+    if (!__syncthreads_or(any)) { converged = true; break; }
+    double dm = 0.0;
+    for (int w = 0; w < kJacThreads / 64; ++w) dm = fmax(dm, s_dmax[w]);
+    if (dm < 1e-7) { converged = true; break; }
   }
   for (int a = tid; a < kj; a += nt) {
     double sq = 0.0;
@@ -520,6 +586,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
     }
   if (tid == 0) {
     *st.rounds = fuse ? -1 : round;
+    st.kj[1] = round;   // diagnostic: rounds taken
     if (!converged) atomicOr(st.info, 4);
   }
 }

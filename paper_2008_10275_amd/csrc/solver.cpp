@@ -238,6 +238,16 @@ void enqueue_trunc(const TruncPlan<T>& p, const TruncBatch<T>& b, hipStream_t s)
   enqueue_select(p.sel, b.sel, s);
   enqueue_small_gemm(p.xab, b.xab, s);
   enqueue_tsmm(p.t2, b.t2, s);
+  // diagnostics (eager launches only): width, Jacobi dimension and rounds of
+  // the first item's truncation, one JSON line each on stderr
+  static const bool stats = std::getenv("LRC_TRUNC_STATS") != nullptr;
+  if (stats) {
+    int h[3] = {0, 0, 0};
+    LRC_HIP(hipMemcpyAsync(&h[0], p.jac.st.k, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&h[1], p.jac.st.kj, 8, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "{\"tstat\": [%d, %d, %d, %d]}\n", int(sizeof(T)), h[0], h[1], h[2]);
+  }
 }
 
 template <class T>
@@ -357,17 +367,18 @@ void Truncator<T>::run(const BlockView<T>& A, int64_t n, const BlockView<T>& B, 
                      norm_out),
                 TruncBatch<T>(), s);
   if (log_enabled()) {
-    int hk[5] = {0, 0, 0, 0, 0};
+    int hk[6] = {0, 0, 0, 0, 0, 0};
     double hn = 0.0;
     LRC_HIP(hipMemcpyAsync(&hk[4], st.kj, 4, hipMemcpyDeviceToHost, s));
+    LRC_HIP(hipMemcpyAsync(&hk[5], st.kj + 1, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[0], st.k, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[1], rank_out, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[2], st.info, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hk[3], st.rounds, 4, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipMemcpyAsync(&hn, norm_out, 8, hipMemcpyDeviceToHost, s));
     LRC_HIP(hipStreamSynchronize(s));
-    std::fprintf(stderr, "{\"trunc\": %d, \"k\": %d, \"kj\": %d, \"rank\": %d, \"norm\": %.9e, \"info\": %d, \"rounds\": %d}\n",
-                 int(sizeof(T)), hk[0], hk[4], hk[1], hn, hk[2], hk[3]);
+    std::fprintf(stderr, "{\"trunc\": %d, \"k\": %d, \"kj\": %d, \"rank\": %d, \"norm\": %.9e, \"info\": %d, \"rounds\": %d, \"jacobi_rounds\": %d}\n",
+                 int(sizeof(T)), hk[0], hk[4], hk[1], hn, hk[2], hk[3], hk[5]);
     if (hk[0] > 0 && hk[4] == 0) {
       // diagnostics of a truncation whose core came out empty
       const int kk = hk[0];
