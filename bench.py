@@ -46,9 +46,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--small", action="store_true", help="reduced grid (tests)")
-    ap.add_argument("--precision", default="dir", choices=["mixed", "dir", "fp64"],
+    ap.add_argument("--precision", default="dir", choices=["mixed", "dir", "fp64", "bf16gram"],
                     help="mixed: fp32 ChebyshevT in fp64 refinement; dir: fp64 iterate and "
-                         "residual with fp32 preconditioner solves and directions")
+                         "residual with fp32 preconditioner solves and directions; bf16gram: "
+                         "mixed with bf16 first-pass Gram products")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no event timing in the timed region")
@@ -127,6 +128,33 @@ def main_batched(a, L, torch):
         seq = dict(seconds=(time.perf_counter() - t1) / reps,
                    iters=[i["iters"] for i in seq_infos],
                    max_relres=max(i["relres"] for i in seq_infos))
+    # kernel table of the batched solve (eager launches, HIP events)
+    oe = L.default_opts(**{f: getattr(opts, f) for f, _ in opts._fields_})
+    oe.eager = 1
+    ktab = {} if a.no_profile else profiled(L, lambda: batched_solve(L, probs, oe, res_tol),
+                                            a.steps, torch)
+    roof = roofline_of(ktab, "HIP events on the library stream around every launch, in a "
+                             "repeat of the batched solve with eager launches")
+    cpu = None
+    if not a.no_cpu:
+        # the oracle on a bounded sample: two of the subsets, scaled to all 16
+        # by their parameter counts
+        subs_cfg = cfg["subsets"]
+        pick = [0, 5]
+        secs, its = 0.0, []
+        for j in pick:
+            t, it = cpu_oracle_solve(subs_cfg[j]["ops"].K, subs_cfg[j]["d"], cfg["f"],
+                                     cfg["rank_cap"], cfg["trunc_tol"], res_tol)
+            secs += t
+            its.append(it)
+        msample = sum(subs_cfg[j]["d"].shape[1] for j in pick)
+        mall = sum(s_["d"].shape[1] for s_ in subs_cfg)
+        cpu = dict(value=secs * mall / msample, unit="s", cores=int(blas_threads()),
+                   kind="oracle", host=host_info(),
+                   sample=(f"oracle solves of subsets {pick} ({msample} of {mall} parameters, "
+                           f"{its} iterations, {secs:.2f} s), scaled to all subsets by "
+                           f"parameter count; SuperLU single-threaded, BLAS on "
+                           f"{blas_threads()} threads"))
     n = cfg["base_ops"].n
     sizes = cfg["sizes"]
     line = {
@@ -147,8 +175,9 @@ def main_batched(a, L, torch):
                    "setup_s": setup_s},
         "sequential_fp64": seq,
         "speedup_vs_sequential_fp64": (seq["seconds"] / sec) if seq else None,
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": roof,
+        "kernels": ktab,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -189,26 +218,35 @@ def main_surrogate(a, L, torch):
     Ud[:, :k] = torch.from_numpy(U).cuda()
     Vd = torch.zeros((V.shape[0], ld), dtype=torch.float64, device="cuda")
     Vd[:, :k] = torch.from_numpy(V).cuda()
-    U0 = torch.zeros((n, 32), dtype=torch.float64, device="cuda")
-    V0 = torch.zeros((V.shape[0], 32), dtype=torch.float64, device="cuda")
-    # POD basis: the snapshots truncated at the solver's own tolerance (modes
-    # below it are rounding noise that would only widen the residual)
-    s0, rr = L.truncate_dev(ctx, Ud, sv, Vd, r, cfg["trunc_tol"], U0, V0)
-    Ctr = (V0[:, :rr] * torch.from_numpy(s0).cuda()).contiguous()
-    net = L.MLP(ctx, mlp_init(11, sizes=(2, 64, 64, rr)))
     Xtr = torch.from_numpy(np.ascontiguousarray(dtr[1:].T)).cuda()
-    net.fit_scaling(Xtr, Ctr)
-    hist = net.train(Xtr, Ctr, 2000, lr=3e-3)
     Xte = torch.from_numpy(np.ascontiguousarray(dte[1:].T)).cuda()
-    U0r = U0[:, :rr].contiguous()
+
+    def surrogate(tol):
+        """POD basis of the snapshots (rank cap r, tail cut at tol) and the
+        network trained on its coefficients."""
+        U0 = torch.zeros((n, 32), dtype=torch.float64, device="cuda")
+        V0 = torch.zeros((V.shape[0], 32), dtype=torch.float64, device="cuda")
+        s0, rr = L.truncate_dev(ctx, Ud, sv, Vd, r, tol, U0, V0)
+        Ctr = (V0[:, :rr] * torch.from_numpy(s0).cuda()).contiguous()
+        net = L.MLP(ctx, mlp_init(11, sizes=(2, 64, 64, rr)))
+        net.fit_scaling(Xtr, Ctr)
+        hist = net.train(Xtr, Ctr, 2000, lr=3e-3)
+        return U0[:, :rr].contiguous(), rr, net, hist
+
+    # POD basis truncated at the solver's own tolerance (modes below it are
+    # rounding noise that would only widen the residual), and the same basis
+    # kept at the configured rank r (tail cut at zero)
+    U0r, rr, net, hist = surrogate(cfg["trunc_tol"])
+    U0w, rw, netw, histw = surrogate(0.0)
     prec = {"mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR, "fp64": L.LRC_FP64}[a.precision]
     o_l = L.default_opts(**base, init=L.LRC_INIT_GIVEN, precision=prec)
+    o_j = L.default_opts(**base, init=L.LRC_INIT_GIVEN_JUDGED, precision=prec)
     o_m = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=prec)
     o_p = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=L.LRC_FP64)
 
-    def learned():
-        C = net.predict(Xte)
-        code, info = pte.solve_x0_dev(U0r, C, opts=o_l)
+    def learned(o=o_l, U=U0r, nt=net):
+        C = nt.predict(Xte)
+        code, info = pte.solve_x0_dev(U, C, opts=o)
         return code, info
 
     def median(o):
@@ -227,8 +265,23 @@ def main_surrogate(a, L, torch):
         return (time.perf_counter() - t0) / a.steps, info
 
     t_l, i_l = timed(learned)
+    t_j, i_j = timed(lambda: learned(o_j))
+    t_w, i_w = timed(lambda: learned(o_l, U0w, netw))
     t_m, i_m = timed(lambda: median(o_m))
     t_p, i_p = timed(lambda: median(o_p))
+    ktab, roof, cpu = {}, None, None
+    if not a.no_profile:
+        ol_e = L.default_opts(**base, init=L.LRC_INIT_GIVEN, precision=prec, eager=1)
+        ktab = profiled(L, lambda: learned(ol_e), a.steps, torch)
+        roof = roofline_of(ktab, "HIP events on the library stream around every launch, in a "
+                                 "repeat of the learned-guess solve with eager launches")
+    if not a.no_cpu:
+        secs, its = cpu_oracle_solve(K, dte, f, cfg["rank_cap"], cfg["trunc_tol"], res_tol)
+        cpu = dict(value=secs, unit="s", cores=int(blas_threads()), kind="oracle",
+                   host=host_info(),
+                   sample=(f"one oracle solve of the held-out set from the median guess "
+                           f"(n={n}, m={dte.shape[1]}, {its} iterations); SuperLU "
+                           f"single-threaded, BLAS on {blas_threads()} threads"))
     line = {
         "metric": "time to rel. residual 1e-6 (s), learned initial guess",
         "value": t_l, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -242,14 +295,21 @@ def main_surrogate(a, L, torch):
                    "n": int(n), "m_train": int(dtr.shape[1]), "m_test": int(dte.shape[1]),
                    "rank_cap": cfg["rank_cap"], "pod_rank": int(rr), "precision": a.precision},
         "result": {"learned": dict(seconds=t_l, iters=i_l["iters"], relres=i_l["relres"]),
+                   "learned_judged": dict(seconds=t_j, iters=i_j["iters"], relres=i_j["relres"],
+                                          fallback_cols=i_j["median_fallback_cols"],
+                                          fallback_rate=i_j["median_fallback_cols"] /
+                                          dte.shape[1]),
+                   "learned_rank_r": dict(seconds=t_w, iters=i_w["iters"], relres=i_w["relres"],
+                                          pod_rank=int(rw)),
                    "median": dict(seconds=t_m, iters=i_m["iters"], relres=i_m["relres"],
                                   median_iters=i_m["median_iters"]),
                    "fp64_median": dict(seconds=t_p, iters=i_p["iters"], relres=i_p["relres"]),
                    "train_loss": [float(hist[0]), float(hist[-1])]},
         "speedup_vs_median": t_m / t_l,
         "speedup_vs_fp64_median": t_p / t_l,
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": roof,
+        "kernels": ktab,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -258,7 +318,8 @@ def solve_opts(L, cfg, precision, eager=0):
     return L.default_opts(rank_cap=cfg["rank_cap"], trunc_tol=cfg["trunc_tol"],
                           res_tol=cfg["res_tol"], init=L.LRC_INIT_MEDIAN, verify_fp64=1,
                           precision={"mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR,
-                                     "fp64": L.LRC_FP64}[precision],
+                                     "fp64": L.LRC_FP64,
+                                     "bf16gram": L.LRC_MIXED_BF16GRAM}[precision],
                           eager=eager)
 
 
@@ -411,6 +472,67 @@ def consecutive_direct(cfg, workers, sample):
                 sample=(f"{len(cols)} of the {m} columns factorised and solved with SuperLU "
                         f"in a pool of {workers} processes ({wall:.2f} s wall, "
                         f"{np.mean(per):.3f} s per column), scaled to all {m} columns"))
+
+
+def profiled(L, run_once, steps, torch):
+    """Kernel table of `run_once` (which must launch eagerly): one run records
+    the algorithmic work per launch, `steps` more the HIP-event times."""
+    L.profile_enable(2)
+    run_once()
+    torch.cuda.synchronize()
+    work = L.profile_read()
+    L.profile_enable(1)
+    for _ in range(steps):
+        run_once()
+    torch.cuda.synchronize()
+    times = L.profile_read()
+    L.profile_enable(0)
+    return kernel_table(work, times, steps)
+
+
+def roofline_of(ktab, source):
+    """The dominant modelled kernel of a kernel table, as the bench line's
+    roofline object (event timing; no counter traffic for this workload)."""
+    if not ktab:
+        return None
+    total = sum(r["ms_per_step"] for r in ktab.values())
+    modelled = [(r["ms_per_step"], k) for k, r in ktab.items() if "achieved" in r]
+    if not modelled:
+        return None
+    _, k = max(modelled)
+    r = ktab[k]
+    return dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
+                frac=r["frac"], traffic=None, kernel=k, work_per_launch=r["work_per_launch"],
+                time_share=r["ms_per_step"] / total, avg_launch_us=r["avg_launch_us"],
+                source=source)
+
+
+def cpu_oracle_solve(K, d, f, cap, tol, res_tol):
+    """Seconds of one oracle solve (median SuperLU solve + FP64 ChebyshevT)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle import chebyshev as och
+    from oracle import driver as odrv
+    from oracle import lowrank as olr
+    m = d.shape[1]
+    dbar = och.mean_parameters(d)
+    P = och.DirectPreconditioner(och.mean_preconditioner(K, dbar))
+    c, dc = och.chebyshev_interval(d, dbar)
+    ref = np.linalg.norm(f) * np.sqrt(m)
+    t0 = time.perf_counter()
+    jmed = odrv.upper_median_offset(m)
+    xt = spla.splu(sp.csc_matrix(olr.column_operator(K, d, jmed))).solve(f)
+    B = odrv.median_rhs(K, d, f, xt)
+    _, info = och.chebyshev_t(K, d, B, P, c, dc, cap, tol, res_tol, ref, max_iter=60)
+    return time.perf_counter() - t0, info.iters
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(cfg):
@@ -644,7 +766,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "bf16gram": "bf16+f32+f64"}.get(a.precision, "f32+f64"),
         "data": "synthetic",
         "config": {"workload": workload_name(cfg, n, m), "n": int(n), "m": int(m),
                    "q": len(cfg["ops"].K),
@@ -653,7 +775,10 @@ def main():
                    "precision": {"mixed": "fp32 inner ChebyshevT, fp64 residual + refinement",
                                  "dir": ("fp64 iterate and residual, fp32 preconditioner "
                                          "solves and direction updates"),
-                                 "fp64": "fp64"}[a.precision]},
+                                 "fp64": "fp64",
+                                 "bf16gram": ("fp32 inner ChebyshevT with bf16 first-pass "
+                                              "Gram products, fp64 residual + refinement")
+                                 }[a.precision]},
         "result": {"relres_fp64": last["relres"], "max_col_relres": last["max_col_relres"],
                    "iters": last["iters"], "refinements": last["refinements"],
                    "rank": last["rank"], "median_iters": last["median_iters"],

@@ -54,8 +54,12 @@ enum {
 /* precision of the iteration.  LRC_MIXED_FP32: fp32 ChebyshevT on the
  * correction equation inside fp64 iterative refinement.  LRC_MIXED_FP32_DIR:
  * one ChebyshevT whose iterate and residual (SpMM and truncation) are fp64
- * while the preconditioner solves and the direction updates run in fp32. */
-enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2 };
+ * while the preconditioner solves and the direction updates run in fp32.
+ * LRC_MIXED_BF16GRAM: LRC_MIXED_FP32 whose fp32 truncations take their first
+ * CholeskyQR pass on bf16 Gram products (operands rounded to bf16, fp32
+ * accumulation, a preset shift of 1e-2 on the equilibrated Gram), the second
+ * pass in fp32; the fp64 residual and refinement decide the accuracy. */
+enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2, LRC_MIXED_BF16GRAM = 3 };
 /* low-rank solver of the update equation (Sec. 4.1 names both): the
  * preconditioned Chebyshev iteration with truncation, or GMREST, restarted
  * GMRES with truncation on the left-preconditioned operator in the Frobenius
@@ -245,7 +249,9 @@ lrc_status lrc_get_solution(lrc_prob prob, int* rank, double* U, double* s, doub
 lrc_status lrc_residual(lrc_prob prob, double* relres, double* colres);
 
 /* Truncation T_{R,eps}(A diag(c) B^T) of device factors (row-major fp64 or fp32:
- * dtype 0/1): A n x k (ld lda), B m x k (ld ldb), c (k host doubles).  Outputs:
+ * dtype 0/1; dtype 2: fp32 factors whose first CholeskyQR pass runs on bf16
+ * Gram products, as the fp32 steps of LRC_MIXED_BF16GRAM do): A n x k (ld
+ * lda), B m x k (ld ldb), c (k host doubles).  Outputs:
  * U (n x rank, ld ldu), V (m x rank, ld ldv) device; s (host, rank values);
  * k <= 128, rank_cap <= 64.  CholeskyQR2 on both factors + fp64 SVD of the core. */
 lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,

@@ -788,7 +788,7 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
                             int ldv, int* rank) {
   if (!ctx) return LRC_EINVAL;
   return guarded(&ctx->c, [&]() -> lrc_status {
-    LRC_CHECK(dtype == 0 || dtype == 1, ST_EINVAL, "truncate: dtype must be 0 or 1");
+    LRC_CHECK(dtype == 0 || dtype == 1 || dtype == 2, ST_EINVAL, "truncate: dtype must be 0, 1 or 2");
     LRC_CHECK(n >= 1 && m >= 1 && k >= 1 && k <= kTruncCap, ST_EINVAL,
               "truncate: need n, m >= 1 and 1 <= k <= 128");
     LRC_CHECK(rank_cap >= 1 && rank_cap <= 64 && rank_cap <= ldu && rank_cap <= ldv, ST_EINVAL,
@@ -808,6 +808,7 @@ lrc_status lrc_truncate_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m, int k,
       using T = std::remove_pointer_t<decltype(tag)>;
       Truncator<T> tr;
       tr.alloc(n, m, st);
+      tr.bf16 = dtype == 2;
       BlockView<T> av = view1<T>(static_cast<const T*>(A), lda, nullptr, k);
       BlockView<T> bv = view1<T>(static_cast<const T*>(B), ldb, nullptr, k);
       int* rk = reinterpret_cast<int*>(outs.as<double>() + 2);

@@ -349,6 +349,125 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(GramArgs<T> a0, const Gram
   gram_body<T, 2, KTM, SCALED1>(a, job, wg, nwg, KT, red);
 }
 
+// ---------------------------------------------------------- BF16 first pass
+// The same Gram products with the fp32 operands rounded to bf16 as they are
+// loaded and multiplied on v_mfma_f32_16x16x32_bf16 (fp32 accumulation): a
+// lane holds 8 consecutive rows of one column of a 16-column tile (rows 8 s
+// + e of a 32-row step, s = lane / 16, column lane % 16), which is the A
+// operand of X^T and the B operand of X alike, so the fragments of every
+// column tile serve all tiles of the upper triangle.  A step covers 32 rows
+// with one MFMA per tile (8 with the fp32 16x16x4 form); the partials have
+// the fp32 kernel's layout and are summed by its reduction.
+typedef __bf16 bf16x8_g __attribute__((ext_vector_type(8)));
+
+template <int KTM, int NG, int G, bool SCALED>
+__device__ inline void gram_rows_bf16(const ColRef<float>* cr, int KT, int64_t r0, int64_t r1,
+                                      int stream, int nstream, int sub, floatx4* acc) {
+  constexpr TileTab<KTM> tt{};
+  const int64_t rl = r1 - 1;
+  const int64_t step = 32 * int64_t(nstream);
+  float cur[KTM][8];
+  int64_t q = r0 + 32 * stream;
+#pragma unroll
+  for (int t = 0; t < KTM; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cur[t][e] = t < KT ? col_load<float, SCALED>(cr[t], q + 8 * sub + e, rl) : 0.0f;
+  for (; q < r1; q += step) {
+    bf16x8_g fr[KTM];
+#pragma unroll
+    for (int t = 0; t < KTM; ++t)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) fr[t][e] = __bf16(q + 8 * sub + e < r1 ? cur[t][e] : 0.0f);
+    const int64_t qn = q + step;
+#pragma unroll
+    for (int t = 0; t < KTM; ++t)
+      if (t < KT)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[t][e] = col_load<float, SCALED>(cr[t], qn + 8 * sub + e, rl);
+#pragma unroll
+    for (int u = G; u < tt.N; u += NG)
+      if (tt.bj[u] < KT)
+        acc[u / NG] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[tt.bi[u]], fr[tt.bj[u]],
+                                                              acc[u / NG], 0, 0, 0);
+  }
+}
+
+template <int KTM, bool SCALED1>
+__device__ __forceinline__ void gram_body_bf16(const GramArgs<float>& a, int job, int wg, int nwg,
+                                               int KT, float* red) {
+  constexpr int NG = KTM <= 4 ? 1 : 2;
+  constexpr TileTab<KTM> tt{};
+  constexpr int NTM = TileTab<KTM>::N;
+  constexpr int MAXT = (NTM + NG - 1) / NG;
+  constexpr int NS = 4 / NG;
+  const BlockView<float>& X = a.X[job];
+  const int64_t rows = a.rows[job];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = wave % NG, stream = wave / NG;
+  ColRef<float> cr[KTM];
+#pragma unroll
+  for (int t = 0; t < KTM; ++t) cr[t] = resolve_col(X, 16 * t + (lane & 15));
+  floatx4 acc[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) acc[t] = floatx4{};
+  const int64_t per = ceil_div(ceil_div(rows, int64_t(32)), int64_t(nwg)) * 32;
+  const int64_t r0 = int64_t(wg) * per, r1 = std::min<int64_t>(rows, r0 + per);
+  if (r0 < r1) {
+    const bool sc = SCALED1 && job == 1;
+    if (g == 0) {
+      if (sc) gram_rows_bf16<KTM, NG, 0, true>(cr, KT, r0, r1, stream, NS, lane >> 4, acc);
+      else gram_rows_bf16<KTM, NG, 0, false>(cr, KT, r0, r1, stream, NS, lane >> 4, acc);
+    }
+    if constexpr (NG > 1)
+      if (g == 1) {
+        if (sc) gram_rows_bf16<KTM, NG, 1, true>(cr, KT, r0, r1, stream, NS, lane >> 4, acc);
+        else gram_rows_bf16<KTM, NG, 1, false>(cr, KT, r0, r1, stream, NS, lane >> 4, acc);
+      }
+  }
+  for (int s = 0; s < NS; ++s) {
+    if (stream == s) {
+#pragma unroll
+      for (int u = 0; u < NTM; ++u) {
+        if (u % NG == g && tt.bj[u] < KT) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float* d = &red[u * 256 + Mfma<float>::drow(lane, i) * 16 + (lane & 15)];
+            *d = s == 0 ? acc[u / NG][i] : *d + acc[u / NG][i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = a.partial + size_t(blockIdx.x) * kGN * 256;
+  for (int e = threadIdx.x; e < NTM * 256; e += blockDim.x) {
+    const int u = e >> 8;
+    if (tt.bj[u] < KT) out[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
+  }
+}
+
+template <int KTM, bool SCALED1>
+__global__ __launch_bounds__(256, 2) void gram_bf16_kernel(GramArgs<float> a0,
+                                                         const GramArgs<float>* ab,
+                                                         const int* done) {
+  if (done && done[blockIdx.z]) return;
+  const GramArgs<float>& a = ab ? ab[blockIdx.z] : a0;
+  if (int(blockIdx.x) >= a.nwg0 + a.nwg1) return;
+  __shared__ float red[TileTab<KTM>::N * 256];
+  const int job = int(blockIdx.x) < a.nwg0 ? 0 : 1;
+  const int wg = job == 0 ? blockIdx.x : blockIdx.x - a.nwg0;
+  const int nwg = job == 0 ? a.nwg0 : a.nwg1;
+  const int k = min(view_width(a.X[job]), 16 * KTM);
+  const int KT = __builtin_amdgcn_readfirstlane((k + 15) / 16);
+  if constexpr (KTM >= 8)
+    if (KT > 6) return gram_body_bf16<8, SCALED1>(a, job, wg, nwg, KT, red);
+  if constexpr (KTM >= 6)
+    if (KT > 4) return gram_body_bf16<6, SCALED1>(a, job, wg, nwg, KT, red);
+  if constexpr (KTM >= 4)
+    if (KT > 2) return gram_body_bf16<4, SCALED1>(a, job, wg, nwg, KT, red);
+  gram_body_bf16<2, SCALED1>(a, job, wg, nwg, KT, red);
+}
+
 // G[r][c] = sum over the job's workgroup partials (fixed order), both triangles
 // written; also publishes the width k = min(width, kcap) and flags widths
 // beyond the capacity (info bit 8).
@@ -425,6 +544,13 @@ static GramFn<T> gram_fn(int kb, bool sc1) {
   return sc1 ? gram_kernel<T, 8, true> : gram_kernel<T, 8, false>;
 }
 
+static GramFn<float> gram_bf16_fn(int kb, bool sc1) {
+  if (kb <= 32) return sc1 ? gram_bf16_kernel<2, true> : gram_bf16_kernel<2, false>;
+  if (kb <= 64) return sc1 ? gram_bf16_kernel<4, true> : gram_bf16_kernel<4, false>;
+  if (kb <= 96) return sc1 ? gram_bf16_kernel<6, true> : gram_bf16_kernel<6, false>;
+  return sc1 ? gram_bf16_kernel<8, true> : gram_bf16_kernel<8, false>;
+}
+
 static int gram_wgs(int64_t rows) {
   // about 128 rows per workgroup for short operands (so that their serial
   // load chains stay short), at most kGramWgMax workgroups for long ones
@@ -481,7 +607,14 @@ GramLaunch<T> make_gram(const GramJob<T>* jobs, int njobs, int kcap, double* ws_
 template <class T>
 void enqueue_gram(const GramLaunch<T>& l, Batched<GramArgs<T>> bg, Batched<GramRedArgs<T>> br,
                   hipStream_t s) {
-  {
+  if constexpr (sizeof(T) == 4) {
+    if (l.bf16) {
+      ProfScope ps(kcls(K_GRAM_BF16, true), s, l.work);
+      const dim3 grid(l.grid, 1, bg.n), blk(256);
+      gram_bf16_fn(l.kb, l.sc1)<<<grid, blk, 0, s>>>(l.g, bg.dev, bg.done);
+    }
+  }
+  if (!l.bf16) {
     ProfScope ps(kcls(K_GRAM, is_f32<T>()), s, l.work);
     const GramArgs<T>& a = l.g;
     const dim3 grid(l.grid, 1, bg.n), blk(256);

@@ -83,10 +83,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(CholArgs a0, const C
   for (int j = tid; j < k; j += nt) {
     const double g = A[j * kCL + j];
     dsc[j] = (g > 1e-300 && g > 1e-28 * s_gm) ? 1.0 / sqrt(g) : 0.0;
+    // a non-finite diagonal means non-finite operand data: a breakdown, not
+    // a vanishing column to be dropped
+    if (!isfinite(g)) atomicOr(st.info, 2);
   }
   __syncthreads();
   const double tau = eps * k;
-  double shift = 0.0;
+  double shift = ca.shift0;
   bool fail = true;
   const int lr = lane >> 4, lc = lane & 15;   // MFMA slice row group, column
   for (int attempt = 0; attempt < 6 && fail; ++attempt) {
@@ -662,7 +665,8 @@ void enqueue_replay(const RepArgs& a, Batched<RepArgs> b, hipStream_t s) {
 // applies it to the other columns and to Q.  It stops once the trailing block's
 // Frobenius norm is at most 1e-3 of the truncation's tail budget
 // max(tol ||M||_F, abs_tol): what is left cannot move the rank decision or any
-// kept singular value by more than (1e-3 budget)^2 / sigma.  Outputs: R (kj x
+// kept singular value by more than (1e-3 budget)^2 / sigma.  For factors held
+// in fp32 it also stops at 1e-7 ||M||_F, their rounding level.  Outputs: R (kj x
 // k, by original column, so that M = Q R) in st.W, Q (k x kj) in st.H, the
 // pivot order in st.piv and kj in st.kj.  Two barriers per step; every wave
 // takes the pivot decision itself from the same LDS data (same order of
@@ -723,7 +727,10 @@ __global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArg
     if (j == 0) {
       const double b1 = qa_.tol > 0.0 ? 1e-3 * qa_.tol : 0.0;
       const double b2 = 1e-3 * qa_.abs_tol;
-      thr2 = fmax(b1 * b1 * tot, b2 * b2);
+      // factors held in fp32 resolve nothing below their rounding level: the
+      // directions there are noise of the data, not of the method
+      const double b3 = qa_.data_eps;
+      thr2 = fmax(fmax(b1 * b1, b3 * b3) * tot, b2 * b2);
     }
     if (!(tot > thr2) || !(best > 0.0) || bi >= k) break;   // the same in every wave
     const int p = bi;

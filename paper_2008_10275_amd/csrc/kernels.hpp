@@ -203,6 +203,7 @@ struct GramLaunch {
   int grid = 0;      // partial workgroups
   int kb = 0;        // host bound of the width (selects the tile class)
   bool sc1 = false;  // second operand row-scaled
+  bool bf16 = false; // fp32 operands rounded to bf16 on load, bf16 MFMA, fp32 accumulation
   Work work;
 };
 template <class T>
@@ -277,6 +278,7 @@ struct CholArgs {
   int pass;
   int kcap;
   double eps;
+  double shift0;     // diagonal shift of the first attempt (equilibrated Gram)
 };
 // Pivoted Householder QR of the core, stopped once the trailing block's
 // Frobenius norm is below 1e-3 of the truncation's tail budget
@@ -286,6 +288,8 @@ struct QrArgs {
   int kcap;
   double tol;
   double abs_tol;    // absolute tail budget of the truncation (0: none)
+  double data_eps;   // relative precision of the truncated factors (fp32: 1e-7, fp64: 0):
+                     // the QR also stops once the trailing block is below data_eps ||M||_F
 };
 struct JacArgs {
   TruncState st;

@@ -9,7 +9,7 @@ const char* kclass_name(int c) {
   static const char* names[K_NBASE] = {"spmm", "gram", "gram_reduce", "chol", "tsmm", "jacobi",
                                        "jacobi_replay", "small_gemm", "select", "prec_gather",
                                        "prec_product", "residual", "vector", "qrcp", "mlp",
-                                       "graph"};
+                                       "graph", "gram_bf16"};
   static std::vector<std::string> full;
   if (full.empty())
     for (int k = 0; k < K_COUNT; ++k)

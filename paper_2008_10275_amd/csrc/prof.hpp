@@ -15,7 +15,7 @@ namespace lrc {
 enum KClass {
   K_SPMM = 0, K_GRAM, K_GRAM_REDUCE, K_CHOL, K_TSMM, K_JACOBI, K_REPLAY, K_SMALL_GEMM,
   K_SELECT, K_PREC_GATHER, K_PREC_PRODUCT, K_RESIDUAL, K_VECTOR, K_QRCP, K_MLP, K_GRAPH,
-  K_NBASE
+  K_GRAM_BF16, K_NBASE
 };
 // class index = base * 2 + (fp32 ? 1 : 0)
 constexpr int K_COUNT = 2 * K_NBASE;

@@ -198,7 +198,13 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   TruncPlan<T> p;
   GramJob<T> g1[2] = {{A, n, st.G[0], st.k}, {B, m, st.G[1], nullptr}};
   p.g1 = make_gram<T>(g1, 2, kcap, gws, gram_bytes, st.info);
-  p.c1 = CholArgs{st, 1, kcap, eps};
+  // bf16 first pass (fp32 operands only): the Gram carries relative errors of
+  // a few 2^-9 per entry, so its Cholesky starts from a preset shift of 1e-2
+  // (on the unit diagonal) and takes the pivot threshold of bf16 rounding;
+  // the fp32 second pass restores orthogonality
+  const bool b16 = bf16 && sizeof(T) == 4;
+  p.g1.bf16 = b16;
+  p.c1 = CholArgs{st, 1, kcap, b16 ? 4e-3 : eps, b16 ? 1e-2 : 0.0};
   TsmmJob<T> t1[2] = {{A, n, st.T1[0], kcap, st.k, qa, ldq}, {B, m, st.T1[1], kcap, st.k, qb, ldq}};
   // the first pass writes st.k <= min(kcap, width bound) columns
   // (T1 = D R1^{-1} is upper triangular)
@@ -207,9 +213,9 @@ TruncPlan<T> Truncator<T>::plan(const BlockView<T>& A, int64_t n, const BlockVie
   va.cap[0] = vb.cap[0] = std::min(kcap, std::max(view_cap(A), view_cap(B)));
   GramJob<T> g2[2] = {{va, n, st.G[0], nullptr}, {vb, m, st.G[1], nullptr}};
   p.g2 = make_gram<T>(g2, 2, kcap, gws, gram_bytes, st.info);
-  p.c2 = CholArgs{st, 2, kcap, eps};
+  p.c2 = CholArgs{st, 2, kcap, eps, 0.0};
   make_core_gemms(st, core, kcap, p.core);
-  p.qr = QrArgs{st, kcap, tol, abs_tol};
+  p.qr = QrArgs{st, kcap, tol, abs_tol, sizeof(T) == 4 ? 1e-7 : 0.0};
   p.jac = JacArgs{st, kcap, max_rounds, tol, abs_tol};
   p.rep = RepArgs{st, kcap};
   SmallGemmArgs fin[2];
@@ -777,12 +783,15 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
                                                     ? 1e-6
                                                     : 1e-2 * (o.inner_tol > 0 ? o.inner_tol : 1e-3));
   LRC_CHECK(o.precision == LRC_FP64 || o.precision == LRC_MIXED_FP32 ||
-                o.precision == LRC_MIXED_FP32_DIR,
+                o.precision == LRC_MIXED_FP32_DIR || o.precision == LRC_MIXED_BF16GRAM,
             ST_EINVAL, "lrc_solve: unknown precision");
   LRC_CHECK(o.solver == LRC_SOLVER_CHEBYSHEV ||
                 (o.solver == LRC_SOLVER_GMREST && o.precision == LRC_FP64),
             ST_EINVAL, "lrc_solve: unknown solver (GMREST runs in fp64)");
-  if (o.precision == LRC_MIXED_FP32) alloc_mixed();
+  if (o.precision == LRC_MIXED_FP32 || o.precision == LRC_MIXED_BF16GRAM) {
+    alloc_mixed();
+    c32->tr.bf16 = o.precision == LRC_MIXED_BF16GRAM;
+  }
   if (o.precision == LRC_MIXED_FP32_DIR) ensure_cheb(c32, P, cap);   // fp32 direction and Z
 }
 

@@ -129,6 +129,7 @@ struct Truncator {
   T* qa = nullptr;                // first-pass factor of the A side (nmax x kcap)
   T* qb = nullptr;                // first-pass factor of the B side (mmax x kcap)
   size_t arena_bytes = 0, ints_bytes = 0, gram_bytes = 0;
+  bool bf16 = false;              // first CholeskyQR pass on bf16 Gram products (fp32 only)
   TruncState st{};
   // owns a workspace for nmax_ x mmax_ rows (grow-only)
   void alloc(int64_t nmax_, int64_t mmax_, hipStream_t s);

@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrcheb.h")
 
 LRC_OK, LRC_ENOTCONV, LRC_EINVAL, LRC_ENOMEM, LRC_EDEVICE = 0, 1, -1, -2, -3
 LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
-LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR = 0, 1, 2
+LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR, LRC_MIXED_BF16GRAM = 0, 1, 2, 3
 LRC_SOLVER_CHEBYSHEV, LRC_SOLVER_GMREST = 0, 1
 LRC_SPMM_SKIP_EMPTY = 4
 LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN, LRC_INIT_GIVEN_JUDGED, LRC_INIT_NEWTON = 0, 1, 2, 3, 4
@@ -494,11 +494,12 @@ def profile_read():
             for i in range(n)}
 
 
-def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V, noalloc=False):
+def truncate_dev(ctx, A, c, B, rank_cap, tol, U, V, noalloc=False, bf16=False):
     """lrc_truncate_dev on row-major device tensors; returns (s, rank).
-    noalloc=True calls lrc_truncate_noalloc_dev (fixed per-device scratch)."""
+    noalloc=True calls lrc_truncate_noalloc_dev (fixed per-device scratch);
+    bf16=True (fp32 tensors) takes the first CholeskyQR pass on bf16 Grams."""
     import torch
-    dtype = 0 if A.dtype == torch.float64 else 1
+    dtype = 0 if A.dtype == torch.float64 else (2 if bf16 else 1)
     cc = _f64(np.ravel(c))
     n, k = A.shape[0], cc.size
     m = B.shape[0]
