@@ -196,18 +196,27 @@ lrc_status lrc_prob_create(lrc_ops ops, int64_t m, const double* d, int rF, cons
                            const double* Fs, const double* FV, lrc_prob* prob);
 void lrc_prob_destroy(lrc_prob prob);
 /* Factorise P = sum_i dbar_i K_i (dbar: q values, NULL = arithmetic means of the
- * rows of d).  Nested-dissection ordering + multifrontal LU without pivoting
- * on the host, inverted supernode blocks uploaded for the level-scheduled GPU
- * solves.  leaf_size: nodes per nested-dissection leaf (<= 0: the default, 64).
- * LRC_ESINGULAR on a bad pivot. */
-lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size);
+ * rows of d), the centre preconditioner of Sec. 4.2.  kind LRC_PREC_LU: the
+ * exact factorisation Sec. 5 uses (nested-dissection ordering + multifrontal
+ * LU without pivoting on the host, inverted supernode blocks uploaded for the
+ * level-scheduled GPU solves; leaf_size: nodes per nested-dissection leaf,
+ * <= 0: the default, 64).  kind LRC_PREC_ILU0: the incomplete LU without
+ * fill on P's pattern (for operators whose exact factors do not fit), applied
+ * by one launch per level of its triangular solves; leaf_size is ignored.
+ * lrc_prob_spectrum's interval holds for the exact kind only: with ILU(0)
+ * give cheb_c / cheb_d or use LRC_SOLVER_GMREST.  LRC_ESINGULAR on a zero or
+ * non-finite pivot. */
+enum { LRC_PREC_LU = 0, LRC_PREC_ILU0 = 1 };
+lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size, int kind);
 /* Interval [d - c, d + c] enclosing the preconditioned spectra: the smallest
  * interval holding 1 and every ratio d[i, j] / dbar_i (valid when K_0 + K_0^T
  * and K_1..K_{q-1} are positive semi-definite). */
 lrc_status lrc_prob_spectrum(lrc_prob prob, double* c, double* d);
 /* Statistics of the factorisation: out[0] supernodes, [1] forward levels,
  * [2] backward levels, [3] max front, [4] stored block entries,
- * [5] host ordering s, [6] host factor s, [7] upload s. */
+ * [5] host ordering s, [6] host factor s, [7] upload s.  For ILU(0): [0]
+ * rows, [1], [2] the levels of its two triangular solves, [3] 1, [4] stored
+ * entries of L\U, [5], [6] 0, [7] upload s. */
 lrc_status lrc_prob_precond_stats(lrc_prob prob, double out[8]);
 /* Z = P^{-1} R on device columns (row-major n x k, k <= 64). dtype 0/1. */
 lrc_status lrc_prob_prec_apply_dev(lrc_prob prob, int dtype, int k, const void* R_dev, int ldr,
@@ -374,6 +383,7 @@ typedef int (*lrc_linearize_fn)(void* user, int k, int stage, const double* x,
  *      operators (eq. picard_matrix1).
  * cb NULL: the operators are linear (J = K) and B_k(x) = f 1^T - L(x 1^T),
  * with f (n values) the load vector; f is ignored when cb is given.
+ * kind: the preconditioner (LRC_PREC_LU or LRC_PREC_ILU0) of every subset.
  * Results: out[k] receives the subset's problem (owned by the caller, free
  * with lrc_prob_destroy; its solution is X^k); info[k] (may be NULL) its
  * statistics, relative to ||b|| sqrt(m_k); sizes_out (K values, may be NULL)
@@ -381,8 +391,8 @@ typedef int (*lrc_linearize_fn)(void* user, int k, int stage, const double* x,
 lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
                               const int64_t* sizes, const double* f, const double* x_init,
                               lrc_linearize_fn cb, void* user, double eps_newton,
-                              int newton_max, int picard, const lrc_opts* opts, lrc_prob* out,
-                              lrc_info* info, int64_t* sizes_out);
+                              int newton_max, int picard, int kind, const lrc_opts* opts,
+                              lrc_prob* out, lrc_info* info, int64_t* sizes_out);
 
 /* --------------------------------------------------------------- theta-scheme
  * Time stepping of one parameter subset (Sec. 4.3, eq. timedep_matrix1) for

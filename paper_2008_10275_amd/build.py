@@ -23,7 +23,7 @@ HOST_FLAGS = ["-O3", "-mavx2", "-mfma", "-fopenmp", "-fPIC", "-std=c++17"]
 
 HIP_SOURCES = ["k_sparse.hip", "k_dense.hip", "k_small.hip", "k_mlp.hip", "solver.cpp", "batch.cpp",
                "tune.cpp", "capi.cpp", "prof.cpp", "noalloc.hip", "timedep.cpp", "gmrest.cpp"]
-HOST_SOURCES = ["host/ndfact.cpp"]
+HOST_SOURCES = ["host/ndfact.cpp", "host/ilu0.cpp"]
 
 
 def _run(cmd):

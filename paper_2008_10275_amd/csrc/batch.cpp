@@ -119,7 +119,10 @@ struct PrecBatch {
     kcap = kcap_;
     ldw = ldw_;
     for (auto* x : pre)
-      if (!same_structure(x->F, pre[0]->F)) shared = false;
+      if (x->kind != pre[0]->kind ||
+          (x->kind == 0 ? !same_structure(x->F, pre[0]->F)
+                        : (x->ilu.rowptr != pre[0]->ilu.rowptr || x->ilu.col != pre[0]->ilu.col)))
+        shared = false;
     for (const auto& x : items) check_prec_item(x, kcap, ldw);
     all = upload_items(items, done, buf, s);
     one.clear();

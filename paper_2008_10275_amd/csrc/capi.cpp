@@ -168,6 +168,7 @@ void upload_prec(Prec& pr, hipStream_t s) {
   }
   pr.cb_rows = F.cb_off[F.nsn];
   auto fill = [&](auto& P, const void* fw, const void* bw) {
+    P.kind = 0;
     P.n = F.n;
     P.perm = pr.perm.as<int>();
     P.j0 = pr.j0.as<int>();
@@ -599,18 +600,85 @@ lrc_status lrc_prob_create(lrc_ops ops, int64_t m, const double* d, int rF, cons
 
 void lrc_prob_destroy(lrc_prob prob) { delete prob; }
 
-lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size) {
+// ILU(0) of P on the device: L\U values in fp64 and fp32 on P's pattern, the
+// level row lists, one level entry per forward / backward level
+static void upload_ilu(Prec& pr, hipStream_t s) {
+  auto t0 = clk::now();
+  const Ilu0& I = pr.ilu;
+  std::vector<int> rp(I.rowptr.begin(), I.rowptr.end());
+  pr.irp = upload(rp, s);
+  pr.icol = upload(I.col, s);
+  pr.idiag = upload(I.diag, s);
+  pr.irows_f = upload(I.rows_f, s);
+  pr.irows_b = upload(I.rows_b, s);
+  pr.ilu64 = upload(I.lu, s);
+  std::vector<float> f32(I.lu.begin(), I.lu.end());
+  pr.ilu32 = upload(f32, s);
+  LRC_HIP(hipStreamSynchronize(s));   // rp and f32 are temporaries
+  auto levels = [&](const std::vector<int32_t>& rows, const std::vector<int32_t>& off, bool fw,
+                    std::vector<LevelTasks>& out) {
+    out.clear();
+    for (size_t l = 0; l + 1 < off.size(); ++l) {
+      LevelTasks L{};
+      L.count = off[l + 1] - off[l];
+      L.ilu_off = off[l];
+      int64_t nnz = 0;
+      for (int32_t x = off[l]; x < off[l + 1]; ++x) {
+        const int32_t r = rows[x];
+        nnz += fw ? I.diag[r] - I.rowptr[r] : I.rowptr[r + 1] - I.diag[r];
+      }
+      L.ilu_nnz = nnz;
+      out.push_back(L);
+    }
+  };
+  levels(I.rows_f, I.off_f, true, pr.fwd);
+  levels(I.rows_b, I.off_b, false, pr.bwd);
+  pr.stage_rows = 0;
+  pr.cb_rows = 0;
+  auto fill = [&](auto& P, const void* lu) {
+    P = {};
+    P.kind = 1;
+    P.n = I.n;
+    P.irp = pr.irp.as<int>();
+    P.icol = pr.icol.as<int>();
+    P.idiag = pr.idiag.as<int>();
+    P.irows_f = pr.irows_f.as<int>();
+    P.irows_b = pr.irows_b.as<int>();
+    using TT = std::remove_const_t<std::remove_pointer_t<decltype(P.fw)>>;
+    P.fw = static_cast<const TT*>(lu);
+    P.bw = static_cast<const TT*>(lu);
+  };
+  fill(pr.p64, pr.ilu64.p);
+  fill(pr.p32, pr.ilu32.p);
+  pr.seconds_upload = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+lrc_status lrc_prob_precondition(lrc_prob prob, const double* dbar, int leaf_size, int kind) {
   if (!prob) return LRC_EINVAL;
   Prob& P = prob->p;
   return guarded(P.ctx, [&]() -> lrc_status {
     auto t0 = clk::now();
     const Ops& o = *P.ops;
+    LRC_CHECK(kind == LRC_PREC_LU || kind == LRC_PREC_ILU0, ST_EINVAL,
+              "lrc_prob_precondition: kind must be LRC_PREC_LU or LRC_PREC_ILU0");
     if (dbar) {
       for (int i = 0; i < o.q; ++i)
         LRC_CHECK(std::isfinite(dbar[i]), ST_EINVAL, "lrc_prob_precondition: non-finite dbar");
       P.dbar.assign(dbar, dbar + o.q);
     }
     CsrHost Pm = combine(o, P.dbar);
+    if (kind == LRC_PREC_ILU0) {
+      auto pr = std::make_unique<Prec>();
+      pr->kind = 1;
+      std::string err;
+      const int rc = ilu0_factor(Pm, &pr->ilu, &err);
+      if (rc == -4) throw Error(ST_ESINGULAR, err);
+      if (rc != 0) throw Error(ST_EINVAL, err);
+      upload_ilu(*pr, P.ctx->stream);
+      P.prec = std::move(pr);
+      P.seconds_setup = std::chrono::duration<double>(clk::now() - t0).count();
+      return LRC_OK;
+    }
     auto pr = std::make_unique<Prec>();
     std::string err;
     // 64-node leaves: two tree levels (six launches per apply) fewer than 16-node
@@ -648,6 +716,19 @@ lrc_status lrc_prob_precond_stats(lrc_prob prob, double out[8]) {
     return LRC_EINVAL;
   }
   const auto& F = P.prec->F;
+  if (P.prec->kind == 1) {
+    // ILU(0): rows as "supernodes", its levels, no dense fronts, its entries
+    const Ilu0& I = P.prec->ilu;
+    out[0] = double(I.n);
+    out[1] = double(I.off_f.size() - 1);
+    out[2] = double(I.off_b.size() - 1);
+    out[3] = 1.0;
+    out[4] = double(I.lu.size());
+    out[5] = 0.0;
+    out[6] = 0.0;
+    out[7] = P.prec->seconds_upload;
+    return LRC_OK;
+  }
   out[0] = F.nsn;
   out[1] = F.nlev_fwd;
   out[2] = F.nlev_bwd;
@@ -891,8 +972,8 @@ lrc_status lrc_truncate_scaled_dev(lrc_ctx ctx, int dtype, int64_t n, int64_t m,
 lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
                               const int64_t* sizes, const double* f, const double* x_init,
                               lrc_linearize_fn cb, void* user, double eps_newton,
-                              int newton_max, int picard, const lrc_opts* opts, lrc_prob* out,
-                              lrc_info* info, int64_t* sizes_out) {
+                              int newton_max, int picard, int kind, const lrc_opts* opts,
+                              lrc_prob* out, lrc_info* info, int64_t* sizes_out) {
   if (!ops || !opts || !out || !d) return LRC_EINVAL;
   Ops& base = ops->o;
   return guarded(base.ctx, [&]() -> lrc_status {
@@ -1009,7 +1090,7 @@ lrc_status lrc_newton_subsets(lrc_ops ops, int64_t m, const double* d, int K,
         if (st != LRC_OK) throw Error(st, lrc_last_error(cx));
         std::unique_ptr<lrc_prob_s> np(tmp);
         if (refactor || !pb || !pb->p.prec) {
-          st = lrc_prob_precondition(np.get(), nullptr, 0);
+          st = lrc_prob_precondition(np.get(), nullptr, 0, kind);
           if (st != LRC_OK) throw Error(st, lrc_last_error(cx));
         } else {
           np->p.prec = std::move(pb->p.prec);

@@ -524,6 +524,64 @@ static void launch_product_nw(int KTM, dim3 grid, dim3 blk, hipStream_t s, const
 #undef LRC_PP
 }
 
+// ILU(0) triangular solves, one launch per level: a thread takes one (row,
+// column) of the level, y_i = r_i - sum_{j < i} L_ij y_j forward and
+// z_i = (y_i - sum_{j > i} U_ij z_j) / U_ii backward; the rows a level reads
+// belong to earlier launches.  Threads of one row are consecutive, so the
+// reads of a neighbour's row are contiguous.
+template <class T, bool FWD>
+__global__ __launch_bounds__(256) void ilu_level_kernel(PrecDev<T> P, int off, int count,
+                                                        PrecItem<T> it0, const PrecItem<T>* ab,
+                                                        const int* done, int ldw) {
+  if (done && done[blockIdx.z]) return;
+  const PrecItem<T>& it = ab ? ab[blockIdx.z] : it0;
+  const int k = it.k_dev ? *it.k_dev : it.k_const;
+  if (k <= 0) return;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(count) * k) return;
+  const int c = int(t % k);
+  const int row = (FWD ? P.irows_f : P.irows_b)[off + int(t / k)];
+  const T* __restrict__ lu = it.fw;
+  const int d = P.idiag[row];
+  if (FWD) {
+    T acc = it.R[int64_t(row) * it.ldr + c];
+    for (int e = P.irp[row]; e < d; ++e) acc -= lu[e] * it.y[int64_t(P.icol[e]) * ldw + c];
+    it.y[int64_t(row) * ldw + c] = acc;
+  } else {
+    T acc = it.y[int64_t(row) * ldw + c];
+    for (int e = d + 1; e < P.irp[row + 1]; ++e) acc -= lu[e] * it.Z[int64_t(P.icol[e]) * it.ldz + c];
+    it.Z[int64_t(row) * it.ldz + c] = acc / lu[d];
+  }
+}
+
+template <class T>
+static void enqueue_ilu_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
+                              const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
+                              Batched<PrecItem<T>> b, int kcap, int ldw, hipStream_t s,
+                              const std::vector<WTerm>& kt) {
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fw = pass == 0;
+    for (const auto& L : fw ? fwd : bwd) {
+      if (L.count == 0) continue;
+      Work w;
+      w.groups = {kt};
+      const double nnz = double(L.ilu_nnz), rows = double(L.count);
+      w.f = [=](const std::vector<double>& v) {
+        return nnz * (sizeof(T) + 4) + (nnz + 2.0 * rows) * v[0] * sizeof(T);
+      };
+      ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, w);
+      const dim3 grid(unsigned(ceil_div(int64_t(L.count) * kcap, 256)), 1, b.n);
+      if (fw)
+        hipLaunchKernelGGL((ilu_level_kernel<T, true>), grid, dim3(256), 0, s, P, L.ilu_off,
+                           L.count, it, b.dev, b.done, ldw);
+      else
+        hipLaunchKernelGGL((ilu_level_kernel<T, false>), grid, dim3(256), 0, s, P, L.ilu_off,
+                           L.count, it, b.dev, b.done, ldw);
+    }
+  }
+  LRC_HIP(hipGetLastError());
+}
+
 template <class T>
 void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                         const std::vector<LevelTasks>& bwd, const PrecItem<T>& it,
@@ -531,6 +589,10 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                         const std::vector<WTerm>* kterms) {
   check_prec_item(it, kcap, ldw);
   const std::vector<WTerm> kt = kterms ? *kterms : std::vector<WTerm>{{it.k_dev, it.k_const}};
+  if (P.kind == 1) {
+    enqueue_ilu_apply(P, fwd, bwd, it, b, kcap, ldw, s, kt);
+    return;
+  }
   constexpr int VN = V16<T>::n;
   const int vpr = (kcap + VN - 1) / VN;
   const int KTM = (kcap + 15) / 16;

@@ -101,6 +101,8 @@ struct LevelTasks {
   double blk;          // nonzero dense block entries the level's products read
   int64_t in_rows;     // staged rows the products read (per column)
   int64_t out_rows;    // rows the products write (per column)
+  int ilu_off;         // ILU(0): the level's rows start here in the level row list
+  int64_t ilu_nnz;     // ILU(0): entries of the level's rows in its triangle
 };
 
 template <class T>
@@ -124,6 +126,14 @@ struct PrecDev {
   const int64_t* soff_bwd;   // ... in its backward level
   const int* leaf;           // 1: the supernode has no children, so no front reads
                              // its rows of the permuted solution x (backward)
+  // kind 1 (ILU(0)): L\U on the pattern of P (values: the item's fw), the
+  // diagonal positions and the rows of the levels (forward, backward)
+  int kind;
+  const int* irp;
+  const int* icol;
+  const int* idiag;
+  const int* irows_f;
+  const int* irows_b;
 };
 
 // Z = P^{-1} R  (R, Z: n x k row-major; k read from k_dev or k_const, <= kcap <= 64).

@@ -625,7 +625,13 @@ double residual_fp64(Prob& P, const LR<double>& X0, int r0, const LR<double>& S,
     add_block(B, S.v(), lds, S.r(), 0, P.drow(i));
     add_core(c, S.sv(), -1.0, S.r(), 0);
   }
-  LRC_CHECK(P.rF + o.q * (X0.cap + S.cap) <= 192, ST_EINVAL,
+  // the blocks' host-side width bounds are the factors' rank caps (their
+  // leading dimensions round those up to 8)
+  for (int b = 0; b < A.nb; ++b) {
+    const int cb = b == 0 ? P.rF : (r0 > 0 && (b - 1) % 2 == 0) ? X0.cap : S.cap;
+    A.cap[b] = B.cap[b] = std::min(A.cap[b], cb);
+  }
+  LRC_CHECK(P.rF + o.q * ((r0 > 0 ? X0.cap : 0) + S.cap) <= 192, ST_EINVAL,
             "fp64 residual: more than 192 concatenated columns");
   ensure(P.res_colsq, size_t(m) * 8);
   const size_t wsb = residual_workspace_bytes(n, m);
@@ -946,6 +952,9 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
   inf.info_flags = flags;
   Pr.newton_point = newton_point;
   Pr.ref = ref;
+  if (flags & 8)
+    throw Error(ST_EINVAL, "truncation capacity exceeded: more than 128 concatenated columns "
+                           "(reduce rank_cap or the rank of the right-hand side)");
   if (o.verify_fp64) {
     std::vector<double> col(m);
     const double nr = residual_fp64(Pr, Pr.X0, newton_point ? 0 : Pr.rank_x0, Pr.S, col.data());
@@ -976,9 +985,6 @@ lrc_status SolveRun::finish(const lrc_opts& o, lrc_info* info) {
   const bool ok = conv && (!o.verify_fp64 || inf.relres <= o.res_tol);
   inf.status = ok ? ST_OK : ST_NOTCONV;
   if (info) *info = inf;
-  if (flags & 8)
-    throw Error(ST_EINVAL, "truncation capacity exceeded: more than 128 concatenated columns "
-                           "(reduce rank_cap or the rank of the right-hand side)");
   return ok ? ST_OK : ST_NOTCONV;
 }
 

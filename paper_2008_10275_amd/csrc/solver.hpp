@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/lrcheb.h"
+#include "host/ilu0.h"
 #include "host/ndfact.h"
 #include "kernels.hpp"
 
@@ -45,8 +46,12 @@ struct Ops {
   void upload_values(int i);
 };
 
-// supernodal factor of the preconditioner on the device
+// factor of the preconditioner on the device: supernodal exact LU (kind 0)
+// or ILU(0) on the pattern of P (kind 1)
 struct Prec {
+  int kind = 0;
+  Ilu0 ilu;             // kind 1: host copy of the incomplete factor
+  DevBuf irp, icol, idiag, irows_f, irows_b, ilu64, ilu32;
   SupernodalFactor F;   // host copy (blocks freed after upload)
   DevBuf perm, j0, ns, nb, fw_off, bw_off, front_off, cb_off, asm_ptr, asm_src, bnd_off, bnd, leaf;
   DevBuf fw64, bw64, fw32, bw32;

@@ -162,7 +162,7 @@ extern "C" lrc_status lrc_theta_scheme(lrc_ops ops, const int64_t* M_rowptr, con
         pb->p.prec = std::move(prev->p.prec);
         pb->p.seconds_setup = prev->p.seconds_setup;
       } else {
-        st = lrc_prob_precondition(pb.get(), nullptr, 0);
+        st = lrc_prob_precondition(pb.get(), nullptr, 0, LRC_PREC_LU);
         if (st != LRC_OK) return st;
       }
       lrc_opts o = *opts;

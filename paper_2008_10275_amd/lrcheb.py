@@ -26,6 +26,7 @@ LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
 LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR, LRC_MIXED_BF16GRAM = 0, 1, 2, 3
 LRC_SOLVER_CHEBYSHEV, LRC_SOLVER_GMREST = 0, 1
 LRC_SPMM_SKIP_EMPTY = 4
+LRC_PREC_LU, LRC_PREC_ILU0 = 0, 1
 LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN, LRC_INIT_GIVEN_JUDGED, LRC_INIT_NEWTON = 0, 1, 2, 3, 4
 
 
@@ -79,7 +80,7 @@ _SIGS = {
     "lrc_ops_spmm_shape_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int, _P]),
     "lrc_prob_create": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, _P, C.POINTER(_P)]),
     "lrc_prob_destroy": (None, [_P]),
-    "lrc_prob_precondition": (C.c_int, [_P, _P, C.c_int]),
+    "lrc_prob_precondition": (C.c_int, [_P, _P, C.c_int, C.c_int]),
     "lrc_prob_spectrum": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lrc_prob_precond_stats": (C.c_int, [_P, _P]),
     "lrc_prob_prec_apply_dev": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, C.c_int]),
@@ -114,7 +115,7 @@ _SIGS = {
                                    _P, C.c_double, C.c_double, C.c_int, C.POINTER(lrc_opts),
                                    C.POINTER(_P), C.POINTER(lrc_info)]),
     "lrc_newton_subsets": (C.c_int, [_P, C.c_int64, _P, C.c_int, _P, _P, _P, LINEARIZE_FN, _P,
-                                     C.c_double, C.c_int, C.c_int, C.POINTER(lrc_opts),
+                                     C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(lrc_opts),
                                      C.POINTER(_P), C.POINTER(lrc_info), _P]),
 }
 
@@ -297,9 +298,11 @@ class Problem:
                                                        _ptr(FU), _ptr(fs), _ptr(FV),
                                                        C.byref(self.handle)))
 
-    def precondition(self, dbar=None, leaf_size=0):
+    def precondition(self, dbar=None, leaf_size=0, kind=0):
+        """lrc_prob_precondition; kind LRC_PREC_LU (exact) or LRC_PREC_ILU0."""
         db = None if dbar is None else _f64(dbar)
-        _check(self.ctx.handle, load().lrc_prob_precondition(self.handle, _ptr(db), leaf_size))
+        _check(self.ctx.handle, load().lrc_prob_precondition(self.handle, _ptr(db), leaf_size,
+                                                             kind))
 
     def spectrum(self):
         c, d = C.c_double(), C.c_double()
@@ -536,7 +539,7 @@ def truncate_scaled_dev(ctx, A, c, B, k1, w, rank_cap, tol, U, V):
 
 
 def newton_subsets(ops, d, K, f=None, opts=None, sizes=None, linearize=None, x_init=None,
-                   eps_newton=None, newton_max=8, picard=False, **kw):
+                   eps_newton=None, newton_max=8, picard=False, prec_kind=0, **kw):
     """lrc_newton_subsets (Algorithm 1).
 
     linearize(k, stage, x) -> (vals, BU, BV, bnorm): vals a list of q value
@@ -598,7 +601,8 @@ def newton_subsets(ops, d, K, f=None, opts=None, sizes=None, linearize=None, x_i
         sizes_out[:] = sz if sz is not None else [m // K] * (K - 1) + [m - (K - 1) * (m // K)]
     code = lib.lrc_newton_subsets(ops.handle, dd.shape[1], _ptr(dd), K, _ptr(sz), _ptr(ff),
                                   _ptr(xi), cb, None, float(eps_newton), int(newton_max),
-                                  int(bool(picard)), C.byref(o), out, infos, _ptr(sizes_out))
+                                  int(bool(picard)), int(prec_kind), C.byref(o), out, infos,
+                                  _ptr(sizes_out))
     if err:
         raise err[0]
     _check(ops.ctx.handle, code)

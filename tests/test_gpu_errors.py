@@ -99,3 +99,26 @@ def test_wrong_interval_does_not_converge(torch, L):
     # the right interval converges on the same problem
     code, info = p.solve(rank_cap=20, trunc_tol=1e-8, res_tol=1e-8, init=L.LRC_INIT_MEDIAN)
     assert code == 0 and info["relres"] <= 1e-8
+
+
+def test_truncation_capacity_exceeded(torch, L):
+    """A random right-hand side of rank 8 (the least room the solver keeps
+    for it) with rank_cap 64 and q = 3: once S passes rank 40 the residual
+    B - L(S) concatenates more than 8 + 3 * 40 columns, beyond the
+    truncation's 128.
+    The device clamps the width (no access past the workspace), flags it, and
+    the call fails with LRC_EINVAL naming the capacity, before the fp64
+    residual check."""
+    say("truncation capacity")
+    ctx = L.Context(0)
+    cfg = config("c1")
+    K, d = cfg["ops"].K, cfg["d"]
+    n, m = K[0].shape[0], d.shape[1]
+    rng = np.random.default_rng(11)
+    ops = L.Operators(ctx, K)
+    p = L.Problem(ops, d, rng.standard_normal((n, 8)), rng.standard_normal((m, 8)))
+    p.precondition()
+    with pytest.raises(L.LrcError) as e:
+        p.solve(rank_cap=64, trunc_tol=1e-14, res_tol=1e-12, init=L.LRC_INIT_ZERO, max_iter=12)
+    say("error", e.value.code, str(e.value))
+    assert e.value.code == L.LRC_EINVAL and "capacity" in str(e.value)
