@@ -94,7 +94,8 @@ typedef struct {
   double cheb_d;       /* centre of the spectrum interval                       */
   int precision;       /* LRC_FP64, LRC_MIXED_FP32 or LRC_MIXED_FP32_DIR          */
   int refine_max;      /* mixed: maximum fp64 refinement steps                  */
-  double inner_tol;    /* mixed: residual reduction asked of each fp32 inner solve */
+  double inner_tol;    /* mixed: residual reduction asked of each fp32 inner solve
+                          (default 1e-4)                                         */
   int init;            /* LRC_INIT_*                                            */
   double median_tol;   /* relative residual of the median-parameter solve (the
                           accuracy eps_N of Sec. 3.1; default 1e-6 as in Sec. 5) */

@@ -333,7 +333,7 @@ void lrc_opts_default(lrc_opts* o) {
   o->cheb_d = 0.0;
   o->precision = LRC_FP64;
   o->refine_max = 8;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-4;
   o->init = LRC_INIT_MEDIAN;
   o->median_tol = 1e-6;   // the Newton accuracy of the median problem in Sec. 5
   o->verify_fp64 = 1;

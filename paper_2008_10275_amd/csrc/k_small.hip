@@ -417,7 +417,7 @@ constexpr int kJacE = 16;                   // column entries per lane (k <= 16 
 static_assert(SK * SK <= kJacLds, "X must fit in LDS at the largest width");
 static_assert(kJacE * 8 >= SK, "a team of 8 lanes must hold a column");
 // One round for the pairs of one team size TL (16 lanes per pair while at
-// most 32 pairs fit the 8 waves, else 8): a lane keeps its E = k / TL entries
+// most 32 pairs fit the 8 waves, else 8): a lane keeps its E >= k / TL entries
 // of both columns in registers between the dot products and the rotation, so
 // that a round reads each column from LDS once and writes it once.
 // Sum of a double over the 16 lanes of a DPP row, in every lane: four
@@ -438,10 +438,28 @@ __device__ __forceinline__ double row_sum16(double x) {
   return x;
 }
 
-template <int TL>
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// each (quadratic convergence from the estimate's ~2^-23 to the last bits);
+// x finite and normal.  The fp64 divide and square root expand to long
+// dependent sequences that set the length of a Jacobi round.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
+// E: column entries per lane actually live (k <= TL E), so that a narrow core
+// issues no work for the empty slots
+template <int TL, int E>
 __device__ __forceinline__ int jacobi_pair(double* X, double* Y, bool fuse, int k, int kj, int p,
                                            int q, int tl, double* cs, double& dmax) {
-  constexpr int E = SK / TL;
   double* xp = X + p * k;
   double* xq = X + q * k;
   double u[E], v[E];
@@ -472,17 +490,20 @@ __device__ __forceinline__ int jacobi_pair(double* X, double* Y, bool fuse, int 
     }
   }
   double c = 1.0, s = 0.0;
-  const double nab = sqrt(al * be);
-  if (nab > 1e-300) dmax = fmax(dmax, fabs(ga) / nab);
-  // only an underflow guard: pairs of tiny columns are still rotated, so that
+  // squared relative coupling g^2 / (a b) (the exit test needs no accuracy)
+  const double ab = al * be, g2 = ga * ga;
+  if (ab > 1e-300) dmax = fmax(dmax, g2 * __builtin_amdgcn_rcp(ab));
+  // rotate when |g| > 1e-14 sqrt(a b); where a b underflows only the guard
+  // |g| > 1e-300 applies: pairs of tiny columns are still rotated, so that
   // the singular vectors of small singular values stay orthogonal
-  if (fabs(ga) > fmax(1e-14 * nab, 1e-300)) {
-    const double zeta = (be - al) / (2.0 * ga);
+  if (fabs(ga) > 1e-300 && (g2 > 1e-28 * ab || !(ab > 0.0))) {
+    const double zeta = (be - al) * (0.5 * rcp_nr(ga));
     const double az = fabs(zeta);
     // sqrt(1 + zeta^2) without overflow for huge |zeta|
-    const double hyp = az > 1e150 ? az : sqrt(1.0 + az * az);
-    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (az + hyp);
-    c = 1.0 / sqrt(1.0 + tt * tt);
+    const double w = fma(az, az, 1.0);
+    const double hyp = az > 1e150 ? az : w * rsq_nr(w);
+    const double tt = zeta >= 0.0 ? rcp_nr(az + hyp) : -rcp_nr(az + hyp);
+    c = rsq_nr(fma(tt, tt, 1.0));
     s = c * tt;
   }
   cs[0] = c;
@@ -538,7 +559,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
   const int slot = wave * (64 / TL) + lane / TL;
   const int tl = lane % TL;
   // Sweeps end when none rotates, or once the largest relative coupling
-  // |x_p^T x_q| / (||x_p|| ||x_q||) met in a sweep is below 1e-7: convergence
+  // |x_p^T x_q| / (||x_p|| ||x_q||) met in a sweep is below 1e-7 (its square
+  // below 1e-14): convergence
   // is quadratic, so the next sweep would only meet couplings near 1e-14,
   // the rounding level of the dot products themselves (a sweep spent on
   // rounding noise is saved).
@@ -553,9 +575,18 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
         int p = rr_player(slot, t, kp), q = rr_player(kp - 1 - slot, t, kp);
         if (p > q) { const int x = p; p = q; q = x; }
         double cs[2] = {1.0, 0.0};
-        if (q < kj)
-          any |= wide ? jacobi_pair<8>(X, Y, fuse, k, kj, p, q, tl, cs, dmax)
-                      : jacobi_pair<16>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+        if (q < kj) {
+          if (wide)
+            any |= jacobi_pair<8, SK / 8>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+          else if (k <= 16)
+            any |= jacobi_pair<16, 1>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+          else if (k <= 32)
+            any |= jacobi_pair<16, 2>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+          else if (k <= 64)
+            any |= jacobi_pair<16, 4>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+          else
+            any |= jacobi_pair<16, SK / 16>(X, Y, fuse, k, kj, p, q, tl, cs, dmax);
+        }
         if (!fuse && tl == 0) {
           st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 0] = cs[0];
           st.rot[(size_t(round) * (SK / 2) + slot) * 2 + 1] = cs[1];
@@ -568,7 +599,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(JacArgs a0, const J
     if (!__syncthreads_or(any)) { converged = true; break; }
     double dm = 0.0;
     for (int w = 0; w < kJacThreads / 64; ++w) dm = fmax(dm, s_dmax[w]);
-    if (dm < 1e-7) { converged = true; break; }
+    if (dm < 1e-14) { converged = true; break; }
   }
   for (int a = tid; a < kj; a += nt) {
     double sq = 0.0;
@@ -681,22 +712,23 @@ __device__ inline double team8_sum(double v) {
   v += __shfl_xor(v, 1);
   return v;
 }
-__global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArgs* ab,
-                                                          const int* done) {
-  LRC_ITEM(QrArgs, qa_, a0, ab, done)
+// NS: slots per lane actually live (k <= 8 NS), so that a narrow core issues
+// no work for the empty slots.  Waves whose teams all lie beyond k only keep
+// the barriers: the pivot search runs in the waves that hold columns, and
+// wave 0 publishes the stop decision for the others.
+template <int NS>
+__device__ __forceinline__ void qrcp_body(const QrArgs& qa_, int k, double* nrm, double* vb,
+                                          double* s_tau, int* s_stop) {
   const TruncState& st = qa_.st;
   const int kcap = qa_.kcap;
-  __shared__ double nrm[SK];     // trailing squared norm of each column (-1: chosen or absent)
-  __shared__ double vb[SK];      // reflector of the current step
-  __shared__ double s_tau;
-  const int k = *st.k;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int team = tid >> 3, tl = tid & 7;
   const bool inside = team < k;
-  double mc[kQrSlots], qr[kQrSlots];
+  const bool wave_live = wave * (64 / kQrTeam) < k;
+  double mc[NS], qr[NS];
   double ss = 0.0;
 #pragma unroll
-  for (int t = 0; t < kQrSlots; ++t) {
+  for (int t = 0; t < NS; ++t) {
     const int i = tl + kQrTeam * t;
     mc[t] = (inside && i < k) ? st.M[size_t(i) * kcap + team] : 0.0;   // M[i][team]
     qr[t] = (inside && i == team) ? 1.0 : 0.0;                          // Q[team][i]
@@ -709,68 +741,77 @@ __global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArg
   double thr2 = 0.0;
   int kj = 0;
   for (int j = 0; j < k; ++j) {
-    double best = -1.0, tot = 0.0;
-    int bi = SK;
-    for (int c = lane; c < k; c += 64) {
-      const double v = nrm[c];
-      if (v >= 0.0) {
-        tot += v;
-        if (v > best) { best = v; bi = c; }
+    int p = -1;
+    if (wave_live) {
+      double best = -1.0, tot = 0.0;
+      int bi = SK;
+      for (int c = lane; c < k; c += 64) {
+        const double v = nrm[c];
+        if (v >= 0.0) {
+          tot += v;
+          if (v > best) { best = v; bi = c; }
+        }
       }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      tot += __shfl_xor(tot, o);
-      const double ob = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (j == 0) {
-      const double b1 = qa_.tol > 0.0 ? 1e-3 * qa_.tol : 0.0;
-      const double b2 = 1e-3 * qa_.abs_tol;
-      // factors held in fp32 resolve nothing below their rounding level: the
-      // directions there are noise of the data, not of the method
-      const double b3 = qa_.data_eps;
-      thr2 = fmax(fmax(b1 * b1, b3 * b3) * tot, b2 * b2);
-    }
-    if (!(tot > thr2) || !(best > 0.0) || bi >= k) break;   // the same in every wave
-    const int p = bi;
-    if (team == p) {
-      double s2 = 0.0, x0 = 0.0;
+      for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o);
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (j == 0) {
+        const double b1 = qa_.tol > 0.0 ? 1e-3 * qa_.tol : 0.0;
+        const double b2 = 1e-3 * qa_.abs_tol;
+        // factors held in fp32 resolve nothing below their rounding level: the
+        // directions there are noise of the data, not of the method
+        const double b3 = qa_.data_eps;
+        thr2 = fmax(fmax(b1 * b1, b3 * b3) * tot, b2 * b2);
+      }
+      const bool stop = !(tot > thr2) || !(best > 0.0) || bi >= k;   // the same in every wave
+      if (wave == 0 && lane == 0) *s_stop = stop ? 1 : 0;
+      p = stop ? -1 : bi;
+      if (!stop && team == p) {
+        double s2 = 0.0, x0 = 0.0;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
-        const int i = tl + kQrTeam * t;
-        if (i >= j && i < k) s2 = fma(mc[t], mc[t], s2);
-        if (i == j) x0 = mc[t];
-      }
-      s2 = team8_sum(s2);
-      x0 = team8_sum(x0);
-      const double nx = sqrt(s2);
-      const double beta = x0 >= 0.0 ? -nx : nx;
-      const double inv = 1.0 / (x0 - beta);     // |x0 - beta| = |x0| + ||x|| > 0
+        for (int t = 0; t < NS; ++t) {
+          const int i = tl + kQrTeam * t;
+          if (i >= j && i < k) s2 = fma(mc[t], mc[t], s2);
+          if (i == j) x0 = mc[t];
+        }
+        s2 = team8_sum(s2);
+        x0 = team8_sum(x0);
+        const double nx = sqrt(s2);               // s2 >= best > 0
+        const double beta = x0 >= 0.0 ? -nx : nx;
+        // |x0 - beta| = |x0| + ||x|| >= |beta| > 0; the refined estimate
+        // needs a normal operand
+        const bool normal = nx > 1e-290;
+        const double inv = normal ? rcp_nr(x0 - beta) : 1.0 / (x0 - beta);
+        const double rb = normal ? rcp_nr(beta) : 1.0 / beta;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
-        const int i = tl + kQrTeam * t;
-        if (i < k) vb[i] = i < j ? 0.0 : (i == j ? 1.0 : mc[t] * inv);
-      }
-      if (tl == 0) {
-        s_tau = (beta - x0) / beta;
-        st.W[size_t(j) * kcap + p] = beta;
-        st.piv[j] = p;
+        for (int t = 0; t < NS; ++t) {
+          const int i = tl + kQrTeam * t;
+          if (i < k) vb[i] = i < j ? 0.0 : (i == j ? 1.0 : mc[t] * inv);
+        }
+        if (tl == 0) {
+          *s_tau = (beta - x0) * rb;
+          st.W[size_t(j) * kcap + p] = beta;
+          st.piv[j] = p;
+        }
       }
     }
     __syncthreads();
-    const double tau = s_tau;
+    if (*s_stop) break;                         // the same in every wave
+    const double tau = *s_tau;
     if (active && team != p) {
       double w = 0.0;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
+      for (int t = 0; t < NS; ++t) {
         const int i = tl + kQrTeam * t;
         if (i < k) w = fma(vb[i], mc[t], w);
       }
       w = team8_sum(w) * tau;
       double s2 = 0.0, rj = 0.0;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
+      for (int t = 0; t < NS; ++t) {
         const int i = tl + kQrTeam * t;
         if (i < k) {
           mc[t] = fma(-w, vb[i], mc[t]);
@@ -795,13 +836,13 @@ __global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArg
     if (inside) {
       double w = 0.0;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
+      for (int t = 0; t < NS; ++t) {
         const int c = tl + kQrTeam * t;
         if (c < k) w = fma(qr[t], vb[c], w);
       }
       w = team8_sum(w) * tau;
 #pragma unroll
-      for (int t = 0; t < kQrSlots; ++t) {
+      for (int t = 0; t < NS; ++t) {
         const int c = tl + kQrTeam * t;
         if (c < k) qr[t] = fma(-w, vb[c], qr[t]);
       }
@@ -811,12 +852,27 @@ __global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArg
   }
   if (inside) {
 #pragma unroll
-    for (int t = 0; t < kQrSlots; ++t) {
+    for (int t = 0; t < NS; ++t) {
       const int c = tl + kQrTeam * t;
       if (c < kj) st.H[size_t(team) * kcap + c] = qr[t];
     }
   }
   if (tid == 0) *st.kj = kj;
+}
+
+__global__ __launch_bounds__(kQrThreads) void qrcp_kernel(QrArgs a0, const QrArgs* ab,
+                                                          const int* done) {
+  LRC_ITEM(QrArgs, qa_, a0, ab, done)
+  __shared__ double nrm[SK];     // trailing squared norm of each column (-1: chosen or absent)
+  __shared__ double vb[SK];      // reflector of the current step
+  __shared__ double s_tau;
+  __shared__ int s_stop;
+  const int k = *qa_.st.k;
+  if (k <= 8) qrcp_body<1>(qa_, k, nrm, vb, &s_tau, &s_stop);
+  else if (k <= 16) qrcp_body<2>(qa_, k, nrm, vb, &s_tau, &s_stop);
+  else if (k <= 32) qrcp_body<4>(qa_, k, nrm, vb, &s_tau, &s_stop);
+  else if (k <= 64) qrcp_body<8>(qa_, k, nrm, vb, &s_tau, &s_stop);
+  else qrcp_body<kQrSlots>(qa_, k, nrm, vb, &s_tau, &s_stop);
 }
 
 void enqueue_qrcp(const QrArgs& a, Batched<QrArgs> b, hipStream_t s) {
