@@ -626,6 +626,40 @@ def spmm_roofline(L, ops, K, ranks, torch, reps=20):
     return out
 
 
+def orthogonality(L, ctx, prob, n, m, torch, r0):
+    """max |Q^T Q - I| of the solution's correction factors (after the r0
+    columns of the fixed initial term), and of the factors one
+    truncation returns at c2's widest concatenation (k = 124 columns: the
+    residual [F | K_i S] at rank cap 40) in each precision of its passes.
+    The products Q^T Q are formed in fp64 (torch on the device)."""
+    U, _, V = prob.solution()
+    U, V = U[:, r0:], V[:, r0:]
+    sol = dict(U=float(np.abs(U.T @ U - np.eye(U.shape[1])).max()) if U.size else 0.0,
+               V=float(np.abs(V.T @ V - np.eye(V.shape[1])).max()) if V.size else 0.0,
+               rank=int(U.shape[1]))
+    k, cap = 124, 40
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((n, k)) * rng.uniform(0.1, 10, k)
+    B = rng.standard_normal((m, k))
+    c = np.logspace(0, -9, k)
+    out = dict(solution=sol)
+    for name, tdt, bf16 in (("f64", torch.float64, False), ("f32", torch.float32, False),
+                            ("bf16_first_pass", torch.float32, True)):
+        Ad = torch.from_numpy(A).to(device="cuda", dtype=tdt)
+        Bd = torch.from_numpy(B).to(device="cuda", dtype=tdt)
+        Ud = torch.zeros((n, cap), dtype=tdt, device="cuda")
+        Vd = torch.zeros((m, cap), dtype=tdt, device="cuda")
+        _, r = L.truncate_dev(ctx, Ad, c, Bd, cap, 1e-8, Ud, Vd, bf16=bf16)
+        eye = torch.eye(r, dtype=torch.float64, device="cuda")
+        u = Ud[:, :r].double()
+        v = Vd[:, :r].double()
+        out[f"truncation_k{k}_{name}"] = dict(
+            U=float((u.T @ u - eye).abs().max()), V=float((v.T @ v - eye).abs().max()), rank=r)
+        del Ad, Bd, Ud, Vd, u, v
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -754,6 +788,7 @@ def main():
     spmm = None if a.no_spmm_roofline else spmm_roofline(
         L, ops, cfg["ops"].K, sorted({max(1, int(last["rank"])), int(cfg["rank_cap"])}), torch)
     n, m = cfg["ops"].K[0].shape[0], cfg["d"].shape[1]
+    orth = orthogonality(L, ctx, prob, n, m, torch, int(last.get("rank_x0", 0)))
     line = {
         "metric": "time to rel. residual 1e-6 (s)" if res_tol == 1e-6 else
                   f"time to rel. residual {res_tol:g} (s)",
@@ -786,6 +821,7 @@ def main():
         "eager_ms_per_step": eager_ms,
         "fp64_plain": fp64,
         "mixed_refinement": refine,
+        "orthogonality": orth,
         "speedup_vs_fp64": (fp64["seconds"] / (ms / 1e3)) if fp64 else None,
         "roofline": roof,
         "spmm_roofline": spmm,
