@@ -192,6 +192,8 @@ struct MedianBatch {
   SpmmLaunch<double> sp0;
   Batched<SpmmArgs<double>> spB;
   PrecBatch<double> pb;
+  PrecBatch<float> pb32;
+  bool f32 = false;
   Replay rep;
 
   DevBuf& newbuf() {
@@ -199,8 +201,14 @@ struct MedianBatch {
     return *bufs.back();
   }
 
-  // seed: hand each item's solution to its run as the fixed term X0 = x 1^T
-  void solve(std::vector<SolveRun*>& run, hipStream_t s_, bool eager, bool seed = true) {
+  // seed: hand each item's solution to its run as the fixed term X0 = x 1^T.
+  // f32prec: the preconditioner solves run on the fp32 factors (the
+  // residual, the iterate and the steps stay fp64, so the iteration still
+  // converges to the fp64 solution; an inexact but fixed preconditioner only
+  // moves the rate, by ~1e-7 relative), for the mixed-precision forms.
+  void solve(std::vector<SolveRun*>& run, hipStream_t s_, bool eager, bool seed = true,
+             bool f32prec = false) {
+    f32 = f32prec;
     s = s_;
     nb = int(run.size());
     rep.eager = eager;
@@ -208,6 +216,7 @@ struct MedianBatch {
     std::vector<SpmmLaunch<double>> sl;
     std::vector<SpmmArgs<double>> sa;
     std::vector<PrecItem<double>> pi;
+    std::vector<PrecItem<float>> pi32;
     std::vector<const Prec*> pre;
     hctl.assign(nb, MedCtl{});
     for (int j = 0; j < nb; ++j) {
@@ -236,9 +245,16 @@ struct MedianBatch {
       ensure(x.pcb, size_t(std::max<int64_t>(P.prec->cb_rows, 1)) * 8 * 8);
       ensure(x.pst, size_t(std::max<int64_t>(P.prec->stage_rows, 1)) * 8 * 8);
       ensure(x.part, size_t(med_partials()) * 8);
+      if (f32) {
+        ensure(x.r32, size_t(n) * 8 * 4);
+        ensure(x.z32, size_t(n) * 8 * 4);
+        LRC_HIP(hipMemsetAsync(x.r32.p, 0, x.r32.bytes, s));
+        LRC_HIP(hipMemsetAsync(x.z32.p, 0, x.z32.bytes, s));
+      }
       hi[j] = MedItem{x.f.as<double>(), x.W.as<double>(), x.coef.as<double>(), x.x.as<double>(),
                       x.dl.as<double>(), x.r.as<double>(), x.z.as<double>(),
-                      x.part.as<double>(), n, op.q};
+                      x.part.as<double>(), f32 ? x.r32.as<float>() : nullptr,
+                      f32 ? x.z32.as<float>() : nullptr, n, op.q};
       double* Wp[kMaxOps];
       for (int i = 0; i < op.q; ++i) Wp[i] = x.W.as<double>() + size_t(i) * n * 8;
       sl.push_back(make_spmm<double>(op.d64.data(), op.q, x.x.as<double>(), 8, nullptr, 1, 1, Wp,
@@ -247,6 +263,10 @@ struct MedianBatch {
       pi.push_back(PrecItem<double>{P.prec->p64.fw, P.prec->p64.bw, x.r.as<double>(), 8,
                                     x.z.as<double>(), 8, nullptr, 1, x.py.as<double>(),
                                     x.px.as<double>(), x.pcb.as<double>(), x.pst.as<double>()});
+      // fp32 work rows of ld 8 fit the fp64 buffers sized for ld 8
+      pi32.push_back(PrecItem<float>{P.prec->p32.fw, P.prec->p32.bw, x.r32.as<float>(), 8,
+                                     x.z32.as<float>(), 8, nullptr, 1, x.py.as<float>(),
+                                     x.px.as<float>(), x.pcb.as<float>(), x.pst.as<float>()});
       pre.push_back(P.prec.get());
       double fn = 0.0;
       for (double v : r.fmed) fn += v * v;
@@ -265,7 +285,10 @@ struct MedianBatch {
     const int* dn = done.as<int>();
     sp0 = merge_spmm(sl);
     spB = upload_items(sa, dn, newbuf(), s);
-    pb.setup(pre, pi, dn, 1, 8, newbuf(), s);
+    if (f32)
+      pb32.setup(pre, pi32, dn, 1, 8, newbuf(), s);
+    else
+      pb.setup(pre, pi, dn, 1, 8, newbuf(), s);
     const MedItem* it = items.as<MedItem>();
     MedCtl* ct = ctl.as<MedCtl>();
     int* dd = done.as<int>();
@@ -282,7 +305,10 @@ struct MedianBatch {
       if (all) break;
       rep.run(s, kcls(K_GRAPH, false), [&]() {
         for (int k = 0; k < kIterPerReplay; ++k) {
-          pb.enqueue(s);
+          if (f32)
+            pb32.enqueue(s);
+          else
+            pb.enqueue(s);
           launch_med_update(it, ct, dd, nb, nmax, s);
           enqueue_spmm(sp0, spB, s);
           launch_med_resid(it, dd, nb, s);
@@ -795,7 +821,7 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       if (r->jmed >= 0) med.push_back(r);
     if (!med.empty()) {
       MedianBatch mb;
-      mb.solve(med, s, eager);
+      mb.solve(med, s, eager, true, o.precision != LRC_FP64);
       LRC_HIP(hipStreamSynchronize(s));
       cx.sync();
     }

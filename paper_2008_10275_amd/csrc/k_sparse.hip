@@ -717,7 +717,8 @@ __global__ __launch_bounds__(256) void med_update_kernel(const MedItem* __restri
   const double al = ctl[j].alpha, be = ctl[j].beta;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const double d = al * a.dl[i * 8] + be * a.z[i * 8];
+    const double zi = a.z32 ? double(a.z32[i * 8]) : a.z[i * 8];
+    const double d = al * a.dl[i * 8] + be * zi;
     a.dl[i * 8] = d;
     a.x[i * 8] += d;
   }
@@ -736,6 +737,7 @@ __global__ __launch_bounds__(256) void med_resid_kernel(const MedItem* __restric
     double v = a.f[i];
     for (int t = 0; t < a.q; ++t) v -= a.coef[t] * a.W[(int64_t(t) * a.n + i) * 8];
     a.r[i * 8] = v;
+    if (a.r32) a.r32[i * 8] = float(v);
     acc += v * v;
   }
   sh[threadIdx.x] = acc;

@@ -398,6 +398,8 @@ struct MedItem {
   double* r;            // residual f - sum_t coef_t K_t x
   const double* z;      // preconditioned residual
   double* part;         // med_partials() partial sums of r^2
+  float* r32;           // non-null: fp32 copy of r for an fp32 preconditioner solve,
+  const float* z32;     // whose result z32 replaces z (both n x 8, column 0)
   int64_t n;
   int q;
 };

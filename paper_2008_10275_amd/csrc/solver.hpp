@@ -219,7 +219,7 @@ inline void ensure(DevBuf& b, size_t bytes) {
 }
 // Median-column solve workspace (column 0 of n x 8 blocks).
 struct MedWork {
-  DevBuf f, coef, x, dl, r, z, W, py, px, pcb, pst, part;
+  DevBuf f, coef, x, dl, r, z, W, py, px, pcb, pst, part, r32, z32;
 };
 
 // SpMM autotuning (tune.cpp): time every candidate launch shape of the fused
