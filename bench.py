@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5r"],
+                    help="c5r: the 3D workload at 48^3 and rank cap 40")
     ap.add_argument("--small", action="store_true", help="reduced grid (tests)")
     ap.add_argument("--precision", default="dir", choices=["mixed", "dir", "fp64", "bf16gram"],
                     help="mixed: fp32 ChebyshevT in fp64 refinement; dir: fp64 iterate and "
@@ -324,6 +325,12 @@ def solve_opts(L, cfg, precision, eager=0):
 
 
 def workload_name(cfg, n, m):
+    if cfg["ops"].dim == 3:
+        N = cfg["ops"].N
+        return (f"3-term 3D stencil equation (7-point upwind convection-diffusion + 27-point "
+                f"solid-cube Laplacian and grad-div), {N}^3 grid, n={n}, m={m} parameters, rank "
+                f"cap {cfg['rank_cap']} (reduced from 102^3 and cap 60: the truncation holds "
+                f"128 columns), relres {cfg['res_tol']:g}")
     N = int(round(np.sqrt(n)))
     return (f"3-term 2D stencil equation (upwind convection-diffusion + solid-box Laplacian "
             f"and grad-div), {N}x{N} grid, n={n}, m={m} parameters, rank cap "
@@ -780,8 +787,25 @@ def main():
                                                    time_share=dom_all[0] / total)
 
     cpu = None
-    if not a.no_cpu:
+    if not a.no_cpu and cfg["ops"].dim == 2:
+        # (3D: SuperLU's fill on the 27-point pattern puts one column solve
+        # beyond the host budget; the 2D line carries the host baseline)
         cpu = cpu_baseline(cfg)
+
+    # the 3D workload: every precision form of the same solve
+    forms = None
+    if cfg["ops"].dim == 3 and not a.no_fp64_compare:
+        forms = {}
+        for pname in ("fp64", "dir", "mixed", "bf16gram"):
+            of = solve_opts(L, cfg, pname)
+            one_solve(prob, of, res_tol)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            fi = [one_solve(prob, of, res_tol) for _ in range(a.steps)]
+            torch.cuda.synchronize()
+            forms[pname] = dict(ms=(time.perf_counter() - t4) / a.steps * 1e3,
+                                iters=fi[-1]["iters"], refinements=fi[-1]["refinements"],
+                                rank=fi[-1]["rank"], relres=fi[-1]["relres"])
 
     last = infos[-1]
     # the SpMM alone at the solution's rank and at the rank cap
@@ -822,6 +846,7 @@ def main():
         "fp64_plain": fp64,
         "mixed_refinement": refine,
         "orthogonality": orth,
+        "forms": forms,
         "speedup_vs_fp64": (fp64["seconds"] / (ms / 1e3)) if fp64 else None,
         "roofline": roof,
         "spmm_roofline": spmm,

@@ -41,3 +41,46 @@ def test_seven_term_operators_semidefinite():
     for i, K in enumerate(ops.K):
         S = (K + K.T).toarray() / 2
         assert np.linalg.eigvalsh(S).min() >= -1e-12 * max(1.0, abs(S).max()), i
+
+
+def test_three_dimensional_operators():
+    """The 3D stand-ins (c5, c5r): K_0 is the 7-point upwind
+    convection-diffusion operator (non-positive off-diagonal entries,
+    non-negative row sums); K_1, K_2 live on the solid cube only, on the full
+    27-point pattern, and are symmetric positive semi-definite; the row of
+    K_1 (the Q1 Laplacian) at a node whose 26 neighbours are all solid sums to
+    zero (small grid)."""
+    from workloads.stencils import three_term_3d
+    ops = three_term_3d(7)
+    K0, K1, K2 = ops.K
+    n = ops.n
+    assert n == 343 and ops.dim == 3
+    A = K0.toarray()
+    off = A - np.diag(np.diag(A))
+    assert off.max() <= 0 and (A.sum(axis=1) >= -1e-15).all()
+    assert max(np.diff(K0.indptr)) == 7
+    solid = ops.solid
+    for K in (K1, K2):
+        D = K.toarray()
+        assert np.allclose(D, D.T, atol=1e-15)
+        assert np.linalg.eigvalsh(D).min() >= -1e-12 * abs(D).max()
+        rows = np.nonzero(np.diff(K.indptr))[0]
+        assert solid[rows].all() and max(np.diff(K.indptr)) == 27
+    # Q1 Laplacian rows of nodes whose 26 neighbours are all solid sum to 0
+    L1 = K1.toarray()
+    N = 7
+    idx = np.arange(n).reshape(N, N, N)
+    inner = [i for i in range(n) if solid[i] and all(
+        solid[idx[tuple(np.clip(np.array(np.unravel_index(i, (N,) * 3)) + o, 0, N - 1))]]
+        for o in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).reshape(3, -1).T)]
+    assert inner
+    for i in inner:
+        assert abs(L1[i].sum()) <= 1e-14 * abs(L1[i]).max()
+
+
+def test_reduced_3d_workload_fits_truncation():
+    """c5r keeps c5's operators and parameters at a grid and rank cap whose
+    residual concatenation fits 128 columns: 1 + 3 * 40 <= 128."""
+    c = config("c5r", small=True)
+    assert c["ops"].dim == 3 and c["rank_cap"] * len(c["ops"].K) + 1 <= 128
+    assert c["d"].shape == (3, 40)

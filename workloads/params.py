@@ -106,6 +106,16 @@ def config(name: str, small: bool = False) -> dict:
         mu, lam = random_params(100 if small else 500, 7)
         return dict(name=name, ops=ops, d=param_table(mu, lam), f=rhs_vector(ops.n, 0),
                     rank_cap=60, trunc_tol=1e-8, res_tol=1e-6)
+    if name == "c5r":
+        # the 3D workload of "c5" on a 48^3 grid (n = 110,592) with rank cap
+        # 40, the widest cap whose residual [B | K_0 S | K_1 S | K_2 S] fits
+        # the truncation's 128 columns at q = 3; same operators, parameter
+        # ranges, seeds and tolerances
+        N = 16 if small else 48
+        ops = three_term_3d(N)
+        mu, lam = random_params(40 if small else 500, 7)
+        return dict(name=name, ops=ops, d=param_table(mu, lam), f=rhs_vector(ops.n, 0),
+                    rank_cap=40, trunc_tol=1e-8, res_tol=1e-6)
     if name == "q7":
         # one subset of a four-parameter discretisation (mu, nu, lambda, rho;
         # Sec. 4.4) on a little-endian tensor grid, mu fastest, then nu,
