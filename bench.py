@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no event timing in the timed region")
     ap.add_argument("--eager", action="store_true",
                     help="timed steps launch every kernel directly (no graph replay)")
+    ap.add_argument("--no-orthogonality", action="store_true",
+                    help="skip the max |Q^T Q - I| report (profiled runs)")
     ap.add_argument("--no-spmm-roofline", action="store_true",
                     help="skip the SpMM-alone measurement (profiler runs of the solve)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -812,7 +814,8 @@ def main():
     spmm = None if a.no_spmm_roofline else spmm_roofline(
         L, ops, cfg["ops"].K, sorted({max(1, int(last["rank"])), int(cfg["rank_cap"])}), torch)
     n, m = cfg["ops"].K[0].shape[0], cfg["d"].shape[1]
-    orth = orthogonality(L, ctx, prob, n, m, torch, int(last.get("rank_x0", 0)))
+    orth = None if a.no_orthogonality else orthogonality(L, ctx, prob, n, m, torch,
+                                                         int(last.get("rank_x0", 0)))
     line = {
         "metric": "time to rel. residual 1e-6 (s)" if res_tol == 1e-6 else
                   f"time to rel. residual {res_tol:g} (s)",
