@@ -429,10 +429,47 @@ lrc_status lrc_ops_create(lrc_ctx ctx, int64_t n, int q, const int64_t* const* r
       LRC_HIP(hipStreamSynchronize(s));   // nz is a temporary
       const int* rl = list ? O.rowlist.back().as<int>() : nullptr;
       const int64_t nr = list ? int64_t(nz.size()) : n;
+      // padded copy for the solver's SpMM when the rows are about equally long
+      // (stencils: a row then costs one round of index loads before its
+      // factor rows, without the row-pointer round)
+      const int ew = (mr >= 1 && mr <= 27 && double(mr) * double(nr) <= 1.5 * double(nnz) + 64.0 &&
+                      double(mr) * double(nr) < double(int64_t(1) << 31))
+                         ? mr
+                         : 0;
+      std::vector<int64_t> mp;
+      if (ew) {
+        mp.assign(size_t(ew) * nr, -1);
+        std::vector<int> ec(size_t(ew) * nr, 0);
+        for (int64_t x = 0; x < nr; ++x) {
+          const int64_t r = list ? nz[size_t(x)] : x;
+          const int64_t b = rp[r], e = rp[r + 1];
+          for (int u = 0; u < ew; ++u) {
+            const size_t slot = size_t(u) * nr + x;
+            if (b + u < e) {
+              mp[slot] = b + u;
+              ec[slot] = O.host[i].col[size_t(b + u)];
+            } else {
+              ec[slot] = e > b ? O.host[i].col[size_t(b)] : int(r);
+            }
+          }
+        }
+        O.ecol.push_back(upload(ec, s));
+        LRC_HIP(hipStreamSynchronize(s));   // ec is a temporary
+        O.eval64.push_back(DevBuf(mp.size() * 8));
+        O.eval32.push_back(DevBuf(mp.size() * 4));
+      } else {
+        O.ecol.push_back(DevBuf());
+        O.eval64.push_back(DevBuf());
+        O.eval32.push_back(DevBuf());
+      }
+      O.emap.push_back(std::move(mp));
+      O.upload_values(i);
       O.d64.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val64[i].as<double>(), n, nnz,
-                       mr, rl, nr});
+                       mr, rl, nr, ew ? O.ecol[i].as<int>() : nullptr,
+                       ew ? O.eval64[i].as<double>() : nullptr, ew});
       O.d32.push_back({O.rowptr[i].as<int>(), O.col[i].as<int>(), O.val32[i].as<float>(), n, nnz,
-                       mr, rl, nr});
+                       mr, rl, nr, ew ? O.ecol[i].as<int>() : nullptr,
+                       ew ? O.eval32[i].as<float>() : nullptr, ew});
     }
     *out = o.release();
     return LRC_OK;
@@ -605,6 +642,8 @@ void lrc_prob_destroy(lrc_prob prob) { delete prob; }
 static void upload_ilu(Prec& pr, hipStream_t s) {
   auto t0 = clk::now();
   const Ilu0& I = pr.ilu;
+  LRC_CHECK(I.rowptr.back() < (int64_t(1) << 31) && I.n < (int64_t(1) << 31), ST_EINVAL,
+            "ILU(0): the level kernels index rows and entries with 32-bit integers");
   std::vector<int> rp(I.rowptr.begin(), I.rowptr.end());
   pr.irp = upload(rp, s);
   pr.icol = upload(I.col, s);

@@ -35,39 +35,17 @@ template <> struct V16<double> {
 // lpr follows the device rank (lanes past it would idle).  The nonzeros of a
 // row are taken in batches, their column indices loaded before the U rows
 // they select (padding slots reuse the row's first column with a zero value),
-// so that a row costs two dependent load rounds per batch.
-// One row of one operator: acc = K(row, :) U, stored to W.
-template <class T, int NV, int NZB>
-__device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
-                                         const T* __restrict__ U, int ldu, T* __restrict__ W,
-                                         int ldw, int r, int nvec, int lpr, int chunk, bool wpad) {
+// so that a row costs two dependent load rounds per batch after the row
+// pointers.  Operators whose rows are about equally long (stencils, up to 27
+// entries) also carry a padded column-major copy: a row then needs no row
+// pointers, and a wave's index loads for consecutive rows are contiguous.
+// The row of W: a lane's NV vectors of the accumulated row.
+template <class T, int NV>
+__device__ __forceinline__ void spmm_store(const typename V16<T>::t* acc, int64_t row,
+                                           T* __restrict__ W, int ldw, int r, int nvec, int lpr,
+                                           int chunk, bool wpad) {
   typedef typename V16<T>::t V;
   constexpr int VW = V16<T>::n;
-  V acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = V16<T>::zero();
-  const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
-  for (int e = e0; e < e1; e += NZB) {
-    int cj[NZB];
-    T vj[NZB];
-#pragma unroll
-    for (int u = 0; u < NZB; ++u) {
-      const bool ok = e + u < e1;
-      const int x = ok ? e + u : e0;
-      cj[u] = K.col[x];
-      const T val = K.val[x];
-      vj[u] = ok ? val : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < NZB; ++u) {
-      const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int j = chunk + v * lpr;
-        if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
-      }
-    }
-  }
   T* __restrict__ wr = W + row * ldw;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -94,6 +72,72 @@ __device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
       }
     }
   }
+}
+
+// One row of one operator: acc = K(row, :) U, stored to W.
+template <class T, int NV, int NZB>
+__device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
+                                         const T* __restrict__ U, int ldu, T* __restrict__ W,
+                                         int ldw, int r, int nvec, int lpr, int chunk, bool wpad) {
+  typedef typename V16<T>::t V;
+  V acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = V16<T>::zero();
+  const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
+  for (int e = e0; e < e1; e += NZB) {
+    int cj[NZB];
+    T vj[NZB];
+#pragma unroll
+    for (int u = 0; u < NZB; ++u) {
+      const bool ok = e + u < e1;
+      const int x = ok ? e + u : e0;
+      cj[u] = K.col[x];
+      const T val = K.val[x];
+      vj[u] = ok ? val : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NZB; ++u) {
+      const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int j = chunk + v * lpr;
+        if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
+      }
+    }
+  }
+  spmm_store<T, NV>(acc, row, W, ldw, r, nvec, lpr, chunk, wpad);
+}
+
+// The same product from the padded copy: visited row x's EW entries are one
+// round of coalesced index and value loads (consecutive rows adjacent), then
+// the factor rows they select; padding slots add 0 times a valid row, so the
+// sum (taken in the row's entry order) has the CSR path's bits.
+template <class T, int NV, int EW>
+__device__ __forceinline__ void spmm_row_ell(const DevCsr<T>& K, int64_t x, int64_t row,
+                                             const T* __restrict__ U, int ldu, T* __restrict__ W,
+                                             int ldw, int r, int nvec, int lpr, int chunk,
+                                             bool wpad) {
+  typedef typename V16<T>::t V;
+  V acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = V16<T>::zero();
+  int cj[EW];
+  T vj[EW];
+#pragma unroll
+  for (int u = 0; u < EW; ++u) {
+    cj[u] = K.ecol[int64_t(u) * K.nrows + x];
+    vj[u] = K.eval[int64_t(u) * K.nrows + x];
+  }
+#pragma unroll
+  for (int u = 0; u < EW; ++u) {
+    const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int j = chunk + v * lpr;
+      if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
+    }
+  }
+  spmm_store<T, NV>(acc, row, W, ldw, r, nvec, lpr, chunk, wpad);
 }
 
 // Workgroups per operator and row block: consecutive workgroups of one XCD
@@ -136,7 +180,21 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
   // lookups are one contiguous span
   const int* __restrict__ rl = args.skip_empty ? K.rows : nullptr;
   const int64_t nvis = rl ? K.nrows : K.n;
-  if (maxrow <= 5) {
+  // the padded copy covers exactly the visited rows (all rows, or the list)
+  const int ew = __builtin_amdgcn_readfirstlane((rl || !K.rows) ? K.ew : 0);
+#define LRC_ELL(EW)                                                                               \
+  for (int64_t x = first; x < nvis; x += stride)                                                  \
+    spmm_row_ell<T, NV, EW>(K, x, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, \
+                            lpr, chunk, wpad)
+  if (ew == 5) {
+    LRC_ELL(5);
+  } else if (ew == 7) {
+    LRC_ELL(7);
+  } else if (ew == 9) {
+    LRC_ELL(9);
+  } else if (ew == 27) {
+    LRC_ELL(27);
+  } else if (maxrow <= 5) {
     for (int64_t x = first; x < nvis; x += stride)
       spmm_row<T, NV, 5>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
                          chunk, wpad);
@@ -149,6 +207,7 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
       spmm_row<T, NV, 4>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
                          chunk, wpad);
   }
+#undef LRC_ELL
 }
 
 template <class T>

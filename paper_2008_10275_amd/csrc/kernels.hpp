@@ -30,6 +30,12 @@ struct DevCsr {
   int maxrow;   // most entries in one row
   const int* rows;   // the rows that hold entries, ascending (nullptr: every row does)
   int64_t nrows;     // their number (n when rows is nullptr)
+  // the same entries in a padded column-major layout over those nrows rows
+  // (entry u of visited row x at u * nrows + x; padding: the row's first
+  // column with value 0), ew entries per row; ew = 0: none (CSR only)
+  const int* ecol;
+  const T* eval;
+  int ew;
 };
 
 constexpr int kMaxOps = 8;

@@ -33,6 +33,18 @@ void Ops::upload_values(int i) {
   hipStream_t s = ctx->stream;
   LRC_HIP(hipMemcpyAsync(val64[i].p, h.val.data(), h.val.size() * 8, hipMemcpyHostToDevice, s));
   LRC_HIP(hipMemcpyAsync(val32[i].p, v32.data(), v32.size() * 4, hipMemcpyHostToDevice, s));
+  if (size_t(i) < emap.size() && !emap[i].empty()) {
+    const auto& mp = emap[i];
+    std::vector<double> e64(mp.size());
+    std::vector<float> e32(mp.size());
+    for (size_t e = 0; e < mp.size(); ++e) {
+      e64[e] = mp[e] >= 0 ? h.val[size_t(mp[e])] : 0.0;
+      e32[e] = float(e64[e]);
+    }
+    LRC_HIP(hipMemcpyAsync(eval64[i].p, e64.data(), e64.size() * 8, hipMemcpyHostToDevice, s));
+    LRC_HIP(hipMemcpyAsync(eval32[i].p, e32.data(), e32.size() * 4, hipMemcpyHostToDevice, s));
+    LRC_HIP(hipStreamSynchronize(s));   // e64, e32 are temporaries
+  }
   LRC_HIP(hipStreamSynchronize(s));   // v32 is a temporary
 }
 

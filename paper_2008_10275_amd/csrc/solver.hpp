@@ -41,6 +41,9 @@ struct Ops {
   std::vector<CsrHost> host;
   std::vector<DevBuf> rowptr, col, val64, val32;
   std::vector<DevBuf> rowlist;   // per operator: its non-empty rows (empty when all are)
+  // padded (ELL) copy of stencil-like operators: slot -> CSR entry (-1: padding)
+  std::vector<std::vector<int64_t>> emap;
+  std::vector<DevBuf> ecol, eval64, eval32;
   std::vector<DevCsr<double>> d64;
   std::vector<DevCsr<float>> d32;
   void upload_values(int i);
