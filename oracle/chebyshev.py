@@ -160,3 +160,69 @@ def chebyshev_t(K, d, B, prec, c, dc, rank_cap, trunc_tol, res_tol, ref_norm,
                                         (Z, np.diag((2.0 * rho_new / c) * sz), Vz)),
                              rank_cap, trunc_tol)
             rho = rho_new
+
+
+def chebyshev_t3(K, d, B, prec, c, dc, rank_cap, trunc_tol, res_tol, ref_norm,
+                 restart=6, max_iter=200, S0=None, res_rank_cap=None):
+    """ChebyshevT in the three-term form of the Chebyshev iteration.
+
+    The same polynomial iteration as `chebyshev_t` (same interval [dc - c,
+    dc + c], same restarts, stops and residual truncation) written without
+    the direction Dl: in exact arithmetic Dl = S_{k+1} - S_k, so the direction
+    update of `chebyshev_t` becomes the classical three-term recurrence of the
+    Chebyshev polynomials applied to the iterates,
+
+        S_1     <- T(S_0 + P^-1 R_0 / dc),                  rho <- c / dc
+        S_{k+1} <- T((1 + rho' rho) S_k - rho' rho S_{k-1} + (2 rho' / c) P^-1 R_k),
+        rho' = 1 / (2 sigma - rho),  rho <- rho',
+
+    which truncates once per update instead of twice (the direction and the
+    iterate).  With truncation the two forms differ only by where the
+    truncation errors enter.  Arguments and result as for `chebyshev_t`.
+    """
+    n, m = B[0].shape[0], B[2].shape[0]
+    rcap_res = rank_cap if res_rank_cap is None else res_rank_cap
+    info = ChebInfo()
+    S = (np.zeros((n, 0)), np.zeros(0), np.zeros((m, 0))) if S0 is None else S0
+    sigma = dc / c if c > 0 else np.inf
+
+    def resid(S):
+        A, C, Bm = residual_factored(K, d, B, S)
+        return lr.truncate(A, C, Bm, rcap_res, trunc_tol)
+
+    def precond(R):
+        info.prec_applies += 1
+        U, s, V = R
+        return prec.solve(U), s, V
+
+    R = resid(S)
+    info.history.append(float(np.linalg.norm(R[1])))
+    while True:
+        if info.history[-1] <= res_tol * ref_norm or R[1].size == 0:
+            info.converged = True
+            return S, info
+        if info.iters >= max_iter:
+            return S, info
+        cycle = restart if restart > 0 else max_iter
+        rho = c / dc
+        S_prev = None
+        for k in range(cycle):
+            Z, sz, Vz = precond(R)
+            if S_prev is None:
+                new = lr.lr_sum(lr.usv(*S), (Z, np.diag(sz / dc), Vz))
+            else:
+                rho_new = 1.0 / (2.0 * sigma - rho)
+                a = rho_new * rho
+                new = lr.lr_sum(lr.lr_scale(lr.usv(*S), 1.0 + a),
+                                lr.lr_scale(lr.usv(*S_prev), -a),
+                                (Z, np.diag((2.0 * rho_new / c) * sz), Vz))
+                rho = rho_new
+            S_prev = S
+            S = lr.truncate(*new, rank_cap, trunc_tol)
+            info.iters += 1
+            info.ranks.append(S[1].size)
+            R = resid(S)
+            nr = float(np.linalg.norm(R[1]))
+            info.history.append(nr)
+            if nr <= res_tol * ref_norm or R[1].size == 0 or info.iters >= max_iter:
+                break

@@ -165,10 +165,15 @@ def _diag_problem(n=12, m=7, seed=2):
     return K, d, rng
 
 
+FORMS = {"direction": ch.chebyshev_t, "three_term": ch.chebyshev_t3}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("k", [1, 2, 5, 9])
-def test_chebyshev_residual_is_scaled_chebyshev_polynomial(k):
+def test_chebyshev_residual_is_scaled_chebyshev_polynomial(k, form):
     """Without truncation the residual of every eigencomponent is
-    T_k((d - lam)/c) / T_k(d/c) times the initial one (Chebyshev acceleration)."""
+    T_k((d - lam)/c) / T_k(d/c) times the initial one (Chebyshev acceleration),
+    in the direction form and in the three-term form alike."""
     K, d, rng = _diag_problem()
     n, m = K[0].shape[0], d.shape[1]
     dbar = d.mean(axis=1)
@@ -177,8 +182,8 @@ def test_chebyshev_residual_is_scaled_chebyshev_polynomial(k):
                     for p in range(n)])
     c, dc = 0.5 * (lam.max() - lam.min()) * 1.05, 0.5 * (lam.max() + lam.min())
     B = (rng.standard_normal((n, 2)), np.eye(2), rng.standard_normal((m, 2)))
-    S, info = ch.chebyshev_t(K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap=1000,
-                             trunc_tol=0.0, res_tol=0.0, ref_norm=1.0, restart=0, max_iter=k)
+    S, info = FORMS[form](K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap=1000,
+                          trunc_tol=0.0, res_tol=0.0, ref_norm=1.0, restart=0, max_iter=k)
     assert info.iters == k
     R0 = lr.lr_dense(*B)
     Rk = R0 - lr.apply_L_dense(K, d, lr.lr_dense(*lr.usv(*S)))
@@ -188,14 +193,15 @@ def test_chebyshev_residual_is_scaled_chebyshev_polynomial(k):
     assert np.allclose(Rk, poly * R0, rtol=1e-9, atol=1e-12 * np.abs(R0).max())
 
 
-def test_chebyshev_exact_preconditioner_converges_in_one_step():
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_chebyshev_exact_preconditioner_converges_in_one_step(form):
     K, d, rng = _diag_problem()
     m = d.shape[1]
     d = np.repeat(d[:, :1], m, axis=1)                 # every column equals the mean
     P = ch.mean_preconditioner(K, d.mean(axis=1))
     B = (rng.standard_normal((K[0].shape[0], 2)), np.eye(2), rng.standard_normal((m, 2)))
-    S, info = ch.chebyshev_t(K, d, B, ch.DirectPreconditioner(P), 0.5, 1.0, 100, 1e-14,
-                             1e-12, 1.0, restart=0, max_iter=5)
+    S, info = FORMS[form](K, d, B, ch.DirectPreconditioner(P), 0.5, 1.0, 100, 1e-14,
+                          1e-12, 1.0, restart=0, max_iter=5)
     assert info.iters == 1 and info.converged
 
 
@@ -278,8 +284,9 @@ def test_chebyshev_interval_skewed_grid_encloses_dense_spectrum():
     assert hi >= dc + c - 0.1 * 2 * c and lo <= dc - c + 0.1 * 2 * c
 
 
+@pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("iters", [4, 5])
-def test_chebyshev_restart_is_product_of_polynomials(iters):
+def test_chebyshev_restart_is_product_of_polynomials(iters, form):
     """Restarting every 2 updates without truncation: the recurrence starts
     again from the current iterate, so after cycles of lengths l_1, l_2, ...
     each eigencomponent's residual is the product of the scaled Chebyshev
@@ -292,9 +299,9 @@ def test_chebyshev_restart_is_product_of_polynomials(iters):
                     for p in range(n)])
     c, dc = 0.5 * (lam.max() - lam.min()) * 1.1, 0.5 * (lam.max() + lam.min())
     B = (rng.standard_normal((n, 2)), np.eye(2), rng.standard_normal((m, 2)))
-    S, info = ch.chebyshev_t(K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap=1000,
-                             trunc_tol=0.0, res_tol=0.0, ref_norm=1.0, restart=2,
-                             max_iter=iters)
+    S, info = FORMS[form](K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap=1000,
+                          trunc_tol=0.0, res_tol=0.0, ref_norm=1.0, restart=2,
+                          max_iter=iters)
     assert info.iters == iters
     R0 = lr.lr_dense(*B)
     Rk = R0 - lr.apply_L_dense(K, d, lr.lr_dense(*lr.usv(*S)))
@@ -308,6 +315,33 @@ def test_chebyshev_restart_is_product_of_polynomials(iters):
     assert np.allclose(Rk, poly * R0, rtol=1e-9, atol=1e-12 * np.abs(R0).max())
     # a single unrestarted cycle of the same length gives a different residual
     assert not np.allclose(poly, p(iters), rtol=1e-3)
+
+
+def test_three_term_form_truncates_once_per_update_and_tracks_direction_form():
+    """With truncation the forms differ only by where the truncation errors
+    enter: on c1 (tolerance 1e-8) both reach the target in the same number of
+    updates with residual histories within a few per cent and nearly the
+    same iterate, each applying the preconditioner once per update."""
+    cfg = config("c1")
+    K, d, f = cfg["ops"].K, cfg["d"], cfg["f"]
+    m = d.shape[1]
+    jmed = driver.upper_median_offset(m)
+    xt = sla.lu_solve(sla.lu_factor(lr.column_operator(K, d, jmed).toarray()), f)
+    B = driver.median_rhs(K, d, f, xt)
+    dbar = ch.mean_parameters(d)
+    c, dc = ch.chebyshev_interval(d, dbar)
+    P = ch.DirectPreconditioner(ch.mean_preconditioner(K, dbar))
+    ref = np.linalg.norm(f) * np.sqrt(m)
+    args = (K, d, B, P, c, dc, cfg["rank_cap"], cfg["trunc_tol"], cfg["res_tol"], ref)
+    S2, i2 = ch.chebyshev_t(*args)
+    S3, i3 = ch.chebyshev_t3(*args)
+    assert i2.converged and i3.converged
+    assert i3.iters == i2.iters
+    h2, h3 = np.array(i2.history), np.array(i3.history)
+    assert np.all(np.abs(h3 - h2) <= 0.05 * h2)
+    assert i3.prec_applies == i3.iters == i2.prec_applies
+    X2, X3 = lr.lr_dense(*lr.usv(*S2)), lr.lr_dense(*lr.usv(*S3))
+    assert np.linalg.norm(X3 - X2) <= 1e-6 * np.linalg.norm(X2)
 
 
 # ------------------------------------------------------------------ Newton driver
