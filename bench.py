@@ -5,10 +5,15 @@ step on a parameter subset, Sec. 3.4 and Algorithm 1; ChebyshevT, Sec. 4.1).
 
 Workload (default): the 3-term stencil problem on a 513 x 513 grid
 (n = 263,169), m = 1,000 random parameters, rank cap 40, truncation tolerance
-1e-8, mixed precision (fp32 inner ChebyshevT, fp64 residual and refinement).
-A step is one complete solve: median-parameter initial guess, ChebyshevT with
-refinement, and the fp64 entry-wise residual that confirms relres <= 1e-6.
-The preconditioner factorisation is set-up and is timed separately.
+1e-8, mixed precision (--precision dir: fp64 iterate, residual SpMM and
+truncations, fp32 preconditioner solves) and the three-term form of the
+Chebyshev recurrence (--recurrence; one truncation per update instead of the
+direction form's two).  A step is one complete solve: median-parameter
+initial guess, ChebyshevT, and the fp64 entry-wise residual that confirms
+relres <= 1e-6.  The line also times plain fp64 in the direction form, fp64
+in the timed solve's recurrence, the fp32-inner refinement form and the other
+recurrence.  The preconditioner factorisation is set-up and is timed
+separately.
 
 --workload c3 times the batched form instead: 16 parameter subsets of uneven
 size (20..300, 2,000 parameters in all), each with its own perturbed
@@ -51,6 +56,8 @@ def parse():
                     help="mixed: fp32 ChebyshevT in fp64 refinement; dir: fp64 iterate and "
                          "residual with fp32 preconditioner solves and directions; bf16gram: "
                          "mixed with bf16 first-pass Gram products")
+    ap.add_argument("--recurrence", default="three_term", choices=["direction", "three_term"],
+                    help="form of the Chebyshev recurrence of the timed solve")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="no event timing in the timed region")
@@ -107,7 +114,7 @@ def main_batched(a, L, torch):
     cfg, ctx, subs, setup_s = batched_setup(L, a.small)
     probs = [p for _, p in subs]
     res_tol = cfg["res_tol"]
-    opts = solve_opts(L, cfg, a.precision)
+    opts = solve_opts(L, cfg, a.precision, recurrence=a.recurrence)
     for _ in range(max(1, a.warmup)):
         batched_solve(L, probs, opts, res_tol)
     torch.cuda.synchronize()
@@ -317,13 +324,15 @@ def main_surrogate(a, L, torch):
     print(json.dumps(line), flush=True)
 
 
-def solve_opts(L, cfg, precision, eager=0):
+def solve_opts(L, cfg, precision, eager=0, recurrence="direction"):
     return L.default_opts(rank_cap=cfg["rank_cap"], trunc_tol=cfg["trunc_tol"],
                           res_tol=cfg["res_tol"], init=L.LRC_INIT_MEDIAN, verify_fp64=1,
                           precision={"mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR,
                                      "fp64": L.LRC_FP64,
                                      "bf16gram": L.LRC_MIXED_BF16GRAM}[precision],
-                          eager=eager)
+                          eager=eager,
+                          recurrence={"direction": L.LRC_CHEB_DIRECTION,
+                                      "three_term": L.LRC_CHEB_THREE_TERM}[recurrence])
 
 
 def workload_name(cfg, n, m):
@@ -700,7 +709,7 @@ def main():
         return
 
     cfg, ctx, ops, prob, setup_s = problem_setup(L, a.workload, a.small)
-    opts = solve_opts(L, cfg, a.precision, eager=int(a.eager))
+    opts = solve_opts(L, cfg, a.precision, eager=int(a.eager), recurrence=a.recurrence)
     res_tol = cfg["res_tol"]
 
     # warm-up (also captures the graphs and tunes the SpMM shapes)
@@ -721,7 +730,7 @@ def main():
     # stream; the first repeat also records the algorithmic work per launch
     prof_work, prof_time, eager_ms = {}, {}, None
     if not a.no_profile:
-        oe = solve_opts(L, cfg, a.precision, eager=1)
+        oe = solve_opts(L, cfg, a.precision, eager=1, recurrence=a.recurrence)
         L.profile_enable(2)
         one_solve(prob, oe, res_tol)
         torch.cuda.synchronize()
@@ -745,12 +754,24 @@ def main():
         f_infos = [one_solve(prob, o64, res_tol) for _ in range(a.steps)]
         torch.cuda.synchronize()
         fp64 = dict(seconds=(time.perf_counter() - t1) / a.steps, iters=f_infos[-1]["iters"],
-                    relres=f_infos[-1]["relres"])
+                    relres=f_infos[-1]["relres"], recurrence="direction")
+        if a.recurrence != "direction":
+            # fp64 in the timed solve's recurrence: what the precision alone buys
+            o3 = solve_opts(L, cfg, "fp64", recurrence=a.recurrence)
+            one_solve(prob, o3, res_tol)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            g_infos = [one_solve(prob, o3, res_tol) for _ in range(a.steps)]
+            torch.cuda.synchronize()
+            fp64["same_recurrence"] = dict(seconds=(time.perf_counter() - t2) / a.steps,
+                                           iters=g_infos[-1]["iters"],
+                                           relres=g_infos[-1]["relres"],
+                                           recurrence=a.recurrence)
 
     # the other mixed form (fp32 ChebyshevT inside fp64 refinement), for reference
     refine = None
     if a.precision == "dir" and not a.no_fp64_compare:
-        orf = solve_opts(L, cfg, "mixed")
+        orf = solve_opts(L, cfg, "mixed", recurrence=a.recurrence)
         one_solve(prob, orf, res_tol)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
@@ -758,6 +779,19 @@ def main():
         torch.cuda.synchronize()
         refine = dict(seconds=(time.perf_counter() - t3) / a.steps, iters=r_infos[-1]["iters"],
                       refinements=r_infos[-1]["refinements"], relres=r_infos[-1]["relres"])
+
+    # the same solve in the other form of the recurrence, for reference
+    other = None
+    if cfg["ops"].dim == 2 and a.precision != "fp64" and not a.no_fp64_compare:
+        oname = "direction" if a.recurrence == "three_term" else "three_term"
+        oo = solve_opts(L, cfg, a.precision, recurrence=oname)
+        one_solve(prob, oo, res_tol)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        o_infos = [one_solve(prob, oo, res_tol) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        other = dict(recurrence=oname, seconds=(time.perf_counter() - t5) / a.steps,
+                     iters=o_infos[-1]["iters"], relres=o_infos[-1]["relres"])
 
     ktab = kernel_table(prof_work, prof_time, a.steps) if prof_time else {}
     roof = None
@@ -799,7 +833,8 @@ def main():
     if cfg["ops"].dim == 3 and not a.no_fp64_compare:
         forms = {}
         for pname in ("fp64", "dir", "mixed", "bf16gram"):
-            of = solve_opts(L, cfg, pname)
+            of = solve_opts(L, cfg, pname,
+                            recurrence="direction" if pname == "fp64" else a.recurrence)
             one_solve(prob, of, res_tol)
             torch.cuda.synchronize()
             t4 = time.perf_counter()
@@ -834,6 +869,7 @@ def main():
                    "q": len(cfg["ops"].K),
                    "rank_cap": cfg["rank_cap"], "trunc_tol": cfg["trunc_tol"],
                    "res_tol": res_tol,
+                   "recurrence": a.recurrence,
                    "precision": {"mixed": "fp32 inner ChebyshevT, fp64 residual + refinement",
                                  "dir": ("fp64 iterate and residual, fp32 preconditioner "
                                          "solves and direction updates"),
@@ -848,6 +884,7 @@ def main():
         "eager_ms_per_step": eager_ms,
         "fp64_plain": fp64,
         "mixed_refinement": refine,
+        "other_recurrence": other,
         "orthogonality": orth,
         "forms": forms,
         "speedup_vs_fp64": (fp64["seconds"] / (ms / 1e3)) if fp64 else None,

@@ -66,6 +66,16 @@ enum { LRC_FP64 = 0, LRC_MIXED_FP32 = 1, LRC_MIXED_FP32_DIR = 2, LRC_MIXED_BF16G
  * inner product (fp64 only; needs no spectrum interval; restart = the
  * Krylov dimension of a cycle; iters counts Arnoldi steps). */
 enum { LRC_SOLVER_CHEBYSHEV = 0, LRC_SOLVER_GMREST = 1 };
+/* form of the Chebyshev recurrence (both are the same polynomial iteration;
+ * they differ only in where the truncation errors enter).
+ * LRC_CHEB_DIRECTION: a direction D is kept, D <- T(a D + b P^-1 R), and the
+ * iterate is updated by S <- T(S + D): two truncations per update.
+ * LRC_CHEB_THREE_TERM: the three-term recurrence of the Chebyshev polynomials
+ * on the iterates, S_{k+1} <- T((1 + a) S_k - a S_{k-1} + b P^-1 R_k), one
+ * truncation of up to 2 rank_cap + rank(R) columns per update; every
+ * precision takes it (with LRC_MIXED_FP32_DIR the fp32 solve P^-1 R is
+ * widened to fp64 for the fp64 update).  Needs 2 rank_cap + rank_cap <= 128. */
+enum { LRC_CHEB_DIRECTION = 0, LRC_CHEB_THREE_TERM = 1 };
 /* initial guess of lrc_solve: none; the upper-median column's solution x~
  * as the fixed term X0 = x~ 1^T; given factors as the fixed term X0.  The
  * guess stays a separate exact term (X = X0 + S) so that truncation errors
@@ -111,6 +121,7 @@ typedef struct {
                           column against res_ref / sqrt(m); 0: ||F||_F and
                           ||F_j|| (the Newton driver passes ||b|| sqrt(m))    */
   int solver;          /* LRC_SOLVER_CHEBYSHEV (default) or LRC_SOLVER_GMREST   */
+  int recurrence;      /* LRC_CHEB_DIRECTION (default) or LRC_CHEB_THREE_TERM   */
 } lrc_opts;
 
 typedef struct {

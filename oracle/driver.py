@@ -69,11 +69,12 @@ def median_rhs(K, d, f, xt):
 
 
 def newton_subset(K, d, f, rank_cap, trunc_tol, res_tol, restart=6, max_iter=200,
-                  cheb=None, dbar=None):
+                  cheb=None, dbar=None, form="direction"):
     """One Newton step on a subset (Algorithm 1, loop body).
 
     Returns dict(xt, S=(U, s, V), info, c, d) with X = xt 1^T + U diag(s) V^T.
-    The stopping tolerance is relative to ||F||_F = ||f|| sqrt(m)."""
+    The stopping tolerance is relative to ||F||_F = ||f|| sqrt(m).  form:
+    "direction" (chebyshev_t) or "three_term" (chebyshev_t3)."""
     m = d.shape[1]
     jmed = upper_median_offset(m)
     Amed = lr.column_operator(K, d, jmed)
@@ -83,8 +84,9 @@ def newton_subset(K, d, f, rank_cap, trunc_tol, res_tol, restart=6, max_iter=200
     P = ch.mean_preconditioner(K, dbar)
     c, dc = ch.chebyshev_interval(d, dbar) if cheb is None else cheb
     ref = np.linalg.norm(f) * np.sqrt(m)
-    S, info = ch.chebyshev_t(K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap,
-                             trunc_tol, res_tol, ref, restart=restart, max_iter=max_iter)
+    solve = {"direction": ch.chebyshev_t, "three_term": ch.chebyshev_t3}[form]
+    S, info = solve(K, d, B, ch.DirectPreconditioner(P), c, dc, rank_cap,
+                    trunc_tol, res_tol, ref, restart=restart, max_iter=max_iter)
     return dict(xt=xt, S=S, info=info, c=c, d=dc, jmed=jmed)
 
 

@@ -350,6 +350,18 @@ struct BatchCheb {
   TruncBatch<T> residB, dstartB, supdB;
   std::vector<TruncPlan<T>> dstep0;
   std::vector<TruncBatch<T>> dstepB;
+  // three-term form: the iterate alternates between S (0) and the buffer of
+  // D (1), which the direction form needs and this form does not; the SpMM
+  // and the residual exist for either, the update per step of the cycle
+  bool three = false;
+  SpmmLaunch<T> spmm1;
+  Batched<SpmmArgs<T>> spmmB1;
+  TruncPlan<T> resid1;
+  TruncBatch<T> residB1;
+  std::vector<TruncPlan<T>> u30;
+  std::vector<TruncBatch<T>> u3B;
+  DevBuf back;       // per item: copy of D's buffer into S (odd cycles)
+  int64_t rows_max = 0;
   Replay rep;
 
   DevBuf& newbuf() {
@@ -360,13 +372,15 @@ struct BatchCheb {
   // res_abs: per item, the absolute floor of the residual's truncation
   void setup(const std::vector<Cheb<T>*>& items, const std::vector<const LR<T>*>& rhs,
              const std::vector<double>& c_, const std::vector<double>& dc_, double tol,
-             const std::vector<double>& res_abs, int cycle_, bool eager, hipStream_t s_) {
+             const std::vector<double>& res_abs, int cycle_, bool eager, hipStream_t s_,
+             bool three_ = false) {
     it = items;
     B = rhs;
     c = c_;
     dc = dc_;
     cycle = cycle_;
     s = s_;
+    three = three_;
     rep.eager = eager;
     nb = int(it.size());
     done.alloc(size_t(nb) * sizeof(int));
@@ -406,6 +420,10 @@ struct BatchCheb {
     site([&](int j) {
       return it[j]->resid_plan(*B[j], it[j]->norm.template as<double>(), tol, 0, res_abs[j]);
     }, resid0, residB);
+    if (three) {
+      setup_three(tol, res_abs, site);
+      return;
+    }
     site([&](int j) { return it[j]->dstart_plan(dc[j]); }, dstart0, dstartB);
     site([&](int j) { return it[j]->supd_plan(); }, supd0, supdB);
     // D updates of a cycle: the coefficients follow rho_0 = c/dc,
@@ -423,16 +441,101 @@ struct BatchCheb {
     }
   }
 
-  void resid(int after_update) {
-    enqueue_spmm(spmm0, spmmB, s);
-    enqueue_trunc(resid0, residB, s);
+  // The three-term sites: SpMM and residual of the iterate in D's buffer,
+  // and per step k of a cycle the update of the iterate in buffer k % 2 (and
+  // its predecessor in the other) into buffer (k + 1) % 2:
+  //   k = 0:  T(S + P^-1 R / dc)
+  //   k > 0:  T((1 + rn rho) X_k - rn rho X_{k-1} + (2 rn / c) P^-1 R),
+  //           rn = 1 / (2 dc / c - rho), rho <- rn, from rho = c / dc.
+  // A cycle of odd length ends in D's buffer and is copied back into S, so
+  // that every cycle starts from S.
+  template <class Site>
+  void setup_three(double tol, const std::vector<double>& res_abs, Site& site) {
+    const int* dn = done.template as<int>();
+    for (auto* x : it)
+      LRC_CHECK(3 * x->S.ld <= kTruncCap, ST_EINVAL,
+                "three-term recurrence: 3 * rank_cap must not exceed 128 columns");
+    {
+      std::vector<SpmmLaunch<T>> v;
+      std::vector<SpmmArgs<T>> a;
+      for (auto* x : it) {
+        v.push_back(x->spmm_plan(x->D.u(), x->D.ld, x->D.r()));
+        a.push_back(v.back().a);
+      }
+      spmm1 = merge_spmm(v);
+      spmmB1 = upload_items(a, dn, newbuf(), s);
+    }
+    site([&](int j) {
+      return it[j]->resid_plan(*B[j], it[j]->norm.template as<double>(), tol, 0, res_abs[j],
+                               &it[j]->D);
+    }, resid1, residB1);
+    std::vector<double> rho(nb);
+    for (int j = 0; j < nb; ++j) rho[j] = c[j] / dc[j];
+    u30.resize(cycle);
+    u3B.resize(cycle);
+    for (int k = 0; k < cycle; ++k) {
+      std::vector<double> a(nb, 1.0), b(nb, 0.0), g(nb);
+      for (int j = 0; j < nb; ++j) {
+        if (k == 0) {
+          g[j] = 1.0 / dc[j];
+          continue;
+        }
+        const double rn = 1.0 / (2.0 * dc[j] / c[j] - rho[j]);
+        a[j] = 1.0 + rn * rho[j];
+        b[j] = -rn * rho[j];
+        g[j] = 2.0 * rn / c[j];
+        rho[j] = rn;
+      }
+      site([&](int j) {
+        Cheb<T>& x = *it[j];
+        const LR<T>& X = (k & 1) ? x.D : x.S;
+        const LR<T>& Y = (k & 1) ? x.S : x.D;
+        return x.upd3_plan(X, a[j], k == 0 ? nullptr : &Y, b[j], g[j], Y);
+      }, u30[k], u3B[k]);
+    }
+    if (cycle & 1) {
+      std::vector<CastItem<T, T>> v;
+      for (auto* x : it) {
+        v.push_back(CastItem<T, T>{x->D.u(), x->D.v(), x->D.sv(), x->D.r(), x->S.u(), x->S.v(),
+                                   x->S.sv(), x->S.r(), x->D.ld, x->D.ld, x->S.ld, x->S.ld,
+                                   x->S.n, x->S.m, x->S.cap});
+        rows_max = std::max(rows_max, x->S.n + x->S.m);
+      }
+      upload_items(v, dn, back, s);
+    }
+  }
+
+  void resid(int after_update, int buf = 0) {
+    enqueue_spmm(buf ? spmm1 : spmm0, buf ? spmmB1 : spmmB, s);
+    enqueue_trunc(buf ? resid1 : resid0, buf ? residB1 : residB, s);
     launch_batch_check(ctl.as<BCtl>(), done.as<int>(), nb, after_update, s);
+  }
+
+  // After the run: an item that stopped at step k of a cycle (k = (iters - 1)
+  // mod cycle) of the three-term form holds its iterate in D's buffer when k
+  // is even; it is copied into S, where the callers read the solution.
+  void three_back() {
+    if (!three) return;
+    for (int j = 0; j < nb; ++j) {
+      const int t = hctl[j].iters;
+      if (t >= 1 && ((t - 1) % cycle) % 2 == 0) cast_lr<T, T>(it[j]->D, it[j]->S, s);
+    }
   }
 
   // one restart cycle: D = T(P^-1 R / dc), then `cycle` updates
   // S = T(S + D), each followed by the residual and, before the next, the
   // direction D = T(alpha D + beta P^-1 R)
   void cycle_steps() {
+    if (three) {
+      for (int k = 0; k < cycle; ++k) {
+        pb.enqueue(s);
+        enqueue_trunc(u30[k], u3B[k], s);
+        resid(1, (k + 1) & 1);
+      }
+      if (cycle & 1)
+        launch_cast_lr(back.as<CastItem<T, T>>(), done.as<int>(), nb, rows_max, it[0]->S.cap, s);
+      return;
+    }
     pb.enqueue(s);
     enqueue_trunc(dstart0, dstartB, s);
     for (int k = 0; k < cycle; ++k) {
@@ -489,6 +592,7 @@ struct BatchCheb {
       if (all) break;
       rep.run(s, kcls(K_GRAPH, is_f32<T>()), [&]() { cycle_steps(); });
     }
+    three_back();
     if (log_on())
       for (int j = 0; j < nb; ++j)
         std::fprintf(stderr,
@@ -519,6 +623,16 @@ struct BatchDir {
   TruncBatch<float> dstartB;
   std::vector<TruncPlan<float>> dstep0;
   std::vector<TruncBatch<float>> dstepB;
+  // three-term form (as in BatchCheb): fp64 iterate alternating between S and
+  // D's buffer, the fp32 solve P^-1 R widened to fp64 before each update
+  bool three = false;
+  SpmmLaunch<double> sp1;
+  Batched<SpmmArgs<double>> spB1;
+  TruncPlan<double> resid1;
+  TruncBatch<double> residB1;
+  std::vector<TruncPlan<double>> u30;
+  std::vector<TruncBatch<double>> u3B;
+  DevBuf castZ, zscr, back;
   Replay rep;
 
   DevBuf& newbuf() {
@@ -531,6 +645,7 @@ struct BatchDir {
     nb = int(run.size());
     s = s_;
     cycle = o.restart;
+    three = o.recurrence == LRC_CHEB_THREE_TERM;
     rep.eager = eager;
     cap = run[0]->cap;
     done.alloc(size_t(nb) * sizeof(int));
@@ -583,6 +698,10 @@ struct BatchDir {
       return C.resid_plan(run[j]->B64, C.norm.as<double>(), o.trunc_tol, 0,
                           kResFloor * run[j]->target);
     }, resid0, residB);
+    if (three) {
+      setup_three(o, site64);
+      return;
+    }
     site64([&](int j) { return run[j]->c64->supd_plan(); }, supd0, supdB);
     site32([&](int j) { return run[j]->c32->dstart_plan(run[j]->dc); }, dstart0, dstartB);
     std::vector<double> rho(nb);
@@ -599,19 +718,92 @@ struct BatchDir {
     }
   }
 
+  template <class Site>
+  void setup_three(const lrc_opts& o, Site& site64) {
+    const int* dn = done.as<int>();
+    LRC_CHECK(3 * ld_for(cap) <= kTruncCap, ST_EINVAL,
+              "three-term recurrence: 3 * rank_cap must not exceed 128 columns");
+    std::vector<SpmmLaunch<double>> sl;
+    std::vector<SpmmArgs<double>> sa;
+    std::vector<CastItem<float, double>> cz;
+    std::vector<CastItem<double, double>> cb;
+    zscr.alloc(size_t(nb) * (64 * sizeof(double) + 16));
+    for (int j = 0; j < nb; ++j) {
+      Cheb<double>& C = *run[j]->c64;
+      Cheb<float>& F = *run[j]->c32;
+      sl.push_back(C.spmm_plan(C.D.u(), C.D.ld, C.D.r()));
+      sa.push_back(sl.back().a);
+      // Z only (m = 0 rows of V); its core and rank copies land in scratch
+      double* zs = zscr.as<double>() + size_t(j) * 66;
+      cz.push_back(CastItem<float, double>{F.Z.as<float>(), nullptr, F.R.sv(), F.R.r(),
+                                           C.Z.as<double>(), nullptr, zs,
+                                           reinterpret_cast<int*>(zs + 64), ld_for(cap), 0,
+                                           ld_for(cap), 0, C.R.n, 0, cap});
+      cb.push_back(CastItem<double, double>{C.D.u(), C.D.v(), C.D.sv(), C.D.r(), C.S.u(),
+                                            C.S.v(), C.S.sv(), C.S.r(), C.D.ld, C.D.ld, C.S.ld,
+                                            C.S.ld, C.S.n, C.S.m, C.S.cap});
+    }
+    sp1 = merge_spmm(sl);
+    spB1 = upload_items(sa, dn, newbuf(), s);
+    upload_items(cz, dn, castZ, s);
+    if (cycle & 1) upload_items(cb, dn, back, s);
+    site64([&](int j) {
+      Cheb<double>& C = *run[j]->c64;
+      return C.resid_plan(run[j]->B64, C.norm.as<double>(), o.trunc_tol, 0,
+                          kResFloor * run[j]->target, &C.D);
+    }, resid1, residB1);
+    std::vector<double> rho(nb);
+    for (int j = 0; j < nb; ++j) rho[j] = run[j]->c / run[j]->dc;
+    u30.resize(cycle);
+    u3B.resize(cycle);
+    for (int k = 0; k < cycle; ++k) {
+      std::vector<double> a(nb, 1.0), b(nb, 0.0), g(nb);
+      for (int j = 0; j < nb; ++j) {
+        const double cj = run[j]->c, dj = run[j]->dc;
+        if (k == 0) {
+          g[j] = 1.0 / dj;
+          continue;
+        }
+        const double rn = 1.0 / (2.0 * dj / cj - rho[j]);
+        a[j] = 1.0 + rn * rho[j];
+        b[j] = -rn * rho[j];
+        g[j] = 2.0 * rn / cj;
+        rho[j] = rn;
+      }
+      site64([&](int j) {
+        Cheb<double>& C = *run[j]->c64;
+        const LR<double>& X = (k & 1) ? C.D : C.S;
+        const LR<double>& Y = (k & 1) ? C.S : C.D;
+        return C.upd3_plan(X, a[j], k == 0 ? nullptr : &Y, b[j], g[j], Y);
+      }, u30[k], u3B[k]);
+    }
+  }
+
   void cast_r() {
     launch_cast_lr(castR.as<CastItem<double, float>>(), done.as<int>(), nb, rows_max, cap, s);
   }
   void cast_d() {
     launch_cast_lr(castD.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap, s);
   }
-  void resid(int after_update) {
-    enqueue_spmm(sp0, spB, s);
-    enqueue_trunc(resid0, residB, s);
+  void resid(int after_update, int buf = 0) {
+    enqueue_spmm(buf ? sp1 : sp0, buf ? spB1 : spB, s);
+    enqueue_trunc(buf ? resid1 : resid0, buf ? residB1 : residB, s);
     launch_batch_check(ctl.as<BCtl>(), done.as<int>(), nb, after_update, s);
     cast_r();
   }
   void cycle_steps() {
+    if (three) {
+      for (int k = 0; k < cycle; ++k) {
+        pb.enqueue(s);
+        launch_cast_lr(castZ.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap,
+                       s);
+        enqueue_trunc(u30[k], u3B[k], s);
+        resid(1, (k + 1) & 1);
+      }
+      if (cycle & 1)
+        launch_cast_lr(back.as<CastItem<double, double>>(), done.as<int>(), nb, rows_max, cap, s);
+      return;
+    }
     pb.enqueue(s);
     enqueue_trunc(dstart0, dstartB, s);
     cast_d();
@@ -662,6 +854,14 @@ struct BatchDir {
       if (all) break;
       rep.run(s, kcls(K_GRAPH, false), [&]() { cycle_steps(); });
     }
+    // an item that stopped at an even step k of a cycle holds its iterate in
+    // D's buffer (see BatchCheb::three_back)
+    if (three)
+      for (int j = 0; j < nb; ++j) {
+        const int t = hctl[j].iters;
+        if (t >= 1 && ((t - 1) % cycle) % 2 == 0) cast_lr<double, double>(run[j]->c64->D,
+                                                                            run[j]->c64->S, s);
+      }
   }
 };
 
@@ -884,7 +1084,8 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
     }
     std::vector<double> res_abs;
     for (auto* r : run) res_abs.push_back(kResFloor * r->target);
-    bc.setup(items, rhs, c, dc, o.trunc_tol, res_abs, o.restart, eager, s);
+    bc.setup(items, rhs, c, dc, o.trunc_tol, res_abs, o.restart, eager, s,
+             o.recurrence == LRC_CHEB_THREE_TERM);
     bc.run(std::vector<int>(nb, 0), tgt, mi, 1 << 30, &bn);
     for (int j = 0; j < nb; ++j) {
       run[j]->iters = bc.hctl[j].iters;
@@ -945,7 +1146,7 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
         rhs.push_back(&r->Bin);
       }
       bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, std::vector<double>(nb, 0.0),
-               o.restart, eager, s);
+               o.restart, eager, s, o.recurrence == LRC_CHEB_THREE_TERM);
     }
     const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
     while (true) {

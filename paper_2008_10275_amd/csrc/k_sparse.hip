@@ -912,6 +912,10 @@ template void launch_cast_lr<double, float>(const CastItem<double, float>*, cons
                                             int64_t, int, hipStream_t);
 template void launch_cast_lr<float, double>(const CastItem<float, double>*, const int*, int,
                                             int64_t, int, hipStream_t);
+template void launch_cast_lr<double, double>(const CastItem<double, double>*, const int*, int,
+                                             int64_t, int, hipStream_t);
+template void launch_cast_lr<float, float>(const CastItem<float, float>*, const int*, int,
+                                           int64_t, int, hipStream_t);
 
 __global__ void fill_kernel(double* p, int64_t count, double v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;

@@ -490,8 +490,9 @@ SpmmLaunch<T> Cheb<T>::spmm_plan(const T* U, int ldu, const int* r_dev) const {
 // R = T(B - sum_i K_i S D_i): blocks [B | K_0 S | ... ] and [B_V | D_0 S_V | ...]
 template <class T>
 TruncPlan<T> Cheb<T>::resid_plan(const LR<T>& B, double* norm_dev, double tol_, int rank_cap,
-                                 double abs_tol) const {
+                                 double abs_tol, const LR<T>* X) const {
   const Ops& o = *P->ops;
+  const LR<T>& S = X ? *X : this->S;
   const int ld = ld_for(cap);
   BlockView<T> A{}, Bv{};
   CoreView c{};
@@ -548,6 +549,28 @@ TruncPlan<T> Cheb<T>::dstep_plan(double alpha, double beta) const {
   add_core(cv, R.sv(), beta, R.r(), 0);
   return tr.plan(A, P->ops->n, Bv, P->m, cv, cap, tol, D.u(), D.ld, D.v(), D.ld, D.sv(), D.r(),
                  norm.as<double>() + 1);
+}
+
+// out = T(a X + b Y + g Z R_V^T), Z = P^{-1} R_U (the three-term update)
+template <class T>
+TruncPlan<T> Cheb<T>::upd3_plan(const LR<T>& X, double a, const LR<T>* Y, double b, double g,
+                                const LR<T>& out) const {
+  const int ld = ld_for(cap);
+  BlockView<T> A{}, Bv{};
+  CoreView cv{};
+  add_block(A, X.u(), X.ld, X.r(), 0);
+  add_block(Bv, X.v(), X.ld, X.r(), 0);
+  add_core(cv, X.sv(), a, X.r(), 0);
+  if (Y) {
+    add_block(A, Y->u(), Y->ld, Y->r(), 0);
+    add_block(Bv, Y->v(), Y->ld, Y->r(), 0);
+    add_core(cv, Y->sv(), b, Y->r(), 0);
+  }
+  add_block(A, Z.as<T>(), ld, R.r(), 0);
+  add_block(Bv, R.v(), R.ld, R.r(), 0);
+  add_core(cv, R.sv(), g, R.r(), 0);
+  return tr.plan(A, P->ops->n, Bv, P->m, cv, cap, tol, out.u(), out.ld, out.v(), out.ld,
+                 out.sv(), out.r(), norm.as<double>() + 2);
 }
 
 // Z = P^{-1} R_U
@@ -803,6 +826,10 @@ void SolveRun::prepare(Prob& P_, const lrc_opts& o, int r0, const double* U0, co
   LRC_CHECK(o.precision == LRC_FP64 || o.precision == LRC_MIXED_FP32 ||
                 o.precision == LRC_MIXED_FP32_DIR || o.precision == LRC_MIXED_BF16GRAM,
             ST_EINVAL, "lrc_solve: unknown precision");
+  LRC_CHECK(o.recurrence == LRC_CHEB_DIRECTION || o.recurrence == LRC_CHEB_THREE_TERM, ST_EINVAL,
+            "lrc_solve: unknown recurrence");
+  LRC_CHECK(o.recurrence != LRC_CHEB_THREE_TERM || 3 * ld_for(cap) <= kTruncCap, ST_EINVAL,
+            "lrc_solve: the three-term recurrence needs 3 * rank_cap <= 128");
   LRC_CHECK(o.solver == LRC_SOLVER_CHEBYSHEV ||
                 (o.solver == LRC_SOLVER_GMREST && o.precision == LRC_FP64),
             ST_EINVAL, "lrc_solve: unknown solver (GMREST runs in fp64)");

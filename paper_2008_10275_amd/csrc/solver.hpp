@@ -176,11 +176,18 @@ struct Cheb {
   SpmmLaunch<T> spmm_plan(const T* U, int ldu, const int* r_dev) const;
   // rank_cap <= 0: the solve's cap
   // abs_tol: directions whose total weight stays below it are dropped as well
+  // X: the iterate the residual is taken of (nullptr: S; the SpMM of X must
+  // have written W)
   TruncPlan<T> resid_plan(const LR<T>& B, double* norm_dev, double tol, int rank_cap = 0,
-                          double abs_tol = 0.0) const;
+                          double abs_tol = 0.0, const LR<T>* X = nullptr) const;
   TruncPlan<T> dstart_plan(double dc) const;
   TruncPlan<T> supd_plan() const;
   TruncPlan<T> dstep_plan(double alpha, double beta) const;
+  // three-term update out = T(a X + b Y + g Z R_V^T) (Y == nullptr: no Y
+  // term); out may be Y, whose factors the truncation has read before it
+  // writes its result
+  TruncPlan<T> upd3_plan(const LR<T>& X, double a, const LR<T>* Y, double b, double g,
+                         const LR<T>& out) const;
   PrecItem<T> prec_item() const;
 };
 

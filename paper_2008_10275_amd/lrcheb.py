@@ -25,6 +25,7 @@ LRC_OK, LRC_ENOTCONV, LRC_EINVAL, LRC_ENOMEM, LRC_EDEVICE = 0, 1, -1, -2, -3
 LRC_ESINGULAR, LRC_EBREAKDOWN, LRC_ECALLBACK = -4, -5, -6
 LRC_FP64, LRC_MIXED_FP32, LRC_MIXED_FP32_DIR, LRC_MIXED_BF16GRAM = 0, 1, 2, 3
 LRC_SOLVER_CHEBYSHEV, LRC_SOLVER_GMREST = 0, 1
+LRC_CHEB_DIRECTION, LRC_CHEB_THREE_TERM = 0, 1
 LRC_SPMM_SKIP_EMPTY = 4
 LRC_PREC_LU, LRC_PREC_ILU0 = 0, 1
 LRC_INIT_ZERO, LRC_INIT_MEDIAN, LRC_INIT_GIVEN, LRC_INIT_GIVEN_JUDGED, LRC_INIT_NEWTON = 0, 1, 2, 3, 4
@@ -42,7 +43,7 @@ class lrc_opts(C.Structure):
                 ("cheb_d", C.c_double), ("precision", C.c_int), ("refine_max", C.c_int),
                 ("inner_tol", C.c_double), ("init", C.c_int), ("median_tol", C.c_double),
                 ("verify_fp64", C.c_int), ("eager", C.c_int), ("inner_trunc_tol", C.c_double),
-                ("res_ref", C.c_double), ("solver", C.c_int)]
+                ("res_ref", C.c_double), ("solver", C.c_int), ("recurrence", C.c_int)]
 
 
 class lrc_info(C.Structure):

@@ -63,23 +63,27 @@ def _dense(sol):
     return U @ np.diag(s) @ V.T
 
 
-def _kw(L, precision):
+def _kw(L, precision, recurrence="direction"):
     prec = {"fp64": L.LRC_FP64, "mixed": L.LRC_MIXED_FP32, "dir": L.LRC_MIXED_FP32_DIR}[precision]
+    rec = {"direction": L.LRC_CHEB_DIRECTION, "three_term": L.LRC_CHEB_THREE_TERM}[recurrence]
     return dict(rank_cap=30, trunc_tol=1e-8, res_tol=1e-6, init=L.LRC_INIT_MEDIAN,
-                precision=prec, verify_fp64=1)
+                precision=prec, verify_fp64=1, recurrence=rec)
 
 
+@pytest.mark.parametrize("recurrence", ["direction", "three_term"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "dir"])
-def test_batched_matches_subset_solves(torch, L, ctx, c3, precision):
+def test_batched_matches_subset_solves(torch, L, ctx, c3, precision, recurrence):
+    """The subsets stop at different steps of a cycle, so in the three-term
+    form their iterates end in either of its two buffers."""
     cfg, subs = c3
-    kw = _kw(L, precision)
+    kw = _kw(L, precision, recurrence)
     seq = []
     for j, sb in enumerate(subs):
-        say("sequential", precision, "subset", j, "m", sb["d"].shape[1])
+        say("sequential", precision, recurrence, "subset", j, "m", sb["d"].shape[1])
         code, info = sb["prob"].solve(**kw)
         assert code == 0, (j, info)
         seq.append((info, _dense(sb["prob"].solution())))
-    say("batched", precision, len(subs), "subsets")
+    say("batched", precision, recurrence, len(subs), "subsets")
     code, infos = L.solve_batched([sb["prob"] for sb in subs], **kw)
     assert code == 0, infos
     f = cfg["f"]
