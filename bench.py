@@ -179,7 +179,8 @@ def main_batched(a, L, torch):
                                 f"{int(round(np.sqrt(n)))} grid, n={n}, rank cap "
                                 f"{cfg['rank_cap']}, relres {res_tol:g}, batched lockstep solve"),
                    "n": int(n), "subsets": len(sizes), "m_total": int(sum(sizes)),
-                   "rank_cap": cfg["rank_cap"], "trunc_tol": cfg["trunc_tol"]},
+                   "rank_cap": cfg["rank_cap"], "trunc_tol": cfg["trunc_tol"],
+                   "precision": a.precision, "recurrence": a.recurrence},
         "result": {"iters": [i["iters"] for i in infos],
                    "max_relres_fp64": max(i["relres"] for i in infos),
                    "setup_s": setup_s},
@@ -217,7 +218,8 @@ def main_surrogate(a, L, torch):
     ptr, pte = prob(dtr), prob(dte)
     res_tol = cfg["res_tol"]
     base = dict(rank_cap=cfg["rank_cap"], trunc_tol=cfg["trunc_tol"], res_tol=res_tol,
-                verify_fp64=1)
+                verify_fp64=1, recurrence={"direction": L.LRC_CHEB_DIRECTION,
+                                           "three_term": L.LRC_CHEB_THREE_TERM}[a.recurrence])
     code, _ = ptr.solve(L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=L.LRC_FP64))
     if code != 0:
         raise RuntimeError("training snapshots did not converge")
@@ -252,7 +254,8 @@ def main_surrogate(a, L, torch):
     o_l = L.default_opts(**base, init=L.LRC_INIT_GIVEN, precision=prec)
     o_j = L.default_opts(**base, init=L.LRC_INIT_GIVEN_JUDGED, precision=prec)
     o_m = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=prec)
-    o_p = L.default_opts(**base, init=L.LRC_INIT_MEDIAN, precision=L.LRC_FP64)
+    o_p = L.default_opts(**dict(base, recurrence=L.LRC_CHEB_DIRECTION), init=L.LRC_INIT_MEDIAN,
+                         precision=L.LRC_FP64)
 
     def learned(o=o_l, U=U0r, nt=net):
         C = nt.predict(Xte)
@@ -303,7 +306,8 @@ def main_surrogate(a, L, torch):
                                 f"(POD rank {rr}), 3-term stencil equation on a "
                                 f"{int(round(np.sqrt(n)))}x{int(round(np.sqrt(n)))} grid, n={n}"),
                    "n": int(n), "m_train": int(dtr.shape[1]), "m_test": int(dte.shape[1]),
-                   "rank_cap": cfg["rank_cap"], "pod_rank": int(rr), "precision": a.precision},
+                   "rank_cap": cfg["rank_cap"], "pod_rank": int(rr), "precision": a.precision,
+                   "recurrence": a.recurrence},
         "result": {"learned": dict(seconds=t_l, iters=i_l["iters"], relres=i_l["relres"]),
                    "learned_judged": dict(seconds=t_j, iters=i_j["iters"], relres=i_j["relres"],
                                           fallback_cols=i_j["median_fallback_cols"],
