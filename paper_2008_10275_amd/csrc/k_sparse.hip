@@ -147,7 +147,11 @@ __device__ __forceinline__ void spmm_row_ell(const DevCsr<T>& K, int64_t x, int6
 // multiple of 8 q.  The nonzeros of a row are taken NZB at a time: the
 // operator's longest row when it is 5 or 9 (the stencils' own widths: no
 // padded slot on interior rows), else 4.
-template <class T, int NV>
+// WIDE: the launch holds an operator whose padded copy is 27 entries wide;
+// the narrower instantiation leaves that path out, whose 27 index and value
+// registers per lane would otherwise set the register count (and so the
+// occupancy) of every launch.
+template <class T, int NV, bool WIDE>
 __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArgs<T>* ab,
                                                    const int* done, int lpr_cap) {
   constexpr int VW = V16<T>::n;
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
     LRC_ELL(7);
   } else if (ew == 9) {
     LRC_ELL(9);
-  } else if (ew == 27) {
+  } else if (WIDE && ew == 27) {
     LRC_ELL(27);
   } else if (maxrow <= 5) {
     for (int64_t x = first; x < nvis; x += stride)
@@ -241,6 +245,8 @@ SpmmLaunch<T> make_spmm(const DevCsr<T>* ops, int q, const T* U, int ldu, const 
     n = std::max(n, ops[i].n);
   }
   a.q = q;
+  l.wide = false;
+  for (int i = 0; i < q; ++i) l.wide = l.wide || ops[i].ew > 9;
   a.U = U;
   a.ldu = ldu;
   a.r_dev = r_dev;
@@ -280,17 +286,19 @@ template <class T>
 void enqueue_spmm(const SpmmLaunch<T>& l, Batched<SpmmArgs<T>> b, hipStream_t s) {
   ProfScope ps(kcls(K_SPMM, is_f32<T>()), s, l.work);
   const dim3 grid(unsigned(l.blocks), 1, unsigned(b.n)), blk(64 * l.waves);
+#define LRC_SPMM(NV)                                                                              \
+  do {                                                                                            \
+    if (l.wide)                                                                                   \
+      hipLaunchKernelGGL((spmm_kernel<T, NV, true>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);  \
+    else                                                                                          \
+      hipLaunchKernelGGL((spmm_kernel<T, NV, false>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr); \
+  } while (0)
   switch (l.nv) {
-    case 1:
-      hipLaunchKernelGGL((spmm_kernel<T, 1>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
-      break;
-    case 2:
-      hipLaunchKernelGGL((spmm_kernel<T, 2>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
-      break;
-    default:
-      hipLaunchKernelGGL((spmm_kernel<T, 4>), grid, blk, 0, s, l.a, b.dev, b.done, l.lpr);
-      break;
+    case 1: LRC_SPMM(1); break;
+    case 2: LRC_SPMM(2); break;
+    default: LRC_SPMM(4); break;
   }
+#undef LRC_SPMM
   LRC_HIP(hipGetLastError());
 }
 

@@ -68,6 +68,7 @@ struct SpmmLaunch {
   int waves = 4;   // waves per workgroup
   int blocks = 1;
   int q = 1;
+  bool wide = false;   // an operator's padded copy is wider than 9 entries
   Work work;
 };
 // Launch shape of the SpMM: columns per lane (0: the dtype's default), waves
