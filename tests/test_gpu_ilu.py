@@ -110,10 +110,12 @@ def _c1_newton_rhs():
 
 
 @pytest.mark.parametrize("solver,cap,tt,tol", [("cheb", 20, 1e-8, 1e-8),
+                                               ("cheb3", 20, 1e-8, 1e-8),
                                                ("gmrest", 40, 1e-10, 1e-4)])
 def test_ilu0_solves_c1(L, ctx, solver, cap, tt, tol):
     """Both solvers with the ILU(0) kind reach the tolerance (checked densely
-    on the host); the ChebyshevT iteration count is between 0.8 and 1.1
+    on the host); the ChebyshevT iteration count (either form of its
+    recurrence, against the oracle's same form) is between 0.8 and 1.1
     times the oracle's (the same recurrence from the same start, but its
     last ~40 steps creep along a truncation-noise floor near the tolerance,
     where the rounding of each truncation moves the crossing by up to a
@@ -131,16 +133,19 @@ def test_ilu0_solves_c1(L, ctx, solver, cap, tt, tol):
     code, info = prob.solve(rank_cap=cap, trunc_tol=tt, res_tol=tol, init=L.LRC_INIT_MEDIAN,
                             median_tol=1e-12, max_iter=400,
                             solver=L.LRC_SOLVER_GMREST if solver == "gmrest" else
-                            L.LRC_SOLVER_CHEBYSHEV)
+                            L.LRC_SOLVER_CHEBYSHEV,
+                            recurrence=L.LRC_CHEB_THREE_TERM if solver == "cheb3" else
+                            L.LRC_CHEB_DIRECTION)
     P = _oracle_prec("c1")[1]
-    if solver == "cheb":
+    if solver.startswith("cheb"):
         c, dc = och.chebyshev_interval(d, och.mean_parameters(d))
-        S, oi = och.chebyshev_t(K, d, B, P, c, dc, cap, tt, tol, ref, restart=6, max_iter=400)
+        form = och.chebyshev_t3 if solver == "cheb3" else och.chebyshev_t
+        S, oi = form(K, d, B, P, c, dc, cap, tt, tol, ref, restart=6, max_iter=400)
     else:
         S, oi = ogm.gmrest(K, d, B, P, cap, tt, tol, ref, restart=6, max_iter=400)
     say("gpu", code, info["iters"], info["relres"], "oracle", oi.iters, oi.converged)
     assert code == 0 and info["relres"] <= tol and oi.converged
-    if solver == "cheb":
+    if solver.startswith("cheb"):
         assert 0.8 * oi.iters <= info["iters"] <= 1.1 * oi.iters
     else:
         assert abs(info["iters"] - oi.iters) <= 3
