@@ -156,14 +156,42 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
                                                    const int* done, int lpr_cap) {
   constexpr int VW = V16<T>::n;
   if (done && done[blockIdx.z]) return;
-  const SpmmArgs<T>& args = ab ? ab[blockIdx.z] : a0;
-  const int q = args.q;
+  // the item's fields are copied through a pointer of one address space
+  // (device array or kernel argument), so that they arrive in scalar
+  // registers instead of through generic per-lane loads
+  const SpmmArgs<T>* ap = ab ? ab + blockIdx.z : nullptr;
+  const int q = ap ? ap->q : a0.q;
   const int L = blockIdx.x, xcd = L & 7, kx = L >> 3;
   const int op = kx % q, rb = (kx / q) * 8 + xcd;   // row block of this workgroup's sweep
   const int nrb = int(gridDim.x) / q;                // row blocks per sweep
   if (rb >= nrb) return;
-  const DevCsr<T> K = args.op[op];
-  const int r = __builtin_amdgcn_readfirstlane(args.r_dev ? *args.r_dev : args.r_const);
+  DevCsr<T> K;
+  T* W;
+  const T* U;
+  const int* r_dev;
+  int r_const, ldu, ldw, wpad_i, skip;
+  if (ap) {
+    K = ap->op[op];
+    W = ap->W[op];
+    U = ap->U;
+    r_dev = ap->r_dev;
+    r_const = ap->r_const;
+    ldu = ap->ldu;
+    ldw = ap->ldw;
+    wpad_i = ap->wpad;
+    skip = ap->skip_empty;
+  } else {
+    K = a0.op[op];
+    W = a0.W[op];
+    U = a0.U;
+    r_dev = a0.r_dev;
+    r_const = a0.r_const;
+    ldu = a0.ldu;
+    ldw = a0.ldw;
+    wpad_i = a0.wpad;
+    skip = a0.skip_empty;
+  }
+  const int r = __builtin_amdgcn_readfirstlane(r_dev ? *r_dev : r_const);
   if (r <= 0) return;
   const int nvec = (r + VW - 1) / VW;            // vectors per row
   const int lpr = min(lpr_cap, (nvec + NV - 1) / NV);
@@ -175,21 +203,20 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
   if (sub >= rpw || chunk >= nvec) return;
   const int64_t rows_per_block = int64_t(rpw) * (blockDim.x >> 6);
   const int64_t stride = int64_t(nrb) * rows_per_block;
-  T* __restrict__ W = args.W[op];
   const int64_t first = int64_t(rb) * rows_per_block + int64_t(wave) * rpw + sub;
   const int maxrow = __builtin_amdgcn_readfirstlane(K.maxrow);
-  const bool wpad = args.wpad != 0;
+  const bool wpad = wpad_i != 0;
   // with a row list only the non-empty rows are visited (the solid box of
   // K_1, K_2: a sixth of the rows); the list is read in order, so a wave's
   // lookups are one contiguous span
-  const int* __restrict__ rl = args.skip_empty ? K.rows : nullptr;
+  const int* __restrict__ rl = skip ? K.rows : nullptr;
   const int64_t nvis = rl ? K.nrows : K.n;
   // the padded copy covers exactly the visited rows (all rows, or the list)
   const int ew = __builtin_amdgcn_readfirstlane((rl || !K.rows) ? K.ew : 0);
 #define LRC_ELL(EW)                                                                               \
   for (int64_t x = first; x < nvis; x += stride)                                                  \
-    spmm_row_ell<T, NV, EW>(K, x, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, \
-                            lpr, chunk, wpad)
+    spmm_row_ell<T, NV, EW>(K, x, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, \
+                            wpad)
   if (ew == 5) {
     LRC_ELL(5);
   } else if (ew == 7) {
@@ -200,16 +227,13 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
     LRC_ELL(27);
   } else if (maxrow <= 5) {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 5>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
-                         chunk, wpad);
+      spmm_row<T, NV, 5>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   } else if (maxrow <= 9) {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 9>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
-                         chunk, wpad);
+      spmm_row<T, NV, 9>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   } else {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 4>(K, rl ? int64_t(rl[x]) : x, args.U, args.ldu, W, args.ldw, r, nvec, lpr,
-                         chunk, wpad);
+      spmm_row<T, NV, 4>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   }
 #undef LRC_ELL
 }
@@ -367,14 +391,25 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __res
                                                           const int* done, int ldw) {
   typedef typename V16<T>::t vec;
   constexpr int VN = V16<T>::n;
-  if (done && done[blockIdx.z]) return;
-  const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
+  // the done flag, the item and the thread's first row descriptor are read in
+  // one round (all are valid memory whatever the flag says); the empty asm
+  // statement keeps them ahead of the exit, so that a launch does not wait
+  // on one round per pointer
   const int64_t total = int64_t(nrows) * vpr;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
+  const int64_t e0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int dn = done ? done[blockIdx.z] : 0;
+  PrecItem<T> it;
+  if (ab)
+    it = ab[blockIdx.z];
+  else
+    it = a0;
+  const GatherRow g0 = e0 < total ? rows[int(e0 / vpr)] : GatherRow{};
+  asm volatile("" ::"v"(dn), "v"(g0.src), "v"(g0.na));
+  if (dn) return;
+  for (int64_t e = e0; e < total; e += int64_t(gridDim.x) * blockDim.x) {
     const int row = int(e / vpr);
     const int c = int(e - int64_t(row) * vpr) * VN;
-    const GatherRow g = rows[row];
+    const GatherRow g = e == e0 ? g0 : rows[row];
     vec v;
     if (FWD) {
       v = g.src >= 0 ? *reinterpret_cast<const vec*>(it.R + int64_t(g.src) * it.ldr + c)
@@ -400,21 +435,33 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   constexpr int WPB = NW > 4 ? NW : 4;    // waves per workgroup
   constexpr int TPB = WPB / NW;           // tasks per workgroup
   __shared__ T red[NW > 1 ? NW : 1][KTM * 4][64];
-  if (done && done[blockIdx.z]) return;
-  const PrecItem<T>& it = ab ? ab[blockIdx.z] : a0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // workgroups are dealt to the 8 XCDs in turn (w -> XCD w % 8): the grid (a
   // multiple of 8) gives XCD x the contiguous eighth x of the task range, so
   // that the tasks of one supernode, which all read its input rows, share an L2
   const int bx = int(blockIdx.x & 7) * int(gridDim.x >> 3) + int(blockIdx.x >> 3);
   const int tk = bx * TPB + wave / NW;   // uniform per workgroup when NW > 1
-  if (tk >= ntasks) return;
+  const bool live = tk < ntasks;
   const int wv = wave % NW;
-  const int2 task = tasks[tk];
+  // Launches of the upper levels are short, so their cost is the chain of
+  // dependent loads before the first product: the done flag, the item and the
+  // task are read in one round, the supernode's fields and the width in the
+  // next (all valid memory whatever the flag says; a wave past the last task
+  // reads task 0); the empty asm statement keeps these loads ahead of the
+  // exit (uniform per workgroup when NW > 1).
+  const int dn = done ? done[blockIdx.z] : 0;
+  PrecItem<T> it;
+  if (ab)
+    it = ab[blockIdx.z];
+  else
+    it = a0;
+  const int2 task = tasks[live ? tk : 0];
   const int sn = task.x, row0 = task.y;
   const int k = it.k_dev ? *it.k_dev : it.k_const;
   const int ns = P.ns[sn], f = ns + P.nb[sn], j0 = P.j0[sn];
   const int leaf = FWD ? 0 : P.leaf[sn];
+  asm volatile("" ::"v"(dn), "v"(k), "v"(f), "v"(j0), "v"(leaf));
+  if (!live || dn) return;
   const int nin = FWD ? ns : f;
   const int nout = FWD ? f : ns;
   const T* __restrict__ M = FWD ? it.fw + P.fw_off[sn] : it.bw + P.bw_off[sn];
