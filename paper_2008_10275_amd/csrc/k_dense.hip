@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 
+#include "gmem.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
 
@@ -83,8 +84,8 @@ __device__ inline int build_coltab(const BlockView<T>& v, unsigned char* blk, sh
 
 template <class T>
 __device__ inline T view_at(const BlockView<T>& v, int b, int lc, int64_t row) {
-  T x = v.ptr[b][row * v.ld[b] + lc];
-  if (v.rowscale[b]) x *= T(v.rowscale[b][row]);
+  T x = gmem(v.ptr[b])[row * v.ld[b] + lc];
+  if (v.rowscale[b]) x *= T(gmem(v.rowscale[b])[row]);
   return x;
 }
 
@@ -149,9 +150,9 @@ __device__ inline ColRef<T> resolve_col(const BlockView<T>& v, int c) {
 template <class T, bool SCALED>
 __device__ inline T col_load(const ColRef<T>& c, int64_t row, int64_t rmax) {
   const int r = int(row < rmax ? row : rmax);
-  T x = c.p[r * c.ld];
+  T x = gmem(c.p)[r * c.ld];
   if constexpr (SCALED) {
-    const double f = c.sc[r];
+    const double f = gmem(c.sc)[r];
     x *= c.ss ? T(f) : T(1);
   }
   return x;
@@ -321,7 +322,7 @@ __device__ __forceinline__ void gram_body(const GramArgs<T>& a, int job, int wg,
   T* out = a.partial + size_t(blockIdx.x) * kGN * 256;
   for (int e = threadIdx.x; e < NTM * 256; e += blockDim.x) {
     const int u = e >> 8;
-    if (tt.bj[u] < KT) out[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
+    if (tt.bj[u] < KT) gmem(out)[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
   }
 }
 
@@ -442,7 +443,7 @@ __device__ __forceinline__ void gram_body_bf16(const GramArgs<float>& a, int job
   float* out = a.partial + size_t(blockIdx.x) * kGN * 256;
   for (int e = threadIdx.x; e < NTM * 256; e += blockDim.x) {
     const int u = e >> 8;
-    if (tt.bj[u] < KT) out[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
+    if (tt.bj[u] < KT) gmem(out)[gtile_id(tt.bi[u], tt.bj[u]) * 256 + (e & 255)] = red[e];
   }
 }
 
@@ -513,11 +514,11 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(GramRedArgs<T> r0, co
     for (; p + 16 * 7 < nw; p += 16 * 8) {
       T v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = pp[size_t(p + 16 * u) * st];
+      for (int u = 0; u < 8; ++u) v[u] = gmem(pp)[size_t(p + 16 * u) * st];
 #pragma unroll
       for (int u = 0; u < 8; ++u) s += double(v[u]);
     }
-    for (; p < nw; p += 16) s += double(pp[size_t(p) * st]);
+    for (; p < nw; p += 16) s += double(gmem(pp)[size_t(p) * st]);
   }
   sh[grp][l] = s;
   __syncthreads();
@@ -528,8 +529,8 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(GramRedArgs<T> r0, co
   const int r = tbi * 16 + (w >> 4), c = tbj * 16 + (w & 15);
   if (r >= k || c >= k || r > c) return;
   double* G = job == 0 ? G0 : G1;
-  G[size_t(r) * kcap + c] = t;
-  G[size_t(c) * kcap + r] = t;
+  gmem(G)[size_t(r) * kcap + c] = t;
+  gmem(G)[size_t(c) * kcap + r] = t;
 }
 
 template <class T>
@@ -699,7 +700,7 @@ __device__ __forceinline__ void ts_tile(const T (&a)[KQ], const T* Ms, int kq, i
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t row = row0 + Mfma<T>::drow(lane, i);
-        if (row < rows) Y[row * ldy + c] = acc[t][i];
+        if (row < rows) gmem(Y)[row * ldy + c] = acc[t][i];
       }
     }
   }
@@ -912,7 +913,7 @@ __device__ __forceinline__ void res_load(double (&a)[KQ], const ResCol* acol, in
   for (int q = 0; q < KQ; ++q)
     if (q < kq) {
       const ResCol e = acol[4 * q + g];
-      a[q] = (ok && e.p) ? e.p[row * e.ld] : 0.0;
+      a[q] = (ok && e.p) ? gmem(e.p)[row * e.ld] : 0.0;
     }
 }
 
@@ -1018,7 +1019,7 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(BlockView<double>
   for (int jj = threadIdx.x; jj < NC; jj += blockDim.x) {
     double v = 0.0;
     for (int w = 0; w < nw; ++w) v += colacc[w * NC + jj];
-    if (j0 + jj < m) part[size_t(rg) * m + j0 + jj] = v;
+    if (j0 + jj < m) gmem(part)[size_t(rg) * m + j0 + jj] = v;
   }
 }
 
@@ -1027,7 +1028,7 @@ __global__ void residual_reduce_kernel(const double* __restrict__ part, int grou
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= m) return;
   double s = 0.0;
-  for (int g = 0; g < groups; ++g) s += part[size_t(g) * m + j];
+  for (int g = 0; g < groups; ++g) s += gmem(part)[size_t(g) * m + j];
   colsq[j] = s;
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "gmem.hpp"
 #include "prof.hpp"
 
 namespace lrc {
@@ -52,7 +53,7 @@ __device__ __forceinline__ void spmm_store(const typename V16<T>::t* acc, int64_
     const int j = chunk + v * lpr;
     if (j >= nvec) break;
     if ((j + 1) * VW <= r) {
-      *reinterpret_cast<V*>(wr + j * VW) = acc[v];
+      gstore(reinterpret_cast<V*>(wr + j * VW), acc[v]);
     } else {
       // the row's last, partial vector (static element indices: the
       // accumulator stays in registers).  With wpad the columns past the rank
@@ -64,11 +65,11 @@ __device__ __forceinline__ void spmm_store(const typename V16<T>::t* acc, int64_
 #pragma unroll
         for (int x = 0; x < VW; ++x)
           if (j * VW + x >= r) ap[x] = T(0);
-        *reinterpret_cast<V*>(wr + j * VW) = *reinterpret_cast<const V*>(ap);
+        gstore(reinterpret_cast<V*>(wr + j * VW), *reinterpret_cast<const V*>(ap));
       } else {
 #pragma unroll
         for (int x = 0; x < VW; ++x)
-          if (j * VW + x < r) wr[j * VW + x] = ap[x];
+          if (j * VW + x < r) gmem(wr)[j * VW + x] = ap[x];
       }
     }
   }
@@ -83,7 +84,7 @@ __device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
   V acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = V16<T>::zero();
-  const int e0 = K.rowptr[row], e1 = K.rowptr[row + 1];
+  const int e0 = gmem(K.rowptr)[row], e1 = gmem(K.rowptr)[row + 1];
   for (int e = e0; e < e1; e += NZB) {
     int cj[NZB];
     T vj[NZB];
@@ -91,17 +92,17 @@ __device__ __forceinline__ void spmm_row(const DevCsr<T>& K, int64_t row,
     for (int u = 0; u < NZB; ++u) {
       const bool ok = e + u < e1;
       const int x = ok ? e + u : e0;
-      cj[u] = K.col[x];
-      const T val = K.val[x];
+      cj[u] = gmem(K.col)[x];
+      const T val = gmem(K.val)[x];
       vj[u] = ok ? val : T(0);
     }
 #pragma unroll
     for (int u = 0; u < NZB; ++u) {
-      const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
+      const V* ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int j = chunk + v * lpr;
-        if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
+        if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], gload(ur + j));
       }
     }
   }
@@ -125,16 +126,16 @@ __device__ __forceinline__ void spmm_row_ell(const DevCsr<T>& K, int64_t x, int6
   T vj[EW];
 #pragma unroll
   for (int u = 0; u < EW; ++u) {
-    cj[u] = K.ecol[int64_t(u) * K.nrows + x];
-    vj[u] = K.eval[int64_t(u) * K.nrows + x];
+    cj[u] = gmem(K.ecol)[int64_t(u) * K.nrows + x];
+    vj[u] = gmem(K.eval)[int64_t(u) * K.nrows + x];
   }
 #pragma unroll
   for (int u = 0; u < EW; ++u) {
-    const V* __restrict__ ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
+    const V* ur = reinterpret_cast<const V*>(U + int64_t(cj[u]) * ldu);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int j = chunk + v * lpr;
-      if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], ur[j]);
+      if (NV == 1 || j < nvec) V16<T>::fma(acc[v], vj[u], gload(ur + j));
     }
   }
   spmm_store<T, NV>(acc, row, W, ldw, r, nvec, lpr, chunk, wpad);
@@ -215,8 +216,8 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
   const int ew = __builtin_amdgcn_readfirstlane((rl || !K.rows) ? K.ew : 0);
 #define LRC_ELL(EW)                                                                               \
   for (int64_t x = first; x < nvis; x += stride)                                                  \
-    spmm_row_ell<T, NV, EW>(K, x, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, \
-                            wpad)
+    spmm_row_ell<T, NV, EW>(K, x, rl ? int64_t(gmem(rl)[x]) : x, U, ldu, W, ldw, r, nvec, lpr,    \
+                            chunk, wpad)
   if (ew == 5) {
     LRC_ELL(5);
   } else if (ew == 7) {
@@ -227,13 +228,13 @@ __global__ __launch_bounds__(512) void spmm_kernel(SpmmArgs<T> a0, const SpmmArg
     LRC_ELL(27);
   } else if (maxrow <= 5) {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 5>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
+      spmm_row<T, NV, 5>(K, rl ? int64_t(gmem(rl)[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   } else if (maxrow <= 9) {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 9>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
+      spmm_row<T, NV, 9>(K, rl ? int64_t(gmem(rl)[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   } else {
     for (int64_t x = first; x < nvis; x += stride)
-      spmm_row<T, NV, 4>(K, rl ? int64_t(rl[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
+      spmm_row<T, NV, 4>(K, rl ? int64_t(gmem(rl)[x]) : x, U, ldu, W, ldw, r, nvec, lpr, chunk, wpad);
   }
 #undef LRC_ELL
 }
@@ -412,15 +413,16 @@ __global__ __launch_bounds__(256) void prec_gather_kernel(const GatherRow* __res
     const GatherRow g = e == e0 ? g0 : rows[row];
     vec v;
     if (FWD) {
-      v = g.src >= 0 ? *reinterpret_cast<const vec*>(it.R + int64_t(g.src) * it.ldr + c)
-                     : V16<T>::zero();
+      v = V16<T>::zero();
+      if (g.src >= 0) v = gload(reinterpret_cast<const vec*>(it.R + int64_t(g.src) * it.ldr + c));
       for (int q = 0; q < g.na; ++q)
-        V16<T>::add(v, *reinterpret_cast<const vec*>(it.cb + asm_src[g.a0 + q] * ldw + c));
+        V16<T>::add(v, gload(reinterpret_cast<const vec*>(it.cb + gmem(asm_src)[g.a0 + q] * ldw +
+                                                          c)));
     } else {
-      v = g.src >= 0 ? *reinterpret_cast<const vec*>(it.y + int64_t(g.src) * ldw + c)
-                     : *reinterpret_cast<const vec*>(it.x + int64_t(-g.src - 1) * ldw + c);
+      const T* src = g.src >= 0 ? it.y + int64_t(g.src) * ldw : it.x + int64_t(-g.src - 1) * ldw;
+      v = gload(reinterpret_cast<const vec*>(src + c));
     }
-    *reinterpret_cast<vec*>(it.stage + int64_t(row) * ldw + c) = v;
+    gstore(reinterpret_cast<vec*>(it.stage + int64_t(row) * ldw + c), v);
   }
 }
 
@@ -473,8 +475,8 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
   // one iteration ahead so that an iteration waits on one round of loads
   auto in_idx = [&](int i) -> int {
     if (!DIRECT) return i;
-    if (FWD) return P.perm[j0 + i];
-    return i < ns ? j0 + i : bnd[i - ns];
+    if (FWD) return gmem(P.perm)[j0 + i];
+    return i < ns ? j0 + i : gmem(bnd)[i - ns];
   };
   auto in_row = [&](int i, int idx) -> const T* {
     if (!DIRECT) return In + int64_t(idx) * ldw;
@@ -532,11 +534,11 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     for (int u = 0; u < U; ++u) {
       const int i = kk + 4 * u + (lane >> 4);
       const bool iok = i < i1;
-      a[u] = (iok && rowok) ? M[int64_t(i) * ldM + orow] : T(0);
+      a[u] = (iok && rowok) ? gmem(M)[int64_t(i) * ldM + orow] : T(0);
 #pragma unroll
       for (int t = 0; t < KTM; ++t) {
         const int c = t * 16 + (lane & 15);
-        b[u][t] = (iok && c < k) ? rp[u][c] : T(0);
+        b[u][t] = (iok && c < k) ? gmem(rp[u])[c] : T(0);
       }
     }
 #pragma unroll
@@ -548,11 +550,13 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
     const int row = row0 + r;
     if (c >= k || row >= nout) return;
     if (FWD) {
-      if (row < ns) it.y[int64_t(j0 + row) * ldw + c] = v;
-      else it.cb[(P.cb_off[sn] + row - ns) * ldw + c] = DIRECT ? v : v + In[int64_t(row) * ldw + c];
+      if (row < ns) gmem(it.y)[int64_t(j0 + row) * ldw + c] = v;
+      else
+        gmem(it.cb)[(P.cb_off[sn] + row - ns) * ldw + c] =
+            DIRECT ? v : v + gmem(In)[int64_t(row) * ldw + c];
     } else {
-      if (!leaf) it.x[int64_t(j0 + row) * ldw + c] = v;
-      it.Z[int64_t(P.perm[j0 + row]) * it.ldz + c] = v;
+      if (!leaf) gmem(it.x)[int64_t(j0 + row) * ldw + c] = v;
+      gmem(it.Z)[int64_t(gmem(P.perm)[j0 + row]) * it.ldz + c] = v;
     }
   };
   if (NW == 1) {
