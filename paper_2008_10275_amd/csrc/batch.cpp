@@ -200,6 +200,7 @@ struct Replay {
 // item at once; a few iterations per graph replay.
 struct MedianBatch {
   static constexpr int kIterPerReplay = 4;
+  Replay rep1;   // a single update, for the last ones
   int nb = 0;
   hipStream_t s = nullptr;
   std::vector<MedWork*> b;
@@ -232,6 +233,7 @@ struct MedianBatch {
     s = s_;
     nb = int(run.size());
     rep.eager = eager;
+    rep1.eager = eager;
     std::vector<MedItem> hi(nb);
     std::vector<SpmmLaunch<double>> sl;
     std::vector<SpmmArgs<double>> sa;
@@ -317,6 +319,19 @@ struct MedianBatch {
     launch_med_resid(it, dd, nb, s);
     launch_med_check(it, ct, dd, nb, 0, s);
     bool overlapped = false;
+    std::vector<double> norm0(nb, 0.0);
+    auto iterations = [&](int count) {
+      for (int k = 0; k < count; ++k) {
+        if (f32)
+          pb32.enqueue(s);
+        else
+          pb.enqueue(s);
+        launch_med_update(it, ct, dd, nb, nmax, s);
+        enqueue_spmm(sp0, spB, s);
+        launch_med_resid(it, dd, nb, s);
+        launch_med_check(it, ct, dd, nb, 1, s);
+      }
+    };
     while (true) {
       LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, hctl.size() * sizeof(MedCtl),
                              hipMemcpyDeviceToHost, s));
@@ -324,18 +339,27 @@ struct MedianBatch {
       bool all = true;
       for (const auto& c : hctl) all = all && c.state != 0;
       if (all) break;
-      rep.run(s, kcls(K_GRAPH, false), [&]() {
-        for (int k = 0; k < kIterPerReplay; ++k) {
-          if (f32)
-            pb32.enqueue(s);
-          else
-            pb.enqueue(s);
-          launch_med_update(it, ct, dd, nb, nmax, s);
-          enqueue_spmm(sp0, spB, s);
-          launch_med_resid(it, dd, nb, s);
-          launch_med_check(it, ct, dd, nb, 1, s);
+      // After the first replay the observed rate of each running item gives
+      // the updates it still needs; when every item needs at most two, single
+      // updates are replayed: an update of a finished item still costs its
+      // ~45 launches of early exits (about a quarter of a millisecond)
+      double need_max = 0.0;
+      for (int j = 0; j < nb; ++j) {
+        const MedCtl& c = hctl[j];
+        if (c.iters == 0) norm0[j] = c.norm;
+        if (c.state != 0) continue;
+        double need = kIterPerReplay;
+        if (c.iters > 0 && norm0[j] > 0.0) {
+          const double rate = std::pow(c.norm / norm0[j], 1.0 / c.iters);
+          if (rate > 0.0 && rate < 0.95 && c.norm > c.target)
+            need = std::ceil(std::log(c.target / c.norm) / std::log(rate));
         }
-      });
+        need_max = std::max(need_max, need);
+      }
+      if (need_max <= 2.0)
+        rep1.run(s, kcls(K_GRAPH, false), [&]() { iterations(1); });
+      else
+        rep.run(s, kcls(K_GRAPH, false), [&]() { iterations(kIterPerReplay); });
       if (overlap && !overlapped) {
         overlapped = true;
         overlap();
