@@ -195,6 +195,72 @@ struct Replay {
   }
 };
 
+// A restart cycle replayed as two graphs, steps [0, half) and [half, cycle).
+// At a cycle's start both halves are launched back to back, unless the
+// residual rates measured so far say that every running item stops within
+// the first half: then the host checks after it, so that the second half's
+// updates, which every finished item would still launch and skip, are not
+// run.  `step_range(k0, k1)` enqueues steps [k0, k1) of a cycle; the two
+// halves together enqueue exactly one cycle.
+struct HalfCycles {
+  Replay a, b;
+  int cycle = 1, half = 1, pos = 0;
+  std::vector<double> pnorm;
+  std::vector<int> piters;
+  void setup(int cycle_, bool eager, int nb) {
+    cycle = std::max(cycle_, 1);
+    half = (cycle + 1) / 2;
+    a.eager = b.eager = eager;
+    pnorm.assign(nb, -1.0);
+    piters.assign(nb, 0);
+  }
+  template <class F>
+  void prepare(hipStream_t cs, F step_range) {
+    a.prepare(cs, [&]() { step_range(0, half); });
+    if (half < cycle) b.prepare(cs, [&]() { step_range(half, cycle); });
+  }
+  void restart() {
+    pos = 0;
+    std::fill(pnorm.begin(), pnorm.end(), -1.0);
+    std::fill(piters.begin(), piters.end(), 0);
+  }
+  // the largest number of updates a running item still needs, from its
+  // residual's rate since the previous check (a whole cycle when unknown)
+  double need(const std::vector<BCtl>& h) {
+    double worst = 0.0;
+    for (size_t j = 0; j < h.size(); ++j) {
+      if (h[j].state != 0) continue;
+      double nd = cycle;
+      const int di = h[j].iters - piters[j];
+      if (pnorm[j] > 0.0 && di > 0 && h[j].last > h[j].target) {
+        const double rate = std::pow(h[j].last / pnorm[j], 1.0 / di);
+        if (rate > 0.0 && rate < 0.95)
+          nd = std::ceil(std::log(h[j].target / h[j].last) / std::log(rate));
+      }
+      worst = std::max(worst, nd);
+      pnorm[j] = h[j].last;
+      piters[j] = h[j].iters;
+    }
+    return worst;
+  }
+  template <class F>
+  void run(hipStream_t s, int cls, const std::vector<BCtl>& h, F step_range) {
+    const double nd = need(h);
+    if (pos == 0) {
+      a.run(s, cls, [&]() { step_range(0, half); });
+      if (half == cycle) return;
+      if (nd > half) {
+        b.run(s, cls, [&]() { step_range(half, cycle); });
+      } else {
+        pos = half;
+      }
+    } else {
+      b.run(s, cls, [&]() { step_range(half, cycle); });
+      pos = 0;
+    }
+  }
+};
+
 // ------------------------------------------------------------------ median columns
 // Preconditioned Chebyshev on the median parameter's single column, for every
 // item at once; a few iterations per graph replay.
@@ -412,7 +478,8 @@ struct BatchCheb {
   std::vector<TruncBatch<T>> u3B;
   DevBuf back;       // per item: copy of D's buffer into S (odd cycles)
   int64_t rows_max = 0;
-  Replay rep;
+  Replay rep;        // its eager flag only: the cycle runs as two halves
+  HalfCycles hc;
 
   DevBuf& newbuf() {
     bufs.push_back(std::make_unique<DevBuf>());
@@ -555,9 +622,10 @@ struct BatchCheb {
     }
   }
 
-  // capture the cycle's graph on the set-up stream, then run on `main`
+  // capture the cycle's graphs on the set-up stream, then run on `main`
   void prepare_on(hipStream_t main) {
-    rep.prepare(s, [&]() { cycle_steps(); });
+    hc.setup(cycle, rep.eager, nb);
+    hc.prepare(s, [&](int k0, int k1) { steps(k0, k1); });
     s = main;
   }
 
@@ -578,23 +646,26 @@ struct BatchCheb {
     }
   }
 
-  // one restart cycle: D = T(P^-1 R / dc), then `cycle` updates
-  // S = T(S + D), each followed by the residual and, before the next, the
-  // direction D = T(alpha D + beta P^-1 R)
-  void cycle_steps() {
+  // Steps [k0, k1) of a restart cycle.  Direction form: step 0 starts with
+  // D = T(P^-1 R / dc); step k updates S = T(S + D), takes the residual and,
+  // before the next step, the direction D = T(alpha D + beta P^-1 R).
+  // Three-term form: step k is the update of setup_three and the residual.
+  void steps(int k0, int k1) {
     if (three) {
-      for (int k = 0; k < cycle; ++k) {
+      for (int k = k0; k < k1; ++k) {
         pb.enqueue(s);
         enqueue_trunc(u30[k], u3B[k], s);
         resid(1, (k + 1) & 1);
       }
-      if (cycle & 1)
+      if (k1 == cycle && (cycle & 1))
         launch_cast_lr(back.as<CastItem<T, T>>(), done.as<int>(), nb, rows_max, it[0]->S.cap, s);
       return;
     }
-    pb.enqueue(s);
-    enqueue_trunc(dstart0, dstartB, s);
-    for (int k = 0; k < cycle; ++k) {
+    for (int k = k0; k < k1; ++k) {
+      if (k == 0) {
+        pb.enqueue(s);
+        enqueue_trunc(dstart0, dstartB, s);
+      }
       enqueue_trunc(supd0, supdB, s);
       resid(1);
       if (k + 1 == cycle) break;
@@ -639,6 +710,8 @@ struct BatchCheb {
     LRC_HIP(hipMemcpyAsync(done.p, dn.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice,
                            s));
     if (!copy) resid(0);
+    if (int(hc.pnorm.size()) != nb) hc.setup(cycle, rep.eager, nb);
+    hc.restart();
     while (true) {
       LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, size_t(nb) * sizeof(BCtl),
                              hipMemcpyDeviceToHost, s));
@@ -646,7 +719,7 @@ struct BatchCheb {
       bool all = true;
       for (const auto& h : hctl) all = all && h.state != 0;
       if (all) break;
-      rep.run(s, kcls(K_GRAPH, is_f32<T>()), [&]() { cycle_steps(); });
+      hc.run(s, kcls(K_GRAPH, is_f32<T>()), hctl, [&](int k0, int k1) { steps(k0, k1); });
     }
     three_back();
     if (log_on())
@@ -689,7 +762,8 @@ struct BatchDir {
   std::vector<TruncPlan<double>> u30;
   std::vector<TruncBatch<double>> u3B;
   DevBuf castZ, zscr, back;
-  Replay rep;
+  Replay rep;        // its eager flag only: the cycle runs as two halves
+  HalfCycles hc;
 
   DevBuf& newbuf() {
     bufs.push_back(std::make_unique<DevBuf>());
@@ -842,7 +916,8 @@ struct BatchDir {
     launch_cast_lr(castD.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap, s);
   }
   void prepare_on(hipStream_t main) {
-    rep.prepare(s, [&]() { cycle_steps(); });
+    hc.setup(cycle, rep.eager, nb);
+    hc.prepare(s, [&](int k0, int k1) { steps(k0, k1); });
     s = main;
   }
 
@@ -852,23 +927,26 @@ struct BatchDir {
     launch_batch_check(ctl.as<BCtl>(), done.as<int>(), nb, after_update, s);
     cast_r();
   }
-  void cycle_steps() {
+  // steps [k0, k1) of a cycle
+  void steps(int k0, int k1) {
     if (three) {
-      for (int k = 0; k < cycle; ++k) {
+      for (int k = k0; k < k1; ++k) {
         pb.enqueue(s);
         launch_cast_lr(castZ.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap,
                        s);
         enqueue_trunc(u30[k], u3B[k], s);
         resid(1, (k + 1) & 1);
       }
-      if (cycle & 1)
+      if (k1 == cycle && (cycle & 1))
         launch_cast_lr(back.as<CastItem<double, double>>(), done.as<int>(), nb, rows_max, cap, s);
       return;
     }
-    pb.enqueue(s);
-    enqueue_trunc(dstart0, dstartB, s);
-    cast_d();
-    for (int k = 0; k < cycle; ++k) {
+    for (int k = k0; k < k1; ++k) {
+      if (k == 0) {
+        pb.enqueue(s);
+        enqueue_trunc(dstart0, dstartB, s);
+        cast_d();
+      }
       enqueue_trunc(supd0, supdB, s);
       resid(1);
       if (k + 1 == cycle) break;
@@ -906,6 +984,8 @@ struct BatchDir {
     LRC_HIP(hipMemcpyAsync(done.p, dn.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice, s));
     if (copy) cast_r();
     else resid(0);
+    if (int(hc.pnorm.size()) != nb) hc.setup(cycle, rep.eager, nb);
+    hc.restart();
     while (true) {
       LRC_HIP(hipMemcpyAsync(hctl.data(), ctl.p, size_t(nb) * sizeof(BCtl),
                              hipMemcpyDeviceToHost, s));
@@ -913,7 +993,7 @@ struct BatchDir {
       bool all = true;
       for (const auto& h : hctl) all = all && h.state != 0;
       if (all) break;
-      rep.run(s, kcls(K_GRAPH, false), [&]() { cycle_steps(); });
+      hc.run(s, kcls(K_GRAPH, false), hctl, [&](int k0, int k1) { steps(k0, k1); });
     }
     // an item that stopped at an even step k of a cycle holds its iterate in
     // D's buffer (see BatchCheb::three_back)
