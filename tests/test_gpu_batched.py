@@ -151,3 +151,31 @@ def test_graph_replay_matches_eager_launches(torch, L, ctx, c3, precision):
     for a, b, xe, xg in zip(inf_e, inf_g, X_e, X_g):
         assert a["iters"] == b["iters"] and a["median_iters"] == b["median_iters"]
         assert np.linalg.norm(xe - xg) <= 1e-12 * np.linalg.norm(xe)
+
+
+@pytest.mark.parametrize("restart", [5, 3])
+@pytest.mark.parametrize("precision", ["fp64", "dir"])
+def test_half_cycles_three_term_odd_restart(torch, L, ctx, c3, precision, restart):
+    """A cycle runs as two captured halves, the second skipped when every
+    running subset's measured rate says it stops within the first; with an
+    odd cycle the three-term iterate ends a cycle in the second buffer and is
+    copied back.  Graph replays against direct launches and against the
+    subsets solved one by one: identical iteration counts and solutions."""
+    _, subs = c3
+    probs = [subs[j]["prob"] for j in (0, 2, 5, 7)]
+    kw = dict(_kw(L, precision, "three_term"), restart=restart)
+    say("half cycles", precision, "restart", restart)
+    code_e, inf_e = L.solve_batched(probs, **dict(kw, eager=1))
+    X_e = [_dense(p.solution()) for p in probs]
+    code_g, inf_g = L.solve_batched(probs, **kw)
+    X_g = [_dense(p.solution()) for p in probs]
+    assert code_e == 0 and code_g == 0
+    for j, p in enumerate(probs):
+        code, info = p.solve(**kw)
+        assert code == 0
+        X = _dense(p.solution())
+        say("subset", j, "iters", inf_g[j]["iters"], inf_e[j]["iters"], info["iters"])
+        assert inf_g[j]["iters"] == inf_e[j]["iters"] == info["iters"]
+        assert inf_g[j]["relres"] <= 1e-6
+        assert np.linalg.norm(X_g[j] - X_e[j]) <= 1e-12 * np.linalg.norm(X_e[j])
+        assert np.linalg.norm(X_g[j] - X) <= 1e-10 * np.linalg.norm(X)
