@@ -428,6 +428,10 @@ struct MedianBatch {
         rep.run(s, kcls(K_GRAPH, false), [&]() { iterations(kIterPerReplay); });
       if (overlap && !overlapped) {
         overlapped = true;
+        // one more update is queued before the host work, so that the GPU
+        // keeps working while the host is busy; an item already finished
+        // skips it, one still running would have taken it next anyway
+        rep1.run(s, kcls(K_GRAPH, false), [&]() { iterations(1); });
         overlap();
       }
     }
