@@ -19,8 +19,8 @@ separately.
 size (20..300, 2,000 parameters in all), each with its own perturbed
 convection coefficients, on a 257 x 257 grid (n = 66,049), rank cap 30; a
 step is one lockstep solve of all subsets (lrc_solve_batched, mixed precision,
-one HIP graph per restart cycle), compared with the 16 subsets solved one
-after another in plain FP64.
+each restart cycle replayed from captured HIP graphs), compared with the 16
+subsets solved one after another in plain FP64.
 
 Prints one JSON line.  Per-kernel times come from HIP events recorded by the
 library on the stream each kernel runs on (lrc_profile_*), the algorithmic

@@ -252,10 +252,12 @@ lrc_status lrc_solve_x0_dev(lrc_prob prob, const lrc_opts* opts, int r0, const d
  * treats the parameter subsets independently, so their Newton steps can run
  * together).  Same options and results as K calls of lrc_solve with
  * opts->init LRC_INIT_MEDIAN or LRC_INIT_ZERO (LRC_INIT_GIVEN is refused);
- * opts->restart must be in [1, 64] (as for lrc_solve): one restart cycle of the ChebyshevT
- * recurrence for all problems is captured once as a HIP graph and replayed
- * until every problem has converged or stopped, each step being one launch
- * over all problems, with finished problems skipped on the device.  Problems
+ * opts->restart must be in [1, 64] (as for lrc_solve): a restart cycle of the
+ * ChebyshevT recurrence for all problems is captured once as two HIP graphs
+ * (its two halves) and replayed until every problem has converged or
+ * stopped, each step being one launch over all problems, with finished
+ * problems skipped on the device; the host reads the problems' states after
+ * the first half when their measured rates say that they all stop within it.  Problems
  * may differ in m, F, the operator values and the preconditioner; problems
  * whose factorisations share one supernode structure (same sparsity pattern)
  * share each preconditioner launch as well.  infos (K entries, may be NULL)

@@ -384,8 +384,8 @@ class Problem:
 
 def solve_batched(problems, opts=None, **kw):
     """lrc_solve_batched: all problems (one context, each preconditioned) in
-    lockstep, one launch per step and one HIP graph per restart cycle.
-    Returns (worst status, [info dict per problem])."""
+    lockstep, one launch per step, each restart cycle replayed from captured
+    HIP graphs.  Returns (worst status, [info dict per problem])."""
     if not problems:
         raise ValueError("solve_batched: no problems")
     o = opts if opts is not None else default_opts(**kw)
