@@ -766,6 +766,8 @@ struct BatchDir {
   std::vector<TruncPlan<double>> u30;
   std::vector<TruncBatch<double>> u3B;
   DevBuf castZ, zscr, back;
+  bool all_lu = true;   // every item's preconditioner is the exact LU
+  bool zcast = false;   // some item's solve (ILU(0)) writes fp32 Z: widen it
   Replay rep;        // its eager flag only: the cycle runs as two halves
   HalfCycles hc;
 
@@ -780,6 +782,8 @@ struct BatchDir {
     s = s_;
     cycle = o.restart;
     three = o.recurrence == LRC_CHEB_THREE_TERM;
+    all_lu = true;
+    for (auto* x : run) all_lu = all_lu && x->P->prec->kind == 0;
     rep.eager = eager;
     cap = run[0]->cap;
     done.alloc(size_t(nb) * sizeof(int));
@@ -802,6 +806,10 @@ struct BatchDir {
       sl.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
       sa.push_back(sl.back().a);
       pi.push_back(F.prec_item());
+      // three-term form, exact LU throughout: the fp32 solve writes fp64 Z
+      // directly (ILU(0) reads its own Z rows back, so a batch holding it
+      // keeps fp32 Z and widens it)
+      if (three && all_lu) pi.back().Z64 = C.Z.as<double>();
       pre.push_back(x->P->prec.get());
       cr.push_back(CastItem<double, float>{C.R.u(), C.R.v(), C.R.sv(), C.R.r(), F.R.u(), F.R.v(),
                                            F.R.sv(), F.R.r(), C.R.ld, C.R.ld, F.R.ld, F.R.ld,
@@ -879,7 +887,8 @@ struct BatchDir {
     }
     sp1 = merge_spmm(sl);
     spB1 = upload_items(sa, dn, newbuf(), s);
-    upload_items(cz, dn, castZ, s);
+    zcast = !all_lu;
+    if (zcast) upload_items(cz, dn, castZ, s);
     if (cycle & 1) upload_items(cb, dn, back, s);
     site64([&](int j) {
       Cheb<double>& C = *run[j]->c64;
@@ -936,8 +945,9 @@ struct BatchDir {
     if (three) {
       for (int k = k0; k < k1; ++k) {
         pb.enqueue(s);
-        launch_cast_lr(castZ.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap,
-                       s);
+        if (zcast)
+          launch_cast_lr(castZ.as<CastItem<float, double>>(), done.as<int>(), nb, rows_max, cap,
+                         s);
         enqueue_trunc(u30[k], u3B[k], s);
         resid(1, (k + 1) & 1);
       }

@@ -556,7 +556,11 @@ __global__ __launch_bounds__(NW > 4 ? 64 * NW : 256) void prec_product_kernel(
             DIRECT ? v : v + gmem(In)[int64_t(row) * ldw + c];
     } else {
       if (!leaf) gmem(it.x)[int64_t(j0 + row) * ldw + c] = v;
-      gmem(it.Z)[int64_t(gmem(P.perm)[j0 + row]) * it.ldz + c] = v;
+      const int64_t zo = int64_t(gmem(P.perm)[j0 + row]) * it.ldz + c;
+      if (it.Z64)
+        gmem(it.Z64)[zo] = double(v);
+      else
+        gmem(it.Z)[zo] = v;
     }
   };
   if (NW == 1) {

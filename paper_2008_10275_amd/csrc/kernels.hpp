@@ -167,6 +167,9 @@ struct PrecItem {
   T* x;
   T* cb;
   T* stage;
+  // when set (exact-LU kind only), the solution rows go here in fp64 instead
+  // of to Z: a solve computed in fp32 feeds an fp64 consumer without a copy
+  double* Z64 = nullptr;
 };
 // kterms: the widths of every item the launch covers, for the work model
 // (nullptr: the single item `it`)
