@@ -129,9 +129,11 @@ void build_levels(Prec& pr, hipStream_t s) {
   for (size_t l = 0; l < ft.size(); ++l)
     pr.fwd.push_back({base + fto[l], int(ft[l].size()), base + fro[l], int(fr[l].size()),
                       gbase + gfo[l], nin_f[l], contrib_f[l] ? 0 : 1, blk_f[l], ns_f[l], lf[l]});
-  for (size_t l = 0; l < bt.size(); ++l)
+  for (size_t l = 0; l < bt.size(); ++l) {
     pr.bwd.push_back({base + bto[l], int(bt[l].size()), base + bro[l], int(br[l].size()),
                       gbase + gbo[l], nin_b[l], 1, blk_b[l], lb[l], out_b[l]});
+    pr.bwd.back().z_rows = ns_b[l];
+  }
   LRC_HIP(hipStreamSynchronize(s));
 }
 

@@ -597,12 +597,16 @@ static Work gather_work(const LevelTasks& L, const std::vector<WTerm>& kterms) {
   w.f = [=](const std::vector<double>& v) { return 2.0 * rows * v[0] * sizeof(T); };
   return w;
 }
+// (z64: the backward output rows of the solution go out in fp64, z_rows of
+// them per level, each k columns wider by 8 - sizeof(T) bytes)
 template <class T>
-static Work product_work(const LevelTasks& L, const std::vector<WTerm>& kterms) {
+static Work product_work(const LevelTasks& L, const std::vector<WTerm>& kterms,
+                         double z_rows = 0.0) {
   Work w;
   const double blk = L.blk * double(kterms.size()), io = double(L.in_rows + L.out_rows);
+  const double zx = z_rows * (8.0 - sizeof(T));
   w.groups = {kterms};
-  w.f = [=](const std::vector<double>& v) { return (blk + io * v[0]) * sizeof(T); };
+  w.f = [=](const std::vector<double>& v) { return (blk + io * v[0]) * sizeof(T) + zx * v[0]; };
   return w;
 }
 
@@ -736,7 +740,8 @@ void enqueue_prec_apply(const PrecDev<T>& P, const std::vector<LevelTasks>& fwd,
                              L.nrows, vpr, P.asm_src, it, b.dev, b.done, ldw);
       }
       {
-        ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s, product_work<T>(L, kt));
+        ProfScope ps(kcls(K_PREC_PRODUCT, is_f32<T>()), s,
+                     product_work<T>(L, kt, (!fw && it.Z64) ? double(L.z_rows) : 0.0));
         // waves per task by the level's longest input; a level with more tasks
         // than the GPU holds waves is throughput-bound: one wave per task there
         // (no partial tiles to sum) unless the inputs are long

@@ -110,6 +110,7 @@ struct LevelTasks {
   int64_t out_rows;    // rows the products write (per column)
   int ilu_off;         // ILU(0): the level's rows start here in the level row list
   int64_t ilu_nnz;     // ILU(0): entries of the level's rows in its triangle
+  int64_t z_rows;      // backward: rows of the solution Z the products write
 };
 
 template <class T>
