@@ -1154,6 +1154,76 @@ void ops_apply_vector(Ops& o, const std::vector<double>& x, std::vector<double>&
   ops_apply_block(o, x, 1, W);
 }
 
+// The fp64 iterative refinement's outer sites (residual SpMM and truncation,
+// accumulation of the correction) and its fp32 inner ChebyshevT, built like
+// the other forms' phase: plans, uploads and graphs on the given stream,
+// which may be a second one while the median iterations run.
+struct RefineSetup {
+  DevBuf odone, octl;
+  std::vector<BCtl> ho;
+  std::vector<int> hd;
+  std::vector<std::unique_ptr<DevBuf>> bufs;
+  SpmmLaunch<double> sp0;
+  Batched<SpmmArgs<double>> spB;
+  TruncPlan<double> res0, acc0;
+  TruncBatch<double> resB, accB;
+  BatchCheb<float> bc;
+  void setup(std::vector<SolveRun*>& run, const lrc_opts& o, const std::vector<double>& c,
+             const std::vector<double>& dc, const std::vector<double>& tgt, bool eager,
+             hipStream_t s) {
+    const int nb = int(run.size());
+    odone.alloc(size_t(nb) * sizeof(int));
+    octl.alloc(size_t(nb) * sizeof(BCtl));
+    ho.assign(nb, BCtl{});
+    hd.assign(nb, 0);
+    for (int j = 0; j < nb; ++j) {
+      ho[j] = BCtl{};
+      ho[j].norm = run[j]->c64->norm.as<double>();
+      ho[j].target = tgt[j];
+      ho[j].max_iter = 1 << 30;
+      ho[j].stall_limit = 1 << 30;
+    }
+    LRC_HIP(hipMemcpyAsync(octl.p, ho.data(), size_t(nb) * sizeof(BCtl), hipMemcpyHostToDevice, s));
+    LRC_HIP(hipMemcpyAsync(odone.p, hd.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice, s));
+    auto nbuf = [&]() -> DevBuf& {
+      bufs.push_back(std::make_unique<DevBuf>());
+      return *bufs.back();
+    };
+    const int* od = odone.as<int>();
+    // outer residual (fp64, truncated at the inner solve's accuracy) and accumulation sites
+    {
+      std::vector<SpmmLaunch<double>> v;
+      std::vector<SpmmArgs<double>> a;
+      std::vector<TruncPlan<double>> vr, va;
+      for (auto* r : run) {
+        Cheb<double>& C = *r->c64;
+        v.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
+        a.push_back(v.back().a);
+        // truncated straight to the inner solve's cap: its first residual
+        vr.push_back(C.resid_plan(r->B64, C.norm.as<double>(), r->rhs_tol, r->inner_cap));
+        va.push_back(r->accumulate_plan(o));
+      }
+      sp0 = merge_spmm(v);
+      spB = upload_items(a, od, nbuf(), s);
+      res0 = merge_plans(vr);
+      resB = upload_plans(vr, od, nbuf(), s);
+      acc0 = merge_plans(va);
+      accB = upload_plans(va, od, nbuf(), s);
+    }
+    {
+      std::vector<Cheb<float>*> items;
+      std::vector<const LR<float>*> rhs;
+      for (auto* r : run) {
+        items.push_back(r->c32.get());
+        rhs.push_back(&r->Bin);
+      }
+      bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, std::vector<double>(nb, 0.0),
+               o.restart, eager, s, o.recurrence == LRC_CHEB_THREE_TERM);
+    }
+  }
+  void prepare_on(hipStream_t main) { bc.prepare_on(main); }
+};
+
 void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   const int nb = int(run.size());
   LRC_CHECK(nb >= 1, ST_EINVAL, "lockstep: no problems");
@@ -1184,6 +1254,7 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   OwnStream aux;
   std::unique_ptr<BatchDir> bd;
   std::unique_ptr<BatchCheb<double>> bc64;
+  std::unique_ptr<RefineSetup> rsu;
   std::vector<Cheb<double>*> items64;
   std::vector<const LR<double>*> rhs64;
   std::vector<double> res_abs;
@@ -1203,6 +1274,10 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       bc64->setup(items64, rhs64, c, dc, o.trunc_tol, res_abs, o.restart, eager, aux.s,
                   o.recurrence == LRC_CHEB_THREE_TERM);
       bc64->prepare_on(s);
+    } else if (o.precision == LRC_MIXED_FP32 || o.precision == LRC_MIXED_BF16GRAM) {
+      rsu = std::make_unique<RefineSetup>();
+      rsu->setup(run, o, c, dc, tgt, eager, aux.s);
+      rsu->prepare_on(s);
     }
     if (log_on())
       std::fprintf(stderr, "{\"cheb_setup_s\": %.5f}\n",
@@ -1211,8 +1286,11 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
   bool cheb_ready = false;
   // the SpMM tuner times its candidates on an idle GPU: its first call for
   // the iterate's capacity happens here, before the median iterations run
-  if (o.precision == LRC_MIXED_FP32_DIR || o.precision == LRC_FP64)
-    for (auto* r : run) (void)spmm_config<double>(*r->P->ops, r->cap);
+  for (auto* r : run) {
+    (void)spmm_config<double>(*r->P->ops, r->cap);
+    if (o.precision == LRC_MIXED_FP32 || o.precision == LRC_MIXED_BF16GRAM)
+      (void)spmm_config<float>(*r->P->ops, r->cap);
+  }
   // 1. median-parameter columns (init LRC_INIT_MEDIAN)
   {
     std::vector<SolveRun*> med;
@@ -1274,59 +1352,18 @@ void lockstep(std::vector<SolveRun*>& run, const lrc_opts& o) {
       run[j]->flags |= read_info(run[j]->c64->tr.st.info, s);
     }
   } else {
-    DevBuf odone(size_t(nb) * sizeof(int)), octl(size_t(nb) * sizeof(BCtl));
-    std::vector<BCtl> ho(nb);
-    std::vector<int> hd(nb, 0);
-    for (int j = 0; j < nb; ++j) {
-      ho[j] = BCtl{};
-      ho[j].norm = run[j]->c64->norm.as<double>();
-      ho[j].target = tgt[j];
-      ho[j].max_iter = 1 << 30;
-      ho[j].stall_limit = 1 << 30;
-    }
-    LRC_HIP(hipMemcpyAsync(octl.p, ho.data(), size_t(nb) * sizeof(BCtl), hipMemcpyHostToDevice, s));
-    LRC_HIP(hipMemcpyAsync(odone.p, hd.data(), size_t(nb) * sizeof(int), hipMemcpyHostToDevice, s));
-    std::vector<std::unique_ptr<DevBuf>> bufs;
-    auto nbuf = [&]() -> DevBuf& {
-      bufs.push_back(std::make_unique<DevBuf>());
-      return *bufs.back();
-    };
-    const int* od = odone.as<int>();
-    // outer residual (fp64, truncated at the inner solve's accuracy) and accumulation sites
-    SpmmLaunch<double> sp0;
-    Batched<SpmmArgs<double>> spB;
-    TruncPlan<double> res0, acc0;
-    TruncBatch<double> resB, accB;
-    {
-      std::vector<SpmmLaunch<double>> v;
-      std::vector<SpmmArgs<double>> a;
-      std::vector<TruncPlan<double>> vr, va;
-      for (auto* r : run) {
-        Cheb<double>& C = *r->c64;
-        v.push_back(C.spmm_plan(C.S.u(), C.S.ld, C.S.r()));
-        a.push_back(v.back().a);
-        // truncated straight to the inner solve's cap: its first residual
-        vr.push_back(C.resid_plan(r->B64, C.norm.as<double>(), r->rhs_tol, r->inner_cap));
-        va.push_back(r->accumulate_plan(o));
-      }
-      sp0 = merge_spmm(v);
-      spB = upload_items(a, od, nbuf(), s);
-      res0 = merge_plans(vr);
-      resB = upload_plans(vr, od, nbuf(), s);
-      acc0 = merge_plans(va);
-      accB = upload_plans(va, od, nbuf(), s);
-    }
-    BatchCheb<float> bc;
-    {
-      std::vector<Cheb<float>*> items;
-      std::vector<const LR<float>*> rhs;
-      for (auto* r : run) {
-        items.push_back(r->c32.get());
-        rhs.push_back(&r->Bin);
-      }
-      bc.setup(items, rhs, c, dc, run[0]->inner_trunc_tol, std::vector<double>(nb, 0.0),
-               o.restart, eager, s, o.recurrence == LRC_CHEB_THREE_TERM);
-    }
+    RefineSetup& R = *rsu;
+    DevBuf& odone = R.odone;
+    DevBuf& octl = R.octl;
+    std::vector<BCtl>& ho = R.ho;
+    std::vector<int>& hd = R.hd;
+    const SpmmLaunch<double>& sp0 = R.sp0;
+    const Batched<SpmmArgs<double>>& spB = R.spB;
+    const TruncPlan<double>& res0 = R.res0;
+    const TruncPlan<double>& acc0 = R.acc0;
+    const TruncBatch<double>& resB = R.resB;
+    const TruncBatch<double>& accB = R.accB;
+    BatchCheb<float>& bc = R.bc;
     const double itol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
     while (true) {
       enqueue_spmm(sp0, spB, s);
